@@ -1,0 +1,692 @@
+/*
+ * ens_oracle.c -- plain, slow, obviously-correct FP64 CPU oracle for the
+ * ensemble diffusion solve of Phipps et al., "Embedded Ensemble Propagation
+ * for Improving Performance, Portability and Scalability of Uncertainty
+ * Quantification on Emerging Computational Architectures" (arXiv 1511.03703).
+ *
+ * THIS IS TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no source, header,
+ * table or helper with the GPU library; the two meet only through seeded
+ * input arrays generated outside both.
+ *
+ * What it computes (each function names the passage it follows):
+ *   - the Q1 hexahedral mesh of the unit cube and the CRS graph of its
+ *     stiffness matrix (Sec. 2, Fig. "crs"; Sec. 4, Alg. "assembly":
+ *     NodeIndex / ElemGraph maps);
+ *   - the truncated Karhunen-Loeve coefficient kappa(x,y) (Sec. 4, equations
+ *     for kappa and the exponential covariance C(x,x'));
+ *   - per-sample scalar finite-element assembly of A and f (Sec. 4,
+ *     Alg. "assembly"), one sample at a time, scattered in ascending element
+ *     order (the atomic scatter of the paper made sequential);
+ *   - the scalar CRS product (Fig. "crs") and the ensemble product in the
+ *     commuted layout (Fig. "ensemble_crs", Eq. kron_sys_commuted);
+ *   - textbook Jacobi-preconditioned CG, one sample at a time (Sec. 3.4 uses
+ *     CG; the ensemble system is block diagonal, Eq. kron_sys, so an ensemble
+ *     solve with per-sample scalars is s independent scalar solves);
+ *   - a dense Cholesky solve for brute-force checks on tiny meshes.
+ *
+ * Readings of points the paper leaves open (source term, boundary condition,
+ * KL scaling and mode order, quadrature, stopping rule) are listed where they
+ * are used.  Floating point: FP64 throughout; build with -ffp-contract=off so
+ * every product and sum rounds as written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_E_ARG (-1)
+#define ORC_E_NOMEM (-4)
+
+/* per-sample solver outcomes */
+#define ORC_CONVERGED 0
+#define ORC_MAXITER 1
+#define ORC_BREAKDOWN 2
+#define ORC_NONFINITE 3
+
+/* ------------------------------------------------------------------------ */
+/* Mesh (Sec. 4: D = [0,1]^3, linear finite elements on hexahedra).          */
+/* Reading: N elements per axis, h = 1/N; node (i,j,k) has id                */
+/* i + (N+1)(j + (N+1)k); element (ex,ey,ez) has id ex + N(ey + N ez);       */
+/* local vertex a has bits (a&1, (a>>1)&1, (a>>2)&1) along x, y, z.          */
+/* ------------------------------------------------------------------------ */
+
+int64_t orc_num_nodes(int N) { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
+int64_t orc_num_elems(int N) { return (int64_t)N * N * N; }
+
+static int64_t node_id(int N, int i, int j, int k) {
+  return (int64_t)i + (int64_t)(N + 1) * ((int64_t)j + (int64_t)(N + 1) * k);
+}
+
+/* NodeIndex(e, a) of Alg. "assembly". */
+static int64_t elem_node(int N, int64_t e, int a) {
+  int ex = (int)(e % N), ey = (int)((e / N) % N), ez = (int)(e / ((int64_t)N * N));
+  return node_id(N, ex + (a & 1), ey + ((a >> 1) & 1), ez + ((a >> 2) & 1));
+}
+
+static int is_boundary_node(int N, int64_t id) {
+  int i = (int)(id % (N + 1));
+  int j = (int)((id / (N + 1)) % (N + 1));
+  int k = (int)(id / ((int64_t)(N + 1) * (N + 1)));
+  return i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
+}
+
+static int cmp_int(const void *p, const void *q) {
+  int a = *(const int *)p, b = *(const int *)q;
+  return (a > b) - (a < b);
+}
+
+/* Row lengths of the CRS graph by its definition: column j appears in row i
+ * iff nodes i and j are vertices of a common element.  Brute force over the
+ * (at most 8) elements around node i and their 8 vertices each.           */
+static int row_columns(int N, int64_t i, int *cols) {
+  int ii = (int)(i % (N + 1));
+  int jj = (int)((i / (N + 1)) % (N + 1));
+  int kk = (int)(i / ((int64_t)(N + 1) * (N + 1)));
+  int cand[64];
+  int nc = 0;
+  for (int dz = -1; dz <= 0; ++dz)
+    for (int dy = -1; dy <= 0; ++dy)
+      for (int dx = -1; dx <= 0; ++dx) {
+        int ex = ii + dx, ey = jj + dy, ez = kk + dz;
+        if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
+        int64_t e = (int64_t)ex + (int64_t)N * ((int64_t)ey + (int64_t)N * ez);
+        for (int a = 0; a < 8; ++a) cand[nc++] = (int)elem_node(N, e, a);
+      }
+  qsort(cand, (size_t)nc, sizeof(int), cmp_int);
+  int n = 0;
+  for (int t = 0; t < nc; ++t)
+    if (n == 0 || cand[t] != cols[n - 1]) cols[n++] = cand[t];
+  return n;
+}
+
+/* CRS graph (Fig. "crs": row_map / col_entry), columns ascending per row,
+ * Dirichlet rows and columns kept in the pattern.  row_ptr has n+1 entries;
+ * col_idx must hold nnz = row_ptr[n] entries (query with orc_graph_nnz).   */
+int64_t orc_graph_nnz(int N) {
+  if (N < 1) return -1;
+  int cols[64];
+  int64_t n = orc_num_nodes(N), nnz = 0;
+  for (int64_t i = 0; i < n; ++i) nnz += row_columns(N, i, cols);
+  return nnz;
+}
+
+int orc_graph(int N, int32_t *row_ptr, int32_t *col_idx) {
+  if (N < 1 || !row_ptr || !col_idx) return ORC_E_ARG;
+  int cols[64];
+  int64_t n = orc_num_nodes(N), pos = 0;
+  row_ptr[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int c = row_columns(N, i, cols);
+    for (int t = 0; t < c; ++t) col_idx[pos + t] = cols[t];
+    pos += c;
+    row_ptr[i + 1] = (int32_t)pos;
+  }
+  return ORC_OK;
+}
+
+/* Position of column J inside row I (binary search over the sorted row). */
+static int64_t find_slot(const int32_t *row_ptr, const int32_t *col_idx, int64_t I, int64_t J) {
+  int64_t lo = row_ptr[I], hi = row_ptr[I + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (col_idx[mid] == J) return mid;
+    if (col_idx[mid] < J) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+/* ElemGraph(e, a, b) of Alg. "assembly": absolute CRS index of entry
+ * (NodeIndex(e,a), NodeIndex(e,b)).  Output [N^3][8][8].                  */
+int orc_elem_slot(int N, const int32_t *row_ptr, const int32_t *col_idx, int64_t *slot) {
+  if (N < 1) return ORC_E_ARG;
+  int64_t ne = orc_num_elems(N);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b) {
+        int64_t s = find_slot(row_ptr, col_idx, elem_node(N, e, a), elem_node(N, e, b));
+        if (s < 0) return ORC_E_ARG;
+        slot[(e * 8 + a) * 8 + b] = s;
+      }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Karhunen-Loeve coefficient (Sec. 4): kappa(x,y) = kappa0 +               */
+/* sigma * sum_i kappa_i(x) y_i, with kappa_i eigenfunctions of the          */
+/* exponential covariance exp(-|x-x'|_1 / L).                                */
+/* Readings: kappa_i = sqrt(lambda_i) phi_i of the unit-variance kernel      */
+/* (sigma in front of the sum carries the variance); the L1 distance makes   */
+/* the kernel a product of 1D kernels exp(-|t-t'|/L), so 3D modes are        */
+/* products of 1D modes on [0,1] and lambda_3D = product of 1D lambdas;      */
+/* modes are ranked by lambda descending, ties broken by ascending           */
+/* (ix,iy,iz), and each 3D lambda is formed from its three 1D factors taken  */
+/* in ascending index order so permuted triples tie exactly.                 */
+/* 1D eigenpairs on [-a,a] (a = 1/2 after centring t = x - 1/2, c = 1/L):    */
+/*   even: c - w tan(w a) = 0,  phi = cos(w t) / sqrt(a + sin(2wa)/(2w))     */
+/*   odd:  w + c tan(w a) = 0,  phi = sin(w t) / sqrt(a - sin(2wa)/(2w))     */
+/*   lambda = 2c / (w^2 + c^2).                                              */
+/* ------------------------------------------------------------------------ */
+
+/* plain bisection on [lo, hi] for a function with g(lo) < 0 < g(hi)
+ * after the sign normalisation sgn; run until the interval stops shrinking */
+static double bisect(double (*g)(double, double, double), double a, double c, double lo, double hi) {
+  double glo = g(lo, a, c);
+  for (int it = 0; it < 2000; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    double gm = g(mid, a, c);
+    if (gm == 0.0) return mid;
+    if ((gm < 0.0) == (glo < 0.0)) { lo = mid; glo = gm; } else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+static double even_eq(double w, double a, double c) { return c - w * tan(w * a); }
+static double odd_eq(double w, double a, double c) { return w + c * tan(w * a); }
+
+/* First K 1D eigenpairs on [0,1] in lambda-descending order.
+ * parity[k] = 0 (even / cosine) or 1 (odd / sine); nrm[k] = 1/sqrt(...)   */
+int orc_kl_1d(int K, double L, double *omega, double *lam, double *nrm, int32_t *parity) {
+  if (K < 1 || !(L > 0.0)) return ORC_E_ARG;
+  const double a = 0.5, c = 1.0 / L, pi = acos(-1.0);
+  for (int k = 0; k < K; ++k) {
+    int m = k / 2 + 1; /* m-th root of its parity */
+    double w;
+    if (k % 2 == 0) {
+      /* root in ((m-1) pi / a, (m - 1/2) pi / a) */
+      double lo = (m - 1) * pi / a, hi = (m - 0.5) * pi / a;
+      double eps = 1e-15 * hi;
+      w = bisect(even_eq, a, c, lo + (m == 1 ? 0.0 : eps), hi - eps);
+      nrm[k] = 1.0 / sqrt(a + sin(2.0 * w * a) / (2.0 * w));
+      parity[k] = 0;
+    } else {
+      double lo = (m - 0.5) * pi / a, hi = m * pi / a;
+      double eps = 1e-15 * hi;
+      w = bisect(odd_eq, a, c, lo + eps, hi - eps);
+      nrm[k] = 1.0 / sqrt(a - sin(2.0 * w * a) / (2.0 * w));
+      parity[k] = 1;
+    }
+    omega[k] = w;
+    lam[k] = 2.0 * c / (w * w + c * c);
+  }
+  return ORC_OK;
+}
+
+static double phi1d(double w, double nrm, int parity, double x) {
+  double t = x - 0.5;
+  return parity == 0 ? nrm * cos(w * t) : nrm * sin(w * t);
+}
+
+typedef struct { double lam; int i, j, k; } orc_triple;
+
+static int cmp_triple(const void *p, const void *q) {
+  const orc_triple *A = (const orc_triple *)p, *B = (const orc_triple *)q;
+  if (A->lam > B->lam) return -1;
+  if (A->lam < B->lam) return 1;
+  if (A->i != B->i) return A->i < B->i ? -1 : 1;
+  if (A->j != B->j) return A->j < B->j ? -1 : 1;
+  if (A->k != B->k) return A->k < B->k ? -1 : 1;
+  return 0;
+}
+
+static double lam_product(const double *lam1, int i, int j, int k) {
+  int v[3] = {i, j, k};
+  /* ascending index order */
+  for (int p = 0; p < 3; ++p)
+    for (int q = p + 1; q < 3; ++q)
+      if (v[q] < v[p]) { int t = v[p]; v[p] = v[q]; v[q] = t; }
+  return (lam1[v[0]] * lam1[v[1]]) * lam1[v[2]];
+}
+
+/* First M 3D modes: triples[m] = (ix, iy, iz) 1D ranks, lam3[m].
+ * A mode of rank m cannot use a 1D index >= M (the M modes (i,0,0), i < M,
+ * dominate it), so M 1D modes per axis suffice.                          */
+int orc_kl_modes(int M, double L, int32_t *triples, double *lam3) {
+  if (M < 1) return ORC_E_ARG;
+  double *w = malloc(sizeof(double) * M), *l1 = malloc(sizeof(double) * M), *nr = malloc(sizeof(double) * M);
+  int32_t *par = malloc(sizeof(int32_t) * M);
+  orc_triple *all = malloc(sizeof(orc_triple) * (size_t)M * M * M);
+  if (!w || !l1 || !nr || !par || !all) return ORC_E_NOMEM;
+  orc_kl_1d(M, L, w, l1, nr, par);
+  int64_t t = 0;
+  for (int i = 0; i < M; ++i)
+    for (int j = 0; j < M; ++j)
+      for (int k = 0; k < M; ++k) {
+        all[t].lam = lam_product(l1, i, j, k);
+        all[t].i = i; all[t].j = j; all[t].k = k;
+        ++t;
+      }
+  qsort(all, (size_t)t, sizeof(orc_triple), cmp_triple);
+  for (int m = 0; m < M; ++m) {
+    triples[3 * m] = all[m].i; triples[3 * m + 1] = all[m].j; triples[3 * m + 2] = all[m].k;
+    lam3[m] = all[m].lam;
+  }
+  free(w); free(l1); free(nr); free(par); free(all);
+  return ORC_OK;
+}
+
+/* kappa at arbitrary points pts[npts][3] for one sample y = xi[M]. */
+int orc_kl_coef_points(int M, double L, double kappa0, double sigma, const double *xi,
+                       int64_t npts, const double *pts, double *out) {
+  if (M < 0 || (M > 0 && !xi)) return ORC_E_ARG;
+  int Mk = M > 0 ? M : 1;
+  double *w = malloc(sizeof(double) * Mk), *l1 = malloc(sizeof(double) * Mk), *nr = malloc(sizeof(double) * Mk);
+  int32_t *par = malloc(sizeof(int32_t) * Mk), *tr = malloc(sizeof(int32_t) * 3 * Mk);
+  double *l3 = malloc(sizeof(double) * Mk);
+  if (M > 0) {
+    orc_kl_1d(M, L, w, l1, nr, par);
+    orc_kl_modes(M, L, tr, l3);
+  }
+  for (int64_t p = 0; p < npts; ++p) {
+    double sum = 0.0;
+    for (int m = 0; m < M; ++m) {
+      int i = tr[3 * m], j = tr[3 * m + 1], k = tr[3 * m + 2];
+      double phi = phi1d(w[i], nr[i], par[i], pts[3 * p]) *
+                   phi1d(w[j], nr[j], par[j], pts[3 * p + 1]) *
+                   phi1d(w[k], nr[k], par[k], pts[3 * p + 2]);
+      sum += sqrt(l3[m]) * phi * xi[m];
+    }
+    out[p] = kappa0 + sigma * sum;
+  }
+  free(w); free(l1); free(nr); free(par); free(tr); free(l3);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quadrature (Alg. "assembly": N_qp = 8).  Reading: the tensor 2x2x2        */
+/* Gauss-Legendre rule; abscissae (1 -+ 1/sqrt 3)/2 on [0,1], weight 1/2     */
+/* each; qp index q = qx + 2 qy + 4 qz; physical point                       */
+/* ((ex + g_qx)/N, (ey + g_qy)/N, (ez + g_qz)/N), weight h^3/8.              */
+/* ------------------------------------------------------------------------ */
+
+static double gauss01(int q) {
+  double r = 1.0 / sqrt(3.0);
+  return q == 0 ? 0.5 * (1.0 - r) : 0.5 * (1.0 + r);
+}
+
+/* Coordinates of all quadrature points, [N^3][8][3]. */
+int orc_qp_coords(int N, double *pts) {
+  if (N < 1) return ORC_E_ARG;
+  int64_t ne = orc_num_elems(N);
+  for (int64_t e = 0; e < ne; ++e) {
+    int ex = (int)(e % N), ey = (int)((e / N) % N), ez = (int)(e / ((int64_t)N * N));
+    for (int q = 0; q < 8; ++q) {
+      double *p = pts + (e * 8 + q) * 3;
+      p[0] = ((double)ex + gauss01(q & 1)) / (double)N;
+      p[1] = ((double)ey + gauss01((q >> 1) & 1)) / (double)N;
+      p[2] = ((double)ez + gauss01((q >> 2) & 1)) / (double)N;
+    }
+  }
+  return ORC_OK;
+}
+
+/* kappa at every quadrature point of every element, [N^3][8]. */
+int orc_kl_coef_qp(int N, int M, double L, double kappa0, double sigma, const double *xi, double *acoef) {
+  if (N < 1) return ORC_E_ARG;
+  int64_t np = orc_num_elems(N) * 8;
+  double *pts = malloc(sizeof(double) * 3 * (size_t)np);
+  if (!pts) return ORC_E_NOMEM;
+  orc_qp_coords(N, pts);
+  int rc = orc_kl_coef_points(M, L, kappa0, sigma, xi, np, pts, acoef);
+  free(pts);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scalar assembly of one sample (Alg. "assembly", with alpha = beta = 0 so  */
+/* the residual is linear and the Jacobian is the stiffness matrix).         */
+/*   K_e[a][b] = sum_q kappa(x_q) grad N_a(x_q) . grad N_b(x_q) w_q          */
+/*   f_e[a]    = sum_q f(x_q) N_a(x_q) w_q                                   */
+/* Shape functions N_a = l_{ax}(s) l_{ay}(t) l_{az}(u), l0 = 1-t, l1 = t;    */
+/* on the uniform mesh grad_x = grad_ref / h.  K_e is formed for a <= b and  */
+/* mirrored.  The scatter runs over elements in ascending id, so each global */
+/* entry is 0 + (contributions in ascending element order).                  */
+/* Source: src_kind 0 -> f = fconst; 1 -> f = 3 pi^2 sin(pi x)sin(pi y)      */
+/* sin(pi z) (manufactured solution u = sin sin sin at kappa = 1).           */
+/* Dirichlet reading (u = 0 on the boundary): boundary rows become identity  */
+/* rows, interior rows drop their boundary columns (stored as zeros), and    */
+/* boundary load entries are zero.                                            */
+/* ------------------------------------------------------------------------ */
+
+static double lfun(int a, double t) { return a ? t : 1.0 - t; }
+static double dlfun(int a) { return a ? 1.0 : -1.0; }
+
+int orc_assemble_scalar(int N, const int32_t *row_ptr, const int32_t *col_idx,
+                        const double *acoef, int src_kind, double fconst, int dirichlet,
+                        double *values, double *rhs) {
+  if (N < 1 || !row_ptr || !col_idx || !acoef || !values || !rhs) return ORC_E_ARG;
+  const double h = 1.0 / (double)N;
+  const double wq = h * h * h / 8.0;
+  const double pi = acos(-1.0);
+  int64_t n = orc_num_nodes(N), nnz = row_ptr[n], ne = orc_num_elems(N);
+  for (int64_t k = 0; k < nnz; ++k) values[k] = 0.0;
+  for (int64_t i = 0; i < n; ++i) rhs[i] = 0.0;
+
+  /* reference values and gradients at the 8 quadrature points */
+  double Nq[8][8], G[8][8][3];
+  for (int q = 0; q < 8; ++q) {
+    double s = gauss01(q & 1), t = gauss01((q >> 1) & 1), u = gauss01((q >> 2) & 1);
+    for (int a = 0; a < 8; ++a) {
+      int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      Nq[q][a] = lfun(ax, s) * lfun(ay, t) * lfun(az, u);
+      G[q][a][0] = dlfun(ax) * lfun(ay, t) * lfun(az, u) / h;
+      G[q][a][1] = lfun(ax, s) * dlfun(ay) * lfun(az, u) / h;
+      G[q][a][2] = lfun(ax, s) * lfun(ay, t) * dlfun(az) / h;
+    }
+  }
+  for (int64_t e = 0; e < ne; ++e) {
+    double Ke[8][8], fe[8];
+    for (int a = 0; a < 8; ++a) {
+      for (int b = a; b < 8; ++b) {
+        double sum = 0.0;
+        for (int q = 0; q < 8; ++q) {
+          double dot = G[q][a][0] * G[q][b][0] + G[q][a][1] * G[q][b][1] + G[q][a][2] * G[q][b][2];
+          sum += acoef[e * 8 + q] * dot * wq;
+        }
+        Ke[a][b] = sum;
+        Ke[b][a] = sum;
+      }
+      double fs = 0.0;
+      for (int q = 0; q < 8; ++q) {
+        double f = fconst;
+        if (src_kind == 1) {
+          int ex = (int)(e % N), ey = (int)((e / N) % N), ez = (int)(e / ((int64_t)N * N));
+          double x = ((double)ex + gauss01(q & 1)) / (double)N;
+          double y = ((double)ey + gauss01((q >> 1) & 1)) / (double)N;
+          double z = ((double)ez + gauss01((q >> 2) & 1)) / (double)N;
+          f = 3.0 * pi * pi * sin(pi * x) * sin(pi * y) * sin(pi * z);
+        }
+        fs += f * Nq[q][a] * wq;
+      }
+      fe[a] = fs;
+    }
+    for (int a = 0; a < 8; ++a) {
+      int64_t I = elem_node(N, e, a);
+      rhs[I] += fe[a];
+      for (int b = 0; b < 8; ++b) {
+        int64_t slot = find_slot(row_ptr, col_idx, I, elem_node(N, e, b));
+        values[slot] += Ke[a][b];
+      }
+    }
+  }
+  if (dirichlet) {
+    for (int64_t i = 0; i < n; ++i) {
+      int bi = is_boundary_node(N, i);
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        if (bi) values[k] = (col_idx[k] == i) ? 1.0 : 0.0;
+        else if (is_boundary_node(N, col_idx[k])) values[k] = 0.0;
+      }
+      if (bi) rhs[i] = 0.0;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Ensemble assembly in the commuted layout (Eq. kron_sys_commuted):
+ * values[k*s + e], rhs[i*s + e].  Plainly a loop over samples, each one a
+ * scalar KL evaluation plus scalar assembly, interleaved afterwards.      */
+int orc_assemble_ensemble(int N, const int32_t *row_ptr, const int32_t *col_idx,
+                          int M, double L, double kappa0, double sigma, double fconst,
+                          int s, const double *xi, double *values, double *rhs) {
+  if (N < 1 || s < 1) return ORC_E_ARG;
+  int64_t n = orc_num_nodes(N), nnz = row_ptr[n], ne = orc_num_elems(N);
+  int rc = ORC_OK;
+  #pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < s; ++e) {
+    double *ac = malloc(sizeof(double) * 8 * (size_t)ne);
+    double *v = malloc(sizeof(double) * (size_t)nnz);
+    double *f = malloc(sizeof(double) * (size_t)n);
+    if (!ac || !v || !f) { rc = ORC_E_NOMEM; free(ac); free(v); free(f); continue; }
+    orc_kl_coef_qp(N, M, L, kappa0, sigma, xi + (int64_t)e * M, ac);
+    orc_assemble_scalar(N, row_ptr, col_idx, ac, 0, fconst, 1, v, f);
+    for (int64_t k = 0; k < nnz; ++k) values[k * s + e] = v[k];
+    for (int64_t i = 0; i < n; ++i) rhs[i * s + e] = f[i];
+    free(ac); free(v); free(f);
+  }
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sparse products                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* z = A x for one scalar matrix (Fig. "crs"). */
+void orc_spmv(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+              const double *x, double *z) {
+  for (int64_t row = 0; row < n; ++row) {
+    double sum = 0.0;
+    for (int64_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) sum += values[k] * x[col_idx[k]];
+    z[row] = sum;
+  }
+}
+
+/* Ensemble product in the commuted layout (Fig. "ensemble_crs"):
+ * sample loop innermost, one partial sum per sample, values[k*s+e].       */
+void orc_ens_spmv(int64_t n, int s, const int32_t *row_ptr, const int32_t *col_idx,
+                  const double *values, const double *x, double *z) {
+  double *sum = malloc(sizeof(double) * (size_t)s);
+  for (int64_t row = 0; row < n; ++row) {
+    for (int e = 0; e < s; ++e) sum[e] = 0.0;
+    for (int64_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
+      int64_t col = col_idx[k];
+      for (int e = 0; e < s; ++e) sum[e] += values[k * s + e] * x[col * s + e];
+    }
+    for (int e = 0; e < s; ++e) z[row * s + e] = sum[e];
+  }
+  free(sum);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Jacobi-preconditioned CG for one sample (Sec. 3.4: CG; preconditioner     */
+/* D = diag(A), the trivial instance of M_c = sum M_i (x) e_i e_i^T).        */
+/* Readings: stop when the recursive residual satisfies |r|_2 <= rtol |b|_2  */
+/* (one iteration = one product q = A p); |b| = 0 gives x = 0; a start with  */
+/* |r0| <= rtol |b| takes 0 iterations; p.q <= 0 or non-finite scalars stop  */
+/* the sample with a breakdown / non-finite status.  fixed_iters >= 0 runs   */
+/* exactly that many iterations with the tolerance test switched off (used   */
+/* to compare against another implementation at equal iteration counts).     */
+/* rel_res is the true residual |b - A x| / |b| of the returned x.           */
+/* ------------------------------------------------------------------------ */
+
+static double dot(int64_t n, const double *u, const double *v) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += u[i] * v[i];
+  return s;
+}
+
+int orc_pcg(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+            const double *b, double *x, double rtol, int max_iter, int fixed_iters,
+            int32_t *iters_out, double *rel_res_out, int32_t *status_out) {
+  double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
+  double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
+  double *dinv = malloc(sizeof(double) * (size_t)n);
+  if (!r || !z || !p || !q || !dinv) return ORC_E_NOMEM;
+  int status = ORC_CONVERGED, iters = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double d = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+      if (col_idx[k] == i) d = values[k];
+    dinv[i] = 1.0 / d;
+  }
+  double nb = sqrt(dot(n, b, b));
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    *iters_out = 0; *rel_res_out = 0.0; *status_out = ORC_CONVERGED;
+    free(r); free(z); free(p); free(q); free(dinv);
+    return ORC_OK;
+  }
+  orc_spmv(n, row_ptr, col_idx, values, x, q);
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  int limit = fixed_iters >= 0 ? fixed_iters : max_iter;
+  int test = fixed_iters < 0;
+  if (test && sqrt(dot(n, r, r)) <= rtol * nb) {
+    limit = 0;
+  } else {
+    for (int64_t i = 0; i < n; ++i) { z[i] = dinv[i] * r[i]; p[i] = z[i]; }
+    double rho = dot(n, r, z);
+    status = ORC_MAXITER;
+    for (int k = 1; k <= limit; ++k) {
+      orc_spmv(n, row_ptr, col_idx, values, p, q);
+      double eta = dot(n, p, q);
+      if (!isfinite(eta) || !isfinite(rho)) { status = ORC_NONFINITE; break; }
+      if (!(eta > 0.0)) { status = ORC_BREAKDOWN; break; }
+      double alpha = rho / eta;
+      for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+      iters = k;
+      double rr = dot(n, r, r);
+      if (!isfinite(rr)) { status = ORC_NONFINITE; break; }
+      if (test && sqrt(rr) <= rtol * nb) { status = ORC_CONVERGED; break; }
+      if (!test && k == limit) { status = ORC_CONVERGED; break; }
+      for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+      double rho_new = dot(n, r, z);
+      double beta = rho_new / rho;
+      for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+      rho = rho_new;
+    }
+    if (!test && limit == 0) status = ORC_CONVERGED;
+  }
+  orc_spmv(n, row_ptr, col_idx, values, x, q);
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  *iters_out = iters;
+  *rel_res_out = sqrt(dot(n, r, r)) / nb;
+  *status_out = status;
+  free(r); free(z); free(p); free(q); free(dinv);
+  return ORC_OK;
+}
+
+/* Ensemble solve with per-sample scalars: by the block-diagonal structure
+ * of the Kronecker system (Eq. kron_sys) this is exactly s scalar solves.
+ * values [nnz][s], b and x [n][s]; fixed_iters nullable ([s], -1 = off).  */
+int orc_ens_pcg(int64_t n, int s, const int32_t *row_ptr, const int32_t *col_idx,
+                const double *values, const double *b, double *x, double rtol, int max_iter,
+                const int32_t *fixed_iters, int32_t *iters, double *rel_res, int32_t *status) {
+  int64_t nnz = row_ptr[n];
+  int rc = ORC_OK;
+  #pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < s; ++e) {
+    double *v = malloc(sizeof(double) * (size_t)nnz);
+    double *be = malloc(sizeof(double) * (size_t)n), *xe = malloc(sizeof(double) * (size_t)n);
+    if (!v || !be || !xe) { rc = ORC_E_NOMEM; free(v); free(be); free(xe); continue; }
+    for (int64_t k = 0; k < nnz; ++k) v[k] = values[k * s + e];
+    for (int64_t i = 0; i < n; ++i) { be[i] = b[i * s + e]; xe[i] = x[i * s + e]; }
+    int r = orc_pcg(n, row_ptr, col_idx, v, be, xe, rtol, max_iter,
+                    fixed_iters ? fixed_iters[e] : -1, &iters[e], &rel_res[e], &status[e]);
+    if (r) rc = r;
+    for (int64_t i = 0; i < n; ++i) x[i * s + e] = xe[i];
+    free(v); free(be); free(xe);
+  }
+  return rc;
+}
+
+/* One complete sample from scratch: graph, KL coefficient, assembly and
+ * Jacobi-CG from a zero guess.  x [n] out.  Used for full-size checks and
+ * as the CPU baseline.                                                    */
+int orc_solve_sample(int N, int M, double L, double kappa0, double sigma, double fconst,
+                     const double *xi, double rtol, int max_iter, double *x,
+                     int32_t *iters, double *rel_res, int32_t *status) {
+  int64_t n = orc_num_nodes(N), ne = orc_num_elems(N);
+  int64_t nnz = orc_graph_nnz(N);
+  int32_t *rp = malloc(sizeof(int32_t) * (size_t)(n + 1)), *ci = malloc(sizeof(int32_t) * (size_t)nnz);
+  double *ac = malloc(sizeof(double) * 8 * (size_t)ne), *v = malloc(sizeof(double) * (size_t)nnz);
+  double *b = malloc(sizeof(double) * (size_t)n);
+  if (!rp || !ci || !ac || !v || !b) return ORC_E_NOMEM;
+  orc_graph(N, rp, ci);
+  orc_kl_coef_qp(N, M, L, kappa0, sigma, xi, ac);
+  orc_assemble_scalar(N, rp, ci, ac, 0, fconst, 1, v, b);
+  for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+  int rc = orc_pcg(n, rp, ci, v, b, x, rtol, max_iter, -1, iters, rel_res, status);
+  free(rp); free(ci); free(ac); free(v); free(b);
+  return rc;
+}
+
+/* Several samples of orc_solve_sample in parallel, one per thread.
+ * xi [count][M]; x [count][n] (sample-major, nullable); returns the number
+ * of threads used in *threads_used.                                        */
+int orc_solve_samples(int N, int M, double L, double kappa0, double sigma, double fconst,
+                      int count, const double *xi, double rtol, int max_iter, double *x,
+                      int32_t *iters, double *rel_res, int32_t *status, int32_t *threads_used) {
+  int64_t n = orc_num_nodes(N);
+  int rc = ORC_OK;
+  int used = 1;
+  #pragma omp parallel
+  {
+#ifdef _OPENMP
+    #pragma omp single
+    used = omp_get_num_threads();
+#endif
+    #pragma omp for schedule(dynamic, 1)
+    for (int e = 0; e < count; ++e) {
+      double *xe = x ? x + (int64_t)e * n : malloc(sizeof(double) * (size_t)n);
+      int r = orc_solve_sample(N, M, L, kappa0, sigma, fconst, xi + (int64_t)e * M, rtol, max_iter,
+                               xe, &iters[e], &rel_res[e], &status[e]);
+      if (r) rc = r;
+      if (!x) free(xe);
+    }
+  }
+  if (threads_used) *threads_used = used < count ? used : count;
+  return rc;
+}
+
+/* True residual |b - A x| / |b| per sample in the commuted layout. */
+void orc_ens_true_residual(int64_t n, int s, const int32_t *row_ptr, const int32_t *col_idx,
+                           const double *values, const double *b, const double *x, double *rel) {
+  double *ax = malloc(sizeof(double) * (size_t)(n * s));
+  orc_ens_spmv(n, s, row_ptr, col_idx, values, x, ax);
+  for (int e = 0; e < s; ++e) {
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double d = b[i * s + e] - ax[i * s + e];
+      rr += d * d;
+      bb += b[i * s + e] * b[i * s + e];
+    }
+    rel[e] = bb > 0.0 ? sqrt(rr) / sqrt(bb) : sqrt(rr);
+  }
+  free(ax);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense brute force for tiny meshes                                         */
+/* ------------------------------------------------------------------------ */
+
+void orc_crs_to_dense(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                      const double *values, double *dense) {
+  for (int64_t i = 0; i < n * n; ++i) dense[i] = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) dense[i * n + col_idx[k]] = values[k];
+}
+
+/* Cholesky A = L L^T of a dense SPD matrix (overwritten by L in its lower
+ * triangle), then forward and back substitution.  Returns 1 if a pivot is
+ * not positive (A is not SPD), 0 on success.                               */
+int orc_cholesky_solve(int64_t n, double *A, const double *b, double *x) {
+  for (int64_t j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int64_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+    if (!(d > 0.0)) return 1;
+    double ljj = sqrt(d);
+    A[j * n + j] = ljj;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double v = A[i * n + j];
+      for (int64_t k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+      A[i * n + j] = v / ljj;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    double v = b[i];
+    for (int64_t k = 0; k < i; ++k) v -= A[i * n + k] * x[k];
+    x[i] = v / A[i * n + i];
+  }
+  for (int64_t i = n - 1; i >= 0; --i) {
+    double v = x[i];
+    for (int64_t k = i + 1; k < n; ++k) v -= A[k * n + i] * x[k];
+    x[i] = v / A[i * n + i];
+  }
+  return 0;
+}
+
+int orc_version(void) { return 1; }

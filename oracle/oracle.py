@@ -1,0 +1,273 @@
+"""ctypes front end of the FP64 CPU oracle (``ens_oracle.c``).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this module.  It never imports the GPU
+package, and the GPU package never imports it.
+
+Every function follows one passage of Phipps et al. (arXiv 1511.03703); the
+C source names the passage next to each routine.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ens_oracle.c")
+_LIB = os.path.join(_HERE, "libensoracle.so")
+
+CONVERGED, MAXITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-Wall", "-Wno-unused-function", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        L.orc_num_nodes.restype = i64
+        L.orc_num_nodes.argtypes = [ctypes.c_int]
+        L.orc_num_elems.restype = i64
+        L.orc_num_elems.argtypes = [ctypes.c_int]
+        L.orc_graph_nnz.restype = i64
+        L.orc_graph_nnz.argtypes = [ctypes.c_int]
+        L.orc_graph.argtypes = [ctypes.c_int, vp, vp]
+        L.orc_elem_slot.argtypes = [ctypes.c_int, vp, vp, vp]
+        L.orc_kl_1d.argtypes = [ctypes.c_int, dbl, vp, vp, vp, vp]
+        L.orc_kl_modes.argtypes = [ctypes.c_int, dbl, vp, vp]
+        L.orc_kl_coef_points.argtypes = [ctypes.c_int, dbl, dbl, dbl, vp, i64, vp, vp]
+        L.orc_qp_coords.argtypes = [ctypes.c_int, vp]
+        L.orc_kl_coef_qp.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, vp, vp]
+        L.orc_assemble_scalar.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, vp, vp]
+        L.orc_assemble_ensemble.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, dbl, dbl, dbl, dbl,
+                                            ctypes.c_int, vp, vp, vp]
+        L.orc_spmv.restype = None
+        L.orc_spmv.argtypes = [i64, vp, vp, vp, vp, vp]
+        L.orc_ens_spmv.restype = None
+        L.orc_ens_spmv.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_pcg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.orc_ens_pcg.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, dbl, ctypes.c_int, vp, vp, vp, vp]
+        L.orc_solve_sample.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, dbl,
+                                       ctypes.c_int, vp, vp, vp, vp]
+        L.orc_solve_samples.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int,
+                                        vp, dbl, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_ens_true_residual.restype = None
+        L.orc_ens_true_residual.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.orc_crs_to_dense.restype = None
+        L.orc_crs_to_dense.argtypes = [i64, vp, vp, vp, vp]
+        L.orc_cholesky_solve.argtypes = [i64, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError(f"oracle call failed with status {rc}")
+
+
+# --------------------------------------------------------------------- mesh
+
+
+def num_nodes(N: int) -> int:
+    return int(lib().orc_num_nodes(N))
+
+
+def num_elems(N: int) -> int:
+    return int(lib().orc_num_elems(N))
+
+
+def graph(N: int):
+    """CRS graph of the Q1 stiffness matrix (Fig. crs), columns ascending."""
+    n = num_nodes(N)
+    nnz = int(lib().orc_graph_nnz(N))
+    rp = np.zeros(n + 1, np.int32)
+    ci = np.zeros(nnz, np.int32)
+    _check(lib().orc_graph(N, _p(rp), _p(ci)))
+    return rp, ci
+
+
+def elem_slot(N: int, rp, ci):
+    """ElemGraph map of Alg. assembly: CRS index of (node(e,a), node(e,b))."""
+    out = np.zeros((num_elems(N), 8, 8), np.int64)
+    _check(lib().orc_elem_slot(N, _p(rp), _p(ci), _p(out)))
+    return out
+
+
+# ----------------------------------------------------------------------- KL
+
+
+def kl_1d(K: int, L: float = 1.0):
+    """First K 1D eigenpairs of exp(-|t-t'|/L) on [0,1], lambda descending."""
+    w = np.zeros(K)
+    lam = np.zeros(K)
+    nrm = np.zeros(K)
+    par = np.zeros(K, np.int32)
+    _check(lib().orc_kl_1d(K, L, _p(w), _p(lam), _p(nrm), _p(par)))
+    return w, lam, nrm, par
+
+
+def kl_modes(M: int, L: float = 1.0):
+    tr = np.zeros((M, 3), np.int32)
+    lam = np.zeros(M)
+    _check(lib().orc_kl_modes(M, L, _p(tr), _p(lam)))
+    return tr, lam
+
+
+def kl_coef_points(M, L, kappa0, sigma, xi, pts):
+    xi = _f64(xi).reshape(-1)
+    pts = _f64(pts).reshape(-1, 3)
+    out = np.zeros(pts.shape[0])
+    _check(lib().orc_kl_coef_points(M, L, kappa0, sigma, _p(xi), pts.shape[0], _p(pts), _p(out)))
+    return out
+
+
+def qp_coords(N):
+    out = np.zeros((num_elems(N), 8, 3))
+    _check(lib().orc_qp_coords(N, _p(out)))
+    return out
+
+
+def kl_coef_qp(N, M, L, kappa0, sigma, xi):
+    out = np.zeros((num_elems(N), 8))
+    xi = _f64(xi).reshape(-1)
+    _check(lib().orc_kl_coef_qp(N, M, L, kappa0, sigma, _p(xi), _p(out)))
+    return out
+
+
+# ----------------------------------------------------------------- assembly
+
+
+def assemble_scalar(N, rp, ci, acoef, src_kind=0, fconst=1.0, dirichlet=True):
+    """One sample's A (CRS values) and load vector f from the coefficient at
+    the quadrature points, acoef[N^3][8] (Alg. assembly)."""
+    n = num_nodes(N)
+    vals = np.zeros(int(rp[-1]))
+    rhs = np.zeros(n)
+    acoef = _f64(acoef)
+    _check(lib().orc_assemble_scalar(N, _p(rp), _p(ci), _p(acoef), src_kind, fconst, int(dirichlet),
+                                     _p(vals), _p(rhs)))
+    return vals, rhs
+
+
+def assemble_ensemble(N, rp, ci, M, L, kappa0, sigma, fconst, xi):
+    """values [nnz][s] and rhs [n][s] in the commuted layout."""
+    xi = _f64(xi)
+    s = xi.shape[0]
+    n = num_nodes(N)
+    vals = np.zeros((int(rp[-1]), s))
+    rhs = np.zeros((n, s))
+    _check(lib().orc_assemble_ensemble(N, _p(rp), _p(ci), M, L, kappa0, sigma, fconst, s, _p(xi),
+                                       _p(vals), _p(rhs)))
+    return vals, rhs
+
+
+# ----------------------------------------------------------------- products
+
+
+def spmv(rp, ci, vals, x):
+    n = rp.shape[0] - 1
+    x = _f64(x)
+    z = np.zeros(n)
+    lib().orc_spmv(n, _p(rp), _p(ci), _p(_f64(vals)), _p(x), _p(z))
+    return z
+
+
+def ens_spmv(rp, ci, vals, x):
+    n = rp.shape[0] - 1
+    s = vals.shape[1]
+    z = np.zeros((n, s))
+    lib().orc_ens_spmv(n, s, _p(rp), _p(ci), _p(_f64(vals)), _p(_f64(x)), _p(z))
+    return z
+
+
+# ------------------------------------------------------------------- solves
+
+
+def pcg(rp, ci, vals, b, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=-1):
+    n = rp.shape[0] - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    it = np.zeros(1, np.int32)
+    rr = np.zeros(1)
+    st = np.zeros(1, np.int32)
+    _check(lib().orc_pcg(n, _p(rp), _p(ci), _p(_f64(vals)), _p(_f64(b)), _p(x), rtol, max_iter,
+                         fixed_iters, _p(it), _p(rr), _p(st)))
+    return x, int(it[0]), float(rr[0]), int(st[0])
+
+
+def ens_pcg(rp, ci, vals, b, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=None):
+    n = rp.shape[0] - 1
+    s = vals.shape[1]
+    x = np.zeros((n, s)) if x0 is None else _f64(x0).copy()
+    it = np.zeros(s, np.int32)
+    rr = np.zeros(s)
+    st = np.zeros(s, np.int32)
+    fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, np.int32)
+    _check(lib().orc_ens_pcg(n, s, _p(rp), _p(ci), _p(_f64(vals)), _p(_f64(b)), _p(x), rtol, max_iter,
+                             None if fi is None else _p(fi), _p(it), _p(rr), _p(st)))
+    return x, it, rr, st
+
+
+def solve_samples(N, M, L, kappa0, sigma, fconst, xi, rtol, max_iter=10000, want_x=True):
+    """Independent per-sample graph + KL + assembly + Jacobi-CG, one sample per
+    OpenMP thread.  Returns (x [count][n] or None, iters, rel_res, status, threads)."""
+    xi = _f64(xi)
+    count = xi.shape[0]
+    n = num_nodes(N)
+    x = np.zeros((count, n)) if want_x else None
+    it = np.zeros(count, np.int32)
+    rr = np.zeros(count)
+    st = np.zeros(count, np.int32)
+    th = np.zeros(1, np.int32)
+    _check(lib().orc_solve_samples(N, M, L, kappa0, sigma, fconst, count, _p(xi), rtol, max_iter,
+                                   None if x is None else _p(x), _p(it), _p(rr), _p(st), _p(th)))
+    return x, it, rr, st, int(th[0])
+
+
+def ens_true_residual(rp, ci, vals, b, x):
+    n = rp.shape[0] - 1
+    s = vals.shape[1]
+    rel = np.zeros(s)
+    lib().orc_ens_true_residual(n, s, _p(rp), _p(ci), _p(_f64(vals)), _p(_f64(b)), _p(_f64(x)), _p(rel))
+    return rel
+
+
+def crs_to_dense(rp, ci, vals):
+    n = rp.shape[0] - 1
+    d = np.zeros((n, n))
+    lib().orc_crs_to_dense(n, _p(rp), _p(ci), _p(_f64(vals)), _p(d))
+    return d
+
+
+def cholesky_solve(A, b):
+    """Returns (x, ok): ok is False when a pivot is not positive (not SPD)."""
+    A = _f64(A).copy()
+    n = A.shape[0]
+    x = np.zeros(n)
+    rc = lib().orc_cholesky_solve(n, _p(A), _p(_f64(b)), _p(x))
+    return x, rc == 0
