@@ -1,0 +1,253 @@
+/*
+ * ens.h -- C ABI of libens, an MI355X (gfx950) implementation of embedded
+ * ensemble propagation for the sampled diffusion problem
+ *     -div(kappa(x,y) grad u) = f  on D = [0,1]^3,  u = 0 on the boundary,
+ * discretised with trilinear (Q1) hexahedra (Phipps et al., arXiv 1511.03703,
+ * Sec. 4, with alpha = beta = 0 so the system is linear, symmetric and
+ * positive definite).
+ *
+ * s samples y_1..y_s share one CRS graph.  Following the commuted Kronecker
+ * system (Sec. 2, Eq. kron_sys_commuted) every matrix value and vector entry
+ * is an s-long ensemble stored contiguously:
+ *     values[k*s + e]   (k = CRS entry, e = sample)     "[nnz][s]"
+ *     x[i*s + e]        (i = node)                      "[n][s]"
+ *     xi[e*M + m]       (KL inputs of sample e)         "[s][M]"
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked (device) are device memory the caller allocated and
+ *     owns; the library never frees them and keeps no reference after the
+ *     call.  Pointers marked (host) are host memory.
+ *   - Device buffers holding ensembles must be 16-byte aligned.
+ *   - Work is enqueued on `stream` (a hipStream_t) in stream order.  Entry
+ *     points that return results on the host (ens_cg, ens_scalar_cg,
+ *     ens_solve_batch) synchronise that stream before returning; the others
+ *     never synchronise.
+ *   - Errors are reported by the return value, never by aborting: arguments
+ *     are validated on the host before any launch (ENS_E_ARG,
+ *     ENS_E_UNSUPPORTED, ENS_E_RANGE); HIP failures return ENS_E_HIP.  A
+ *     text description of the last error of the calling thread is available
+ *     from ens_last_error().  Numerical outcomes of solves are reported per
+ *     sample in ens_cg_stat.status.
+ *   - Indices are int32 (4 bytes per column entry, as in the paper's byte
+ *     model, Sec. 4); all value offsets are computed in 64-bit.
+ *   - Supported ensemble sizes s: 4, 8, 16, 32 (compile-time instantiations,
+ *     the role explicit template instantiation plays in Sec. 3.6).
+ */
+#ifndef ENS_H
+#define ENS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ens_status;
+enum {
+  ENS_OK = 0,
+  ENS_W_NOT_CONVERGED = 1, /* a solve finished but some sample did not converge */
+  ENS_E_ARG = -1,          /* null / misaligned pointer, bad size or option     */
+  ENS_E_UNSUPPORTED = -2,  /* ensemble size or dtype not compiled in            */
+  ENS_E_HIP = -3,          /* a HIP runtime call or kernel launch failed        */
+  ENS_E_NOMEM = -4,        /* caller workspace smaller than required            */
+  ENS_E_RANGE = -5         /* sizes beyond the 32-bit index range               */
+};
+
+/* per-sample outcome of a solve (ens_cg_stat.status) */
+enum {
+  ENS_SAMPLE_CONVERGED = 0,
+  ENS_SAMPLE_MAXITER = 1,   /* iteration cap reached                            */
+  ENS_SAMPLE_BREAKDOWN = 2, /* p.Ap <= 0: the sample's matrix is not SPD        */
+  ENS_SAMPLE_NONFINITE = 3, /* NaN or Inf in a scalar of the iteration          */
+  ENS_SAMPLE_STAGNATED = 4  /* refinement: outer residual stopped decreasing     */
+};
+
+typedef enum { ENS_F64 = 0, ENS_F32 = 1 } ens_dtype;
+
+/* CRS graph (Sec. 2, Fig. "crs"): row_ptr[n+1], col_idx[nnz], columns
+ * ascending within a row.  Both arrays are device memory. */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+} ens_graph;
+
+/* Diffusion coefficient (Sec. 4): kappa(x,y) = kappa0 + sigma *
+ * sum_{m<M} sqrt(lambda_m) phi_m(x) y_m with (lambda_m, phi_m) the
+ * eigenpairs of exp(-|x-x'|_1 / L) on [0,1]^3 ranked by lambda descending
+ * (ties by ascending 1D index triple); source f is a constant. */
+typedef struct {
+  int32_t M;
+  double L;
+  double kappa0;
+  double sigma;
+  double f;
+} ens_problem;
+
+const char* ens_last_error(void);
+const char* ens_status_string(ens_status st);
+int32_t ens_abi_version(void);
+
+/* ------------------------------------------------------------ mesh/graph */
+
+/* Sizes of the N x N x N element mesh of the unit cube (host, no GPU use):
+ * n = (N+1)^3 nodes, nnz = (3N+1)^3 stored entries (full 27-point pattern,
+ * Dirichlet rows and columns kept), N^3 elements.  ENS_E_RANGE if nnz*32
+ * exceeds the 64-bit range or n exceeds int32. */
+ens_status ens_mesh_sizes(int32_t N, int64_t* n, int64_t* nnz, int64_t* n_elem);
+
+/* CRS graph of the Q1 stiffness matrix (Fig. "crs"; NodeIndex/ElemGraph
+ * maps of Alg. "assembly").  Node (i,j,k) has id i + (N+1)(j + (N+1)k);
+ * row i lists, ascending, every node that shares an element with i.
+ * row_ptr (device) [n+1], col_idx (device) [nnz].  Never synchronises. */
+ens_status ens_graph_build(int32_t N, int32_t* row_ptr, int32_t* col_idx, hipStream_t stream);
+
+/* ------------------------------------------------------------------- KL */
+
+/* Bytes of the device KL table for an N-element mesh and M terms. */
+ens_status ens_kl_bytes(int32_t N, int32_t M, size_t* bytes);
+
+/* Build the KL table on the device (Sec. 4, KL expansion of kappa): the
+ * first M 1D eigenpairs of exp(-|t-t'|/L) on [0,1], the top-M 3D modes,
+ * and the 1D eigenfunctions at the 2N Gauss abscissae of each axis.
+ * Layout of `kl` (device, ens_kl_bytes bytes, 16-byte aligned):
+ *   double sqrt_lam3[M]; double lam3[M]; double omega[M]; double lam1[M];
+ *   double norm1[M]; int32 parity1[M]; int32 triple[M][3];
+ *   (padding to 8 bytes) double phi1d[M][2N]   (phi of 1D mode k at
+ *   abscissa (e + g_q)/N, index 2e+q, g_0 < g_1 the 2-point Gauss nodes). */
+ens_status ens_kl_build(int32_t N, int32_t M, double L, void* kl, hipStream_t stream);
+
+/* ------------------------------------------------------------- assembly */
+
+/* Ensemble assembly of A and f (Alg. "assembly" made atomic-free): every
+ * stored entry A_ij[e] is the sum over the elements containing i and j, in
+ * ascending element id, of the element stiffness
+ *   K_e[a][b] = sum_q kappa(x_q, y_e) grad N_a(x_q).grad N_b(x_q) h^3/8
+ * over the 2x2x2 Gauss points; f_i[e] = sum over elements of f h^3/8.
+ * Dirichlet u = 0: boundary rows become identity rows, boundary columns of
+ * interior rows are stored zeros, boundary loads are zero.
+ *   graph      from ens_graph_build(N)
+ *   kl         from ens_kl_build(N, problem->M, problem->L)
+ *   xi         (device) [s][M] KL inputs y
+ *   values     (device) [nnz][s] FP64 out
+ *   values32   (device) [nnz][s] FP32 out, round-to-nearest of values; may be NULL
+ *   rhs        (device) [n][s] FP64 out
+ * Never synchronises. */
+ens_status ens_assemble(int32_t N, const ens_graph* graph, const void* kl, const ens_problem* problem,
+                        int32_t s, const double* xi, double* values, float* values32, double* rhs,
+                        hipStream_t stream);
+
+/* ----------------------------------------------------------------- SpMV */
+
+/* Ensemble CRS product y = A x in the commuted layout (Fig.
+ * "ensemble_crs"): y[i][e] = sum_k values[k][e] x[col_idx[k]][e], entries
+ * summed in ascending k.  values [nnz][s], x and y [n][s] (device) of the
+ * dtype given; y must not overlap x or values.  Never synchronises. */
+ens_status ens_spmv(const ens_graph* graph, int32_t s, ens_dtype dtype, const void* values,
+                    const void* x, void* y, hipStream_t stream);
+
+/* Scalar CRS product (Fig. "crs") of ONE sample: values [nnz], x and y [n]
+ * (device).  This is the one-sample-at-a-time baseline of the paper's
+ * speed-up definition (Sec. 4).  lanes_per_row in {4, 8, 16, 32, 64}
+ * (0 = default 8) selects how many lanes cooperate on one row. */
+ens_status ens_scalar_spmv(const ens_graph* graph, ens_dtype dtype, const void* values, const void* x,
+                           void* y, int32_t lanes_per_row, hipStream_t stream);
+
+/* ------------------------------------------------------------------ CG */
+
+typedef struct {
+  double rtol;            /* stop sample e when |r_e|_2 <= rtol |b_e|_2      */
+  int32_t max_iter;       /* FP64 CG: iteration cap per sample (<=0: 10000)   */
+  int32_t mixed;          /* 0: FP64 Jacobi-CG; 1: FP32 Jacobi-CG inside FP64
+                             iterative refinement (needs values32)           */
+  double inner_rtol;      /* mixed: inner stop |r_in| <= inner_rtol |r_out|   */
+  int32_t inner_max_iter; /* mixed: cap per inner solve (<=0: 10000)          */
+  int32_t max_outer;      /* mixed: cap on refinement steps (<=0: 10)         */
+  int32_t check_every;    /* iterations between polls of the device done flag
+                             (<=0: 16)                                       */
+  int32_t reserved;
+} ens_cg_opts;
+
+typedef struct {
+  int32_t iters;       /* CG iterations (mixed: total inner iterations)      */
+  int32_t outer_iters; /* mixed: refinement steps taken; 0 for FP64 CG       */
+  int32_t status;      /* ENS_SAMPLE_*                                       */
+  int32_t reserved;
+  double rel_res;      /* true FP64 residual |b - A x| / |b| of the result   */
+} ens_cg_stat;
+
+/* Bytes of caller workspace ens_cg needs for this graph, s and options. */
+ens_status ens_cg_workspace_bytes(const ens_graph* graph, int32_t s, const ens_cg_opts* opts,
+                                  size_t* bytes);
+
+/* Ensemble Jacobi-preconditioned CG with per-sample scalars (Sec. 3.4: CG
+ * on the ensemble system; preconditioner D_c = sum_i D_i (x) e_i e_i^T,
+ * the diagonal instance of Sec. 3.5's M_c).  Every sample e keeps its own
+ * alpha_e, beta_e, rho_e and convergence mask, so the ensemble iteration is
+ * sample by sample the scalar iteration (Eq. kron_sys block structure);
+ * a converged sample's x, r and p are frozen.  Iteration:
+ *   q = A p; alpha = rho/(p.q); x += alpha p; r -= alpha q;
+ *   stop if |r| <= rtol |b|; z = D^-1 r; rho' = r.z; p = z + (rho'/rho) p.
+ *   values   (device) [nnz][s] FP64
+ *   values32 (device) [nnz][s] FP32, used only when opts->mixed
+ *   b        (device) [n][s] FP64
+ *   x        (device) [n][s] FP64 in: initial guess x0, out: solution
+ *   workspace(device) >= ens_cg_workspace_bytes, 256-byte aligned
+ *   stats    (host)   [s] out
+ * Mixed mode: outer FP64 residual r = b - A x, then the FP32 Jacobi-CG
+ * above on the FP32 matrix for the correction d to inner_rtol, then
+ * x += d in FP64; repeated until |b - A x| <= rtol |b| per sample.
+ * Synchronises the stream; returns ENS_W_NOT_CONVERGED if any sample ends
+ * with a status other than ENS_SAMPLE_CONVERGED. */
+ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const float* values32,
+                  const double* b, double* x, const ens_cg_opts* opts, void* workspace,
+                  size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream);
+
+/* The same Jacobi-CG for s independent systems solved one after another
+ * with one-sample kernels on the sample-major layout of Eq. kron_sys:
+ * values [s][nnz], b and x [s][n] (device).  FP64 only (opts->mixed must
+ * be 0).  This is the "s times a single sample" side of the speed-up
+ * definition of Sec. 4.  Workspace from ens_cg_workspace_bytes(graph, 4,
+ * opts) suffices.  Synchronises. */
+ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values, const double* b,
+                         double* x, const ens_cg_opts* opts, int32_t lanes_per_row, void* workspace,
+                         size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream);
+
+/* Layout change between the commuted [rows][s] and the sample-major
+ * [s][rows] arrangement (Eqs. kron_sys_commuted and kron_sys), FP64,
+ * out-of-place.  to_sample_major = 1: src [rows][s] -> dst [s][rows]. */
+ens_status ens_relayout(const double* src, double* dst, int64_t rows, int32_t s, int32_t to_sample_major,
+                        hipStream_t stream);
+
+/* ----------------------------------------------------------- measurement */
+
+/* Plain device copy of `bytes` bytes (multiple of 16), used to calibrate
+ * hardware traffic counters against a kernel of known traffic, and the
+ * STREAM-style triad a[i] = b[i] + q c[i] in FP64 (the bandwidth the paper
+ * bounds its SpMV with, Sec. 4).  Never synchronise. */
+ens_status ens_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
+ens_status ens_stream_triad(double* a, const double* b, const double* c, double q, int64_t n,
+                            hipStream_t stream);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of the listed kernels while enabled. */
+enum {
+  ENS_K_SPMV_F64 = 0,   /* ensemble SpMV (standalone and inside CG), FP64 */
+  ENS_K_SPMV_F32 = 1,   /* ensemble SpMV, FP32 (refinement inner loop)   */
+  ENS_K_ASSEMBLE = 2,
+  ENS_K_SCALAR_SPMV = 3,
+  ENS_K_COUNT = 4
+};
+ens_status ens_prof_enable(int32_t on);
+ens_status ens_prof_reset(void);
+/* Totals since the last reset: summed event durations (ms), launches, and
+ * algorithmic bytes (the byte model of the kernel, summed per launch). */
+ens_status ens_prof_query(int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ENS_H */

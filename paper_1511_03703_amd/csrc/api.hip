@@ -1,0 +1,209 @@
+// Library-wide glue of libens: error text, per-device context, kernel timing
+// with HIP events, and the copy / triad kernels used to calibrate bandwidth.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace ens {
+
+thread_local char g_last_error[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+
+// ------------------------------------------------------------ device ctx ---
+
+static std::mutex g_ctx_mu;
+static std::vector<DeviceCtx*> g_ctx;
+
+DeviceCtx* device_ctx() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1, nullptr);
+  if (!g_ctx[dev]) {
+    DeviceCtx* c = new DeviceCtx();
+    c->device = dev;
+    if (hipHostMalloc((void**)&c->host_flag, 64, hipHostMallocDefault) != hipSuccess) {
+      delete c;
+      return nullptr;
+    }
+    g_ctx[dev] = c;
+  }
+  return g_ctx[dev];
+}
+
+// ------------------------------------------------------------- profiling ---
+
+struct PendingPair {
+  hipEvent_t a, b;
+  int kernel;
+  double bytes;
+};
+
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<hipEvent_t> g_free_events;
+static std::vector<PendingPair> g_pending;
+static hipEvent_t g_open[ENS_K_COUNT];
+static bool g_open_valid[ENS_K_COUNT];
+static double g_total_ms[ENS_K_COUNT];
+static int64_t g_launches[ENS_K_COUNT];
+static double g_bytes[ENS_K_COUNT];
+
+static hipEvent_t take_event() {
+  if (!g_free_events.empty()) {
+    hipEvent_t e = g_free_events.back();
+    g_free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(int k, hipStream_t st) {
+  if (!g_prof_on || k < 0 || k >= ENS_K_COUNT) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t e = take_event();
+  if (!e) return;
+  (void)hipEventRecord(e, st);
+  g_open[k] = e;
+  g_open_valid[k] = true;
+}
+
+void prof_end(int k, hipStream_t st, double bytes) {
+  if (!g_prof_on || k < 0 || k >= ENS_K_COUNT) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_open_valid[k]) return;
+  hipEvent_t e = take_event();
+  if (!e) return;
+  (void)hipEventRecord(e, st);
+  g_pending.push_back({g_open[k], e, k, bytes});
+  g_open_valid[k] = false;
+}
+
+void prof_collect() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::vector<PendingPair> keep;
+  for (auto& p : g_pending) {
+    if (hipEventQuery(p.b) != hipSuccess) {
+      keep.push_back(p);
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_total_ms[p.kernel] += ms;
+      g_launches[p.kernel] += 1;
+      g_bytes[p.kernel] += p.bytes;
+    }
+    g_free_events.push_back(p.a);
+    g_free_events.push_back(p.b);
+  }
+  g_pending.swap(keep);
+}
+
+// --------------------------------------------------------- stream kernels ---
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                 int64_t n16) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+    dst[i] = __builtin_nontemporal_load(src + i);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_triad(double* __restrict__ a, const double* __restrict__ b,
+                                                const double* __restrict__ c, double q, int64_t n) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    a[i] = b[i] + q * c[i];
+  }
+}
+
+}  // namespace ens
+
+using namespace ens;
+
+extern "C" {
+
+const char* ens_last_error(void) { return g_last_error; }
+
+const char* ens_status_string(ens_status st) {
+  switch (st) {
+    case ENS_OK: return "ok";
+    case ENS_W_NOT_CONVERGED: return "some sample did not converge";
+    case ENS_E_ARG: return "invalid argument";
+    case ENS_E_UNSUPPORTED: return "unsupported ensemble size or dtype";
+    case ENS_E_HIP: return "HIP runtime error";
+    case ENS_E_NOMEM: return "workspace too small";
+    case ENS_E_RANGE: return "size out of range";
+    default: return "unknown status";
+  }
+}
+
+int32_t ens_abi_version(void) { return 1; }
+
+ens_status ens_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
+  ENS_ARG_CHECK(src && dst, "null pointer");
+  ENS_ARG_CHECK(bytes % 16 == 0, "bytes must be a multiple of 16");
+  ENS_ARG_CHECK(aligned16(src) && aligned16(dst), "buffers must be 16-byte aligned");
+  if (bytes == 0) return ENS_OK;
+  int64_t n16 = (int64_t)(bytes / 16);
+  int64_t blocks = (n16 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, stream, (const u32x4*)src, (u32x4*)dst,
+                     n16);
+  ENS_LAUNCH_CHECK();
+  return ENS_OK;
+}
+
+ens_status ens_stream_triad(double* a, const double* b, const double* c, double q, int64_t n,
+                            hipStream_t stream) {
+  ENS_ARG_CHECK(a && b && c && n >= 0, "bad triad arguments");
+  if (n == 0) return ENS_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_triad, dim3((unsigned)blocks), dim3(256), 0, stream, a, b, c, q, n);
+  ENS_LAUNCH_CHECK();
+  return ENS_OK;
+}
+
+ens_status ens_prof_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return ENS_OK;
+}
+
+ens_status ens_prof_reset(void) {
+  prof_collect();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int k = 0; k < ENS_K_COUNT; ++k) {
+    g_total_ms[k] = 0.0;
+    g_launches[k] = 0;
+    g_bytes[k] = 0.0;
+  }
+  return ENS_OK;
+}
+
+ens_status ens_prof_query(int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes) {
+  ENS_ARG_CHECK(kernel_id >= 0 && kernel_id < ENS_K_COUNT, "kernel id");
+  prof_collect();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (total_ms) *total_ms = g_total_ms[kernel_id];
+  if (launches) *launches = g_launches[kernel_id];
+  if (bytes) *bytes = g_bytes[kernel_id];
+  return ENS_OK;
+}
+
+}  // extern "C"

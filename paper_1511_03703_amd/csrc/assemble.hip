@@ -1,0 +1,209 @@
+// Ensemble Q1 assembly of the stiffness matrix and load vector.
+//
+// Alg. "assembly" (Sec. 4) loops over cells and scatters each element matrix
+// into the global matrix with atomic adds.  Here the loop is turned inside
+// out: a group of s lanes owns one matrix row (one node), and lane e owns
+// sample e of that row.  The lane visits the (up to 8) elements around the
+// node in ascending element id, evaluates the coefficient of its sample at
+// the element's 8 Gauss points, and adds the element row K_e[a_i][.] into a
+// 27-entry register row.  No atomics are needed, each entry is
+// 0 + K_e1 + K_e2 + ... in ascending element order, and since every K_e is
+// formed from a symmetric table with the same operations for (a,b) and (b,a)
+// the assembled matrix is bitwise symmetric.  The writes of a row are
+// s-contiguous ([nnz][s]) and coalesced across the lane group.
+//
+// Element matrix on the uniform mesh (h = 1/N, 2x2x2 Gauss, weight h^3/8):
+//   K_e[a][b] = sum_q kappa_q (h/8) G_q[a][b],
+//   G_q[a][b] = grad_ref N_a(g_q) . grad_ref N_b(g_q)       (dimensionless)
+// kappa_q = kappa0 + sigma sum_m sqrt(lambda_m) phi_m(x_q) y_m, with the 1D
+// factors of phi_m read from the KL table.
+#include "common.hpp"
+
+namespace ens {
+
+constexpr int kAsmMaxM = 16;
+
+__constant__ double c_G[8][8][8];  // [q][a][b], symmetric in (a,b)
+
+static bool g_G_ready[64];
+
+static hipError_t upload_G() {
+  double G[8][8][8];
+  const double r = 0.57735026918962576451;
+  const double g[2] = {0.5 * (1.0 - r), 0.5 * (1.0 + r)};
+  for (int q = 0; q < 8; ++q) {
+    double s[3] = {g[q & 1], g[(q >> 1) & 1], g[(q >> 2) & 1]};
+    double l[2][3], d[2] = {-1.0, 1.0};
+    for (int t = 0; t < 3; ++t) {
+      l[0][t] = 1.0 - s[t];
+      l[1][t] = s[t];
+    }
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b) {
+        int ax[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
+        int bx[3] = {b & 1, (b >> 1) & 1, (b >> 2) & 1};
+        double dot = 0.0;
+        for (int dim = 0; dim < 3; ++dim) {
+          double fa = d[ax[dim]], fb = d[bx[dim]];
+          for (int o = 0; o < 3; ++o)
+            if (o != dim) {
+              fa *= l[ax[o]][o];
+              fb *= l[bx[o]][o];
+            }
+          dot += fa * fb;
+        }
+        G[q][a][b] = dot;
+      }
+    // force exact symmetry of the table
+    for (int a = 0; a < 8; ++a)
+      for (int b = a + 1; b < 8; ++b) G[q][b][a] = G[q][a][b];
+  }
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_G), G, sizeof(G));
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_assemble(int N, const double* __restrict__ kl_sqrt_lam,
+                                                   const int32_t* __restrict__ kl_triple,
+                                                   const double* __restrict__ kl_phi, int M, double kappa0,
+                                                   double sigma, double fsrc, const double* __restrict__ xi,
+                                                   const int32_t* __restrict__ row_ptr,
+                                                   double* __restrict__ values, float* __restrict__ values32,
+                                                   double* __restrict__ rhs) {
+  constexpr int RPB = 256 / S;  // rows per block
+  // sigma sqrt(lambda_m) y_m of every sample of the block, [e][m]
+  __shared__ double s_cm[S * kAsmMaxM];
+  for (int t = threadIdx.x; t < S * M; t += blockDim.x) {
+    const int ee = t / M, m = t % M;
+    s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)ee * M + m];
+  }
+  __syncthreads();
+
+  const int n1 = N + 1;
+  const int64_t n = (int64_t)n1 * n1 * n1;
+  const int e = threadIdx.x % S;
+  const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / S;
+  if (row >= n) return;
+  const int ii = (int)(row % n1), jj = (int)((row / n1) % n1), kk = (int)(row / ((int64_t)n1 * n1));
+  const double h = 1.0 / (double)N;
+  const double wscale = h * 0.125;  // w_q / h^2
+  const int64_t two_n = 2 * (int64_t)N;
+
+  double acc[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = 0.0;
+  int nelem = 0;
+
+  // elements around the node in ascending id: (ez, ey, ex) lexicographic
+#pragma unroll
+  for (int ez_off = -1; ez_off <= 0; ++ez_off)
+#pragma unroll
+    for (int ey_off = -1; ey_off <= 0; ++ey_off)
+#pragma unroll
+      for (int ex_off = -1; ex_off <= 0; ++ex_off) {
+        const int ex = ii + ex_off, ey = jj + ey_off, ez = kk + ez_off;
+        if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
+        ++nelem;
+        const int ai = (-ex_off) + 2 * (-ey_off) + 4 * (-ez_off);  // local index of the node
+        double kq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) kq[q] = 0.0;
+        for (int m = 0; m < M; ++m) {
+          const double c = s_cm[e * M + m];
+          const double* px = kl_phi + kl_triple[3 * m + 0] * two_n + 2 * ex;
+          const double* py = kl_phi + kl_triple[3 * m + 1] * two_n + 2 * ey;
+          const double* pz = kl_phi + kl_triple[3 * m + 2] * two_n + 2 * ez;
+          const double fx[2] = {px[0], px[1]}, fy[2] = {py[0], py[1]}, fz[2] = {pz[0], pz[1]};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) kq[q] += c * (fx[q & 1] * fy[(q >> 1) & 1] * fz[(q >> 2) & 1]);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) kq[q] = (kappa0 + kq[q]) * wscale;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int dx = ex_off + (b & 1), dy = ey_off + ((b >> 1) & 1), dz = ez_off + ((b >> 2) & 1);
+          const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+          double kab = 0.0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) kab += kq[q] * c_G[q][ai][b];
+          acc[slot27] += kab;
+        }
+      }
+
+  const bool bnd_row = (ii == 0 || ii == N || jj == 0 || jj == N || kk == 0 || kk == N);
+  const int64_t start = row_ptr[row];
+  int pos = 0;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = ii + dx, y = jj + dy, z = kk + dz;
+        if (x < 0 || y < 0 || z < 0 || x > N || y > N || z > N) continue;
+        const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        double v = acc[slot27];
+        const bool bnd_col = (x == 0 || x == N || y == 0 || y == N || z == 0 || z == N);
+        if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
+        else if (bnd_col) v = 0.0;
+        const int64_t k = (start + pos) * S + e;
+        values[k] = v;
+        if (values32) values32[k] = (float)v;
+        ++pos;
+      }
+  // load: each element adds sum_q f N_a(g_q) h^3/8 = f h^3/8 to its vertices
+  rhs[row * S + e] = bnd_row ? 0.0 : (double)nelem * (fsrc * h * h * h * 0.125);
+}
+
+}  // namespace ens
+
+using namespace ens;
+
+extern "C" ens_status ens_assemble(int32_t N, const ens_graph* graph, const void* kl, const ens_problem* prob,
+                                   int32_t s, const double* xi, double* values, float* values32, double* rhs,
+                                   hipStream_t stream) {
+  int64_t n = 0, nnz = 0;
+  ens_status st = ens_mesh_sizes(N, &n, &nnz, nullptr);
+  if (st != ENS_OK) return st;
+  ENS_ARG_CHECK(graph && prob, "null graph or problem");
+  ENS_ARG_CHECK(graph->n == n && graph->nnz == nnz && graph->row_ptr && graph->col_idx,
+                "graph does not match the mesh");
+  ENS_ARG_CHECK(values && rhs, "null output");
+  ENS_ARG_CHECK(prob->M >= 0 && prob->M <= kAsmMaxM, "M out of range");
+  ENS_ARG_CHECK(prob->M == 0 || (kl && xi), "null KL table or inputs");
+  if (!supported_s(s)) {
+    set_error("ensemble size %d not compiled in", s);
+    return ENS_E_UNSUPPORTED;
+  }
+  int dev = 0;
+  ENS_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 64 && !g_G_ready[dev]) {
+    ENS_HIP_TRY(upload_G());
+    g_G_ready[dev] = true;
+  }
+  const int M = prob->M;
+  const char* base = (const char*)kl;
+  // KL table layout (see ens_kl_build): sqrt_lam3 at 0, triple at 5M doubles + M ints
+  size_t phi_off = ((size_t)M * 5 * sizeof(double) + (size_t)M * 4 * sizeof(int32_t) + 15) & ~(size_t)15;
+  const double* sq = (const double*)base;
+  const int32_t* tr = (const int32_t*)(base + (size_t)M * 5 * sizeof(double) + (size_t)M * sizeof(int32_t));
+  const double* phi = (const double*)(base + phi_off);
+  const int rpb = 256 / s;
+  int64_t blocks = (n + rpb - 1) / rpb;
+  prof_begin(ENS_K_ASSEMBLE, stream);
+  switch (s) {
+#define ENS_ASM_CASE(SS)                                                                                  \
+  case SS:                                                                                                \
+    hipLaunchKernelGGL(k_assemble<SS>, dim3((unsigned)blocks), dim3(256), 0, stream, N, sq, tr, phi, M,   \
+                       prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values, values32, rhs);    \
+    break;
+    ENS_ASM_CASE(4)
+    ENS_ASM_CASE(8)
+    ENS_ASM_CASE(16)
+    ENS_ASM_CASE(32)
+#undef ENS_ASM_CASE
+  }
+  ENS_LAUNCH_CHECK();
+  double bytes = (double)nnz * s * (8.0 + (values32 ? 4.0 : 0.0)) + (double)n * s * 8.0 + 4.0 * (n + 1);
+  prof_end(ENS_K_ASSEMBLE, stream, bytes);
+  return ENS_OK;
+}

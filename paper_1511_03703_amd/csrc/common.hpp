@@ -1,0 +1,100 @@
+// Internal helpers shared by the HIP sources of libens (never part of the ABI).
+//
+// Layout conventions of the ensemble (commuted) system, Eq. kron_sys_commuted:
+// a matrix value is an s-long ensemble stored contiguously, values[k*s + e];
+// a vector entry likewise, x[i*s + e].  One 16-byte load therefore carries
+// V = 16/sizeof(T) consecutive samples of one entry, and the s samples of an
+// entry are spread over L = s/V consecutive lanes of a 64-wide wavefront.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/ens.h"
+
+namespace ens {
+
+// ---------------------------------------------------------------- status ---
+
+extern thread_local char g_last_error[512];
+void set_error(const char* fmt, ...);
+
+#define ENS_HIP_TRY(expr)                                                          \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      ::ens::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),      \
+                       __FILE__, __LINE__);                                        \
+      return ENS_E_HIP;                                                            \
+    }                                                                              \
+  } while (0)
+
+#define ENS_LAUNCH_CHECK()                                                         \
+  do {                                                                             \
+    hipError_t _e = hipGetLastError();                                             \
+    if (_e != hipSuccess) {                                                        \
+      ::ens::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(_e),  \
+                       __FILE__, __LINE__);                                        \
+      return ENS_E_HIP;                                                            \
+    }                                                                              \
+  } while (0)
+
+#define ENS_ARG_CHECK(cond, msg)                                                   \
+  do {                                                                             \
+    if (!(cond)) {                                                                 \
+      ::ens::set_error("invalid argument: %s", msg);                               \
+      return ENS_E_ARG;                                                            \
+    }                                                                              \
+  } while (0)
+
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// ----------------------------------------------------------- vector types ---
+
+template <typename T, int N>
+struct vec_t {
+  typedef T type __attribute__((ext_vector_type(N)));
+};
+
+template <typename T>
+struct pack {
+  static constexpr int V = 16 / (int)sizeof(T);  // samples per 16-byte load
+  typedef typename vec_t<T, V>::type type;
+};
+
+// Lanes that hold the same samples of different entries must be combined
+// when a per-sample sum is needed: with L lanes per entry these lanes are
+// L, 2L, ... apart, so butterfly over offsets L..32.
+template <int L>
+__device__ inline double wave_sum_stride(double v) {
+#pragma unroll
+  for (int off = L; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Ensemble sizes compiled into the library (explicit instantiation).
+inline bool supported_s(int s) { return s == 4 || s == 8 || s == 16 || s == 32; }
+
+// Number of workgroups for grid-stride streaming kernels: enough waves to
+// cover HBM latency on all 256 CUs without making the per-block partial
+// arrays of the reductions large.
+constexpr int kStreamBlocks = 2048;
+constexpr int kBlock = 256;
+
+// The reduction partial buffers hold up to this many blocks.
+constexpr int kMaxPartBlocks = 4096;
+
+// Per-device pinned scalars and events kept for the life of the process.
+struct DeviceCtx {
+  int device = -1;
+  int32_t* host_flag = nullptr;  // pinned, for the once-per-chunk poll
+};
+DeviceCtx* device_ctx();
+
+// Profiling of the hot kernels with HIP events recorded on the launch stream.
+void prof_begin(int kernel_id, hipStream_t st);
+void prof_end(int kernel_id, hipStream_t st, double bytes);
+void prof_collect();  // resolve pending event pairs (call after a stream sync)
+
+}  // namespace ens

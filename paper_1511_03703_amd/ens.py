@@ -1,0 +1,321 @@
+"""Thin ctypes binding of libens (include/ens.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream, every computation runs in the library's HIP kernels.
+If the library is missing this module raises instead of falling back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libens.so")
+
+ENS_OK, ENS_W_NOT_CONVERGED = 0, 1
+ENS_E_ARG, ENS_E_UNSUPPORTED, ENS_E_HIP, ENS_E_NOMEM, ENS_E_RANGE = -1, -2, -3, -4, -5
+SAMPLE_CONVERGED, SAMPLE_MAXITER, SAMPLE_BREAKDOWN, SAMPLE_NONFINITE, SAMPLE_STAGNATED = 0, 1, 2, 3, 4
+F64, F32 = 0, 1
+K_SPMV_F64, K_SPMV_F32, K_ASSEMBLE, K_SCALAR_SPMV = 0, 1, 2, 3
+
+
+class EnsError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+class ens_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class ens_problem(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("L", ctypes.c_double), ("kappa0", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("f", ctypes.c_double)]
+
+
+class ens_cg_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mixed", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ens_cg_stat(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rel_res", ctypes.c_double)]
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_SZ = ctypes.c_size_t
+_GP = ctypes.POINTER(ens_graph)
+_SIGS = [
+    ("ens_last_error", ctypes.c_char_p, []),
+    ("ens_status_string", ctypes.c_char_p, [_I32]),
+    ("ens_abi_version", _I32, []),
+    ("ens_mesh_sizes", _I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    ("ens_graph_build", _I32, [_I32, _P, _P, _P]),
+    ("ens_kl_bytes", _I32, [_I32, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_kl_build", _I32, [_I32, _I32, _D, _P, _P]),
+    ("ens_assemble", _I32, [_I32, _GP, _P, ctypes.POINTER(ens_problem), _I32, _P, _P, _P, _P, _P]),
+    ("ens_spmv", _I32, [_GP, _I32, _I32, _P, _P, _P, _P]),
+    ("ens_scalar_spmv", _I32, [_GP, _I32, _P, _P, _P, _I32, _P]),
+    ("ens_cg_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(_SZ)]),
+    ("ens_cg", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _P, _SZ,
+                      ctypes.POINTER(ens_cg_stat), _P]),
+    ("ens_scalar_cg", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _I32, _P, _SZ,
+                             ctypes.POINTER(ens_cg_stat), _P]),
+    ("ens_relayout", _I32, [_P, _P, _I64, _I32, _I32, _P]),
+    ("ens_stream_copy", _I32, [_P, _P, _SZ, _P]),
+    ("ens_stream_triad", _I32, [_P, _P, _P, _D, _I64, _P]),
+    ("ens_prof_enable", _I32, [_I32]),
+    ("ens_prof_reset", _I32, []),
+    ("ens_prof_query", _I32, [_I32, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+]
+EXPORTED = [s[0] for s in _SIGS]
+
+
+def lib():
+    """Load libens.so (built in-tree by build.py); raise if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not found: build it with `python -m paper_1511_03703_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str, allow=(ENS_OK,)):
+    if st not in allow:
+        detail = lib().ens_last_error().decode(errors="replace")
+        raise EnsError(st, where, detail or lib().ens_status_string(st).decode())
+    return st
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ mesh
+
+
+def mesh_sizes(N: int):
+    n, nnz, ne = _I64(), _I64(), _I64()
+    _check(lib().ens_mesh_sizes(N, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(ne)), "ens_mesh_sizes")
+    return n.value, nnz.value, ne.value
+
+
+@dataclass
+class Graph:
+    N: int
+    n: int
+    nnz: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+
+    def c(self) -> ens_graph:
+        return ens_graph(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr())
+
+
+def graph_build(N: int, device="cuda", stream=None) -> Graph:
+    n, nnz, _ = mesh_sizes(N)
+    rp = torch.empty(n + 1, dtype=torch.int32, device=device)
+    ci = torch.empty(nnz, dtype=torch.int32, device=device)
+    _check(lib().ens_graph_build(N, _ptr(rp), _ptr(ci), _stream(stream)), "ens_graph_build")
+    return Graph(N, n, nnz, rp, ci)
+
+
+def graph_from_arrays(row_ptr: torch.Tensor, col_idx: torch.Tensor, N: int = 0) -> Graph:
+    return Graph(N, row_ptr.numel() - 1, col_idx.numel(), row_ptr, col_idx)
+
+
+# -------------------------------------------------------------------- KL
+
+
+def kl_bytes(N: int, M: int) -> int:
+    b = _SZ()
+    _check(lib().ens_kl_bytes(N, M, ctypes.byref(b)), "ens_kl_bytes")
+    return b.value
+
+
+def kl_build(N: int, M: int, L: float = 1.0, device="cuda", stream=None) -> torch.Tensor:
+    buf = torch.zeros(kl_bytes(N, M), dtype=torch.uint8, device=device)
+    _check(lib().ens_kl_build(N, M, L, _ptr(buf), _stream(stream)), "ens_kl_build")
+    return buf
+
+
+def kl_parse(buf: torch.Tensor, N: int, M: int) -> dict:
+    """Host view of the KL table layout documented in ens.h."""
+    import numpy as np
+    b = buf.cpu().numpy().tobytes()
+    d = np.frombuffer(b, dtype=np.float64, count=5 * M)
+    i = np.frombuffer(b, dtype=np.int32, count=4 * M, offset=5 * M * 8)
+    off = (5 * M * 8 + 4 * M * 4 + 15) & ~15
+    phi = np.frombuffer(b, dtype=np.float64, count=M * 2 * N, offset=off).reshape(M, 2 * N)
+    return {"sqrt_lam3": d[0:M], "lam3": d[M:2 * M], "omega": d[2 * M:3 * M], "lam1": d[3 * M:4 * M],
+            "norm1": d[4 * M:5 * M], "parity": i[0:M], "triple": i[M:4 * M].reshape(M, 3), "phi": phi}
+
+
+# -------------------------------------------------------------- assembly
+
+
+def assemble(g: Graph, kl: torch.Tensor, xi: torch.Tensor, M: int, sigma: float, L: float = 1.0,
+             kappa0: float = 1.0, f: float = 1.0, values=None, values32=None, rhs=None, want32=False,
+             stream=None):
+    """values [nnz][s] FP64, optional values32 [nnz][s] FP32, rhs [n][s] FP64."""
+    s = xi.shape[0]
+    dev = xi.device
+    if values is None:
+        values = torch.empty((g.nnz, s), dtype=torch.float64, device=dev)
+    if want32 and values32 is None:
+        values32 = torch.empty((g.nnz, s), dtype=torch.float32, device=dev)
+    if rhs is None:
+        rhs = torch.empty((g.n, s), dtype=torch.float64, device=dev)
+    prob = ens_problem(M, L, kappa0, sigma, f)
+    gc = g.c()
+    _check(lib().ens_assemble(g.N, ctypes.byref(gc), _ptr(kl), ctypes.byref(prob), s, _ptr(xi), _ptr(values),
+                              _ptr(values32), _ptr(rhs), _stream(stream)), "ens_assemble")
+    return values, values32, rhs
+
+
+# ------------------------------------------------------------------ SpMV
+
+
+def spmv(g: Graph, values: torch.Tensor, x: torch.Tensor, y=None, stream=None):
+    s = values.shape[1]
+    dt = F64 if values.dtype == torch.float64 else F32
+    if y is None:
+        y = torch.empty_like(x)
+    gc = g.c()
+    _check(lib().ens_spmv(ctypes.byref(gc), s, dt, _ptr(values), _ptr(x), _ptr(y), _stream(stream)), "ens_spmv")
+    return y
+
+
+def scalar_spmv(g: Graph, values: torch.Tensor, x: torch.Tensor, y=None, lanes_per_row=0, stream=None):
+    dt = F64 if values.dtype == torch.float64 else F32
+    if y is None:
+        y = torch.empty_like(x)
+    gc = g.c()
+    _check(lib().ens_scalar_spmv(ctypes.byref(gc), dt, _ptr(values), _ptr(x), _ptr(y), lanes_per_row,
+                                 _stream(stream)), "ens_scalar_spmv")
+    return y
+
+
+# -------------------------------------------------------------------- CG
+
+
+def cg_opts(rtol=1e-10, max_iter=10000, mixed=False, inner_rtol=1e-4, inner_max_iter=10000, max_outer=10,
+            check_every=16) -> ens_cg_opts:
+    return ens_cg_opts(rtol, max_iter, int(mixed), inner_rtol, inner_max_iter, max_outer, check_every, 0)
+
+
+def cg_workspace_bytes(g: Graph, s: int, opts: ens_cg_opts) -> int:
+    b = _SZ()
+    gc = g.c()
+    _check(lib().ens_cg_workspace_bytes(ctypes.byref(gc), s, ctypes.byref(opts), ctypes.byref(b)),
+           "ens_cg_workspace_bytes")
+    return b.value
+
+
+def _stats_list(st, count):
+    return [{"iters": st[e].iters, "outer_iters": st[e].outer_iters, "status": st[e].status,
+             "rel_res": st[e].rel_res} for e in range(count)]
+
+
+def cg(g: Graph, values, b, x=None, values32=None, opts: ens_cg_opts | None = None, workspace=None, stream=None):
+    """Ensemble Jacobi-CG (or FP32-in-FP64 refinement when opts.mixed).
+    Returns (x, stats, status)."""
+    s = values.shape[1]
+    if opts is None:
+        opts = cg_opts()
+    if x is None:
+        x = torch.zeros_like(b)
+    nbytes = cg_workspace_bytes(g, s, opts)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    stats = (ens_cg_stat * s)()
+    gc = g.c()
+    st = _check(lib().ens_cg(ctypes.byref(gc), s, _ptr(values), _ptr(values32), _ptr(b), _ptr(x),
+                             ctypes.byref(opts), _ptr(workspace), workspace.numel(), stats, _stream(stream)),
+                "ens_cg", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
+    return x, _stats_list(stats, s), st
+
+
+def scalar_cg(g: Graph, values_sm, b_sm, x_sm=None, opts: ens_cg_opts | None = None, lanes_per_row=0,
+              workspace=None, stream=None):
+    """s independent one-sample solves; sample-major values [s][nnz], b, x [s][n]."""
+    s = values_sm.shape[0]
+    if opts is None:
+        opts = cg_opts()
+    if x_sm is None:
+        x_sm = torch.zeros_like(b_sm)
+    nbytes = cg_workspace_bytes(g, 4, opts)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=b_sm.device)
+    stats = (ens_cg_stat * s)()
+    gc = g.c()
+    st = _check(lib().ens_scalar_cg(ctypes.byref(gc), s, _ptr(values_sm), _ptr(b_sm), _ptr(x_sm),
+                                    ctypes.byref(opts), lanes_per_row, _ptr(workspace), workspace.numel(), stats,
+                                    _stream(stream)), "ens_scalar_cg", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
+    return x_sm, _stats_list(stats, s), st
+
+
+def relayout(src: torch.Tensor, to_sample_major: bool, out=None, stream=None):
+    """[rows][s] <-> [s][rows] (FP64)."""
+    if to_sample_major:
+        rows, s = src.shape
+        if out is None:
+            out = torch.empty((s, rows), dtype=src.dtype, device=src.device)
+    else:
+        s, rows = src.shape
+        if out is None:
+            out = torch.empty((rows, s), dtype=src.dtype, device=src.device)
+    _check(lib().ens_relayout(_ptr(src), _ptr(out), rows, s, int(to_sample_major), _stream(stream)), "ens_relayout")
+    return out
+
+
+# ------------------------------------------------------------ measurement
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    nb = src.numel() * src.element_size()
+    _check(lib().ens_stream_copy(_ptr(src), _ptr(dst), nb, _stream(stream)), "ens_stream_copy")
+
+
+def stream_triad(a, b, c, q: float, stream=None):
+    _check(lib().ens_stream_triad(_ptr(a), _ptr(b), _ptr(c), q, a.numel(), _stream(stream)), "ens_stream_triad")
+
+
+def prof_enable(on: bool = True):
+    _check(lib().ens_prof_enable(int(on)), "ens_prof_enable")
+
+
+def prof_reset():
+    _check(lib().ens_prof_reset(), "ens_prof_reset")
+
+
+def prof_query(kernel_id: int):
+    ms, n, by = _D(), _I64(), _D()
+    _check(lib().ens_prof_query(kernel_id, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)), "ens_prof_query")
+    return {"total_ms": ms.value, "launches": n.value, "bytes": by.value}

@@ -1,0 +1,310 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars (from the method and its arithmetic):
+  - graph and index arrays: bit-exact;
+  - assembled values: Frobenius-relative <= 1e-13 (summation order and FMA
+    contraction differ), GPU matrix bitwise symmetric;
+  - FP64 SpMV: relative <= 1e-14 per sample; FP32 SpMV vs FP64: <= 1e-6;
+  - FP64 CG: at the GPU's per-sample iteration count the oracle's iterate
+    agrees to relative 1e-9; the oracle's own stopping count is within +-1;
+  - mixed-precision refinement: true FP64 residual <= 1e-8 per sample.
+"""
+import numpy as np
+import pytest
+import torch
+
+from workloads import SMALL, draw_xi, draw_vector
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1511_03703_amd import ens
+    ens.lib()
+    assert torch.cuda.is_available()
+    return ens
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+# ------------------------------------------------------------------ graph
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 16, 33])
+def test_graph_bit_exact(E, orc, N):
+    g = E.graph_build(N)
+    rp, ci = orc.graph(N)
+    assert np.array_equal(_np(g.row_ptr), rp)
+    assert np.array_equal(_np(g.col_idx), ci)
+
+
+# --------------------------------------------------------------------- KL
+
+@pytest.mark.parametrize("M", [1, 3, 10, 16])
+def test_kl_table_matches_oracle(E, orc, M):
+    N = 7
+    kl = E.kl_parse(E.kl_build(N, M, 1.0), N, M)
+    w, lam, nrm, par = orc.kl_1d(M, 1.0)
+    tr, lam3 = orc.kl_modes(M, 1.0)
+    np.testing.assert_allclose(kl["omega"], w, rtol=1e-14)
+    np.testing.assert_allclose(kl["lam1"], lam, rtol=1e-14)
+    np.testing.assert_allclose(kl["norm1"], nrm, rtol=1e-14)
+    assert np.array_equal(kl["parity"], par)
+    assert np.array_equal(kl["triple"], tr)
+    np.testing.assert_allclose(kl["lam3"], lam3, rtol=1e-14)
+    # table products reproduce sqrt(lambda_m) phi_m at every quadrature point
+    pts = orc.qp_coords(N)
+    for m in range(M):
+        xi = np.zeros(M)
+        xi[m] = 1.0
+        ref = orc.kl_coef_points(M, 1.0, 0.0, 1.0, xi, pts.reshape(-1, 3)).reshape(N ** 3, 8)
+        t = kl["triple"][m]
+        got = np.zeros((N ** 3, 8))
+        for e in range(N ** 3):
+            ex, ey, ez = e % N, (e // N) % N, e // (N * N)
+            for q in range(8):
+                got[e, q] = (kl["sqrt_lam3"][m] * kl["phi"][t[0], 2 * ex + (q & 1)]
+                             * kl["phi"][t[1], 2 * ey + ((q >> 1) & 1)] * kl["phi"][t[2], 2 * ez + ((q >> 2) & 1)])
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
+
+
+# --------------------------------------------------------------- assembly
+
+def _gpu_system(E, N, s, M, sigma, xi, want32=False, f=1.0):
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M, 1.0)
+    vals, v32, rhs = E.assemble(g, kl, _t(xi), M, sigma, f=f, want32=want32)
+    return g, vals, v32, rhs
+
+
+@pytest.mark.parametrize("N,s,M,sigma", [(16, 4, 3, 0.1), (5, 8, 10, 0.3), (6, 16, 10, 0.2), (3, 32, 16, 0.3),
+                                         (1, 4, 10, 0.2), (9, 32, 10, 0.3)])
+def test_assembly_matches_oracle(E, orc, N, s, M, sigma):
+    xi = draw_xi(100 + N, s, M)
+    g, vals, v32, rhs = _gpu_system(E, N, s, M, sigma, xi, want32=True)
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    gv, gb = _np(vals), _np(rhs)
+    for e in range(s):
+        assert _rel(gv[:, e], ov[:, e]) <= 1e-13
+        assert _rel(gb[:, e], ob[:, e]) <= 1e-14
+    # bitwise symmetry of the GPU matrix, every sample
+    n = rp.shape[0] - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    key = rows.astype(np.int64) * n + ci
+    tkey = ci.astype(np.int64) * n + rows
+    order = np.argsort(key)
+    perm = order[np.searchsorted(key[order], tkey)]
+    assert np.array_equal(gv, gv[perm])
+    # FP32 copy is the round-to-nearest of the FP64 values
+    assert np.array_equal(_np(v32), gv.astype(np.float32))
+
+
+def test_assembly_deterministic(E):
+    N, s, M = 8, 16, 10
+    xi = draw_xi(7, s, M)
+    a = _np(_gpu_system(E, N, s, M, 0.3, xi)[1])
+    b = _np(_gpu_system(E, N, s, M, 0.3, xi)[1])
+    assert np.array_equal(a, b)
+
+
+# -------------------------------------------------------------------- SpMV
+
+def _random_crs(rng, n, maxlen, ncols):
+    lens = rng.integers(0, maxlen + 1, n)
+    lens[rng.integers(0, n, max(1, n // 10))] = 0  # some empty rows
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum(lens)
+    ci = np.concatenate([np.sort(rng.choice(ncols, L, replace=False)) for L in lens]).astype(np.int32)
+    return rp, ci
+
+
+@pytest.mark.parametrize("s", [4, 8, 16, 32])
+@pytest.mark.parametrize("n", [1, 37, 1000, 4099])
+def test_spmv_random_graphs(E, orc, s, n):
+    rng = np.random.default_rng(n * 100 + s)
+    rp, ci = _random_crs(rng, n, 64, n)
+    nnz = int(rp[-1])
+    vals = rng.standard_normal((nnz, s))
+    x = rng.standard_normal((n, s))
+    ref = orc.ens_spmv(rp, ci, vals, x)
+    g = E.graph_from_arrays(_t(rp, torch.int32), _t(ci, torch.int32))
+    y = _np(E.spmv(g, _t(vals), _t(x)))
+    scale = np.abs(vals).max() * np.abs(x).max() * 64
+    assert np.max(np.abs(y - ref)) <= 1e-15 * scale
+    y32 = _np(E.spmv(g, _t(vals, torch.float32), _t(x, torch.float32)))
+    assert np.max(np.abs(y32 - ref)) <= 2e-6 * scale
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
+def test_scalar_spmv(E, orc, lanes):
+    rng = np.random.default_rng(lanes)
+    n = 3001
+    rp, ci = _random_crs(rng, n, 70, n)
+    vals = rng.standard_normal(int(rp[-1]))
+    x = rng.standard_normal(n)
+    ref = orc.spmv(rp, ci, vals, x)
+    g = E.graph_from_arrays(_t(rp, torch.int32), _t(ci, torch.int32))
+    y = _np(E.scalar_spmv(g, _t(vals), _t(x), lanes_per_row=lanes))
+    assert np.max(np.abs(y - ref)) <= 1e-13 * (1 + np.abs(ref).max())
+
+
+def test_spmv_on_assembled_matrix(E, orc):
+    N, s, M = 12, 16, 10
+    xi = draw_xi(5, s, M)
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, 0.2, 1.0, xi)
+    x = draw_vector(6, ((N + 1) ** 3, s))
+    ref = orc.ens_spmv(rp, ci, ov, x)
+    g = E.graph_build(N)
+    y = _np(E.spmv(g, _t(ov), _t(x)))
+    for e in range(s):
+        assert _rel(y[:, e], ref[:, e]) <= 1e-14
+
+
+# ---------------------------------------------------------------------- CG
+
+def _check_cg_against_oracle(orc, rp, ci, ov, ob, x_gpu, stats, rtol, x0=None):
+    s = ov.shape[1]
+    iters = np.array([st["iters"] for st in stats], np.int32)
+    xo, ito, relo, sto = orc.ens_pcg(rp, ci, ov, ob, x0=x0, fixed_iters=iters)
+    xt, itt, relt, stt = orc.ens_pcg(rp, ci, ov, ob, x0=x0, rtol=rtol)
+    true_res = orc.ens_true_residual(rp, ci, ov, ob, x_gpu)
+    for e in range(s):
+        assert stats[e]["status"] == 0, stats[e]
+        assert _rel(x_gpu[:, e], xo[:, e]) <= 1e-9, (e, _rel(x_gpu[:, e], xo[:, e]))
+        assert abs(int(itt[e]) - int(iters[e])) <= 1, (e, itt[e], iters[e])
+        assert true_res[e] <= rtol * (1 + 1e-6), (e, true_res[e])
+        assert abs(stats[e]["rel_res"] - true_res[e]) <= 1e-6 * rtol + 1e-3 * true_res[e]
+
+
+def test_cg_small_config(E, orc):
+    """16^3 elements, s=4, M=3, sigma=0.1, Jacobi-CG to 1e-10 (FP64)."""
+    w = SMALL
+    xi = w.xi()
+    g, vals, _, rhs = _gpu_system(E, w.N, w.s, w.M, w.sigma, xi)
+    x, stats, st = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=w.rtol))
+    assert st == E.ENS_OK
+    rp, ci = orc.graph(w.N)
+    ov, ob = orc.assemble_ensemble(w.N, rp, ci, w.M, 1.0, 1.0, w.sigma, 1.0, xi)
+    _check_cg_against_oracle(orc, rp, ci, ov, ob, _np(x), stats, w.rtol)
+
+
+@pytest.mark.parametrize("s", [4, 8, 16, 32])
+def test_cg_every_ensemble_size(E, orc, s):
+    N, M, sigma, rtol = 7, 10, 0.3, 1e-10
+    xi = draw_xi(40 + s, s, M)
+    g, vals, _, rhs = _gpu_system(E, N, s, M, sigma, xi)
+    x, stats, st = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=rtol, check_every=3))
+    assert st == E.ENS_OK
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    _check_cg_against_oracle(orc, rp, ci, ov, ob, _np(x), stats, rtol)
+
+
+def test_cg_nonzero_initial_guess(E, orc):
+    N, s, M, rtol = 9, 8, 10, 1e-10
+    xi = draw_xi(3, s, M)
+    g, vals, _, rhs = _gpu_system(E, N, s, M, 0.2, xi)
+    x0 = draw_vector(8, ((N + 1) ** 3, s), 0.0, 0.05)
+    x, stats, st = E.cg(g, vals, rhs, x=_t(x0), opts=E.cg_opts(rtol=rtol))
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, 0.2, 1.0, xi)
+    _check_cg_against_oracle(orc, rp, ci, ov, ob, _np(x), stats, rtol, x0=x0)
+
+
+def test_ensemble_equals_scalar_solves(E, orc):
+    N, s, M, rtol = 10, 8, 10, 1e-10
+    xi = draw_xi(12, s, M)
+    g, vals, _, rhs = _gpu_system(E, N, s, M, 0.3, xi)
+    x, stats, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=rtol))
+    vsm = E.relayout(vals, True)
+    bsm = E.relayout(rhs, True)
+    for lanes in (4, 16):
+        xs, sstats, st = E.scalar_cg(g, vsm, bsm, opts=E.cg_opts(rtol=rtol), lanes_per_row=lanes)
+        assert st == E.ENS_OK
+        xe = _np(x)
+        xsn = _np(xs)
+        for e in range(s):
+            d = _rel(xsn[e], xe[:, e])
+            assert abs(sstats[e]["iters"] - stats[e]["iters"]) <= 1
+            assert d <= (1e-10 if sstats[e]["iters"] == stats[e]["iters"] else 1e-6), (e, d)
+    back = _np(E.relayout(vsm, False))
+    assert np.array_equal(back, _np(vals))
+
+
+def test_cg_edge_cases(E, orc):
+    N, s, M = 6, 4, 3
+    xi = draw_xi(2, s, M)
+    g, vals, _, rhs = _gpu_system(E, N, s, M, 0.1, xi)
+    # zero right-hand side with a nonzero start: x = 0, no iterations
+    x, stats, st = E.cg(g, vals, torch.zeros_like(rhs), x=torch.ones_like(rhs))
+    assert st == E.ENS_OK and not _np(x).any()
+    assert all(t["iters"] == 0 and t["status"] == 0 for t in stats)
+    # starting at the solution: no iterations
+    xs, _, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=1e-13))
+    x, stats, st = E.cg(g, vals, rhs, x=xs.clone(), opts=E.cg_opts(rtol=1e-8))
+    assert all(t["iters"] == 0 and t["status"] == 0 for t in stats)
+    # iteration cap
+    x, stats, st = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=1e-12, max_iter=1))
+    assert st == E.ENS_W_NOT_CONVERGED
+    assert all(t["iters"] == 1 and t["status"] == E.SAMPLE_MAXITER for t in stats)
+    # negative definite: breakdown at the first p.Ap
+    x, stats, st = E.cg(g, -vals, rhs)
+    assert all(t["status"] == E.SAMPLE_BREAKDOWN and t["iters"] == 0 for t in stats)
+    # one NaN sample does not disturb the others
+    xi2 = xi.copy()
+    xi2[1, 0] = np.nan
+    g2, v2, _, b2 = _gpu_system(E, N, s, M, 0.1, xi2)
+    x, stats, st = E.cg(g2, v2, b2)
+    assert stats[1]["status"] == E.SAMPLE_NONFINITE
+    assert all(stats[e]["status"] == 0 for e in (0, 2, 3))
+
+
+def test_cg_masks_freeze_converged_samples(E, orc):
+    # samples with very different conditioning converge at different
+    # iterations; each must match the oracle at its own count
+    N, s, M = 10, 8, 10
+    xi = draw_xi(77, s, M)
+    xi[::2] *= 0.0  # half the samples have constant coefficient
+    g, vals, _, rhs = _gpu_system(E, N, s, M, 0.3, xi)
+    x, stats, st = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=1e-10, check_every=5))
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, 0.3, 1.0, xi)
+    _check_cg_against_oracle(orc, rp, ci, ov, ob, _np(x), stats, 1e-10)
+
+
+# ---------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("N,s,sigma", [(16, 4, 0.1), (12, 32, 0.3), (20, 16, 0.3)])
+def test_mixed_refinement_reaches_fp64_residual(E, orc, N, s, sigma):
+    M, rtol = 10, 1e-8
+    xi = draw_xi(200 + N, s, M)
+    g, vals, v32, rhs = _gpu_system(E, N, s, M, sigma, xi, want32=True)
+    x, stats, st = E.cg(g, vals, rhs, values32=v32, opts=E.cg_opts(rtol=rtol, mixed=True))
+    assert st == E.ENS_OK, stats
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    xg = _np(x)
+    true_res = orc.ens_true_residual(rp, ci, ov, ob, xg)
+    xref, _, _, _ = orc.ens_pcg(rp, ci, ov, ob, rtol=1e-12)
+    for e in range(s):
+        assert stats[e]["status"] == 0 and stats[e]["outer_iters"] >= 1
+        assert true_res[e] <= rtol * (1 + 1e-6), (e, true_res[e])
+        assert abs(stats[e]["rel_res"] - true_res[e]) <= 1e-3 * true_res[e] + 1e-14
+        # error against the FP64 solve is stated, bounded by kappa * rtol
+        assert _rel(xg[:, e], xref[:, e]) <= 1e-5
