@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Benchmark: solved samples/s of the ensemble diffusion solve on one MI355X.
+
+Workload (default): 128^3 hexahedra (2,146,689 nodes, 57,066,625 stored
+entries), M = 10 KL terms, sigma = 0.3, ensemble size s = 32, FP32 Jacobi-CG
+inside FP64 iterative refinement to a true relative residual of 1e-8 per
+sample.  One step = ensemble assembly (FP64 values, FP32 copy, load vector)
++ the refined solve of all 32 samples from a zero guess; inputs (graph, KL
+table, KL inputs y) are resident in HBM before the timed region.
+
+Printed: one JSON line with the contract fields plus
+  roofline      the dominant kernel (FP32 ensemble SpMV of the inner CG):
+                algorithmic bytes per launch / mean launch time from HIP
+                events recorded on the launch stream during the timed steps;
+  cpu_baseline  the FP64 CPU oracle on the host cores (bounded sample);
+  context       FP64 ensemble CG and s one-sample GPU solves of the same
+                samples, per-sample error against an FP64 solve, SpMV GB/s.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solved samples/s at 128^3, s=32, 1e-8 resid; ensemble SpMV HBM GB/s vs scalar"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def spmv_bytes(n, nnz, s, w):
+    """Algorithmic bytes of one ensemble CRS product: values and column
+    indices once, row offsets once, x read once, y written once."""
+    return nnz * (s * w + 4.0) + 4.0 * (n + 1) + 2.0 * n * s * w
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("rowops.hpp", "cg.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1511_03703_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_name):
+    """HBM traffic per launch measured with rocprofv3 counters (see profiles/),
+    valid only while the kernel sources are unchanged."""
+    p = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    ent = d.get(kernel_name)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(w, iters_fp64, cap_iters, threads):
+    """The FP64 oracle (graph, KL, assembly, Jacobi-CG) on `threads` samples in
+    parallel, one sample per thread, on the host cores.  Bounded: each solve
+    runs `cap_iters` iterations; the oracle reports per-sample set-up and
+    solve wall times, and the full solve is scaled with the per-sample FP64
+    iteration counts of the same samples."""
+    from oracle import oracle as orc
+
+    xi = w.xi()[:threads]
+    t0 = time.perf_counter()
+    _, it, _, _, used, tm = orc.solve_samples(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, xi, w.rtol,
+                                              max_iter=cap_iters, want_x=False, timing=True)
+    measured = time.perf_counter() - t0
+    full = []
+    for e in range(threads):
+        t_iter = tm[e, 1] / max(int(it[e]), 1)
+        full.append(tm[e, 0] + iters_fp64[e] * t_iter)
+    wall = max(full)
+    return {
+        "value": threads / wall,
+        "unit": "samples/s",
+        "cores": int(used),
+        "kind": "oracle",
+        "sample": (f"{threads} samples of the same workload, one per OpenMP thread; set-up (graph+KL+assembly) "
+                   f"{tm[:, 0].max():.1f} s, Jacobi-CG capped at {cap_iters} iterations "
+                   f"({tm[:, 1].max():.1f} s); full FP64 solve to {w.rtol:g} scaled with the per-sample FP64 "
+                   f"iteration counts {[int(i) for i in iters_fp64[:threads]]}"),
+        "seconds_measured": round(measured, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="headline", choices=["headline", "mid", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-context", action="store_true", help="skip the FP64 / scalar comparison runs")
+    ap.add_argument("--cpu-threads", type=int, default=4)
+    ap.add_argument("--cpu-cap-iters", type=int, default=25)
+    ap.add_argument("--inner-rtol", type=float, default=1e-4)
+    ap.add_argument("--check-every", type=int, default=16)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
+              f"path is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1511_03703_amd import ens
+    import workloads
+
+    w = {"headline": workloads.HEADLINE, "mid": workloads.MID, "small": workloads.SMALL}[args.workload]
+    dev = "cuda"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    log(f"workload {w.name}: N={w.N} n={w.n} nnz={w.nnz} s={w.s} M={w.M} sigma={w.sigma} mixed={w.mixed}")
+    g = ens.graph_build(w.N)
+    kl = ens.kl_build(w.N, w.M, w.L)
+    xi = torch.as_tensor(w.xi(), device=dev)
+    vals = torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
+    v32 = torch.empty((w.nnz, w.s), dtype=torch.float32, device=dev) if w.mixed else None
+    rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
+    x = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)
+    opts = ens.cg_opts(rtol=w.rtol, mixed=w.mixed, inner_rtol=args.inner_rtol, check_every=args.check_every)
+    ws = torch.empty(ens.cg_workspace_bytes(g, w.s, opts), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, values32=v32, rhs=rhs)
+        x.zero_()
+        return ens.cg(g, vals, rhs, x=x, values32=v32, opts=opts, workspace=ws)
+
+    for i in range(args.warmup):
+        _, stats, st = step()
+        log(f"warmup {i}: status {st}, iters {[s['iters'] for s in stats][:8]}...")
+    torch.cuda.synchronize()
+
+    ens.prof_reset()
+    ens.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_stats = []
+    for i in range(args.steps):
+        _, stats, st = step()
+        all_stats.append(stats)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ens.prof_enable(False)
+    kid = ens.K_SPMV_F32 if w.mixed else ens.K_SPMV_F64
+    pq = ens.prof_query(kid)
+    pa = ens.prof_query(ens.K_ASSEMBLE)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+
+    stats = all_stats[-1]
+    ok = all(s["status"] == 0 and s["rel_res"] <= w.rtol * (1 + 1e-6) for s in stats)
+    value = args.steps * w.s / elapsed
+    wb = 4.0 if w.mixed else 8.0
+    per_launch_bytes = spmv_bytes(w.n, w.nnz, w.s, wb)
+    avg_ms = pq["total_ms"] / max(pq["launches"], 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    kname = f"k_cg_spmv_dot<{'float' if w.mixed else 'double'},{w.s}>"
+    traffic = load_traffic(kname)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kname, "bytes_per_launch": per_launch_bytes, "avg_launch_ms": round(avg_ms, 5),
+                "launches": pq["launches"]}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-in-f64" if w.mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "mesh": f"{w.N}^3 Q1 hexahedra", "n": w.n, "nnz": w.nnz, "s": w.s,
+                   "M": w.M, "sigma": w.sigma, "L": w.L, "rtol": w.rtol, "seed": w.seed,
+                   "inner_rtol": args.inner_rtol if w.mixed else None},
+        "roofline": roofline,
+        "all_converged": ok,
+        "iters": {"inner_total": [s["iters"] for s in stats], "outer": [s["outer_iters"] for s in stats]},
+        "assembly_ms": round(pa["total_ms"] / max(pa["launches"], 1), 3),
+    }
+
+    iters_fp64 = None
+    if not args.no_context:
+        # FP64 ensemble CG of the same samples: reference solution at 1e-12 for
+        # the per-sample error, and the FP64 timing at the target tolerance
+        xr = torch.zeros_like(x)
+        _, st12, _ = ens.cg(g, vals, rhs, x=xr, opts=ens.cg_opts(rtol=1e-12), workspace=None)
+        xs = x.cpu().numpy()
+        xrn = xr.cpu().numpy()
+        err = [float(np.linalg.norm(xs[:, e] - xrn[:, e]) / np.linalg.norm(xrn[:, e])) for e in range(w.s)]
+        x64 = torch.zeros_like(x)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st64, _ = ens.cg(g, vals, rhs, x=x64, opts=ens.cg_opts(rtol=w.rtol, check_every=args.check_every))
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        iters_fp64 = [s["iters"] for s in st64]
+        # s one-sample solves on the same GPU (sample-major layout)
+        vsm = ens.relayout(vals, True)
+        bsm = ens.relayout(rhs, True)
+        del xr
+        best = None
+        for lanes in (8, 16):
+            xsm = torch.zeros_like(bsm)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            _, sst, _ = ens.scalar_cg(g, vsm, bsm, xsm, opts=ens.cg_opts(rtol=w.rtol, check_every=args.check_every),
+                                      lanes_per_row=lanes)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t2
+            if best is None or ts < best[0]:
+                best = (ts, lanes, [s["iters"] for s in sst])
+        del vsm, bsm
+        # standalone SpMV bandwidth, ensemble vs one-sample kernel
+        V = v32 if w.mixed else vals
+        xv = torch.rand((w.n, w.s), dtype=V.dtype, device=dev)
+        yv = torch.empty_like(xv)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            ens.spmv(g, V, xv, yv)
+        e0.record()
+        for _ in range(10):
+            ens.spmv(g, V, xv, yv)
+        e1.record()
+        torch.cuda.synchronize()
+        t_ens = e0.elapsed_time(e1) / 10
+        vs1 = vals[:, 0].contiguous() if not w.mixed else v32[:, 0].contiguous()
+        x1 = torch.rand(w.n, dtype=vs1.dtype, device=dev)
+        y1 = torch.empty_like(x1)
+        for _ in range(3):
+            ens.scalar_spmv(g, vs1, x1, y1, lanes_per_row=16)
+        e0.record()
+        for _ in range(10):
+            ens.scalar_spmv(g, vs1, x1, y1, lanes_per_row=16)
+        e1.record()
+        torch.cuda.synchronize()
+        t_sc = e0.elapsed_time(e1) / 10
+        b_ens = spmv_bytes(w.n, w.nnz, w.s, wb)
+        b_sc = spmv_bytes(w.n, w.nnz, 1, wb)
+        out["context"] = {
+            "per_sample_error_vs_fp64": {"max": max(err), "median": float(np.median(err)),
+                                          "reference": "GPU FP64 ensemble Jacobi-CG to 1e-12"},
+            "fp64_ensemble_cg": {"seconds": round(t64, 4), "samples_per_s": round(w.s / t64, 3),
+                                 "iters": iters_fp64},
+            "scalar_gpu_fp64": {"seconds": round(best[0], 4), "samples_per_s": round(w.s / best[0], 3),
+                                "lanes_per_row": best[1], "iters": best[2],
+                                "speedup_mixed_ensemble": round((w.s / elapsed * args.steps) / (w.s / best[0]), 3),
+                                "speedup_fp64_ensemble": round(best[0] / t64, 3)},
+            "spmv": {"ensemble_ms": round(t_ens, 5), "ensemble_GBs": round(b_ens / t_ens / 1e6, 1),
+                     "ensemble_GFLOPs": round(2.0 * w.nnz * w.s / t_ens / 1e6, 1),
+                     "scalar_ms": round(t_sc, 5), "scalar_GBs": round(b_sc / t_sc / 1e6, 1),
+                     "speedup_s_times_scalar_over_ensemble": round(w.s * t_sc / t_ens, 3),
+                     "dtype": "f32" if w.mixed else "f64"},
+        }
+        del xv, yv, x1, y1
+
+    if not args.no_cpu_baseline:
+        its = iters_fp64 if iters_fp64 is not None else [300] * w.s
+        log("CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(w, its, args.cpu_cap_iters, min(args.cpu_threads, w.s))
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -586,9 +586,18 @@ int orc_ens_pcg(int64_t n, int s, const int32_t *row_ptr, const int32_t *col_idx
 /* One complete sample from scratch: graph, KL coefficient, assembly and
  * Jacobi-CG from a zero guess.  x [n] out.  Used for full-size checks and
  * as the CPU baseline.                                                    */
+static double wall_seconds(void) {
+#ifdef _OPENMP
+  return omp_get_wtime();
+#else
+  return 0.0;
+#endif
+}
+
 int orc_solve_sample(int N, int M, double L, double kappa0, double sigma, double fconst,
                      const double *xi, double rtol, int max_iter, double *x,
-                     int32_t *iters, double *rel_res, int32_t *status) {
+                     int32_t *iters, double *rel_res, int32_t *status, double *timing) {
+  double t0 = wall_seconds();
   int64_t n = orc_num_nodes(N), ne = orc_num_elems(N);
   int64_t nnz = orc_graph_nnz(N);
   int32_t *rp = malloc(sizeof(int32_t) * (size_t)(n + 1)), *ci = malloc(sizeof(int32_t) * (size_t)nnz);
@@ -599,17 +608,22 @@ int orc_solve_sample(int N, int M, double L, double kappa0, double sigma, double
   orc_kl_coef_qp(N, M, L, kappa0, sigma, xi, ac);
   orc_assemble_scalar(N, rp, ci, ac, 0, fconst, 1, v, b);
   for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+  double t1 = wall_seconds();
   int rc = orc_pcg(n, rp, ci, v, b, x, rtol, max_iter, -1, iters, rel_res, status);
+  double t2 = wall_seconds();
+  if (timing) { timing[0] = t1 - t0; timing[1] = t2 - t1; }
   free(rp); free(ci); free(ac); free(v); free(b);
   return rc;
 }
 
 /* Several samples of orc_solve_sample in parallel, one per thread.
- * xi [count][M]; x [count][n] (sample-major, nullable); returns the number
- * of threads used in *threads_used.                                        */
+ * xi [count][M]; x [count][n] (sample-major, nullable); timing [count][2]
+ * (nullable) receives each sample's set-up and solve wall seconds; returns
+ * the number of threads used in *threads_used.                            */
 int orc_solve_samples(int N, int M, double L, double kappa0, double sigma, double fconst,
                       int count, const double *xi, double rtol, int max_iter, double *x,
-                      int32_t *iters, double *rel_res, int32_t *status, int32_t *threads_used) {
+                      int32_t *iters, double *rel_res, int32_t *status, int32_t *threads_used,
+                      double *timing) {
   int64_t n = orc_num_nodes(N);
   int rc = ORC_OK;
   int used = 1;
@@ -623,7 +637,7 @@ int orc_solve_samples(int N, int M, double L, double kappa0, double sigma, doubl
     for (int e = 0; e < count; ++e) {
       double *xe = x ? x + (int64_t)e * n : malloc(sizeof(double) * (size_t)n);
       int r = orc_solve_sample(N, M, L, kappa0, sigma, fconst, xi + (int64_t)e * M, rtol, max_iter,
-                               xe, &iters[e], &rel_res[e], &status[e]);
+                               xe, &iters[e], &rel_res[e], &status[e], timing ? timing + 2 * e : NULL);
       if (r) rc = r;
       if (!x) free(xe);
     }

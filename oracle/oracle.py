@@ -65,9 +65,9 @@ def lib():
         L.orc_pcg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.orc_ens_pcg.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, dbl, ctypes.c_int, vp, vp, vp, vp]
         L.orc_solve_sample.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, dbl,
-                                       ctypes.c_int, vp, vp, vp, vp]
+                                       ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_solve_samples.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int,
-                                        vp, dbl, ctypes.c_int, vp, vp, vp, vp, vp]
+                                        vp, dbl, ctypes.c_int, vp, vp, vp, vp, vp, vp]
         L.orc_ens_true_residual.restype = None
         L.orc_ens_true_residual.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, vp]
         L.orc_crs_to_dense.restype = None
@@ -233,9 +233,10 @@ def ens_pcg(rp, ci, vals, b, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=No
     return x, it, rr, st
 
 
-def solve_samples(N, M, L, kappa0, sigma, fconst, xi, rtol, max_iter=10000, want_x=True):
+def solve_samples(N, M, L, kappa0, sigma, fconst, xi, rtol, max_iter=10000, want_x=True, timing=False):
     """Independent per-sample graph + KL + assembly + Jacobi-CG, one sample per
-    OpenMP thread.  Returns (x [count][n] or None, iters, rel_res, status, threads)."""
+    OpenMP thread.  Returns (x [count][n] or None, iters, rel_res, status,
+    threads) and, with timing=True, per-sample [set-up, solve] wall seconds."""
     xi = _f64(xi)
     count = xi.shape[0]
     n = num_nodes(N)
@@ -244,8 +245,11 @@ def solve_samples(N, M, L, kappa0, sigma, fconst, xi, rtol, max_iter=10000, want
     rr = np.zeros(count)
     st = np.zeros(count, np.int32)
     th = np.zeros(1, np.int32)
+    tm = np.zeros((count, 2))
     _check(lib().orc_solve_samples(N, M, L, kappa0, sigma, fconst, count, _p(xi), rtol, max_iter,
-                                   None if x is None else _p(x), _p(it), _p(rr), _p(st), _p(th)))
+                                   None if x is None else _p(x), _p(it), _p(rr), _p(st), _p(th), _p(tm)))
+    if timing:
+        return x, it, rr, st, int(th[0]), tm
     return x, it, rr, st, int(th[0])
 
 

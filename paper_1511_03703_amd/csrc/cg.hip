@@ -35,7 +35,8 @@ struct Ctl {
   int32_t active[kMaxS], oactive[kMaxS], iters[kMaxS], oiters[kMaxS], kiter[kMaxS], status[kMaxS];
   int32_t zero_b[kMaxS];
   int32_t n_active, n_oactive;
-  uint32_t counter[4];
+  uint32_t counter[4];               // last-group counters, one per reduction site
+  uint32_t gcount[4][kMaxGroups];    // per-group arrival counters
   double rtol, inner_rtol;
   int32_t max_iter, inner_max_iter, max_outer, mixed;
   double tot[2 * kMaxS];
@@ -177,17 +178,18 @@ __device__ void finalize(Ctl* c, int op, int arg) {
   }
 }
 
-// Finishes a reduction site: block partials, last-block totals, finalize.
+// Finishes a reduction site: block partials, grid total, finalize.  The
+// partial buffer holds kMaxPartBlocks block rows followed by kMaxGroups
+// group rows of NQ*S doubles.
 template <int S, int VS, int NQ>
 __device__ inline void reduce_site(double (&vals)[NQ][VS], double* __restrict__ part, Ctl* c, int site, int op,
                                    int arg) {
   block_partials<S, VS, NQ>(vals, part);
-  if (last_block_done(&c->counter[site])) {
-    final_totals<S, NQ>(part, gridDim.x, c->tot);
+  double* gpart = part + (int64_t)kMaxPartBlocks * NQ * S;
+  if (grid_total<NQ * S>(part, gpart, c->gcount[site], &c->counter[site], c->tot)) {
     if (NQ == 1 && threadIdx.x < S) c->tot[S + threadIdx.x] = 0.0;
     __syncthreads();
     finalize<S>(c, op, arg);
-    if (threadIdx.x == 0) c->counter[site] = 0;
   }
 }
 
@@ -222,6 +224,7 @@ __global__ void k_ctl_init(Ctl* c, double rtol, double inner_rtol, int max_iter,
     c->n_oactive = 0;
     for (int i = 0; i < 4; ++i) c->counter[i] = 0;
   }
+  for (int i = threadIdx.x; i < 4 * kMaxGroups; i += blockDim.x) c->gcount[i / kMaxGroups][i % kMaxGroups] = 0;
   if (threadIdx.x < kMaxS) {
     const int e = threadIdx.x;
     c->active[e] = 0;
@@ -265,6 +268,7 @@ __global__ __launch_bounds__(256) void k_residual(int n, const int32_t* __restri
 #pragma unroll
   for (int j = 0; j < M::V; ++j) acc[0][j] = acc[1][j] = 0.0;
   const int64_t tiles = ((int64_t)n + 4 * M::RPW - 1) / (4 * M::RPW);
+#pragma unroll 1
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t row = (tile * 4 + wave) * M::RPW + lane / M::L;
     if (row < n) {
@@ -327,6 +331,7 @@ __global__ __launch_bounds__(256) void k_cg_spmv_dot(int n, const int32_t* __res
 #pragma unroll
   for (int j = 0; j < M::V; ++j) acc[0][j] = 0.0;
   const int64_t tiles = ((int64_t)n + 4 * M::RPW - 1) / (4 * M::RPW);
+#pragma unroll 1
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t row = (tile * 4 + wave) * M::RPW + lane / M::L;
     if (row < n) {
@@ -504,7 +509,7 @@ static size_t ws_layout(int64_t n, int s, bool mixed, Work* w, char* base) {
     return p;
   };
   Ctl* ctl = (Ctl*)take(sizeof(Ctl));
-  double* part = (double*)take((size_t)kMaxPartBlocks * 2 * kMaxS * sizeof(double));
+  double* part = (double*)take((size_t)(kMaxPartBlocks + kMaxGroups) * 2 * kMaxS * sizeof(double));
   const size_t vb = (size_t)n * s * (mixed ? sizeof(float) : sizeof(double));
   void* v[5];
   for (int i = 0; i < 5; ++i) v[i] = take(vb);

@@ -96,46 +96,77 @@ __device__ inline void block_partials(double (&vals)[NQ][VS], double* __restrict
   }
 }
 
-// Returns true in exactly one block: the last to finish writing its
-// partials.  Release/acquire at device scope makes the other blocks'
-// partials visible to it across the XCD L2 caches.
-__device__ inline bool last_block_done(uint32_t* counter) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t prev = atomicAdd(counter, 1u);
-    s_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
+// Deterministic grid-wide total of the per-block partials, finished inside
+// the kernel without a second launch.  Blocks form groups of kGroup
+// consecutive ids; the last block of a group to arrive (device-scope
+// counter) sums its group's partials in block order, and the last group to
+// finish sums the group totals in group order.  Release fences before each
+// arrival and acquire fences after it make the partials written on other
+// XCDs visible.  The summation order depends only on the grid size, so the
+// result is bit-reproducible.  Returns true in the one block that holds the
+// totals (tot[P], global) on exit; counters are left at zero.
+constexpr int kGroup = 32;
+constexpr int kMaxGroups = (kMaxPartBlocks + kGroup - 1) / kGroup;
 
-// In the last block: tot[q][e] = sum over blocks of part[b][q][e], in
-// ascending block order within each of G interleaved stripes, stripes then
-// combined in order (deterministic for a fixed grid size).
-template <int S, int NQ>
-__device__ inline void final_totals(const double* __restrict__ part, int nblocks, double* __restrict__ tot) {
-  constexpr int P = NQ * S;
-  constexpr int G = kBlock / P > 0 ? kBlock / P : 1;
+// dst[qe] = sum over r < rows of src[r*P + qe], rows split into G stripes
+// that are then added in order.
+template <int P>
+__device__ inline void sum_rows(const double* __restrict__ src, int rows, double* __restrict__ dst) {
+  constexpr int G = kBlock / P;
   __shared__ double stripe[G][P];
   const int t = threadIdx.x;
-  if (t < G * P) {
-    const int g = t / P, qe = t % P;
-    double acc = 0.0;
-    const volatile double* vp = part;
-    for (int b = g; b < nblocks; b += G) acc += vp[(int64_t)b * P + qe];
-    stripe[g][qe] = acc;
+  const int g = t / P, qe = t % P;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int r = g;
+  for (; r + 3 * G < rows; r += 4 * G) {
+    const double v0 = src[(int64_t)r * P + qe];
+    const double v1 = src[(int64_t)(r + G) * P + qe];
+    const double v2 = src[(int64_t)(r + 2 * G) * P + qe];
+    const double v3 = src[(int64_t)(r + 3 * G) * P + qe];
+    a0 += v0;
+    a1 += v1;
+    a2 += v2;
+    a3 += v3;
   }
+  for (; r < rows; r += G) a0 += src[(int64_t)r * P + qe];
+  stripe[g][qe] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   if (t < P) {
     double acc = 0.0;
 #pragma unroll
-    for (int g = 0; g < G; ++g) acc += stripe[g][t];
-    tot[t] = acc;
+    for (int k = 0; k < G; ++k) acc += stripe[k][t];
+    dst[t] = acc;
   }
   __syncthreads();
+}
+
+template <int P>
+__device__ inline bool grid_total(const double* __restrict__ part, double* __restrict__ gpart,
+                                  uint32_t* __restrict__ gcount, uint32_t* __restrict__ topcount,
+                                  double* __restrict__ tot) {
+  __shared__ int s_last;
+  const int nb = gridDim.x;
+  const int ng = (nb + kGroup - 1) / kGroup;
+  const int grp = blockIdx.x / kGroup;
+  const int gsize = min(kGroup, nb - grp * kGroup);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = (atomicAdd(&gcount[grp], 1u) == (uint32_t)gsize - 1);
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  sum_rows<P>(part + (int64_t)grp * kGroup * P, gsize, gpart + (int64_t)grp * P);
+  if (threadIdx.x == 0) gcount[grp] = 0;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = (atomicAdd(topcount, 1u) == (uint32_t)ng - 1);
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  sum_rows<P>(gpart, ng, tot);
+  if (threadIdx.x == 0) *topcount = 0;
+  __syncthreads();
+  return true;
 }
 
 }  // namespace ens
