@@ -10,17 +10,22 @@
 // pass over the graph.  The preconditioner is the diagonal instance of the
 // ensemble preconditioner M_c = sum_i M_i (x) e_i e_i^T of Sec. 3.5.
 //
-// One iteration is three fused kernels:
-//   A: q = A p and the per-sample partials of p.q   -> alpha_e (last block)
+// One iteration is three fused streaming kernels plus two small reduction
+// kernels after each of the first two:
+//   A: q = A p and per-block partials of p.q          -> alpha_e
 //   B: x += alpha p, r -= alpha q, z = D^-1 r, partials of r.z and r.r
-//                                                   -> masks, beta_e (last block)
+//                                                      -> masks, beta_e, rho_e
 //   C: p = z + beta p
-// Reductions are two-level and deterministic: wave butterflies between lanes
-// holding the same samples, a fixed-order LDS sum per block, and the block
-// partials summed in a fixed order by the last block to finish.  That block
-// also updates the per-sample scalars and the count of active samples; every
-// kernel returns immediately when the count is zero, and the host reads the
-// count once per chunk of iterations, so the loop ends on the device.
+// Reductions are deterministic: wave butterflies between lanes holding the
+// same samples, a fixed-order LDS sum per block, then the block partials are
+// summed by a striped first stage and a one-block final stage, each in a
+// fixed order, and the final stage updates the per-sample scalars and the
+// count of active samples.  Producing kernels publish their partials by
+// ending (no device-scope fences inside kernels: on this part a fence
+// writes back and invalidates the XCD's L2, which costs more than the
+// launch it saves).  Every kernel of the iteration returns immediately when
+// the active count is zero, and the host reads the count once per chunk of
+// iterations, so the loop ends on the device.
 #include "rowops.hpp"
 
 namespace ens {
@@ -35,8 +40,6 @@ struct Ctl {
   int32_t active[kMaxS], oactive[kMaxS], iters[kMaxS], oiters[kMaxS], kiter[kMaxS], status[kMaxS];
   int32_t zero_b[kMaxS];
   int32_t n_active, n_oactive;
-  uint32_t counter[4];               // last-group counters, one per reduction site
-  uint32_t gcount[4][kMaxGroups];    // per-group arrival counters
   double rtol, inner_rtol;
   int32_t max_iter, inner_max_iter, max_outer, mixed;
   double tot[2 * kMaxS];
@@ -178,19 +181,35 @@ __device__ void finalize(Ctl* c, int op, int arg) {
   }
 }
 
-// Finishes a reduction site: block partials, grid total, finalize.  The
-// partial buffer holds kMaxPartBlocks block rows followed by kMaxGroups
-// group rows of NQ*S doubles.
-template <int S, int VS, int NQ>
-__device__ inline void reduce_site(double (&vals)[NQ][VS], double* __restrict__ part, Ctl* c, int site, int op,
-                                   int arg) {
-  block_partials<S, VS, NQ>(vals, part);
-  double* gpart = part + (int64_t)kMaxPartBlocks * NQ * S;
-  if (grid_total<NQ * S>(part, gpart, c->gcount[site], &c->counter[site], c->tot)) {
-    if (NQ == 1 && threadIdx.x < S) c->tot[S + threadIdx.x] = 0.0;
-    __syncthreads();
-    finalize<S>(c, op, arg);
-  }
+// Streaming kernels process kU chunks per thread: all loads of a thread
+// are issued before its stores, so the in-order memory counter never makes
+// a load wait for an earlier store.
+constexpr int kU = 4;
+// First reduction stage: at most this many blocks, each summing >= 64 rows.
+constexpr int kRedBlocks = 128;
+
+// Stage 1: rows split into gridDim.x contiguous ranges, block b sums its
+// range (fixed order) into out[b][P].
+template <int P>
+__global__ __launch_bounds__(256) void k_reduce_stage1(const double* __restrict__ part, int64_t nrows,
+                                                       double* __restrict__ out, const Ctl* c, int gate) {
+  if (gate && c->n_active == 0) return;
+  const int64_t chunk = (nrows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = r0 + chunk < nrows ? r0 + chunk : nrows;
+  sum_rows<P>(part + r0 * P, r1 > r0 ? r1 - r0 : 0, out + (int64_t)blockIdx.x * P);
+}
+
+// Stage 2: one block sums the stage-1 rows in order and updates the
+// per-sample state.
+template <int S, int NQ>
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ rows, int64_t nrows, Ctl* c,
+                                                      int op, int arg, int gate) {
+  if (gate && c->n_active == 0) return;
+  sum_rows<NQ * S>(rows, nrows, c->tot);
+  if (NQ == 1 && threadIdx.x < S) c->tot[S + threadIdx.x] = 0.0;
+  __syncthreads();
+  finalize<S>(c, op, arg);
 }
 
 // --------------------------------------------------------- vector mapping ---
@@ -222,9 +241,7 @@ __global__ void k_ctl_init(Ctl* c, double rtol, double inner_rtol, int max_iter,
     c->mixed = mixed;
     c->n_active = 0;
     c->n_oactive = 0;
-    for (int i = 0; i < 4; ++i) c->counter[i] = 0;
   }
-  for (int i = threadIdx.x; i < 4 * kMaxGroups; i += blockDim.x) c->gcount[i / kMaxGroups][i % kMaxGroups] = 0;
   if (threadIdx.x < kMaxS) {
     const int e = threadIdx.x;
     c->active[e] = 0;
@@ -254,74 +271,80 @@ __global__ __launch_bounds__(256) void k_diag_inv(int n, const int32_t* __restri
 }
 
 // r = b - A x in FP64 for every sample (ensemble layout), optionally stored
-// (rounded to TR), with partials |r|^2 and |b|^2.
+// (rounded to TR), with block partials |r|^2 and |b|^2.  One row tile per
+// block.
 template <int S, typename TR>
 __global__ __launch_bounds__(256) void k_residual(int n, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const double* __restrict__ vals,
                                                   const double* __restrict__ x, const double* __restrict__ b,
-                                                  TR* __restrict__ rout, Ctl* c, double* __restrict__ part, int op,
-                                                  int arg) {
+                                                  TR* __restrict__ rout, double* __restrict__ part) {
   using M = EnsMap<double, S>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane % M::L;
   double acc[2][M::V];
 #pragma unroll
   for (int j = 0; j < M::V; ++j) acc[0][j] = acc[1][j] = 0.0;
-  const int64_t tiles = ((int64_t)n + 4 * M::RPW - 1) / (4 * M::RPW);
-#pragma unroll 1
-  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const int64_t row = (tile * 4 + wave) * M::RPW + lane / M::L;
-    if (row < n) {
-      typename M::vt ax = ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
-      typename M::vt bv = ((const typename M::vt*)b)[row * M::L + sub];
-      typename M::vt r = bv - ax;
+  const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
+  if (row < n) {
+    typename M::vt ax = ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
+    typename M::vt bv = ((const typename M::vt*)b)[row * M::L + sub];
+    typename M::vt r = bv - ax;
 #pragma unroll
-      for (int j = 0; j < M::V; ++j) {
-        acc[0][j] += r[j] * r[j];
-        acc[1][j] += bv[j] * bv[j];
-      }
-      if (rout) {
+    for (int j = 0; j < M::V; ++j) {
+      acc[0][j] = r[j] * r[j];
+      acc[1][j] = bv[j] * bv[j];
+    }
+    if (rout) {
 #pragma unroll
-        for (int j = 0; j < M::V; ++j) rout[row * S + sub * M::V + j] = (TR)r[j];
-      }
+      for (int j = 0; j < M::V; ++j) rout[row * S + sub * M::V + j] = (TR)r[j];
     }
   }
-  reduce_site<S, M::V, 2>(acc, part, c, 0, op, arg);
+  block_partials<S, M::V, 2>(acc, part);
 }
 
 // z = D^-1 r, p = z (all samples); optionally zero the solution vector;
-// partials r.z and r.r; finalize OP_RHO.
+// block partials r.z and r.r.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cg_start(int64_t nchunks, const T* __restrict__ r,
                                                   const T* __restrict__ dinv, T* __restrict__ p,
-                                                  T* __restrict__ xzero, Ctl* c, double* __restrict__ part) {
+                                                  T* __restrict__ xzero, double* __restrict__ part) {
   using M = VecMap<T, S>;
   using vt = typename M::vt;
-  const int sub = (threadIdx.x & 63) % M::L;
   double acc[2][M::VS];
 #pragma unroll
   for (int j = 0; j < M::VS; ++j) acc[0][j] = acc[1][j] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nchunks; i += stride) {
-    vt rv = ((const vt*)r)[i], dv = ((const vt*)dinv)[i];
-    vt z = dv * rv;
-    ((vt*)p)[i] = z;
-    if (xzero) ((vt*)xzero)[i] = (vt)0;
+  const int64_t base = (int64_t)blockIdx.x * kBlock * kU + threadIdx.x;
+  vt rv[kU], dv[kU];
 #pragma unroll
-    for (int v = 0; v < M::V; ++v) {
-      acc[0][M::slot(v)] += (double)rv[v] * (double)z[v];
-      acc[1][M::slot(v)] += (double)rv[v] * (double)rv[v];
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      rv[u] = ((const vt*)r)[i];
+      dv[u] = ((const vt*)dinv)[i];
     }
   }
-  (void)sub;
-  reduce_site<S, M::VS, 2>(acc, part, c, 1, OP_RHO, 0);
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      vt z = dv[u] * rv[u];
+      ((vt*)p)[i] = z;
+      if (xzero) ((vt*)xzero)[i] = (vt)0;
+#pragma unroll
+      for (int v = 0; v < M::V; ++v) {
+        acc[0][M::slot(v)] += (double)rv[u][v] * (double)z[v];
+        acc[1][M::slot(v)] += (double)rv[u][v] * (double)rv[u][v];
+      }
+    }
+  }
+  block_partials<S, M::VS, 2>(acc, part);
 }
 
-// A: q = A p, partials p.q, finalize alpha.
+// A: q = A p, block partials p.q.  One row tile per block.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cg_spmv_dot(int n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const T* __restrict__ vals,
-                                                     const T* __restrict__ p, T* __restrict__ q, Ctl* c,
+                                                     const T* __restrict__ p, T* __restrict__ q, const Ctl* c,
                                                      double* __restrict__ part) {
   if (c->n_active == 0) return;
   using M = EnsMap<T, S>;
@@ -330,70 +353,89 @@ __global__ __launch_bounds__(256) void k_cg_spmv_dot(int n, const int32_t* __res
   double acc[1][M::V];
 #pragma unroll
   for (int j = 0; j < M::V; ++j) acc[0][j] = 0.0;
-  const int64_t tiles = ((int64_t)n + 4 * M::RPW - 1) / (4 * M::RPW);
-#pragma unroll 1
-  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const int64_t row = (tile * 4 + wave) * M::RPW + lane / M::L;
-    if (row < n) {
-      typename M::vt qv = ens_row_product<T, S>(ci, vals, p, rp[row], rp[row + 1], sub);
-      ((typename M::vt*)q)[row * M::L + sub] = qv;
-      typename M::vt pv = ((const typename M::vt*)p)[row * M::L + sub];
+  const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
+  if (row < n) {
+    typename M::vt qv = ens_row_product<T, S>(ci, vals, p, rp[row], rp[row + 1], sub);
+    ((typename M::vt*)q)[row * M::L + sub] = qv;
+    typename M::vt pv = ((const typename M::vt*)p)[row * M::L + sub];
 #pragma unroll
-      for (int j = 0; j < M::V; ++j) acc[0][j] += (double)pv[j] * (double)qv[j];
-    }
+    for (int j = 0; j < M::V; ++j) acc[0][j] = (double)pv[j] * (double)qv[j];
   }
-  reduce_site<S, M::V, 1>(acc, part, c, 2, OP_ALPHA, 0);
+  block_partials<S, M::V, 1>(acc, part);
 }
 
-// B: x += alpha p; r -= alpha q; z = D^-1 r; partials r.z, r.r; finalize.
+// B: x += alpha p; r -= alpha q; z = D^-1 r; block partials r.z, r.r.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cg_update(int64_t nchunks, T* __restrict__ x, const T* __restrict__ p,
                                                    const T* __restrict__ q, T* __restrict__ r,
-                                                   const T* __restrict__ dinv, Ctl* c, double* __restrict__ part,
-                                                   int k) {
+                                                   const T* __restrict__ dinv, const Ctl* c,
+                                                   double* __restrict__ part) {
   if (c->n_active == 0) return;
   using M = VecMap<T, S>;
   using vt = typename M::vt;
   const int sub = (threadIdx.x & 63) % M::L;
   vt al;
-  bool any = false;
   int act[M::V];
 #pragma unroll
   for (int v = 0; v < M::V; ++v) {
     const int e = M::sample(sub, v);
     act[v] = c->active[e];
     al[v] = act[v] ? (T)c->alpha[e] : (T)0;
-    any |= act[v] != 0;
   }
   double acc[2][M::VS];
 #pragma unroll
   for (int j = 0; j < M::VS; ++j) acc[0][j] = acc[1][j] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (any) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nchunks; i += stride) {
-      vt pv = ((const vt*)p)[i], qv = ((const vt*)q)[i], rv = ((const vt*)r)[i], xv = ((const vt*)x)[i];
-      vt dv = ((const vt*)dinv)[i];
-      xv += al * pv;
-      rv -= al * qv;
-      vt z = dv * rv;
-      ((vt*)x)[i] = xv;
-      ((vt*)r)[i] = rv;
+  const int64_t base = (int64_t)blockIdx.x * kBlock * kU + threadIdx.x;
+  vt pv[kU], qv[kU], rv[kU], xv[kU], dv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      pv[u] = ((const vt*)p)[i];
+      qv[u] = ((const vt*)q)[i];
+      rv[u] = ((const vt*)r)[i];
+      xv[u] = ((const vt*)x)[i];
+      dv[u] = ((const vt*)dinv)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      vt xn = xv[u] + al * pv[u];
+      vt rn = rv[u] - al * qv[u];
+#pragma unroll
+      for (int v = 0; v < M::V; ++v)  // converged or stopped samples stay frozen
+        if (!act[v]) {
+          xn[v] = xv[u][v];
+          rn[v] = rv[u][v];
+        }
+      xv[u] = xn;
+      rv[u] = rn;
+      vt z = dv[u] * rn;
 #pragma unroll
       for (int v = 0; v < M::V; ++v) {
-        if (act[v]) {
-          acc[0][M::slot(v)] += (double)rv[v] * (double)z[v];
-          acc[1][M::slot(v)] += (double)rv[v] * (double)rv[v];
-        }
+        const double rr = act[v] ? (double)rn[v] : 0.0;
+        acc[0][M::slot(v)] += rr * (double)z[v];
+        acc[1][M::slot(v)] += rr * rr;
       }
     }
   }
-  reduce_site<S, M::VS, 2>(acc, part, c, 3, OP_UPDATE, k);
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      ((vt*)x)[i] = xv[u];
+      ((vt*)r)[i] = rv[u];
+    }
+  }
+  block_partials<S, M::VS, 2>(acc, part);
 }
 
 // C: p = D^-1 r + beta p for the samples still active.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cg_pupdate(int64_t nchunks, const T* __restrict__ r,
-                                                    const T* __restrict__ dinv, T* __restrict__ p, Ctl* c) {
+                                                    const T* __restrict__ dinv, T* __restrict__ p, const Ctl* c) {
   if (c->n_active == 0) return;
   using M = VecMap<T, S>;
   using vt = typename M::vt;
@@ -409,14 +451,27 @@ __global__ __launch_bounds__(256) void k_cg_pupdate(int64_t nchunks, const T* __
     any |= act[v] != 0;
   }
   if (!any) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nchunks; i += stride) {
-    vt rv = ((const vt*)r)[i], dv = ((const vt*)dinv)[i], pv = ((const vt*)p)[i];
-    vt pn = dv * rv + be * pv;
+  const int64_t base = (int64_t)blockIdx.x * kBlock * kU + threadIdx.x;
+  vt pv[kU], rv[kU], dv[kU];
 #pragma unroll
-    for (int v = 0; v < M::V; ++v)  // inactive samples keep their p
-      if (!act[v]) pn[v] = pv[v];
-    ((vt*)p)[i] = pn;
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      pv[u] = ((const vt*)p)[i];
+      rv[u] = ((const vt*)r)[i];
+      dv[u] = ((const vt*)dinv)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      vt pn = dv[u] * rv[u] + be * pv[u];
+#pragma unroll
+      for (int v = 0; v < M::V; ++v)  // inactive samples keep their p
+        if (!act[v]) pn[v] = pv[u][v];
+      ((vt*)p)[i] = pn;
+    }
   }
 }
 
@@ -442,64 +497,74 @@ __global__ __launch_bounds__(256) void k_zero_where(int64_t total, double* __res
 
 // ----------------------------------------------- one-sample (scalar) path ---
 
-// residual with G lanes per row (scalar CRS)
+// r = b - A x with G lanes per row (scalar CRS), block partials |r|^2, |b|^2.
 template <int G>
 __global__ __launch_bounds__(256) void k_residual_scalar(int n, const int32_t* __restrict__ rp,
                                                          const int32_t* __restrict__ ci,
                                                          const double* __restrict__ vals,
                                                          const double* __restrict__ x,
                                                          const double* __restrict__ b, double* __restrict__ rout,
-                                                         Ctl* c, double* __restrict__ part, int op) {
+                                                         double* __restrict__ part) {
   const int g = threadIdx.x % G;
   double acc[2][1] = {{0.0}, {0.0}};
-  const int64_t rows_per_iter = (int64_t)gridDim.x * (256 / G);
-  for (int64_t row = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; row < n; row += rows_per_iter) {
-    double s = 0.0;
+  const int64_t row = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  double s = 0.0;
+  if (row < n)
     for (int64_t k = rp[row] + g; k < rp[row + 1]; k += G) s += __builtin_nontemporal_load(vals + k) * x[ci[k]];
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (g == 0) {
-      const double r = b[row] - s;
-      if (rout) rout[row] = r;
-      acc[0][0] += r * r;
-      acc[1][0] += b[row] * b[row];
-    }
+  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (row < n && g == 0) {
+    const double r = b[row] - s;
+    if (rout) rout[row] = r;
+    acc[0][0] = r * r;
+    acc[1][0] = b[row] * b[row];
   }
-  reduce_site<1, 1, 2>(acc, part, c, 0, op, 0);
+  block_partials<1, 1, 2>(acc, part);
 }
 
+// q = A p with G lanes per row, block partials p.q.
 template <int G>
 __global__ __launch_bounds__(256) void k_cg_spmv_dot_scalar(int n, const int32_t* __restrict__ rp,
                                                             const int32_t* __restrict__ ci,
                                                             const double* __restrict__ vals,
                                                             const double* __restrict__ p, double* __restrict__ q,
-                                                            Ctl* c, double* __restrict__ part) {
+                                                            const Ctl* c, double* __restrict__ part) {
   if (c->n_active == 0) return;
   const int g = threadIdx.x % G;
   double acc[1][1] = {{0.0}};
-  const int64_t rows_per_iter = (int64_t)gridDim.x * (256 / G);
-  for (int64_t row = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; row < n; row += rows_per_iter) {
-    double s = 0.0;
+  const int64_t row = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  double s = 0.0;
+  if (row < n)
     for (int64_t k = rp[row] + g; k < rp[row + 1]; k += G) s += __builtin_nontemporal_load(vals + k) * p[ci[k]];
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (g == 0) {
-      q[row] = s;
-      acc[0][0] += p[row] * s;
-    }
+  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (row < n && g == 0) {
+    q[row] = s;
+    acc[0][0] = p[row] * s;
   }
-  reduce_site<1, 1, 1>(acc, part, c, 2, OP_ALPHA, 0);
+  block_partials<1, 1, 1>(acc, part);
 }
 
 // ------------------------------------------------------------ host side ---
 
 struct Work {
   Ctl* ctl;
-  double* part;
+  double* part;   // block partials, [blocks][2 s]
+  double* part1;  // first-stage sums, [kRedBlocks][2 s]
   void* vec[5];
 };
 
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Largest grid of any kernel that writes block partials for this problem.
+static int64_t max_partial_blocks(int64_t n, int s) {
+  if (s == 1) return (n * 32 + kBlock - 1) / kBlock + 1;  // up to 32 lanes per row
+  // row kernels: 4 waves x 64/L rows, L = s/V >= s/2 (FP64 rows of the residual)
+  const int64_t row_blocks = (n * s + 511) / 512 + 1;
+  // streaming kernels: kU chunks of >= 2 samples per thread
+  const int64_t vec_blocks = (n * s / 2 + kBlock * kU - 1) / (kBlock * kU) + 1;
+  return row_blocks > vec_blocks ? row_blocks : vec_blocks;
+}
 
 static size_t ws_layout(int64_t n, int s, bool mixed, Work* w, char* base) {
   size_t off = 0;
@@ -509,30 +574,39 @@ static size_t ws_layout(int64_t n, int s, bool mixed, Work* w, char* base) {
     return p;
   };
   Ctl* ctl = (Ctl*)take(sizeof(Ctl));
-  double* part = (double*)take((size_t)(kMaxPartBlocks + kMaxGroups) * 2 * kMaxS * sizeof(double));
+  double* part = (double*)take((size_t)max_partial_blocks(n, s) * 2 * s * sizeof(double));
+  double* part1 = (double*)take((size_t)kRedBlocks * 2 * s * sizeof(double));
   const size_t vb = (size_t)n * s * (mixed ? sizeof(float) : sizeof(double));
   void* v[5];
   for (int i = 0; i < 5; ++i) v[i] = take(vb);
   if (w) {
     w->ctl = ctl;
     w->part = part;
+    w->part1 = part1;
     for (int i = 0; i < 5; ++i) w->vec[i] = v[i];
   }
   return off;
 }
 
-static int stream_blocks(int64_t items) {
-  int64_t b = (items + kBlock - 1) / kBlock;
-  if (b > kStreamBlocks) b = kStreamBlocks;
-  if (b < 1) b = 1;
-  return (int)b;
+static unsigned grid_for(int64_t items, int64_t per_block) {
+  int64_t b = (items + per_block - 1) / per_block;
+  return (unsigned)(b < 1 ? 1 : b);
 }
 
-static int row_blocks(int64_t n, int rows_per_tile) {
-  int64_t b = (n + rows_per_tile - 1) / rows_per_tile;
-  if (b > kStreamBlocks) b = kStreamBlocks;
-  if (b < 1) b = 1;
-  return (int)b;
+// Sum `nrows` block partials of NQ*S doubles and run the finalize step.
+// Small grids go straight to the one-block final stage.
+template <int S, int NQ>
+static void reduce(const Work& w, int64_t nrows, int op, int arg, int gate, hipStream_t st) {
+  constexpr int P = NQ * S;
+  if (nrows <= 512) {
+    hipLaunchKernelGGL((k_reduce_final<S, NQ>), dim3(1), dim3(kBlock), 0, st, w.part, nrows, w.ctl, op, arg, gate);
+    return;
+  }
+  int64_t r = nrows / 64;
+  if (r > kRedBlocks) r = kRedBlocks;
+  hipLaunchKernelGGL((k_reduce_stage1<P>), dim3((unsigned)r), dim3(kBlock), 0, st, w.part, nrows, w.part1, w.ctl,
+                     gate);
+  hipLaunchKernelGGL((k_reduce_final<S, NQ>), dim3(1), dim3(kBlock), 0, st, w.part1, r, w.ctl, op, arg, gate);
 }
 
 static ens_status poll_active(Ctl* ctl, bool outer, hipStream_t st, int32_t* out) {
@@ -549,29 +623,36 @@ static ens_status poll_active(Ctl* ctl, bool outer, hipStream_t st, int32_t* out
   return ENS_OK;
 }
 
+// Launches of one CG iteration (A, reductions, B, reductions, C).
+template <typename T, int S>
+static void cg_iteration(const ens_graph* g, const T* vals, T* x, T* r, T* p, T* q, T* dinv, const Work& w, int k,
+                         hipStream_t st) {
+  using M = EnsMap<T, S>;
+  using VM = VecMap<T, S>;
+  const int64_t nchunks = (int64_t)g->n * S / VM::V;
+  const unsigned sb = grid_for(g->n, 4 * M::RPW);
+  const unsigned vb = grid_for(nchunks, (int64_t)kBlock * kU);
+  const int kid = sizeof(T) == 8 ? ENS_K_SPMV_F64 : ENS_K_SPMV_F32;
+  const double wv = sizeof(T);
+  const double spmv_bytes = (double)g->nnz * (S * wv + 4.0) + 4.0 * (g->n + 1) + 2.0 * g->n * S * wv;
+  prof_begin(kid, st);
+  hipLaunchKernelGGL((k_cg_spmv_dot<T, S>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, p, q,
+                     w.ctl, w.part);
+  prof_end(kid, st, spmv_bytes);
+  reduce<S, 1>(w, sb, OP_ALPHA, 0, 1, st);
+  hipLaunchKernelGGL((k_cg_update<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, x, p, q, r, dinv, w.ctl, w.part);
+  reduce<S, 2>(w, vb, OP_UPDATE, k, 1, st);
+  hipLaunchKernelGGL((k_cg_pupdate<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, r, dinv, p, w.ctl);
+}
+
 // CG loop on already-initialised state; x is the solution (FP64 CG) or
 // the correction d (refinement inner solve).
 template <typename T, int S>
 static ens_status cg_loop(const ens_graph* g, const T* vals, T* x, T* r, T* p, T* q, T* dinv, Work& w,
                           int max_iter, int check_every, hipStream_t st) {
-  using M = EnsMap<T, S>;
-  const int64_t nchunks = (int64_t)g->n * S / VecMap<T, S>::V;
-  const int vb = stream_blocks(nchunks);
-  const int sb = row_blocks(g->n, 4 * M::RPW);
-  const int kid = sizeof(T) == 8 ? ENS_K_SPMV_F64 : ENS_K_SPMV_F32;
-  const double w_ = sizeof(T);
-  const double spmv_bytes = (double)g->nnz * (S * w_ + 4.0) + 4.0 * (g->n + 1) + 2.0 * g->n * S * w_;
   for (int k0 = 0; k0 < max_iter; k0 += check_every) {
     const int k1 = k0 + check_every < max_iter ? k0 + check_every : max_iter;
-    for (int k = k0 + 1; k <= k1; ++k) {
-      prof_begin(kid, st);
-      hipLaunchKernelGGL((k_cg_spmv_dot<T, S>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals,
-                         p, q, w.ctl, w.part);
-      prof_end(kid, st, spmv_bytes);
-      hipLaunchKernelGGL((k_cg_update<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, x, p, q, r, dinv, w.ctl,
-                         w.part, k);
-      hipLaunchKernelGGL((k_cg_pupdate<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, r, dinv, p, w.ctl);
-    }
+    for (int k = k0 + 1; k <= k1; ++k) cg_iteration<T, S>(g, vals, x, r, p, q, dinv, w, k, st);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
     ens_status s2 = poll_active(w.ctl, false, st, &act);
@@ -598,30 +679,44 @@ static ens_status read_stats(Ctl* ctl, int s, ens_cg_stat* stats, hipStream_t st
   return rc;
 }
 
+// FP64 residual r = b - A x (stored as TR when rout is given) and the
+// finalize step `op` on its norms.
+template <int S, typename TR>
+static void residual(const ens_graph* g, const double* vals, const double* x, const double* b, TR* rout,
+                     const Work& w, int op, int arg, hipStream_t st) {
+  using M = EnsMap<double, S>;
+  const unsigned sb = grid_for(g->n, 4 * M::RPW);
+  hipLaunchKernelGGL((k_residual<S, TR>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
+                     rout, w.part);
+  reduce<S, 2>(w, sb, op, arg, 0, st);
+}
+
+template <typename T, int S>
+static void cg_start(int64_t n, const T* r, const T* dinv, T* p, T* xzero, const Work& w, hipStream_t st) {
+  const int64_t nchunks = n * S / VecMap<T, S>::V;
+  const unsigned vb = grid_for(nchunks, (int64_t)kBlock * kU);
+  hipLaunchKernelGGL((k_cg_start<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, r, dinv, p, xzero, w.part);
+  reduce<S, 2>(w, vb, OP_RHO, 0, 0, st);
+}
+
 template <int S>
 static ens_status cg_fp64(const ens_graph* g, const double* vals, const double* b, double* x,
                           const ens_cg_opts& o, Work& w, hipStream_t st) {
-  using M = EnsMap<double, S>;
   double* r = (double*)w.vec[0];
   double* p = (double*)w.vec[1];
   double* q = (double*)w.vec[2];
   double* dinv = (double*)w.vec[3];
   const int64_t n = g->n;
   const int64_t total = n * S;
-  const int sb = row_blocks(n, 4 * M::RPW);
-  const int vb = stream_blocks(total / VecMap<double, S>::V);
-  hipLaunchKernelGGL((k_diag_inv<double, S>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g->n,
-                     g->row_ptr, g->col_idx, vals, dinv);
-  hipLaunchKernelGGL((k_residual<S, double>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x,
-                     b, r, w.ctl, w.part, (int)OP_START, 0);
-  hipLaunchKernelGGL(k_zero_where<S>, dim3(stream_blocks(total)), dim3(kBlock), 0, st, total, x, w.ctl);
-  hipLaunchKernelGGL((k_cg_start<double, S>), dim3(vb), dim3(kBlock), 0, st, total / VecMap<double, S>::V, r, dinv, p,
-                     (double*)nullptr, w.ctl, w.part);
+  hipLaunchKernelGGL((k_diag_inv<double, S>), dim3(grid_for(total, 256)), dim3(256), 0, st, g->n, g->row_ptr,
+                     g->col_idx, vals, dinv);
+  residual<S, double>(g, vals, x, b, r, w, OP_START, 0, st);
+  hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
+  cg_start<double, S>(n, r, dinv, p, (double*)nullptr, w, st);
   ENS_LAUNCH_CHECK();
   ens_status rc = cg_loop<double, S>(g, vals, x, r, p, q, dinv, w, o.max_iter, o.check_every, st);
   if (rc != ENS_OK) return rc;
-  hipLaunchKernelGGL((k_residual<S, double>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x,
-                     b, (double*)nullptr, w.ctl, w.part, (int)OP_TRUE, 0);
+  residual<S, double>(g, vals, x, b, (double*)nullptr, w, OP_TRUE, 0, st);
   ENS_LAUNCH_CHECK();
   return ENS_OK;
 }
@@ -629,7 +724,6 @@ static ens_status cg_fp64(const ens_graph* g, const double* vals, const double* 
 template <int S>
 static ens_status cg_mixed(const ens_graph* g, const double* vals, const float* vals32, const double* b, double* x,
                            const ens_cg_opts& o, Work& w, hipStream_t st) {
-  using M = EnsMap<double, S>;
   float* r = (float*)w.vec[0];
   float* p = (float*)w.vec[1];
   float* q = (float*)w.vec[2];
@@ -637,27 +731,23 @@ static ens_status cg_mixed(const ens_graph* g, const double* vals, const float* 
   float* d = (float*)w.vec[4];
   const int64_t n = g->n;
   const int64_t total = n * S;
-  const int sb = row_blocks(n, 4 * M::RPW);
-  const int vb = stream_blocks(total / VecMap<float, S>::V);
-  hipLaunchKernelGGL((k_diag_inv<float, S>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g->n,
-                     g->row_ptr, g->col_idx, vals32, dinv);
+  hipLaunchKernelGGL((k_diag_inv<float, S>), dim3(grid_for(total, 256)), dim3(256), 0, st, g->n, g->row_ptr,
+                     g->col_idx, vals32, dinv);
   ENS_LAUNCH_CHECK();
   for (int outer = 0;; ++outer) {
-    hipLaunchKernelGGL((k_residual<S, float>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals,
-                       x, b, r, w.ctl, w.part, (int)OP_OUTER, outer);
-    if (outer == 0) hipLaunchKernelGGL(k_zero_where<S>, dim3(stream_blocks(total)), dim3(kBlock), 0, st, total, x,
-                                       w.ctl);
+    residual<S, float>(g, vals, x, b, r, w, OP_OUTER, outer, st);
+    if (outer == 0)
+      hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
     ens_status rc = poll_active(w.ctl, true, st, &act);
     if (rc != ENS_OK) return rc;
     if (act == 0) break;
-    hipLaunchKernelGGL((k_cg_start<float, S>), dim3(vb), dim3(kBlock), 0, st, total / VecMap<float, S>::V, r, dinv, p, d,
-                       w.ctl, w.part);
+    cg_start<float, S>(n, r, dinv, p, d, w, st);
     ENS_LAUNCH_CHECK();
     rc = cg_loop<float, S>(g, vals32, d, r, p, q, dinv, w, o.inner_max_iter, o.check_every, st);
     if (rc != ENS_OK) return rc;
-    hipLaunchKernelGGL(k_ir_update<S>, dim3(stream_blocks(total)), dim3(kBlock), 0, st, total, x, d, w.ctl);
+    hipLaunchKernelGGL(k_ir_update<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, d, w.ctl);
     ENS_LAUNCH_CHECK();
   }
   return ENS_OK;
@@ -671,18 +761,18 @@ static ens_status cg_scalar_one(const ens_graph* g, const double* vals, const do
   double* q = (double*)w.vec[2];
   double* dinv = (double*)w.vec[3];
   const int64_t n = g->n;
-  const int rb = row_blocks(n, 256 / G);
+  const unsigned rb = grid_for(n, kBlock / G);
+  const unsigned vb = grid_for(n, (int64_t)kBlock * kU);
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, w.ctl, o.rtol, o.inner_rtol, o.max_iter,
                      o.inner_max_iter, o.max_outer, 0);
-  hipLaunchKernelGGL((k_diag_inv<double, 1>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g->n, g->row_ptr,
+  hipLaunchKernelGGL((k_diag_inv<double, 1>), dim3(grid_for(n, 256)), dim3(256), 0, st, g->n, g->row_ptr,
                      g->col_idx, vals, dinv);
   hipLaunchKernelGGL(k_residual_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
-                     r, w.ctl, w.part, (int)OP_START);
-  hipLaunchKernelGGL(k_zero_where<1>, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, x, w.ctl);
-  hipLaunchKernelGGL((k_cg_start<double, 1>), dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, r, dinv, p,
-                     (double*)nullptr, w.ctl, w.part);
+                     r, w.part);
+  reduce<1, 2>(w, rb, OP_START, 0, 0, st);
+  hipLaunchKernelGGL(k_zero_where<1>, dim3(grid_for(n, 256 * 8)), dim3(kBlock), 0, st, n, x, w.ctl);
+  cg_start<double, 1>(n, r, dinv, p, (double*)nullptr, w, st);
   ENS_LAUNCH_CHECK();
-  const int vb = stream_blocks(n);
   for (int k0 = 0; k0 < o.max_iter; k0 += o.check_every) {
     const int k1 = k0 + o.check_every < o.max_iter ? k0 + o.check_every : o.max_iter;
     for (int k = k0 + 1; k <= k1; ++k) {
@@ -690,8 +780,10 @@ static ens_status cg_scalar_one(const ens_graph* g, const double* vals, const do
       hipLaunchKernelGGL(k_cg_spmv_dot_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx,
                          vals, p, q, w.ctl, w.part);
       prof_end(ENS_K_SCALAR_SPMV, st, (double)g->nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n);
+      reduce<1, 1>(w, rb, OP_ALPHA, 0, 1, st);
       hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(vb), dim3(kBlock), 0, st, n, x, p, q, r, dinv, w.ctl,
-                         w.part, k);
+                         w.part);
+      reduce<1, 2>(w, vb, OP_UPDATE, k, 1, st);
       hipLaunchKernelGGL((k_cg_pupdate<double, 1>), dim3(vb), dim3(kBlock), 0, st, n, r, dinv, p, w.ctl);
     }
     ENS_LAUNCH_CHECK();
@@ -701,7 +793,8 @@ static ens_status cg_scalar_one(const ens_graph* g, const double* vals, const do
     if (act == 0) break;
   }
   hipLaunchKernelGGL(k_residual_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
-                     (double*)nullptr, w.ctl, w.part, (int)OP_TRUE);
+                     (double*)nullptr, w.part);
+  reduce<1, 2>(w, rb, OP_TRUE, 0, 0, st);
   ENS_LAUNCH_CHECK();
   return ENS_OK;
 }
@@ -764,7 +857,6 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
   Work w;
   ws_layout(graph->n, s, mixed, &w, (char*)workspace);
   ens_cg_opts o = normalized(opts);
-  static_assert(kStreamBlocks <= kMaxPartBlocks, "reduction partial buffer too small");
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, w.ctl, o.rtol, o.inner_rtol, o.max_iter,
                      o.inner_max_iter, o.max_outer, (int)mixed);
   ENS_LAUNCH_CHECK();

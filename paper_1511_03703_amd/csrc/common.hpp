@@ -76,14 +76,8 @@ __device__ inline double wave_sum_stride(double v) {
 // Ensemble sizes compiled into the library (explicit instantiation).
 inline bool supported_s(int s) { return s == 4 || s == 8 || s == 16 || s == 32; }
 
-// Number of workgroups for grid-stride streaming kernels: enough waves to
-// cover HBM latency on all 256 CUs without making the per-block partial
-// arrays of the reductions large.
-constexpr int kStreamBlocks = 2048;
+// Workgroup size of every kernel: 4 wavefronts.
 constexpr int kBlock = 256;
-
-// The reduction partial buffers hold up to this many blocks.
-constexpr int kMaxPartBlocks = 4096;
 
 // Per-device pinned scalars and events kept for the life of the process.
 struct DeviceCtx {

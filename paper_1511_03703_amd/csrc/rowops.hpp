@@ -44,30 +44,23 @@ __device__ inline typename EnsMap<T, S>::vt ens_row_product(const int32_t* __res
   const vt* xv = (const vt*)x + sub;
   vt acc = (vt)0;
   int64_t k = k0;
-  for (; k + 8 < k1; k += 9) {
-    int32_t c[9];
-    vt a[9], b[9];
+  for (; k + 2 < k1; k += 3) {
+    int32_t c[3];
+    vt a[3], b[3];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) c[j] = ci[k + j];
+    for (int j = 0; j < 3; ++j) c[j] = ci[k + j];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) a[j] = load_stream(vv + (k + j) * M::L);
+    for (int j = 0; j < 3; ++j) a[j] = load_stream(vv + (k + j) * M::L);
 #pragma unroll
-    for (int j = 0; j < 9; ++j) b[j] = xv[(int64_t)c[j] * M::L];
+    for (int j = 0; j < 3; ++j) b[j] = xv[(int64_t)c[j] * M::L];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) acc += a[j] * b[j];
+    for (int j = 0; j < 3; ++j) acc += a[j] * b[j];
   }
   for (; k < k1; ++k) {
     int32_t c = ci[k];
     acc += load_stream(vv + k * M::L) * xv[(int64_t)c * M::L];
   }
   return acc;
-}
-
-// Lanes that hold the same V samples (of different rows / entries) are L
-// apart; sum a double over them.
-template <int L>
-__device__ inline double sum_same_samples(double v) {
-  return wave_sum_stride<L>(v);
 }
 
 // Block-wide per-sample reduction of NQ quantities.  Each lane holds
@@ -96,39 +89,29 @@ __device__ inline void block_partials(double (&vals)[NQ][VS], double* __restrict
   }
 }
 
-// Deterministic grid-wide total of the per-block partials, finished inside
-// the kernel without a second launch.  Blocks form groups of kGroup
-// consecutive ids; the last block of a group to arrive (device-scope
-// counter) sums its group's partials in block order, and the last group to
-// finish sums the group totals in group order.  Release fences before each
-// arrival and acquire fences after it make the partials written on other
-// XCDs visible.  The summation order depends only on the grid size, so the
-// result is bit-reproducible.  Returns true in the one block that holds the
-// totals (tot[P], global) on exit; counters are left at zero.
-constexpr int kGroup = 32;
-constexpr int kMaxGroups = (kMaxPartBlocks + kGroup - 1) / kGroup;
-
-// dst[qe] = sum over r < rows of src[r*P + qe], rows split into G stripes
-// that are then added in order.
+// dst[qe] = sum over r < rows of src[r*P + qe] for the P columns of a
+// row-major partial array, with the rows split into G = 256/P interleaved
+// stripes that are added in stripe order afterwards.  The order depends only
+// on `rows`, so the result is bit-reproducible.
 template <int P>
-__device__ inline void sum_rows(const double* __restrict__ src, int rows, double* __restrict__ dst) {
+__device__ inline void sum_rows(const double* __restrict__ src, int64_t rows, double* __restrict__ dst) {
   constexpr int G = kBlock / P;
   __shared__ double stripe[G][P];
   const int t = threadIdx.x;
   const int g = t / P, qe = t % P;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int r = g;
+  int64_t r = g;
   for (; r + 3 * G < rows; r += 4 * G) {
-    const double v0 = src[(int64_t)r * P + qe];
-    const double v1 = src[(int64_t)(r + G) * P + qe];
-    const double v2 = src[(int64_t)(r + 2 * G) * P + qe];
-    const double v3 = src[(int64_t)(r + 3 * G) * P + qe];
+    const double v0 = src[r * P + qe];
+    const double v1 = src[(r + G) * P + qe];
+    const double v2 = src[(r + 2 * G) * P + qe];
+    const double v3 = src[(r + 3 * G) * P + qe];
     a0 += v0;
     a1 += v1;
     a2 += v2;
     a3 += v3;
   }
-  for (; r < rows; r += G) a0 += src[(int64_t)r * P + qe];
+  for (; r < rows; r += G) a0 += src[r * P + qe];
   stripe[g][qe] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   if (t < P) {
@@ -138,35 +121,6 @@ __device__ inline void sum_rows(const double* __restrict__ src, int rows, double
     dst[t] = acc;
   }
   __syncthreads();
-}
-
-template <int P>
-__device__ inline bool grid_total(const double* __restrict__ part, double* __restrict__ gpart,
-                                  uint32_t* __restrict__ gcount, uint32_t* __restrict__ topcount,
-                                  double* __restrict__ tot) {
-  __shared__ int s_last;
-  const int nb = gridDim.x;
-  const int ng = (nb + kGroup - 1) / kGroup;
-  const int grp = blockIdx.x / kGroup;
-  const int gsize = min(kGroup, nb - grp * kGroup);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(&gcount[grp], 1u) == (uint32_t)gsize - 1);
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  sum_rows<P>(part + (int64_t)grp * kGroup * P, gsize, gpart + (int64_t)grp * P);
-  if (threadIdx.x == 0) gcount[grp] = 0;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(topcount, 1u) == (uint32_t)ng - 1);
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  sum_rows<P>(gpart, ng, tot);
-  if (threadIdx.x == 0) *topcount = 0;
-  __syncthreads();
-  return true;
 }
 
 }  // namespace ens
