@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--cpu-cap-iters", type=int, default=25)
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--check-every", type=int, default=16)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (hardware-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -136,6 +138,14 @@ def main():
     opts = ens.cg_opts(rtol=w.rtol, mixed=w.mixed, inner_rtol=args.inner_rtol, check_every=args.check_every)
     ws = torch.empty(ens.cg_workspace_bytes(g, w.s, opts), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        ens.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {nb} bytes done")
+        del src, dst
 
     def step():
         ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, values32=v32, rhs=rhs)

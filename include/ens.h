@@ -243,8 +243,11 @@ enum {
 };
 ens_status ens_prof_enable(int32_t on);
 ens_status ens_prof_reset(void);
-/* Totals since the last reset: summed event durations (ms), launches, and
- * algorithmic bytes (the byte model of the kernel, summed per launch). */
+/* Totals since the last reset over the working launches of a kernel:
+ * summed event durations (ms), launch count, and algorithmic bytes (the
+ * kernel's byte model, summed per launch).  Launches shorter than a quarter
+ * of the median duration -- solver kernels that found no active sample and
+ * returned at once -- are left out. */
 ens_status ens_prof_query(int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
 
 #ifdef __cplusplus

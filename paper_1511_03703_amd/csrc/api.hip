@@ -3,6 +3,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -55,9 +56,8 @@ static std::vector<hipEvent_t> g_free_events;
 static std::vector<PendingPair> g_pending;
 static hipEvent_t g_open[ENS_K_COUNT];
 static bool g_open_valid[ENS_K_COUNT];
-static double g_total_ms[ENS_K_COUNT];
-static int64_t g_launches[ENS_K_COUNT];
-static double g_bytes[ENS_K_COUNT];
+static std::vector<float> g_ms[ENS_K_COUNT];    // one duration per launch
+static std::vector<double> g_by[ENS_K_COUNT];   // algorithmic bytes per launch
 
 static hipEvent_t take_event() {
   if (!g_free_events.empty()) {
@@ -101,9 +101,8 @@ void prof_collect() {
     }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      g_total_ms[p.kernel] += ms;
-      g_launches[p.kernel] += 1;
-      g_bytes[p.kernel] += p.bytes;
+      g_ms[p.kernel].push_back(ms);
+      g_by[p.kernel].push_back(p.bytes);
     }
     g_free_events.push_back(p.a);
     g_free_events.push_back(p.b);
@@ -189,9 +188,8 @@ ens_status ens_prof_reset(void) {
   prof_collect();
   std::lock_guard<std::mutex> lk(g_prof_mu);
   for (int k = 0; k < ENS_K_COUNT; ++k) {
-    g_total_ms[k] = 0.0;
-    g_launches[k] = 0;
-    g_bytes[k] = 0.0;
+    g_ms[k].clear();
+    g_by[k].clear();
   }
   return ENS_OK;
 }
@@ -200,9 +198,23 @@ ens_status ens_prof_query(int32_t kernel_id, double* total_ms, int64_t* launches
   ENS_ARG_CHECK(kernel_id >= 0 && kernel_id < ENS_K_COUNT, "kernel id");
   prof_collect();
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  if (total_ms) *total_ms = g_total_ms[kernel_id];
-  if (launches) *launches = g_launches[kernel_id];
-  if (bytes) *bytes = g_bytes[kernel_id];
+  const std::vector<float>& d = g_ms[kernel_id];
+  double tot = 0.0, by = 0.0;
+  int64_t cnt = 0;
+  if (!d.empty()) {
+    std::vector<float> sorted(d);
+    std::nth_element(sorted.begin(), sorted.begin() + sorted.size() / 2, sorted.end());
+    const float med = sorted[sorted.size() / 2];
+    for (size_t i = 0; i < d.size(); ++i)
+      if (d[i] >= 0.25f * med) {  // launches that found no work return at once
+        tot += d[i];
+        by += g_by[kernel_id][i];
+        ++cnt;
+      }
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  if (bytes) *bytes = by;
   return ENS_OK;
 }
 
