@@ -1,0 +1,100 @@
+"""Full-size GPU parity at the mid and headline workloads, in the launch
+configuration bench.py times, on samples the oracle can afford one by one.
+
+  64^3, s = 16, FP64 Jacobi-CG to 1e-10: samples 0-3 compared at the GPU's
+      iteration counts (relative 1e-9), iteration counts within +-1, values
+      of those samples against the oracle's scalar assembly (1e-13).
+  128^3, s = 32, FP32 CG in FP64 refinement to 1e-8: samples 0 and 31 --
+      the oracle assembles each sample from scratch and checks the true FP64
+      residual of the GPU solution (<= 1e-8) and the assembled values (1e-13).
+"""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import HEADLINE, MID
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1511_03703_amd import ens
+    ens.lib()
+    return ens
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _oracle_sample(orc, rp, ci, w, xi_e):
+    ac = orc.kl_coef_qp(w.N, w.M, w.L, w.kappa0, w.sigma, xi_e)
+    return orc.assemble_scalar(w.N, rp, ci, ac, fconst=w.f)
+
+
+def test_mid_workload_fp64(E, orc):
+    w = MID
+    xi = w.xi()
+    g = E.graph_build(w.N)
+    kl = E.kl_build(w.N, w.M, w.L)
+    vals, _, rhs = E.assemble(g, kl, torch.as_tensor(xi, device="cuda"), w.M, w.sigma)
+    x, stats, st = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=w.rtol))
+    assert st == E.ENS_OK
+    check = [0, 1, 2, 3]
+    gv = {e: vals[:, e].cpu().numpy() for e in check}
+    xg = x.cpu().numpy()
+    print(f"GPU done: iterations {[s['iters'] for s in stats]}", flush=True)
+    rp, ci = orc.graph(w.N)
+
+    def one(e):
+        v, b = _oracle_sample(orc, rp, ci, w, xi[e])
+        xo = orc.pcg(rp, ci, v, b, fixed_iters=stats[e]["iters"])[0]
+        _, it_tol, _, _ = orc.pcg(rp, ci, v, b, rtol=w.rtol)
+        res = np.linalg.norm(b - orc.spmv(rp, ci, v, xg[:, e])) / np.linalg.norm(b)
+        return e, _rel(gv[e], v), _rel(xg[:, e], xo), it_tol, res
+
+    with cf.ThreadPoolExecutor(4) as ex:
+        for e, dv, dx, it_tol, res in ex.map(one, check):
+            print(f"sample {e}: values {dv:.2e} x {dx:.2e} iters gpu {stats[e]['iters']} oracle {it_tol} "
+                  f"true residual {res:.2e}", flush=True)
+            assert dv <= 1e-13
+            assert dx <= 1e-9
+            assert abs(it_tol - stats[e]["iters"]) <= 1
+            assert res <= w.rtol * (1 + 1e-6)
+
+
+def test_headline_workload_refinement(E, orc):
+    w = HEADLINE
+    xi = w.xi()
+    g = E.graph_build(w.N)
+    kl = E.kl_build(w.N, w.M, w.L)
+    vals, v32, rhs = E.assemble(g, kl, torch.as_tensor(xi, device="cuda"), w.M, w.sigma, want32=True)
+    opts = E.cg_opts(rtol=w.rtol, mixed=True, inner_rtol=1e-4, check_every=16)
+    x, stats, st = E.cg(g, vals, rhs, values32=v32, opts=opts)
+    assert st == E.ENS_OK
+    assert all(s["status"] == 0 and s["rel_res"] <= w.rtol * (1 + 1e-6) for s in stats)
+    check = [0, w.s - 1]
+    gv = {e: vals[:, e].cpu().numpy() for e in check}
+    xg = {e: x[:, e].cpu().numpy() for e in check}
+    g32 = v32[:, check[0]].cpu().numpy()
+    assert np.array_equal(g32, gv[check[0]].astype(np.float32))
+    del vals, v32
+    torch.cuda.empty_cache()
+    print(f"GPU done: inner iterations {[s['iters'] for s in stats]}", flush=True)
+    rp, ci = orc.graph(w.N)
+
+    def one(e):
+        v, b = _oracle_sample(orc, rp, ci, w, xi[e])
+        res = np.linalg.norm(b - orc.spmv(rp, ci, v, xg[e])) / np.linalg.norm(b)
+        return e, _rel(gv[e], v), res
+
+    with cf.ThreadPoolExecutor(2) as ex:
+        for e, dv, res in ex.map(one, check):
+            print(f"sample {e}: values {dv:.2e} true residual {res:.3e} (GPU reported {stats[e]['rel_res']:.3e})",
+                  flush=True)
+            assert dv <= 1e-13
+            assert res <= w.rtol * (1 + 1e-6)
+            assert abs(res - stats[e]["rel_res"]) <= 1e-3 * res
