@@ -222,6 +222,79 @@ ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values
 ens_status ens_relayout(const double* src, double* dst, int64_t rows, int32_t s, int32_t to_sample_major,
                         hipStream_t stream);
 
+/* ------------------------------------------------- learned initial guess */
+
+/* A reduced basis and a small network predict an initial guess for CG from
+ * the KL inputs y of a sample; CG remains the solver and the judge of the
+ * error (an extension of the method; the paper solves from zero).
+ *
+ * Network: 10 -> 256 -> 256 -> 32, GELU (exact erf form) after the two
+ * hidden layers, linear output.  Parameters are one FP32 array of
+ * ens_mlp_param_count() = 76,832 floats:
+ *   W1 [256][10] | b1 [256] | W2 [256][256] | b2 [256] | W3 [32][256] | b3 [32]
+ * Products run on the matrix cores with BF16 operands (inputs, weights and
+ * activations rounded to nearest even) and FP32 accumulation; bias, GELU,
+ * loss and Adam are FP32.  `batch` must be a multiple of 32 in [32, 65536].
+ * Workspace (device, 256-byte aligned) from ens_mlp_workspace_bytes. */
+int64_t ens_mlp_param_count(void);
+ens_status ens_mlp_workspace_bytes(int32_t batch, size_t* bytes);
+
+/* out [batch][32] (device) = network(xi [batch][10] (device)). */
+ens_status ens_mlp_forward(const float* params, int32_t batch, const float* xi, float* out, void* workspace,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* One forward and backward pass of the mean squared error
+ * L = mean over batch and outputs of (out - target)^2: grad [76832] and
+ * loss [1] (device) out; out [batch][32] optional. */
+ens_status ens_mlp_grad(const float* params, int32_t batch, const float* xi, const float* target, float* out,
+                        float* grad, float* loss, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* `steps` Adam steps (lr, beta = (0.9, 0.999), eps = 1e-8) on mini-batches
+ * of the training set xi [count][10], target [count][32] (device): step s
+ * uses the rows batch_idx[s*batch .. s*batch+batch-1] (device int32, the
+ * caller's shuffle).  params, adam_m, adam_v [76832] are updated in place;
+ * step0 = number of Adam steps already taken (bias correction); loss
+ * [steps] (device, nullable) receives each step's batch loss. */
+ens_status ens_mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const float* xi,
+                         const float* target, int32_t count, int32_t batch, int32_t steps, const int32_t* batch_idx,
+                         float lr, float* loss, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* POD by the method of snapshots, FP64.  S [n][m] (device) holds one
+ * solution per column.
+ * ens_pod_collect: S[i][col0 + e] = x[i][e] for an ensemble x [n][s].
+ * ens_pod_gram:    G [m][m] = S^T S (split-K workspace of
+ *                  ens_pod_gram_workspace_bytes).
+ * ens_pod_eig:     top-r eigenpairs of G by `iters` steps of block subspace
+ *                  iteration on k >= r columns from the seeded start block
+ *                  start [m][k], then Rayleigh-Ritz (Jacobi on k x k);
+ *                  V [m][r] orthonormal, lambda [r] descending (device).
+ * ens_pod_basis:   Phi [n][r] = S V diag(lambda)^(-1/2), each column's
+ *                  largest-magnitude entry made positive.
+ * ens_pod_project: C [s][r] = X^T Phi for an ensemble X [n][s].
+ * ens_pod_standardize: per-coefficient mean mu [r] and standard deviation
+ *                  sd [r] of C [m][r], and the network targets
+ *                  T [m][r] = (C - mu) / sd in FP32.
+ * ens_pod_reconstruct: x0 [n][s] = Phi (mu + sd c)^T for network outputs
+ *                  c [s][r] (FP32; mu, sd nullable for raw coefficients),
+ *                  written in the ensemble layout ready for ens_cg. */
+ens_status ens_pod_collect(const double* x, int64_t n, int32_t s, double* S, int32_t m, int32_t col0,
+                           hipStream_t stream);
+ens_status ens_pod_gram_workspace_bytes(int64_t n, int32_t m, size_t* bytes);
+ens_status ens_pod_gram(const double* S, int64_t n, int32_t m, double* G, void* workspace, size_t ws_bytes,
+                        hipStream_t stream);
+ens_status ens_pod_eig_workspace_bytes(int32_t m, int32_t k, size_t* bytes);
+ens_status ens_pod_eig(const double* G, int32_t m, int32_t k, int32_t r, const double* start, int32_t iters,
+                       double* V, double* lambda, void* workspace, size_t ws_bytes, hipStream_t stream);
+ens_status ens_pod_basis(const double* S, int64_t n, int32_t m, const double* V, const double* lambda, int32_t r,
+                         double* Phi, hipStream_t stream);
+ens_status ens_pod_project_workspace_bytes(int64_t n, int32_t r, int32_t s, size_t* bytes);
+ens_status ens_pod_project(const double* Phi, const double* X, int64_t n, int32_t r, int32_t s, double* C,
+                           void* workspace, size_t ws_bytes, hipStream_t stream);
+ens_status ens_pod_standardize(const double* C, int32_t m, int32_t r, double* mu, double* sd, float* T,
+                               hipStream_t stream);
+ens_status ens_pod_reconstruct(const double* Phi, int64_t n, int32_t r, const float* c, const double* mu,
+                               const double* sd, int32_t s, double* x0, hipStream_t stream);
+
 /* ----------------------------------------------------------- measurement */
 
 /* Plain device copy of `bytes` bytes (multiple of 16), used to calibrate

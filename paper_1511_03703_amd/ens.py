@@ -78,6 +78,21 @@ _SIGS = [
     ("ens_relayout", _I32, [_P, _P, _I64, _I32, _I32, _P]),
     ("ens_stream_copy", _I32, [_P, _P, _SZ, _P]),
     ("ens_stream_triad", _I32, [_P, _P, _P, _D, _I64, _P]),
+    ("ens_mlp_param_count", _I64, []),
+    ("ens_mlp_workspace_bytes", _I32, [_I32, ctypes.POINTER(_SZ)]),
+    ("ens_mlp_forward", _I32, [_P, _I32, _P, _P, _P, _SZ, _P]),
+    ("ens_mlp_grad", _I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    ("ens_mlp_train", _I32, [_P, _P, _P, _I32, _P, _P, _I32, _I32, _I32, _P, ctypes.c_float, _P, _P, _SZ, _P]),
+    ("ens_pod_collect", _I32, [_P, _I64, _I32, _P, _I32, _I32, _P]),
+    ("ens_pod_gram_workspace_bytes", _I32, [_I64, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_pod_gram", _I32, [_P, _I64, _I32, _P, _P, _SZ, _P]),
+    ("ens_pod_eig_workspace_bytes", _I32, [_I32, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_pod_eig", _I32, [_P, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _SZ, _P]),
+    ("ens_pod_basis", _I32, [_P, _I64, _I32, _P, _P, _I32, _P, _P]),
+    ("ens_pod_project_workspace_bytes", _I32, [_I64, _I32, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_pod_project", _I32, [_P, _P, _I64, _I32, _I32, _P, _P, _SZ, _P]),
+    ("ens_pod_standardize", _I32, [_P, _I32, _I32, _P, _P, _P, _P]),
+    ("ens_pod_reconstruct", _I32, [_P, _I64, _I32, _P, _P, _P, _I32, _P, _P]),
     ("ens_prof_enable", _I32, [_I32]),
     ("ens_prof_reset", _I32, []),
     ("ens_prof_query", _I32, [_I32, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
@@ -319,3 +334,115 @@ def prof_query(kernel_id: int):
     ms, n, by = _D(), _I64(), _D()
     _check(lib().ens_prof_query(kernel_id, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)), "ens_prof_query")
     return {"total_ms": ms.value, "launches": n.value, "bytes": by.value}
+
+
+# ------------------------------------------------- learned initial guess
+
+MLP_IN, MLP_HID, MLP_OUT = 10, 256, 32
+
+
+def mlp_param_count() -> int:
+    return int(lib().ens_mlp_param_count())
+
+
+def _mlp_ws(batch, device):
+    b = _SZ()
+    _check(lib().ens_mlp_workspace_bytes(batch, ctypes.byref(b)), "ens_mlp_workspace_bytes")
+    return torch.empty(b.value, dtype=torch.uint8, device=device)
+
+
+def mlp_forward(params: torch.Tensor, xi: torch.Tensor, workspace=None, stream=None):
+    batch = xi.shape[0]
+    out = torch.empty((batch, MLP_OUT), dtype=torch.float32, device=xi.device)
+    ws = workspace if workspace is not None else _mlp_ws(batch, xi.device)
+    _check(lib().ens_mlp_forward(_ptr(params), batch, _ptr(xi), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "ens_mlp_forward")
+    return out
+
+
+def mlp_grad(params, xi, target, workspace=None, stream=None):
+    batch = xi.shape[0]
+    out = torch.empty((batch, MLP_OUT), dtype=torch.float32, device=xi.device)
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=xi.device)
+    ws = workspace if workspace is not None else _mlp_ws(batch, xi.device)
+    _check(lib().ens_mlp_grad(_ptr(params), batch, _ptr(xi), _ptr(target), _ptr(out), _ptr(grad), _ptr(loss),
+                              _ptr(ws), ws.numel(), _stream(stream)), "ens_mlp_grad")
+    return out, grad, loss
+
+
+def mlp_train(params, adam_m, adam_v, step0, xi, target, batch, batch_idx, lr, loss=None, workspace=None,
+              stream=None):
+    steps = batch_idx.numel() // batch
+    ws = workspace if workspace is not None else _mlp_ws(batch, xi.device)
+    _check(lib().ens_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), step0, _ptr(xi), _ptr(target),
+                               xi.shape[0], batch, steps, _ptr(batch_idx), lr, _ptr(loss), _ptr(ws), ws.numel(),
+                               _stream(stream)), "ens_mlp_train")
+    return steps
+
+
+def pod_collect(x, S, col0, stream=None):
+    n, s = x.shape
+    _check(lib().ens_pod_collect(_ptr(x), n, s, _ptr(S), S.shape[1], col0, _stream(stream)), "ens_pod_collect")
+
+
+def pod_gram(S, stream=None):
+    n, m = S.shape
+    b = _SZ()
+    _check(lib().ens_pod_gram_workspace_bytes(n, m, ctypes.byref(b)), "ens_pod_gram_workspace_bytes")
+    ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=S.device)
+    G = torch.empty((m, m), dtype=torch.float64, device=S.device)
+    _check(lib().ens_pod_gram(_ptr(S), n, m, _ptr(G), _ptr(ws), ws.numel(), _stream(stream)), "ens_pod_gram")
+    return G
+
+
+def pod_eig(G, r, start, iters, stream=None):
+    m, k = start.shape
+    b = _SZ()
+    _check(lib().ens_pod_eig_workspace_bytes(m, k, ctypes.byref(b)), "ens_pod_eig_workspace_bytes")
+    ws = torch.empty(b.value, dtype=torch.uint8, device=G.device)
+    V = torch.empty((m, r), dtype=torch.float64, device=G.device)
+    lam = torch.empty(r, dtype=torch.float64, device=G.device)
+    _check(lib().ens_pod_eig(_ptr(G), m, k, r, _ptr(start), iters, _ptr(V), _ptr(lam), _ptr(ws), ws.numel(),
+                             _stream(stream)), "ens_pod_eig")
+    return V, lam
+
+
+def pod_basis(S, V, lam, stream=None):
+    n, m = S.shape
+    r = V.shape[1]
+    Phi = torch.empty((n, r), dtype=torch.float64, device=S.device)
+    _check(lib().ens_pod_basis(_ptr(S), n, m, _ptr(V), _ptr(lam), r, _ptr(Phi), _stream(stream)), "ens_pod_basis")
+    return Phi
+
+
+def pod_project(Phi, X, stream=None):
+    n, r = Phi.shape
+    s = X.shape[1]
+    b = _SZ()
+    _check(lib().ens_pod_project_workspace_bytes(n, r, s, ctypes.byref(b)), "ens_pod_project_workspace_bytes")
+    ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=X.device)
+    C = torch.empty((s, r), dtype=torch.float64, device=X.device)
+    _check(lib().ens_pod_project(_ptr(Phi), _ptr(X), n, r, s, _ptr(C), _ptr(ws), ws.numel(), _stream(stream)),
+           "ens_pod_project")
+    return C
+
+
+def pod_standardize(C, stream=None):
+    m, r = C.shape
+    mu = torch.empty(r, dtype=torch.float64, device=C.device)
+    sd = torch.empty(r, dtype=torch.float64, device=C.device)
+    T = torch.empty((m, r), dtype=torch.float32, device=C.device)
+    _check(lib().ens_pod_standardize(_ptr(C), m, r, _ptr(mu), _ptr(sd), _ptr(T), _stream(stream)),
+           "ens_pod_standardize")
+    return mu, sd, T
+
+
+def pod_reconstruct(Phi, c, mu=None, sd=None, x0=None, stream=None):
+    n, r = Phi.shape
+    s = c.shape[0]
+    if x0 is None:
+        x0 = torch.empty((n, s), dtype=torch.float64, device=Phi.device)
+    _check(lib().ens_pod_reconstruct(_ptr(Phi), n, r, _ptr(c), _ptr(mu), _ptr(sd), s, _ptr(x0), _stream(stream)),
+           "ens_pod_reconstruct")
+    return x0
