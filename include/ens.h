@@ -216,6 +216,62 @@ ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values
                          double* x, const ens_cg_opts* opts, int32_t lanes_per_row, void* workspace,
                          size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream);
 
+/* ---------------------------------------------------------------- batch */
+
+/* One sample group of a batch: an ensemble of s samples on its own mesh. */
+typedef struct {
+  const ens_graph* graph; /* (host struct) device graph of the group's mesh      */
+  const double* values;   /* (device) [nnz][s] FP64                              */
+  const double* b;        /* (device) [n][s]                                     */
+  double* x;              /* (device) [n][s]: in initial guess, out solution     */
+  ens_cg_stat* stats;     /* (host) [s] out                                      */
+} ens_group;
+
+typedef struct {
+  double rtol;          /* per sample: |r| <= rtol |b|                          */
+  int32_t max_iter;     /* per sample (<= 0: 10000)                             */
+  int32_t check_every;  /* iterations per graph replay / host poll (<= 0: 16)   */
+  int32_t tile;         /* wavefronts per row-tile workgroup: 2, 4 or 8          */
+  int32_t use_graph;    /* 1: capture one chunk of iterations in a HIP graph and
+                           replay it; 0: launch the same kernels directly      */
+} ens_batch_opts;
+
+/* Bytes of workspace ens_solve_batch needs for these groups. */
+ens_status ens_batch_workspace_bytes(const ens_group* groups, int32_t n_groups, int32_t s,
+                                     const ens_batch_opts* opts, size_t* bytes);
+
+/* FP64 Jacobi-CG (the iteration of ens_cg, per-sample scalars and masks) of
+ * all groups at once: every CG phase is one launch over the row tiles or
+ * vector blocks of all groups, groups of different mesh sizes included, and
+ * each group's reductions and stopping decisions are its own.  Groups are
+ * independent systems (the block structure of Eq. kron_sys; Sec. 5 notes
+ * that grouped ensembles propagate independently).  s in {8, 16, 32}, the
+ * same for all groups.  Work runs on a library stream ordered after
+ * `stream` and joined back to it; synchronises; per-sample stats written to
+ * each group's host array; ENS_W_NOT_CONVERGED if any sample did not
+ * converge. */
+ens_status ens_solve_batch(const ens_group* groups, int32_t n_groups, int32_t s, const ens_batch_opts* opts,
+                           void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Autotuner for ens_solve_batch (the ensemble size must suit the
+ * architecture, Sec. 3 and Sec. 5): for every candidate ensemble size
+ * s_cand[ns] (8, 16, 32) and row-tile shape tile_cand[nt] (2, 4, 8
+ * wavefronts per workgroup), solves the same 32 samples of each mesh in
+ * meshes[nm] (N per axis), split into 32/s groups, with ens_solve_batch
+ * under the options *base (its tile ignored), and returns the pair with the
+ * most solved samples per second.  xi_host (host) [nm][32][problem->M] holds
+ * the KL inputs.  scores (host, nullable) [ns*nt] receives every score
+ * (samples/s, index a*nt + c).  With scores NULL and an entry for the same
+ * meshes, problem and options in cache_path (nullable; a text file of lines
+ * "key s tile", the last one wins), the cached pair is returned without
+ * trials; every completed search appends its result.  Allocates the trial
+ * buffers with hipMalloc (about 32 * 8 * (nnz + 3 n) bytes per mesh) and
+ * frees them before returning; synchronises. */
+ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, const ens_problem* problem, const double* xi_host,
+                              const int32_t* s_cand, int32_t ns, const int32_t* tile_cand, int32_t nt,
+                              const ens_batch_opts* base, const char* cache_path, int32_t* best_s,
+                              int32_t* best_tile, double* scores, hipStream_t stream);
+
 /* Layout change between the commuted [rows][s] and the sample-major
  * [s][rows] arrangement (Eqs. kron_sys_commuted and kron_sys), FP64,
  * out-of-place.  to_sample_major = 1: src [rows][s] -> dst [s][rows]. */

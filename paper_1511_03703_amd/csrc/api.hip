@@ -33,7 +33,10 @@ DeviceCtx* device_ctx() {
   if (!g_ctx[dev]) {
     DeviceCtx* c = new DeviceCtx();
     c->device = dev;
-    if (hipHostMalloc((void**)&c->host_flag, 64, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->host_flag, 64, hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->work_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
       delete c;
       return nullptr;
     }

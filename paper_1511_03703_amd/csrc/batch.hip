@@ -1,0 +1,661 @@
+// Batched solve of many sample groups: every group is an ensemble of S
+// samples on its own Q1 mesh (meshes of different sizes in one batch), and
+// every CG phase runs for all groups in one launch.
+//
+// The work of a phase is a flat list of blocks: group g owns a contiguous
+// range of row tiles (products) or of chunk blocks (vector updates), and a
+// table maps each block to its group.  Block partials of the reductions are
+// summed per group in two fixed-order stages (the first over chunks of at
+// most kSegRows partial rows, the second one workgroup per group), and the
+// second stage updates that group's per-sample state, so groups converge and
+// stop independently: a finished group's blocks return at once.  A chunk of
+// iterations is captured once into a HIP graph and replayed until every
+// group has finished; the host reads one active count per replay.
+//
+// Why not one persistent kernel with in-kernel barriers between the phases:
+// on this part a device-scope release/acquire fence writes back and
+// invalidates the XCD's L2, and with one fence per block per phase the
+// measured cost exceeds the launches a graph replays.
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "cgcore.hpp"
+
+namespace ens {
+
+constexpr int kSegRows = 256;
+
+struct GroupDev {
+  int32_t n;
+  int32_t nred, nredv;  // stage-1 rows of the row / vector reductions
+  int64_t nnz;
+  const int32_t* rp;
+  const int32_t* ci;
+  const double* vals;
+  const double* b;
+  double* x;
+  double *r, *p, *q, *dinv;
+  Ctl* ctl;
+  int64_t row0, nrowb;  // flat row-tile blocks
+  int64_t vec0, nvecb;  // flat chunk blocks
+  int64_t red0, redv0;  // first stage-1 row
+};
+
+struct BatchDev {
+  const GroupDev* groups;
+  const int32_t* row_grp;   // [row blocks]
+  const int32_t* vec_grp;   // [vector blocks]
+  const int32_t* red_grp;   // [stage-1 rows of row reductions]
+  const int32_t* redv_grp;  // [stage-1 rows of vector reductions]
+  double* part;             // [max(row, vector blocks)][2S]
+  double* out1;             // [max(stage-1 rows)][2S]
+};
+
+template <int S, int NW>
+__global__ __launch_bounds__(NW * 64) void kb_spmv_dot(BatchDev bd) {
+  const int64_t blk = blockIdx.x;
+  const GroupDev& g = bd.groups[bd.row_grp[blk]];
+  if (g.ctl->n_active == 0) return;
+  spmv_dot_body<double, S, NW>(g.n, g.rp, g.ci, g.vals, g.p, g.q, blk - g.row0, bd.part + blk * S);
+}
+
+template <int S, int NW>
+__global__ __launch_bounds__(NW * 64) void kb_residual(BatchDev bd, int store_r) {
+  const int64_t blk = blockIdx.x;
+  const GroupDev& g = bd.groups[bd.row_grp[blk]];
+  residual_body<S, double, NW>(g.n, g.rp, g.ci, g.vals, g.x, g.b, store_r ? g.r : (double*)nullptr, blk - g.row0,
+                               bd.part + blk * 2 * S);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void kb_update(BatchDev bd) {
+  const int64_t blk = blockIdx.x;
+  const GroupDev& g = bd.groups[bd.vec_grp[blk]];
+  if (g.ctl->n_active == 0) return;
+  const int64_t nchunks = (int64_t)g.n * S / VecMap<double, S>::V;
+  update_body<double, S>(nchunks, g.x, g.p, g.q, g.r, g.dinv, g.ctl, blk - g.vec0, bd.part + blk * 2 * S);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void kb_pupdate(BatchDev bd) {
+  const int64_t blk = blockIdx.x;
+  const GroupDev& g = bd.groups[bd.vec_grp[blk]];
+  if (g.ctl->n_active == 0) return;
+  const int64_t nchunks = (int64_t)g.n * S / VecMap<double, S>::V;
+  pupdate_body<double, S>(nchunks, g.r, g.dinv, g.p, g.ctl, blk - g.vec0);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void kb_cg_start(BatchDev bd) {
+  const int64_t blk = blockIdx.x;
+  const GroupDev& g = bd.groups[bd.vec_grp[blk]];
+  const int64_t nchunks = (int64_t)g.n * S / VecMap<double, S>::V;
+  cg_start_body<double, S>(nchunks, g.r, g.dinv, g.p, (double*)nullptr, blk - g.vec0, bd.part + blk * 2 * S);
+}
+
+// Stage 1: stage-1 row c of group g sums partial rows
+// [first + j kSegRows, first + (j+1) kSegRows) of that group, j = c - red0.
+template <int P, int VEC>
+__global__ __launch_bounds__(256) void kb_stage1(BatchDev bd, int gate) {
+  const int64_t c = blockIdx.x;
+  const GroupDev& g = bd.groups[(VEC ? bd.redv_grp : bd.red_grp)[c]];
+  if (gate && g.ctl->n_active == 0) return;
+  const int64_t first = VEC ? g.vec0 : g.row0;
+  const int64_t count = VEC ? g.nvecb : g.nrowb;
+  const int64_t j = c - (VEC ? g.redv0 : g.red0);
+  const int64_t r0 = j * kSegRows;
+  const int64_t r1 = r0 + kSegRows < count ? r0 + kSegRows : count;
+  sum_rows<P>(bd.part + (first + r0) * P, r1 - r0, bd.out1 + c * P);
+}
+
+// Stage 2: workgroup g sums its stage-1 rows and updates its state.
+template <int S, int NQ, int VEC>
+__global__ __launch_bounds__(256) void kb_final(BatchDev bd, int op, int arg, int gate) {
+  const GroupDev& g = bd.groups[blockIdx.x];
+  Ctl* c = g.ctl;
+  if (gate && c->n_active == 0) return;
+  sum_rows<NQ * S>(bd.out1 + (VEC ? g.redv0 : g.red0) * NQ * S, VEC ? g.nredv : g.nred, c->tot);
+  if (NQ == 1 && threadIdx.x < S) c->tot[S + threadIdx.x] = 0.0;
+  __syncthreads();
+  finalize<S>(c, op, arg);
+}
+
+// Per-group active counts summed into one word the host polls.
+__global__ void kb_count(BatchDev bd, int ngroups, int32_t* out) {
+  __shared__ int32_t red[256];
+  int32_t a = 0;
+  for (int g = threadIdx.x; g < ngroups; g += blockDim.x) a += bd.groups[g].ctl->n_active;
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void kb_diag_inv(BatchDev bd, int ngroups) {
+  // grid-stride over all groups' (row, sample) pairs, one group at a time
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const GroupDev& g = bd.groups[gi];
+    const int64_t total = (int64_t)g.n * S;
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < total; t0 += (int64_t)gridDim.x * blockDim.x)
+      diag_inv_body<double, S>(g.n, g.rp, g.ci, g.vals, g.dinv, t0 / blockDim.x);
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void kb_zero_where(BatchDev bd, int ngroups) {
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const GroupDev& g = bd.groups[gi];
+    zero_where_body<S>((int64_t)g.n * S, g.x, g.ctl, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                       (int64_t)gridDim.x * blockDim.x);
+  }
+}
+
+static __global__ void kb_ctl_init(BatchDev bd, int ngroups, double rtol, int max_iter) {
+  for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+    Ctl* c = bd.groups[gi].ctl;
+    if (threadIdx.x == 0) {
+      c->rtol = rtol;
+      c->inner_rtol = 0.0;
+      c->max_iter = max_iter;
+      c->inner_max_iter = max_iter;
+      c->max_outer = 0;
+      c->mixed = 0;
+      c->n_active = 0;
+      c->n_oactive = 0;
+    }
+    if (threadIdx.x < kMaxS) {
+      const int e = threadIdx.x;
+      c->active[e] = 0;
+      c->oactive[e] = 0;
+      c->iters[e] = 0;
+      c->oiters[e] = 0;
+      c->kiter[e] = 0;
+      c->status[e] = ENS_SAMPLE_MAXITER;
+      c->zero_b[e] = 0;
+      c->rel_res[e] = 0.0;
+    }
+  }
+}
+
+// ------------------------------------------------------------ host side ---
+
+static size_t r256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+template <int S, int NW>
+struct Plan {
+  static constexpr int RB = NW * EnsMap<double, S>::RPW;  // rows per row tile
+  static constexpr int VB = kBlock * kU;                  // chunks per vector block
+};
+
+struct Layout {
+  std::vector<GroupDev> g;
+  std::vector<int32_t> row_grp, vec_grp, red_grp, redv_grp;
+  int64_t row_blocks = 0, vec_blocks = 0, red_rows = 0, redv_rows = 0;
+  size_t bytes = 0;
+  size_t off_groups, off_tables, off_part, off_out1, off_ctl, off_vec, off_count;
+};
+
+template <int S, int NW>
+static ens_status plan(const ens_group* groups, int ng, Layout& L) {
+  using PL = Plan<S, NW>;
+  L.g.resize(ng);
+  L.row_blocks = L.vec_blocks = L.red_rows = L.redv_rows = 0;
+  size_t vec_bytes = 0;
+  for (int i = 0; i < ng; ++i) {
+    const ens_group& gr = groups[i];
+    ENS_ARG_CHECK(gr.graph && gr.values && gr.b && gr.x && gr.stats, "null group pointer");
+    ENS_ARG_CHECK(gr.graph->n > 0 && gr.graph->row_ptr && gr.graph->col_idx, "empty group graph");
+    ENS_ARG_CHECK(aligned16(gr.values) && aligned16(gr.b) && aligned16(gr.x), "group buffers must be 16-byte aligned");
+    GroupDev& d = L.g[i];
+    memset(&d, 0, sizeof(d));
+    d.n = gr.graph->n;
+    d.nnz = gr.graph->nnz;
+    d.rp = gr.graph->row_ptr;
+    d.ci = gr.graph->col_idx;
+    d.vals = gr.values;
+    d.b = gr.b;
+    d.x = gr.x;
+    d.nrowb = (d.n + PL::RB - 1) / PL::RB;
+    const int64_t nchunks = (int64_t)d.n * S / VecMap<double, S>::V;
+    d.nvecb = (nchunks + PL::VB - 1) / PL::VB;
+    d.row0 = L.row_blocks;
+    d.vec0 = L.vec_blocks;
+    L.row_blocks += d.nrowb;
+    L.vec_blocks += d.nvecb;
+    d.nred = (int32_t)((d.nrowb + kSegRows - 1) / kSegRows);
+    d.nredv = (int32_t)((d.nvecb + kSegRows - 1) / kSegRows);
+    d.red0 = L.red_rows;
+    d.redv0 = L.redv_rows;
+    L.red_rows += d.nred;
+    L.redv_rows += d.nredv;
+    vec_bytes += 4 * r256((size_t)d.n * S * sizeof(double));
+  }
+  L.row_grp.resize(L.row_blocks);
+  L.vec_grp.resize(L.vec_blocks);
+  L.red_grp.resize(L.red_rows);
+  L.redv_grp.resize(L.redv_rows);
+  for (int i = 0; i < ng; ++i) {
+    const GroupDev& d = L.g[i];
+    for (int64_t b = 0; b < d.nrowb; ++b) L.row_grp[d.row0 + b] = i;
+    for (int64_t b = 0; b < d.nvecb; ++b) L.vec_grp[d.vec0 + b] = i;
+    for (int64_t b = 0; b < d.nred; ++b) L.red_grp[d.red0 + b] = i;
+    for (int64_t b = 0; b < d.nredv; ++b) L.redv_grp[d.redv0 + b] = i;
+  }
+  size_t off = 0;
+  L.off_groups = off;
+  off += r256(sizeof(GroupDev) * ng);
+  L.off_tables = off;
+  off += r256(sizeof(int32_t) * (L.row_blocks + L.vec_blocks + L.red_rows + L.redv_rows));
+  L.off_part = off;
+  off += r256(sizeof(double) * 2 * S * (size_t)(L.row_blocks > L.vec_blocks ? L.row_blocks : L.vec_blocks));
+  L.off_out1 = off;
+  off += r256(sizeof(double) * 2 * S * (size_t)(L.red_rows > L.redv_rows ? L.red_rows : L.redv_rows));
+  L.off_ctl = off;
+  off += r256(sizeof(Ctl) * ng);
+  L.off_count = off;
+  off += 256;
+  L.off_vec = off;
+  off += vec_bytes;
+  L.bytes = off;
+  return ENS_OK;
+}
+
+static BatchDev bind(Layout& L, char* ws, int ng, int S) {
+  BatchDev bd;
+  int32_t* tables = (int32_t*)(ws + L.off_tables);
+  bd.groups = (const GroupDev*)(ws + L.off_groups);
+  bd.row_grp = tables;
+  bd.vec_grp = tables + L.row_blocks;
+  bd.red_grp = tables + L.row_blocks + L.vec_blocks;
+  bd.redv_grp = tables + L.row_blocks + L.vec_blocks + L.red_rows;
+  bd.part = (double*)(ws + L.off_part);
+  bd.out1 = (double*)(ws + L.off_out1);
+  char* vp = ws + L.off_vec;
+  Ctl* ctl = (Ctl*)(ws + L.off_ctl);
+  for (int i = 0; i < ng; ++i) {
+    GroupDev& d = L.g[i];
+    const size_t vb = r256((size_t)d.n * S * sizeof(double));
+    d.r = (double*)vp;
+    d.p = (double*)(vp + vb);
+    d.q = (double*)(vp + 2 * vb);
+    d.dinv = (double*)(vp + 3 * vb);
+    vp += 4 * vb;
+    d.ctl = ctl + i;
+  }
+  return bd;
+}
+
+template <int S, int NW>
+static void batch_iteration(const BatchDev& bd, const Layout& L, int ng, hipStream_t st) {
+  hipLaunchKernelGGL((kb_spmv_dot<S, NW>), dim3((unsigned)L.row_blocks), dim3(NW * 64), 0, st, bd);
+  hipLaunchKernelGGL((kb_stage1<S, 0>), dim3((unsigned)L.red_rows), dim3(256), 0, st, bd, 1);
+  hipLaunchKernelGGL((kb_final<S, 1, 0>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_ALPHA, 0, 1);
+  hipLaunchKernelGGL(kb_update<S>, dim3((unsigned)L.vec_blocks), dim3(256), 0, st, bd);
+  hipLaunchKernelGGL((kb_stage1<2 * S, 1>), dim3((unsigned)L.redv_rows), dim3(256), 0, st, bd, 1);
+  hipLaunchKernelGGL((kb_final<S, 2, 1>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_UPDATE, 0, 1);
+  hipLaunchKernelGGL(kb_pupdate<S>, dim3((unsigned)L.vec_blocks), dim3(256), 0, st, bd);
+}
+
+static ens_status poll(int32_t* dev_count, hipStream_t st, int32_t* out) {
+  DeviceCtx* cx = device_ctx();
+  if (!cx) {
+    set_error("device context unavailable");
+    return ENS_E_HIP;
+  }
+  ENS_HIP_TRY(hipMemcpyAsync(cx->host_flag, dev_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  ENS_HIP_TRY(hipStreamSynchronize(st));
+  *out = *cx->host_flag;
+  return ENS_OK;
+}
+
+template <int S, int NW>
+static ens_status solve_batch(const ens_group* groups, int ng, const ens_batch_opts& o, void* ws, size_t ws_bytes,
+                              hipStream_t user) {
+  Layout L;
+  ens_status rc = plan<S, NW>(groups, ng, L);
+  if (rc != ENS_OK) return rc;
+  if (ws_bytes < L.bytes) {
+    set_error("batch workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.bytes);
+    return ENS_E_NOMEM;
+  }
+  char* w = (char*)ws;
+  BatchDev bd = bind(L, w, ng, S);
+  int32_t* dcount = (int32_t*)(w + L.off_count);
+  DeviceCtx* cx = device_ctx();
+  if (!cx) {
+    set_error("device context unavailable");
+    return ENS_E_HIP;
+  }
+  // all work runs on the library's own stream, ordered after and before the
+  // caller's stream by events (graph capture needs a non-default stream)
+  hipStream_t st = cx->work_stream;
+  ENS_HIP_TRY(hipEventRecord(cx->ev_in, user));
+  ENS_HIP_TRY(hipStreamWaitEvent(st, cx->ev_in, 0));
+  ENS_HIP_TRY(hipMemcpyAsync(w + L.off_groups, L.g.data(), sizeof(GroupDev) * ng, hipMemcpyHostToDevice, st));
+  std::vector<int32_t> tables;
+  tables.insert(tables.end(), L.row_grp.begin(), L.row_grp.end());
+  tables.insert(tables.end(), L.vec_grp.begin(), L.vec_grp.end());
+  tables.insert(tables.end(), L.red_grp.begin(), L.red_grp.end());
+  tables.insert(tables.end(), L.redv_grp.begin(), L.redv_grp.end());
+  ENS_HIP_TRY(hipMemcpyAsync(w + L.off_tables, tables.data(), sizeof(int32_t) * tables.size(),
+                             hipMemcpyHostToDevice, st));
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
+  const int chunk = o.check_every > 0 ? o.check_every : 16;
+  hipLaunchKernelGGL(kb_ctl_init, dim3((unsigned)(ng < 1024 ? ng : 1024)), dim3(64), 0, st, bd, ng, o.rtol, max_iter);
+  hipLaunchKernelGGL(kb_diag_inv<S>, dim3(2048), dim3(256), 0, st, bd, ng);
+  hipLaunchKernelGGL((kb_residual<S, NW>), dim3((unsigned)L.row_blocks), dim3(NW * 64), 0, st, bd, 1);
+  hipLaunchKernelGGL((kb_stage1<2 * S, 0>), dim3((unsigned)L.red_rows), dim3(256), 0, st, bd, 0);
+  hipLaunchKernelGGL((kb_final<S, 2, 0>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_START, 0, 0);
+  hipLaunchKernelGGL(kb_zero_where<S>, dim3(1024), dim3(256), 0, st, bd, ng);
+  hipLaunchKernelGGL(kb_cg_start<S>, dim3((unsigned)L.vec_blocks), dim3(256), 0, st, bd);
+  hipLaunchKernelGGL((kb_stage1<2 * S, 1>), dim3((unsigned)L.redv_rows), dim3(256), 0, st, bd, 0);
+  hipLaunchKernelGGL((kb_final<S, 2, 1>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_RHO, 0, 0);
+  ENS_LAUNCH_CHECK();
+
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (o.use_graph) {
+    ENS_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < chunk; ++k) batch_iteration<S, NW>(bd, L, ng, st);
+    hipLaunchKernelGGL(kb_count, dim3(1), dim3(256), 0, st, bd, ng, dcount);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      set_error("graph capture failed: %s / %s", hipGetErrorString(e1), hipGetErrorString(e2));
+      return ENS_E_HIP;
+    }
+    hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      set_error("graph instantiation failed: %s", hipGetErrorString(e3));
+      return ENS_E_HIP;
+    }
+  }
+  ens_status out = ENS_OK;
+  for (int k0 = 0; k0 < max_iter; k0 += chunk) {
+    if (o.use_graph) {
+      hipError_t e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess) {
+        set_error("graph launch failed: %s", hipGetErrorString(e));
+        out = ENS_E_HIP;
+        break;
+      }
+    } else {
+      for (int k = 0; k < chunk; ++k) batch_iteration<S, NW>(bd, L, ng, st);
+      hipLaunchKernelGGL(kb_count, dim3(1), dim3(256), 0, st, bd, ng, dcount);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        set_error("launch failed: %s", hipGetErrorString(e));
+        out = ENS_E_HIP;
+        break;
+      }
+    }
+    int32_t act = 0;
+    out = poll(dcount, st, &act);
+    if (out != ENS_OK || act == 0) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (out != ENS_OK) return out;
+  // true residuals
+  hipLaunchKernelGGL((kb_residual<S, NW>), dim3((unsigned)L.row_blocks), dim3(NW * 64), 0, st, bd, 0);
+  hipLaunchKernelGGL((kb_stage1<2 * S, 0>), dim3((unsigned)L.red_rows), dim3(256), 0, st, bd, 0);
+  hipLaunchKernelGGL((kb_final<S, 2, 0>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_TRUE, 0, 0);
+  ENS_LAUNCH_CHECK();
+  std::vector<Ctl> h(ng);
+  ENS_HIP_TRY(hipMemcpyAsync(h.data(), w + L.off_ctl, sizeof(Ctl) * ng, hipMemcpyDeviceToHost, st));
+  ENS_HIP_TRY(hipStreamSynchronize(st));
+  ENS_HIP_TRY(hipEventRecord(cx->ev_out, st));
+  ENS_HIP_TRY(hipStreamWaitEvent(user, cx->ev_out, 0));
+  ens_status agg = ENS_OK;
+  for (int i = 0; i < ng; ++i)
+    for (int e = 0; e < S; ++e) {
+      ens_cg_stat& s = groups[i].stats[e];
+      s.iters = h[i].iters[e];
+      s.outer_iters = 0;
+      s.status = h[i].status[e];
+      s.reserved = 0;
+      s.rel_res = h[i].rel_res[e];
+      if (s.status != ENS_SAMPLE_CONVERGED) agg = ENS_W_NOT_CONVERGED;
+    }
+  return agg;
+}
+
+static bool tile_ok(int t) { return t == 2 || t == 4 || t == 8; }
+
+template <int S>
+static ens_status dispatch_tile(const ens_group* g, int ng, const ens_batch_opts& o, void* ws, size_t b,
+                                hipStream_t st, size_t* need) {
+  Layout L;
+  ens_status rc;
+  switch (o.tile) {
+    case 2: rc = need ? plan<S, 2>(g, ng, L) : solve_batch<S, 2>(g, ng, o, ws, b, st); break;
+    case 4: rc = need ? plan<S, 4>(g, ng, L) : solve_batch<S, 4>(g, ng, o, ws, b, st); break;
+    default: rc = need ? plan<S, 8>(g, ng, L) : solve_batch<S, 8>(g, ng, o, ws, b, st); break;
+  }
+  if (need && rc == ENS_OK) *need = L.bytes;
+  return rc;
+}
+
+static ens_status dispatch(const ens_group* g, int ng, int32_t s, const ens_batch_opts& o, void* ws, size_t b,
+                           hipStream_t st, size_t* need) {
+  switch (s) {
+    case 8: return dispatch_tile<8>(g, ng, o, ws, b, st, need);
+    case 16: return dispatch_tile<16>(g, ng, o, ws, b, st, need);
+    case 32: return dispatch_tile<32>(g, ng, o, ws, b, st, need);
+    default: set_error("batch ensemble size %d not compiled in (8, 16, 32)", s); return ENS_E_UNSUPPORTED;
+  }
+}
+
+}  // namespace ens
+
+using namespace ens;
+
+extern "C" {
+
+ens_status ens_batch_workspace_bytes(const ens_group* groups, int32_t n_groups, int32_t s, const ens_batch_opts* opts,
+                                     size_t* bytes) {
+  ENS_ARG_CHECK(groups && n_groups >= 1 && opts && bytes, "bad batch arguments");
+  ENS_ARG_CHECK(tile_ok(opts->tile), "tile must be 2, 4 or 8 wavefronts");
+  return dispatch(groups, n_groups, s, *opts, nullptr, 0, nullptr, bytes);
+}
+
+ens_status ens_solve_batch(const ens_group* groups, int32_t n_groups, int32_t s, const ens_batch_opts* opts,
+                           void* workspace, size_t ws_bytes, hipStream_t stream) {
+  ENS_ARG_CHECK(groups && n_groups >= 1 && opts && workspace, "bad batch arguments");
+  ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
+  ENS_ARG_CHECK(tile_ok(opts->tile), "tile must be 2, 4 or 8 wavefronts");
+  ENS_ARG_CHECK(opts->rtol >= 0.0, "rtol must be >= 0");
+  return dispatch(groups, n_groups, s, *opts, workspace, ws_bytes, stream, nullptr);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- autotuner ---
+
+namespace ens {
+
+static std::string tune_key(const int32_t* meshes, int nm, const ens_problem& pr, const ens_batch_opts& o) {
+  char buf[160];
+  std::string k = "gfx950:N";
+  for (int i = 0; i < nm; ++i) k += "_" + std::to_string(meshes[i]);
+  snprintf(buf, sizeof(buf), ":M%d:sig%.4g:L%.4g:rtol%.3g:ce%d", pr.M, pr.sigma, pr.L, o.rtol, o.check_every);
+  return k + buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, int* s, int* tile) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char kb[512];
+  int a = 0, b = 0;
+  bool found = false;
+  while (fscanf(f, "%511s %d %d", kb, &a, &b) == 3)
+    if (key == kb) {  // the last entry for a key wins
+      *s = a;
+      *tile = b;
+      found = true;
+    }
+  fclose(f);
+  return found;
+}
+
+static void cache_store(const char* path, const std::string& key, int s, int tile) {
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d\n", key.c_str(), s, tile);
+  fclose(f);
+}
+
+// Trial buffers of one mesh: graph, KL table, and 32 samples' values, b and
+// x, carved into 32/s groups of s samples for a candidate s.
+struct TrialMesh {
+  int N = 0;
+  int64_t n = 0, nnz = 0;
+  int32_t *rp = nullptr, *ci = nullptr;
+  void* kl = nullptr;
+  double *xi = nullptr, *vals = nullptr, *b = nullptr, *x = nullptr;
+  ens_graph g{};
+};
+
+}  // namespace ens
+
+extern "C" ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, const ens_problem* prob,
+                                         const double* xi_host, const int32_t* s_cand, int32_t ns,
+                                         const int32_t* tile_cand, int32_t nt, const ens_batch_opts* base,
+                                         const char* cache_path, int32_t* best_s, int32_t* best_tile,
+                                         double* scores, hipStream_t stream) {
+  ENS_ARG_CHECK(meshes && nm >= 1 && prob && xi_host && s_cand && ns >= 1 && tile_cand && nt >= 1 && base,
+                "bad arguments");
+  ENS_ARG_CHECK(best_s && best_tile && base->rtol >= 0.0, "bad arguments");
+  for (int i = 0; i < nm; ++i) ENS_ARG_CHECK(meshes[i] >= 1, "mesh sizes must be >= 1");
+  for (int i = 0; i < ns; ++i)
+    if (s_cand[i] != 8 && s_cand[i] != 16 && s_cand[i] != 32) {
+      set_error("candidate ensemble size %d not compiled in (8, 16, 32)", s_cand[i]);
+      return ENS_E_UNSUPPORTED;
+    }
+  for (int i = 0; i < nt; ++i) ENS_ARG_CHECK(tile_ok(tile_cand[i]), "tile must be 2, 4 or 8");
+  const std::string key = tune_key(meshes, nm, *prob, *base);
+  int cs = 0, ct = 0;
+  if (!scores && cache_lookup(cache_path, key, &cs, &ct)) {
+    *best_s = cs;
+    *best_tile = ct;
+    return ENS_OK;
+  }
+  constexpr int kTrial = 32;  // samples per mesh in every trial
+  const int M = prob->M;
+  std::vector<TrialMesh> t(nm);
+  std::vector<ens_cg_stat> stats((size_t)nm * kTrial);
+  void* ws = nullptr;
+  size_t ws_have = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ens_status rc = ENS_OK;
+  double best = -1.0;
+#define TUNE_TRY(expr)                                             \
+  do {                                                             \
+    hipError_t _e = (expr);                                        \
+    if (_e != hipSuccess) {                                        \
+      set_error("autotune: %s: %s", #expr, hipGetErrorString(_e)); \
+      rc = ENS_E_HIP;                                              \
+      goto done;                                                   \
+    }                                                              \
+  } while (0)
+  TUNE_TRY(hipEventCreate(&e0));
+  TUNE_TRY(hipEventCreate(&e1));
+  for (int i = 0; i < nm; ++i) {
+    TrialMesh& m = t[i];
+    m.N = meshes[i];
+    rc = ens_mesh_sizes(m.N, &m.n, &m.nnz, nullptr);
+    if (rc != ENS_OK) goto done;
+    size_t klb = 0;
+    rc = ens_kl_bytes(m.N, M, &klb);
+    if (rc != ENS_OK) goto done;
+    TUNE_TRY(hipMalloc(&m.rp, sizeof(int32_t) * (m.n + 1)));
+    TUNE_TRY(hipMalloc(&m.ci, sizeof(int32_t) * m.nnz));
+    TUNE_TRY(hipMalloc(&m.kl, klb));
+    TUNE_TRY(hipMalloc(&m.xi, sizeof(double) * kTrial * (M > 0 ? M : 1)));
+    TUNE_TRY(hipMalloc(&m.vals, sizeof(double) * kTrial * m.nnz));
+    TUNE_TRY(hipMalloc(&m.b, sizeof(double) * kTrial * m.n));
+    TUNE_TRY(hipMalloc(&m.x, sizeof(double) * kTrial * m.n));
+    if (M > 0)
+      TUNE_TRY(hipMemcpyAsync(m.xi, xi_host + (size_t)i * kTrial * M, sizeof(double) * kTrial * M,
+                              hipMemcpyHostToDevice, stream));
+    rc = ens_graph_build(m.N, m.rp, m.ci, stream);
+    if (rc == ENS_OK) rc = ens_kl_build(m.N, M, prob->L, m.kl, stream);
+    if (rc != ENS_OK) goto done;
+    m.g = ens_graph{(int32_t)m.n, m.nnz, m.rp, m.ci};
+  }
+  for (int a = 0; a < ns; ++a) {
+    const int s = s_cand[a];
+    const int per = kTrial / s;  // groups per mesh
+    std::vector<ens_group> gr;
+    for (int i = 0; i < nm; ++i)
+      for (int j = 0; j < per; ++j) {
+        TrialMesh& m = t[i];
+        double* v = m.vals + (size_t)j * s * m.nnz;
+        double* b = m.b + (size_t)j * s * m.n;
+        double* x = m.x + (size_t)j * s * m.n;
+        rc = ens_assemble(m.N, &m.g, m.kl, prob, s, m.xi + (size_t)j * s * M, v, nullptr, b, stream);
+        if (rc != ENS_OK) goto done;
+        gr.push_back(ens_group{&m.g, v, b, x, stats.data() + ((size_t)i * kTrial + (size_t)j * s)});
+      }
+    for (int c = 0; c < nt; ++c) {
+      ens_batch_opts o = *base;
+      o.tile = tile_cand[c];
+      size_t need = 0;
+      rc = ens_batch_workspace_bytes(gr.data(), (int)gr.size(), s, &o, &need);
+      if (rc != ENS_OK) goto done;
+      if (need > ws_have) {
+        if (ws) (void)hipFree(ws);
+        ws = nullptr;
+        ws_have = 0;
+        TUNE_TRY(hipMalloc(&ws, need));
+        ws_have = need;
+      }
+      float ms = 0.f;
+      const int reps = (a == 0 && c == 0) ? 2 : 1;  // the very first solve also warms up
+      for (int rep = 0; rep < reps; ++rep) {
+        for (int i = 0; i < nm; ++i) TUNE_TRY(hipMemsetAsync(t[i].x, 0, sizeof(double) * kTrial * t[i].n, stream));
+        TUNE_TRY(hipEventRecord(e0, stream));
+        rc = ens_solve_batch(gr.data(), (int)gr.size(), s, &o, ws, ws_have, stream);
+        if (rc != ENS_OK && rc != ENS_W_NOT_CONVERGED) goto done;
+        TUNE_TRY(hipEventRecord(e1, stream));
+        TUNE_TRY(hipEventSynchronize(e1));
+        TUNE_TRY(hipEventElapsedTime(&ms, e0, e1));
+      }
+      rc = ENS_OK;
+      const double score = (double)nm * kTrial / (ms * 1e-3);  // solved samples per second
+      if (scores) scores[a * nt + c] = score;
+      if (score > best) {
+        best = score;
+        *best_s = s;
+        *best_tile = tile_cand[c];
+      }
+    }
+  }
+  cache_store(cache_path, key, *best_s, *best_tile);
+done:
+#undef TUNE_TRY
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (auto& m : t) {
+    (void)hipFree(m.rp);
+    (void)hipFree(m.ci);
+    (void)hipFree(m.kl);
+    (void)hipFree(m.xi);
+    (void)hipFree(m.vals);
+    (void)hipFree(m.b);
+    (void)hipFree(m.x);
+  }
+  if (ws) (void)hipFree(ws);
+  return rc;
+}

@@ -26,165 +26,10 @@
 // launch it saves).  Every kernel of the iteration returns immediately when
 // the active count is zero, and the host reads the count once per chunk of
 // iterations, so the loop ends on the device.
-#include "rowops.hpp"
+#include "cgcore.hpp"
 
 namespace ens {
 
-constexpr int kMaxS = 32;
-
-enum CgOp { OP_START = 0, OP_RHO = 1, OP_ALPHA = 2, OP_UPDATE = 3, OP_TRUE = 4, OP_OUTER = 5 };
-
-struct Ctl {
-  double rho[kMaxS], alpha[kMaxS], beta[kMaxS], tol2[kMaxS], bnorm2[kMaxS];
-  double rel_res[kMaxS], orr_prev[kMaxS];
-  int32_t active[kMaxS], oactive[kMaxS], iters[kMaxS], oiters[kMaxS], kiter[kMaxS], status[kMaxS];
-  int32_t zero_b[kMaxS];
-  int32_t n_active, n_oactive;
-  double rtol, inner_rtol;
-  int32_t max_iter, inner_max_iter, max_outer, mixed;
-  double tot[2 * kMaxS];
-};
-
-// ------------------------------------------------------------- finalize ---
-
-template <int S>
-__device__ void finalize(Ctl* c, int op, int arg) {
-  const int e = threadIdx.x;
-  if (e < S) {
-    const double t0 = c->tot[e], t1 = c->tot[S + e];
-    switch (op) {
-      case OP_START: {  // t0 = |b - A x0|^2, t1 = |b|^2
-        c->bnorm2[e] = t1;
-        c->tol2[e] = c->rtol * c->rtol * t1;
-        c->iters[e] = 0;
-        c->oiters[e] = 0;
-        c->kiter[e] = 0;
-        c->zero_b[e] = (t1 == 0.0);
-        c->active[e] = 0;
-        if (t1 == 0.0) {
-          c->status[e] = ENS_SAMPLE_CONVERGED;
-        } else if (!isfinite(t0) || !isfinite(t1)) {
-          c->status[e] = ENS_SAMPLE_NONFINITE;
-        } else if (t0 <= c->tol2[e]) {
-          c->status[e] = ENS_SAMPLE_CONVERGED;
-        } else {
-          c->status[e] = ENS_SAMPLE_MAXITER;
-          c->active[e] = 1;
-        }
-        break;
-      }
-      case OP_RHO: {  // t0 = r.z
-        if (c->active[e]) {
-          c->kiter[e] = 0;
-          if (!isfinite(t0)) {
-            c->status[e] = ENS_SAMPLE_NONFINITE;
-            c->active[e] = 0;
-            c->oactive[e] = 0;
-          } else {
-            c->rho[e] = t0;
-          }
-        }
-        break;
-      }
-      case OP_ALPHA: {  // t0 = p.q
-        if (c->active[e]) {
-          const double rho = c->rho[e];
-          if (!isfinite(t0) || !isfinite(rho)) {
-            c->status[e] = ENS_SAMPLE_NONFINITE;
-            c->active[e] = 0;
-            c->oactive[e] = 0;
-          } else if (!(t0 > 0.0)) {
-            c->status[e] = ENS_SAMPLE_BREAKDOWN;
-            c->active[e] = 0;
-            c->oactive[e] = 0;
-          } else {
-            c->alpha[e] = rho / t0;
-          }
-        }
-        break;
-      }
-      case OP_UPDATE: {  // t0 = r.z, t1 = r.r
-        if (c->active[e]) {
-          c->iters[e] += 1;
-          c->kiter[e] += 1;
-          const int cap = c->mixed ? c->inner_max_iter : c->max_iter;
-          if (!isfinite(t0) || !isfinite(t1)) {
-            c->status[e] = ENS_SAMPLE_NONFINITE;
-            c->active[e] = 0;
-            c->oactive[e] = 0;
-          } else if (t1 <= c->tol2[e]) {
-            c->active[e] = 0;
-            if (!c->mixed) c->status[e] = ENS_SAMPLE_CONVERGED;
-          } else if (c->kiter[e] >= cap) {
-            c->active[e] = 0;
-            if (!c->mixed) c->status[e] = ENS_SAMPLE_MAXITER;
-          } else {
-            c->beta[e] = t0 / c->rho[e];
-            c->rho[e] = t0;
-          }
-        }
-        break;
-      }
-      case OP_TRUE: {  // t0 = |b - A x|^2, t1 = |b|^2
-        c->rel_res[e] = t1 > 0.0 ? sqrt(t0 / t1) : sqrt(t0);
-        break;
-      }
-      case OP_OUTER: {  // t0 = |b - A x|^2, t1 = |b|^2, arg = refinement step
-        const int o = arg;
-        if (o == 0) {
-          c->bnorm2[e] = t1;
-          c->zero_b[e] = (t1 == 0.0);
-          c->oactive[e] = (t1 != 0.0);
-          c->status[e] = t1 == 0.0 ? ENS_SAMPLE_CONVERGED : ENS_SAMPLE_MAXITER;
-          c->iters[e] = 0;
-          c->oiters[e] = 0;
-          c->orr_prev[e] = INFINITY;
-        }
-        c->rel_res[e] = t1 > 0.0 ? sqrt(t0 / t1) : 0.0;
-        c->active[e] = 0;
-        if (c->oactive[e]) {
-          const double rt = c->rtol;
-          if (!isfinite(t0)) {
-            c->status[e] = ENS_SAMPLE_NONFINITE;
-            c->oactive[e] = 0;
-          } else if (t0 <= rt * rt * t1) {
-            c->status[e] = ENS_SAMPLE_CONVERGED;
-            c->oactive[e] = 0;
-          } else if (o >= 1 && t0 > 0.25 * c->orr_prev[e]) {
-            c->status[e] = ENS_SAMPLE_STAGNATED;
-            c->oactive[e] = 0;
-          } else if (o >= c->max_outer) {
-            c->status[e] = ENS_SAMPLE_MAXITER;
-            c->oactive[e] = 0;
-          } else {
-            const double it = c->inner_rtol * c->inner_rtol * t0;
-            const double fl = 0.09 * rt * rt * t1;
-            c->tol2[e] = it > fl ? it : fl;
-            c->active[e] = 1;
-            c->oiters[e] += 1;
-          }
-          c->orr_prev[e] = t0;
-        }
-        break;
-      }
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int na = 0, no = 0;
-    for (int j = 0; j < S; ++j) {
-      na += c->active[j];
-      no += c->oactive[j];
-    }
-    c->n_active = na;
-    c->n_oactive = no;
-  }
-}
-
-// Streaming kernels process kU chunks per thread: all loads of a thread
-// are issued before its stores, so the in-order memory counter never makes
-// a load wait for an earlier store.
-constexpr int kU = 4;
 // First reduction stage: at most this many blocks, each summing >= 64 rows.
 constexpr int kRedBlocks = 128;
 
@@ -212,267 +57,54 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
   finalize<S>(c, op, arg);
 }
 
-// --------------------------------------------------------- vector mapping ---
-
-// Streaming kernels treat an [n][S] vector as chunks of V = min(16/sizeof(T),
-// S) consecutive samples of one row (one 16-byte load for S >= 4; a single
-// element for the one-sample path).  Lanes L = S/V apart hold the same
-// samples, and a grid-stride loop keeps each lane on the same samples.
-template <typename T, int S>
-struct VecMap {
-  static constexpr int V = pack<T>::V < S ? pack<T>::V : S;
-  static constexpr int VS = V;
-  static constexpr int L = S / V;
-  typedef typename vec_t<T, V>::type vt;
-  __device__ static inline int sample(int sub, int v) { return sub * V + v; }
-  __device__ static inline int slot(int v) { return v; }
-};
-
 // ------------------------------------------------------------ kernels ---
 
-__global__ void k_ctl_init(Ctl* c, double rtol, double inner_rtol, int max_iter, int inner_max_iter,
-                           int max_outer, int mixed) {
-  if (threadIdx.x == 0) {
-    c->rtol = rtol;
-    c->inner_rtol = inner_rtol;
-    c->max_iter = max_iter;
-    c->inner_max_iter = inner_max_iter;
-    c->max_outer = max_outer;
-    c->mixed = mixed;
-    c->n_active = 0;
-    c->n_oactive = 0;
-  }
-  if (threadIdx.x < kMaxS) {
-    const int e = threadIdx.x;
-    c->active[e] = 0;
-    c->oactive[e] = 0;
-    c->iters[e] = 0;
-    c->oiters[e] = 0;
-    c->kiter[e] = 0;
-    c->status[e] = ENS_SAMPLE_MAXITER;
-    c->zero_b[e] = 0;
-    c->rel_res[e] = 0.0;
-  }
-}
-
-// dinv[i][e] = 1 / A_ii[e]
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_diag_inv(int n, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const T* __restrict__ vals,
                                                   T* __restrict__ dinv) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = t / S;
-  const int e = (int)(t % S);
-  if (row >= n) return;
-  T d = (T)0;
-  for (int64_t k = rp[row]; k < rp[row + 1]; ++k)
-    if (ci[k] == row) d = vals[k * S + e];
-  dinv[row * S + e] = (T)1 / d;
+  diag_inv_body<T, S>(n, rp, ci, vals, dinv, blockIdx.x);
 }
 
-// r = b - A x in FP64 for every sample (ensemble layout), optionally stored
-// (rounded to TR), with block partials |r|^2 and |b|^2.  One row tile per
-// block.
+// One row tile per block (4 wavefronts).
 template <int S, typename TR>
 __global__ __launch_bounds__(256) void k_residual(int n, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const double* __restrict__ vals,
                                                   const double* __restrict__ x, const double* __restrict__ b,
                                                   TR* __restrict__ rout, double* __restrict__ part) {
-  using M = EnsMap<double, S>;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sub = lane % M::L;
-  double acc[2][M::V];
-#pragma unroll
-  for (int j = 0; j < M::V; ++j) acc[0][j] = acc[1][j] = 0.0;
-  const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
-  if (row < n) {
-    typename M::vt ax = ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
-    typename M::vt bv = ((const typename M::vt*)b)[row * M::L + sub];
-    typename M::vt r = bv - ax;
-#pragma unroll
-    for (int j = 0; j < M::V; ++j) {
-      acc[0][j] = r[j] * r[j];
-      acc[1][j] = bv[j] * bv[j];
-    }
-    if (rout) {
-#pragma unroll
-      for (int j = 0; j < M::V; ++j) rout[row * S + sub * M::V + j] = (TR)r[j];
-    }
-  }
-  block_partials<S, M::V, 2>(acc, part);
+  residual_body<S, TR, 4>(n, rp, ci, vals, x, b, rout, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
 }
 
-// z = D^-1 r, p = z (all samples); optionally zero the solution vector;
-// block partials r.z and r.r.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cg_start(int64_t nchunks, const T* __restrict__ r,
                                                   const T* __restrict__ dinv, T* __restrict__ p,
                                                   T* __restrict__ xzero, double* __restrict__ part) {
-  using M = VecMap<T, S>;
-  using vt = typename M::vt;
-  double acc[2][M::VS];
-#pragma unroll
-  for (int j = 0; j < M::VS; ++j) acc[0][j] = acc[1][j] = 0.0;
-  const int64_t base = (int64_t)blockIdx.x * kBlock * kU + threadIdx.x;
-  vt rv[kU], dv[kU];
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int64_t i = base + u * kBlock;
-    if (i < nchunks) {
-      rv[u] = ((const vt*)r)[i];
-      dv[u] = ((const vt*)dinv)[i];
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int64_t i = base + u * kBlock;
-    if (i < nchunks) {
-      vt z = dv[u] * rv[u];
-      ((vt*)p)[i] = z;
-      if (xzero) ((vt*)xzero)[i] = (vt)0;
-#pragma unroll
-      for (int v = 0; v < M::V; ++v) {
-        acc[0][M::slot(v)] += (double)rv[u][v] * (double)z[v];
-        acc[1][M::slot(v)] += (double)rv[u][v] * (double)rv[u][v];
-      }
-    }
-  }
-  block_partials<S, M::VS, 2>(acc, part);
+  cg_start_body<T, S>(nchunks, r, dinv, p, xzero, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
 }
 
-// A: q = A p, block partials p.q.  One row tile per block.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cg_spmv_dot(int n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const T* __restrict__ vals,
                                                      const T* __restrict__ p, T* __restrict__ q, const Ctl* c,
                                                      double* __restrict__ part) {
   if (c->n_active == 0) return;
-  using M = EnsMap<T, S>;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sub = lane % M::L;
-  double acc[1][M::V];
-#pragma unroll
-  for (int j = 0; j < M::V; ++j) acc[0][j] = 0.0;
-  const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
-  if (row < n) {
-    typename M::vt qv = ens_row_product<T, S>(ci, vals, p, rp[row], rp[row + 1], sub);
-    ((typename M::vt*)q)[row * M::L + sub] = qv;
-    typename M::vt pv = ((const typename M::vt*)p)[row * M::L + sub];
-#pragma unroll
-    for (int j = 0; j < M::V; ++j) acc[0][j] = (double)pv[j] * (double)qv[j];
-  }
-  block_partials<S, M::V, 1>(acc, part);
+  spmv_dot_body<T, S, 4>(n, rp, ci, vals, p, q, blockIdx.x, part + (int64_t)blockIdx.x * S);
 }
 
-// B: x += alpha p; r -= alpha q; z = D^-1 r; block partials r.z, r.r.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cg_update(int64_t nchunks, T* __restrict__ x, const T* __restrict__ p,
                                                    const T* __restrict__ q, T* __restrict__ r,
                                                    const T* __restrict__ dinv, const Ctl* c,
                                                    double* __restrict__ part) {
   if (c->n_active == 0) return;
-  using M = VecMap<T, S>;
-  using vt = typename M::vt;
-  const int sub = (threadIdx.x & 63) % M::L;
-  vt al;
-  int act[M::V];
-#pragma unroll
-  for (int v = 0; v < M::V; ++v) {
-    const int e = M::sample(sub, v);
-    act[v] = c->active[e];
-    al[v] = act[v] ? (T)c->alpha[e] : (T)0;
-  }
-  double acc[2][M::VS];
-#pragma unroll
-  for (int j = 0; j < M::VS; ++j) acc[0][j] = acc[1][j] = 0.0;
-  const int64_t base = (int64_t)blockIdx.x * kBlock * kU + threadIdx.x;
-  vt pv[kU], qv[kU], rv[kU], xv[kU], dv[kU];
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int64_t i = base + u * kBlock;
-    if (i < nchunks) {
-      pv[u] = ((const vt*)p)[i];
-      qv[u] = ((const vt*)q)[i];
-      rv[u] = ((const vt*)r)[i];
-      xv[u] = ((const vt*)x)[i];
-      dv[u] = ((const vt*)dinv)[i];
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int64_t i = base + u * kBlock;
-    if (i < nchunks) {
-      vt xn = xv[u] + al * pv[u];
-      vt rn = rv[u] - al * qv[u];
-#pragma unroll
-      for (int v = 0; v < M::V; ++v)  // converged or stopped samples stay frozen
-        if (!act[v]) {
-          xn[v] = xv[u][v];
-          rn[v] = rv[u][v];
-        }
-      xv[u] = xn;
-      rv[u] = rn;
-      vt z = dv[u] * rn;
-#pragma unroll
-      for (int v = 0; v < M::V; ++v) {
-        const double rr = act[v] ? (double)rn[v] : 0.0;
-        acc[0][M::slot(v)] += rr * (double)z[v];
-        acc[1][M::slot(v)] += rr * rr;
-      }
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int64_t i = base + u * kBlock;
-    if (i < nchunks) {
-      ((vt*)x)[i] = xv[u];
-      ((vt*)r)[i] = rv[u];
-    }
-  }
-  block_partials<S, M::VS, 2>(acc, part);
+  update_body<T, S>(nchunks, x, p, q, r, dinv, c, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
 }
 
-// C: p = D^-1 r + beta p for the samples still active.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_cg_pupdate(int64_t nchunks, const T* __restrict__ r,
                                                     const T* __restrict__ dinv, T* __restrict__ p, const Ctl* c) {
   if (c->n_active == 0) return;
-  using M = VecMap<T, S>;
-  using vt = typename M::vt;
-  const int sub = (threadIdx.x & 63) % M::L;
-  vt be;
-  int act[M::V];
-  bool any = false;
-#pragma unroll
-  for (int v = 0; v < M::V; ++v) {
-    const int e = M::sample(sub, v);
-    act[v] = c->active[e];
-    be[v] = act[v] ? (T)c->beta[e] : (T)0;
-    any |= act[v] != 0;
-  }
-  if (!any) return;
-  const int64_t base = (int64_t)blockIdx.x * kBlock * kU + threadIdx.x;
-  vt pv[kU], rv[kU], dv[kU];
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int64_t i = base + u * kBlock;
-    if (i < nchunks) {
-      pv[u] = ((const vt*)p)[i];
-      rv[u] = ((const vt*)r)[i];
-      dv[u] = ((const vt*)dinv)[i];
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int64_t i = base + u * kBlock;
-    if (i < nchunks) {
-      vt pn = dv[u] * rv[u] + be * pv[u];
-#pragma unroll
-      for (int v = 0; v < M::V; ++v)  // inactive samples keep their p
-        if (!act[v]) pn[v] = pv[u][v];
-      ((vt*)p)[i] = pn;
-    }
-  }
+  pupdate_body<T, S>(nchunks, r, dinv, p, c, blockIdx.x);
 }
 
 // x += d for the samples still in refinement (FP64 += FP32 correction).
@@ -489,10 +121,7 @@ __global__ __launch_bounds__(256) void k_ir_update(int64_t total, double* __rest
 // x = 0 for samples whose right-hand side is zero.
 template <int S>
 __global__ __launch_bounds__(256) void k_zero_where(int64_t total, double* __restrict__ x, const Ctl* c) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    if (c->zero_b[i % S]) x[i] = 0.0;
-  }
+  zero_where_body<S>(total, x, c, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 // ----------------------------------------------- one-sample (scalar) path ---
@@ -519,7 +148,7 @@ __global__ __launch_bounds__(256) void k_residual_scalar(int n, const int32_t* _
     acc[0][0] = r * r;
     acc[1][0] = b[row] * b[row];
   }
-  block_partials<1, 1, 2>(acc, part);
+  block_partials<1, 1, 2, kBlock / 64>(acc, part + (int64_t)blockIdx.x * 2);
 }
 
 // q = A p with G lanes per row, block partials p.q.
@@ -542,7 +171,7 @@ __global__ __launch_bounds__(256) void k_cg_spmv_dot_scalar(int n, const int32_t
     q[row] = s;
     acc[0][0] = p[row] * s;
   }
-  block_partials<1, 1, 1>(acc, part);
+  block_partials<1, 1, 1, kBlock / 64>(acc, part + (int64_t)blockIdx.x);
 }
 
 // ------------------------------------------------------------ host side ---

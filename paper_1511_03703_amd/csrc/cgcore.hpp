@@ -1,0 +1,431 @@
+// Device side of the Jacobi-CG: per-sample state, the finalize step of each
+// reduction, and the bodies of the fused CG kernels.  Each body takes the
+// block index it works on and the row of the partial array it writes, so the
+// same code runs one ensemble per launch (cg.hip) or many sample groups per
+// launch (batch.hip).
+#pragma once
+
+#include "rowops.hpp"
+
+namespace ens {
+
+constexpr int kMaxS = 32;
+
+enum CgOp { OP_START = 0, OP_RHO = 1, OP_ALPHA = 2, OP_UPDATE = 3, OP_TRUE = 4, OP_OUTER = 5 };
+
+struct Ctl {
+  double rho[kMaxS], alpha[kMaxS], beta[kMaxS], tol2[kMaxS], bnorm2[kMaxS];
+  double rel_res[kMaxS], orr_prev[kMaxS];
+  int32_t active[kMaxS], oactive[kMaxS], iters[kMaxS], oiters[kMaxS], kiter[kMaxS], status[kMaxS];
+  int32_t zero_b[kMaxS];
+  int32_t n_active, n_oactive;
+  double rtol, inner_rtol;
+  int32_t max_iter, inner_max_iter, max_outer, mixed;
+  double tot[2 * kMaxS];
+};
+
+// ------------------------------------------------------------- finalize ---
+
+template <int S>
+__device__ void finalize(Ctl* c, int op, int arg) {
+  const int e = threadIdx.x;
+  if (e < S) {
+    const double t0 = c->tot[e], t1 = c->tot[S + e];
+    switch (op) {
+      case OP_START: {  // t0 = |b - A x0|^2, t1 = |b|^2
+        c->bnorm2[e] = t1;
+        c->tol2[e] = c->rtol * c->rtol * t1;
+        c->iters[e] = 0;
+        c->oiters[e] = 0;
+        c->kiter[e] = 0;
+        c->zero_b[e] = (t1 == 0.0);
+        c->active[e] = 0;
+        if (t1 == 0.0) {
+          c->status[e] = ENS_SAMPLE_CONVERGED;
+        } else if (!isfinite(t0) || !isfinite(t1)) {
+          c->status[e] = ENS_SAMPLE_NONFINITE;
+        } else if (t0 <= c->tol2[e]) {
+          c->status[e] = ENS_SAMPLE_CONVERGED;
+        } else {
+          c->status[e] = ENS_SAMPLE_MAXITER;
+          c->active[e] = 1;
+        }
+        break;
+      }
+      case OP_RHO: {  // t0 = r.z
+        if (c->active[e]) {
+          c->kiter[e] = 0;
+          if (!isfinite(t0)) {
+            c->status[e] = ENS_SAMPLE_NONFINITE;
+            c->active[e] = 0;
+            c->oactive[e] = 0;
+          } else {
+            c->rho[e] = t0;
+          }
+        }
+        break;
+      }
+      case OP_ALPHA: {  // t0 = p.q
+        if (c->active[e]) {
+          const double rho = c->rho[e];
+          if (!isfinite(t0) || !isfinite(rho)) {
+            c->status[e] = ENS_SAMPLE_NONFINITE;
+            c->active[e] = 0;
+            c->oactive[e] = 0;
+          } else if (!(t0 > 0.0)) {
+            c->status[e] = ENS_SAMPLE_BREAKDOWN;
+            c->active[e] = 0;
+            c->oactive[e] = 0;
+          } else {
+            c->alpha[e] = rho / t0;
+          }
+        }
+        break;
+      }
+      case OP_UPDATE: {  // t0 = r.z, t1 = r.r
+        if (c->active[e]) {
+          c->iters[e] += 1;
+          c->kiter[e] += 1;
+          const int cap = c->mixed ? c->inner_max_iter : c->max_iter;
+          if (!isfinite(t0) || !isfinite(t1)) {
+            c->status[e] = ENS_SAMPLE_NONFINITE;
+            c->active[e] = 0;
+            c->oactive[e] = 0;
+          } else if (t1 <= c->tol2[e]) {
+            c->active[e] = 0;
+            if (!c->mixed) c->status[e] = ENS_SAMPLE_CONVERGED;
+          } else if (c->kiter[e] >= cap) {
+            c->active[e] = 0;
+            if (!c->mixed) c->status[e] = ENS_SAMPLE_MAXITER;
+          } else {
+            c->beta[e] = t0 / c->rho[e];
+            c->rho[e] = t0;
+          }
+        }
+        break;
+      }
+      case OP_TRUE: {  // t0 = |b - A x|^2, t1 = |b|^2
+        c->rel_res[e] = t1 > 0.0 ? sqrt(t0 / t1) : sqrt(t0);
+        break;
+      }
+      case OP_OUTER: {  // t0 = |b - A x|^2, t1 = |b|^2, arg = refinement step
+        const int o = arg;
+        if (o == 0) {
+          c->bnorm2[e] = t1;
+          c->zero_b[e] = (t1 == 0.0);
+          c->oactive[e] = (t1 != 0.0);
+          c->status[e] = t1 == 0.0 ? ENS_SAMPLE_CONVERGED : ENS_SAMPLE_MAXITER;
+          c->iters[e] = 0;
+          c->oiters[e] = 0;
+          c->orr_prev[e] = INFINITY;
+        }
+        c->rel_res[e] = t1 > 0.0 ? sqrt(t0 / t1) : 0.0;
+        c->active[e] = 0;
+        if (c->oactive[e]) {
+          const double rt = c->rtol;
+          if (!isfinite(t0)) {
+            c->status[e] = ENS_SAMPLE_NONFINITE;
+            c->oactive[e] = 0;
+          } else if (t0 <= rt * rt * t1) {
+            c->status[e] = ENS_SAMPLE_CONVERGED;
+            c->oactive[e] = 0;
+          } else if (o >= 1 && t0 > 0.25 * c->orr_prev[e]) {
+            c->status[e] = ENS_SAMPLE_STAGNATED;
+            c->oactive[e] = 0;
+          } else if (o >= c->max_outer) {
+            c->status[e] = ENS_SAMPLE_MAXITER;
+            c->oactive[e] = 0;
+          } else {
+            const double it = c->inner_rtol * c->inner_rtol * t0;
+            const double fl = 0.09 * rt * rt * t1;
+            c->tol2[e] = it > fl ? it : fl;
+            c->active[e] = 1;
+            c->oiters[e] += 1;
+          }
+          c->orr_prev[e] = t0;
+        }
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int na = 0, no = 0;
+    for (int j = 0; j < S; ++j) {
+      na += c->active[j];
+      no += c->oactive[j];
+    }
+    c->n_active = na;
+    c->n_oactive = no;
+  }
+}
+
+// Streaming kernels process kU chunks per thread: all loads of a thread
+// are issued before its stores, so the in-order memory counter never makes
+// a load wait for an earlier store.
+constexpr int kU = 4;
+
+// Streaming kernels treat an [n][S] vector as chunks of V = min(16/sizeof(T),
+// S) consecutive samples of one row (one 16-byte load for S >= 4; a single
+// element for the one-sample path).  Lanes L = S/V apart hold the same
+// samples.
+template <typename T, int S>
+struct VecMap {
+  static constexpr int V = pack<T>::V < S ? pack<T>::V : S;
+  static constexpr int VS = V;
+  static constexpr int L = S / V;
+  typedef typename vec_t<T, V>::type vt;
+  __device__ static inline int sample(int sub, int v) { return sub * V + v; }
+  __device__ static inline int slot(int v) { return v; }
+};
+
+static __global__ void k_ctl_init(Ctl* c, double rtol, double inner_rtol, int max_iter, int inner_max_iter,
+                                  int max_outer, int mixed) {
+  if (threadIdx.x == 0) {
+    c->rtol = rtol;
+    c->inner_rtol = inner_rtol;
+    c->max_iter = max_iter;
+    c->inner_max_iter = inner_max_iter;
+    c->max_outer = max_outer;
+    c->mixed = mixed;
+    c->n_active = 0;
+    c->n_oactive = 0;
+  }
+  if (threadIdx.x < kMaxS) {
+    const int e = threadIdx.x;
+    c->active[e] = 0;
+    c->oactive[e] = 0;
+    c->iters[e] = 0;
+    c->oiters[e] = 0;
+    c->kiter[e] = 0;
+    c->status[e] = ENS_SAMPLE_MAXITER;
+    c->zero_b[e] = 0;
+    c->rel_res[e] = 0.0;
+  }
+}
+
+// dinv[i][e] = 1 / A_ii[e] for the rows of block `blk` (256 (row, sample)
+// pairs per block).
+template <typename T, int S>
+__device__ inline void diag_inv_body(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                     const T* __restrict__ vals, T* __restrict__ dinv, int64_t blk) {
+  const int64_t t = blk * blockDim.x + threadIdx.x;
+  const int64_t row = t / S;
+  const int e = (int)(t % S);
+  if (row >= n) return;
+  T d = (T)0;
+  for (int64_t k = rp[row]; k < rp[row + 1]; ++k)
+    if (ci[k] == row) d = vals[k * S + e];
+  dinv[row * S + e] = (T)1 / d;
+}
+
+// r = b - A x in FP64 for the row tile `blk` (NW wavefronts), optionally
+// stored (rounded to TR), with the block's partials |r|^2 and |b|^2 written
+// to dst[2][S].
+template <int S, typename TR, int NW>
+__device__ inline void residual_body(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                     const double* __restrict__ vals, const double* __restrict__ x,
+                                     const double* __restrict__ b, TR* __restrict__ rout, int64_t blk,
+                                     double* __restrict__ dst) {
+  using M = EnsMap<double, S>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane % M::L;
+  double acc[2][M::V];
+#pragma unroll
+  for (int j = 0; j < M::V; ++j) acc[0][j] = acc[1][j] = 0.0;
+  const int64_t row = (blk * NW + wave) * M::RPW + lane / M::L;
+  if (row < n) {
+    typename M::vt ax = ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
+    typename M::vt bv = ((const typename M::vt*)b)[row * M::L + sub];
+    typename M::vt r = bv - ax;
+#pragma unroll
+    for (int j = 0; j < M::V; ++j) {
+      acc[0][j] = r[j] * r[j];
+      acc[1][j] = bv[j] * bv[j];
+    }
+    if (rout) {
+#pragma unroll
+      for (int j = 0; j < M::V; ++j) rout[row * S + sub * M::V + j] = (TR)r[j];
+    }
+  }
+  block_partials<S, M::V, 2, NW>(acc, dst);
+}
+
+// z = D^-1 r, p = z (all samples); optionally zero the solution vector;
+// partials r.z and r.r of chunk block `blk` to dst[2][S].
+template <typename T, int S>
+__device__ inline void cg_start_body(int64_t nchunks, const T* __restrict__ r, const T* __restrict__ dinv,
+                                     T* __restrict__ p, T* __restrict__ xzero, int64_t blk,
+                                     double* __restrict__ dst) {
+  using M = VecMap<T, S>;
+  using vt = typename M::vt;
+  double acc[2][M::VS];
+#pragma unroll
+  for (int j = 0; j < M::VS; ++j) acc[0][j] = acc[1][j] = 0.0;
+  const int64_t base = blk * kBlock * kU + threadIdx.x;
+  vt rv[kU], dv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      rv[u] = ((const vt*)r)[i];
+      dv[u] = ((const vt*)dinv)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      vt z = dv[u] * rv[u];
+      ((vt*)p)[i] = z;
+      if (xzero) ((vt*)xzero)[i] = (vt)0;
+#pragma unroll
+      for (int v = 0; v < M::V; ++v) {
+        acc[0][M::slot(v)] += (double)rv[u][v] * (double)z[v];
+        acc[1][M::slot(v)] += (double)rv[u][v] * (double)rv[u][v];
+      }
+    }
+  }
+  block_partials<S, M::VS, 2, kBlock / 64>(acc, dst);
+}
+
+// A: q = A p for row tile `blk` (NW wavefronts), partials p.q to dst[S].
+template <typename T, int S, int NW>
+__device__ inline void spmv_dot_body(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                     const T* __restrict__ vals, const T* __restrict__ p, T* __restrict__ q,
+                                     int64_t blk, double* __restrict__ dst) {
+  using M = EnsMap<T, S>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane % M::L;
+  double acc[1][M::V];
+#pragma unroll
+  for (int j = 0; j < M::V; ++j) acc[0][j] = 0.0;
+  const int64_t row = (blk * NW + wave) * M::RPW + lane / M::L;
+  if (row < n) {
+    typename M::vt qv = ens_row_product<T, S>(ci, vals, p, rp[row], rp[row + 1], sub);
+    ((typename M::vt*)q)[row * M::L + sub] = qv;
+    typename M::vt pv = ((const typename M::vt*)p)[row * M::L + sub];
+#pragma unroll
+    for (int j = 0; j < M::V; ++j) acc[0][j] = (double)pv[j] * (double)qv[j];
+  }
+  block_partials<S, M::V, 1, NW>(acc, dst);
+}
+
+// B: x += alpha p; r -= alpha q; z = D^-1 r for chunk block `blk`; partials
+// r.z, r.r to dst[2][S].  Samples that are not active stay frozen.
+template <typename T, int S>
+__device__ inline void update_body(int64_t nchunks, T* __restrict__ x, const T* __restrict__ p,
+                                   const T* __restrict__ q, T* __restrict__ r, const T* __restrict__ dinv,
+                                   const Ctl* c, int64_t blk, double* __restrict__ dst) {
+  using M = VecMap<T, S>;
+  using vt = typename M::vt;
+  const int sub = (threadIdx.x & 63) % M::L;
+  vt al;
+  int act[M::V];
+#pragma unroll
+  for (int v = 0; v < M::V; ++v) {
+    const int e = M::sample(sub, v);
+    act[v] = c->active[e];
+    al[v] = act[v] ? (T)c->alpha[e] : (T)0;
+  }
+  double acc[2][M::VS];
+#pragma unroll
+  for (int j = 0; j < M::VS; ++j) acc[0][j] = acc[1][j] = 0.0;
+  const int64_t base = blk * kBlock * kU + threadIdx.x;
+  vt pv[kU], qv[kU], rv[kU], xv[kU], dv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      pv[u] = ((const vt*)p)[i];
+      qv[u] = ((const vt*)q)[i];
+      rv[u] = ((const vt*)r)[i];
+      xv[u] = ((const vt*)x)[i];
+      dv[u] = ((const vt*)dinv)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      vt xn = xv[u] + al * pv[u];
+      vt rn = rv[u] - al * qv[u];
+#pragma unroll
+      for (int v = 0; v < M::V; ++v)  // converged or stopped samples stay frozen
+        if (!act[v]) {
+          xn[v] = xv[u][v];
+          rn[v] = rv[u][v];
+        }
+      xv[u] = xn;
+      rv[u] = rn;
+      vt z = dv[u] * rn;
+#pragma unroll
+      for (int v = 0; v < M::V; ++v) {
+        const double rr = act[v] ? (double)rn[v] : 0.0;
+        acc[0][M::slot(v)] += rr * (double)z[v];
+        acc[1][M::slot(v)] += rr * rr;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      ((vt*)x)[i] = xv[u];
+      ((vt*)r)[i] = rv[u];
+    }
+  }
+  block_partials<S, M::VS, 2, kBlock / 64>(acc, dst);
+}
+
+// C: p = D^-1 r + beta p for the samples still active, chunk block `blk`.
+template <typename T, int S>
+__device__ inline void pupdate_body(int64_t nchunks, const T* __restrict__ r, const T* __restrict__ dinv,
+                                    T* __restrict__ p, const Ctl* c, int64_t blk) {
+  using M = VecMap<T, S>;
+  using vt = typename M::vt;
+  const int sub = (threadIdx.x & 63) % M::L;
+  vt be;
+  int act[M::V];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < M::V; ++v) {
+    const int e = M::sample(sub, v);
+    act[v] = c->active[e];
+    be[v] = act[v] ? (T)c->beta[e] : (T)0;
+    any |= act[v] != 0;
+  }
+  if (!any) return;
+  const int64_t base = blk * kBlock * kU + threadIdx.x;
+  vt pv[kU], rv[kU], dv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      pv[u] = ((const vt*)p)[i];
+      rv[u] = ((const vt*)r)[i];
+      dv[u] = ((const vt*)dinv)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      vt pn = dv[u] * rv[u] + be * pv[u];
+#pragma unroll
+      for (int v = 0; v < M::V; ++v)  // inactive samples keep their p
+        if (!act[v]) pn[v] = pv[u][v];
+      ((vt*)p)[i] = pn;
+    }
+  }
+}
+
+// x = 0 for samples whose right-hand side is zero.
+template <int S>
+__device__ inline void zero_where_body(int64_t total, double* __restrict__ x, const Ctl* c, int64_t i0,
+                                       int64_t stride) {
+  for (int64_t i = i0; i < total; i += stride)
+    if (c->zero_b[i % S]) x[i] = 0.0;
+}
+
+}  // namespace ens

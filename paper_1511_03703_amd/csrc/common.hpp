@@ -82,7 +82,9 @@ constexpr int kBlock = 256;
 // Per-device pinned scalars and events kept for the life of the process.
 struct DeviceCtx {
   int device = -1;
-  int32_t* host_flag = nullptr;  // pinned, for the once-per-chunk poll
+  int32_t* host_flag = nullptr;         // pinned, for the once-per-chunk poll
+  hipStream_t work_stream = nullptr;    // non-default stream for graph capture
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;  // joins with the caller's stream
 };
 DeviceCtx* device_ctx();
 

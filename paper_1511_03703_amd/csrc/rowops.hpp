@@ -63,14 +63,14 @@ __device__ inline typename EnsMap<T, S>::vt ens_row_product(const int32_t* __res
   return acc;
 }
 
-// Block-wide per-sample reduction of NQ quantities.  Each lane holds
-// vals[q][j] for samples sub*VS + j (j < VS); lanes with equal (lane % L)
-// hold the same samples.  Block totals land in part[blockIdx.x][q][s] in a
-// fixed order (deterministic).
-template <int S, int VS, int NQ>
-__device__ inline void block_partials(double (&vals)[NQ][VS], double* __restrict__ part) {
+// Block-wide per-sample reduction of NQ quantities over NW wavefronts.
+// Each lane holds vals[q][j] for samples sub*VS + j (j < VS); lanes with
+// equal (lane % L) hold the same samples.  The block totals are written to
+// dst[q][s] (one row of the partial array) in a fixed order.
+template <int S, int VS, int NQ, int NW>
+__device__ inline void block_partials(double (&vals)[NQ][VS], double* __restrict__ dst) {
   constexpr int L = S / VS;
-  __shared__ double red[kBlock / 64][NQ][S];
+  __shared__ double red[NW][NQ][S];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -84,8 +84,8 @@ __device__ inline void block_partials(double (&vals)[NQ][VS], double* __restrict
     const int q = threadIdx.x / S, e = threadIdx.x % S;
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) t += red[w][q][e];
-    part[((int64_t)blockIdx.x * NQ + q) * S + e] = t;
+    for (int w = 0; w < NW; ++w) t += red[w][q][e];
+    dst[q * S + e] = t;
   }
 }
 

@@ -50,6 +50,16 @@ class ens_cg_stat(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("rel_res", ctypes.c_double)]
 
 
+class ens_group(ctypes.Structure):
+    _fields_ = [("graph", ctypes.POINTER(ens_graph)), ("values", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("stats", ctypes.POINTER(ens_cg_stat))]
+
+
+class ens_batch_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
 _lib = None
 
 # (name, restype, argtypes)
@@ -76,6 +86,12 @@ _SIGS = [
     ("ens_scalar_cg", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _I32, _P, _SZ,
                              ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_relayout", _I32, [_P, _P, _I64, _I32, _I32, _P]),
+    ("ens_batch_workspace_bytes", _I32, [ctypes.POINTER(ens_group), _I32, _I32, ctypes.POINTER(ens_batch_opts),
+                                         ctypes.POINTER(_SZ)]),
+    ("ens_solve_batch", _I32, [ctypes.POINTER(ens_group), _I32, _I32, ctypes.POINTER(ens_batch_opts), _P, _SZ, _P]),
+    ("ens_batch_autotune", _I32, [_P, _I32, ctypes.POINTER(ens_problem), _P, _P, _I32, _P, _I32,
+                                  ctypes.POINTER(ens_batch_opts), ctypes.c_char_p, ctypes.POINTER(_I32),
+                                  ctypes.POINTER(_I32), _P, _P]),
     ("ens_stream_copy", _I32, [_P, _P, _SZ, _P]),
     ("ens_stream_triad", _I32, [_P, _P, _P, _D, _I64, _P]),
     ("ens_mlp_param_count", _I64, []),
@@ -446,3 +462,62 @@ def pod_reconstruct(Phi, c, mu=None, sd=None, x0=None, stream=None):
     _check(lib().ens_pod_reconstruct(_ptr(Phi), n, r, _ptr(c), _ptr(mu), _ptr(sd), s, _ptr(x0), _stream(stream)),
            "ens_pod_reconstruct")
     return x0
+
+
+# ------------------------------------------------------------------ batch
+
+
+def batch_opts(rtol=1e-8, max_iter=10000, check_every=16, tile=4, use_graph=True) -> ens_batch_opts:
+    return ens_batch_opts(rtol, max_iter, check_every, tile, int(use_graph))
+
+
+def solve_batch(groups, s, opts: ens_batch_opts | None = None, workspace=None, stream=None):
+    """groups: list of (Graph, values [nnz][s], b [n][s], x [n][s]).  Returns
+    (per-group stats lists, status, workspace)."""
+    if opts is None:
+        opts = batch_opts()
+    keep = []
+    arr = (ens_group * len(groups))()
+    stats = []
+    for i, (g, v, b, x) in enumerate(groups):
+        gc = g.c()
+        st = (ens_cg_stat * s)()
+        keep.append(gc)
+        stats.append(st)
+        arr[i] = ens_group(ctypes.pointer(gc), v.data_ptr(), b.data_ptr(), x.data_ptr(), st)
+    nb = _SZ()
+    _check(lib().ens_batch_workspace_bytes(arr, len(groups), s, ctypes.byref(opts), ctypes.byref(nb)),
+           "ens_batch_workspace_bytes")
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=groups[0][1].device)
+    rc = _check(lib().ens_solve_batch(arr, len(groups), s, ctypes.byref(opts), _ptr(workspace), workspace.numel(),
+                                      _stream(stream)), "ens_solve_batch", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
+    return [_stats_list(st, s) for st in stats], rc, workspace
+
+
+def batch_autotune(meshes, M, sigma, xi_host, opts: ens_batch_opts | None = None, s_cand=(8, 16, 32),
+                   tile_cand=(2, 4, 8), cache_path=None, want_scores=True, L=1.0, kappa0=1.0, f=1.0, stream=None):
+    """Pick (s, tile) for ens_solve_batch by solving 32 samples per mesh with
+    every candidate.  xi_host: [len(meshes)][32][M].  Returns (best_s,
+    best_tile, {(s, tile): samples/s} or None when served from the cache)."""
+    import numpy as np
+    if opts is None:
+        opts = batch_opts()
+    m = np.ascontiguousarray(meshes, dtype=np.int32)
+    xi = np.ascontiguousarray(xi_host, dtype=np.float64)
+    if xi.shape != (len(m), 32, M):
+        raise ValueError(f"xi_host must have shape ({len(m)}, 32, {M})")
+    sc = np.ascontiguousarray(s_cand, dtype=np.int32)
+    tc = np.ascontiguousarray(tile_cand, dtype=np.int32)
+    scores = np.zeros(len(sc) * len(tc)) if want_scores else None
+    bs, bt = _I32(), _I32()
+    prob = ens_problem(M, L, kappa0, sigma, f)
+    _check(lib().ens_batch_autotune(m.ctypes.data, len(m), ctypes.byref(prob), xi.ctypes.data, sc.ctypes.data,
+                                    len(sc), tc.ctypes.data, len(tc), ctypes.byref(opts),
+                                    None if cache_path is None else str(cache_path).encode(), ctypes.byref(bs),
+                                    ctypes.byref(bt), None if scores is None else scores.ctypes.data,
+                                    _stream(stream)), "ens_batch_autotune")
+    table = None
+    if scores is not None:
+        table = {(int(a), int(b)): float(scores[i * len(tc) + j]) for i, a in enumerate(sc) for j, b in enumerate(tc)}
+    return bs.value, bt.value, table

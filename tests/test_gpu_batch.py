@@ -1,0 +1,211 @@
+"""GPU parity of the batched multi-group solve and its autotuner.
+
+Each group of a batch is an ensemble of s samples on its own mesh; the batch
+runs the FP64 Jacobi-CG of every group in shared launches.  Bars are those of
+the single-ensemble solve: at each sample's iteration count the oracle's
+iterate agrees to relative 1e-9, the oracle's own stopping count is within
++-1, and the true residual meets the tolerance.  Graph replay and direct
+launches run the same kernels in the same order, so they agree bitwise.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import draw_xi, draw_vector
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1511_03703_amd import ens
+    ens.lib()
+    assert torch.cuda.is_available()
+    return ens
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+_GRAPHS = {}
+
+
+def _group(E, N, s, M, sigma, xi, x0=None):
+    key = (N, M)
+    if key not in _GRAPHS:
+        _GRAPHS[key] = (E.graph_build(N), E.kl_build(N, M))
+    g, kl = _GRAPHS[key]
+    v, _, b = E.assemble(g, kl, torch.as_tensor(xi, device=DEV), M, sigma)
+    x = torch.zeros_like(b) if x0 is None else torch.as_tensor(x0, device=DEV).clone()
+    return [g, v, b, x]
+
+
+def _oracle_check(orc, N, M, sigma, xi, x_gpu, stats, rtol, x0=None):
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    iters = np.array([st["iters"] for st in stats], np.int32)
+    xo, _, _, _ = orc.ens_pcg(rp, ci, ov, ob, x0=x0, fixed_iters=iters)
+    _, itt, _, _ = orc.ens_pcg(rp, ci, ov, ob, x0=x0, rtol=rtol)
+    true_res = orc.ens_true_residual(rp, ci, ov, ob, x_gpu)
+    for e in range(ov.shape[1]):
+        assert stats[e]["status"] == 0, (N, e, stats[e])
+        assert _rel(x_gpu[:, e], xo[:, e]) <= 1e-9, (N, e, _rel(x_gpu[:, e], xo[:, e]))
+        assert abs(int(itt[e]) - int(iters[e])) <= 1, (N, e, itt[e], iters[e])
+        assert true_res[e] <= rtol * (1 + 1e-6), (N, e, true_res[e])
+        assert abs(stats[e]["rel_res"] - true_res[e]) <= 1e-6 * rtol + 1e-3 * true_res[e]
+
+
+@pytest.mark.parametrize("tile", [2, 4, 8])
+@pytest.mark.parametrize("s", [8, 16, 32])
+def test_batch_matches_oracle(E, orc, s, tile):
+    """Uneven meshes in one batch; every group against the oracle."""
+    meshes, M, sigma, rtol = [6, 10, 4, 8, 10], 10, 0.3, 1e-10
+    xis = [draw_xi(500 + 7 * i + s, s, M) for i in range(len(meshes))]
+    groups = [_group(E, N, s, M, sigma, xi) for N, xi in zip(meshes, xis)]
+    stats, rc, _ = E.solve_batch(groups, s, E.batch_opts(rtol=rtol, check_every=5, tile=tile))
+    assert rc == E.ENS_OK
+    for (N, xi, gr, st) in zip(meshes, xis, groups, stats):
+        _oracle_check(orc, N, M, sigma, xi, _np(gr[3]), st, rtol)
+
+
+def test_batch_multi_segment_reductions(E, orc):
+    """Groups with more than 256 row tiles and more than 256 vector blocks, so
+    both reduction stages combine several segments per group."""
+    s, M, sigma, rtol = 32, 10, 0.2, 1e-10
+    meshes = [26, 5, 16]
+    xis = [draw_xi(600 + i, s, M) for i in range(len(meshes))]
+    groups = [_group(E, N, s, M, sigma, xi) for N, xi in zip(meshes, xis)]
+    stats, rc, _ = E.solve_batch(groups, s, E.batch_opts(rtol=rtol, check_every=16, tile=2))
+    assert rc == E.ENS_OK
+    for (N, xi, gr, st) in zip(meshes, xis, groups, stats):
+        _oracle_check(orc, N, M, sigma, xi, _np(gr[3]), st, rtol)
+
+
+def test_batch_graph_replay_equals_direct_launches(E):
+    s, M, sigma = 16, 10, 0.3
+    meshes = [12, 7, 9]
+    xis = [draw_xi(700 + i, s, M) for i in range(len(meshes))]
+    results = []
+    for use_graph in (1, 0, 1):
+        groups = [_group(E, N, s, M, sigma, xi) for N, xi in zip(meshes, xis)]
+        stats, rc, _ = E.solve_batch(groups, s, E.batch_opts(rtol=1e-10, check_every=7, tile=4,
+                                                             use_graph=use_graph))
+        assert rc == E.ENS_OK
+        results.append(([_np(g[3]) for g in groups], stats))
+    for xs, st in results[1:]:
+        for a, b in zip(xs, results[0][0]):
+            assert np.array_equal(a, b)
+        assert st == results[0][1]
+
+
+def test_batch_group_equals_single_ensemble_solve(E):
+    """A group of the batch reaches the single-ensemble solve's answer."""
+    s, M, sigma, rtol = 8, 10, 0.3, 1e-10
+    meshes = [11, 6]
+    xis = [draw_xi(800 + i, s, M) for i in range(len(meshes))]
+    groups = [_group(E, N, s, M, sigma, xi) for N, xi in zip(meshes, xis)]
+    stats, rc, _ = E.solve_batch(groups, s, E.batch_opts(rtol=rtol))
+    for gr, st in zip(groups, stats):
+        x1, st1, rc1 = E.cg(gr[0], gr[1], gr[2], opts=E.cg_opts(rtol=rtol))
+        assert rc1 == E.ENS_OK
+        xb, xs = _np(gr[3]), _np(x1)
+        for e in range(s):
+            assert abs(st[e]["iters"] - st1[e]["iters"]) <= 1
+            tol = 1e-10 if st[e]["iters"] == st1[e]["iters"] else 1e-8
+            assert _rel(xb[:, e], xs[:, e]) <= tol
+
+
+def test_batch_initial_guess_and_divergent_groups(E, orc):
+    """Nonzero initial guesses, and a group of constant-coefficient samples
+    that finishes long before the others."""
+    s, M, sigma, rtol = 16, 10, 0.3, 1e-10
+    meshes = [9, 9, 13]
+    xis = [draw_xi(900 + i, s, M) for i in range(len(meshes))]
+    xis[1] = xis[1] * 0.0
+    x0s = [draw_vector(910 + i, ((N + 1) ** 3, s), 0.0, 0.05) for i, N in enumerate(meshes)]
+    groups = [_group(E, N, s, M, sigma, xi, x0) for N, xi, x0 in zip(meshes, xis, x0s)]
+    stats, rc, _ = E.solve_batch(groups, s, E.batch_opts(rtol=rtol, check_every=4))
+    assert rc == E.ENS_OK
+    assert max(t["iters"] for t in stats[1]) < min(t["iters"] for t in stats[2])
+    for N, xi, x0, gr, st in zip(meshes, xis, x0s, groups, stats):
+        _oracle_check(orc, N, M, sigma, xi, _np(gr[3]), st, rtol, x0=x0)
+
+
+def test_batch_edge_cases(E):
+    s, M, sigma = 8, 10, 0.2
+    # group 0: zero right-hand side with a nonzero start -> x = 0, no iterations
+    g0 = _group(E, 5, s, M, sigma, draw_xi(1, s, M))
+    g0[2] = torch.zeros_like(g0[2])
+    g0[3] = torch.ones_like(g0[3])
+    # group 1: one NaN sample
+    xi1 = draw_xi(2, s, M)
+    xi1[3, 0] = np.nan
+    g1 = _group(E, 6, s, M, sigma, xi1)
+    # group 2: ordinary
+    g2 = _group(E, 7, s, M, sigma, draw_xi(3, s, M))
+    stats, rc, _ = E.solve_batch([g0, g1, g2], s, E.batch_opts(rtol=1e-10))
+    assert rc == E.ENS_W_NOT_CONVERGED
+    assert not _np(g0[3]).any()
+    assert all(t["iters"] == 0 and t["status"] == 0 for t in stats[0])
+    assert stats[1][3]["status"] == E.SAMPLE_NONFINITE
+    assert all(stats[1][e]["status"] == 0 for e in range(s) if e != 3)
+    assert all(t["status"] == 0 for t in stats[2])
+    # iteration cap: every sample stops at exactly max_iter
+    g3 = _group(E, 8, s, M, sigma, draw_xi(4, s, M))
+    stats, rc, _ = E.solve_batch([g3, g2], s, E.batch_opts(rtol=1e-14, max_iter=3, check_every=2))
+    assert rc == E.ENS_W_NOT_CONVERGED
+    for st in stats:
+        assert all(t["iters"] == 3 and t["status"] == E.SAMPLE_MAXITER for t in st)
+    # a 2^3-element mesh: one interior node, solved in one Jacobi-CG step
+    g4 = _group(E, 2, s, M, sigma, draw_xi(5, s, M))
+    stats, rc, _ = E.solve_batch([g4], s, E.batch_opts(rtol=1e-12))
+    assert rc == E.ENS_OK and all(t["iters"] == 1 for t in stats[0])
+
+
+def test_batch_rejects_bad_arguments(E):
+    s, M = 8, 10
+    g = _group(E, 4, s, M, 0.2, draw_xi(6, s, M))
+    with pytest.raises(E.EnsError) as ex:
+        E.solve_batch([g], 4, E.batch_opts())
+    assert ex.value.status == E.ENS_E_UNSUPPORTED
+    with pytest.raises(E.EnsError):
+        E.solve_batch([g], s, E.batch_opts(tile=3))
+    # a workspace below ens_batch_workspace_bytes is refused before any launch
+    small = torch.empty(256, dtype=torch.uint8, device=DEV)
+    gc = g[0].c()
+    st = (E.ens_cg_stat * s)()
+    arr = (E.ens_group * 1)()
+    arr[0] = E.ens_group(ctypes.pointer(gc), g[1].data_ptr(), g[2].data_ptr(), g[3].data_ptr(), st)
+    o = E.batch_opts()
+    need = ctypes.c_size_t()
+    assert E.lib().ens_batch_workspace_bytes(arr, 1, s, ctypes.byref(o), ctypes.byref(need)) == E.ENS_OK
+    assert need.value > small.numel()
+    rc = E.lib().ens_solve_batch(arr, 1, s, ctypes.byref(o), ctypes.c_void_p(small.data_ptr()), small.numel(), None)
+    assert rc == E.ENS_E_NOMEM
+
+
+def test_autotuner_choice_and_cache(E, tmp_path):
+    meshes, M, sigma = [6, 10], 10, 0.2
+    xi = np.stack([draw_xi(1100 + i, 32, M) for i in range(len(meshes))])
+    cache = tmp_path / "tune.txt"
+    opts = E.batch_opts(rtol=1e-8)
+    s, tile, scores = E.batch_autotune(meshes, M, sigma, xi, opts=opts, cache_path=cache)
+    assert (s, tile) in scores and len(scores) == 9
+    assert all(v > 0 for v in scores.values())
+    assert scores[(s, tile)] == max(scores.values())
+    s2, tile2, none = E.batch_autotune(meshes, M, sigma, xi, opts=opts, cache_path=cache, want_scores=False)
+    assert (s2, tile2, none) == (s, tile, None)
+    # the chosen configuration solves the tuning samples to tolerance
+    groups = [_group(E, N, s, M, sigma, xi[i, :s]) for i, N in enumerate(meshes)]
+    stats, rc, _ = E.solve_batch(groups, s, E.batch_opts(rtol=1e-8, tile=tile))
+    assert rc == E.ENS_OK
