@@ -361,6 +361,22 @@ def mlp_param_count() -> int:
     return int(lib().ens_mlp_param_count())
 
 
+def mlp_init(seed: int, device="cuda") -> torch.Tensor:
+    """Seeded FP32 parameters: every weight and bias of a layer uniform in
+    +-1/sqrt(fan_in).  Layout W1 [256][10], b1 [256], W2 [256][256], b2 [256],
+    W3 [32][256], b3 [32]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for rows, fan_in in ((MLP_HID, MLP_IN), (MLP_HID, MLP_HID), (MLP_OUT, MLP_HID)):
+        lim = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-lim, lim, rows * fan_in))
+        parts.append(rng.uniform(-lim, lim, rows))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == mlp_param_count()
+    return torch.as_tensor(p, device=device)
+
+
 def _mlp_ws(batch, device):
     b = _SZ()
     _check(lib().ens_mlp_workspace_bytes(batch, ctypes.byref(b)), "ens_mlp_workspace_bytes")
@@ -471,9 +487,11 @@ def batch_opts(rtol=1e-8, max_iter=10000, check_every=16, tile=4, use_graph=True
     return ens_batch_opts(rtol, max_iter, check_every, tile, int(use_graph))
 
 
-def solve_batch(groups, s, opts: ens_batch_opts | None = None, workspace=None, stream=None):
+def solve_batch(groups, s, opts: ens_batch_opts | None = None, workspace=None, stream=None,
+                strict_workspace=False):
     """groups: list of (Graph, values [nnz][s], b [n][s], x [n][s]).  Returns
-    (per-group stats lists, status, workspace)."""
+    (per-group stats lists, status, workspace).  A workspace smaller than
+    required is replaced by a new one, or refused with strict_workspace."""
     if opts is None:
         opts = batch_opts()
     keep = []
@@ -488,6 +506,8 @@ def solve_batch(groups, s, opts: ens_batch_opts | None = None, workspace=None, s
     nb = _SZ()
     _check(lib().ens_batch_workspace_bytes(arr, len(groups), s, ctypes.byref(opts), ctypes.byref(nb)),
            "ens_batch_workspace_bytes")
+    if workspace is not None and workspace.numel() < nb.value and strict_workspace:
+        raise EnsError(ENS_E_NOMEM, "solve_batch", f"workspace of {workspace.numel()} bytes, {nb.value} required")
     if workspace is None or workspace.numel() < nb.value:
         workspace = torch.empty(nb.value, dtype=torch.uint8, device=groups[0][1].device)
     rc = _check(lib().ens_solve_batch(arr, len(groups), s, ctypes.byref(opts), _ptr(workspace), workspace.numel(),

@@ -67,6 +67,7 @@ BATCH_MESHES = (32, 48, 64, 96)
 BATCH_GROUPS = 256
 BATCH_MESH_SEED = 1003
 BATCH_XI_SEED = 1004
+BATCH_TUNE_SEED = 1010   # autotuner trial samples, one draw per mesh size
 BATCH_SIGMA = 0.2
 BATCH_M = 10
 BATCH_RTOL = 1e-8
