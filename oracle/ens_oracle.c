@@ -583,6 +583,47 @@ int orc_ens_pcg(int64_t n, int s, const int32_t *row_ptr, const int32_t *col_idx
   return rc;
 }
 
+/* Coupled ensemble solve (the paper's solve of the whole commuted system,
+ * Sec. 3.4 and Sec. 3.7): the ensemble inner products are summed over the
+ * samples, so CG runs on the block-diagonal system blockdiag(A_1 .. A_s) of
+ * Eq. kron_sys as ONE system, with one alpha and beta for all samples and one
+ * stopping test on the norms over all samples.  Written out literally: the
+ * block-diagonal CRS matrix (sample-major: row e*n + i) is built and the
+ * scalar Jacobi-PCG above is run on it.  x, b [n][s] (commuted layout);
+ * iters/rel_res/status describe the whole system.                         */
+int orc_ens_pcg_coupled(int64_t n, int s, const int32_t *row_ptr, const int32_t *col_idx,
+                        const double *values, const double *b, double *x, double rtol, int max_iter,
+                        int fixed_iters, int32_t *iters, double *rel_res, int32_t *status) {
+  int64_t nnz = row_ptr[n];
+  int64_t N = n * s, NZ = nnz * s;
+  if (s < 1 || N > INT32_MAX || NZ > INT32_MAX) return ORC_E_ARG;
+  int32_t *rp = calloc((size_t)(N + 1), sizeof(int32_t)), *ci = calloc((size_t)NZ + 1, sizeof(int32_t));
+  double *v = calloc((size_t)NZ + 1, sizeof(double));
+  double *bb = calloc((size_t)N + 1, sizeof(double)), *xx = calloc((size_t)N + 1, sizeof(double));
+  if (!rp || !ci || !v || !bb || !xx) {
+    free(rp); free(ci); free(v); free(bb); free(xx);
+    return ORC_E_NOMEM;
+  }
+  rp[0] = 0;
+  for (int e = 0; e < s; ++e)
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t row = e * n + i;
+      rp[row + 1] = (int32_t)(rp[row] + (row_ptr[i + 1] - row_ptr[i]));
+      int64_t o = rp[row];
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k, ++o) {
+        ci[o] = (int32_t)(e * n + col_idx[k]);
+        v[o] = values[k * s + e];
+      }
+      bb[row] = b[i * s + e];
+      xx[row] = x[i * s + e];
+    }
+  int rc = orc_pcg(N, rp, ci, v, bb, xx, rtol, max_iter, fixed_iters, iters, rel_res, status);
+  for (int e = 0; e < s; ++e)
+    for (int64_t i = 0; i < n; ++i) x[i * s + e] = xx[e * n + i];
+  free(rp); free(ci); free(v); free(bb); free(xx);
+  return rc;
+}
+
 /* One complete sample from scratch: graph, KL coefficient, assembly and
  * Jacobi-CG from a zero guess.  x [n] out.  Used for full-size checks and
  * as the CPU baseline.                                                    */

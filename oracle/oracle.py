@@ -64,6 +64,8 @@ def lib():
         L.orc_ens_spmv.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_pcg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.orc_ens_pcg.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, dbl, ctypes.c_int, vp, vp, vp, vp]
+        L.orc_ens_pcg_coupled.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int,
+                                          vp, vp, vp]
         L.orc_solve_sample.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, dbl,
                                        ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_solve_samples.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int,
@@ -231,6 +233,20 @@ def ens_pcg(rp, ci, vals, b, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=No
     _check(lib().orc_ens_pcg(n, s, _p(rp), _p(ci), _p(_f64(vals)), _p(_f64(b)), _p(x), rtol, max_iter,
                              None if fi is None else _p(fi), _p(it), _p(rr), _p(st)))
     return x, it, rr, st
+
+
+def ens_pcg_coupled(rp, ci, vals, b, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=-1):
+    """Coupled ensemble CG (one system over all samples).  Returns (x [n][s],
+    iters, rel_res over all samples, status)."""
+    n = rp.shape[0] - 1
+    s = vals.shape[1]
+    x = np.zeros((n, s)) if x0 is None else _f64(x0).copy()
+    it = np.zeros(1, np.int32)
+    rr = np.zeros(1)
+    st = np.zeros(1, np.int32)
+    _check(lib().orc_ens_pcg_coupled(n, s, _p(rp), _p(ci), _p(_f64(vals)), _p(_f64(b)), _p(x), rtol, max_iter,
+                                     int(fixed_iters), _p(it), _p(rr), _p(st)))
+    return x, int(it[0]), float(rr[0]), int(st[0])
 
 
 def solve_samples(N, M, L, kappa0, sigma, fconst, xi, rtol, max_iter=10000, want_x=True, timing=False):

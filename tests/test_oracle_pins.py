@@ -512,3 +512,62 @@ def test_start_already_converged(orc):
     xs = orc.pcg(rp, ci, vals, rhs, rtol=1e-14)[0]
     x, it, rel, st = orc.pcg(rp, ci, vals, rhs, x0=xs, rtol=1e-8)
     assert it == 0 and st == orc.CONVERGED and np.array_equal(x, xs)
+
+
+# ----------------------------------------------- coupled ensemble CG (oracle)
+
+def _block_system(orc, N, s, sigma, seed):
+    rp, ci = orc.graph(N)
+    xi = draw_xi(seed, s, 10)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, 10, 1.0, 1.0, sigma, 1.0, xi)
+    blocks = [orc.crs_to_dense(rp, ci, np.ascontiguousarray(ov[:, e])) for e in range(s)]
+    n = rp.shape[0] - 1
+    A = np.zeros((n * s, n * s))
+    for e, Ae in enumerate(blocks):
+        A[e * n:(e + 1) * n, e * n:(e + 1) * n] = Ae
+    b = ob.T.ravel()  # sample-major
+    return rp, ci, ov, ob, A, b
+
+
+def test_coupled_cg_iterates_are_block_krylov_galerkin(orc):
+    # Coupled CG is CG on blockdiag(A_1..A_s): k steps from 0 give the
+    # Galerkin projection onto the Jacobi-preconditioned Krylov space of the
+    # whole block system (one space for all samples, not one per sample).
+    N, s = 3, 3
+    rp, ci, ov, ob, A, b = _block_system(orc, N, s, 0.3, 31)
+    n = rp.shape[0] - 1
+    Dinv = 1.0 / np.diag(A)
+    v = Dinv * b
+    basis = []
+    for k in range(1, 7):
+        basis.append(v)
+        Q, _ = np.linalg.qr(np.array(basis).T)
+        xg = Q @ np.linalg.solve(Q.T @ A @ Q, Q.T @ b)
+        xk, it, _, _ = orc.ens_pcg_coupled(rp, ci, ov, ob, fixed_iters=k)
+        assert it == k
+        np.testing.assert_allclose(xk.T.ravel(), xg, rtol=0, atol=1e-12 * np.abs(xg).max())
+        v = Dinv * (A @ v)
+    # differs from the per-sample iteration, whose Krylov spaces are separate
+    xs, _, _, _ = orc.ens_pcg(rp, ci, ov, ob, fixed_iters=np.full(s, 3, np.int32))
+    xc, _, _, _ = orc.ens_pcg_coupled(rp, ci, ov, ob, fixed_iters=3)
+    assert np.abs(xs - xc).max() > 1e-8 * np.abs(xs).max()
+    # converged: every block solved; total residual within tolerance
+    x, it, rel, st = orc.ens_pcg_coupled(rp, ci, ov, ob, rtol=1e-13)
+    assert st == orc.CONVERGED and rel <= 1e-13 * (1 + 1e-6)
+    xd = np.linalg.solve(A, b)
+    assert np.linalg.norm(x.T.ravel() - xd) <= 1e-11 * np.linalg.norm(xd)
+    assert 1 <= it <= n * s
+
+
+def test_coupled_cg_of_identical_samples_is_the_scalar_cg(orc):
+    # with s equal samples every ensemble sum is s times the sample's own, so
+    # alpha, beta and the stopping test are those of the one-sample CG
+    N, s = 6, 4
+    rp, ci = orc.graph(N)
+    xi = np.repeat(draw_xi(32, 1, 10), s, axis=0)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, 10, 1.0, 1.0, 0.3, 1.0, xi)
+    x1, it1, rel1, _ = orc.pcg(rp, ci, np.ascontiguousarray(ov[:, 0]), np.ascontiguousarray(ob[:, 0]), rtol=1e-10)
+    xc, itc, relc, stc = orc.ens_pcg_coupled(rp, ci, ov, ob, rtol=1e-10)
+    assert itc == it1 and stc == orc.CONVERGED
+    for e in range(s):
+        np.testing.assert_allclose(xc[:, e], x1, rtol=0, atol=1e-12 * np.abs(x1).max())
