@@ -232,6 +232,14 @@ def run_solve(args):
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
         iters_fp64 = [s["iters"] for s in st64]
+        xcp = torch.zeros_like(x)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, stcp, _ = ens.cg(g, vals, rhs, x=xcp, opts=ens.cg_opts(rtol=w.rtol, check_every=args.check_every,
+                                                                 coupled=True))
+        torch.cuda.synchronize()
+        tcp = time.perf_counter() - t1
+        del xcp
         # s one-sample solves on the same GPU (sample-major layout)
         vsm = ens.relayout(vals, True)
         bsm = ens.relayout(rhs, True)
@@ -247,7 +255,19 @@ def run_solve(args):
             ts = time.perf_counter() - t2
             if best is None or ts < best[0]:
                 best = (ts, lanes, [s["iters"] for s in sst])
-        del vsm, bsm
+        conc = None
+        for streams in (4, 8):
+            xsm = torch.zeros_like(bsm)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            _, sst, _ = ens.scalar_cg_concurrent(g, vsm, bsm, xsm,
+                                                 opts=ens.cg_opts(rtol=w.rtol, check_every=args.check_every),
+                                                 lanes_per_row=best[1], streams=streams)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t2
+            if conc is None or ts < conc[0]:
+                conc = (ts, streams)
+        del vsm, bsm, xsm
         # standalone SpMV bandwidth, ensemble vs one-sample kernel
         V = v32 if w.mixed else vals
         xv = torch.rand((w.n, w.s), dtype=V.dtype, device=dev)
@@ -279,10 +299,20 @@ def run_solve(args):
                                           "reference": "GPU FP64 ensemble Jacobi-CG to 1e-12"},
             "fp64_ensemble_cg": {"seconds": round(t64, 4), "samples_per_s": round(w.s / t64, 3),
                                  "iters": iters_fp64},
+            "fp64_coupled_ensemble_cg": {"seconds": round(tcp, 4), "samples_per_s": round(w.s / tcp, 3),
+                                         "iters": stcp[0]["iters"],
+                                         "max_sample_rel_res": max(t["rel_res"] for t in stcp),
+                                         "note": "one alpha/beta for the ensemble; stop on the residual over all "
+                                                 "samples"},
             "scalar_gpu_fp64": {"seconds": round(best[0], 4), "samples_per_s": round(w.s / best[0], 3),
                                 "lanes_per_row": best[1], "iters": best[2],
                                 "speedup_mixed_ensemble": round((w.s / elapsed * args.steps) / (w.s / best[0]), 3),
                                 "speedup_fp64_ensemble": round(best[0] / t64, 3)},
+            "scalar_gpu_fp64_concurrent": {"seconds": round(conc[0], 4), "samples_per_s": round(w.s / conc[0], 3),
+                                           "streams": conc[1], "lanes_per_row": best[1],
+                                           "speedup_mixed_ensemble": round((w.s / elapsed * args.steps) /
+                                                                           (w.s / conc[0]), 3),
+                                           "speedup_fp64_ensemble": round(conc[0] / t64, 3)},
             "spmv": {"ensemble_ms": round(t_ens, 5), "ensemble_GBs": round(b_ens / t_ens / 1e6, 1),
                      "ensemble_GFLOPs": round(2.0 * w.nnz * w.s / t_ens / 1e6, 1),
                      "scalar_ms": round(t_sc, 5), "scalar_GBs": round(b_sc / t_sc / 1e6, 1),

@@ -168,7 +168,14 @@ typedef struct {
   int32_t max_outer;      /* mixed: cap on refinement steps (<=0: 10)         */
   int32_t check_every;    /* iterations between polls of the device done flag
                              (<=0: 16)                                       */
-  int32_t reserved;
+  int32_t coupled;        /* 0: per-sample scalars and masks (default);
+                             1: the coupled solve of the whole commuted
+                             system (Sec. 3.4, Sec. 3.7): inner products are
+                             summed over the ensemble, so every sample takes
+                             the same alpha, beta and iteration count, and
+                             the test is |r| <= rtol |b| over all samples
+                             together.  FP64 only (mixed must be 0); stats
+                             still report each sample's true residual. */
 } ens_cg_opts;
 
 typedef struct {
@@ -271,6 +278,18 @@ ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, const ens_probl
                               const int32_t* s_cand, int32_t ns, const int32_t* tile_cand, int32_t nt,
                               const ens_batch_opts* base, const char* cache_path, int32_t* best_s,
                               int32_t* best_tile, double* scores, hipStream_t stream);
+
+/* The one-sample baseline with up to `streams` (1..32) solves in flight at
+ * once, each on its own library stream (default priority) with its own
+ * workspace slice, so that independent solves overlap on the device as they
+ * would when run side by side.  Same arguments, layouts and per-sample
+ * results as ens_scalar_cg; workspace from
+ * ens_scalar_cg_concurrent_workspace_bytes.  Ordered after earlier work on
+ * `stream` and before later work on it; synchronises. */
+ens_status ens_scalar_cg_concurrent_workspace_bytes(const ens_graph* graph, int32_t streams, size_t* bytes);
+ens_status ens_scalar_cg_concurrent(const ens_graph* graph, int32_t s, const double* values, const double* b,
+                                    double* x, const ens_cg_opts* opts, int32_t lanes_per_row, int32_t streams,
+                                    void* workspace, size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream);
 
 /* Layout change between the commuted [rows][s] and the sample-major
  * [s][rows] arrangement (Eqs. kron_sys_commuted and kron_sys), FP64,

@@ -33,7 +33,7 @@ DeviceCtx* device_ctx() {
   if (!g_ctx[dev]) {
     DeviceCtx* c = new DeviceCtx();
     c->device = dev;
-    if (hipHostMalloc((void**)&c->host_flag, 64, hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void**)&c->host_flag, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&c->work_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
@@ -43,6 +43,22 @@ DeviceCtx* device_ctx() {
     g_ctx[dev] = c;
   }
   return g_ctx[dev];
+}
+
+bool ensure_side_streams(DeviceCtx* c, int count) {
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  while ((int)c->side.size() < count) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(s);
+      return false;
+    }
+    c->side.push_back(s);
+    c->side_ev.push_back(e);
+  }
+  return true;
 }
 
 // ------------------------------------------------------------- profiling ---

@@ -382,18 +382,19 @@ static ens_status cg_mixed(const ens_graph* g, const double* vals, const float* 
   return ENS_OK;
 }
 
+// One-sample Jacobi-CG in three phases so that several independent solves
+// can be interleaved on their own streams: set-up (control block, D^-1,
+// r = b - A x, first direction), iterations k0+1..k1, true residual.
 template <int G>
-static ens_status cg_scalar_one(const ens_graph* g, const double* vals, const double* b, double* x,
-                                const ens_cg_opts& o, Work& w, hipStream_t st) {
+static void scalar_setup(const ens_graph* g, const double* vals, const double* b, double* x, const ens_cg_opts& o,
+                         const Work& w, hipStream_t st) {
   double* r = (double*)w.vec[0];
   double* p = (double*)w.vec[1];
-  double* q = (double*)w.vec[2];
   double* dinv = (double*)w.vec[3];
   const int64_t n = g->n;
   const unsigned rb = grid_for(n, kBlock / G);
-  const unsigned vb = grid_for(n, (int64_t)kBlock * kU);
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, w.ctl, o.rtol, o.inner_rtol, o.max_iter,
-                     o.inner_max_iter, o.max_outer, 0);
+                     o.inner_max_iter, o.max_outer, 0, 0);
   hipLaunchKernelGGL((k_diag_inv<double, 1>), dim3(grid_for(n, 256)), dim3(256), 0, st, g->n, g->row_ptr,
                      g->col_idx, vals, dinv);
   hipLaunchKernelGGL(k_residual_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
@@ -401,31 +402,117 @@ static ens_status cg_scalar_one(const ens_graph* g, const double* vals, const do
   reduce<1, 2>(w, rb, OP_START, 0, 0, st);
   hipLaunchKernelGGL(k_zero_where<1>, dim3(grid_for(n, 256 * 8)), dim3(kBlock), 0, st, n, x, w.ctl);
   cg_start<double, 1>(n, r, dinv, p, (double*)nullptr, w, st);
+}
+
+template <int G>
+static void scalar_iters(const ens_graph* g, const double* vals, double* x, const Work& w, int k0, int k1,
+                         hipStream_t st) {
+  double* r = (double*)w.vec[0];
+  double* p = (double*)w.vec[1];
+  double* q = (double*)w.vec[2];
+  double* dinv = (double*)w.vec[3];
+  const int64_t n = g->n;
+  const unsigned rb = grid_for(n, kBlock / G);
+  const unsigned vb = grid_for(n, (int64_t)kBlock * kU);
+  for (int k = k0 + 1; k <= k1; ++k) {
+    prof_begin(ENS_K_SCALAR_SPMV, st);
+    hipLaunchKernelGGL(k_cg_spmv_dot_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals,
+                       p, q, w.ctl, w.part);
+    prof_end(ENS_K_SCALAR_SPMV, st, (double)g->nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n);
+    reduce<1, 1>(w, rb, OP_ALPHA, 0, 1, st);
+    hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(vb), dim3(kBlock), 0, st, n, x, p, q, r, dinv, w.ctl, w.part);
+    reduce<1, 2>(w, vb, OP_UPDATE, k, 1, st);
+    hipLaunchKernelGGL((k_cg_pupdate<double, 1>), dim3(vb), dim3(kBlock), 0, st, n, r, dinv, p, w.ctl);
+  }
+}
+
+template <int G>
+static void scalar_finish(const ens_graph* g, const double* vals, const double* b, const double* x, const Work& w,
+                          hipStream_t st) {
+  const unsigned rb = grid_for(g->n, kBlock / G);
+  hipLaunchKernelGGL(k_residual_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
+                     (double*)nullptr, w.part);
+  reduce<1, 2>(w, rb, OP_TRUE, 0, 0, st);
+}
+
+template <int G>
+static ens_status cg_scalar_one(const ens_graph* g, const double* vals, const double* b, double* x,
+                                const ens_cg_opts& o, Work& w, hipStream_t st) {
+  scalar_setup<G>(g, vals, b, x, o, w, st);
   ENS_LAUNCH_CHECK();
   for (int k0 = 0; k0 < o.max_iter; k0 += o.check_every) {
     const int k1 = k0 + o.check_every < o.max_iter ? k0 + o.check_every : o.max_iter;
-    for (int k = k0 + 1; k <= k1; ++k) {
-      prof_begin(ENS_K_SCALAR_SPMV, st);
-      hipLaunchKernelGGL(k_cg_spmv_dot_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx,
-                         vals, p, q, w.ctl, w.part);
-      prof_end(ENS_K_SCALAR_SPMV, st, (double)g->nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n);
-      reduce<1, 1>(w, rb, OP_ALPHA, 0, 1, st);
-      hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(vb), dim3(kBlock), 0, st, n, x, p, q, r, dinv, w.ctl,
-                         w.part);
-      reduce<1, 2>(w, vb, OP_UPDATE, k, 1, st);
-      hipLaunchKernelGGL((k_cg_pupdate<double, 1>), dim3(vb), dim3(kBlock), 0, st, n, r, dinv, p, w.ctl);
-    }
+    scalar_iters<G>(g, vals, x, w, k0, k1, st);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
     ens_status rc = poll_active(w.ctl, false, st, &act);
     if (rc != ENS_OK) return rc;
     if (act == 0) break;
   }
-  hipLaunchKernelGGL(k_residual_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
-                     (double*)nullptr, w.part);
-  reduce<1, 2>(w, rb, OP_TRUE, 0, 0, st);
+  scalar_finish<G>(g, vals, b, x, w, st);
   ENS_LAUNCH_CHECK();
   return ENS_OK;
+}
+
+// Up to `ns` one-sample solves at a time, each on its own stream with its
+// own workspace slice; the host launches a chunk of iterations for every
+// unfinished solve, then polls all of them once.
+template <int G>
+static ens_status cg_scalar_concurrent(const ens_graph* g, int s, const double* values, const double* b, double* x,
+                                       const ens_cg_opts& o, int ns, char* ws, size_t slice, ens_cg_stat* stats,
+                                       hipStream_t user) {
+  DeviceCtx* cx = device_ctx();
+  if (!cx || !ensure_side_streams(cx, ns)) {
+    set_error("could not create the side streams");
+    return ENS_E_HIP;
+  }
+  const int64_t n = g->n, nnz = g->nnz;
+  std::vector<Work> w(ns);
+  for (int i = 0; i < ns; ++i) ws_layout(n, 1, false, &w[i], ws + (size_t)i * slice);
+  ENS_HIP_TRY(hipEventRecord(cx->ev_in, user));
+  for (int i = 0; i < ns; ++i) ENS_HIP_TRY(hipStreamWaitEvent(cx->side[i], cx->ev_in, 0));
+  ens_status agg = ENS_OK;
+  for (int e0 = 0; e0 < s; e0 += ns) {
+    const int m = s - e0 < ns ? s - e0 : ns;
+    std::vector<int> active;
+    for (int i = 0; i < m; ++i) {
+      const int e = e0 + i;
+      scalar_setup<G>(g, values + (int64_t)e * nnz, b + (int64_t)e * n, x + (int64_t)e * n, o, w[i], cx->side[i]);
+      active.push_back(i);
+    }
+    ENS_LAUNCH_CHECK();
+    for (int k0 = 0; k0 < o.max_iter && !active.empty(); k0 += o.check_every) {
+      const int k1 = k0 + o.check_every < o.max_iter ? k0 + o.check_every : o.max_iter;
+      for (int i : active) {
+        const int e = e0 + i;
+        scalar_iters<G>(g, values + (int64_t)e * nnz, x + (int64_t)e * n, w[i], k0, k1, cx->side[i]);
+        ENS_HIP_TRY(hipMemcpyAsync(cx->host_flag + i, &w[i].ctl->n_active, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   cx->side[i]));
+      }
+      ENS_LAUNCH_CHECK();
+      for (int i : active) ENS_HIP_TRY(hipStreamSynchronize(cx->side[i]));
+      prof_collect();
+      std::vector<int> still;
+      for (int i : active)
+        if (cx->host_flag[i] != 0) still.push_back(i);
+      active.swap(still);
+    }
+    for (int i = 0; i < m; ++i) {
+      const int e = e0 + i;
+      scalar_finish<G>(g, values + (int64_t)e * nnz, b + (int64_t)e * n, x + (int64_t)e * n, w[i], cx->side[i]);
+    }
+    ENS_LAUNCH_CHECK();
+    for (int i = 0; i < m; ++i) {
+      ens_status st = read_stats(w[i].ctl, 1, &stats[e0 + i], cx->side[i]);
+      if (st == ENS_W_NOT_CONVERGED) agg = st;
+      else if (st != ENS_OK) return st;
+    }
+  }
+  for (int i = 0; i < ns; ++i) {
+    ENS_HIP_TRY(hipEventRecord(cx->side_ev[i], cx->side[i]));
+    ENS_HIP_TRY(hipStreamWaitEvent(user, cx->side_ev[i], 0));
+  }
+  return agg;
 }
 
 ens_status check_graph(const ens_graph* g);
@@ -469,6 +556,10 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
   ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
   ENS_ARG_CHECK(opts->rtol >= 0.0, "rtol must be >= 0");
   ENS_ARG_CHECK(!opts->mixed || (values32 && aligned16(values32)), "mixed mode needs values32");
+  if (opts->mixed && opts->coupled) {
+    set_error("coupled CG is implemented for FP64 (mixed = 0) only");
+    return ENS_E_UNSUPPORTED;
+  }
   if (!supported_s(s)) {
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
@@ -487,7 +578,7 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
   ws_layout(graph->n, s, mixed, &w, (char*)workspace);
   ens_cg_opts o = normalized(opts);
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, w.ctl, o.rtol, o.inner_rtol, o.max_iter,
-                     o.inner_max_iter, o.max_outer, (int)mixed);
+                     o.inner_max_iter, o.max_outer, (int)mixed, o.coupled ? 1 : 0);
   ENS_LAUNCH_CHECK();
   switch (s) {
 #define ENS_CG_CASE(SS)                                                                                      \
@@ -505,6 +596,44 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
   return read_stats(w.ctl, s, stats, stream);
 }
 
+ens_status ens_scalar_cg_concurrent_workspace_bytes(const ens_graph* graph, int32_t streams, size_t* bytes) {
+  ens_status st = check_graph(graph);
+  if (st != ENS_OK) return st;
+  ENS_ARG_CHECK(bytes && streams >= 1 && streams <= kMaxSideStreams, "streams must be in 1..32");
+  *bytes = (size_t)streams * ws_layout(graph->n, 1, false, nullptr, nullptr);
+  return ENS_OK;
+}
+
+ens_status ens_scalar_cg_concurrent(const ens_graph* graph, int32_t s, const double* values, const double* b,
+                                    double* x, const ens_cg_opts* opts, int32_t lanes_per_row, int32_t streams,
+                                    void* workspace, size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream) {
+  ens_status st = check_graph(graph);
+  if (st != ENS_OK) return st;
+  ENS_ARG_CHECK(opts && stats && s >= 1, "bad arguments");
+  ENS_ARG_CHECK(streams >= 1 && streams <= kMaxSideStreams, "streams must be in 1..32");
+  ENS_ARG_CHECK(!opts->mixed && !opts->coupled, "the scalar baseline is per-sample FP64");
+  ENS_ARG_CHECK(values && b && x && workspace, "null device pointer");
+  ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
+  if (graph->n == 0) {
+    for (int e = 0; e < s; ++e) stats[e] = ens_cg_stat{0, 0, ENS_SAMPLE_CONVERGED, 0, 0.0};
+    return ENS_OK;
+  }
+  const size_t slice = ws_layout(graph->n, 1, false, nullptr, nullptr);
+  const int ns = streams < s ? streams : s;
+  if (ws_bytes < (size_t)ns * slice) {
+    set_error("workspace of %zu bytes is smaller than the %zu required", ws_bytes, (size_t)ns * slice);
+    return ENS_E_NOMEM;
+  }
+  ens_cg_opts o = normalized(opts);
+  switch (lanes_per_row > 0 ? lanes_per_row : 8) {
+    case 4: return cg_scalar_concurrent<4>(graph, s, values, b, x, o, ns, (char*)workspace, slice, stats, stream);
+    case 8: return cg_scalar_concurrent<8>(graph, s, values, b, x, o, ns, (char*)workspace, slice, stats, stream);
+    case 16: return cg_scalar_concurrent<16>(graph, s, values, b, x, o, ns, (char*)workspace, slice, stats, stream);
+    case 32: return cg_scalar_concurrent<32>(graph, s, values, b, x, o, ns, (char*)workspace, slice, stats, stream);
+    default: set_error("lanes_per_row %d not supported", lanes_per_row); return ENS_E_ARG;
+  }
+}
+
 ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,
                          const ens_cg_opts* opts, int32_t lanes_per_row, void* workspace, size_t ws_bytes,
                          ens_cg_stat* stats, hipStream_t stream) {
@@ -512,6 +641,7 @@ ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values
   if (st != ENS_OK) return st;
   ENS_ARG_CHECK(opts && stats && s >= 1, "bad arguments");
   ENS_ARG_CHECK(!opts->mixed, "the scalar baseline is FP64 only");
+  ENS_ARG_CHECK(!opts->coupled, "the scalar baseline solves samples independently (coupled must be 0)");
   ENS_ARG_CHECK(values && b && x && workspace, "null device pointer");
   ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
   const size_t need = ws_layout(graph->n, 1, false, nullptr, nullptr);

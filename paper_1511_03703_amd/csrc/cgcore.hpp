@@ -21,16 +21,29 @@ struct Ctl {
   int32_t n_active, n_oactive;
   double rtol, inner_rtol;
   int32_t max_iter, inner_max_iter, max_outer, mixed;
+  int32_t coupled, pad;
   double tot[2 * kMaxS];
 };
 
 // ------------------------------------------------------------- finalize ---
 
+// Coupled mode (the solve of the whole commuted system, Sec. 3.4 and 3.7):
+// the CG scalars use the ensemble sums of the inner products, added here in
+// sample order by every thread alike, so all samples take the same alpha,
+// beta and stopping decision; true residuals stay per sample.
 template <int S>
 __device__ void finalize(Ctl* c, int op, int arg) {
   const int e = threadIdx.x;
   if (e < S) {
-    const double t0 = c->tot[e], t1 = c->tot[S + e];
+    double t0 = c->tot[e], t1 = c->tot[S + e];
+    if (c->coupled && op != OP_TRUE && op != OP_OUTER) {
+      t0 = 0.0;
+      t1 = 0.0;
+      for (int j = 0; j < S; ++j) {
+        t0 += c->tot[j];
+        t1 += c->tot[S + j];
+      }
+    }
     switch (op) {
       case OP_START: {  // t0 = |b - A x0|^2, t1 = |b|^2
         c->bnorm2[e] = t1;
@@ -180,7 +193,7 @@ struct VecMap {
 };
 
 static __global__ void k_ctl_init(Ctl* c, double rtol, double inner_rtol, int max_iter, int inner_max_iter,
-                                  int max_outer, int mixed) {
+                                  int max_outer, int mixed, int coupled) {
   if (threadIdx.x == 0) {
     c->rtol = rtol;
     c->inner_rtol = inner_rtol;
@@ -188,6 +201,7 @@ static __global__ void k_ctl_init(Ctl* c, double rtol, double inner_rtol, int ma
     c->inner_max_iter = inner_max_iter;
     c->max_outer = max_outer;
     c->mixed = mixed;
+    c->coupled = coupled;
     c->n_active = 0;
     c->n_oactive = 0;
   }

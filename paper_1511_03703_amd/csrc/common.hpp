@@ -7,6 +7,8 @@
 // entry are spread over L = s/V consecutive lanes of a 64-wide wavefront.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
@@ -80,13 +82,21 @@ inline bool supported_s(int s) { return s == 4 || s == 8 || s == 16 || s == 32; 
 constexpr int kBlock = 256;
 
 // Per-device pinned scalars and events kept for the life of the process.
+constexpr int kMaxSideStreams = 32;
+
 struct DeviceCtx {
   int device = -1;
-  int32_t* host_flag = nullptr;         // pinned, for the once-per-chunk poll
+  int32_t* host_flag = nullptr;         // pinned [64], for the once-per-chunk polls
   hipStream_t work_stream = nullptr;    // non-default stream for graph capture
   hipEvent_t ev_in = nullptr, ev_out = nullptr;  // joins with the caller's stream
+  // streams of the concurrent one-sample baseline (default priority),
+  // created on first use, with one event each to join the caller's stream
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_ev;
 };
 DeviceCtx* device_ctx();
+// Make sure the context holds at least `count` side streams.
+bool ensure_side_streams(DeviceCtx* c, int count);
 
 // Profiling of the hot kernels with HIP events recorded on the launch stream.
 void prof_begin(int kernel_id, hipStream_t st);

@@ -42,7 +42,7 @@ class ens_problem(ctypes.Structure):
 class ens_cg_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mixed", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32),
-                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32), ("coupled", ctypes.c_int32)]
 
 
 class ens_cg_stat(ctypes.Structure):
@@ -85,6 +85,9 @@ _SIGS = [
                       ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_scalar_cg", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _I32, _P, _SZ,
                              ctypes.POINTER(ens_cg_stat), _P]),
+    ("ens_scalar_cg_concurrent_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_scalar_cg_concurrent", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _I32, _I32, _P, _SZ,
+                                        ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_relayout", _I32, [_P, _P, _I64, _I32, _I32, _P]),
     ("ens_batch_workspace_bytes", _I32, [ctypes.POINTER(ens_group), _I32, _I32, ctypes.POINTER(ens_batch_opts),
                                          ctypes.POINTER(_SZ)]),
@@ -257,8 +260,8 @@ def scalar_spmv(g: Graph, values: torch.Tensor, x: torch.Tensor, y=None, lanes_p
 
 
 def cg_opts(rtol=1e-10, max_iter=10000, mixed=False, inner_rtol=1e-4, inner_max_iter=10000, max_outer=10,
-            check_every=16) -> ens_cg_opts:
-    return ens_cg_opts(rtol, max_iter, int(mixed), inner_rtol, inner_max_iter, max_outer, check_every, 0)
+            check_every=16, coupled=False) -> ens_cg_opts:
+    return ens_cg_opts(rtol, max_iter, int(mixed), inner_rtol, inner_max_iter, max_outer, check_every, int(coupled))
 
 
 def cg_workspace_bytes(g: Graph, s: int, opts: ens_cg_opts) -> int:
@@ -309,6 +312,28 @@ def scalar_cg(g: Graph, values_sm, b_sm, x_sm=None, opts: ens_cg_opts | None = N
     st = _check(lib().ens_scalar_cg(ctypes.byref(gc), s, _ptr(values_sm), _ptr(b_sm), _ptr(x_sm),
                                     ctypes.byref(opts), lanes_per_row, _ptr(workspace), workspace.numel(), stats,
                                     _stream(stream)), "ens_scalar_cg", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
+    return x_sm, _stats_list(stats, s), st
+
+
+def scalar_cg_concurrent(g: Graph, values_sm, b_sm, x_sm=None, opts: ens_cg_opts | None = None, lanes_per_row=0,
+                         streams=4, workspace=None, stream=None):
+    """scalar_cg with up to `streams` one-sample solves in flight at once."""
+    s = values_sm.shape[0]
+    if opts is None:
+        opts = cg_opts()
+    if x_sm is None:
+        x_sm = torch.zeros_like(b_sm)
+    gc = g.c()
+    nb = _SZ()
+    _check(lib().ens_scalar_cg_concurrent_workspace_bytes(ctypes.byref(gc), streams, ctypes.byref(nb)),
+           "ens_scalar_cg_concurrent_workspace_bytes")
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=b_sm.device)
+    stats = (ens_cg_stat * s)()
+    st = _check(lib().ens_scalar_cg_concurrent(ctypes.byref(gc), s, _ptr(values_sm), _ptr(b_sm), _ptr(x_sm),
+                                               ctypes.byref(opts), lanes_per_row, streams, _ptr(workspace),
+                                               workspace.numel(), stats, _stream(stream)),
+                "ens_scalar_cg_concurrent", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
     return x_sm, _stats_list(stats, s), st
 
 

@@ -245,6 +245,14 @@ def test_ensemble_equals_scalar_solves(E, orc):
             assert d <= (1e-10 if sstats[e]["iters"] == stats[e]["iters"] else 1e-6), (e, d)
     back = _np(E.relayout(vsm, False))
     assert np.array_equal(back, _np(vals))
+    # the concurrent one-sample baseline runs the same kernels per sample, so
+    # its results equal the sequential baseline's bitwise
+    xs1, st1, _ = E.scalar_cg(g, vsm, bsm, opts=E.cg_opts(rtol=rtol, check_every=5), lanes_per_row=8)
+    for streams in (1, 3, 8):
+        xc, stc, rc = E.scalar_cg_concurrent(g, vsm, bsm, opts=E.cg_opts(rtol=rtol, check_every=5), lanes_per_row=8,
+                                             streams=streams)
+        assert rc == E.ENS_OK
+        assert torch.equal(xc, xs1) and stc == st1
 
 
 def test_cg_edge_cases(E, orc):
@@ -308,3 +316,52 @@ def test_mixed_refinement_reaches_fp64_residual(E, orc, N, s, sigma):
         assert abs(stats[e]["rel_res"] - true_res[e]) <= 1e-3 * true_res[e] + 1e-14
         # error against the FP64 solve is stated, bounded by kappa * rtol
         assert _rel(xg[:, e], xref[:, e]) <= 1e-5
+
+
+# ---------------------------------------------------- coupled ensemble CG
+
+@pytest.mark.parametrize("N,s", [(7, 8), (12, 32), (5, 4)])
+def test_coupled_cg_matches_oracle(E, orc, N, s):
+    """Coupled solve (one alpha, beta and stopping test for the ensemble)
+    against the oracle's CG on the block-diagonal system at the GPU's
+    iteration count."""
+    M, sigma, rtol = 10, 0.3, 1e-10
+    xi = draw_xi(300 + N, s, M)
+    g, vals, _, rhs = _gpu_system(E, N, s, M, sigma, xi)
+    x, stats, st = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=rtol, coupled=True, check_every=4))
+    assert st == E.ENS_OK
+    its = {t["iters"] for t in stats}
+    assert len(its) == 1
+    k = its.pop()
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    xo, _, _, _ = orc.ens_pcg_coupled(rp, ci, ov, ob, fixed_iters=k)
+    _, ko, relo, sto = orc.ens_pcg_coupled(rp, ci, ov, ob, rtol=rtol)
+    xg = _np(x)
+    assert _rel(xg, xo) <= 1e-9, _rel(xg, xo)
+    assert abs(ko - k) <= 1 and sto == orc.CONVERGED
+    per = orc.ens_true_residual(rp, ci, ov, ob, xg)
+    total = np.sqrt(np.sum(per ** 2 * np.sum(ob * ob, axis=0)) / np.sum(ob * ob))
+    assert total <= rtol * (1 + 1e-6)
+    for e in range(s):
+        assert abs(stats[e]["rel_res"] - per[e]) <= 1e-6 * rtol + 1e-3 * per[e]
+    _, st_ps, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=rtol))
+    print(f"coupled iterations {k}; per-sample {min(t['iters'] for t in st_ps)}..{max(t['iters'] for t in st_ps)}")
+
+
+def test_coupled_cg_of_identical_samples(E):
+    N, s, M = 9, 16, 10
+    xi = np.repeat(draw_xi(77, 1, M), s, axis=0)
+    g, vals, _, rhs = _gpu_system(E, N, s, M, 0.3, xi)
+    xc, stc, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=1e-10, coupled=True))
+    xp, stp, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=1e-10))
+    assert [t["iters"] for t in stc] == [t["iters"] for t in stp]
+    assert _rel(_np(xc), _np(xp)) <= 1e-12
+
+
+def test_coupled_mixed_is_refused(E):
+    N, s, M = 4, 4, 3
+    g, vals, v32, rhs = _gpu_system(E, N, s, M, 0.1, draw_xi(1, s, M), want32=True)
+    with pytest.raises(E.EnsError) as ex:
+        E.cg(g, vals, rhs, values32=v32, opts=E.cg_opts(mixed=True, coupled=True))
+    assert ex.value.status == E.ENS_E_UNSUPPORTED
