@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--no-context", action="store_true", help="skip the FP64 / scalar comparison runs")
     ap.add_argument("--cpu-threads", type=int, default=4)
     ap.add_argument("--cpu-cap-iters", type=int, default=25)
-    ap.add_argument("--inner-rtol", type=float, default=1e-4)
+    ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--check-every", type=int, default=16)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (hardware-counter calibration)")

@@ -523,7 +523,7 @@ static ens_cg_opts normalized(const ens_cg_opts* in) {
   if (o.inner_max_iter <= 0) o.inner_max_iter = 10000;
   if (o.max_outer <= 0) o.max_outer = 10;
   if (o.check_every <= 0) o.check_every = 16;
-  if (!(o.inner_rtol > 0.0)) o.inner_rtol = 1e-4;
+  if (!(o.inner_rtol > 0.0)) o.inner_rtol = 1e-5;
   return o;
 }
 

@@ -259,7 +259,7 @@ def scalar_spmv(g: Graph, values: torch.Tensor, x: torch.Tensor, y=None, lanes_p
 # -------------------------------------------------------------------- CG
 
 
-def cg_opts(rtol=1e-10, max_iter=10000, mixed=False, inner_rtol=1e-4, inner_max_iter=10000, max_outer=10,
+def cg_opts(rtol=1e-10, max_iter=10000, mixed=False, inner_rtol=1e-5, inner_max_iter=10000, max_outer=10,
             check_every=16, coupled=False) -> ens_cg_opts:
     return ens_cg_opts(rtol, max_iter, int(mixed), inner_rtol, inner_max_iter, max_outer, check_every, int(coupled))
 
