@@ -209,3 +209,33 @@ def test_autotuner_choice_and_cache(E, tmp_path):
     groups = [_group(E, N, s, M, sigma, xi[i, :s]) for i, N in enumerate(meshes)]
     stats, rc, _ = E.solve_batch(groups, s, E.batch_opts(rtol=1e-8, tile=tile))
     assert rc == E.ENS_OK
+
+
+def test_pool_waves_equal_one_batch(E):
+    """Streaming groups through a pool too small for all of them (several
+    waves) gives bitwise the results of one batch over all groups: each
+    group's arithmetic depends only on its own blocks."""
+    from paper_1511_03703_amd import batchpool as bp
+    s, M, sigma = 16, 10, 0.2
+    meshes = [6, 9, 4, 12, 7, 9, 5]
+    G = len(meshes)
+    xi = torch.as_tensor(draw_xi(1200, G * s, M).reshape(G, s, M), device=DEV)
+    opts = E.batch_opts(rtol=1e-10, check_every=6, tile=4)
+    groups = [_group(E, N, s, M, sigma, xi[i].cpu().numpy()) for i, N in enumerate(meshes)]
+    stats_one, rc, _ = E.solve_batch(groups, s, opts)
+    assert rc == E.ENS_OK
+    # room for the largest group and a little more: waves of 3, 1 and 3 groups
+    pool_bytes = int(1.2 * max(bp.group_buffer_bytes(N, s) + bp.group_workspace_bound(N, s) for N in meshes))
+    pool = bp.BatchPool(E, meshes, s, M, pool_bytes)
+    assert len(pool.waves) >= 3
+    xs = {}
+
+    def keep(wv, grs, st):
+        for j, gr in enumerate(grs):
+            xs[wv.first + j] = gr[3].clone()
+
+    stats_pool, rc2 = pool.run(xi, sigma, opts, on_wave=keep)
+    assert rc2 == E.ENS_OK
+    assert stats_pool == stats_one
+    for i in range(G):
+        assert torch.equal(xs[i], groups[i][3])

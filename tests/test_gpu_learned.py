@@ -159,3 +159,34 @@ def test_learned_guess_saves_iterations(E):
           f"initial-guess error median {np.median(err0):.2e}", flush=True)
     assert np.median(err0) < 0.05
     assert np.mean(saved) > 2
+
+
+def test_learned_guess_driver(E):
+    """The package's learned-guess driver: basis from solver snapshots,
+    staged-learning-rate training, guesses that CG accepts and improves on."""
+    from paper_1511_03703_amd.learned import LearnedGuess
+    N, M, sigma, s = 10, 10, 0.2, 32
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    train_xi = draw_xi(1310, 256, M)
+    Sm = torch.zeros((g.n, 256), dtype=torch.float64, device=DEV)
+    for j in range(8):
+        v, _, b = E.assemble(g, kl, torch.as_tensor(train_xi[32 * j:32 * j + 32], device=DEV), M, sigma)
+        x, _, rc = E.cg(g, v, b, opts=E.cg_opts(rtol=1e-10))
+        assert rc == E.ENS_OK
+        E.pod_collect(x, Sm, 32 * j)
+    lg = LearnedGuess(r=32, device=DEV)
+    T = lg.fit_basis(Sm, eig_seed=1311)
+    lam = lg.lam.cpu().numpy()
+    assert np.all(np.diff(lam) <= 0) and lam[-1] > 0
+    loss = lg.fit_network(_f32(train_xi), T, steps=600, init_seed=1312, order_seed=1313, batch=64, halvings=2)
+    ln = loss.cpu().numpy()
+    assert np.all(np.isfinite(ln)) and ln[-30:].mean() < 0.1 * ln[:5].mean()
+    test_xi = draw_xi(1314, s, M)
+    v, _, b = E.assemble(g, kl, torch.as_tensor(test_xi, device=DEV), M, sigma)
+    x0 = lg.guess(_f32(test_xi))
+    x1, st1, rc1 = E.cg(g, v, b, x=x0.clone(), opts=E.cg_opts(rtol=1e-8))
+    xz, st0, rc0 = E.cg(g, v, b, opts=E.cg_opts(rtol=1e-8))
+    assert rc1 == E.ENS_OK and rc0 == E.ENS_OK
+    assert np.mean([a["iters"] - c["iters"] for a, c in zip(st0, st1)]) > 2
+    assert _rel(x0.cpu().numpy(), xz.cpu().numpy()) < 0.05
