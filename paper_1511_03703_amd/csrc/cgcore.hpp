@@ -291,7 +291,7 @@ __device__ inline void cg_start_body(int64_t nchunks, const T* __restrict__ r, c
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
       vt z = dv[u] * rv[u];
-      ((vt*)p)[i] = z;
+      store_stream((vt*)p + i, z);
       if (xzero) ((vt*)xzero)[i] = (vt)0;
 #pragma unroll
       for (int v = 0; v < M::V; ++v) {
@@ -317,7 +317,7 @@ __device__ inline void spmv_dot_body(int n, const int32_t* __restrict__ rp, cons
   const int64_t row = (blk * NW + wave) * M::RPW + lane / M::L;
   if (row < n) {
     typename M::vt qv = ens_row_product<T, S>(ci, vals, p, rp[row], rp[row + 1], sub);
-    ((typename M::vt*)q)[row * M::L + sub] = qv;
+    store_stream((typename M::vt*)q + row * M::L + sub, qv);
     typename M::vt pv = ((const typename M::vt*)p)[row * M::L + sub];
 #pragma unroll
     for (int j = 0; j < M::V; ++j) acc[0][j] = (double)pv[j] * (double)qv[j];
@@ -385,8 +385,8 @@ __device__ inline void update_body(int64_t nchunks, T* __restrict__ x, const T* 
   for (int u = 0; u < kU; ++u) {
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
-      ((vt*)x)[i] = xv[u];
-      ((vt*)r)[i] = rv[u];
+      store_stream((vt*)x + i, xv[u]);
+      store_stream((vt*)r + i, rv[u]);
     }
   }
   block_partials<S, M::VS, 2, kBlock / 64>(acc, dst);
@@ -429,7 +429,7 @@ __device__ inline void pupdate_body(int64_t nchunks, const T* __restrict__ r, co
 #pragma unroll
       for (int v = 0; v < M::V; ++v)  // inactive samples keep their p
         if (!act[v]) pn[v] = pv[u][v];
-      ((vt*)p)[i] = pn;
+      store_stream((vt*)p + i, pn);
     }
   }
 }

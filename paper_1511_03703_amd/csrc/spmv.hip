@@ -15,7 +15,7 @@ __global__ __launch_bounds__(256) void k_ens_spmv(int n, const int32_t* __restri
   const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
   if (row >= n) return;
   typename M::vt acc = ens_row_product<T, S>(ci, vals, x, rp[row], rp[row + 1], sub);
-  ((typename M::vt*)y)[row * M::L + sub] = acc;
+  store_stream((typename M::vt*)y + row * M::L + sub, acc);
 }
 
 // Scalar CRS (Fig. "crs") with G lanes per row: lane g sums entries
