@@ -351,7 +351,8 @@ ens_status ens_mlp_train(float* params, float* adam_m, float* adam_v, int32_t st
  *                  T [m][r] = (C - mu) / sd in FP32.
  * ens_pod_reconstruct: x0 [n][s] = Phi (mu + sd c)^T for network outputs
  *                  c [s][r] (FP32; mu, sd nullable for raw coefficients),
- *                  written in the ensemble layout ready for ens_cg. */
+ *                  written in the ensemble layout ready for ens_cg;
+ *                  s * r <= 8192 (ENS_E_ARG otherwise). */
 ens_status ens_pod_collect(const double* x, int64_t n, int32_t s, double* S, int32_t m, int32_t col0,
                            hipStream_t stream);
 ens_status ens_pod_gram_workspace_bytes(int64_t n, int32_t m, size_t* bytes);

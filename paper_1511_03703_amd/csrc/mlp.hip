@@ -180,12 +180,27 @@ __global__ __launch_bounds__(256) void k_mse(int B, const float* __restrict__ y,
 }
 
 // Column sums of an FP32 [M][N] matrix (bias gradients), fixed order.
-__global__ void k_colsum(int M, int N, const float* __restrict__ a, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.0f;
-  for (int m = 0; m < M; ++m) s += a[(int64_t)m * N + n];
-  out[n] = s;
+// out[n] = sum over m of a[m][n]: a block of 256 threads covers 64 columns,
+// four thread groups take interleaved rows with four running sums each, and
+// the sixteen partial sums of a column are added in a fixed order.
+__global__ __launch_bounds__(256) void k_colsum(int M, int N, const float* __restrict__ a, float* __restrict__ out) {
+  __shared__ float part[4][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  if (col < N) {
+    int m = g;
+    for (; m + 12 < M; m += 16) {
+      s0 += a[(int64_t)m * N + col];
+      s1 += a[(int64_t)(m + 4) * N + col];
+      s2 += a[(int64_t)(m + 8) * N + col];
+      s3 += a[(int64_t)(m + 12) * N + col];
+    }
+    for (; m < M; m += 4) s0 += a[(int64_t)m * N + col];
+  }
+  part[g][threadIdx.x & 63] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (g == 0 && col < N) out[col] = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
 }
 
 __global__ void k_adam(int64_t P, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -295,9 +310,9 @@ static void backward(int B, const MlpWork& w, hipStream_t st) {
                   epi(nullptr, w.dz1, kHid, nullptr, 0, w.dz1bt, B, w.z1, kHid), st);
   // dW1[n][k] = sum_b dZ1[b][n] X[b][k], k < 10
   gemm<EPI_STORE>(kHid, kIn, B, w.dz1bt, B, w.xbt, B, epi(nullptr, g + kOffW1, kIn, nullptr, 0, nullptr, 0), st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, B, kHid, w.dz1, g + kOffB1);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, B, kHid, w.dz2, g + kOffB2);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, st, B, kOut, w.dy, g + kOffB3);
+  hipLaunchKernelGGL(k_colsum, dim3((kHid + 63) / 64), dim3(256), 0, st, B, kHid, w.dz1, g + kOffB1);
+  hipLaunchKernelGGL(k_colsum, dim3((kHid + 63) / 64), dim3(256), 0, st, B, kHid, w.dz2, g + kOffB2);
+  hipLaunchKernelGGL(k_colsum, dim3((kOut + 63) / 64), dim3(256), 0, st, B, kOut, w.dy, g + kOffB3);
 }
 
 static void weights_bf16(const float* p, const MlpWork& w, hipStream_t st) {

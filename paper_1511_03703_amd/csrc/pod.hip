@@ -263,20 +263,28 @@ __global__ void k_collect(int64_t n, int s, const double* __restrict__ x, double
 }
 
 // x0[i][e] = sum_j Phi[i][j] (mu[j] + sd[j] c[e][j])   (c FP32; mu, sd nullable)
-__global__ void k_reconstruct(int64_t n, int r, int s, const double* __restrict__ Phi, const float* __restrict__ c,
-                              const double* __restrict__ mu, const double* __restrict__ sd,
-                              double* __restrict__ x0) {
+__global__ __launch_bounds__(256) void k_reconstruct(int64_t n, int r, int s, const double* __restrict__ Phi,
+                                                     const float* __restrict__ c, const double* __restrict__ mu,
+                                                     const double* __restrict__ sd, double* __restrict__ x0) {
+  // the de-standardised coefficients chat[e][j] = mu_j + sd_j c[e][j] of all
+  // samples, staged once per block
+  extern __shared__ double chat[];
+  for (int t = threadIdx.x; t < s * r; t += blockDim.x) {
+    const int j = t % r;
+    double cj = (double)c[t];
+    if (sd) cj *= sd[j];
+    if (mu) cj += mu[j];
+    chat[t] = cj;
+  }
+  __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * s) return;
   const int64_t i = t / s;
   const int e = (int)(t % s);
+  const double* prow = Phi + i * r;
+  const double* ce = chat + (int64_t)e * r;
   double acc = 0.0;
-  for (int j = 0; j < r; ++j) {
-    double cj = (double)c[(int64_t)e * r + j];
-    if (sd) cj *= sd[j];
-    if (mu) cj += mu[j];
-    acc += Phi[i * r + j] * cj;
-  }
+  for (int j = 0; j < r; ++j) acc += prow[j] * ce[j];
   x0[t] = acc;
 }
 
@@ -440,8 +448,9 @@ ens_status ens_pod_project(const double* Phi, const double* X, int64_t n, int32_
 ens_status ens_pod_reconstruct(const double* Phi, int64_t n, int32_t r, const float* c, const double* mu,
                                const double* sd, int32_t s, double* x0, hipStream_t stream) {
   ENS_ARG_CHECK(Phi && c && x0 && n >= 1 && r >= 1 && s >= 1, "bad reconstruction arguments");
-  hipLaunchKernelGGL(k_reconstruct, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, stream, n, r, s, Phi, c,
-                     mu, sd, x0);
+  ENS_ARG_CHECK((int64_t)s * r <= 8192, "s * r must not exceed 8192 (coefficients staged in 64 KB of LDS)");
+  hipLaunchKernelGGL(k_reconstruct, dim3((unsigned)((n * s + 255) / 256)), dim3(256),
+                     (size_t)s * r * sizeof(double), stream, n, r, s, Phi, c, mu, sd, x0);
   ENS_LAUNCH_CHECK();
   return ENS_OK;
 }
