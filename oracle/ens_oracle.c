@@ -744,4 +744,361 @@ int orc_cholesky_solve(int64_t n, double *A, const double *b, double *x) {
   return 0;
 }
 
+/* ------------------------------------------------------------ multigrid
+ *
+ * V-cycle preconditioner (Sec. 3.5, Alg. vcycle) on the nested Q1 meshes
+ * N, N/2, N/4, ... (coarsened while the element count per axis is even and
+ * above 4).  Each level's operator is the Q1 matrix assembled on that mesh
+ * with the same KL coefficient; prolongation P is trilinear interpolation
+ * from the coarse nodes (the coarse Q1 basis written in the fine one) and
+ * restriction is its transpose, both restricted to interior nodes so the
+ * Dirichlet identity rows stay untouched.  Smoothers are order-2 Chebyshev
+ * polynomials in D^-1 A on [lmax/4, lmax], lmax the Gershgorin bound
+ * max_i sum_j |a_ij| / a_ii; the coarsest level is solved exactly (dense
+ * Cholesky of its interior block; boundary rows are identities).  The
+ * ensemble preconditioner applies each sample's own hierarchy
+ * (M_c = sum_i M_i (x) e_i e_i^T).                                        */
+
+#define ORC_MG_MAX_LEVELS 16
+#define ORC_MG_RATIO 4.0
+
+int orc_mg_levels(int N, int32_t *Ns) {
+  int L = 0;
+  Ns[L++] = N;
+  while (L < ORC_MG_MAX_LEVELS && Ns[L - 1] % 2 == 0 && Ns[L - 1] > 4) {
+    Ns[L] = Ns[L - 1] / 2;
+    ++L;
+  }
+  return L;
+}
+
+/* Coarse neighbours of fine index i along one axis with their
+ * interpolation weights: an even i sits on coarse node i/2, an odd i
+ * halfway between (i-1)/2 and (i+1)/2. */
+static int axis_parents(int i, int *I, double *w) {
+  if (i % 2 == 0) {
+    I[0] = i / 2; w[0] = 1.0;
+    return 1;
+  }
+  I[0] = (i - 1) / 2; w[0] = 0.5;
+  I[1] = (i + 1) / 2; w[1] = 0.5;
+  return 2;
+}
+
+/* xf += P xc on the interior nodes of the fine mesh (2 Nc elements per
+ * axis); coarse boundary nodes contribute nothing. */
+void orc_mg_prolong_add(int Nc, const double *xc, double *xf) {
+  const int Nf = 2 * Nc;
+  for (int k = 1; k < Nf; ++k)
+    for (int j = 1; j < Nf; ++j)
+      for (int i = 1; i < Nf; ++i) {
+        int Ii[2], Jj[2], Kk[2];
+        double wi[2], wj[2], wk[2];
+        const int ni = axis_parents(i, Ii, wi), nj = axis_parents(j, Jj, wj), nk = axis_parents(k, Kk, wk);
+        double v = 0.0;
+        for (int c = 0; c < nk; ++c)
+          for (int b = 0; b < nj; ++b)
+            for (int a = 0; a < ni; ++a) {
+              const int I = Ii[a], J = Jj[b], K = Kk[c];
+              if (I == 0 || J == 0 || K == 0 || I == Nc || J == Nc || K == Nc) continue;
+              v += wi[a] * wj[b] * wk[c] * xc[node_id(Nc, I, J, K)];
+            }
+        xf[node_id(Nf, i, j, k)] += v;
+      }
+}
+
+/* rc = P^T rf, written as the scatter of every interior fine residual onto
+ * the interior coarse nodes it interpolates from. */
+void orc_mg_restrict(int Nf, const double *rf, double *rc) {
+  const int Nc = Nf / 2;
+  const int64_t nc = orc_num_nodes(Nc);
+  for (int64_t t = 0; t < nc; ++t) rc[t] = 0.0;
+  for (int k = 1; k < Nf; ++k)
+    for (int j = 1; j < Nf; ++j)
+      for (int i = 1; i < Nf; ++i) {
+        int Ii[2], Jj[2], Kk[2];
+        double wi[2], wj[2], wk[2];
+        const int ni = axis_parents(i, Ii, wi), nj = axis_parents(j, Jj, wj), nk = axis_parents(k, Kk, wk);
+        const double r = rf[node_id(Nf, i, j, k)];
+        for (int c = 0; c < nk; ++c)
+          for (int b = 0; b < nj; ++b)
+            for (int a = 0; a < ni; ++a) {
+              const int I = Ii[a], J = Jj[b], K = Kk[c];
+              if (I == 0 || J == 0 || K == 0 || I == Nc || J == Nc || K == Nc) continue;
+              rc[node_id(Nc, I, J, K)] += wi[a] * wj[b] * wk[c] * r;
+            }
+      }
+}
+
+double orc_gershgorin(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values) {
+  double m = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0, d = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      s += fabs(values[k]);
+      if (col_idx[k] == i) d = values[k];
+    }
+    const double q = s / d;
+    if (q > m) m = q;
+  }
+  return m;
+}
+
+/* Order-2 Chebyshev smoother for A x = b preconditioned by D^-1 on the
+ * interval [lmax/4, lmax] (the three-term Chebyshev iteration):
+ *   theta = (hi + lo)/2, delta = (hi - lo)/2, sigma = theta/delta;
+ *   d = D^-1 (b - A x) / theta; x += d;
+ *   rho0 = 1/sigma, rho1 = 1/(2 sigma - rho0);
+ *   d = rho1 rho0 d + (2 rho1/delta) D^-1 (b - A x); x += d.
+ * x_is_zero skips the first product.  r, d, ax: scratch [n].  */
+void orc_mg_cheb2(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+                  double lmax, const double *b, double *x, int x_is_zero, double *r, double *d, double *ax) {
+  const double hi = lmax, lo = lmax / ORC_MG_RATIO;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  if (x_is_zero) {
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+  } else {
+    orc_spmv(n, row_ptr, col_idx, values, x, ax);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - ax[i];
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    double dg = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+      if (col_idx[k] == i) dg = values[k];
+    d[i] = (r[i] / dg) / theta;
+    x[i] = x_is_zero ? d[i] : x[i] + d[i];
+  }
+  const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+  orc_spmv(n, row_ptr, col_idx, values, x, ax);
+  for (int64_t i = 0; i < n; ++i) {
+    double dg = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+      if (col_idx[k] == i) dg = values[k];
+    d[i] = rho1 * rho0 * d[i] + (2.0 * rho1 / delta) * ((b[i] - ax[i]) / dg);
+    x[i] += d[i];
+  }
+}
+
+typedef struct {
+  int N;
+  int64_t n, nnz;
+  int32_t *rp, *ci;
+  double *v, lmax;
+  double *b, *x, *r, *d, *ax;
+  int64_t m;        /* coarsest level: interior unknowns */
+  int64_t *imap;    /* coarsest level: interior node ids */
+  double *chol;     /* coarsest level: Cholesky factor of the interior block */
+} orc_level;
+
+static void free_levels(orc_level *lv, int L) {
+  for (int k = 0; k < L; ++k) {
+    free(lv[k].rp); free(lv[k].ci); free(lv[k].v);
+    free(lv[k].b); free(lv[k].x); free(lv[k].r); free(lv[k].d); free(lv[k].ax);
+    free(lv[k].imap); free(lv[k].chol);
+  }
+}
+
+static int chol_factor(int64_t m, double *A) {
+  for (int64_t j = 0; j < m; ++j) {
+    double dd = A[j * m + j];
+    for (int64_t k = 0; k < j; ++k) dd -= A[j * m + k] * A[j * m + k];
+    if (!(dd > 0.0)) return 1;
+    const double ljj = sqrt(dd);
+    A[j * m + j] = ljj;
+    for (int64_t i = j + 1; i < m; ++i) {
+      double v = A[i * m + j];
+      for (int64_t k = 0; k < j; ++k) v -= A[i * m + k] * A[j * m + k];
+      A[i * m + j] = v / ljj;
+    }
+  }
+  return 0;
+}
+
+static void chol_solve(int64_t m, const double *Lf, const double *b, double *x) {
+  for (int64_t i = 0; i < m; ++i) {
+    double v = b[i];
+    for (int64_t k = 0; k < i; ++k) v -= Lf[i * m + k] * x[k];
+    x[i] = v / Lf[i * m + i];
+  }
+  for (int64_t i = m - 1; i >= 0; --i) {
+    double v = x[i];
+    for (int64_t k = i + 1; k < m; ++k) v -= Lf[k * m + i] * x[k];
+    x[i] = v / Lf[i * m + i];
+  }
+}
+
+/* Levels for one sample: matrices assembled on every mesh of the hierarchy
+ * with the sample's KL coefficient; level 0's load vector into b0 (nullable). */
+static int build_levels(int N, int M, double L, double kappa0, double sigma, double fconst, const double *xi,
+                        orc_level *lv, int *nlev, double *b0) {
+  int32_t Ns[ORC_MG_MAX_LEVELS];
+  const int nl = orc_mg_levels(N, Ns);
+  memset(lv, 0, sizeof(orc_level) * (size_t)nl);
+  *nlev = nl;
+  for (int k = 0; k < nl; ++k) {
+    orc_level *l = &lv[k];
+    l->N = Ns[k];
+    l->n = orc_num_nodes(l->N);
+    l->nnz = orc_graph_nnz(l->N);
+    const int64_t ne = orc_num_elems(l->N);
+    l->rp = malloc(sizeof(int32_t) * (size_t)(l->n + 1));
+    l->ci = malloc(sizeof(int32_t) * (size_t)l->nnz);
+    l->v = malloc(sizeof(double) * (size_t)l->nnz);
+    l->b = calloc((size_t)l->n, sizeof(double));
+    l->x = calloc((size_t)l->n, sizeof(double));
+    l->r = calloc((size_t)l->n, sizeof(double));
+    l->d = calloc((size_t)l->n, sizeof(double));
+    l->ax = calloc((size_t)l->n, sizeof(double));
+    double *ac = malloc(sizeof(double) * 8 * (size_t)ne);
+    double *load = malloc(sizeof(double) * (size_t)l->n);
+    if (!l->rp || !l->ci || !l->v || !l->b || !l->x || !l->r || !l->d || !l->ax || !ac || !load) {
+      free(ac); free(load);
+      return ORC_E_NOMEM;
+    }
+    orc_graph(l->N, l->rp, l->ci);
+    orc_kl_coef_qp(l->N, M, L, kappa0, sigma, xi, ac);
+    orc_assemble_scalar(l->N, l->rp, l->ci, ac, 0, fconst, 1, l->v, load);
+    if (k == 0 && b0) memcpy(b0, load, sizeof(double) * (size_t)l->n);
+    free(ac); free(load);
+    l->lmax = orc_gershgorin(l->n, l->rp, l->ci, l->v);
+  }
+  orc_level *c = &lv[nl - 1];
+  c->imap = malloc(sizeof(int64_t) * (size_t)c->n);
+  if (!c->imap) return ORC_E_NOMEM;
+  c->m = 0;
+  for (int64_t t = 0; t < c->n; ++t)
+    if (!is_boundary_node(c->N, t)) c->imap[c->m++] = t;
+  c->chol = calloc((size_t)(c->m * c->m) + 1, sizeof(double));
+  if (!c->chol) return ORC_E_NOMEM;
+  for (int64_t a = 0; a < c->m; ++a) {
+    const int64_t row = c->imap[a];
+    for (int64_t k = c->rp[row]; k < c->rp[row + 1]; ++k)
+      for (int64_t bcol = 0; bcol < c->m; ++bcol)
+        if (c->imap[bcol] == c->ci[k]) c->chol[a * c->m + bcol] = c->v[k];
+  }
+  if (c->m > 0 && chol_factor(c->m, c->chol)) return ORC_E_ARG;
+  return ORC_OK;
+}
+
+/* x = V-cycle(b) on level k (x overwritten), in the order of Alg. vcycle. */
+static void vcycle(orc_level *lv, int k, int nl, const double *b, double *x) {
+  orc_level *l = &lv[k];
+  if (k == nl - 1) {
+    for (int64_t t = 0; t < l->n; ++t) x[t] = b[t];  /* identity rows */
+    if (l->m > 0) {
+      double *bi = l->r, *xi = l->d;
+      for (int64_t a = 0; a < l->m; ++a) bi[a] = b[l->imap[a]];
+      chol_solve(l->m, l->chol, bi, xi);
+      for (int64_t a = 0; a < l->m; ++a) x[l->imap[a]] = xi[a];
+    }
+    return;
+  }
+  orc_mg_cheb2(l->n, l->rp, l->ci, l->v, l->lmax, b, x, 1, l->r, l->d, l->ax);
+  orc_spmv(l->n, l->rp, l->ci, l->v, x, l->ax);
+  for (int64_t t = 0; t < l->n; ++t) l->r[t] = b[t] - l->ax[t];
+  orc_level *c = &lv[k + 1];
+  orc_mg_restrict(l->N, l->r, c->b);
+  vcycle(lv, k + 1, nl, c->b, c->x);
+  orc_mg_prolong_add(c->N, c->x, x);
+  orc_mg_cheb2(l->n, l->rp, l->ci, l->v, l->lmax, b, x, 0, l->r, l->d, l->ax);
+}
+
+/* z = M r for one sample's hierarchy (for building M in tests). */
+int orc_mg_apply(int N, int M, double L, double kappa0, double sigma, double fconst, const double *xi,
+                 const double *r, double *z) {
+  orc_level lv[ORC_MG_MAX_LEVELS];
+  int nl = 0;
+  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, lv, &nl, NULL);
+  if (rc == ORC_OK) vcycle(lv, 0, nl, r, z);
+  free_levels(lv, nl);
+  return rc;
+}
+
+/* Multigrid-preconditioned CG for one sample: textbook PCG with z = M r,
+ * the same stopping rule and failure handling as orc_pcg.  x in: x0. */
+int orc_mg_pcg(int N, int M, double L, double kappa0, double sigma, double fconst, const double *xi, double *x,
+               double rtol, int max_iter, int fixed_iters, int32_t *iters_out, double *rel_res_out,
+               int32_t *status_out, double *lmax_out) {
+  orc_level lv[ORC_MG_MAX_LEVELS];
+  int nl = 0;
+  const int64_t n = orc_num_nodes(N);
+  double *b = malloc(sizeof(double) * (size_t)n);
+  double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
+  double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
+  if (!b || !r || !z || !p || !q) return ORC_E_NOMEM;
+  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, lv, &nl, b);
+  if (rc != ORC_OK) { free_levels(lv, nl); free(b); free(r); free(z); free(p); free(q); return rc; }
+  if (lmax_out)
+    for (int k = 0; k < nl; ++k) lmax_out[k] = lv[k].lmax;
+  const int32_t *rp = lv[0].rp, *ci = lv[0].ci;
+  const double *vals = lv[0].v;
+  int status = ORC_CONVERGED, iters = 0;
+  const double nb = sqrt(dot(n, b, b));
+  orc_spmv(n, rp, ci, vals, x, q);
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  int limit = fixed_iters >= 0 ? fixed_iters : max_iter;
+  const int test = fixed_iters < 0;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    limit = 0;
+  } else if (test && sqrt(dot(n, r, r)) <= rtol * nb) {
+    limit = 0;
+  } else {
+    vcycle(lv, 0, nl, r, z);
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+    double rho = dot(n, r, z);
+    status = ORC_MAXITER;
+    for (int k = 1; k <= limit; ++k) {
+      orc_spmv(n, rp, ci, vals, p, q);
+      const double eta = dot(n, p, q);
+      if (!isfinite(eta) || !isfinite(rho)) { status = ORC_NONFINITE; break; }
+      if (!(eta > 0.0)) { status = ORC_BREAKDOWN; break; }
+      const double alpha = rho / eta;
+      for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+      iters = k;
+      const double rr = dot(n, r, r);
+      if (!isfinite(rr)) { status = ORC_NONFINITE; break; }
+      if (test && sqrt(rr) <= rtol * nb) { status = ORC_CONVERGED; break; }
+      if (!test && k == limit) { status = ORC_CONVERGED; break; }
+      vcycle(lv, 0, nl, r, z);
+      const double rho_new = dot(n, r, z);
+      const double beta = rho_new / rho;
+      for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+      rho = rho_new;
+    }
+    if (!test && limit == 0) status = ORC_CONVERGED;
+  }
+  orc_spmv(n, rp, ci, vals, x, q);
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  *iters_out = iters;
+  *rel_res_out = nb > 0.0 ? sqrt(dot(n, r, r)) / nb : 0.0;
+  *status_out = status;
+  free_levels(lv, nl);
+  free(b); free(r); free(z); free(p); free(q);
+  return ORC_OK;
+}
+
+/* The ensemble of orc_mg_pcg, one sample per thread: xi [s][M], x [n][s]
+ * (commuted layout, in: x0), fixed_iters [s] nullable, lmax [s][16]
+ * nullable (each level's Chebyshev bound). */
+int orc_ens_mg_pcg(int N, int M, double L, double kappa0, double sigma, double fconst, int s, const double *xi,
+                   double *x, double rtol, int max_iter, const int32_t *fixed_iters, int32_t *iters,
+                   double *rel_res, int32_t *status, double *lmax) {
+  const int64_t n = orc_num_nodes(N);
+  int rc = ORC_OK;
+  #pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < s; ++e) {
+    double *xe = malloc(sizeof(double) * (size_t)n);
+    if (!xe) { rc = ORC_E_NOMEM; continue; }
+    for (int64_t i = 0; i < n; ++i) xe[i] = x[i * s + e];
+    int r = orc_mg_pcg(N, M, L, kappa0, sigma, fconst, xi + (int64_t)e * M, xe, rtol, max_iter,
+                       fixed_iters ? fixed_iters[e] : -1, &iters[e], &rel_res[e], &status[e],
+                       lmax ? lmax + (int64_t)e * ORC_MG_MAX_LEVELS : NULL);
+    if (r) rc = r;
+    for (int64_t i = 0; i < n; ++i) x[i * s + e] = xe[i];
+    free(xe);
+  }
+  return rc;
+}
+
 int orc_version(void) { return 1; }

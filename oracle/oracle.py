@@ -64,6 +64,17 @@ def lib():
         L.orc_ens_spmv.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_pcg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.orc_ens_pcg.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, dbl, ctypes.c_int, vp, vp, vp, vp]
+        L.orc_mg_levels.argtypes = [ctypes.c_int, vp]
+        L.orc_mg_prolong_add.argtypes = [ctypes.c_int, vp, vp]
+        L.orc_mg_restrict.argtypes = [ctypes.c_int, vp, vp]
+        L.orc_gershgorin.restype = dbl
+        L.orc_gershgorin.argtypes = [i64, vp, vp, vp]
+        L.orc_mg_cheb2.argtypes = [i64, vp, vp, vp, dbl, vp, vp, ctypes.c_int, vp, vp, vp]
+        L.orc_mg_apply.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, vp, vp]
+        L.orc_mg_pcg.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, vp, dbl, ctypes.c_int,
+                                 ctypes.c_int, vp, vp, vp, vp]
+        L.orc_ens_mg_pcg.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int, vp, vp, dbl,
+                                     ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_ens_pcg_coupled.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int,
                                           vp, vp, vp]
         L.orc_solve_sample.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, dbl,
@@ -247,6 +258,63 @@ def ens_pcg_coupled(rp, ci, vals, b, x0=None, rtol=1e-10, max_iter=10000, fixed_
     _check(lib().orc_ens_pcg_coupled(n, s, _p(rp), _p(ci), _p(_f64(vals)), _p(_f64(b)), _p(x), rtol, max_iter,
                                      int(fixed_iters), _p(it), _p(rr), _p(st)))
     return x, int(it[0]), float(rr[0]), int(st[0])
+
+
+MG_MAX_LEVELS = 16
+
+
+def mg_levels(N):
+    Ns = np.zeros(MG_MAX_LEVELS, np.int32)
+    k = lib().orc_mg_levels(N, _p(Ns))
+    return [int(v) for v in Ns[:k]]
+
+
+def mg_prolong_add(Nc, xc, xf):
+    xf = _f64(xf).copy()
+    lib().orc_mg_prolong_add(Nc, _p(_f64(xc)), _p(xf))
+    return xf
+
+
+def mg_restrict(Nf, rf):
+    rc = np.zeros(num_nodes(Nf // 2))
+    lib().orc_mg_restrict(Nf, _p(_f64(rf)), _p(rc))
+    return rc
+
+
+def gershgorin(rp, ci, vals):
+    return float(lib().orc_gershgorin(rp.shape[0] - 1, _p(rp), _p(ci), _p(_f64(vals))))
+
+
+def mg_cheb2(rp, ci, vals, lmax, b, x0=None):
+    n = rp.shape[0] - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    r, d, ax = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_mg_cheb2(n, _p(rp), _p(ci), _p(_f64(vals)), lmax, _p(_f64(b)), _p(x), int(x0 is None), _p(r), _p(d),
+                       _p(ax))
+    return x
+
+
+def mg_apply(N, M, L, kappa0, sigma, fconst, xi, r):
+    z = np.zeros(num_nodes(N))
+    _check(lib().orc_mg_apply(N, M, L, kappa0, sigma, fconst, _p(_f64(xi)), _p(_f64(r)), _p(z)))
+    return z
+
+
+def ens_mg_pcg(N, M, L, kappa0, sigma, fconst, xi, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=None):
+    """Multigrid-preconditioned CG per sample (each sample its own hierarchy).
+    Returns (x [n][s], iters, rel_res, status, lmax [s][levels])."""
+    xi = _f64(xi)
+    s = xi.shape[0]
+    n = num_nodes(N)
+    x = np.zeros((n, s)) if x0 is None else _f64(x0).copy()
+    it = np.zeros(s, np.int32)
+    rr = np.zeros(s)
+    st = np.zeros(s, np.int32)
+    lm = np.zeros((s, MG_MAX_LEVELS))
+    fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, np.int32)
+    _check(lib().orc_ens_mg_pcg(N, M, L, kappa0, sigma, fconst, s, _p(xi), _p(x), rtol, max_iter,
+                                None if fi is None else _p(fi), _p(it), _p(rr), _p(st), _p(lm)))
+    return x, it, rr, st, lm[:, :len(mg_levels(N))]
 
 
 def solve_samples(N, M, L, kappa0, sigma, fconst, xi, rtol, max_iter=10000, want_x=True, timing=False):

@@ -571,3 +571,150 @@ def test_coupled_cg_of_identical_samples_is_the_scalar_cg(orc):
     assert itc == it1 and stc == orc.CONVERGED
     for e in range(s):
         np.testing.assert_allclose(xc[:, e], x1, rtol=0, atol=1e-12 * np.abs(x1).max())
+
+
+# ------------------------------------------------------- multigrid (oracle)
+
+def test_mg_hierarchy_levels(orc):
+    assert orc.mg_levels(128) == [128, 64, 32, 16, 8, 4]
+    assert orc.mg_levels(96) == [96, 48, 24, 12, 6, 3]
+    assert orc.mg_levels(7) == [7] and orc.mg_levels(4) == [4]
+
+
+def _coords(N):
+    t = np.arange(N + 1) / N
+    Z, Y, X = np.meshgrid(t, t, t, indexing="ij")
+    return X.ravel(), Y.ravel(), Z.ravel()
+
+
+def test_mg_prolongation_interpolates_trilinear_functions(orc):
+    # P is the coarse Q1 basis written in the fine one: a trilinear function
+    # given at the coarse nodes is reproduced at every fine node whose parents
+    # are interior; fine boundary nodes receive nothing
+    Nc = 4
+    Nf = 2 * Nc
+    f = lambda x, y, z: 1 + x + 2 * y + 3 * z + x * y - 0.5 * y * z + 2 * x * y * z
+    Xc, Yc, Zc = _coords(Nc)
+    xc = f(Xc, Yc, Zc)
+    Xf, Yf, Zf = _coords(Nf)
+    base = np.random.default_rng(3).uniform(-1, 1, Xf.size)
+    xf = orc.mg_prolong_add(Nc, xc, base) - base
+    idx = np.arange(Xf.size)
+    i, j, k = idx % (Nf + 1), (idx // (Nf + 1)) % (Nf + 1), idx // (Nf + 1) ** 2
+    deep = (i >= 2) & (i <= Nf - 2) & (j >= 2) & (j <= Nf - 2) & (k >= 2) & (k <= Nf - 2)
+    np.testing.assert_allclose(xf[deep], f(Xf, Yf, Zf)[deep], rtol=1e-14, atol=1e-14)
+    bnd = (i == 0) | (j == 0) | (k == 0) | (i == Nf) | (j == Nf) | (k == Nf)
+    assert not xf[bnd].any()
+
+
+def test_mg_restriction_is_the_adjoint_of_prolongation(orc):
+    rng = np.random.default_rng(4)
+    for Nc in (2, 3, 5):
+        u = rng.standard_normal((Nc + 1) ** 3)
+        v = rng.standard_normal((2 * Nc + 1) ** 3)
+        Pu = orc.mg_prolong_add(Nc, u, np.zeros(v.size))
+        Rv = orc.mg_restrict(2 * Nc, v)
+        assert abs(Pu @ v - u @ Rv) <= 1e-13 * np.abs(Pu).sum() * np.abs(v).max()
+
+
+def _dense_P(orc, Nc):
+    nc, nf = (Nc + 1) ** 3, (2 * Nc + 1) ** 3
+    P = np.zeros((nf, nc))
+    for c in range(nc):
+        e = np.zeros(nc)
+        e[c] = 1.0
+        P[:, c] = orc.mg_prolong_add(Nc, e, np.zeros(nf))
+    return P
+
+
+def test_mg_galerkin_product_equals_coarse_assembly(orc):
+    # nested Q1 spaces with an exactly integrated constant coefficient: the
+    # Galerkin operator P^T A_f P is the matrix assembled on the coarse mesh
+    Nc = 3
+    Nf = 2 * Nc
+    mats = []
+    for N in (Nf, Nc):
+        rp, ci = orc.graph(N)
+        ac = orc.kl_coef_qp(N, 4, 1.0, 1.7, 0.0, np.zeros(4))
+        vals, _ = orc.assemble_scalar(N, rp, ci, ac)
+        mats.append(orc.crs_to_dense(rp, ci, vals))
+    Af, Ac = mats
+    P = _dense_P(orc, Nc)
+    G = P.T @ Af @ P
+    idx = np.arange((Nc + 1) ** 3)
+    i, j, k = idx % (Nc + 1), (idx // (Nc + 1)) % (Nc + 1), idx // (Nc + 1) ** 2
+    inner = (i > 0) & (j > 0) & (k > 0) & (i < Nc) & (j < Nc) & (k < Nc)
+    np.testing.assert_allclose(G[np.ix_(inner, inner)], Ac[np.ix_(inner, inner)], rtol=0,
+                               atol=1e-13 * np.abs(Ac).max())
+
+
+def test_chebyshev_smoother_matches_its_polynomial(orc):
+    # order-2 Chebyshev on [lmax/4, lmax] from x = 0: the error in each
+    # eigenvector of D^-1 A is multiplied by T2((theta-l)/delta) / T2(theta/delta)
+    n = 40
+    rp = [0]
+    ci, vals = [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                ci.append(j)
+                vals.append(2.0 if i == j else -1.0)
+        rp.append(len(ci))
+    rp, ci, vals = np.array(rp, np.int32), np.array(ci, np.int32), np.array(vals)
+    A = orc.crs_to_dense(rp, ci, vals)
+    lmax = orc.gershgorin(rp, ci, vals)
+    assert lmax == 2.0
+    b = np.random.default_rng(5).standard_normal(n)
+    xs = np.linalg.solve(A, b)
+    x = orc.mg_cheb2(rp, ci, vals, lmax, b)
+    lam, Q = np.linalg.eigh(A / 2.0)   # D^-1 A, D = 2 I
+    hi, lo = lmax, lmax / 4.0
+    th, de = (hi + lo) / 2, (hi - lo) / 2
+    T2 = lambda t: 2 * t * t - 1
+    R = T2((th - lam) / de) / T2(th / de)
+    np.testing.assert_allclose(xs - x, Q @ (R * (Q.T @ xs)), rtol=0, atol=1e-12 * np.abs(xs).max())
+    # a second application from the result continues with the same polynomial
+    x2 = orc.mg_cheb2(rp, ci, vals, lmax, b, x0=x)
+    np.testing.assert_allclose(xs - x2, Q @ (R * R * (Q.T @ xs)), rtol=0, atol=1e-12 * np.abs(xs).max())
+
+
+def test_vcycle_is_spd_and_contracts(orc):
+    N, M, sigma = 8, 10, 0.3
+    xi = draw_xi(41, 1, M)[0]
+    n = (N + 1) ** 3
+    idx = np.arange(n)
+    i, j, k = idx % (N + 1), (idx // (N + 1)) % (N + 1), idx // (N + 1) ** 2
+    inner = np.flatnonzero((i > 0) & (j > 0) & (k > 0) & (i < N) & (j < N) & (k < N))
+    Mop = np.zeros((n, inner.size))
+    for c, t in enumerate(inner):
+        e = np.zeros(n)
+        e[t] = 1.0
+        Mop[:, c] = orc.mg_apply(N, M, 1.0, 1.0, sigma, 1.0, xi, e)
+    Mi = Mop[inner]
+    np.testing.assert_allclose(Mi, Mi.T, rtol=0, atol=1e-13 * np.abs(Mi).max())
+    assert np.linalg.eigvalsh(0.5 * (Mi + Mi.T)).min() > 0
+    assert not Mop[np.setdiff1d(idx, inner)].any()   # no correction on the boundary
+    rp, ci = orc.graph(N)
+    ac = orc.kl_coef_qp(N, M, 1.0, 1.0, sigma, xi)
+    vals, _ = orc.assemble_scalar(N, rp, ci, ac)
+    Ai = orc.crs_to_dense(rp, ci, vals)[np.ix_(inner, inner)]
+    ev = np.linalg.eigvals(np.eye(inner.size) - Mi @ Ai)
+    assert np.abs(ev).max() < 0.15
+
+
+def test_mg_pcg_converges_to_the_dense_solution(orc):
+    N, M, sigma = 8, 10, 0.3
+    xi = draw_xi(42, 3, M)
+    x, it, rr, st, lm = orc.ens_mg_pcg(N, M, 1.0, 1.0, sigma, 1.0, xi, rtol=1e-12)
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    for e in range(3):
+        A = orc.crs_to_dense(rp, ci, np.ascontiguousarray(ov[:, e]))
+        xd = np.linalg.solve(A, ob[:, e])
+        assert st[e] == orc.CONVERGED and rr[e] <= 1e-12 * (1 + 1e-6)
+        assert np.linalg.norm(x[:, e] - xd) <= 1e-10 * np.linalg.norm(xd)
+        assert it[e] <= 10
+        assert lm[e, 0] == orc.gershgorin(rp, ci, np.ascontiguousarray(ov[:, e]))
+    # fewer iterations than Jacobi, and the count does not grow with the mesh
+    its = [orc.ens_mg_pcg(Nn, M, 1.0, 1.0, sigma, 1.0, xi[:1], rtol=1e-10)[1][0] for Nn in (8, 16, 32)]
+    assert max(its) - min(its) <= 3
