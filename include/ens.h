@@ -279,6 +279,42 @@ ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, const ens_probl
                               const ens_batch_opts* base, const char* cache_path, int32_t* best_s,
                               int32_t* best_tile, double* scores, hipStream_t stream);
 
+/* ------------------------------------------------------------ multigrid */
+
+/* Multigrid preconditioner (Sec. 3.5, Alg. vcycle) for the ensemble Q1
+ * problem on the N^3 mesh: levels N, N/2, ... (halved while even and above
+ * 4; the coarsest level must have at most 512 interior nodes), each level's
+ * ensemble matrix assembled on its own mesh with the samples' KL inputs;
+ * trilinear prolongation onto interior nodes and its transpose as
+ * restriction; order-2 Chebyshev smoothers in D^-1 A on [lmax/4, lmax] with
+ * lmax each sample's Gershgorin bound max_i sum_j |a_ij| / a_ii; the
+ * coarsest interior block solved exactly (per-sample dense inverse).  Each
+ * sample has its own hierarchy, so the ensemble preconditioner is
+ * M_c = sum_i M_i (x) e_i e_i^T.  The hierarchy lives in one caller-owned
+ * device buffer (256-byte aligned, ens_mg_bytes). */
+typedef struct {
+  int32_t N;      /* fine mesh: N elements per axis                        */
+  int32_t M;      /* KL terms of the problem                                */
+  int32_t s;      /* ensemble size (4, 8, 16, 32)                            */
+  int32_t reserved;
+  void* buffer;   /* (device) hierarchy storage                             */
+  size_t bytes;   /* its size, >= ens_mg_bytes(N, M, s)                     */
+} ens_mg;
+
+ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, size_t* bytes);
+/* Build the coarse levels for the fine matrix `values` [nnz][s] of `graph`
+ * (the N^3 mesh), the KL inputs xi [s][M] (device) and `problem`.  Stream
+ * ordered; never synchronises.  The fine values must stay unchanged while
+ * the hierarchy is used. */
+ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const ens_problem* problem,
+                        const double* xi, hipStream_t stream);
+/* FP64 CG with z = M r from the hierarchy (per-sample scalars and masks, the
+ * stopping rule of ens_cg; opts->mixed and opts->coupled must be 0).
+ * Workspace from ens_cg_workspace_bytes(graph, s, opts).  Synchronises. */
+ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,
+                     const ens_cg_opts* opts, const ens_mg* mg, void* workspace, size_t ws_bytes, ens_cg_stat* stats,
+                     hipStream_t stream);
+
 /* The one-sample baseline with up to `streams` (1..32) solves in flight at
  * once, each on its own library stream (default priority) with its own
  * workspace slice, so that independent solves overlap on the device as they

@@ -27,6 +27,7 @@
 // the active count is zero, and the host reads the count once per chunk of
 // iterations, so the loop ends on the device.
 #include "cgcore.hpp"
+#include "mg.hpp"
 
 namespace ens {
 
@@ -515,6 +516,78 @@ static ens_status cg_scalar_concurrent(const ens_graph* g, int s, const double* 
   return agg;
 }
 
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_update_r(int64_t nchunks, double* __restrict__ x,
+                                                     const double* __restrict__ p, const double* __restrict__ q,
+                                                     double* __restrict__ r, const Ctl* c, double* __restrict__ part) {
+  if (c->n_active == 0) return;
+  update_r_body<S>(nchunks, x, p, q, r, c, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_rz(int64_t nchunks, const double* __restrict__ r,
+                                               const double* __restrict__ z, double* __restrict__ pz, const Ctl* c,
+                                               int gate, double* __restrict__ part) {
+  if (gate && c->n_active == 0) return;
+  rz_body<S>(nchunks, r, z, pz, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_pz(int64_t nchunks, const double* __restrict__ z, double* __restrict__ p,
+                                               const Ctl* c) {
+  if (c->n_active == 0) return;
+  pupdate_z_body<S>(nchunks, z, p, c, blockIdx.x);
+}
+
+// Jacobi-CG's iteration with z = M r from the multigrid cycle: A (q = A p,
+// alpha), the update of x and r with the convergence test, the cycle, then
+// r.z for beta and the new direction.
+template <int S>
+static ens_status cg_mg(const ens_graph* g, const double* vals, const double* b, double* x, const ens_cg_opts& o,
+                        const MgPlan& plan, Work& w, hipStream_t st) {
+  double* r = (double*)w.vec[0];
+  double* p = (double*)w.vec[1];
+  double* q = (double*)w.vec[2];
+  double* z = (double*)w.vec[3];
+  const int64_t n = g->n;
+  const int64_t total = n * S;
+  const int64_t nchunks = n * S / VecMap<double, S>::V;
+  const unsigned sb = grid_for(n, 4 * EnsMap<double, S>::RPW);
+  const unsigned vb = grid_for(nchunks, (int64_t)kBlock * kU);
+  const double spmv_bytes = (double)g->nnz * (S * 8.0 + 4.0) + 4.0 * (n + 1) + 2.0 * n * S * 8.0;
+  residual<S, double>(g, vals, x, b, r, w, OP_START, 0, st);
+  hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
+  mg_vcycle<S>(plan, r, z, w.ctl, st);
+  hipLaunchKernelGGL(k_mg_rz<S>, dim3(vb), dim3(kBlock), 0, st, nchunks, r, z, p, w.ctl, 0, w.part);
+  reduce<S, 2>(w, vb, OP_RHO, 0, 0, st);
+  ENS_LAUNCH_CHECK();
+  for (int k0 = 0; k0 < o.max_iter; k0 += o.check_every) {
+    const int k1 = k0 + o.check_every < o.max_iter ? k0 + o.check_every : o.max_iter;
+    for (int k = k0 + 1; k <= k1; ++k) {
+      prof_begin(ENS_K_SPMV_F64, st);
+      hipLaunchKernelGGL((k_cg_spmv_dot<double, S>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx,
+                         vals, p, q, w.ctl, w.part);
+      prof_end(ENS_K_SPMV_F64, st, spmv_bytes);
+      reduce<S, 1>(w, sb, OP_ALPHA, 0, 1, st);
+      hipLaunchKernelGGL(k_mg_update_r<S>, dim3(vb), dim3(kBlock), 0, st, nchunks, x, p, q, r, w.ctl, w.part);
+      reduce<S, 2>(w, vb, OP_UPDATE_R, k, 1, st);
+      mg_vcycle<S>(plan, r, z, w.ctl, st);
+      hipLaunchKernelGGL(k_mg_rz<S>, dim3(vb), dim3(kBlock), 0, st, nchunks, r, z, (double*)nullptr, w.ctl, 1,
+                         w.part);
+      reduce<S, 2>(w, vb, OP_BETA, 0, 1, st);
+      hipLaunchKernelGGL(k_mg_pz<S>, dim3(vb), dim3(kBlock), 0, st, nchunks, z, p, w.ctl);
+    }
+    ENS_LAUNCH_CHECK();
+    int32_t act = 0;
+    ens_status rc = poll_active(w.ctl, false, st, &act);
+    if (rc != ENS_OK) return rc;
+    if (act == 0) break;
+  }
+  residual<S, double>(g, vals, x, b, (double*)nullptr, w, OP_TRUE, 0, st);
+  ENS_LAUNCH_CHECK();
+  return ENS_OK;
+}
+
 ens_status check_graph(const ens_graph* g);
 
 static ens_cg_opts normalized(const ens_cg_opts* in) {
@@ -591,6 +664,55 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
     ENS_CG_CASE(16)
     ENS_CG_CASE(32)
 #undef ENS_CG_CASE
+  }
+  if (st != ENS_OK) return st;
+  return read_stats(w.ctl, s, stats, stream);
+}
+
+ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,
+                     const ens_cg_opts* opts, const ens_mg* mg, void* workspace, size_t ws_bytes, ens_cg_stat* stats,
+                     hipStream_t stream) {
+  ens_status st = check_graph(graph);
+  if (st != ENS_OK) return st;
+  ENS_ARG_CHECK(opts && stats && mg && mg->buffer, "null options, stats or hierarchy");
+  ENS_ARG_CHECK(values && b && x && workspace, "null device pointer");
+  ENS_ARG_CHECK(aligned16(values) && aligned16(b) && aligned16(x), "buffers must be 16-byte aligned");
+  ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
+  ENS_ARG_CHECK(opts->rtol >= 0.0, "rtol must be >= 0");
+  ENS_ARG_CHECK(!opts->mixed && !opts->coupled, "the multigrid solve is per-sample FP64");
+  ENS_ARG_CHECK(mg->s == s, "hierarchy built for another ensemble size");
+  const int64_t nn = (int64_t)(mg->N + 1) * (mg->N + 1) * (mg->N + 1);
+  ENS_ARG_CHECK(graph->n == nn, "graph is not the hierarchy's fine mesh");
+  if (!supported_s(s)) {
+    set_error("ensemble size %d not compiled in", s);
+    return ENS_E_UNSUPPORTED;
+  }
+  const size_t need = ws_layout(graph->n, s, false, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    return ENS_E_NOMEM;
+  }
+  MgPlan plan;
+  if (!mg_plan(mg->N, mg->M, s, (char*)mg->buffer, &plan)) {
+    set_error("multigrid hierarchy of N=%d is not supported", mg->N);
+    return ENS_E_UNSUPPORTED;
+  }
+  if (mg->bytes < plan.bytes) {
+    set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, plan.bytes);
+    return ENS_E_NOMEM;
+  }
+  mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values);
+  Work w;
+  ws_layout(graph->n, s, false, &w, (char*)workspace);
+  ens_cg_opts o = normalized(opts);
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, w.ctl, o.rtol, o.inner_rtol, o.max_iter,
+                     o.inner_max_iter, o.max_outer, 0, 0);
+  ENS_LAUNCH_CHECK();
+  switch (s) {
+    case 4: st = cg_mg<4>(graph, values, b, x, o, plan, w, stream); break;
+    case 8: st = cg_mg<8>(graph, values, b, x, o, plan, w, stream); break;
+    case 16: st = cg_mg<16>(graph, values, b, x, o, plan, w, stream); break;
+    default: st = cg_mg<32>(graph, values, b, x, o, plan, w, stream); break;
   }
   if (st != ENS_OK) return st;
   return read_stats(w.ctl, s, stats, stream);

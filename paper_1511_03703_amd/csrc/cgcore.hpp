@@ -11,7 +11,8 @@ namespace ens {
 
 constexpr int kMaxS = 32;
 
-enum CgOp { OP_START = 0, OP_RHO = 1, OP_ALPHA = 2, OP_UPDATE = 3, OP_TRUE = 4, OP_OUTER = 5 };
+enum CgOp { OP_START = 0, OP_RHO = 1, OP_ALPHA = 2, OP_UPDATE = 3, OP_TRUE = 4, OP_OUTER = 5, OP_UPDATE_R = 6,
+            OP_BETA = 7 };
 
 struct Ctl {
   double rho[kMaxS], alpha[kMaxS], beta[kMaxS], tol2[kMaxS], bnorm2[kMaxS];
@@ -110,6 +111,35 @@ __device__ void finalize(Ctl* c, int op, int arg) {
           } else if (c->kiter[e] >= cap) {
             c->active[e] = 0;
             if (!c->mixed) c->status[e] = ENS_SAMPLE_MAXITER;
+          } else {
+            c->beta[e] = t0 / c->rho[e];
+            c->rho[e] = t0;
+          }
+        }
+        break;
+      }
+      case OP_UPDATE_R: {  // t1 = r.r after x += alpha p, r -= alpha q (preconditioner applied next)
+        if (c->active[e]) {
+          c->iters[e] += 1;
+          c->kiter[e] += 1;
+          if (!isfinite(t1)) {
+            c->status[e] = ENS_SAMPLE_NONFINITE;
+            c->active[e] = 0;
+          } else if (t1 <= c->tol2[e]) {
+            c->active[e] = 0;
+            c->status[e] = ENS_SAMPLE_CONVERGED;
+          } else if (c->kiter[e] >= c->max_iter) {
+            c->active[e] = 0;
+            c->status[e] = ENS_SAMPLE_MAXITER;
+          }
+        }
+        break;
+      }
+      case OP_BETA: {  // t0 = r.z with z = M r
+        if (c->active[e]) {
+          if (!isfinite(t0)) {
+            c->status[e] = ENS_SAMPLE_NONFINITE;
+            c->active[e] = 0;
           } else {
             c->beta[e] = t0 / c->rho[e];
             c->rho[e] = t0;
@@ -428,6 +458,142 @@ __device__ inline void pupdate_body(int64_t nchunks, const T* __restrict__ r, co
       vt pn = dv[u] * rv[u] + be * pv[u];
 #pragma unroll
       for (int v = 0; v < M::V; ++v)  // inactive samples keep their p
+        if (!act[v]) pn[v] = pv[u][v];
+      store_stream((vt*)p + i, pn);
+    }
+  }
+}
+
+// Multigrid-preconditioned iteration, update half: x += alpha p; r -= alpha
+// q for the active samples; partials (0, r.r) of chunk block `blk` to dst.
+template <int S>
+__device__ inline void update_r_body(int64_t nchunks, double* __restrict__ x, const double* __restrict__ p,
+                                     const double* __restrict__ q, double* __restrict__ r, const Ctl* c, int64_t blk,
+                                     double* __restrict__ dst) {
+  using M = VecMap<double, S>;
+  using vt = typename M::vt;
+  const int sub = (threadIdx.x & 63) % M::L;
+  vt al;
+  int act[M::V];
+#pragma unroll
+  for (int v = 0; v < M::V; ++v) {
+    const int e = M::sample(sub, v);
+    act[v] = c->active[e];
+    al[v] = act[v] ? c->alpha[e] : 0.0;
+  }
+  double acc[2][M::VS];
+#pragma unroll
+  for (int j = 0; j < M::VS; ++j) acc[0][j] = acc[1][j] = 0.0;
+  const int64_t base = blk * kBlock * kU + threadIdx.x;
+  vt pv[kU], qv[kU], rv[kU], xv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      pv[u] = ((const vt*)p)[i];
+      qv[u] = ((const vt*)q)[i];
+      rv[u] = ((const vt*)r)[i];
+      xv[u] = ((const vt*)x)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      vt xn = xv[u] + al * pv[u];
+      vt rn = rv[u] - al * qv[u];
+#pragma unroll
+      for (int v = 0; v < M::V; ++v)
+        if (!act[v]) {
+          xn[v] = xv[u][v];
+          rn[v] = rv[u][v];
+        }
+      xv[u] = xn;
+      rv[u] = rn;
+#pragma unroll
+      for (int v = 0; v < M::V; ++v) {
+        const double rr = act[v] ? rn[v] : 0.0;
+        acc[1][M::slot(v)] += rr * rr;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      store_stream((vt*)x + i, xv[u]);
+      store_stream((vt*)r + i, rv[u]);
+    }
+  }
+  block_partials<S, M::VS, 2, kBlock / 64>(acc, dst);
+}
+
+// Partials (r.z, 0) of chunk block `blk`; with pz, also p = z (start).
+template <int S>
+__device__ inline void rz_body(int64_t nchunks, const double* __restrict__ r, const double* __restrict__ z,
+                               double* __restrict__ pz, int64_t blk, double* __restrict__ dst) {
+  using M = VecMap<double, S>;
+  using vt = typename M::vt;
+  double acc[2][M::VS];
+#pragma unroll
+  for (int j = 0; j < M::VS; ++j) acc[0][j] = acc[1][j] = 0.0;
+  const int64_t base = blk * kBlock * kU + threadIdx.x;
+  vt rv[kU], zv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      rv[u] = ((const vt*)r)[i];
+      zv[u] = ((const vt*)z)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      if (pz) store_stream((vt*)pz + i, zv[u]);
+#pragma unroll
+      for (int v = 0; v < M::V; ++v) acc[0][M::slot(v)] += rv[u][v] * zv[u][v];
+    }
+  }
+  block_partials<S, M::VS, 2, kBlock / 64>(acc, dst);
+}
+
+// p = z + beta p for the samples still active.
+template <int S>
+__device__ inline void pupdate_z_body(int64_t nchunks, const double* __restrict__ z, double* __restrict__ p,
+                                      const Ctl* c, int64_t blk) {
+  using M = VecMap<double, S>;
+  using vt = typename M::vt;
+  const int sub = (threadIdx.x & 63) % M::L;
+  vt be;
+  int act[M::V];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < M::V; ++v) {
+    const int e = M::sample(sub, v);
+    act[v] = c->active[e];
+    be[v] = act[v] ? c->beta[e] : 0.0;
+    any |= act[v] != 0;
+  }
+  if (!any) return;
+  const int64_t base = blk * kBlock * kU + threadIdx.x;
+  vt pv[kU], zv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      pv[u] = ((const vt*)p)[i];
+      zv[u] = ((const vt*)z)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      vt pn = zv[u] + be * pv[u];
+#pragma unroll
+      for (int v = 0; v < M::V; ++v)
         if (!act[v]) pn[v] = pv[u][v];
       store_stream((vt*)p + i, pn);
     }

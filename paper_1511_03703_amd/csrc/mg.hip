@@ -1,0 +1,486 @@
+// Multigrid V-cycle for the ensemble Q1 hierarchy (Sec. 3.5, Alg. vcycle):
+// setup of the coarse levels and the kernels of one cycle.  Every sample
+// has its own hierarchy (the matrices, bounds and coarse inverses are
+// per sample; graphs and transfers are shared), so the ensemble cycle is the
+// stacked per-sample preconditioner M_c = sum_i M_i (x) e_i e_i^T.
+//
+// One level of the cycle, rhs B, result OUT (x0 = 0), theta/delta of the
+// per-sample Chebyshev interval [lmax/4, lmax]:
+//   XA = d = D^-1 B / theta                          (elementwise)
+//   d = c1 d + c2 D^-1 (B - A XA);  XB = XA + d        (row pass)
+//   R = B - A XB                                       (row pass)
+//   B' = P^T R on the coarse level; OUT' = cycle(B')
+//   XB += P OUT'                                       (fine nodes)
+//   d = D^-1 (B - A XB) / theta;  XA = XB + d          (row pass)
+//   d = c1 d + c2 D^-1 (B - A XA);  OUT = XA + d       (row pass)
+// with c1 = rho1 rho0, c2 = 2 rho1 / delta, rho0 = delta / theta,
+// rho1 = 1 / (2 theta / delta - rho0).  The x vectors alternate between two
+// buffers because every row pass gathers its input at neighbouring rows.
+#include <string.h>
+
+#include "cgcore.hpp"
+#include "mg.hpp"
+
+namespace ens {
+
+constexpr int kMgPartRows = 1024;
+
+static size_t r256m(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int mg_levels(int N, int* Ns) {
+  int L = 0;
+  Ns[L++] = N;
+  while (L < kMgMaxLevels && Ns[L - 1] % 2 == 0 && Ns[L - 1] > 4) {
+    Ns[L] = Ns[L - 1] / 2;
+    ++L;
+  }
+  return L;
+}
+
+bool mg_plan(int N, int M, int S, char* base, MgPlan* plan) {
+  int Ns[kMgMaxLevels];
+  plan->levels = mg_levels(N, Ns);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += r256m(bytes);
+    return p;
+  };
+  for (int k = 0; k < plan->levels; ++k) {
+    MgLevel& l = plan->lv[k];
+    l = MgLevel();
+    l.N = Ns[k];
+    l.n = (int64_t)(l.N + 1) * (l.N + 1) * (l.N + 1);
+    l.nnz = (int64_t)(3 * l.N + 1) * (3 * l.N + 1) * (3 * l.N + 1);
+    const size_t vb = (size_t)l.n * S * sizeof(double);
+    if (k > 0) {
+      size_t klb = 0;
+      if (ens_kl_bytes(l.N, M, &klb) != ENS_OK) return false;
+      l.own_rp = (int32_t*)take(sizeof(int32_t) * (l.n + 1));
+      l.own_ci = (int32_t*)take(sizeof(int32_t) * l.nnz);
+      l.own_vals = (double*)take(sizeof(double) * l.nnz * S);
+      l.kl = take(klb);
+      l.rp = l.own_rp;
+      l.ci = l.own_ci;
+      l.vals = l.own_vals;
+      l.b = (double*)take(vb);
+    }
+    l.dinv = (double*)take(vb);
+    l.lmax = (double*)take(sizeof(double) * S);
+    l.xa = (double*)take(vb);
+    l.xb = (double*)take(vb);
+    l.r = (double*)take(vb);
+    l.d = (double*)take(vb);
+  }
+  MgLevel& c = plan->lv[plan->levels - 1];
+  c.m = (int64_t)(c.N - 1) * (c.N - 1) * (c.N - 1);
+  if (c.m > kMgMaxCoarse) return false;
+  c.ainv = (double*)take(sizeof(double) * S * (c.m > 0 ? c.m * c.m : 1));
+  plan->part = (double*)take(sizeof(double) * kMgPartRows * S);
+  plan->bytes = off;
+  return true;
+}
+
+void mg_attach_fine(MgPlan* plan, const int32_t* rp, const int32_t* ci, const double* vals) {
+  plan->lv[0].rp = rp;
+  plan->lv[0].ci = ci;
+  plan->lv[0].vals = vals;
+}
+
+// --------------------------------------------------------------- kernels ---
+
+__device__ inline bool mg_idle(const Ctl* gate) { return gate && gate->n_active == 0; }
+
+// Chebyshev constants of sample e's interval [lmax/4, lmax].
+struct ChebK {
+  double inv_theta, c1, c2;
+};
+__device__ inline ChebK cheb_consts(double lmax) {
+  const double hi = lmax, lo = lmax / kMgRatio;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+  const double sigma = theta / delta;
+  const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+  return ChebK{1.0 / theta, rho1 * rho0, 2.0 * rho1 / delta};
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_dinv(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                 const double* __restrict__ vals, double* __restrict__ dinv) {
+  diag_inv_body<double, S>(n, rp, ci, vals, dinv, blockIdx.x);
+}
+
+// Per-sample Gershgorin bound max_i sum_j |a_ij| / a_ii: block maxima over
+// a grid-stride range of rows, then one block over the block maxima.
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_gersh(int64_t n, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, const double* __restrict__ vals,
+                                                  double* __restrict__ part) {
+  constexpr int G = 256 / S;
+  __shared__ double red[G][S];
+  const int e = threadIdx.x % S, g = threadIdx.x / S;
+  double m = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * G + g; row < n; row += (int64_t)gridDim.x * G) {
+    double s = 0.0, dg = 0.0;
+    for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
+      const double v = vals[k * S + e];
+      s += fabs(v);
+      if (ci[k] == row) dg = v;
+    }
+    const double q = s / dg;
+    m = q > m ? q : m;
+  }
+  red[g][e] = m;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double t = red[0][e];
+    for (int j = 1; j < G; ++j) t = red[j][e] > t ? red[j][e] : t;
+    part[(int64_t)blockIdx.x * S + e] = t;
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_max(const double* __restrict__ part, int rows, double* __restrict__ out) {
+  if (threadIdx.x < S) {
+    double t = 0.0;
+    for (int r = 0; r < rows; ++r) {
+      const double v = part[(int64_t)r * S + threadIdx.x];
+      t = v > t ? v : t;
+    }
+    out[threadIdx.x] = t;
+  }
+}
+
+// Dense inverse of sample e's interior block of the coarsest matrix, by
+// Gauss-Jordan elimination in place (the block is symmetric positive
+// definite, so the diagonal pivots are positive).  One workgroup per sample.
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_inverse(int N, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const double* __restrict__ vals,
+                                                    int64_t m, double* __restrict__ ainv) {
+  __shared__ double f[kMgMaxCoarse];
+  const int e = blockIdx.x;
+  double* A = ainv + (int64_t)e * m * m;
+  const int I = N - 1;  // interior nodes per axis
+  for (int64_t t = threadIdx.x; t < m * m; t += blockDim.x) A[t] = 0.0;
+  __syncthreads();
+  for (int64_t a = threadIdx.x; a < m; a += blockDim.x) {
+    const int i = 1 + (int)(a % I), j = 1 + (int)((a / I) % I), k = 1 + (int)(a / ((int64_t)I * I));
+    const int64_t row = i + (int64_t)(N + 1) * (j + (int64_t)(N + 1) * k);
+    for (int64_t q = rp[row]; q < rp[row + 1]; ++q) {
+      const int64_t col = ci[q];
+      const int ci_ = (int)(col % (N + 1)), cj = (int)((col / (N + 1)) % (N + 1)), ck = (int)(col / ((int64_t)(N + 1) * (N + 1)));
+      if (ci_ == 0 || cj == 0 || ck == 0 || ci_ == N || cj == N || ck == N) continue;
+      const int64_t b = (ci_ - 1) + (int64_t)I * ((cj - 1) + (int64_t)I * (ck - 1));
+      A[a * m + b] = vals[q * S + e];
+    }
+  }
+  __syncthreads();
+  for (int64_t p = 0; p < m; ++p) {
+    const double piv = A[p * m + p];
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) A[p * m + j] = (j == p ? 1.0 : A[p * m + j]) / piv;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) f[i] = A[i * m + p];
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < m * m; t += blockDim.x) {
+      const int64_t i = t / m, j = t % m;
+      if (i == p) continue;
+      A[t] = (j == p ? 0.0 : A[t]) - f[i] * A[p * m + j];
+    }
+    __syncthreads();
+  }
+}
+
+// XA = d = D^-1 B / theta (first Chebyshev step from x = 0).
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_cheb0(int64_t nchunks, const double* __restrict__ b,
+                                                  const double* __restrict__ dinv, const double* __restrict__ lmax,
+                                                  double* __restrict__ xa, double* __restrict__ d, const Ctl* gate) {
+  if (mg_idle(gate)) return;
+  using VM = VecMap<double, S>;
+  using vt = typename VM::vt;
+  const int sub = (threadIdx.x & 63) % VM::L;
+  vt it;
+#pragma unroll
+  for (int v = 0; v < VM::V; ++v) it[v] = cheb_consts(lmax[VM::sample(sub, v)]).inv_theta;
+  const int64_t base = (int64_t)blockIdx.x * kBlock * kU + threadIdx.x;
+  vt bv[kU], dv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      bv[u] = ((const vt*)b)[i];
+      dv[u] = ((const vt*)dinv)[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int64_t i = base + u * kBlock;
+    if (i < nchunks) {
+      const vt dd = dv[u] * bv[u] * it;
+      ((vt*)d)[i] = dd;
+      ((vt*)xa)[i] = dd;
+    }
+  }
+}
+
+enum MgRowMode { MG_RES = 0, MG_CHEB1 = 1, MG_CHEB2 = 2 };
+
+// Row passes of the cycle (one row tile of 4 wavefronts per block):
+//   MG_RES:   r = B - A x
+//   MG_CHEB1: d = D^-1 (B - A x) / theta;           xout = x + d
+//   MG_CHEB2: d = c1 d + c2 D^-1 (B - A x);          xout = x + d
+template <int S, int MODE>
+__global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                const double* __restrict__ vals, const double* __restrict__ x,
+                                                const double* __restrict__ b, const double* __restrict__ dinv,
+                                                const double* __restrict__ lmax, double* __restrict__ d,
+                                                double* __restrict__ out, const Ctl* gate) {
+  if (mg_idle(gate)) return;
+  using M = EnsMap<double, S>;
+  using vt = typename M::vt;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane % M::L;
+  const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
+  if (row >= n) return;
+  const vt ax = ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
+  const int64_t i = row * M::L + sub;
+  const vt res = ((const vt*)b)[i] - ax;
+  if (MODE == MG_RES) {
+    store_stream((vt*)out + i, res);
+    return;
+  }
+  vt k1, k2;
+#pragma unroll
+  for (int v = 0; v < M::V; ++v) {
+    const ChebK c = cheb_consts(lmax[sub * M::V + v]);
+    k1[v] = MODE == MG_CHEB1 ? 0.0 : c.c1;
+    k2[v] = MODE == MG_CHEB1 ? c.inv_theta : c.c2;
+  }
+  const vt dv = ((const vt*)dinv)[i] * res;
+  vt dn;
+  if (MODE == MG_CHEB1) dn = k2 * dv;
+  else dn = k1 * ((const vt*)d)[i] + k2 * dv;
+  ((vt*)d)[i] = dn;
+  store_stream((vt*)out + i, ((const vt*)x)[i] + dn);
+}
+
+// Coarse interior node c collects the residual of the fine interior nodes
+// around fine node 2c (weight 1 on the axis, 1/2 one step off), in a fixed
+// order; coarse boundary nodes get 0.
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_restrict(int Nc, const double* __restrict__ rf, double* __restrict__ bc,
+                                                     const Ctl* gate) {
+  if (mg_idle(gate)) return;
+  using VM = VecMap<double, S>;
+  using vt = typename VM::vt;
+  const int Nf = 2 * Nc;
+  const int64_t nc = (int64_t)(Nc + 1) * (Nc + 1) * (Nc + 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * VM::L) return;
+  const int64_t node = t / VM::L;
+  const int sub = (int)(t % VM::L);
+  const int I = (int)(node % (Nc + 1)), J = (int)((node / (Nc + 1)) % (Nc + 1)), K = (int)(node / ((int64_t)(Nc + 1) * (Nc + 1)));
+  vt acc = (vt)0.0;
+  if (I > 0 && J > 0 && K > 0 && I < Nc && J < Nc && K < Nc) {
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+          if (i <= 0 || j <= 0 || k <= 0 || i >= Nf || j >= Nf || k >= Nf) continue;
+          const double w = (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0);
+          const int64_t f = i + (int64_t)(Nf + 1) * (j + (int64_t)(Nf + 1) * k);
+          acc += w * ((const vt*)rf)[f * VM::L + sub];
+        }
+  }
+  ((vt*)bc)[t] = acc;
+}
+
+// Fine interior node: xf += sum of its interior coarse parents with the
+// trilinear weights.
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_prolong(int Nc, const double* __restrict__ xc, double* __restrict__ xf,
+                                                    const Ctl* gate) {
+  if (mg_idle(gate)) return;
+  using VM = VecMap<double, S>;
+  using vt = typename VM::vt;
+  const int Nf = 2 * Nc;
+  const int64_t nf = (int64_t)(Nf + 1) * (Nf + 1) * (Nf + 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nf * VM::L) return;
+  const int64_t node = t / VM::L;
+  const int sub = (int)(t % VM::L);
+  const int i = (int)(node % (Nf + 1)), j = (int)((node / (Nf + 1)) % (Nf + 1)), k = (int)(node / ((int64_t)(Nf + 1) * (Nf + 1)));
+  if (i == 0 || j == 0 || k == 0 || i == Nf || j == Nf || k == Nf) return;
+  int Ii[2], Jj[2], Kk[2];
+  double wi[2], wj[2], wk[2];
+  auto parents = [](int q, int* P, double* w) -> int {
+    if (q % 2 == 0) {
+      P[0] = q / 2;
+      w[0] = 1.0;
+      return 1;
+    }
+    P[0] = (q - 1) / 2;
+    w[0] = 0.5;
+    P[1] = (q + 1) / 2;
+    w[1] = 0.5;
+    return 2;
+  };
+  const int ni = parents(i, Ii, wi), nj = parents(j, Jj, wj), nk = parents(k, Kk, wk);
+  vt acc = (vt)0.0;
+  for (int c = 0; c < nk; ++c)
+    for (int bq = 0; bq < nj; ++bq)
+      for (int a = 0; a < ni; ++a) {
+        const int I = Ii[a], J = Jj[bq], K = Kk[c];
+        if (I == 0 || J == 0 || K == 0 || I == Nc || J == Nc || K == Nc) continue;
+        const int64_t cn = I + (int64_t)(Nc + 1) * (J + (int64_t)(Nc + 1) * K);
+        acc += (wi[a] * wj[bq] * wk[c]) * ((const vt*)xc)[cn * VM::L + sub];
+      }
+  ((vt*)xf)[t] = ((const vt*)xf)[t] + acc;
+}
+
+// Coarsest level: boundary rows are identities (x = B), interior rows take
+// the per-sample dense inverse.
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_coarse(int Nc, int64_t m, const double* __restrict__ ainv,
+                                                   const double* __restrict__ b, double* __restrict__ x,
+                                                   const Ctl* gate) {
+  if (mg_idle(gate)) return;
+  const int64_t n = (int64_t)(Nc + 1) * (Nc + 1) * (Nc + 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * S) return;
+  const int64_t node = t / S;
+  const int e = (int)(t % S);
+  const int i = (int)(node % (Nc + 1)), j = (int)((node / (Nc + 1)) % (Nc + 1)), k = (int)(node / ((int64_t)(Nc + 1) * (Nc + 1)));
+  if (i == 0 || j == 0 || k == 0 || i == Nc || j == Nc || k == Nc) {
+    x[t] = b[t];
+    return;
+  }
+  const int I = Nc - 1;
+  const int64_t a = (i - 1) + (int64_t)I * ((j - 1) + (int64_t)I * (k - 1));
+  const double* row = ainv + ((int64_t)e * m + a) * m;
+  double acc = 0.0;
+  for (int64_t c = 0; c < m; ++c) {
+    const int ii = 1 + (int)(c % I), jj = 1 + (int)((c / I) % I), kk = 1 + (int)(c / ((int64_t)I * I));
+    const int64_t cn = ii + (int64_t)(Nc + 1) * (jj + (int64_t)(Nc + 1) * kk);
+    acc += row[c] * b[cn * S + e];
+  }
+  x[t] = acc;
+}
+
+// ------------------------------------------------------------ host side ---
+
+static unsigned blocks_for(int64_t items, int64_t per) {
+  const int64_t b = (items + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+template <int S>
+static void cycle(const MgPlan& P, int k, const double* B, double* OUT, const Ctl* gate, hipStream_t st) {
+  using EM = EnsMap<double, S>;
+  using VM = VecMap<double, S>;
+  const MgLevel& l = P.lv[k];
+  if (k == P.levels - 1) {
+    hipLaunchKernelGGL(k_mg_coarse<S>, dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, l.N, l.m, l.ainv, B, OUT,
+                       gate);
+    return;
+  }
+  const MgLevel& c = P.lv[k + 1];
+  const int64_t nchunks = l.n * S / VM::V;
+  const unsigned rb = blocks_for(l.n, 4 * EM::RPW);
+  hipLaunchKernelGGL(k_mg_cheb0<S>, dim3(blocks_for(nchunks, (int64_t)kBlock * kU)), dim3(kBlock), 0, st, nchunks, B,
+                     l.dinv, l.lmax, l.xa, l.d, gate);
+  hipLaunchKernelGGL((k_mg_row<S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xa, B,
+                     l.dinv, l.lmax, l.d, l.xb, gate);
+  hipLaunchKernelGGL((k_mg_row<S, MG_RES>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xb, B,
+                     l.dinv, l.lmax, l.d, l.r, gate);
+  hipLaunchKernelGGL(k_mg_restrict<S>, dim3(blocks_for(c.n * VM::L, 256)), dim3(256), 0, st, c.N, l.r, c.b, gate);
+  cycle<S>(P, k + 1, c.b, c.xb, gate, st);
+  hipLaunchKernelGGL(k_mg_prolong<S>, dim3(blocks_for(l.n * VM::L, 256)), dim3(256), 0, st, c.N, c.xb, l.xb, gate);
+  hipLaunchKernelGGL((k_mg_row<S, MG_CHEB1>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xb, B,
+                     l.dinv, l.lmax, l.d, l.xa, gate);
+  hipLaunchKernelGGL((k_mg_row<S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xa, B,
+                     l.dinv, l.lmax, l.d, OUT, gate);
+}
+
+template <int S>
+void mg_vcycle(const MgPlan& plan, const double* r, double* z, const Ctl* gate, hipStream_t st) {
+  cycle<S>(plan, 0, r, z, gate, st);
+}
+
+template void mg_vcycle<4>(const MgPlan&, const double*, double*, const Ctl*, hipStream_t);
+template void mg_vcycle<8>(const MgPlan&, const double*, double*, const Ctl*, hipStream_t);
+template void mg_vcycle<16>(const MgPlan&, const double*, double*, const Ctl*, hipStream_t);
+template void mg_vcycle<32>(const MgPlan&, const double*, double*, const Ctl*, hipStream_t);
+
+template <int S>
+static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* xi, hipStream_t st) {
+  for (int k = 0; k < P.levels; ++k) {
+    const MgLevel& l = P.lv[k];
+    if (k > 0) {
+      ens_status rc = ens_graph_build(l.N, l.own_rp, l.own_ci, st);
+      if (rc == ENS_OK) rc = ens_kl_build(l.N, prob.M, prob.L, l.kl, st);
+      ens_graph g{(int32_t)l.n, l.nnz, l.own_rp, l.own_ci};
+      if (rc == ENS_OK) rc = ens_assemble(l.N, &g, l.kl, &prob, S, xi, l.own_vals, nullptr, l.b, st);
+      if (rc != ENS_OK) return rc;
+    }
+    hipLaunchKernelGGL(k_mg_dinv<S>, dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals,
+                       l.dinv);
+    const unsigned gb = blocks_for(l.n, 256 / S) < (unsigned)kMgPartRows ? blocks_for(l.n, 256 / S) : kMgPartRows;
+    hipLaunchKernelGGL(k_mg_gersh<S>, dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals, P.part);
+    hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(64), 0, st, P.part, (int)gb, l.lmax);
+  }
+  const MgLevel& c = P.lv[P.levels - 1];
+  if (c.m > 0)
+    hipLaunchKernelGGL(k_mg_inverse<S>, dim3(S), dim3(256), 0, st, c.N, c.rp, c.ci, c.vals, c.m, c.ainv);
+  ENS_LAUNCH_CHECK();
+  return ENS_OK;
+}
+
+}  // namespace ens
+
+using namespace ens;
+
+extern "C" {
+
+ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, size_t* bytes) {
+  ENS_ARG_CHECK(bytes && N >= 1 && M >= 0, "bad multigrid arguments");
+  if (!supported_s(s)) {
+    set_error("ensemble size %d not compiled in", s);
+    return ENS_E_UNSUPPORTED;
+  }
+  MgPlan plan;
+  if (!mg_plan(N, M, s, nullptr, &plan)) {
+    set_error("coarsest multigrid level of N=%d has more than %lld interior unknowns", N, (long long)kMgMaxCoarse);
+    return ENS_E_UNSUPPORTED;
+  }
+  *bytes = plan.bytes;
+  return ENS_OK;
+}
+
+ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const ens_problem* problem,
+                        const double* xi, hipStream_t stream) {
+  ENS_ARG_CHECK(mg && graph && values && problem && xi && mg->buffer, "null multigrid argument");
+  ENS_ARG_CHECK(((uintptr_t)mg->buffer & 255u) == 0, "multigrid buffer must be 256-byte aligned");
+  ENS_ARG_CHECK(aligned16(values), "values must be 16-byte aligned");
+  ENS_ARG_CHECK(problem->M == mg->M, "problem->M differs from the hierarchy's M");
+  const int64_t n = (int64_t)(mg->N + 1) * (mg->N + 1) * (mg->N + 1);
+  ENS_ARG_CHECK(graph->n == n && graph->row_ptr && graph->col_idx, "graph is not the N^3 mesh's graph");
+  MgPlan plan;
+  size_t need = 0;
+  ens_status rc = ens_mg_bytes(mg->N, mg->M, mg->s, &need);
+  if (rc != ENS_OK) return rc;
+  if (mg->bytes < need) {
+    set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, need);
+    return ENS_E_NOMEM;
+  }
+  mg_plan(mg->N, mg->M, mg->s, (char*)mg->buffer, &plan);
+  mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values);
+  switch (mg->s) {
+    case 4: return setup<4>(plan, *problem, xi, stream);
+    case 8: return setup<8>(plan, *problem, xi, stream);
+    case 16: return setup<16>(plan, *problem, xi, stream);
+    default: return setup<32>(plan, *problem, xi, stream);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+"""GPU parity of the multigrid-preconditioned ensemble CG against the
+oracle's per-sample MG-PCG (same hierarchy, transfers, smoother and coarse
+solve).  Bars: at each sample's GPU iteration count the oracle's iterate
+agrees to relative 1e-9; the oracle's own count is within +-1; the true
+residual meets the tolerance."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import draw_xi
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1511_03703_amd import ens
+    ens.lib()
+    assert torch.cuda.is_available()
+    return ens
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _system(E, N, s, M, sigma, xi):
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    vals, _, rhs = E.assemble(g, kl, xt, M, sigma)
+    mg = E.Multigrid(N, M, s).setup(g, vals, xt, sigma)
+    return g, vals, rhs, mg
+
+
+@pytest.mark.parametrize("N,s", [(8, 4), (12, 8), (16, 32), (6, 16), (20, 8)])
+def test_mg_cg_matches_oracle(E, orc, N, s):
+    M, sigma, rtol = 10, 0.3, 1e-10
+    xi = draw_xi(1400 + N, s, M)
+    g, vals, rhs, mg = _system(E, N, s, M, sigma, xi)
+    x, stats, st = E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts(rtol=rtol, check_every=4))
+    assert st == E.ENS_OK, stats
+    iters = np.array([t["iters"] for t in stats], np.int32)
+    xo, _, _, _, _ = orc.ens_mg_pcg(N, M, 1.0, 1.0, sigma, 1.0, xi, fixed_iters=iters)
+    _, ito, _, sto, _ = orc.ens_mg_pcg(N, M, 1.0, 1.0, sigma, 1.0, xi, rtol=rtol)
+    xg = _np(x)
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    true_res = orc.ens_true_residual(rp, ci, ov, ob, xg)
+    for e in range(s):
+        assert stats[e]["status"] == 0
+        assert _rel(xg[:, e], xo[:, e]) <= 1e-9, (e, _rel(xg[:, e], xo[:, e]))
+        assert abs(int(ito[e]) - int(iters[e])) <= 1, (e, ito[e], iters[e])
+        assert true_res[e] <= rtol * (1 + 1e-6)
+        assert abs(stats[e]["rel_res"] - true_res[e]) <= 1e-6 * rtol + 1e-3 * true_res[e]
+    # far fewer iterations than Jacobi-CG on the same samples
+    _, stj, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=rtol))
+    assert max(iters) < min(t["iters"] for t in stj)
+
+
+def test_single_level_is_an_exact_solve(E):
+    # an odd mesh has no coarser level: the preconditioner is A^-1 itself
+    N, s, M = 7, 8, 10
+    g, vals, rhs, mg = _system(E, N, s, M, 0.3, draw_xi(1450, s, M))
+    x, stats, st = E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts(rtol=1e-12))
+    assert st == E.ENS_OK and all(t["iters"] == 1 for t in stats)
+
+
+def test_mg_edge_cases_and_errors(E):
+    N, s, M = 8, 8, 10
+    xi = draw_xi(1460, s, M)
+    g, vals, rhs, mg = _system(E, N, s, M, 0.2, xi)
+    # zero right-hand side with a nonzero start: x = 0, no iterations
+    x, stats, st = E.cg_mg(g, vals, torch.zeros_like(rhs), mg, x=torch.ones_like(rhs))
+    assert st == E.ENS_OK and not _np(x).any() and all(t["iters"] == 0 for t in stats)
+    # iteration cap
+    x, stats, st = E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts(rtol=1e-15, max_iter=2))
+    assert st == E.ENS_W_NOT_CONVERGED and all(t["iters"] == 2 and t["status"] == E.SAMPLE_MAXITER for t in stats)
+    # a NaN sample does not disturb the others
+    xi2 = xi.copy()
+    xi2[2, 0] = np.nan
+    g2, v2, b2, mg2 = _system(E, N, s, M, 0.2, xi2)
+    x, stats, st = E.cg_mg(g2, v2, b2, mg2)
+    assert stats[2]["status"] == E.SAMPLE_NONFINITE
+    assert all(stats[e]["status"] == 0 for e in range(s) if e != 2)
+    # refusals
+    with pytest.raises(E.EnsError):
+        E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts(mixed=True))
+    with pytest.raises(E.EnsError):
+        E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts(coupled=True))
+    g9 = E.graph_build(9)
+    v9, _, b9 = E.assemble(g9, E.kl_build(9, M), torch.as_tensor(xi, device=DEV), M, 0.2)
+    with pytest.raises(E.EnsError):
+        E.cg_mg(g9, v9, b9, mg)
+    with pytest.raises(E.EnsError) as ex:
+        E.Multigrid(11, M, s)  # odd 11: a 1000-unknown coarse block
+    assert ex.value.status == E.ENS_E_UNSUPPORTED
+
+
+def test_mg_is_deterministic(E):
+    N, s, M = 16, 16, 10
+    xi = draw_xi(1470, s, M)
+    out = []
+    for _ in range(2):
+        g, vals, rhs, mg = _system(E, N, s, M, 0.3, xi)
+        x, stats, _ = E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts(rtol=1e-10))
+        out.append((_np(x), stats))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
