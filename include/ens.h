@@ -424,14 +424,15 @@ enum {
   ENS_K_SPMV_F32 = 1,   /* ensemble SpMV, FP32 (refinement inner loop)   */
   ENS_K_ASSEMBLE = 2,
   ENS_K_SCALAR_SPMV = 3,
-  ENS_K_COUNT = 4
+  ENS_K_MG_ROW = 4,     /* fine-level row passes of the multigrid cycle   */
+  ENS_K_COUNT = 5
 };
 ens_status ens_prof_enable(int32_t on);
 ens_status ens_prof_reset(void);
 /* Totals since the last reset over the working launches of a kernel:
  * summed event durations (ms), launch count, and algorithmic bytes (the
- * kernel's byte model, summed per launch).  Launches shorter than a quarter
- * of the median duration -- solver kernels that found no active sample and
+ * kernel's byte model, summed per launch).  Launches shorter than 5 % of
+ * the longest one -- solver kernels that found no active sample and
  * returned at once -- are left out. */
 ens_status ens_prof_query(int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
 

@@ -1101,4 +1101,13 @@ int orc_ens_mg_pcg(int N, int M, double L, double kappa0, double sigma, double f
   return rc;
 }
 
+/* Threads an OpenMP loop of the oracle may use (1 without OpenMP). */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int orc_version(void) { return 1; }

@@ -300,6 +300,10 @@ def mg_apply(N, M, L, kappa0, sigma, fconst, xi, r):
     return z
 
 
+def max_threads():
+    return int(lib().orc_max_threads())
+
+
 def ens_mg_pcg(N, M, L, kappa0, sigma, fconst, xi, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=None):
     """Multigrid-preconditioned CG per sample (each sample its own hierarchy).
     Returns (x [n][s], iters, rel_res, status, lmax [s][levels])."""

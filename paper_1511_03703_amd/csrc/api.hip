@@ -221,11 +221,9 @@ ens_status ens_prof_query(int32_t kernel_id, double* total_ms, int64_t* launches
   double tot = 0.0, by = 0.0;
   int64_t cnt = 0;
   if (!d.empty()) {
-    std::vector<float> sorted(d);
-    std::nth_element(sorted.begin(), sorted.begin() + sorted.size() / 2, sorted.end());
-    const float med = sorted[sorted.size() / 2];
+    const float longest = *std::max_element(d.begin(), d.end());
     for (size_t i = 0; i < d.size(); ++i)
-      if (d[i] >= 0.25f * med) {  // launches that found no work return at once
+      if (d[i] >= 0.05f * longest) {  // launches that found no work return at once
         tot += d[i];
         by += g_by[kernel_id][i];
         ++cnt;

@@ -387,19 +387,32 @@ static void cycle(const MgPlan& P, int k, const double* B, double* OUT, const Ct
   const MgLevel& c = P.lv[k + 1];
   const int64_t nchunks = l.n * S / VM::V;
   const unsigned rb = blocks_for(l.n, 4 * EM::RPW);
+  // algorithmic bytes of the fine row passes: the matrix and the gathered
+  // x once, plus (vectors read + written) x n x S x 8
+  const double mat = (double)l.nnz * (S * 8.0 + 4.0) + 4.0 * (l.n + 1);
+  const double vec = (double)l.n * S * 8.0;
+  const bool fine = k == 0;
   hipLaunchKernelGGL(k_mg_cheb0<S>, dim3(blocks_for(nchunks, (int64_t)kBlock * kU)), dim3(kBlock), 0, st, nchunks, B,
                      l.dinv, l.lmax, l.xa, l.d, gate);
+  if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xa, B,
                      l.dinv, l.lmax, l.d, l.xb, gate);
+  if (fine) prof_end(ENS_K_MG_ROW, st, mat + 6.0 * vec);
+  if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<S, MG_RES>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xb, B,
                      l.dinv, l.lmax, l.d, l.r, gate);
+  if (fine) prof_end(ENS_K_MG_ROW, st, mat + 3.0 * vec);
   hipLaunchKernelGGL(k_mg_restrict<S>, dim3(blocks_for(c.n * VM::L, 256)), dim3(256), 0, st, c.N, l.r, c.b, gate);
   cycle<S>(P, k + 1, c.b, c.xb, gate, st);
   hipLaunchKernelGGL(k_mg_prolong<S>, dim3(blocks_for(l.n * VM::L, 256)), dim3(256), 0, st, c.N, c.xb, l.xb, gate);
+  if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<S, MG_CHEB1>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xb, B,
                      l.dinv, l.lmax, l.d, l.xa, gate);
+  if (fine) prof_end(ENS_K_MG_ROW, st, mat + 5.0 * vec);
+  if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xa, B,
                      l.dinv, l.lmax, l.d, OUT, gate);
+  if (fine) prof_end(ENS_K_MG_ROW, st, mat + 6.0 * vec);
 }
 
 template <int S>

@@ -20,7 +20,7 @@ ENS_OK, ENS_W_NOT_CONVERGED = 0, 1
 ENS_E_ARG, ENS_E_UNSUPPORTED, ENS_E_HIP, ENS_E_NOMEM, ENS_E_RANGE = -1, -2, -3, -4, -5
 SAMPLE_CONVERGED, SAMPLE_MAXITER, SAMPLE_BREAKDOWN, SAMPLE_NONFINITE, SAMPLE_STAGNATED = 0, 1, 2, 3, 4
 F64, F32 = 0, 1
-K_SPMV_F64, K_SPMV_F32, K_ASSEMBLE, K_SCALAR_SPMV = 0, 1, 2, 3
+K_SPMV_F64, K_SPMV_F32, K_ASSEMBLE, K_SCALAR_SPMV, K_MG_ROW = 0, 1, 2, 3, 4
 
 
 class EnsError(RuntimeError):
