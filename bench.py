@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--batch-s", type=int, default=0, help="batch: fix s (skip the autotuner)")
     ap.add_argument("--batch-tile", type=int, default=4, help="batch: tile when --batch-s is given")
     ap.add_argument("--train-steps", type=int, default=8000, help="learned: Adam steps")
+    ap.add_argument("--mg-fp64", action="store_true",
+                    help="mg: FP64 CG with an FP64 cycle instead of the FP32-in-FP64 refinement")
     ap.add_argument("--lr-halvings", type=int, default=3,
                     help="learned: the step count is split into this many + 1 equal stages, lr halved per stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -657,21 +659,23 @@ def run_mg(args):
     g = ens.graph_build(w.N)
     kl = ens.kl_build(w.N, w.M, w.L)
     xi = torch.as_tensor(w.xi(), device=dev)
+    mixed = not args.mg_fp64
     vals = torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
+    v32 = torch.empty((w.nnz, w.s), dtype=torch.float32, device=dev) if mixed else None
     rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
     x = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)
-    mg = ens.Multigrid(w.N, w.M, w.s, device=dev)
+    mg = ens.Multigrid(w.N, w.M, w.s, fp32=mixed, device=dev)
     # a handful of iterations: poll every 4 so few launches run after convergence
     check = min(args.check_every, 4)
-    opts = ens.cg_opts(rtol=w.rtol, check_every=check)
+    opts = ens.cg_opts(rtol=w.rtol, check_every=check, mixed=mixed, inner_rtol=args.inner_rtol)
     ws = torch.empty(ens.cg_workspace_bytes(g, w.s, opts), dtype=torch.uint8, device=dev)
     log(f"mg workload: N={w.N} s={w.s} hierarchy {mg.buffer.numel() / 2**30:.2f} GiB")
 
     def step():
-        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, rhs=rhs)
-        mg.setup(g, vals, xi, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f)
+        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, values32=v32, rhs=rhs)
+        mg.setup(g, vals, xi, w.sigma, values32=v32, L=w.L, kappa0=w.kappa0, f=w.f)
         x.zero_()
-        return ens.cg_mg(g, vals, rhs, mg, x=x, opts=opts, workspace=ws)
+        return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=opts, workspace=ws)
 
     for i in range(args.warmup):
         _, stats, st = step()
@@ -686,18 +690,20 @@ def run_mg(args):
     elapsed = time.perf_counter() - t0
     ens.prof_enable(False)
     pr = ens.prof_query(ens.K_MG_ROW)
-    ps = ens.prof_query(ens.K_SPMV_F64)
+    ps = ens.prof_query(ens.K_SPMV_F32 if mixed else ens.K_SPMV_F64)
     ok = all(t["status"] == 0 and t["rel_res"] <= w.rtol * (1 + 1e-6) for t in stats)
     achieved = pr["bytes"] / (pr["total_ms"] * 1e-3) / 1e9 if pr["launches"] else 0.0
     out = {
-        "metric": "solved samples/s at 128^3, s=32, 1e-8 resid, multigrid-preconditioned FP64 CG",
+        "metric": ("solved samples/s at 128^3, s=32, 1e-8 resid, multigrid-preconditioned "
+                   + ("FP32 CG inside FP64 refinement" if mixed else "FP64 CG")),
         "value": round(args.steps * w.s / elapsed, 3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "q1_128cube_s32_mg_fp64", "mesh": f"{w.N}^3 Q1 hexahedra", "n": w.n, "nnz": w.nnz,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-in-f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": "q1_128cube_s32_mg_mixed" if mixed else "q1_128cube_s32_mg_fp64", "mesh": f"{w.N}^3 Q1 hexahedra", "n": w.n, "nnz": w.nnz,
                    "s": w.s, "M": w.M, "sigma": w.sigma, "rtol": w.rtol, "seed": w.seed,
                    "levels": "128,64,32,16,8,4", "smoother": "Chebyshev order 2 on [lmax/4, lmax]",
-                   "coarse": "dense inverse of the 4^3 interior block", "check_every": check},
+                   "coarse": "dense inverse of the 4^3 interior block", "check_every": check,
+                   "inner_rtol": args.inner_rtol if mixed else None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_mg_row<32,*> (fine-level Chebyshev and residual passes)",
@@ -706,17 +712,28 @@ def run_mg(args):
                      "bytes_per_launch": round(pr["bytes"] / max(pr["launches"], 1))},
         "all_converged": bool(ok),
         "iters": [t["iters"] for t in stats],
+        "outer_iters": [t["outer_iters"] for t in stats],
         "cg_spmv_GBs": round(ps["bytes"] / (ps["total_ms"] * 1e-3) / 1e9, 1) if ps["launches"] else None,
     }
     if not args.no_context:
+        xs = x.clone()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         x.zero_()
         _, stj, _ = ens.cg(g, vals, rhs, x=x, opts=ens.cg_opts(rtol=w.rtol, check_every=args.check_every))
         torch.cuda.synchronize()
         tj = time.perf_counter() - t1
+        # per-sample error against an FP64 multigrid solve to 1e-12
+        mg64 = ens.Multigrid(w.N, w.M, w.s, device=dev).setup(g, vals, xi, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f)
+        xr = torch.zeros_like(x)
+        ens.cg_mg(g, vals, rhs, mg64, x=xr, opts=ens.cg_opts(rtol=1e-12, check_every=4), workspace=None)
+        a, r_ = xs.cpu().numpy(), xr.cpu().numpy()
+        err = [float(np.linalg.norm(a[:, e] - r_[:, e]) / np.linalg.norm(r_[:, e])) for e in range(w.s)]
+        del mg64, xr
         out["context"] = {"jacobi_fp64_ensemble_cg": {"seconds_solve_only": round(tj, 4),
-                                                      "iters_max": max(t["iters"] for t in stj)}}
+                                                      "iters_max": max(t["iters"] for t in stj)},
+                          "per_sample_error_vs_fp64": {"max": max(err), "median": float(np.median(err)),
+                                                       "reference": "GPU FP64 multigrid CG to 1e-12"}}
     if not args.no_cpu_baseline:
         from oracle import oracle as orc
         threads = min(args.cpu_threads, w.s)

@@ -296,24 +296,28 @@ typedef struct {
   int32_t N;      /* fine mesh: N elements per axis                        */
   int32_t M;      /* KL terms of the problem                                */
   int32_t s;      /* ensemble size (4, 8, 16, 32)                            */
-  int32_t reserved;
+  int32_t fp32;   /* 0: FP64 cycle; 1: FP32 cycle on FP32 matrices (for the
+                     refinement's inner solve)                            */
   void* buffer;   /* (device) hierarchy storage                             */
-  size_t bytes;   /* its size, >= ens_mg_bytes(N, M, s)                     */
+  size_t bytes;   /* its size, >= ens_mg_bytes(N, M, s, fp32)               */
 } ens_mg;
 
-ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, size_t* bytes);
+ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, int32_t fp32, size_t* bytes);
 /* Build the coarse levels for the fine matrix `values` [nnz][s] of `graph`
- * (the N^3 mesh), the KL inputs xi [s][M] (device) and `problem`.  Stream
- * ordered; never synchronises.  The fine values must stay unchanged while
- * the hierarchy is used. */
-ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const ens_problem* problem,
-                        const double* xi, hipStream_t stream);
-/* FP64 CG with z = M r from the hierarchy (per-sample scalars and masks, the
- * stopping rule of ens_cg; opts->mixed and opts->coupled must be 0).
- * Workspace from ens_cg_workspace_bytes(graph, s, opts).  Synchronises. */
-ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,
-                     const ens_cg_opts* opts, const ens_mg* mg, void* workspace, size_t ws_bytes, ens_cg_stat* stats,
-                     hipStream_t stream);
+ * (the N^3 mesh; with fp32 also its FP32 copy values32), the KL inputs
+ * xi [s][M] (device) and `problem`.  Stream ordered; never synchronises.
+ * The fine matrices must stay unchanged while the hierarchy is used. */
+ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const float* values32,
+                        const ens_problem* problem, const double* xi, hipStream_t stream);
+/* CG with z = M r from the hierarchy, per-sample scalars and masks and the
+ * stopping rule of ens_cg (opts->coupled must be 0).  opts->mixed = 0: FP64
+ * CG with an FP64 cycle.  opts->mixed = 1: the FP32-in-FP64 refinement of
+ * ens_cg whose FP32 inner CG (on values32) is preconditioned by an FP32
+ * cycle.  Workspace from ens_cg_workspace_bytes(graph, s, opts).
+ * Synchronises. */
+ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, const float* values32, const double* b,
+                     double* x, const ens_cg_opts* opts, const ens_mg* mg, void* workspace, size_t ws_bytes,
+                     ens_cg_stat* stats, hipStream_t stream);
 
 /* The one-sample baseline with up to `streams` (1..32) solves in flight at
  * once, each on its own library stream (default priority) with its own

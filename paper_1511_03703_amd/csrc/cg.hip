@@ -516,32 +516,73 @@ static ens_status cg_scalar_concurrent(const ens_graph* g, int s, const double* 
   return agg;
 }
 
-template <int S>
-__global__ __launch_bounds__(256) void k_mg_update_r(int64_t nchunks, double* __restrict__ x,
-                                                     const double* __restrict__ p, const double* __restrict__ q,
-                                                     double* __restrict__ r, const Ctl* c, double* __restrict__ part) {
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_mg_update_r(int64_t nchunks, T* __restrict__ x, const T* __restrict__ p,
+                                                     const T* __restrict__ q, T* __restrict__ r, const Ctl* c,
+                                                     double* __restrict__ part) {
   if (c->n_active == 0) return;
-  update_r_body<S>(nchunks, x, p, q, r, c, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
+  update_r_body<T, S>(nchunks, x, p, q, r, c, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
 }
 
-template <int S>
-__global__ __launch_bounds__(256) void k_mg_rz(int64_t nchunks, const double* __restrict__ r,
-                                               const double* __restrict__ z, double* __restrict__ pz, const Ctl* c,
-                                               int gate, double* __restrict__ part) {
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_mg_rz(int64_t nchunks, const T* __restrict__ r, const T* __restrict__ z,
+                                               T* __restrict__ pz, const Ctl* c, int gate, double* __restrict__ part) {
   if (gate && c->n_active == 0) return;
-  rz_body<S>(nchunks, r, z, pz, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
+  rz_body<T, S>(nchunks, r, z, pz, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
 }
 
-template <int S>
-__global__ __launch_bounds__(256) void k_mg_pz(int64_t nchunks, const double* __restrict__ z, double* __restrict__ p,
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_mg_pz(int64_t nchunks, const T* __restrict__ z, T* __restrict__ p,
                                                const Ctl* c) {
   if (c->n_active == 0) return;
-  pupdate_z_body<S>(nchunks, z, p, c, blockIdx.x);
+  pupdate_z_body<T, S>(nchunks, z, p, c, blockIdx.x);
 }
 
-// Jacobi-CG's iteration with z = M r from the multigrid cycle: A (q = A p,
-// alpha), the update of x and r with the convergence test, the cycle, then
-// r.z for beta and the new direction.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_zero(int64_t count, T* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) v[i] = (T)0;
+}
+
+// Iterations k0+1..k1 of CG with z = M r in precision T: q = A p and alpha;
+// the update of x and r with the convergence test; the cycle; r.z and beta;
+// the new direction.  x is the solution (FP64 solve) or the correction d
+// (FP32 inner solve of the refinement).
+template <typename T, int S>
+static void mg_iterations(const ens_graph* g, const T* vals, const MgPlan& plan, T* x, T* r, T* p, T* q, T* z,
+                          const Work& w, int k0, int k1, hipStream_t st) {
+  const int64_t n = g->n;
+  const int64_t nchunks = n * S / VecMap<T, S>::V;
+  const unsigned sb = grid_for(n, 4 * EnsMap<T, S>::RPW);
+  const unsigned vb = grid_for(nchunks, (int64_t)kBlock * kU);
+  const int kid = sizeof(T) == 8 ? ENS_K_SPMV_F64 : ENS_K_SPMV_F32;
+  const double spmv_bytes = (double)g->nnz * (S * (double)sizeof(T) + 4.0) + 4.0 * (n + 1) + 2.0 * n * S * sizeof(T);
+  for (int k = k0 + 1; k <= k1; ++k) {
+    prof_begin(kid, st);
+    hipLaunchKernelGGL((k_cg_spmv_dot<T, S>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, p, q,
+                       w.ctl, w.part);
+    prof_end(kid, st, spmv_bytes);
+    reduce<S, 1>(w, sb, OP_ALPHA, 0, 1, st);
+    hipLaunchKernelGGL((k_mg_update_r<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, x, p, q, r, w.ctl, w.part);
+    reduce<S, 2>(w, vb, OP_UPDATE_R, k, 1, st);
+    mg_vcycle<T, S>(plan, r, z, w.ctl, st);
+    hipLaunchKernelGGL((k_mg_rz<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, r, z, (T*)nullptr, w.ctl, 1, w.part);
+    reduce<S, 2>(w, vb, OP_BETA, 0, 1, st);
+    hipLaunchKernelGGL((k_mg_pz<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, z, p, w.ctl);
+  }
+}
+
+// z = M r, p = z and rho = r.z for the active samples.
+template <typename T, int S>
+static void mg_start(int64_t n, const MgPlan& plan, T* r, T* z, T* p, const Work& w, hipStream_t st) {
+  const int64_t nchunks = n * S / VecMap<T, S>::V;
+  const unsigned vb = grid_for(nchunks, (int64_t)kBlock * kU);
+  mg_vcycle<T, S>(plan, r, z, w.ctl, st);
+  hipLaunchKernelGGL((k_mg_rz<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, r, z, p, w.ctl, 0, w.part);
+  reduce<S, 2>(w, vb, OP_RHO, 0, 0, st);
+}
+
+// FP64 CG with z = M r from the FP64 multigrid cycle.
 template <int S>
 static ens_status cg_mg(const ens_graph* g, const double* vals, const double* b, double* x, const ens_cg_opts& o,
                         const MgPlan& plan, Work& w, hipStream_t st) {
@@ -551,32 +592,13 @@ static ens_status cg_mg(const ens_graph* g, const double* vals, const double* b,
   double* z = (double*)w.vec[3];
   const int64_t n = g->n;
   const int64_t total = n * S;
-  const int64_t nchunks = n * S / VecMap<double, S>::V;
-  const unsigned sb = grid_for(n, 4 * EnsMap<double, S>::RPW);
-  const unsigned vb = grid_for(nchunks, (int64_t)kBlock * kU);
-  const double spmv_bytes = (double)g->nnz * (S * 8.0 + 4.0) + 4.0 * (n + 1) + 2.0 * n * S * 8.0;
   residual<S, double>(g, vals, x, b, r, w, OP_START, 0, st);
   hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
-  mg_vcycle<S>(plan, r, z, w.ctl, st);
-  hipLaunchKernelGGL(k_mg_rz<S>, dim3(vb), dim3(kBlock), 0, st, nchunks, r, z, p, w.ctl, 0, w.part);
-  reduce<S, 2>(w, vb, OP_RHO, 0, 0, st);
+  mg_start<double, S>(n, plan, r, z, p, w, st);
   ENS_LAUNCH_CHECK();
   for (int k0 = 0; k0 < o.max_iter; k0 += o.check_every) {
     const int k1 = k0 + o.check_every < o.max_iter ? k0 + o.check_every : o.max_iter;
-    for (int k = k0 + 1; k <= k1; ++k) {
-      prof_begin(ENS_K_SPMV_F64, st);
-      hipLaunchKernelGGL((k_cg_spmv_dot<double, S>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx,
-                         vals, p, q, w.ctl, w.part);
-      prof_end(ENS_K_SPMV_F64, st, spmv_bytes);
-      reduce<S, 1>(w, sb, OP_ALPHA, 0, 1, st);
-      hipLaunchKernelGGL(k_mg_update_r<S>, dim3(vb), dim3(kBlock), 0, st, nchunks, x, p, q, r, w.ctl, w.part);
-      reduce<S, 2>(w, vb, OP_UPDATE_R, k, 1, st);
-      mg_vcycle<S>(plan, r, z, w.ctl, st);
-      hipLaunchKernelGGL(k_mg_rz<S>, dim3(vb), dim3(kBlock), 0, st, nchunks, r, z, (double*)nullptr, w.ctl, 1,
-                         w.part);
-      reduce<S, 2>(w, vb, OP_BETA, 0, 1, st);
-      hipLaunchKernelGGL(k_mg_pz<S>, dim3(vb), dim3(kBlock), 0, st, nchunks, z, p, w.ctl);
-    }
+    mg_iterations<double, S>(g, vals, plan, x, r, p, q, z, w, k0, k1, st);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
     ens_status rc = poll_active(w.ctl, false, st, &act);
@@ -585,6 +607,45 @@ static ens_status cg_mg(const ens_graph* g, const double* vals, const double* b,
   }
   residual<S, double>(g, vals, x, b, (double*)nullptr, w, OP_TRUE, 0, st);
   ENS_LAUNCH_CHECK();
+  return ENS_OK;
+}
+
+// FP32-in-FP64 refinement whose FP32 inner CG is preconditioned by the FP32
+// multigrid cycle: FP64 residual r = b - A x rounded to FP32, inner solve
+// A32 d = r32 to the inner tolerance, x += d in FP64.
+template <int S>
+static ens_status cg_mixed_mg(const ens_graph* g, const double* vals, const float* vals32, const double* b, double* x,
+                              const ens_cg_opts& o, const MgPlan& plan, Work& w, hipStream_t st) {
+  float* r = (float*)w.vec[0];
+  float* p = (float*)w.vec[1];
+  float* q = (float*)w.vec[2];
+  float* z = (float*)w.vec[3];
+  float* d = (float*)w.vec[4];
+  const int64_t n = g->n;
+  const int64_t total = n * S;
+  for (int outer = 0;; ++outer) {
+    residual<S, float>(g, vals, x, b, r, w, OP_OUTER, outer, st);
+    if (outer == 0)
+      hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
+    ENS_LAUNCH_CHECK();
+    int32_t act = 0;
+    ens_status rc = poll_active(w.ctl, true, st, &act);
+    if (rc != ENS_OK) return rc;
+    if (act == 0) break;
+    hipLaunchKernelGGL(k_fill_zero<float>, dim3(grid_for(total, 256)), dim3(256), 0, st, total, d);
+    mg_start<float, S>(n, plan, r, z, p, w, st);
+    ENS_LAUNCH_CHECK();
+    for (int k0 = 0; k0 < o.inner_max_iter; k0 += o.check_every) {
+      const int k1 = k0 + o.check_every < o.inner_max_iter ? k0 + o.check_every : o.inner_max_iter;
+      mg_iterations<float, S>(g, vals32, plan, d, r, p, q, z, w, k0, k1, st);
+      ENS_LAUNCH_CHECK();
+      rc = poll_active(w.ctl, false, st, &act);
+      if (rc != ENS_OK) return rc;
+      if (act == 0) break;
+    }
+    hipLaunchKernelGGL(k_ir_update<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, d, w.ctl);
+    ENS_LAUNCH_CHECK();
+  }
   return ENS_OK;
 }
 
@@ -669,9 +730,9 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
   return read_stats(w.ctl, s, stats, stream);
 }
 
-ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,
-                     const ens_cg_opts* opts, const ens_mg* mg, void* workspace, size_t ws_bytes, ens_cg_stat* stats,
-                     hipStream_t stream) {
+ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, const float* values32, const double* b,
+                     double* x, const ens_cg_opts* opts, const ens_mg* mg, void* workspace, size_t ws_bytes,
+                     ens_cg_stat* stats, hipStream_t stream) {
   ens_status st = check_graph(graph);
   if (st != ENS_OK) return st;
   ENS_ARG_CHECK(opts && stats && mg && mg->buffer, "null options, stats or hierarchy");
@@ -679,7 +740,9 @@ ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, co
   ENS_ARG_CHECK(aligned16(values) && aligned16(b) && aligned16(x), "buffers must be 16-byte aligned");
   ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
   ENS_ARG_CHECK(opts->rtol >= 0.0, "rtol must be >= 0");
-  ENS_ARG_CHECK(!opts->mixed && !opts->coupled, "the multigrid solve is per-sample FP64");
+  ENS_ARG_CHECK(!opts->coupled, "the multigrid solve uses per-sample scalars");
+  ENS_ARG_CHECK((opts->mixed != 0) == (mg->fp32 != 0), "mixed mode needs an FP32 cycle, FP64 CG an FP64 one");
+  ENS_ARG_CHECK(!opts->mixed || (values32 && aligned16(values32)), "mixed mode needs values32");
   ENS_ARG_CHECK(mg->s == s, "hierarchy built for another ensemble size");
   const int64_t nn = (int64_t)(mg->N + 1) * (mg->N + 1) * (mg->N + 1);
   ENS_ARG_CHECK(graph->n == nn, "graph is not the hierarchy's fine mesh");
@@ -687,13 +750,14 @@ ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, co
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
   }
-  const size_t need = ws_layout(graph->n, s, false, nullptr, nullptr);
+  const bool mixed = opts->mixed != 0;
+  const size_t need = ws_layout(graph->n, s, mixed, nullptr, nullptr);
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     return ENS_E_NOMEM;
   }
   MgPlan plan;
-  if (!mg_plan(mg->N, mg->M, s, (char*)mg->buffer, &plan)) {
+  if (!mg_plan(mg->N, mg->M, s, mg->fp32 != 0, (char*)mg->buffer, &plan)) {
     set_error("multigrid hierarchy of N=%d is not supported", mg->N);
     return ENS_E_UNSUPPORTED;
   }
@@ -701,18 +765,24 @@ ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, co
     set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, plan.bytes);
     return ENS_E_NOMEM;
   }
-  mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values);
+  mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values, mixed ? values32 : nullptr);
   Work w;
-  ws_layout(graph->n, s, false, &w, (char*)workspace);
+  ws_layout(graph->n, s, mixed, &w, (char*)workspace);
   ens_cg_opts o = normalized(opts);
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, w.ctl, o.rtol, o.inner_rtol, o.max_iter,
-                     o.inner_max_iter, o.max_outer, 0, 0);
+                     o.inner_max_iter, o.max_outer, (int)mixed, 0);
   ENS_LAUNCH_CHECK();
   switch (s) {
-    case 4: st = cg_mg<4>(graph, values, b, x, o, plan, w, stream); break;
-    case 8: st = cg_mg<8>(graph, values, b, x, o, plan, w, stream); break;
-    case 16: st = cg_mg<16>(graph, values, b, x, o, plan, w, stream); break;
-    default: st = cg_mg<32>(graph, values, b, x, o, plan, w, stream); break;
+#define ENS_MG_CASE(SS)                                                                      \
+  case SS:                                                                                   \
+    st = mixed ? cg_mixed_mg<SS>(graph, values, values32, b, x, o, plan, w, stream)          \
+               : cg_mg<SS>(graph, values, b, x, o, plan, w, stream);                         \
+    break;
+    ENS_MG_CASE(4)
+    ENS_MG_CASE(8)
+    ENS_MG_CASE(16)
+    ENS_MG_CASE(32)
+#undef ENS_MG_CASE
   }
   if (st != ENS_OK) return st;
   return read_stats(w.ctl, s, stats, stream);

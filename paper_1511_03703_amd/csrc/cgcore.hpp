@@ -122,15 +122,17 @@ __device__ void finalize(Ctl* c, int op, int arg) {
         if (c->active[e]) {
           c->iters[e] += 1;
           c->kiter[e] += 1;
+          const int cap = c->mixed ? c->inner_max_iter : c->max_iter;
           if (!isfinite(t1)) {
             c->status[e] = ENS_SAMPLE_NONFINITE;
             c->active[e] = 0;
+            c->oactive[e] = 0;
           } else if (t1 <= c->tol2[e]) {
             c->active[e] = 0;
-            c->status[e] = ENS_SAMPLE_CONVERGED;
-          } else if (c->kiter[e] >= c->max_iter) {
+            if (!c->mixed) c->status[e] = ENS_SAMPLE_CONVERGED;
+          } else if (c->kiter[e] >= cap) {
             c->active[e] = 0;
-            c->status[e] = ENS_SAMPLE_MAXITER;
+            if (!c->mixed) c->status[e] = ENS_SAMPLE_MAXITER;
           }
         }
         break;
@@ -140,6 +142,7 @@ __device__ void finalize(Ctl* c, int op, int arg) {
           if (!isfinite(t0)) {
             c->status[e] = ENS_SAMPLE_NONFINITE;
             c->active[e] = 0;
+            c->oactive[e] = 0;
           } else {
             c->beta[e] = t0 / c->rho[e];
             c->rho[e] = t0;
@@ -466,11 +469,11 @@ __device__ inline void pupdate_body(int64_t nchunks, const T* __restrict__ r, co
 
 // Multigrid-preconditioned iteration, update half: x += alpha p; r -= alpha
 // q for the active samples; partials (0, r.r) of chunk block `blk` to dst.
-template <int S>
-__device__ inline void update_r_body(int64_t nchunks, double* __restrict__ x, const double* __restrict__ p,
-                                     const double* __restrict__ q, double* __restrict__ r, const Ctl* c, int64_t blk,
+template <typename T, int S>
+__device__ inline void update_r_body(int64_t nchunks, T* __restrict__ x, const T* __restrict__ p,
+                                     const T* __restrict__ q, T* __restrict__ r, const Ctl* c, int64_t blk,
                                      double* __restrict__ dst) {
-  using M = VecMap<double, S>;
+  using M = VecMap<T, S>;
   using vt = typename M::vt;
   const int sub = (threadIdx.x & 63) % M::L;
   vt al;
@@ -479,7 +482,7 @@ __device__ inline void update_r_body(int64_t nchunks, double* __restrict__ x, co
   for (int v = 0; v < M::V; ++v) {
     const int e = M::sample(sub, v);
     act[v] = c->active[e];
-    al[v] = act[v] ? c->alpha[e] : 0.0;
+    al[v] = act[v] ? (T)c->alpha[e] : (T)0;
   }
   double acc[2][M::VS];
 #pragma unroll
@@ -512,7 +515,7 @@ __device__ inline void update_r_body(int64_t nchunks, double* __restrict__ x, co
       rv[u] = rn;
 #pragma unroll
       for (int v = 0; v < M::V; ++v) {
-        const double rr = act[v] ? rn[v] : 0.0;
+        const double rr = act[v] ? (double)rn[v] : 0.0;
         acc[1][M::slot(v)] += rr * rr;
       }
     }
@@ -529,10 +532,10 @@ __device__ inline void update_r_body(int64_t nchunks, double* __restrict__ x, co
 }
 
 // Partials (r.z, 0) of chunk block `blk`; with pz, also p = z (start).
-template <int S>
-__device__ inline void rz_body(int64_t nchunks, const double* __restrict__ r, const double* __restrict__ z,
-                               double* __restrict__ pz, int64_t blk, double* __restrict__ dst) {
-  using M = VecMap<double, S>;
+template <typename T, int S>
+__device__ inline void rz_body(int64_t nchunks, const T* __restrict__ r, const T* __restrict__ z,
+                               T* __restrict__ pz, int64_t blk, double* __restrict__ dst) {
+  using M = VecMap<T, S>;
   using vt = typename M::vt;
   double acc[2][M::VS];
 #pragma unroll
@@ -553,17 +556,17 @@ __device__ inline void rz_body(int64_t nchunks, const double* __restrict__ r, co
     if (i < nchunks) {
       if (pz) store_stream((vt*)pz + i, zv[u]);
 #pragma unroll
-      for (int v = 0; v < M::V; ++v) acc[0][M::slot(v)] += rv[u][v] * zv[u][v];
+      for (int v = 0; v < M::V; ++v) acc[0][M::slot(v)] += (double)rv[u][v] * (double)zv[u][v];
     }
   }
   block_partials<S, M::VS, 2, kBlock / 64>(acc, dst);
 }
 
 // p = z + beta p for the samples still active.
-template <int S>
-__device__ inline void pupdate_z_body(int64_t nchunks, const double* __restrict__ z, double* __restrict__ p,
+template <typename T, int S>
+__device__ inline void pupdate_z_body(int64_t nchunks, const T* __restrict__ z, T* __restrict__ p,
                                       const Ctl* c, int64_t blk) {
-  using M = VecMap<double, S>;
+  using M = VecMap<T, S>;
   using vt = typename M::vt;
   const int sub = (threadIdx.x & 63) % M::L;
   vt be;
@@ -573,7 +576,7 @@ __device__ inline void pupdate_z_body(int64_t nchunks, const double* __restrict_
   for (int v = 0; v < M::V; ++v) {
     const int e = M::sample(sub, v);
     act[v] = c->active[e];
-    be[v] = act[v] ? c->beta[e] : 0.0;
+    be[v] = act[v] ? (T)c->beta[e] : (T)0;
     any |= act[v] != 0;
   }
   if (!any) return;

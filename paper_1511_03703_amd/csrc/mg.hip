@@ -4,6 +4,10 @@
 // per sample; graphs and transfers are shared), so the ensemble cycle is the
 // stacked per-sample preconditioner M_c = sum_i M_i (x) e_i e_i^T.
 //
+// The cycle runs in FP64, or in FP32 on FP32 copies of every level's
+// matrix (the preconditioner of the refinement's FP32 inner solve); the
+// bounds, the Chebyshev constants and the coarse inverse stay FP64.
+//
 // One level of the cycle, rhs B, result OUT (x0 = 0), theta/delta of the
 // per-sample Chebyshev interval [lmax/4, lmax]:
 //   XA = d = D^-1 B / theta                          (elementwise)
@@ -37,9 +41,11 @@ int mg_levels(int N, int* Ns) {
   return L;
 }
 
-bool mg_plan(int N, int M, int S, char* base, MgPlan* plan) {
+bool mg_plan(int N, int M, int S, int fp32, char* base, MgPlan* plan) {
   int Ns[kMgMaxLevels];
   plan->levels = mg_levels(N, Ns);
+  plan->fp32 = fp32;
+  const size_t tw = fp32 ? sizeof(float) : sizeof(double);
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -52,25 +58,28 @@ bool mg_plan(int N, int M, int S, char* base, MgPlan* plan) {
     l.N = Ns[k];
     l.n = (int64_t)(l.N + 1) * (l.N + 1) * (l.N + 1);
     l.nnz = (int64_t)(3 * l.N + 1) * (3 * l.N + 1) * (3 * l.N + 1);
-    const size_t vb = (size_t)l.n * S * sizeof(double);
+    const size_t vb = (size_t)l.n * S * tw;
     if (k > 0) {
       size_t klb = 0;
       if (ens_kl_bytes(l.N, M, &klb) != ENS_OK) return false;
       l.own_rp = (int32_t*)take(sizeof(int32_t) * (l.n + 1));
       l.own_ci = (int32_t*)take(sizeof(int32_t) * l.nnz);
       l.own_vals = (double*)take(sizeof(double) * l.nnz * S);
+      if (fp32) l.own_vals32 = (float*)take(sizeof(float) * l.nnz * S);
       l.kl = take(klb);
       l.rp = l.own_rp;
       l.ci = l.own_ci;
       l.vals = l.own_vals;
-      l.b = (double*)take(vb);
+      l.vals32 = l.own_vals32;
+      // FP64 load vector of the coarse assembly (scratch), then the cycle's rhs
+      l.b = take((size_t)l.n * S * sizeof(double));
     }
-    l.dinv = (double*)take(vb);
+    l.dinv = take(vb);
     l.lmax = (double*)take(sizeof(double) * S);
-    l.xa = (double*)take(vb);
-    l.xb = (double*)take(vb);
-    l.r = (double*)take(vb);
-    l.d = (double*)take(vb);
+    l.xa = take(vb);
+    l.xb = take(vb);
+    l.r = take(vb);
+    l.d = take(vb);
   }
   MgLevel& c = plan->lv[plan->levels - 1];
   c.m = (int64_t)(c.N - 1) * (c.N - 1) * (c.N - 1);
@@ -81,10 +90,11 @@ bool mg_plan(int N, int M, int S, char* base, MgPlan* plan) {
   return true;
 }
 
-void mg_attach_fine(MgPlan* plan, const int32_t* rp, const int32_t* ci, const double* vals) {
+void mg_attach_fine(MgPlan* plan, const int32_t* rp, const int32_t* ci, const double* vals, const float* vals32) {
   plan->lv[0].rp = rp;
   plan->lv[0].ci = ci;
   plan->lv[0].vals = vals;
+  plan->lv[0].vals32 = vals32;
 }
 
 // --------------------------------------------------------------- kernels ---
@@ -103,10 +113,10 @@ __device__ inline ChebK cheb_consts(double lmax) {
   return ChebK{1.0 / theta, rho1 * rho0, 2.0 * rho1 / delta};
 }
 
-template <int S>
+template <typename T, int S>
 __global__ __launch_bounds__(256) void k_mg_dinv(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                                 const double* __restrict__ vals, double* __restrict__ dinv) {
-  diag_inv_body<double, S>(n, rp, ci, vals, dinv, blockIdx.x);
+                                                 const T* __restrict__ vals, T* __restrict__ dinv) {
+  diag_inv_body<T, S>(n, rp, ci, vals, dinv, blockIdx.x);
 }
 
 // Per-sample Gershgorin bound max_i sum_j |a_ij| / a_ii: block maxima over
@@ -191,17 +201,17 @@ __global__ __launch_bounds__(256) void k_mg_inverse(int N, const int32_t* __rest
 }
 
 // XA = d = D^-1 B / theta (first Chebyshev step from x = 0).
-template <int S>
-__global__ __launch_bounds__(256) void k_mg_cheb0(int64_t nchunks, const double* __restrict__ b,
-                                                  const double* __restrict__ dinv, const double* __restrict__ lmax,
-                                                  double* __restrict__ xa, double* __restrict__ d, const Ctl* gate) {
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_mg_cheb0(int64_t nchunks, const T* __restrict__ b,
+                                                  const T* __restrict__ dinv, const double* __restrict__ lmax,
+                                                  T* __restrict__ xa, T* __restrict__ d, const Ctl* gate) {
   if (mg_idle(gate)) return;
-  using VM = VecMap<double, S>;
+  using VM = VecMap<T, S>;
   using vt = typename VM::vt;
   const int sub = (threadIdx.x & 63) % VM::L;
   vt it;
 #pragma unroll
-  for (int v = 0; v < VM::V; ++v) it[v] = cheb_consts(lmax[VM::sample(sub, v)]).inv_theta;
+  for (int v = 0; v < VM::V; ++v) it[v] = (T)cheb_consts(lmax[VM::sample(sub, v)]).inv_theta;
   const int64_t base = (int64_t)blockIdx.x * kBlock * kU + threadIdx.x;
   vt bv[kU], dv[kU];
 #pragma unroll
@@ -229,20 +239,20 @@ enum MgRowMode { MG_RES = 0, MG_CHEB1 = 1, MG_CHEB2 = 2 };
 //   MG_RES:   r = B - A x
 //   MG_CHEB1: d = D^-1 (B - A x) / theta;           xout = x + d
 //   MG_CHEB2: d = c1 d + c2 D^-1 (B - A x);          xout = x + d
-template <int S, int MODE>
+template <typename T, int S, int MODE>
 __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                                const double* __restrict__ vals, const double* __restrict__ x,
-                                                const double* __restrict__ b, const double* __restrict__ dinv,
-                                                const double* __restrict__ lmax, double* __restrict__ d,
-                                                double* __restrict__ out, const Ctl* gate) {
+                                                const T* __restrict__ vals, const T* __restrict__ x,
+                                                const T* __restrict__ b, const T* __restrict__ dinv,
+                                                const double* __restrict__ lmax, T* __restrict__ d,
+                                                T* __restrict__ out, const Ctl* gate) {
   if (mg_idle(gate)) return;
-  using M = EnsMap<double, S>;
+  using M = EnsMap<T, S>;
   using vt = typename M::vt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane % M::L;
   const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
   if (row >= n) return;
-  const vt ax = ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
+  const vt ax = ens_row_product<T, S>(ci, vals, x, rp[row], rp[row + 1], sub);
   const int64_t i = row * M::L + sub;
   const vt res = ((const vt*)b)[i] - ax;
   if (MODE == MG_RES) {
@@ -253,8 +263,8 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
 #pragma unroll
   for (int v = 0; v < M::V; ++v) {
     const ChebK c = cheb_consts(lmax[sub * M::V + v]);
-    k1[v] = MODE == MG_CHEB1 ? 0.0 : c.c1;
-    k2[v] = MODE == MG_CHEB1 ? c.inv_theta : c.c2;
+    k1[v] = (T)(MODE == MG_CHEB1 ? 0.0 : c.c1);
+    k2[v] = (T)(MODE == MG_CHEB1 ? c.inv_theta : c.c2);
   }
   const vt dv = ((const vt*)dinv)[i] * res;
   vt dn;
@@ -267,11 +277,11 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
 // Coarse interior node c collects the residual of the fine interior nodes
 // around fine node 2c (weight 1 on the axis, 1/2 one step off), in a fixed
 // order; coarse boundary nodes get 0.
-template <int S>
-__global__ __launch_bounds__(256) void k_mg_restrict(int Nc, const double* __restrict__ rf, double* __restrict__ bc,
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_mg_restrict(int Nc, const T* __restrict__ rf, T* __restrict__ bc,
                                                      const Ctl* gate) {
   if (mg_idle(gate)) return;
-  using VM = VecMap<double, S>;
+  using VM = VecMap<T, S>;
   using vt = typename VM::vt;
   const int Nf = 2 * Nc;
   const int64_t nc = (int64_t)(Nc + 1) * (Nc + 1) * (Nc + 1);
@@ -280,14 +290,14 @@ __global__ __launch_bounds__(256) void k_mg_restrict(int Nc, const double* __res
   const int64_t node = t / VM::L;
   const int sub = (int)(t % VM::L);
   const int I = (int)(node % (Nc + 1)), J = (int)((node / (Nc + 1)) % (Nc + 1)), K = (int)(node / ((int64_t)(Nc + 1) * (Nc + 1)));
-  vt acc = (vt)0.0;
+  vt acc = (vt)0;
   if (I > 0 && J > 0 && K > 0 && I < Nc && J < Nc && K < Nc) {
     for (int dk = -1; dk <= 1; ++dk)
       for (int dj = -1; dj <= 1; ++dj)
         for (int di = -1; di <= 1; ++di) {
           const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
           if (i <= 0 || j <= 0 || k <= 0 || i >= Nf || j >= Nf || k >= Nf) continue;
-          const double w = (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0);
+          const T w = (T)((di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0));
           const int64_t f = i + (int64_t)(Nf + 1) * (j + (int64_t)(Nf + 1) * k);
           acc += w * ((const vt*)rf)[f * VM::L + sub];
         }
@@ -297,11 +307,11 @@ __global__ __launch_bounds__(256) void k_mg_restrict(int Nc, const double* __res
 
 // Fine interior node: xf += sum of its interior coarse parents with the
 // trilinear weights.
-template <int S>
-__global__ __launch_bounds__(256) void k_mg_prolong(int Nc, const double* __restrict__ xc, double* __restrict__ xf,
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_mg_prolong(int Nc, const T* __restrict__ xc, T* __restrict__ xf,
                                                     const Ctl* gate) {
   if (mg_idle(gate)) return;
-  using VM = VecMap<double, S>;
+  using VM = VecMap<T, S>;
   using vt = typename VM::vt;
   const int Nf = 2 * Nc;
   const int64_t nf = (int64_t)(Nf + 1) * (Nf + 1) * (Nf + 1);
@@ -326,24 +336,23 @@ __global__ __launch_bounds__(256) void k_mg_prolong(int Nc, const double* __rest
     return 2;
   };
   const int ni = parents(i, Ii, wi), nj = parents(j, Jj, wj), nk = parents(k, Kk, wk);
-  vt acc = (vt)0.0;
+  vt acc = (vt)0;
   for (int c = 0; c < nk; ++c)
     for (int bq = 0; bq < nj; ++bq)
       for (int a = 0; a < ni; ++a) {
         const int I = Ii[a], J = Jj[bq], K = Kk[c];
         if (I == 0 || J == 0 || K == 0 || I == Nc || J == Nc || K == Nc) continue;
         const int64_t cn = I + (int64_t)(Nc + 1) * (J + (int64_t)(Nc + 1) * K);
-        acc += (wi[a] * wj[bq] * wk[c]) * ((const vt*)xc)[cn * VM::L + sub];
+        acc += (T)(wi[a] * wj[bq] * wk[c]) * ((const vt*)xc)[cn * VM::L + sub];
       }
   ((vt*)xf)[t] = ((const vt*)xf)[t] + acc;
 }
 
 // Coarsest level: boundary rows are identities (x = B), interior rows take
 // the per-sample dense inverse.
-template <int S>
+template <typename T, int S>
 __global__ __launch_bounds__(256) void k_mg_coarse(int Nc, int64_t m, const double* __restrict__ ainv,
-                                                   const double* __restrict__ b, double* __restrict__ x,
-                                                   const Ctl* gate) {
+                                                   const T* __restrict__ b, T* __restrict__ x, const Ctl* gate) {
   if (mg_idle(gate)) return;
   const int64_t n = (int64_t)(Nc + 1) * (Nc + 1) * (Nc + 1);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -362,9 +371,9 @@ __global__ __launch_bounds__(256) void k_mg_coarse(int Nc, int64_t m, const doub
   for (int64_t c = 0; c < m; ++c) {
     const int ii = 1 + (int)(c % I), jj = 1 + (int)((c / I) % I), kk = 1 + (int)(c / ((int64_t)I * I));
     const int64_t cn = ii + (int64_t)(Nc + 1) * (jj + (int64_t)(Nc + 1) * kk);
-    acc += row[c] * b[cn * S + e];
+    acc += row[c] * (double)b[cn * S + e];
   }
-  x[t] = acc;
+  x[t] = (T)acc;
 }
 
 // ------------------------------------------------------------ host side ---
@@ -374,56 +383,67 @@ static unsigned blocks_for(int64_t items, int64_t per) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
-template <int S>
-static void cycle(const MgPlan& P, int k, const double* B, double* OUT, const Ctl* gate, hipStream_t st) {
-  using EM = EnsMap<double, S>;
-  using VM = VecMap<double, S>;
+template <typename T, int S>
+static void cycle(const MgPlan& P, int k, const T* B, T* OUT, const Ctl* gate, hipStream_t st) {
+  using EM = EnsMap<T, S>;
+  using VM = VecMap<T, S>;
   const MgLevel& l = P.lv[k];
+  const T* vals = sizeof(T) == 4 ? (const T*)l.vals32 : (const T*)l.vals;
+  const T* dinv = (const T*)l.dinv;
+  T *xa = (T*)l.xa, *xb = (T*)l.xb, *r = (T*)l.r, *d = (T*)l.d;
   if (k == P.levels - 1) {
-    hipLaunchKernelGGL(k_mg_coarse<S>, dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, l.N, l.m, l.ainv, B, OUT,
-                       gate);
+    hipLaunchKernelGGL((k_mg_coarse<T, S>), dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, l.N, l.m, l.ainv, B,
+                       OUT, gate);
     return;
   }
   const MgLevel& c = P.lv[k + 1];
+  T* cb = (T*)c.b;
+  T* cx = (T*)c.xb;
   const int64_t nchunks = l.n * S / VM::V;
   const unsigned rb = blocks_for(l.n, 4 * EM::RPW);
   // algorithmic bytes of the fine row passes: the matrix and the gathered
-  // x once, plus (vectors read + written) x n x S x 8
-  const double mat = (double)l.nnz * (S * 8.0 + 4.0) + 4.0 * (l.n + 1);
-  const double vec = (double)l.n * S * 8.0;
+  // x once, plus (vectors read + written) x n x S x sizeof(T)
+  const double mat = (double)l.nnz * (S * (double)sizeof(T) + 4.0) + 4.0 * (l.n + 1);
+  const double vec = (double)l.n * S * sizeof(T);
   const bool fine = k == 0;
-  hipLaunchKernelGGL(k_mg_cheb0<S>, dim3(blocks_for(nchunks, (int64_t)kBlock * kU)), dim3(kBlock), 0, st, nchunks, B,
-                     l.dinv, l.lmax, l.xa, l.d, gate);
+  hipLaunchKernelGGL((k_mg_cheb0<T, S>), dim3(blocks_for(nchunks, (int64_t)kBlock * kU)), dim3(kBlock), 0, st,
+                     nchunks, B, dinv, l.lmax, xa, d, gate);
   if (fine) prof_begin(ENS_K_MG_ROW, st);
-  hipLaunchKernelGGL((k_mg_row<S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xa, B,
-                     l.dinv, l.lmax, l.d, l.xb, gate);
+  hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xa, B, dinv,
+                     l.lmax, d, xb, gate);
   if (fine) prof_end(ENS_K_MG_ROW, st, mat + 6.0 * vec);
   if (fine) prof_begin(ENS_K_MG_ROW, st);
-  hipLaunchKernelGGL((k_mg_row<S, MG_RES>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xb, B,
-                     l.dinv, l.lmax, l.d, l.r, gate);
+  hipLaunchKernelGGL((k_mg_row<T, S, MG_RES>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xb, B, dinv,
+                     l.lmax, d, r, gate);
   if (fine) prof_end(ENS_K_MG_ROW, st, mat + 3.0 * vec);
-  hipLaunchKernelGGL(k_mg_restrict<S>, dim3(blocks_for(c.n * VM::L, 256)), dim3(256), 0, st, c.N, l.r, c.b, gate);
-  cycle<S>(P, k + 1, c.b, c.xb, gate, st);
-  hipLaunchKernelGGL(k_mg_prolong<S>, dim3(blocks_for(l.n * VM::L, 256)), dim3(256), 0, st, c.N, c.xb, l.xb, gate);
+  hipLaunchKernelGGL((k_mg_restrict<T, S>), dim3(blocks_for(c.n * VM::L, 256)), dim3(256), 0, st, c.N, r, cb, gate);
+  cycle<T, S>(P, k + 1, cb, cx, gate, st);
+  hipLaunchKernelGGL((k_mg_prolong<T, S>), dim3(blocks_for(l.n * VM::L, 256)), dim3(256), 0, st, c.N, cx, xb, gate);
   if (fine) prof_begin(ENS_K_MG_ROW, st);
-  hipLaunchKernelGGL((k_mg_row<S, MG_CHEB1>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xb, B,
-                     l.dinv, l.lmax, l.d, l.xa, gate);
+  hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB1>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xb, B, dinv,
+                     l.lmax, d, xa, gate);
   if (fine) prof_end(ENS_K_MG_ROW, st, mat + 5.0 * vec);
   if (fine) prof_begin(ENS_K_MG_ROW, st);
-  hipLaunchKernelGGL((k_mg_row<S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals, l.xa, B,
-                     l.dinv, l.lmax, l.d, OUT, gate);
+  hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xa, B, dinv,
+                     l.lmax, d, OUT, gate);
   if (fine) prof_end(ENS_K_MG_ROW, st, mat + 6.0 * vec);
 }
 
-template <int S>
-void mg_vcycle(const MgPlan& plan, const double* r, double* z, const Ctl* gate, hipStream_t st) {
-  cycle<S>(plan, 0, r, z, gate, st);
+template <typename T, int S>
+void mg_vcycle(const MgPlan& plan, const T* r, T* z, const Ctl* gate, hipStream_t st) {
+  cycle<T, S>(plan, 0, r, z, gate, st);
 }
 
-template void mg_vcycle<4>(const MgPlan&, const double*, double*, const Ctl*, hipStream_t);
-template void mg_vcycle<8>(const MgPlan&, const double*, double*, const Ctl*, hipStream_t);
-template void mg_vcycle<16>(const MgPlan&, const double*, double*, const Ctl*, hipStream_t);
-template void mg_vcycle<32>(const MgPlan&, const double*, double*, const Ctl*, hipStream_t);
+#define ENS_MG_INST(T, S) template void mg_vcycle<T, S>(const MgPlan&, const T*, T*, const Ctl*, hipStream_t);
+ENS_MG_INST(double, 4)
+ENS_MG_INST(double, 8)
+ENS_MG_INST(double, 16)
+ENS_MG_INST(double, 32)
+ENS_MG_INST(float, 4)
+ENS_MG_INST(float, 8)
+ENS_MG_INST(float, 16)
+ENS_MG_INST(float, 32)
+#undef ENS_MG_INST
 
 template <int S>
 static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* xi, hipStream_t st) {
@@ -433,11 +453,15 @@ static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* 
       ens_status rc = ens_graph_build(l.N, l.own_rp, l.own_ci, st);
       if (rc == ENS_OK) rc = ens_kl_build(l.N, prob.M, prob.L, l.kl, st);
       ens_graph g{(int32_t)l.n, l.nnz, l.own_rp, l.own_ci};
-      if (rc == ENS_OK) rc = ens_assemble(l.N, &g, l.kl, &prob, S, xi, l.own_vals, nullptr, l.b, st);
+      if (rc == ENS_OK) rc = ens_assemble(l.N, &g, l.kl, &prob, S, xi, l.own_vals, l.own_vals32, (double*)l.b, st);
       if (rc != ENS_OK) return rc;
     }
-    hipLaunchKernelGGL(k_mg_dinv<S>, dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, (int)l.n, l.rp, l.ci, l.vals,
-                       l.dinv);
+    if (P.fp32)
+      hipLaunchKernelGGL((k_mg_dinv<float, S>), dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, (int)l.n, l.rp,
+                         l.ci, l.vals32, (float*)l.dinv);
+    else
+      hipLaunchKernelGGL((k_mg_dinv<double, S>), dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, (int)l.n, l.rp,
+                         l.ci, l.vals, (double*)l.dinv);
     const unsigned gb = blocks_for(l.n, 256 / S) < (unsigned)kMgPartRows ? blocks_for(l.n, 256 / S) : kMgPartRows;
     hipLaunchKernelGGL(k_mg_gersh<S>, dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals, P.part);
     hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(64), 0, st, P.part, (int)gb, l.lmax);
@@ -455,14 +479,14 @@ using namespace ens;
 
 extern "C" {
 
-ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, size_t* bytes) {
+ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, int32_t fp32, size_t* bytes) {
   ENS_ARG_CHECK(bytes && N >= 1 && M >= 0, "bad multigrid arguments");
   if (!supported_s(s)) {
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
   }
   MgPlan plan;
-  if (!mg_plan(N, M, s, nullptr, &plan)) {
+  if (!mg_plan(N, M, s, fp32 != 0, nullptr, &plan)) {
     set_error("coarsest multigrid level of N=%d has more than %lld interior unknowns", N, (long long)kMgMaxCoarse);
     return ENS_E_UNSUPPORTED;
   }
@@ -470,24 +494,25 @@ ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, size_t* bytes) {
   return ENS_OK;
 }
 
-ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const ens_problem* problem,
-                        const double* xi, hipStream_t stream) {
+ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const float* values32,
+                        const ens_problem* problem, const double* xi, hipStream_t stream) {
   ENS_ARG_CHECK(mg && graph && values && problem && xi && mg->buffer, "null multigrid argument");
   ENS_ARG_CHECK(((uintptr_t)mg->buffer & 255u) == 0, "multigrid buffer must be 256-byte aligned");
   ENS_ARG_CHECK(aligned16(values), "values must be 16-byte aligned");
+  ENS_ARG_CHECK(!mg->fp32 || (values32 && aligned16(values32)), "an FP32 cycle needs the FP32 fine matrix");
   ENS_ARG_CHECK(problem->M == mg->M, "problem->M differs from the hierarchy's M");
   const int64_t n = (int64_t)(mg->N + 1) * (mg->N + 1) * (mg->N + 1);
   ENS_ARG_CHECK(graph->n == n && graph->row_ptr && graph->col_idx, "graph is not the N^3 mesh's graph");
   MgPlan plan;
   size_t need = 0;
-  ens_status rc = ens_mg_bytes(mg->N, mg->M, mg->s, &need);
+  ens_status rc = ens_mg_bytes(mg->N, mg->M, mg->s, mg->fp32, &need);
   if (rc != ENS_OK) return rc;
   if (mg->bytes < need) {
     set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, need);
     return ENS_E_NOMEM;
   }
-  mg_plan(mg->N, mg->M, mg->s, (char*)mg->buffer, &plan);
-  mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values);
+  mg_plan(mg->N, mg->M, mg->s, mg->fp32 != 0, (char*)mg->buffer, &plan);
+  mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values, mg->fp32 ? values32 : nullptr);
   switch (mg->s) {
     case 4: return setup<4>(plan, *problem, xi, stream);
     case 8: return setup<8>(plan, *problem, xi, stream);

@@ -22,18 +22,22 @@ struct MgLevel {
   int64_t n = 0, nnz = 0;
   const int32_t* rp = nullptr;  // level 0: the caller's graph
   const int32_t* ci = nullptr;
-  const double* vals = nullptr;  // level 0: the caller's values
+  const double* vals = nullptr;   // FP64 matrix (level 0: the caller's)
+  const float* vals32 = nullptr;  // FP32 matrix of an FP32 cycle (level 0: the caller's)
   int32_t *own_rp = nullptr, *own_ci = nullptr;
   double* own_vals = nullptr;
+  float* own_vals32 = nullptr;
   void* kl = nullptr;
-  double *dinv = nullptr, *lmax = nullptr;
-  double *b = nullptr, *xa = nullptr, *xb = nullptr, *r = nullptr, *d = nullptr;
+  void* dinv = nullptr;  // cycle precision
+  double* lmax = nullptr;
+  void *b = nullptr, *xa = nullptr, *xb = nullptr, *r = nullptr, *d = nullptr;  // cycle precision
   int64_t m = 0;           // coarsest level: interior unknowns
   double* ainv = nullptr;  // coarsest level: [S][m][m]
 };
 
 struct MgPlan {
   int levels = 0;
+  int fp32 = 0;  // cycle in FP32 (vectors, D^-1 and matrices)
   MgLevel lv[kMgMaxLevels];
   double* part = nullptr;  // [kMgPartRows][S] scratch of the bound reduction
   size_t bytes = 0;
@@ -42,12 +46,12 @@ struct MgPlan {
 int mg_levels(int N, int* Ns);
 // Carve the hierarchy buffer (base nullable: sizes only).  Returns false if
 // the coarsest level is too large for its dense solve.
-bool mg_plan(int N, int M, int S, char* base, MgPlan* plan);
-// Attach the fine level's graph and values.
-void mg_attach_fine(MgPlan* plan, const int32_t* rp, const int32_t* ci, const double* vals);
-// z = M r for all samples; every kernel returns at once when the control
-// block (nullable) reports no active sample.
-template <int S>
-void mg_vcycle(const MgPlan& plan, const double* r, double* z, const Ctl* gate, hipStream_t st);
+bool mg_plan(int N, int M, int S, int fp32, char* base, MgPlan* plan);
+// Attach the fine level's graph and matrices (vals32 only for FP32 cycles).
+void mg_attach_fine(MgPlan* plan, const int32_t* rp, const int32_t* ci, const double* vals, const float* vals32);
+// z = M r for all samples in the cycle precision T; every kernel returns at
+// once when the control block (nullable) reports no active sample.
+template <typename T, int S>
+void mg_vcycle(const MgPlan& plan, const T* r, T* z, const Ctl* gate, hipStream_t st);
 
 }  // namespace ens

@@ -35,7 +35,7 @@ class ens_graph(ctypes.Structure):
 
 
 class ens_mg(ctypes.Structure):
-    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("s", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("s", ctypes.c_int32), ("fp32", ctypes.c_int32),
                 ("buffer", ctypes.c_void_p), ("bytes", ctypes.c_size_t)]
 
 
@@ -90,9 +90,9 @@ _SIGS = [
                       ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_scalar_cg", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _I32, _P, _SZ,
                              ctypes.POINTER(ens_cg_stat), _P]),
-    ("ens_mg_bytes", _I32, [_I32, _I32, _I32, ctypes.POINTER(_SZ)]),
-    ("ens_mg_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_problem), _P, _P]),
-    ("ens_cg_mg", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(ens_mg), _P, _SZ,
+    ("ens_mg_bytes", _I32, [_I32, _I32, _I32, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_mg_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, _P, ctypes.POINTER(ens_problem), _P, _P]),
+    ("ens_cg_mg", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(ens_mg), _P, _SZ,
                          ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_scalar_cg_concurrent_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(_SZ)]),
     ("ens_scalar_cg_concurrent", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _I32, _I32, _P, _SZ,
@@ -327,23 +327,26 @@ def scalar_cg(g: Graph, values_sm, b_sm, x_sm=None, opts: ens_cg_opts | None = N
 class Multigrid:
     """Device hierarchy of the multigrid preconditioner for one ensemble."""
 
-    def __init__(self, N: int, M: int, s: int, device="cuda"):
+    def __init__(self, N: int, M: int, s: int, fp32: bool = False, device="cuda"):
         nb = _SZ()
-        _check(lib().ens_mg_bytes(N, M, s, ctypes.byref(nb)), "ens_mg_bytes")
+        _check(lib().ens_mg_bytes(N, M, s, int(fp32), ctypes.byref(nb)), "ens_mg_bytes")
         self.buffer = torch.empty(nb.value, dtype=torch.uint8, device=device)
-        self.desc = ens_mg(N, M, s, 0, self.buffer.data_ptr(), nb.value)
+        self.desc = ens_mg(N, M, s, int(fp32), self.buffer.data_ptr(), nb.value)
 
-    def setup(self, g: Graph, values, xi, sigma, L=1.0, kappa0=1.0, f=1.0, stream=None):
+    def setup(self, g: Graph, values, xi, sigma, values32=None, L=1.0, kappa0=1.0, f=1.0, stream=None):
         prob = ens_problem(self.desc.M, L, kappa0, sigma, f)
         gc = g.c()
-        self._values = values
-        _check(lib().ens_mg_setup(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(values), ctypes.byref(prob),
-                                  _ptr(xi), _stream(stream)), "ens_mg_setup")
+        self._values = (values, values32)
+        _check(lib().ens_mg_setup(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(values), _ptr(values32),
+                                  ctypes.byref(prob), _ptr(xi), _stream(stream)), "ens_mg_setup")
         return self
 
 
-def cg_mg(g: Graph, values, b, mg: Multigrid, x=None, opts: ens_cg_opts | None = None, workspace=None, stream=None):
-    """Multigrid-preconditioned ensemble CG.  Returns (x, stats, status)."""
+def cg_mg(g: Graph, values, b, mg: Multigrid, x=None, values32=None, opts: ens_cg_opts | None = None,
+          workspace=None, stream=None):
+    """Multigrid-preconditioned ensemble CG (opts.mixed: FP32 inner solves
+    with an FP32 cycle inside the FP64 refinement).  Returns (x, stats,
+    status)."""
     s = values.shape[1]
     if opts is None:
         opts = cg_opts()
@@ -354,8 +357,9 @@ def cg_mg(g: Graph, values, b, mg: Multigrid, x=None, opts: ens_cg_opts | None =
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
     stats = (ens_cg_stat * s)()
     gc = g.c()
-    st = _check(lib().ens_cg_mg(ctypes.byref(gc), s, _ptr(values), _ptr(b), _ptr(x), ctypes.byref(opts),
-                                ctypes.byref(mg.desc), _ptr(workspace), workspace.numel(), stats, _stream(stream)),
+    st = _check(lib().ens_cg_mg(ctypes.byref(gc), s, _ptr(values), _ptr(values32), _ptr(b), _ptr(x),
+                                ctypes.byref(opts), ctypes.byref(mg.desc), _ptr(workspace), workspace.numel(), stats,
+                                _stream(stream)),
                 "ens_cg_mg", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
     return x, _stats_list(stats, s), st
 

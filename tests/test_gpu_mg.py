@@ -113,3 +113,36 @@ def test_mg_is_deterministic(E):
         x, stats, _ = E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts(rtol=1e-10))
         out.append((_np(x), stats))
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+@pytest.mark.parametrize("N,s", [(16, 32), (12, 8), (24, 16)])
+def test_mixed_refinement_with_fp32_multigrid(E, orc, N, s):
+    """FP32 inner CG preconditioned by the FP32 cycle inside the FP64
+    refinement: every sample reaches the FP64 true residual; the error
+    against an FP64 solve is stated and bounded by kappa * rtol."""
+    M, sigma, rtol = 10, 0.3, 1e-8
+    xi = draw_xi(1480 + N, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    vals, v32, rhs = E.assemble(g, kl, xt, M, sigma, want32=True)
+    mg = E.Multigrid(N, M, s, fp32=True).setup(g, vals, xt, sigma, values32=v32)
+    x, stats, st = E.cg_mg(g, vals, rhs, mg, values32=v32, opts=E.cg_opts(rtol=rtol, mixed=True, check_every=4))
+    assert st == E.ENS_OK, stats
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    xg = _np(x)
+    true_res = orc.ens_true_residual(rp, ci, ov, ob, xg)
+    xref, _, _, _, _ = orc.ens_mg_pcg(N, M, 1.0, 1.0, sigma, 1.0, xi, rtol=1e-12)
+    for e in range(s):
+        assert stats[e]["status"] == 0 and stats[e]["outer_iters"] >= 1
+        assert true_res[e] <= rtol * (1 + 1e-6), (e, true_res[e])
+        assert abs(stats[e]["rel_res"] - true_res[e]) <= 1e-3 * true_res[e] + 1e-14
+        assert _rel(xg[:, e], xref[:, e]) <= 1e-5
+    assert max(t["iters"] for t in stats) <= 20
+    # an FP64 cycle is refused for the mixed solve, and the FP32 cycle for FP64 CG
+    mg64 = E.Multigrid(N, M, s).setup(g, vals, xt, sigma)
+    with pytest.raises(E.EnsError):
+        E.cg_mg(g, vals, rhs, mg64, values32=v32, opts=E.cg_opts(mixed=True))
+    with pytest.raises(E.EnsError):
+        E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts())
