@@ -167,7 +167,7 @@ def run_solve(args):
         del src, dst
 
     use_mg = args.precond == "mg"
-    mg = ens.Multigrid(w.N, w.M, w.s, fp32=w.mixed, device=dev) if use_mg else None
+    mg = ens.Multigrid(w.N, w.M, w.s, fp32=w.mixed, L=w.L, device=dev) if use_mg else None
     # the multigrid solve takes a handful of iterations: poll every 4
     mg_opts = ens.cg_opts(rtol=w.rtol, mixed=w.mixed, inner_rtol=args.inner_rtol,
                           check_every=min(args.check_every, 4))
@@ -179,7 +179,7 @@ def run_solve(args):
 
     def step_mg():
         ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, values32=v32, rhs=rhs)
-        mg.setup(g, vals, xi, w.sigma, values32=v32, L=w.L, kappa0=w.kappa0, f=w.f)
+        mg.setup(g, vals, xi, w.sigma, values32=v32, kappa0=w.kappa0, f=w.f)
         x.zero_()
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=mg_opts, workspace=ws)
 
@@ -727,7 +727,7 @@ def run_mg(args):
     v32 = torch.empty((w.nnz, w.s), dtype=torch.float32, device=dev) if mixed else None
     rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
     x = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)
-    mg = ens.Multigrid(w.N, w.M, w.s, fp32=mixed, device=dev)
+    mg = ens.Multigrid(w.N, w.M, w.s, fp32=mixed, L=w.L, device=dev)
     # a handful of iterations: poll every 4 so few launches run after convergence
     check = min(args.check_every, 4)
     opts = ens.cg_opts(rtol=w.rtol, check_every=check, mixed=mixed, inner_rtol=args.inner_rtol)
@@ -736,7 +736,7 @@ def run_mg(args):
 
     def step():
         ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, values32=v32, rhs=rhs)
-        mg.setup(g, vals, xi, w.sigma, values32=v32, L=w.L, kappa0=w.kappa0, f=w.f)
+        mg.setup(g, vals, xi, w.sigma, values32=v32, kappa0=w.kappa0, f=w.f)
         x.zero_()
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=opts, workspace=ws)
 
@@ -787,7 +787,7 @@ def run_mg(args):
         torch.cuda.synchronize()
         tj = time.perf_counter() - t1
         # per-sample error against an FP64 multigrid solve to 1e-12
-        mg64 = ens.Multigrid(w.N, w.M, w.s, device=dev).setup(g, vals, xi, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f)
+        mg64 = ens.Multigrid(w.N, w.M, w.s, L=w.L, device=dev).setup(g, vals, xi, w.sigma, kappa0=w.kappa0, f=w.f)
         xr = torch.zeros_like(x)
         ens.cg_mg(g, vals, rhs, mg64, x=xr, opts=ens.cg_opts(rtol=1e-12, check_every=4), workspace=None)
         a, r_ = xs.cpu().numpy(), xr.cpu().numpy()

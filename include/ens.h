@@ -303,10 +303,16 @@ typedef struct {
 } ens_mg;
 
 ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, int32_t fp32, size_t* bytes);
-/* Build the coarse levels for the fine matrix `values` [nnz][s] of `graph`
- * (the N^3 mesh; with fp32 also its FP32 copy values32), the KL inputs
- * xi [s][M] (device) and `problem`.  Stream ordered; never synchronises.
- * The fine matrices must stay unchanged while the hierarchy is used. */
+/* The sample-independent part of the hierarchy: the coarse meshes' graphs
+ * and KL tables (correlation length L).  Once per buffer, before any
+ * ens_mg_setup; stream ordered. */
+ens_status ens_mg_build(const ens_mg* mg, double L, hipStream_t stream);
+/* Set the hierarchy up for one ensemble: the coarse levels' matrices for the
+ * KL inputs xi [s][M] (device) and `problem` (whose M and L are those of
+ * ens_mg_build), D^-1 and bounds of every level, the coarsest inverse.
+ * `values` [nnz][s] is the fine matrix of `graph` (the N^3 mesh); with fp32
+ * also its FP32 copy values32.  Stream ordered; never synchronises.  The fine
+ * matrices must stay unchanged while the hierarchy is used. */
 ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const float* values32,
                         const ens_problem* problem, const double* xi, hipStream_t stream);
 /* CG with z = M r from the hierarchy, per-sample scalars and masks and the

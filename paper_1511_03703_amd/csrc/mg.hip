@@ -113,18 +113,14 @@ __device__ inline ChebK cheb_consts(double lmax) {
   return ChebK{1.0 / theta, rho1 * rho0, 2.0 * rho1 / delta};
 }
 
+// One pass over the rows for D^-1 (in the cycle precision, from the FP64
+// diagonal) and the per-sample Gershgorin bound max_i sum_j |a_ij| / a_ii
+// (row sums in ascending entry order, FP64): block maxima over a
+// grid-stride range of rows, then one block over the block maxima.
 template <typename T, int S>
-__global__ __launch_bounds__(256) void k_mg_dinv(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                                 const T* __restrict__ vals, T* __restrict__ dinv) {
-  diag_inv_body<T, S>(n, rp, ci, vals, dinv, blockIdx.x);
-}
-
-// Per-sample Gershgorin bound max_i sum_j |a_ij| / a_ii: block maxima over
-// a grid-stride range of rows, then one block over the block maxima.
-template <int S>
-__global__ __launch_bounds__(256) void k_mg_gersh(int64_t n, const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ ci, const double* __restrict__ vals,
-                                                  double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_mg_diag_bound(int64_t n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, const double* __restrict__ vals,
+                                                       T* __restrict__ dinv, double* __restrict__ part) {
   constexpr int G = 256 / S;
   __shared__ double red[G][S];
   const int e = threadIdx.x % S, g = threadIdx.x / S;
@@ -136,6 +132,7 @@ __global__ __launch_bounds__(256) void k_mg_gersh(int64_t n, const int32_t* __re
       s += fabs(v);
       if (ci[k] == row) dg = v;
     }
+    dinv[row * S + e] = sizeof(T) == 8 ? (T)(1.0 / dg) : (T)1 / (T)dg;
     const double q = s / dg;
     m = q > m ? q : m;
   }
@@ -148,15 +145,24 @@ __global__ __launch_bounds__(256) void k_mg_gersh(int64_t n, const int32_t* __re
   }
 }
 
+// out[e] = max over `rows` partial rows: G = 256/S threads per sample stride
+// the rows, then combine in LDS (max is exact in any order).
 template <int S>
 __global__ __launch_bounds__(256) void k_mg_max(const double* __restrict__ part, int rows, double* __restrict__ out) {
+  constexpr int G = 256 / S;
+  __shared__ double red[G][S];
+  const int e = threadIdx.x % S, g = threadIdx.x / S;
+  double t = 0.0;
+  for (int r = g; r < rows; r += G) {
+    const double v = part[(int64_t)r * S + e];
+    t = v > t ? v : t;
+  }
+  red[g][e] = t;
+  __syncthreads();
   if (threadIdx.x < S) {
-    double t = 0.0;
-    for (int r = 0; r < rows; ++r) {
-      const double v = part[(int64_t)r * S + threadIdx.x];
-      t = v > t ? v : t;
-    }
-    out[threadIdx.x] = t;
+    double u = red[0][e];
+    for (int j = 1; j < G; ++j) u = red[j][e] > u ? red[j][e] : u;
+    out[e] = u;
   }
 }
 
@@ -445,26 +451,33 @@ ENS_MG_INST(float, 16)
 ENS_MG_INST(float, 32)
 #undef ENS_MG_INST
 
+static ens_status build(const MgPlan& P, int M, double L, hipStream_t st) {
+  for (int k = 1; k < P.levels; ++k) {
+    const MgLevel& l = P.lv[k];
+    ens_status rc = ens_graph_build(l.N, l.own_rp, l.own_ci, st);
+    if (rc == ENS_OK) rc = ens_kl_build(l.N, M, L, l.kl, st);
+    if (rc != ENS_OK) return rc;
+  }
+  return ENS_OK;
+}
+
 template <int S>
 static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* xi, hipStream_t st) {
   for (int k = 0; k < P.levels; ++k) {
     const MgLevel& l = P.lv[k];
     if (k > 0) {
-      ens_status rc = ens_graph_build(l.N, l.own_rp, l.own_ci, st);
-      if (rc == ENS_OK) rc = ens_kl_build(l.N, prob.M, prob.L, l.kl, st);
       ens_graph g{(int32_t)l.n, l.nnz, l.own_rp, l.own_ci};
-      if (rc == ENS_OK) rc = ens_assemble(l.N, &g, l.kl, &prob, S, xi, l.own_vals, l.own_vals32, (double*)l.b, st);
+      ens_status rc = ens_assemble(l.N, &g, l.kl, &prob, S, xi, l.own_vals, l.own_vals32, (double*)l.b, st);
       if (rc != ENS_OK) return rc;
     }
-    if (P.fp32)
-      hipLaunchKernelGGL((k_mg_dinv<float, S>), dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, (int)l.n, l.rp,
-                         l.ci, l.vals32, (float*)l.dinv);
-    else
-      hipLaunchKernelGGL((k_mg_dinv<double, S>), dim3(blocks_for(l.n * S, 256)), dim3(256), 0, st, (int)l.n, l.rp,
-                         l.ci, l.vals, (double*)l.dinv);
     const unsigned gb = blocks_for(l.n, 256 / S) < (unsigned)kMgPartRows ? blocks_for(l.n, 256 / S) : kMgPartRows;
-    hipLaunchKernelGGL(k_mg_gersh<S>, dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals, P.part);
-    hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(64), 0, st, P.part, (int)gb, l.lmax);
+    if (P.fp32)
+      hipLaunchKernelGGL((k_mg_diag_bound<float, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals,
+                         (float*)l.dinv, P.part);
+    else
+      hipLaunchKernelGGL((k_mg_diag_bound<double, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals,
+                         (double*)l.dinv, P.part);
+    hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(256), 0, st, P.part, (int)gb, l.lmax);
   }
   const MgLevel& c = P.lv[P.levels - 1];
   if (c.m > 0)
@@ -492,6 +505,24 @@ ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, int32_t fp32, size_t* b
   }
   *bytes = plan.bytes;
   return ENS_OK;
+}
+
+ens_status ens_mg_build(const ens_mg* mg, double L, hipStream_t stream) {
+  ENS_ARG_CHECK(mg && mg->buffer, "null multigrid argument");
+  ENS_ARG_CHECK(((uintptr_t)mg->buffer & 255u) == 0, "multigrid buffer must be 256-byte aligned");
+  ENS_ARG_CHECK(L > 0.0, "correlation length must be positive");
+  size_t need = 0;
+  ens_status rc = ens_mg_bytes(mg->N, mg->M, mg->s, mg->fp32, &need);
+  if (rc != ENS_OK) return rc;
+  if (mg->bytes < need) {
+    set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, need);
+    return ENS_E_NOMEM;
+  }
+  MgPlan plan;
+  mg_plan(mg->N, mg->M, mg->s, mg->fp32 != 0, (char*)mg->buffer, &plan);
+  rc = build(plan, mg->M, L, stream);
+  if (rc == ENS_OK) ENS_LAUNCH_CHECK();
+  return rc;
 }
 
 ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const float* values32,

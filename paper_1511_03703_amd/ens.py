@@ -91,6 +91,7 @@ _SIGS = [
     ("ens_scalar_cg", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _I32, _P, _SZ,
                              ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_mg_bytes", _I32, [_I32, _I32, _I32, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_mg_build", _I32, [ctypes.POINTER(ens_mg), ctypes.c_double, _P]),
     ("ens_mg_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, _P, ctypes.POINTER(ens_problem), _P, _P]),
     ("ens_cg_mg", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(ens_mg), _P, _SZ,
                          ctypes.POINTER(ens_cg_stat), _P]),
@@ -327,14 +328,18 @@ def scalar_cg(g: Graph, values_sm, b_sm, x_sm=None, opts: ens_cg_opts | None = N
 class Multigrid:
     """Device hierarchy of the multigrid preconditioner for one ensemble."""
 
-    def __init__(self, N: int, M: int, s: int, fp32: bool = False, device="cuda"):
+    def __init__(self, N: int, M: int, s: int, fp32: bool = False, L: float = 1.0, device="cuda", stream=None):
         nb = _SZ()
         _check(lib().ens_mg_bytes(N, M, s, int(fp32), ctypes.byref(nb)), "ens_mg_bytes")
         self.buffer = torch.empty(nb.value, dtype=torch.uint8, device=device)
         self.desc = ens_mg(N, M, s, int(fp32), self.buffer.data_ptr(), nb.value)
+        self.L = L
+        _check(lib().ens_mg_build(ctypes.byref(self.desc), L, _stream(stream)), "ens_mg_build")
 
-    def setup(self, g: Graph, values, xi, sigma, values32=None, L=1.0, kappa0=1.0, f=1.0, stream=None):
-        prob = ens_problem(self.desc.M, L, kappa0, sigma, f)
+    def setup(self, g: Graph, values, xi, sigma, values32=None, L=None, kappa0=1.0, f=1.0, stream=None):
+        if L is not None and L != self.L:
+            raise ValueError("the hierarchy's KL tables were built for another correlation length")
+        prob = ens_problem(self.desc.M, self.L, kappa0, sigma, f)
         gc = g.c()
         self._values = (values, values32)
         _check(lib().ens_mg_setup(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(values), _ptr(values32),
