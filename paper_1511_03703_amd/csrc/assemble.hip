@@ -16,7 +16,7 @@
 //   K_e[a][b] = sum_q kappa_q (h/8) G_q[a][b],
 //   G_q[a][b] = grad_ref N_a(g_q) . grad_ref N_b(g_q)       (dimensionless)
 // kappa_q = kappa0 + sigma sum_m sqrt(lambda_m) phi_m(x_q) y_m, with the 1D
-// factors of phi_m read from the KL table.
+// factors of phi_m read from the KL table (staged in LDS when it fits).
 #include "common.hpp"
 
 namespace ens {
@@ -61,7 +61,10 @@ static hipError_t upload_G() {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_G), G, sizeof(G));
 }
 
-template <int S>
+// LDS: the 1D eigenfunction table (M x 2N doubles) is staged in LDS when it
+// fits (dynamic shared memory of the launch); otherwise it is read from the
+// cached global table.
+template <int S, int LDS>
 __global__ __launch_bounds__(256) void k_assemble(int N, const double* __restrict__ kl_sqrt_lam,
                                                    const int32_t* __restrict__ kl_triple,
                                                    const double* __restrict__ kl_phi, int M, double kappa0,
@@ -72,11 +75,15 @@ __global__ __launch_bounds__(256) void k_assemble(int N, const double* __restric
   constexpr int RPB = 256 / S;  // rows per block
   // sigma sqrt(lambda_m) y_m of every sample of the block, [e][m]
   __shared__ double s_cm[S * kAsmMaxM];
+  extern __shared__ double s_phi[];
   for (int t = threadIdx.x; t < S * M; t += blockDim.x) {
     const int ee = t / M, m = t % M;
     s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)ee * M + m];
   }
+  if (LDS)
+    for (int t = threadIdx.x; t < M * 2 * N; t += blockDim.x) s_phi[t] = kl_phi[t];
   __syncthreads();
+  const double* tab = LDS ? s_phi : kl_phi;
 
   const int n1 = N + 1;
   const int64_t n = (int64_t)n1 * n1 * n1;
@@ -107,14 +114,20 @@ __global__ __launch_bounds__(256) void k_assemble(int N, const double* __restric
         double kq[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) kq[q] = 0.0;
+#pragma unroll 2
         for (int m = 0; m < M; ++m) {
+          // mode m at the 8 points: c_m X(qx) Y(qy) Z(qz), the (qy, qz)
+          // products formed once for both qx
           const double c = s_cm[e * M + m];
-          const double* px = kl_phi + kl_triple[3 * m + 0] * two_n + 2 * ex;
-          const double* py = kl_phi + kl_triple[3 * m + 1] * two_n + 2 * ey;
-          const double* pz = kl_phi + kl_triple[3 * m + 2] * two_n + 2 * ez;
+          const double* px = tab + kl_triple[3 * m + 0] * two_n + 2 * ex;
+          const double* py = tab + kl_triple[3 * m + 1] * two_n + 2 * ey;
+          const double* pz = tab + kl_triple[3 * m + 2] * two_n + 2 * ez;
           const double fx[2] = {px[0], px[1]}, fy[2] = {py[0], py[1]}, fz[2] = {pz[0], pz[1]};
+          double yz[4];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) kq[q] += c * (fx[q & 1] * fy[(q >> 1) & 1] * fz[(q >> 2) & 1]);
+          for (int t = 0; t < 4; ++t) yz[t] = c * (fy[t & 1] * fz[t >> 1]);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) kq[q] = (kappa0 + kq[q]) * wscale;
@@ -189,12 +202,18 @@ extern "C" ens_status ens_assemble(int32_t N, const ens_graph* graph, const void
   const double* phi = (const double*)(base + phi_off);
   const int rpb = 256 / s;
   int64_t blocks = (n + rpb - 1) / rpb;
+  const size_t table = (size_t)M * 2 * N * sizeof(double);
+  const size_t lds_bytes = table > 0 && table <= 48 * 1024 ? table : 0;
   prof_begin(ENS_K_ASSEMBLE, stream);
   switch (s) {
 #define ENS_ASM_CASE(SS)                                                                                  \
   case SS:                                                                                                \
-    hipLaunchKernelGGL(k_assemble<SS>, dim3((unsigned)blocks), dim3(256), 0, stream, N, sq, tr, phi, M,   \
-                       prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values, values32, rhs);    \
+    if (lds_bytes)                                                                                        \
+      hipLaunchKernelGGL((k_assemble<SS, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, stream, N, sq, tr,  \
+                         phi, M, prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values, values32, rhs); \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_assemble<SS, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, N, sq, tr, phi, M, \
+                         prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values, values32, rhs);  \
     break;
     ENS_ASM_CASE(4)
     ENS_ASM_CASE(8)
