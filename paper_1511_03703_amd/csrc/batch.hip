@@ -168,6 +168,7 @@ static __global__ void kb_ctl_init(BatchDev bd, int ngroups, double rtol, int ma
       c->max_outer = 0;
       c->mixed = 0;
       c->coupled = 0;
+      c->xnz = 1;
       c->n_active = 0;
       c->n_oactive = 0;
     }

@@ -72,8 +72,15 @@ template <int S, typename TR>
 __global__ __launch_bounds__(256) void k_residual(int n, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const double* __restrict__ vals,
                                                   const double* __restrict__ x, const double* __restrict__ b,
-                                                  TR* __restrict__ rout, double* __restrict__ part) {
-  residual_body<S, TR, 4>(n, rp, ci, vals, x, b, rout, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
+                                                  TR* __restrict__ rout, double* __restrict__ part,
+                                                  const Ctl* xflag) {
+  // a zero initial guess (xflag->xnz == 0) makes r = b without the product
+  const bool x_zero = xflag && xflag->xnz == 0;
+  residual_body<S, TR, 4>(n, rp, ci, vals, x, b, rout, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S, x_zero);
+}
+
+static __global__ __launch_bounds__(256) void k_x_nonzero(int64_t total, const double* __restrict__ x, Ctl* c) {
+  x_nonzero_body(total, x, c);
 }
 
 template <typename T, int S>
@@ -313,11 +320,16 @@ static ens_status read_stats(Ctl* ctl, int s, ens_cg_stat* stats, hipStream_t st
 // finalize step `op` on its norms.
 template <int S, typename TR>
 static void residual(const ens_graph* g, const double* vals, const double* x, const double* b, TR* rout,
-                     const Work& w, int op, int arg, hipStream_t st) {
+                     const Work& w, int op, int arg, hipStream_t st, bool initial = false) {
   using M = EnsMap<double, S>;
   const unsigned sb = grid_for(g->n, 4 * M::RPW);
+  if (initial) {
+    const int64_t total = (int64_t)g->n * S;
+    hipLaunchKernelGGL(k_x_nonzero, dim3(grid_for(total, 256 * 16) < 1024 ? grid_for(total, 256 * 16) : 1024),
+                       dim3(256), 0, st, total, x, w.ctl);
+  }
   hipLaunchKernelGGL((k_residual<S, TR>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
-                     rout, w.part);
+                     rout, w.part, initial ? (const Ctl*)w.ctl : (const Ctl*)nullptr);
   reduce<S, 2>(w, sb, op, arg, 0, st);
 }
 
@@ -340,7 +352,7 @@ static ens_status cg_fp64(const ens_graph* g, const double* vals, const double* 
   const int64_t total = n * S;
   hipLaunchKernelGGL((k_diag_inv<double, S>), dim3(grid_for(total, 256)), dim3(256), 0, st, g->n, g->row_ptr,
                      g->col_idx, vals, dinv);
-  residual<S, double>(g, vals, x, b, r, w, OP_START, 0, st);
+  residual<S, double>(g, vals, x, b, r, w, OP_START, 0, st, true);
   hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
   cg_start<double, S>(n, r, dinv, p, (double*)nullptr, w, st);
   ENS_LAUNCH_CHECK();
@@ -365,7 +377,7 @@ static ens_status cg_mixed(const ens_graph* g, const double* vals, const float* 
                      g->col_idx, vals32, dinv);
   ENS_LAUNCH_CHECK();
   for (int outer = 0;; ++outer) {
-    residual<S, float>(g, vals, x, b, r, w, OP_OUTER, outer, st);
+    residual<S, float>(g, vals, x, b, r, w, OP_OUTER, outer, st, outer == 0);
     if (outer == 0)
       hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
     ENS_LAUNCH_CHECK();
@@ -592,7 +604,7 @@ static ens_status cg_mg(const ens_graph* g, const double* vals, const double* b,
   double* z = (double*)w.vec[3];
   const int64_t n = g->n;
   const int64_t total = n * S;
-  residual<S, double>(g, vals, x, b, r, w, OP_START, 0, st);
+  residual<S, double>(g, vals, x, b, r, w, OP_START, 0, st, true);
   hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
   mg_start<double, S>(n, plan, r, z, p, w, st);
   ENS_LAUNCH_CHECK();
@@ -624,7 +636,7 @@ static ens_status cg_mixed_mg(const ens_graph* g, const double* vals, const floa
   const int64_t n = g->n;
   const int64_t total = n * S;
   for (int outer = 0;; ++outer) {
-    residual<S, float>(g, vals, x, b, r, w, OP_OUTER, outer, st);
+    residual<S, float>(g, vals, x, b, r, w, OP_OUTER, outer, st, outer == 0);
     if (outer == 0)
       hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
     ENS_LAUNCH_CHECK();

@@ -22,7 +22,8 @@ struct Ctl {
   int32_t n_active, n_oactive;
   double rtol, inner_rtol;
   int32_t max_iter, inner_max_iter, max_outer, mixed;
-  int32_t coupled, pad;
+  int32_t coupled;
+  int32_t xnz;  // set when the initial guess has a nonzero entry
   double tot[2 * kMaxS];
 };
 
@@ -235,6 +236,7 @@ static __global__ void k_ctl_init(Ctl* c, double rtol, double inner_rtol, int ma
     c->max_outer = max_outer;
     c->mixed = mixed;
     c->coupled = coupled;
+    c->xnz = 0;
     c->n_active = 0;
     c->n_oactive = 0;
   }
@@ -273,7 +275,7 @@ template <int S, typename TR, int NW>
 __device__ inline void residual_body(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                      const double* __restrict__ vals, const double* __restrict__ x,
                                      const double* __restrict__ b, TR* __restrict__ rout, int64_t blk,
-                                     double* __restrict__ dst) {
+                                     double* __restrict__ dst, bool x_zero = false) {
   using M = EnsMap<double, S>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane % M::L;
@@ -282,7 +284,7 @@ __device__ inline void residual_body(int n, const int32_t* __restrict__ rp, cons
   for (int j = 0; j < M::V; ++j) acc[0][j] = acc[1][j] = 0.0;
   const int64_t row = (blk * NW + wave) * M::RPW + lane / M::L;
   if (row < n) {
-    typename M::vt ax = ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
+    typename M::vt ax = x_zero ? (typename M::vt)0.0 : ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
     typename M::vt bv = ((const typename M::vt*)b)[row * M::L + sub];
     typename M::vt r = bv - ax;
 #pragma unroll
@@ -601,6 +603,15 @@ __device__ inline void pupdate_z_body(int64_t nchunks, const T* __restrict__ z, 
       store_stream((vt*)p + i, pn);
     }
   }
+}
+
+// c->xnz = 1 if any of the `total` entries of x is nonzero (every block
+// that finds one stores the same value).
+__device__ inline void x_nonzero_body(int64_t total, const double* __restrict__ x, Ctl* c) {
+  int any = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    any |= x[i] != 0.0;
+  if (__syncthreads_or(any) && threadIdx.x == 0) c->xnz = 1;
 }
 
 // x = 0 for samples whose right-hand side is zero.
