@@ -305,7 +305,10 @@ typedef struct {
 ens_status ens_mg_bytes(int32_t N, int32_t M, int32_t s, int32_t fp32, size_t* bytes);
 /* The sample-independent part of the hierarchy: the coarse meshes' graphs
  * and KL tables (correlation length L).  Once per buffer, before any
- * ens_mg_setup; stream ordered. */
+ * ens_mg_setup; stream ordered.  The library records which buffers (by
+ * address and shape) are built and set up, and for which L: ens_mg_setup on
+ * an unbuilt buffer or with another problem->L, and ens_cg_mg on a buffer
+ * not set up, return ENS_E_ARG. */
 ens_status ens_mg_build(const ens_mg* mg, double L, hipStream_t stream);
 /* Set the hierarchy up for one ensemble: the coarse levels' matrices for the
  * KL inputs xi [s][M] (device) and `problem` (whose M and L are those of
@@ -315,6 +318,10 @@ ens_status ens_mg_build(const ens_mg* mg, double L, hipStream_t stream);
  * matrices must stay unchanged while the hierarchy is used. */
 ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const float* values32,
                         const ens_problem* problem, const double* xi, hipStream_t stream);
+/* Forget the buffer's built / set-up record (host only, never fails on an
+ * unknown buffer).  Call it before the buffer is freed: a later allocation
+ * at the same address would otherwise pass as built. */
+ens_status ens_mg_release(const ens_mg* mg);
 /* CG with z = M r from the hierarchy, per-sample scalars and masks and the
  * stopping rule of ens_cg (opts->coupled must be 0).  opts->mixed = 0: FP64
  * CG with an FP64 cycle.  opts->mixed = 1: the FP32-in-FP64 refinement of

@@ -22,10 +22,56 @@
 // buffers because every row pass gathers its input at neighbouring rows.
 #include <string.h>
 
+#include <mutex>
+#include <vector>
+
 #include "cgcore.hpp"
 #include "mg.hpp"
 
 namespace ens {
+
+// Hierarchies whose sample-independent part (ens_mg_build) or whole set-up
+// (ens_mg_setup) is done, by buffer and shape: setting up an unbuilt buffer
+// would read uninitialised graphs, so both calls refuse it.
+struct MgRecord {
+  const void* buffer;
+  int N, M, s, fp32;
+  double L;
+  int stage;  // 1 built, 2 set up
+};
+static std::mutex g_mg_mu;
+static std::vector<MgRecord> g_mg;
+
+static void mg_mark(const ens_mg* mg, double L, int stage) {
+  std::lock_guard<std::mutex> lk(g_mg_mu);
+  for (auto& r : g_mg)
+    if (r.buffer == mg->buffer) {
+      if (stage == 1) r = MgRecord{mg->buffer, mg->N, mg->M, mg->s, mg->fp32, L, 1};
+      else if (r.N == mg->N && r.M == mg->M && r.s == mg->s && r.fp32 == mg->fp32) r.stage = stage;
+      return;
+    }
+  g_mg.push_back(MgRecord{mg->buffer, mg->N, mg->M, mg->s, mg->fp32, L, stage});
+}
+
+static const MgRecord* mg_find(const ens_mg* mg) {
+  for (const auto& r : g_mg)
+    if (r.buffer == mg->buffer && r.N == mg->N && r.M == mg->M && r.s == mg->s && r.fp32 == mg->fp32) return &r;
+  return nullptr;
+}
+
+// The stage reached by this buffer with this shape (0: none).
+int mg_stage(const ens_mg* mg) {
+  std::lock_guard<std::mutex> lk(g_mg_mu);
+  const MgRecord* r = mg_find(mg);
+  return r ? r->stage : 0;
+}
+
+// The correlation length the buffer was built for (0: not built).
+static double mg_built_L(const ens_mg* mg) {
+  std::lock_guard<std::mutex> lk(g_mg_mu);
+  const MgRecord* r = mg_find(mg);
+  return r ? r->L : 0.0;
+}
 
 constexpr int kMgPartRows = 1024;
 
@@ -522,6 +568,7 @@ ens_status ens_mg_build(const ens_mg* mg, double L, hipStream_t stream) {
   mg_plan(mg->N, mg->M, mg->s, mg->fp32 != 0, (char*)mg->buffer, &plan);
   rc = build(plan, mg->M, L, stream);
   if (rc == ENS_OK) ENS_LAUNCH_CHECK();
+  if (rc == ENS_OK) mg_mark(mg, L, 1);
   return rc;
 }
 
@@ -542,14 +589,33 @@ ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* 
     set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, need);
     return ENS_E_NOMEM;
   }
+  const double Lb = mg_built_L(mg);
+  if (Lb <= 0.0) {
+    set_error("multigrid buffer not built: call ens_mg_build first");
+    return ENS_E_ARG;
+  }
+  ENS_ARG_CHECK(problem->L == Lb, "problem->L differs from the correlation length the hierarchy was built for");
   mg_plan(mg->N, mg->M, mg->s, mg->fp32 != 0, (char*)mg->buffer, &plan);
   mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values, mg->fp32 ? values32 : nullptr);
   switch (mg->s) {
-    case 4: return setup<4>(plan, *problem, xi, stream);
-    case 8: return setup<8>(plan, *problem, xi, stream);
-    case 16: return setup<16>(plan, *problem, xi, stream);
-    default: return setup<32>(plan, *problem, xi, stream);
+    case 4: rc = setup<4>(plan, *problem, xi, stream); break;
+    case 8: rc = setup<8>(plan, *problem, xi, stream); break;
+    case 16: rc = setup<16>(plan, *problem, xi, stream); break;
+    default: rc = setup<32>(plan, *problem, xi, stream); break;
   }
+  if (rc == ENS_OK) mg_mark(mg, Lb, 2);
+  return rc;
+}
+
+ens_status ens_mg_release(const ens_mg* mg) {
+  ENS_ARG_CHECK(mg, "null multigrid argument");
+  std::lock_guard<std::mutex> lk(g_mg_mu);
+  for (size_t i = 0; i < g_mg.size(); ++i)
+    if (g_mg[i].buffer == mg->buffer) {
+      g_mg.erase(g_mg.begin() + (long)i);
+      break;
+    }
+  return ENS_OK;
 }
 
 }  // extern "C"

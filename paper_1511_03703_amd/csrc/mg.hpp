@@ -44,6 +44,8 @@ struct MgPlan {
 };
 
 int mg_levels(int N, int* Ns);
+// 0: buffer unknown; 1: built (ens_mg_build); 2: set up (ens_mg_setup).
+int mg_stage(const ens_mg* mg);
 // Carve the hierarchy buffer (base nullable: sizes only).  Returns false if
 // the coarsest level is too large for its dense solve.
 bool mg_plan(int N, int M, int S, int fp32, char* base, MgPlan* plan);

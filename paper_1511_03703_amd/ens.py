@@ -93,6 +93,7 @@ _SIGS = [
     ("ens_mg_bytes", _I32, [_I32, _I32, _I32, _I32, ctypes.POINTER(_SZ)]),
     ("ens_mg_build", _I32, [ctypes.POINTER(ens_mg), ctypes.c_double, _P]),
     ("ens_mg_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, _P, ctypes.POINTER(ens_problem), _P, _P]),
+    ("ens_mg_release", _I32, [ctypes.POINTER(ens_mg)]),
     ("ens_cg_mg", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(ens_mg), _P, _SZ,
                          ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_scalar_cg_concurrent_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(_SZ)]),
@@ -335,6 +336,13 @@ class Multigrid:
         self.desc = ens_mg(N, M, s, int(fp32), self.buffer.data_ptr(), nb.value)
         self.L = L
         _check(lib().ens_mg_build(ctypes.byref(self.desc), L, _stream(stream)), "ens_mg_build")
+
+    def __del__(self):
+        # the library's record of this buffer goes before the memory does
+        try:
+            lib().ens_mg_release(ctypes.byref(self.desc))
+        except Exception:
+            pass
 
     def setup(self, g: Graph, values, xi, sigma, values32=None, L=None, kappa0=1.0, f=1.0, stream=None):
         if L is not None and L != self.L:

@@ -102,6 +102,26 @@ def test_mg_edge_cases_and_errors(E):
     with pytest.raises(E.EnsError) as ex:
         E.Multigrid(11, M, s)  # odd 11: a 1000-unknown coarse block
     assert ex.value.status == E.ENS_E_UNSUPPORTED
+    # a buffer that was never built or set up is refused before any launch
+    import ctypes
+    raw = torch.empty(mg.buffer.numel(), dtype=torch.uint8, device=DEV)
+    desc = E.ens_mg(N, M, s, 0, raw.data_ptr(), raw.numel())
+    prob = E.ens_problem(M, 1.0, 1.0, 0.2, 1.0)
+    gc = g.c()
+    xt = torch.as_tensor(xi, device=DEV)
+    assert E.lib().ens_mg_setup(ctypes.byref(desc), ctypes.byref(gc), ctypes.c_void_p(vals.data_ptr()), None,
+                                ctypes.byref(prob), ctypes.c_void_p(xt.data_ptr()), None) == E.ENS_E_ARG
+    # a built buffer set up for another correlation length is refused too
+    prob2 = E.ens_problem(M, 0.5, 1.0, 0.2, 1.0)
+    assert E.lib().ens_mg_setup(ctypes.byref(mg.desc), ctypes.byref(gc), ctypes.c_void_p(vals.data_ptr()), None,
+                                ctypes.byref(prob2), ctypes.c_void_p(xt.data_ptr()), None) == E.ENS_E_ARG
+    ws = torch.empty(E.cg_workspace_bytes(g, s, E.cg_opts()), dtype=torch.uint8, device=DEV)
+    st_ = (E.ens_cg_stat * s)()
+    xx = torch.zeros_like(rhs)
+    assert E.lib().ens_cg_mg(ctypes.byref(gc), s, ctypes.c_void_p(vals.data_ptr()), None,
+                             ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(xx.data_ptr()),
+                             ctypes.byref(E.cg_opts()), ctypes.byref(desc), ctypes.c_void_p(ws.data_ptr()),
+                             ws.numel(), st_, None) == E.ENS_E_ARG
 
 
 def test_mg_is_deterministic(E):
