@@ -23,7 +23,11 @@
  *   - textbook Jacobi-preconditioned CG, one sample at a time (Sec. 3.4 uses
  *     CG; the ensemble system is block diagonal, Eq. kron_sys, so an ensemble
  *     solve with per-sample scalars is s independent scalar solves);
- *   - a dense Cholesky solve for brute-force checks on tiny meshes.
+ *   - a dense Cholesky solve for brute-force checks on tiny meshes;
+ *   - the nonlinear advection-diffusion-reaction residual and its Jacobian
+ *     (Sec. 4, Eq. diffusion_sys and fenl_lin_sys, Alg. "assembly" with
+ *     alpha, beta != 0), restarted right-preconditioned GMRES for the
+ *     nonsymmetric Newton systems, and Newton's method per sample.
  *
  * Readings of points the paper leaves open (source term, boundary condition,
  * KL scaling and mode order, quadrature, stopping rule) are listed where they
@@ -1097,6 +1101,413 @@ int orc_ens_mg_pcg(int N, int M, double L, double kappa0, double sigma, double f
     if (r) rc = r;
     for (int64_t i = 0; i < n; ++i) x[i * s + e] = xe[i];
     free(xe);
+  }
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The nonlinear problem (Sec. 4, Eq. diffusion_sys):                        */
+/*   -div(kappa grad u) + alpha v.grad u + beta u^2 = f,  u = 0 on the       */
+/* boundary (the source f = fconst and the boundary condition as in the      */
+/* linear case; v a constant velocity vector).  Galerkin Q1 with the same    */
+/* 2x2x2 Gauss rule.  For interior node i                                    */
+/*   F_i(u) = sum_e sum_q w_q [ kappa grad N_a . grad u_h                    */
+/*            + alpha N_a (v . grad u_h) + beta N_a u_h^2 - f N_a ]          */
+/* with u_h = sum_b N_b u_b over the element's 8 nodes (boundary nodes       */
+/* included with their values), and the Jacobian A = dF/du of Eq.            */
+/* fenl_lin_sys:                                                             */
+/*   A_ij = sum_e sum_q w_q [ kappa grad N_a . grad N_b                      */
+/*            + alpha N_a (v . grad N_b) + 2 beta u_h N_a N_b ].             */
+/* Boundary rows: F_i = u_i and an identity row; the boundary columns of     */
+/* interior rows are stored zeros (Dirichlet elimination, as for the linear  */
+/* matrix).  `load` (nullable) receives the source part sum w_q f N_a of     */
+/* interior rows (zero on the boundary): F(0) = -load.                        */
+/* ------------------------------------------------------------------------ */
+
+int orc_nl_assemble_scalar(int N, const int32_t *row_ptr, const int32_t *col_idx, const double *acoef,
+                           double fconst, double alpha, const double *vel, double beta, const double *u,
+                           double *F, double *values, double *load) {
+  if (N < 1 || !row_ptr || !col_idx || !acoef || !vel || !u || !F) return ORC_E_ARG;
+  const double h = 1.0 / (double)N;
+  const double wq = h * h * h / 8.0;
+  int64_t n = orc_num_nodes(N), nnz = row_ptr[n], ne = orc_num_elems(N);
+  for (int64_t i = 0; i < n; ++i) F[i] = 0.0;
+  if (values)
+    for (int64_t k = 0; k < nnz; ++k) values[k] = 0.0;
+  if (load)
+    for (int64_t i = 0; i < n; ++i) load[i] = 0.0;
+  double Nq[8][8], G[8][8][3];
+  for (int q = 0; q < 8; ++q) {
+    double s = gauss01(q & 1), t = gauss01((q >> 1) & 1), w = gauss01((q >> 2) & 1);
+    for (int a = 0; a < 8; ++a) {
+      int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      Nq[q][a] = lfun(ax, s) * lfun(ay, t) * lfun(az, w);
+      G[q][a][0] = dlfun(ax) * lfun(ay, t) * lfun(az, w) / h;
+      G[q][a][1] = lfun(ax, s) * dlfun(ay) * lfun(az, w) / h;
+      G[q][a][2] = lfun(ax, s) * lfun(ay, t) * dlfun(az) / h;
+    }
+  }
+  for (int64_t e = 0; e < ne; ++e) {
+    double ue[8], Fe[8], Ae[8][8], Le[8];
+    for (int a = 0; a < 8; ++a) ue[a] = u[elem_node(N, e, a)];
+    for (int a = 0; a < 8; ++a) {
+      Fe[a] = 0.0;
+      Le[a] = 0.0;
+      for (int b = 0; b < 8; ++b) Ae[a][b] = 0.0;
+    }
+    for (int q = 0; q < 8; ++q) {
+      const double kap = acoef[e * 8 + q];
+      double uq = 0.0, gu[3] = {0.0, 0.0, 0.0};
+      for (int b = 0; b < 8; ++b) {
+        uq += Nq[q][b] * ue[b];
+        for (int d = 0; d < 3; ++d) gu[d] += G[q][b][d] * ue[b];
+      }
+      const double vgu = vel[0] * gu[0] + vel[1] * gu[1] + vel[2] * gu[2];
+      for (int a = 0; a < 8; ++a) {
+        const double diff = G[q][a][0] * gu[0] + G[q][a][1] * gu[1] + G[q][a][2] * gu[2];
+        Fe[a] += wq * (kap * diff + alpha * Nq[q][a] * vgu + beta * Nq[q][a] * uq * uq - fconst * Nq[q][a]);
+        Le[a] += wq * fconst * Nq[q][a];
+        for (int b = 0; b < 8; ++b) {
+          const double gg = G[q][a][0] * G[q][b][0] + G[q][a][1] * G[q][b][1] + G[q][a][2] * G[q][b][2];
+          const double vgb = vel[0] * G[q][b][0] + vel[1] * G[q][b][1] + vel[2] * G[q][b][2];
+          Ae[a][b] += wq * (kap * gg + alpha * Nq[q][a] * vgb + 2.0 * beta * uq * Nq[q][a] * Nq[q][b]);
+        }
+      }
+    }
+    for (int a = 0; a < 8; ++a) {
+      int64_t I = elem_node(N, e, a);
+      F[I] += Fe[a];
+      if (load) load[I] += Le[a];
+      if (values)
+        for (int b = 0; b < 8; ++b) values[find_slot(row_ptr, col_idx, I, elem_node(N, e, b))] += Ae[a][b];
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const int bi = is_boundary_node(N, i);
+    if (bi) {
+      F[i] = u[i];
+      if (load) load[i] = 0.0;
+    }
+    if (values)
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        if (bi) values[k] = (col_idx[k] == i) ? 1.0 : 0.0;
+        else if (is_boundary_node(N, col_idx[k])) values[k] = 0.0;
+      }
+  }
+  return ORC_OK;
+}
+
+/* The ensemble of orc_nl_assemble_scalar in the commuted layout: u, F, load
+ * [n][s]; values [nnz][s] (nullable); vel[3]. */
+int orc_ens_nl_assemble(int N, const int32_t *row_ptr, const int32_t *col_idx, int M, double L, double kappa0,
+                        double sigma, double fconst, double alpha, const double *vel, double beta, int s,
+                        const double *xi, const double *u, double *F, double *values, double *load) {
+  if (N < 1 || s < 1) return ORC_E_ARG;
+  int64_t n = orc_num_nodes(N), nnz = row_ptr[n], ne = orc_num_elems(N);
+  int rc = ORC_OK;
+  #pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < s; ++e) {
+    double *ac = malloc(sizeof(double) * 8 * (size_t)ne);
+    double *ue = malloc(sizeof(double) * (size_t)n), *fe = malloc(sizeof(double) * (size_t)n);
+    double *le = malloc(sizeof(double) * (size_t)n);
+    double *v = values ? malloc(sizeof(double) * (size_t)nnz) : NULL;
+    if (!ac || !ue || !fe || !le || (values && !v)) {
+      rc = ORC_E_NOMEM;
+      free(ac); free(ue); free(fe); free(le); free(v);
+      continue;
+    }
+    for (int64_t i = 0; i < n; ++i) ue[i] = u[i * s + e];
+    orc_kl_coef_qp(N, M, L, kappa0, sigma, xi + (int64_t)e * M, ac);
+    orc_nl_assemble_scalar(N, row_ptr, col_idx, ac, fconst, alpha, vel, beta, ue, fe, v, le);
+    for (int64_t i = 0; i < n; ++i) F[i * s + e] = fe[i];
+    if (load)
+      for (int64_t i = 0; i < n; ++i) load[i * s + e] = le[i];
+    if (values)
+      for (int64_t k = 0; k < nnz; ++k) values[k * s + e] = v[k];
+    free(ac); free(ue); free(fe); free(le); free(v);
+  }
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Restarted GMRES(m) with right preconditioning, one sample, for the        */
+/* nonsymmetric Newton systems (the Krylov solve of Eq. fenl_lin_sys when    */
+/* alpha != 0).  Textbook form: Arnoldi with modified Gram-Schmidt on        */
+/* A M, Givens rotations on the Hessenberg matrix, the residual estimate     */
+/* |g_{j+1}| tested against rtol ||b|| after every step, at a cycle's end    */
+/* y = R^{-1} g and x += M (V y), then the true residual r = b - A x.  The   */
+/* solve has converged when the true residual meets the tolerance; a cycle   */
+/* whose estimate met it but whose true residual does not is followed by     */
+/* another.  M: prec 0 Jacobi (the diagonal of A), 1 the multigrid V-cycle   */
+/* of the sample's diffusion operator (the alpha = beta = 0 matrix).          */
+/* fixed_iters >= 0: exactly that many Arnoldi steps in one cycle (needs     */
+/* fixed_iters <= restart), no residual test.  Iterations count Arnoldi      */
+/* steps (products with A) over all cycles.                                  */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_GM_MAX_RESTART 64
+
+typedef struct {
+  int kind;             /* 0 Jacobi, 1 multigrid */
+  const double *dinv;   /* Jacobi */
+  orc_level *lv;        /* multigrid levels */
+  int nl;
+} orc_prec;
+
+static void prec_apply(const orc_prec *P, int64_t n, const double *r, double *z) {
+  if (P->kind == 0) {
+    for (int64_t i = 0; i < n; ++i) z[i] = P->dinv[i] * r[i];
+  } else {
+    vcycle(P->lv, 0, P->nl, r, z);
+  }
+}
+
+static int gmres_core(int64_t n, const int32_t *rp, const int32_t *ci, const double *vals, const double *b,
+                      double *x, const orc_prec *P, double rtol, int restart, int max_iter, int fixed_iters,
+                      int32_t *iters_out, double *rel_res_out, int32_t *status_out) {
+  if (restart < 1 || restart > ORC_GM_MAX_RESTART) return ORC_E_ARG;
+  if (fixed_iters > restart) return ORC_E_ARG;
+  const int m = restart;
+  double *V = malloc(sizeof(double) * (size_t)n * (size_t)(m + 1));
+  double *w = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
+  double *r = malloc(sizeof(double) * (size_t)n), *t = malloc(sizeof(double) * (size_t)n);
+  double H[ORC_GM_MAX_RESTART + 1][ORC_GM_MAX_RESTART], cs[ORC_GM_MAX_RESTART], sn[ORC_GM_MAX_RESTART];
+  double g[ORC_GM_MAX_RESTART + 1], y[ORC_GM_MAX_RESTART];
+  if (!V || !w || !z || !r || !t) {
+    free(V); free(w); free(z); free(r); free(t);
+    return ORC_E_NOMEM;
+  }
+  const int test = fixed_iters < 0;
+  const int limit = test ? max_iter : fixed_iters;
+  const double nb = sqrt(dot(n, b, b));
+  const double tol = rtol * nb;
+  int total = 0, status = ORC_MAXITER;
+  double beta = 0.0;
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    status = ORC_CONVERGED;
+  } else {
+    orc_spmv(n, rp, ci, vals, x, t);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+    beta = sqrt(dot(n, r, r));
+    if (!isfinite(beta)) status = ORC_NONFINITE;
+    else if (test && beta <= tol) status = ORC_CONVERGED;
+    else if (!test && limit == 0) status = ORC_CONVERGED;
+    while (status == ORC_MAXITER) {
+      for (int64_t i = 0; i < n; ++i) V[i] = r[i] / beta;
+      for (int i = 0; i <= m; ++i) g[i] = 0.0;
+      g[0] = beta;
+      int k = 0;
+      for (int j = 0; j < m && total < limit; ++j) {
+        double *vj = V + (size_t)j * n;
+        prec_apply(P, n, vj, z);
+        orc_spmv(n, rp, ci, vals, z, w);
+        for (int i = 0; i <= j; ++i) {
+          const double *vi = V + (size_t)i * n;
+          H[i][j] = dot(n, w, vi);
+          for (int64_t q = 0; q < n; ++q) w[q] -= H[i][j] * vi[q];
+        }
+        const double hnext = sqrt(dot(n, w, w));
+        H[j + 1][j] = hnext;
+        for (int i = 0; i < j; ++i) {
+          const double a = H[i][j], c = H[i + 1][j];
+          H[i][j] = cs[i] * a + sn[i] * c;
+          H[i + 1][j] = -sn[i] * a + cs[i] * c;
+        }
+        const double a = H[j][j], c = H[j + 1][j];
+        const double den = sqrt(a * a + c * c);
+        ++total;
+        k = j + 1;
+        if (!isfinite(den)) { status = ORC_NONFINITE; break; }
+        if (den == 0.0) { status = ORC_BREAKDOWN; break; }
+        cs[j] = a / den;
+        sn[j] = c / den;
+        H[j][j] = den;
+        H[j + 1][j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        if (test && fabs(g[j + 1]) <= tol) break;
+        if (hnext == 0.0) break; /* the Krylov space is invariant: x is exact */
+        double *vn = V + (size_t)(j + 1) * n;
+        for (int64_t q = 0; q < n; ++q) vn[q] = w[q] / hnext;
+      }
+      if (status != ORC_MAXITER) break;
+      /* y = R^-1 g, x += M (V y) */
+      for (int i = k - 1; i >= 0; --i) {
+        double v = g[i];
+        for (int l = i + 1; l < k; ++l) v -= H[i][l] * y[l];
+        y[i] = v / H[i][i];
+      }
+      for (int64_t q = 0; q < n; ++q) t[q] = 0.0;
+      for (int i = 0; i < k; ++i)
+        for (int64_t q = 0; q < n; ++q) t[q] += y[i] * V[(size_t)i * n + q];
+      prec_apply(P, n, t, z);
+      for (int64_t q = 0; q < n; ++q) x[q] += z[q];
+      orc_spmv(n, rp, ci, vals, x, t);
+      for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+      beta = sqrt(dot(n, r, r));
+      if (!isfinite(beta)) { status = ORC_NONFINITE; break; }
+      if (!test) { status = ORC_CONVERGED; break; }
+      if (beta <= tol) { status = ORC_CONVERGED; break; }
+      if (total >= limit || k == 0) break;
+    }
+  }
+  *iters_out = total;
+  *rel_res_out = nb > 0.0 ? beta / nb : 0.0;
+  *status_out = status;
+  free(V); free(w); free(z); free(r); free(t);
+  return ORC_OK;
+}
+
+/* One sample's GMRES on the matrix `values` of the N^3 mesh's graph; prec 1
+ * builds the multigrid levels of the sample's diffusion problem (M, L,
+ * kappa0, sigma, xi). */
+int orc_gmres(int N, const int32_t *rp, const int32_t *ci, const double *values, const double *b, double *x,
+              int prec, int M, double L, double kappa0, double sigma, const double *xi, double rtol, int restart,
+              int max_iter, int fixed_iters, int32_t *iters, double *rel_res, int32_t *status) {
+  const int64_t n = orc_num_nodes(N);
+  orc_prec P;
+  memset(&P, 0, sizeof(P));
+  P.kind = prec;
+  orc_level lv[ORC_MG_MAX_LEVELS];
+  double *dinv = NULL;
+  int rc = ORC_OK;
+  if (prec == 0) {
+    dinv = malloc(sizeof(double) * (size_t)n);
+    if (!dinv) return ORC_E_NOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+      double dg = 0.0;
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) dg = values[k];
+      dinv[i] = 1.0 / dg;
+    }
+    P.dinv = dinv;
+  } else {
+    rc = build_levels(N, M, L, kappa0, sigma, 1.0, xi, lv, &P.nl, NULL);
+    P.lv = lv;
+  }
+  if (rc == ORC_OK)
+    rc = gmres_core(n, rp, ci, values, b, x, &P, rtol, restart, max_iter, fixed_iters, iters, rel_res, status);
+  if (prec != 0) free_levels(lv, P.nl);
+  free(dinv);
+  return rc;
+}
+
+/* GMRES for every sample of an ensemble (matrix values [nnz][s], b and x
+ * [n][s], one sample per thread); fixed_iters [s] nullable. */
+int orc_ens_gmres(int N, const int32_t *rp, const int32_t *ci, int s, const double *values, const double *b,
+                  double *x, int prec, int M, double L, double kappa0, double sigma, const double *xi, double rtol,
+                  int restart, int max_iter, const int32_t *fixed_iters, int32_t *iters, double *rel_res,
+                  int32_t *status) {
+  const int64_t n = orc_num_nodes(N), nnz = rp[n];
+  int rc = ORC_OK;
+  #pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < s; ++e) {
+    double *ve = malloc(sizeof(double) * (size_t)nnz);
+    double *be = malloc(sizeof(double) * (size_t)n), *xe = malloc(sizeof(double) * (size_t)n);
+    if (!ve || !be || !xe) { rc = ORC_E_NOMEM; free(ve); free(be); free(xe); continue; }
+    for (int64_t k = 0; k < nnz; ++k) ve[k] = values[k * s + e];
+    for (int64_t i = 0; i < n; ++i) { be[i] = b[i * s + e]; xe[i] = x[i * s + e]; }
+    int r = orc_gmres(N, rp, ci, ve, be, xe, prec, M, L, kappa0, sigma, xi + (int64_t)e * M, rtol, restart,
+                      max_iter, fixed_iters ? fixed_iters[e] : -1, &iters[e], &rel_res[e], &status[e]);
+    if (r) rc = r;
+    for (int64_t i = 0; i < n; ++i) x[i * s + e] = xe[i];
+    free(ve); free(be); free(xe);
+  }
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Newton's method on F(u) = 0 (Sec. 4, Eq. fenl_lin_sys), one sample:       */
+/*   k = 0, 1, ...: F, A at u_k; stop when ||F(u_k)|| <= rtol ||load||        */
+/*   (||F(u_0)|| when the load is zero); otherwise A d = F by GMRES to the   */
+/*   relative tolerance lin_rtol from d = 0, and u_{k+1} = u_k - d.          */
+/* Statuses: converged; max steps; breakdown (the linear solve broke down);  */
+/* non-finite.  fnorm (nullable, max_newton + 1 entries) receives ||F(u_k)||. */
+/* ------------------------------------------------------------------------ */
+
+int orc_newton(int N, int M, double L, double kappa0, double sigma, double fconst, double alpha, const double *vel,
+               double beta, const double *xi, double *u, int prec, double rtol, int max_newton, double lin_rtol,
+               int restart, int lin_max_iter, int32_t *newton_iters, int32_t *lin_iters, double *rel_res,
+               int32_t *status, double *fnorm) {
+  const int64_t n = orc_num_nodes(N), nnz = orc_graph_nnz(N), ne = orc_num_elems(N);
+  int32_t *rp = malloc(sizeof(int32_t) * (size_t)(n + 1)), *ci = malloc(sizeof(int32_t) * (size_t)nnz);
+  double *ac = malloc(sizeof(double) * 8 * (size_t)ne), *vals = malloc(sizeof(double) * (size_t)nnz);
+  double *F = malloc(sizeof(double) * (size_t)n), *ld = malloc(sizeof(double) * (size_t)n);
+  double *d = malloc(sizeof(double) * (size_t)n), *dinv = malloc(sizeof(double) * (size_t)n);
+  orc_level lv[ORC_MG_MAX_LEVELS];
+  orc_prec P;
+  memset(&P, 0, sizeof(P));
+  int rc = ORC_OK;
+  if (!rp || !ci || !ac || !vals || !F || !ld || !d || !dinv) rc = ORC_E_NOMEM;
+  if (rc == ORC_OK) {
+    orc_graph(N, rp, ci);
+    orc_kl_coef_qp(N, M, L, kappa0, sigma, xi, ac);
+    P.kind = prec;
+    if (prec != 0) {
+      rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, lv, &P.nl, NULL);
+      P.lv = lv;
+    }
+  }
+  int st = ORC_MAXITER, k = 0, lin_total = 0;
+  double ref = 0.0, fn = 0.0;
+  for (; rc == ORC_OK; ++k) {
+    orc_nl_assemble_scalar(N, rp, ci, ac, fconst, alpha, vel, beta, u, F, vals, ld);
+    fn = sqrt(dot(n, F, F));
+    if (k == 0) {
+      ref = sqrt(dot(n, ld, ld));
+      if (ref == 0.0) ref = fn;
+    }
+    if (fnorm) fnorm[k] = fn;
+    if (!isfinite(fn)) { st = ORC_NONFINITE; break; }
+    if (fn <= rtol * ref) { st = ORC_CONVERGED; break; }
+    if (k == max_newton) { st = ORC_MAXITER; break; }
+    if (prec == 0) {
+      for (int64_t i = 0; i < n; ++i) {
+        double dg = 0.0;
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+          if (ci[q] == i) dg = vals[q];
+        dinv[i] = 1.0 / dg;
+      }
+      P.dinv = dinv;
+    }
+    for (int64_t i = 0; i < n; ++i) d[i] = 0.0;
+    int32_t it = 0, ls = 0;
+    double lr = 0.0;
+    rc = gmres_core(n, rp, ci, vals, F, d, &P, lin_rtol, restart, lin_max_iter, -1, &it, &lr, &ls);
+    lin_total += it;
+    if (ls == ORC_NONFINITE) { st = ORC_NONFINITE; break; }
+    if (ls == ORC_BREAKDOWN) { st = ORC_BREAKDOWN; break; }
+    for (int64_t i = 0; i < n; ++i) u[i] -= d[i];
+  }
+  *newton_iters = k;
+  *lin_iters = lin_total;
+  *rel_res = ref > 0.0 ? fn / ref : 0.0;
+  *status = st;
+  if (prec != 0 && P.lv) free_levels(lv, P.nl);
+  free(rp); free(ci); free(ac); free(vals); free(F); free(ld); free(d); free(dinv);
+  return rc;
+}
+
+/* Newton for every sample (u [n][s] in/out, one sample per thread); fnorm
+ * [s][max_newton + 1] nullable. */
+int orc_ens_newton(int N, int M, double L, double kappa0, double sigma, double fconst, double alpha,
+                   const double *vel, double beta, int s, const double *xi, double *u, int prec, double rtol,
+                   int max_newton, double lin_rtol, int restart, int lin_max_iter, int32_t *newton_iters,
+                   int32_t *lin_iters, double *rel_res, int32_t *status, double *fnorm) {
+  const int64_t n = orc_num_nodes(N);
+  int rc = ORC_OK;
+  #pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < s; ++e) {
+    double *ue = malloc(sizeof(double) * (size_t)n);
+    if (!ue) { rc = ORC_E_NOMEM; continue; }
+    for (int64_t i = 0; i < n; ++i) ue[i] = u[i * s + e];
+    int r = orc_newton(N, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi + (int64_t)e * M, ue, prec, rtol,
+                       max_newton, lin_rtol, restart, lin_max_iter, &newton_iters[e], &lin_iters[e], &rel_res[e],
+                       &status[e], fnorm ? fnorm + (int64_t)e * (max_newton + 1) : NULL);
+    if (r) rc = r;
+    for (int64_t i = 0; i < n; ++i) u[i * s + e] = ue[i];
+    free(ue);
   }
   return rc;
 }

@@ -86,6 +86,18 @@ def lib():
         L.orc_crs_to_dense.restype = None
         L.orc_crs_to_dense.argtypes = [i64, vp, vp, vp, vp]
         L.orc_cholesky_solve.argtypes = [i64, vp, vp, vp]
+        L.orc_nl_assemble_scalar.argtypes = [ctypes.c_int, vp, vp, vp, dbl, dbl, vp, dbl, vp, vp, vp, vp]
+        L.orc_ens_nl_assemble.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl,
+                                          ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_gmres.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, vp,
+                                dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.orc_ens_gmres.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int, dbl,
+                                    dbl, dbl, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
+        L.orc_newton.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl, vp, vp, ctypes.c_int,
+                                 dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_ens_newton.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl, ctypes.c_int, vp,
+                                     vp, ctypes.c_int, dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                     vp, vp]
         _lib = L
     return _lib
 
@@ -363,3 +375,71 @@ def cholesky_solve(A, b):
     x = np.zeros(n)
     rc = lib().orc_cholesky_solve(n, _p(A), _p(_f64(b)), _p(x))
     return x, rc == 0
+
+
+# ------------------------------------------------------- nonlinear problem
+
+PREC_JACOBI, PREC_MG = 0, 1
+
+
+def nl_assemble_scalar(N, rp, ci, acoef, fconst, alpha, vel, beta, u, want_jac=True):
+    """One sample's residual F(u), Jacobian values (or None) and load of the
+    nonlinear problem (Sec. 4, Eq. diffusion_sys and fenl_lin_sys)."""
+    n = num_nodes(N)
+    F = np.zeros(n)
+    ld = np.zeros(n)
+    vals = np.zeros(int(rp[-1])) if want_jac else None
+    _check(lib().orc_nl_assemble_scalar(N, _p(rp), _p(ci), _p(_f64(acoef)), fconst, alpha, _p(_f64(vel)), beta,
+                                        _p(_f64(u)), _p(F), None if vals is None else _p(vals), _p(ld)))
+    return F, vals, ld
+
+
+def ens_nl_assemble(N, rp, ci, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi, u, want_jac=True):
+    """Ensemble residual F [n][s], Jacobian [nnz][s] (or None), load [n][s]."""
+    xi = _f64(xi)
+    s = xi.shape[0]
+    n = num_nodes(N)
+    F = np.zeros((n, s))
+    ld = np.zeros((n, s))
+    vals = np.zeros((int(rp[-1]), s)) if want_jac else None
+    _check(lib().orc_ens_nl_assemble(N, _p(rp), _p(ci), M, L, kappa0, sigma, fconst, alpha, _p(_f64(vel)), beta, s,
+                                     _p(xi), _p(_f64(u)), _p(F), None if vals is None else _p(vals), _p(ld)))
+    return F, vals, ld
+
+
+def ens_gmres(N, rp, ci, values, b, x0=None, prec=PREC_JACOBI, M=0, L=1.0, kappa0=1.0, sigma=0.0, xi=None,
+              rtol=1e-10, restart=30, max_iter=10000, fixed_iters=None):
+    """Right-preconditioned restarted GMRES per sample.  Returns (x [n][s],
+    iters, rel_res, status)."""
+    values = _f64(values)
+    s = values.shape[1]
+    n = num_nodes(N)
+    x = np.zeros((n, s)) if x0 is None else _f64(x0).copy()
+    xi = np.zeros((s, max(M, 1))) if xi is None else _f64(xi)
+    it = np.zeros(s, np.int32)
+    rr = np.zeros(s)
+    st = np.zeros(s, np.int32)
+    fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, np.int32)
+    _check(lib().orc_ens_gmres(N, _p(rp), _p(ci), s, _p(values), _p(_f64(b)), _p(x), prec, M, L, kappa0, sigma,
+                               _p(xi), rtol, restart, max_iter, None if fi is None else _p(fi), _p(it), _p(rr),
+                               _p(st)))
+    return x, it, rr, st
+
+
+def ens_newton(N, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi, u0=None, prec=PREC_MG, rtol=1e-8,
+               max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000):
+    """Newton per sample.  Returns (u [n][s], newton_iters, lin_iters,
+    rel_res, status, fnorm [s][max_newton + 1])."""
+    xi = _f64(xi)
+    s = xi.shape[0]
+    n = num_nodes(N)
+    u = np.zeros((n, s)) if u0 is None else _f64(u0).copy()
+    ni = np.zeros(s, np.int32)
+    li = np.zeros(s, np.int32)
+    rr = np.zeros(s)
+    st = np.zeros(s, np.int32)
+    fn = np.zeros((s, max_newton + 1))
+    _check(lib().orc_ens_newton(N, M, L, kappa0, sigma, fconst, alpha, _p(_f64(vel)), beta, s, _p(xi), _p(u), prec,
+                                rtol, max_newton, lin_rtol, restart, lin_max_iter, _p(ni), _p(li), _p(rr), _p(st),
+                                _p(fn)))
+    return u, ni, li, rr, st, fn
