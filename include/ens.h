@@ -140,6 +140,40 @@ ens_status ens_assemble(int32_t N, const ens_graph* graph, const void* kl, const
                         int32_t s, const double* xi, double* values, float* values32, double* rhs,
                         hipStream_t stream);
 
+/* The nonlinear problem of Sec. 4 (Eq. diffusion_sys):
+ *   -div(kappa grad u) + alpha v.grad u + beta u^2 = f,  u = 0 on the boundary,
+ * kappa as in ens_problem, v = (vx, vy, vz) a constant velocity. */
+typedef struct {
+  int32_t M;
+  double L;
+  double kappa0;
+  double sigma;
+  double f;
+  double alpha;
+  double beta;
+  double vx, vy, vz;
+} ens_nl_problem;
+
+/* Residual F(u) and Jacobian A = dF/du (Eq. fenl_lin_sys) of the Q1
+ * Galerkin discretisation with the 2x2x2 Gauss rule, per sample, assembled
+ * like ens_assemble (row-owned, ascending element order, no atomics):
+ *   F_i = sum_e sum_q w_q [kappa grad N_a.grad u_h + alpha N_a v.grad u_h
+ *                          + beta N_a u_h^2 - f N_a]
+ *   A_ij = sum_e sum_q w_q [kappa grad N_a.grad N_b + alpha N_a v.grad N_b
+ *                           + 2 beta u_h N_a N_b]
+ * with u_h interpolating u at the element's 8 nodes (boundary nodes with
+ * their values).  Boundary rows: F_i = u_i and identity rows; boundary
+ * columns of interior rows are stored zeros.
+ *   u       (device) [n][s] in
+ *   values  (device) [nnz][s] FP64 Jacobian out; may be NULL (residual only)
+ *   F       (device) [n][s] out
+ *   load    (device) [n][s] out, the source part sum w_q f N_a of interior
+ *           rows (zero on the boundary, so F(0) = -load); may be NULL
+ * Other arguments as for ens_assemble.  Never synchronises. */
+ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const void* kl, const ens_nl_problem* problem,
+                           int32_t s, const double* xi, const double* u, double* values, double* F, double* load,
+                           hipStream_t stream);
+
 /* ----------------------------------------------------------------- SpMV */
 
 /* Ensemble CRS product y = A x in the commuted layout (Fig.
@@ -332,6 +366,66 @@ ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, co
                      double* x, const ens_cg_opts* opts, const ens_mg* mg, void* workspace, size_t ws_bytes,
                      ens_cg_stat* stats, hipStream_t stream);
 
+/* ------------------------------------------------- nonlinear: GMRES, Newton */
+
+/* Restarted GMRES(restart) with right preconditioning, per sample, for the
+ * nonsymmetric Newton systems of the nonlinear problem (Eq. fenl_lin_sys
+ * with alpha != 0): Arnoldi on A M with two classical Gram-Schmidt passes,
+ * Givens rotations on each sample's Hessenberg matrix, the estimate
+ * |g_{j+1}| <= rtol |b| tested after every step, at a cycle's end
+ * x += M V y and the true residual recomputed; converged when the true
+ * residual meets rtol |b|.  b = 0 gives x = 0.  Iterations count Arnoldi
+ * steps (products with A) over all cycles. */
+typedef struct {
+  double rtol;
+  int32_t restart;   /* 1..32 */
+  int32_t max_iter;
+} ens_gmres_opts;
+
+ens_status ens_gmres_workspace_bytes(const ens_graph* graph, int32_t s, int32_t restart, size_t* bytes);
+/* values [nnz][s] (the matrix), b and x [n][s] (x in: initial guess), all
+ * device FP64.  Preconditioner M: mg == NULL -> Jacobi (the diagonal of
+ * values); else the V-cycle of the set-up FP64 hierarchy `mg`, whose fine
+ * level is the matrix mg_values [nnz][s] it was set up with (for the
+ * Newton systems: the diffusion matrix of ens_assemble).  stats[e]: iters,
+ * outer_iters = restart cycles, status, rel_res = the final relative
+ * residual.  Synchronises. */
+ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,
+                     const ens_gmres_opts* opts, const ens_mg* mg, const double* mg_values, void* workspace,
+                     size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream);
+
+/* Newton's method per sample on F(u) = 0 (Sec. 4, Eq. fenl_lin_sys):
+ * at u_k assemble F and A = dF/du (ens_nl_assemble); stop the sample when
+ * |F(u_k)| <= rtol |load| (|F(u_0)| if the load is zero), at non-finite
+ * norms, or after max_newton steps; otherwise solve A d = F by ens_gmres to
+ * lin_rtol from d = 0 and set u_{k+1} = u_k - d.  A linear solve that
+ * breaks down or turns non-finite stops its sample with that status. */
+typedef struct {
+  double rtol;
+  int32_t max_newton;
+  double lin_rtol;
+  int32_t restart;       /* GMRES restart length, 1..32 */
+  int32_t lin_max_iter;  /* GMRES iterations per Newton step */
+} ens_newton_opts;
+
+typedef struct {
+  int32_t newton_iters;  /* Newton updates taken */
+  int32_t lin_iters;     /* GMRES iterations over all steps */
+  int32_t status;        /* ens_sample_status */
+  int32_t reserved;
+  double rel_res;        /* |F(u)| / |load| at exit */
+} ens_newton_stat;
+
+ens_status ens_newton_workspace_bytes(const ens_graph* graph, int32_t s, int32_t restart, size_t* bytes);
+/* u [n][s] (device, in: initial guess, out: solution); xi [s][M] (device);
+ * kl from ens_kl_build(N, problem->M, problem->L); mg / mg_values as for
+ * ens_gmres (NULL: Jacobi).  The workspace holds the Jacobian, F, the load,
+ * the step and the GMRES workspace.  Synchronises. */
+ens_status ens_newton(int32_t N, const ens_graph* graph, const void* kl, const ens_nl_problem* problem, int32_t s,
+                      const double* xi, double* u, const ens_newton_opts* opts, const ens_mg* mg,
+                      const double* mg_values, void* workspace, size_t ws_bytes, ens_newton_stat* stats,
+                      hipStream_t stream);
+
 /* The one-sample baseline with up to `streams` (1..32) solves in flight at
  * once, each on its own library stream (default priority) with its own
  * workspace slice, so that independent solves overlap on the device as they
@@ -442,7 +536,10 @@ enum {
   ENS_K_ASSEMBLE = 2,
   ENS_K_SCALAR_SPMV = 3,
   ENS_K_MG_ROW = 4,     /* fine-level row passes of the multigrid cycle   */
-  ENS_K_COUNT = 5
+  ENS_K_NL_ASSEMBLE = 5,/* nonlinear residual and Jacobian                  */
+  ENS_K_GM_SPMV = 6,    /* the product w = A z of a GMRES step (FP64)       */
+  ENS_K_GM_ORTH = 7,    /* GMRES Gram-Schmidt passes over the basis          */
+  ENS_K_COUNT = 8
 };
 ens_status ens_prof_enable(int32_t on);
 ens_status ens_prof_reset(void);

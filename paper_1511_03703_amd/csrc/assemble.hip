@@ -24,6 +24,8 @@ namespace ens {
 constexpr int kAsmMaxM = 16;
 
 __constant__ double c_G[8][8][8];  // [q][a][b], symmetric in (a,b)
+__constant__ double c_N[8][8];     // [q][a]: N_a at Gauss point q
+__constant__ double c_dN[8][8][3]; // [q][a][d]: reference derivative of N_a along axis d
 
 static bool g_G_ready[64];
 
@@ -58,7 +60,52 @@ static hipError_t upload_G() {
     for (int a = 0; a < 8; ++a)
       for (int b = a + 1; b < 8; ++b) G[q][b][a] = G[q][a][b];
   }
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_G), G, sizeof(G));
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_G), G, sizeof(G));
+  if (e != hipSuccess) return e;
+  // shape functions and their reference gradients at the Gauss points
+  double Nq[8][8], dN[8][8][3];
+  for (int q = 0; q < 8; ++q) {
+    double s3[3] = {g[q & 1], g[(q >> 1) & 1], g[(q >> 2) & 1]};
+    for (int a = 0; a < 8; ++a) {
+      int ax[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
+      double l[3], d[3];
+      for (int t = 0; t < 3; ++t) {
+        l[t] = ax[t] ? s3[t] : 1.0 - s3[t];
+        d[t] = ax[t] ? 1.0 : -1.0;
+      }
+      Nq[q][a] = l[0] * l[1] * l[2];
+      dN[q][a][0] = d[0] * l[1] * l[2];
+      dN[q][a][1] = l[0] * d[1] * l[2];
+      dN[q][a][2] = l[0] * l[1] * d[2];
+    }
+  }
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_N), Nq, sizeof(Nq));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_dN), dN, sizeof(dN));
+}
+
+// Sum of the KL modes of sample e at the 8 Gauss points of element
+// (ex, ey, ez): kq[q] = kappa0 + sum_m c_m X(qx) Y(qy) Z(qz).
+__device__ inline void kl_points(const double* __restrict__ tab, const int32_t* __restrict__ kl_triple,
+                                 const double* __restrict__ cm, int M, int64_t two_n, int ex, int ey, int ez,
+                                 double kappa0, double (&kq)[8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) kq[q] = 0.0;
+#pragma unroll 2
+  for (int m = 0; m < M; ++m) {
+    const double c = cm[m];
+    const double* px = tab + kl_triple[3 * m + 0] * two_n + 2 * ex;
+    const double* py = tab + kl_triple[3 * m + 1] * two_n + 2 * ey;
+    const double* pz = tab + kl_triple[3 * m + 2] * two_n + 2 * ez;
+    const double fx[2] = {px[0], px[1]}, fy[2] = {py[0], py[1]}, fz[2] = {pz[0], pz[1]};
+    double yz[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) yz[t] = c * (fy[t & 1] * fz[t >> 1]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) kq[q] = kappa0 + kq[q];
 }
 
 // LDS: the 1D eigenfunction table (M x 2N doubles) is staged in LDS when it
@@ -167,6 +214,138 @@ __global__ __launch_bounds__(256) void k_assemble(int N, const double* __restric
   rhs[row * S + e] = bnd_row ? 0.0 : (double)nelem * (fsrc * h * h * h * 0.125);
 }
 
+// Residual and Jacobian of the nonlinear problem (Sec. 4, Eq.
+// diffusion_sys, Eq. fenl_lin_sys, Alg. "assembly" with alpha, beta != 0),
+// row-owned like k_assemble: lane e of a row's group gathers the element
+// solution u_e of its sample for each element around the node (ascending
+// element id), evaluates u_h and its reference gradient at the 8 Gauss
+// points and adds
+//   F_a  += sum_q (h/8) kappa_q dN_a.g_q + (h^2/8) alpha N_a (v.g_q)
+//                 + (h^3/8) (beta N_a u_q^2 - f N_a)
+//   J_ab += sum_q (h/8) kappa_q G_q[a][b] + (h^2/8) alpha N_a (v.dN_b)
+//                 + (h^3/8) 2 beta u_q N_a N_b
+// with g_q = sum_b dN_b(q) u_b the reference gradient (physical = g/h).
+// Boundary rows: F = u and identity rows; boundary columns of interior
+// rows stored as zeros; load (optional) = the source part of F.
+template <int S, int LDS>
+__global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __restrict__ kl_sqrt_lam,
+                                                      const int32_t* __restrict__ kl_triple,
+                                                      const double* __restrict__ kl_phi, int M, double kappa0,
+                                                      double sigma, double fsrc, double alpha, double beta, double vx,
+                                                      double vy, double vz, const double* __restrict__ xi,
+                                                      const int32_t* __restrict__ row_ptr,
+                                                      const double* __restrict__ u, double* __restrict__ values,
+                                                      double* __restrict__ F, double* __restrict__ load) {
+  constexpr int RPB = 256 / S;
+  __shared__ double s_cm[S * kAsmMaxM];
+  __shared__ double s_dv[8][8];  // v . dN_b at point q
+  extern __shared__ double s_phi[];
+  for (int t = threadIdx.x; t < S * M; t += blockDim.x) {
+    const int ee = t / M, m = t % M;
+    s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)ee * M + m];
+  }
+  if (threadIdx.x < 64) {
+    const int q = threadIdx.x >> 3, b = threadIdx.x & 7;
+    s_dv[q][b] = vx * c_dN[q][b][0] + vy * c_dN[q][b][1] + vz * c_dN[q][b][2];
+  }
+  if (LDS)
+    for (int t = threadIdx.x; t < M * 2 * N; t += blockDim.x) s_phi[t] = kl_phi[t];
+  __syncthreads();
+  const double* tab = LDS ? s_phi : kl_phi;
+
+  const int n1 = N + 1;
+  const int64_t n = (int64_t)n1 * n1 * n1;
+  const int e = threadIdx.x % S;
+  const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / S;
+  if (row >= n) return;
+  const int ii = (int)(row % n1), jj = (int)((row / n1) % n1), kk = (int)(row / ((int64_t)n1 * n1));
+  const double h = 1.0 / (double)N;
+  const double wd = h * 0.125;             // diffusion: w_q / h^2
+  const double wa = h * h * 0.125 * alpha; // advection: alpha w_q / h
+  const double wr = h * h * h * 0.125;     // reaction and source: w_q
+  const int64_t two_n = 2 * (int64_t)N;
+  const bool jac = values != nullptr;
+
+  double acc[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = 0.0;
+  double fa = 0.0, la = 0.0;
+
+#pragma unroll
+  for (int ez_off = -1; ez_off <= 0; ++ez_off)
+#pragma unroll
+    for (int ey_off = -1; ey_off <= 0; ++ey_off)
+#pragma unroll
+      for (int ex_off = -1; ex_off <= 0; ++ex_off) {
+        const int ex = ii + ex_off, ey = jj + ey_off, ez = kk + ez_off;
+        if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
+        const int ai = (-ex_off) + 2 * (-ey_off) + 4 * (-ez_off);
+        double kq[8];
+        kl_points(tab, kl_triple, s_cm + e * M, M, two_n, ex, ey, ez, kappa0, kq);
+        double ue[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int64_t node = (int64_t)(ex + (b & 1)) + n1 * ((int64_t)(ey + ((b >> 1) & 1)) +
+                                                              (int64_t)n1 * (ez + ((b >> 2) & 1)));
+          ue[b] = u[node * S + e];
+        }
+        double rq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          double uq = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            uq += c_N[q][b] * ue[b];
+            g0 += c_dN[q][b][0] * ue[b];
+            g1 += c_dN[q][b][1] * ue[b];
+            g2 += c_dN[q][b][2] * ue[b];
+          }
+          const double na = c_N[q][ai];
+          const double diff = c_dN[q][ai][0] * g0 + c_dN[q][ai][1] * g1 + c_dN[q][ai][2] * g2;
+          fa += wd * kq[q] * diff + wa * na * (vx * g0 + vy * g1 + vz * g2) +
+                wr * (beta * na * uq * uq - fsrc * na);
+          la += wr * fsrc * na;
+          rq[q] = wr * 2.0 * beta * uq * na;
+        }
+        if (jac) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const int dx = ex_off + (b & 1), dy = ey_off + ((b >> 1) & 1), dz = ez_off + ((b >> 2) & 1);
+            const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+            double jab = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              jab += wd * kq[q] * c_G[q][ai][b] + wa * c_N[q][ai] * s_dv[q][b] + rq[q] * c_N[q][b];
+            acc[slot27] += jab;
+          }
+        }
+      }
+
+  const bool bnd_row = (ii == 0 || ii == N || jj == 0 || jj == N || kk == 0 || kk == N);
+  if (jac) {
+    const int64_t start = row_ptr[row];
+    int pos = 0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = ii + dx, y = jj + dy, z = kk + dz;
+          if (x < 0 || y < 0 || z < 0 || x > N || y > N || z > N) continue;
+          const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+          double v = acc[slot27];
+          const bool bnd_col = (x == 0 || x == N || y == 0 || y == N || z == 0 || z == N);
+          if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
+          else if (bnd_col) v = 0.0;
+          values[(start + pos) * S + e] = v;
+          ++pos;
+        }
+  }
+  F[row * S + e] = bnd_row ? u[row * S + e] : fa;
+  if (load) load[row * S + e] = bnd_row ? 0.0 : la;
+}
+
 }  // namespace ens
 
 using namespace ens;
@@ -224,5 +403,63 @@ extern "C" ens_status ens_assemble(int32_t N, const ens_graph* graph, const void
   ENS_LAUNCH_CHECK();
   double bytes = (double)nnz * s * (8.0 + (values32 ? 4.0 : 0.0)) + (double)n * s * 8.0 + 4.0 * (n + 1);
   prof_end(ENS_K_ASSEMBLE, stream, bytes);
+  return ENS_OK;
+}
+
+extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const void* kl,
+                                      const ens_nl_problem* prob, int32_t s, const double* xi, const double* u,
+                                      double* values, double* F, double* load, hipStream_t stream) {
+  int64_t n = 0, nnz = 0;
+  ens_status st = ens_mesh_sizes(N, &n, &nnz, nullptr);
+  if (st != ENS_OK) return st;
+  ENS_ARG_CHECK(graph && prob, "null graph or problem");
+  ENS_ARG_CHECK(graph->n == n && graph->nnz == nnz && graph->row_ptr && graph->col_idx,
+                "graph does not match the mesh");
+  ENS_ARG_CHECK(u && F, "null u or F");
+  ENS_ARG_CHECK(prob->M >= 0 && prob->M <= kAsmMaxM, "M out of range");
+  ENS_ARG_CHECK(prob->M == 0 || (kl && xi), "null KL table or inputs");
+  if (!supported_s(s)) {
+    set_error("ensemble size %d not compiled in", s);
+    return ENS_E_UNSUPPORTED;
+  }
+  int dev = 0;
+  ENS_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 64 && !g_G_ready[dev]) {
+    ENS_HIP_TRY(upload_G());
+    g_G_ready[dev] = true;
+  }
+  const int M = prob->M;
+  const char* base = (const char*)kl;
+  size_t phi_off = ((size_t)M * 5 * sizeof(double) + (size_t)M * 4 * sizeof(int32_t) + 15) & ~(size_t)15;
+  const double* sq = (const double*)base;
+  const int32_t* tr = (const int32_t*)(base + (size_t)M * 5 * sizeof(double) + (size_t)M * sizeof(int32_t));
+  const double* phi = (const double*)(base + phi_off);
+  const int rpb = 256 / s;
+  const int64_t blocks = (n + rpb - 1) / rpb;
+  const size_t table = (size_t)M * 2 * N * sizeof(double);
+  const size_t lds_bytes = table > 0 && table <= 48 * 1024 ? table : 0;
+  prof_begin(ENS_K_NL_ASSEMBLE, stream);
+  switch (s) {
+#define ENS_NL_CASE(SS)                                                                                        \
+  case SS:                                                                                                     \
+    if (lds_bytes)                                                                                             \
+      hipLaunchKernelGGL((k_nl_assemble<SS, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, stream, N, sq, tr, \
+                         phi, M, prob->kappa0, prob->sigma, prob->f, prob->alpha, prob->beta, prob->vx, prob->vy,  \
+                         prob->vz, xi, graph->row_ptr, u, values, F, load);                                      \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_nl_assemble<SS, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, N, sq, tr, phi, M, \
+                         prob->kappa0, prob->sigma, prob->f, prob->alpha, prob->beta, prob->vx, prob->vy, prob->vz, \
+                         xi, graph->row_ptr, u, values, F, load);                                                \
+    break;
+    ENS_NL_CASE(4)
+    ENS_NL_CASE(8)
+    ENS_NL_CASE(16)
+    ENS_NL_CASE(32)
+#undef ENS_NL_CASE
+  }
+  ENS_LAUNCH_CHECK();
+  const double bytes = (values ? (double)nnz * s * 8.0 : 0.0) + (double)n * s * 8.0 * (load ? 3.0 : 2.0) +
+                       4.0 * (n + 1);
+  prof_end(ENS_K_NL_ASSEMBLE, stream, bytes);
   return ENS_OK;
 }

@@ -20,7 +20,7 @@ ENS_OK, ENS_W_NOT_CONVERGED = 0, 1
 ENS_E_ARG, ENS_E_UNSUPPORTED, ENS_E_HIP, ENS_E_NOMEM, ENS_E_RANGE = -1, -2, -3, -4, -5
 SAMPLE_CONVERGED, SAMPLE_MAXITER, SAMPLE_BREAKDOWN, SAMPLE_NONFINITE, SAMPLE_STAGNATED = 0, 1, 2, 3, 4
 F64, F32 = 0, 1
-K_SPMV_F64, K_SPMV_F32, K_ASSEMBLE, K_SCALAR_SPMV, K_MG_ROW = 0, 1, 2, 3, 4
+K_SPMV_F64, K_SPMV_F32, K_ASSEMBLE, K_SCALAR_SPMV, K_MG_ROW, K_NL_ASSEMBLE, K_GM_SPMV, K_GM_ORTH = range(8)
 
 
 class EnsError(RuntimeError):
@@ -60,6 +60,26 @@ class ens_group(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("stats", ctypes.POINTER(ens_cg_stat))]
 
 
+class ens_nl_problem(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("L", ctypes.c_double), ("kappa0", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("f", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("vx", ctypes.c_double), ("vy", ctypes.c_double), ("vz", ctypes.c_double)]
+
+
+class ens_gmres_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+
+
+class ens_newton_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_newton", ctypes.c_int32), ("lin_rtol", ctypes.c_double),
+                ("restart", ctypes.c_int32), ("lin_max_iter", ctypes.c_int32)]
+
+
+class ens_newton_stat(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("lin_iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rel_res", ctypes.c_double)]
+
+
 class ens_batch_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
@@ -83,6 +103,13 @@ _SIGS = [
     ("ens_kl_bytes", _I32, [_I32, _I32, ctypes.POINTER(_SZ)]),
     ("ens_kl_build", _I32, [_I32, _I32, _D, _P, _P]),
     ("ens_assemble", _I32, [_I32, _GP, _P, ctypes.POINTER(ens_problem), _I32, _P, _P, _P, _P, _P]),
+    ("ens_nl_assemble", _I32, [_I32, _GP, _P, ctypes.POINTER(ens_nl_problem), _I32, _P, _P, _P, _P, _P, _P]),
+    ("ens_gmres_workspace_bytes", _I32, [_GP, _I32, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_gmres", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_gmres_opts), ctypes.POINTER(ens_mg), _P, _P, _SZ,
+                         ctypes.POINTER(ens_cg_stat), _P]),
+    ("ens_newton_workspace_bytes", _I32, [_GP, _I32, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_newton", _I32, [_I32, _GP, _P, ctypes.POINTER(ens_nl_problem), _I32, _P, _P, ctypes.POINTER(ens_newton_opts),
+                          ctypes.POINTER(ens_mg), _P, _P, _SZ, ctypes.POINTER(ens_newton_stat), _P]),
     ("ens_spmv", _I32, [_GP, _I32, _I32, _P, _P, _P, _P]),
     ("ens_scalar_spmv", _I32, [_GP, _I32, _P, _P, _P, _I32, _P]),
     ("ens_cg_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(_SZ)]),
@@ -242,6 +269,103 @@ def assemble(g: Graph, kl: torch.Tensor, xi: torch.Tensor, M: int, sigma: float,
     _check(lib().ens_assemble(g.N, ctypes.byref(gc), _ptr(kl), ctypes.byref(prob), s, _ptr(xi), _ptr(values),
                               _ptr(values32), _ptr(rhs), _stream(stream)), "ens_assemble")
     return values, values32, rhs
+
+
+# ------------------------------------------------------ nonlinear problem
+
+DEFAULT_VEL = (3 ** -0.5, 3 ** -0.5, 3 ** -0.5)
+
+
+def nl_problem(M: int, sigma: float, alpha: float, beta: float, vel=DEFAULT_VEL, L: float = 1.0,
+               kappa0: float = 1.0, f: float = 1.0) -> ens_nl_problem:
+    return ens_nl_problem(M, L, kappa0, sigma, f, alpha, beta, float(vel[0]), float(vel[1]), float(vel[2]))
+
+
+def nl_assemble(g: Graph, kl: torch.Tensor, xi: torch.Tensor, prob: ens_nl_problem, u: torch.Tensor,
+                want_jac=True, want_load=False, values=None, F=None, load=None, stream=None):
+    """Residual F [n][s], Jacobian values [nnz][s] (or None) and load [n][s]
+    (or None) of the nonlinear problem at u [n][s]."""
+    s = xi.shape[0]
+    dev = u.device
+    if want_jac and values is None:
+        values = torch.empty((g.nnz, s), dtype=torch.float64, device=dev)
+    if F is None:
+        F = torch.empty((g.n, s), dtype=torch.float64, device=dev)
+    if want_load and load is None:
+        load = torch.empty((g.n, s), dtype=torch.float64, device=dev)
+    gc = g.c()
+    _check(lib().ens_nl_assemble(g.N, ctypes.byref(gc), _ptr(kl), ctypes.byref(prob), s, _ptr(xi), _ptr(u),
+                                 _ptr(values if want_jac else None), _ptr(F), _ptr(load if want_load else None),
+                                 _stream(stream)), "ens_nl_assemble")
+    return F, (values if want_jac else None), (load if want_load else None)
+
+
+def gmres_opts(rtol=1e-10, restart=30, max_iter=1000) -> ens_gmres_opts:
+    return ens_gmres_opts(rtol, restart, max_iter)
+
+
+def gmres_workspace_bytes(g: Graph, s: int, restart: int) -> int:
+    nb = _SZ()
+    _check(lib().ens_gmres_workspace_bytes(ctypes.byref(g.c()), s, restart, ctypes.byref(nb)),
+           "ens_gmres_workspace_bytes")
+    return nb.value
+
+
+def gmres(g: Graph, values, b, x=None, opts: ens_gmres_opts | None = None, mg=None, mg_values=None,
+          workspace=None, stream=None):
+    """Right-preconditioned restarted GMRES per sample (mg: a set-up FP64
+    Multigrid whose fine matrix is mg_values; None: Jacobi).  Returns (x,
+    stats, status)."""
+    s = values.shape[1]
+    if opts is None:
+        opts = gmres_opts()
+    if x is None:
+        x = torch.zeros_like(b)
+    nbytes = gmres_workspace_bytes(g, s, opts.restart)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    stats = (ens_cg_stat * s)()
+    gc = g.c()
+    st = _check(lib().ens_gmres(ctypes.byref(gc), s, _ptr(values), _ptr(b), _ptr(x), ctypes.byref(opts),
+                                ctypes.byref(mg.desc) if mg is not None else None, _ptr(mg_values), _ptr(workspace),
+                                workspace.numel(), stats, _stream(stream)),
+                "ens_gmres", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
+    return x, _stats_list(stats, s), st
+
+
+def newton_opts(rtol=1e-8, max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000) -> ens_newton_opts:
+    return ens_newton_opts(rtol, max_newton, lin_rtol, restart, lin_max_iter)
+
+
+def newton_workspace_bytes(g: Graph, s: int, restart: int) -> int:
+    nb = _SZ()
+    _check(lib().ens_newton_workspace_bytes(ctypes.byref(g.c()), s, restart, ctypes.byref(nb)),
+           "ens_newton_workspace_bytes")
+    return nb.value
+
+
+def newton(g: Graph, kl: torch.Tensor, xi: torch.Tensor, prob: ens_nl_problem, u=None,
+           opts: ens_newton_opts | None = None, mg=None, mg_values=None, workspace=None, stream=None):
+    """Newton's method per sample with GMRES inner solves.  Returns (u,
+    stats, status); stats[e] = dict(newton_iters, lin_iters, status,
+    rel_res)."""
+    s = xi.shape[0]
+    if opts is None:
+        opts = newton_opts()
+    if u is None:
+        u = torch.zeros((g.n, s), dtype=torch.float64, device=xi.device)
+    nbytes = newton_workspace_bytes(g, s, opts.restart)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=xi.device)
+    stats = (ens_newton_stat * s)()
+    gc = g.c()
+    st = _check(lib().ens_newton(g.N, ctypes.byref(gc), _ptr(kl), ctypes.byref(prob), s, _ptr(xi), _ptr(u),
+                                 ctypes.byref(opts), ctypes.byref(mg.desc) if mg is not None else None,
+                                 _ptr(mg_values), _ptr(workspace), workspace.numel(), stats, _stream(stream)),
+                "ens_newton", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
+    out = [dict(newton_iters=stats[e].newton_iters, lin_iters=stats[e].lin_iters, status=stats[e].status,
+                rel_res=stats[e].rel_res) for e in range(s)]
+    return u, out, st
 
 
 # ------------------------------------------------------------------ SpMV
