@@ -95,7 +95,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="default 5 (solve workloads), 1 (batch, learned)")
     ap.add_argument("--warmup", type=int, default=None, help="default 1 (solve workloads), 0 (batch, learned)")
-    ap.add_argument("--workload", default="headline", choices=["headline", "mid", "small", "batch", "learned", "mg"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "mid", "small", "batch", "learned", "mg", "newton"])
     ap.add_argument("--pool-gib", type=float, default=192.0, help="batch: resident pool size")
     ap.add_argument("--batch-s", type=int, default=0, help="batch: fix s (skip the autotuner)")
     ap.add_argument("--batch-tile", type=int, default=4, help="batch: tile when --batch-s is given")
@@ -133,6 +134,8 @@ def main():
         return run_learned(args)
     if args.workload == "mg":
         return run_mg(args)
+    if args.workload == "newton":
+        return run_newton(args)
     return run_solve(args)
 
 
@@ -817,6 +820,106 @@ def run_mg(args):
             "sample": (f"{threads} samples of the same workload, one per OpenMP thread (of {orc.max_threads()} "
                        f"available): hierarchy set-up and multigrid PCG to {w.rtol:g} in full, "
                        f"iterations {[int(v) for v in it]}"),
+            "seconds_measured": round(tc, 2)}
+    print(json.dumps(out), flush=True)
+
+
+def run_newton(args):
+    """The nonlinear problem (advection alpha v.grad u and reaction beta u^2
+    on) for the headline samples: one step = the diffusion matrix for the
+    preconditioner, the multigrid set-up, and Newton's method with
+    multigrid-preconditioned GMRES from u = 0 to |F(u)| <= 1e-8 |load|."""
+    import numpy as np
+    import torch
+
+    from paper_1511_03703_amd import ens
+    import workloads as W
+
+    w = W.NEWTON
+    dev = "cuda"
+    torch.cuda.set_device(0)
+    g = ens.graph_build(w.N)
+    kl = ens.kl_build(w.N, w.M, w.L)
+    xi = torch.as_tensor(w.xi(), device=dev)
+    prob = ens.nl_problem(w.M, w.sigma, W.NEWTON_ALPHA, W.NEWTON_BETA, W.NEWTON_VEL, L=w.L, kappa0=w.kappa0, f=w.f)
+    K = torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
+    rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
+    u = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)
+    mg = ens.Multigrid(w.N, w.M, w.s, L=w.L, device=dev)
+    opts = ens.newton_opts(rtol=w.rtol, lin_rtol=W.NEWTON_LIN_RTOL, restart=W.NEWTON_RESTART)
+    ws = torch.empty(ens.newton_workspace_bytes(g, w.s, W.NEWTON_RESTART), dtype=torch.uint8, device=dev)
+    log(f"newton workload: N={w.N} s={w.s} workspace {ws.numel() / 2**30:.1f} GiB, "
+        f"hierarchy {mg.buffer.numel() / 2**30:.2f} GiB")
+
+    def step():
+        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=K, rhs=rhs)
+        mg.setup(g, K, xi, w.sigma, kappa0=w.kappa0, f=w.f)
+        u.zero_()
+        return ens.newton(g, kl, xi, prob, u=u, opts=opts, mg=mg, mg_values=K, workspace=ws)
+
+    for i in range(args.warmup):
+        _, stats, st = step()
+        log(f"warmup {i}: status {st}, newton {[t['newton_iters'] for t in stats][:8]}..., "
+            f"gmres {[t['lin_iters'] for t in stats][:8]}...")
+    torch.cuda.synchronize()
+    ens.prof_reset()
+    ens.prof_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, stats, st = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ens.prof_enable(False)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    kernels = {"k_mg_row<double,32,*> (fine-level V-cycle passes)": ens.K_MG_ROW,
+               "k_nl_assemble<32,1> (residual and Jacobian)": ens.K_NL_ASSEMBLE,
+               "k_gm_spmv<32> (GMRES product w = A z)": ens.K_GM_SPMV,
+               "k_gm_dots/k_gm_axpy<32> (Gram-Schmidt passes)": ens.K_GM_ORTH,
+               "k_assemble<32,1> (diffusion matrix for the preconditioner)": ens.K_ASSEMBLE}
+    prof = {k: ens.prof_query(v) for k, v in kernels.items()}
+    per_kernel = {k: {"ms_per_step": round(p["total_ms"] / args.steps, 3), "launches": p["launches"],
+                      "GBs": round(p["bytes"] / (p["total_ms"] * 1e-3) / 1e9, 1) if p["launches"] else None}
+                  for k, p in prof.items()}
+    dom = max((k for k in prof if k.startswith(("k_mg_row", "k_gm_spmv", "k_gm_dots"))),
+              key=lambda k: prof[k]["total_ms"])
+    pd = prof[dom]
+    achieved = pd["bytes"] / (pd["total_ms"] * 1e-3) / 1e9 if pd["launches"] else 0.0
+    ok = all(t["status"] == 0 and t["rel_res"] <= w.rtol * (1 + 1e-6) for t in stats)
+    out = {
+        "metric": "solved samples/s at 128^3, s=32: nonlinear (alpha=10, beta=100) Newton to 1e-8 residual",
+        "value": round(args.steps * w.s / elapsed, 3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "mesh": f"{w.N}^3 Q1 hexahedra", "n": w.n, "nnz": w.nnz, "s": w.s, "M": w.M,
+                   "sigma": w.sigma, "alpha": W.NEWTON_ALPHA, "beta": W.NEWTON_BETA,
+                   "velocity": [round(v, 6) for v in W.NEWTON_VEL], "f": w.f, "rtol": w.rtol, "seed": w.seed,
+                   "linear_solver": f"GMRES({W.NEWTON_RESTART}) to {W.NEWTON_LIN_RTOL:g}, right-preconditioned by "
+                                    "the multigrid V-cycle of the diffusion operator"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "launches": pd["launches"], "avg_launch_ms": round(pd["total_ms"] / max(pd["launches"], 1), 5),
+                     "bytes_per_launch": round(pd["bytes"] / max(pd["launches"], 1))},
+        "all_converged": bool(ok),
+        "newton_iters": [t["newton_iters"] for t in stats],
+        "gmres_iters": [t["lin_iters"] for t in stats],
+        "kernels": per_kernel,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        threads = min(args.cpu_threads, w.s)
+        log("CPU oracle baseline (Newton) ...")
+        t0 = time.perf_counter()
+        _, ni, li, rr, st_o, _ = orc.ens_newton(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, W.NEWTON_ALPHA,
+                                                np.array(W.NEWTON_VEL), W.NEWTON_BETA, w.xi()[:threads],
+                                                prec=orc.PREC_MG, rtol=w.rtol, lin_rtol=W.NEWTON_LIN_RTOL,
+                                                restart=W.NEWTON_RESTART)
+        tc = time.perf_counter() - t0
+        cores = min(threads, orc.max_threads())
+        out["cpu_baseline"] = {
+            "value": threads / tc, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{threads} samples of the same workload, one per OpenMP thread: the oracle's Newton with "
+                       f"multigrid-preconditioned GMRES in full, Newton steps {[int(v) for v in ni]}, GMRES "
+                       f"iterations {[int(v) for v in li]}"),
             "seconds_measured": round(tc, 2)}
     print(json.dumps(out), flush=True)
 

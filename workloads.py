@@ -63,6 +63,17 @@ HEADLINE = Workload("q1_128cube_s32_mixed", N=128, s=32, M=10, sigma=0.3, rtol=1
 LEARNED = Workload("q1_64cube_s32_learned", N=64, s=32, M=10, sigma=0.2, rtol=1e-8, mixed=False, seed=1005,
                    notes="POD r=32 from 2048 solves; MLP 10-256-256-32 initial guess")
 
+# The nonlinear problem of Sec. 4 with the advection and reaction terms on:
+# the headline samples (128^3, s = 32, M = 10, sigma = 0.3, seed 1002),
+# alpha v.grad u with v = (1,1,1)/sqrt(3) and beta u^2, Newton to 1e-8.
+NEWTON = Workload("q1_128cube_s32_newton", N=128, s=32, M=10, sigma=0.3, rtol=1e-8, mixed=False, seed=1002,
+                  notes="128^3, s=32, alpha=10, beta=100: Newton with multigrid-preconditioned GMRES(30)")
+NEWTON_ALPHA = 10.0
+NEWTON_BETA = 100.0
+NEWTON_VEL = (3 ** -0.5, 3 ** -0.5, 3 ** -0.5)
+NEWTON_LIN_RTOL = 1e-4
+NEWTON_RESTART = 30
+
 BATCH_MESHES = (32, 48, 64, 96)
 BATCH_GROUPS = 256
 BATCH_MESH_SEED = 1003
