@@ -115,6 +115,7 @@ def main():
                     help="refinement inner tolerance (default: 1e-4 with multigrid, 1e-5 with Jacobi, the measured "
                          "optima at 128^3, s=32)")
     ap.add_argument("--check-every", type=int, default=16)
+    ap.add_argument("--lin-rtol", type=float, default=None, help="newton: GMRES tolerance per Newton step")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (hardware-counter calibration)")
     args = ap.parse_args()
@@ -842,20 +843,23 @@ def run_newton(args):
     kl = ens.kl_build(w.N, w.M, w.L)
     xi = torch.as_tensor(w.xi(), device=dev)
     prob = ens.nl_problem(w.M, w.sigma, W.NEWTON_ALPHA, W.NEWTON_BETA, W.NEWTON_VEL, L=w.L, kappa0=w.kappa0, f=w.f)
+    mg32 = not args.mg_fp64
     K = torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
+    K32 = torch.empty((w.nnz, w.s), dtype=torch.float32, device=dev) if mg32 else None
     rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
     u = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)
-    mg = ens.Multigrid(w.N, w.M, w.s, L=w.L, device=dev)
-    opts = ens.newton_opts(rtol=w.rtol, lin_rtol=W.NEWTON_LIN_RTOL, restart=W.NEWTON_RESTART)
+    mg = ens.Multigrid(w.N, w.M, w.s, fp32=mg32, L=w.L, device=dev)
+    lin_rtol = args.lin_rtol if args.lin_rtol is not None else W.NEWTON_LIN_RTOL
+    opts = ens.newton_opts(rtol=w.rtol, lin_rtol=lin_rtol, restart=W.NEWTON_RESTART)
     ws = torch.empty(ens.newton_workspace_bytes(g, w.s, W.NEWTON_RESTART), dtype=torch.uint8, device=dev)
     log(f"newton workload: N={w.N} s={w.s} workspace {ws.numel() / 2**30:.1f} GiB, "
         f"hierarchy {mg.buffer.numel() / 2**30:.2f} GiB")
 
     def step():
-        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=K, rhs=rhs)
-        mg.setup(g, K, xi, w.sigma, kappa0=w.kappa0, f=w.f)
+        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=K, values32=K32, rhs=rhs)
+        mg.setup(g, K, xi, w.sigma, values32=K32, kappa0=w.kappa0, f=w.f)
         u.zero_()
-        return ens.newton(g, kl, xi, prob, u=u, opts=opts, mg=mg, mg_values=K, workspace=ws)
+        return ens.newton(g, kl, xi, prob, u=u, opts=opts, mg=mg, mg_values=K32 if mg32 else K, workspace=ws)
 
     for i in range(args.warmup):
         _, stats, st = step()
@@ -871,7 +875,7 @@ def run_newton(args):
     elapsed = time.perf_counter() - t0
     ens.prof_enable(False)
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
-    kernels = {"k_mg_row<double,32,*> (fine-level V-cycle passes)": ens.K_MG_ROW,
+    kernels = {f"k_mg_row<{'float' if mg32 else 'double'},32,*> (fine-level V-cycle passes)": ens.K_MG_ROW,
                "k_nl_assemble<32,1> (residual and Jacobian)": ens.K_NL_ASSEMBLE,
                "k_gm_spmv<32> (GMRES product w = A z)": ens.K_GM_SPMV,
                "k_gm_dots/k_gm_axpy<32> (Gram-Schmidt passes)": ens.K_GM_ORTH,
@@ -893,8 +897,9 @@ def run_newton(args):
         "config": {"workload": w.name, "mesh": f"{w.N}^3 Q1 hexahedra", "n": w.n, "nnz": w.nnz, "s": w.s, "M": w.M,
                    "sigma": w.sigma, "alpha": W.NEWTON_ALPHA, "beta": W.NEWTON_BETA,
                    "velocity": [round(v, 6) for v in W.NEWTON_VEL], "f": w.f, "rtol": w.rtol, "seed": w.seed,
-                   "linear_solver": f"GMRES({W.NEWTON_RESTART}) to {W.NEWTON_LIN_RTOL:g}, right-preconditioned by "
-                                    "the multigrid V-cycle of the diffusion operator"},
+                   "linear_solver": f"GMRES({W.NEWTON_RESTART}) to {lin_rtol:g}, right-preconditioned by "
+                                    "the multigrid V-cycle of the diffusion operator"
+                                    + (" in FP32" if mg32 else " in FP64")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
                      "launches": pd["launches"], "avg_launch_ms": round(pd["total_ms"] / max(pd["launches"], 1), 5),
@@ -905,21 +910,27 @@ def run_newton(args):
         "kernels": per_kernel,
     }
     if not args.no_cpu_baseline:
+        # A full oracle solve takes about 90 s per sample at 128^3, so the
+        # bounded sample is the first Newton step (hierarchy, residual and
+        # Jacobian, GMRES, update, and the next residual) of `threads`
+        # samples, scaled by the Newton steps the samples take.
         from oracle import oracle as orc
         threads = min(args.cpu_threads, w.s)
-        log("CPU oracle baseline (Newton) ...")
+        log("CPU oracle baseline (first Newton step) ...")
         t0 = time.perf_counter()
         _, ni, li, rr, st_o, _ = orc.ens_newton(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, W.NEWTON_ALPHA,
                                                 np.array(W.NEWTON_VEL), W.NEWTON_BETA, w.xi()[:threads],
-                                                prec=orc.PREC_MG, rtol=w.rtol, lin_rtol=W.NEWTON_LIN_RTOL,
+                                                prec=orc.PREC_MG, rtol=w.rtol, max_newton=1, lin_rtol=lin_rtol,
                                                 restart=W.NEWTON_RESTART)
         tc = time.perf_counter() - t0
+        steps_full = float(np.mean([t["newton_iters"] for t in stats[:threads]]))
         cores = min(threads, orc.max_threads())
         out["cpu_baseline"] = {
-            "value": threads / tc, "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": (f"{threads} samples of the same workload, one per OpenMP thread: the oracle's Newton with "
-                       f"multigrid-preconditioned GMRES in full, Newton steps {[int(v) for v in ni]}, GMRES "
-                       f"iterations {[int(v) for v in li]}"),
+            "value": threads / (tc * steps_full), "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": (f"the first Newton step of {threads} samples of the same workload (one per OpenMP thread: "
+                       f"the oracle's hierarchy, residual and Jacobian, multigrid-preconditioned GMRES(30) to "
+                       f"{lin_rtol:g} with {[int(v) for v in li]} iterations, update, next residual) in "
+                       f"{tc:.1f} s, scaled by the {steps_full:g} Newton steps these samples take"),
             "seconds_measured": round(tc, 2)}
     print(json.dumps(out), flush=True)
 

@@ -385,13 +385,17 @@ typedef struct {
 ens_status ens_gmres_workspace_bytes(const ens_graph* graph, int32_t s, int32_t restart, size_t* bytes);
 /* values [nnz][s] (the matrix), b and x [n][s] (x in: initial guess), all
  * device FP64.  Preconditioner M: mg == NULL -> Jacobi (the diagonal of
- * values); else the V-cycle of the set-up FP64 hierarchy `mg`, whose fine
- * level is the matrix mg_values [nnz][s] it was set up with (for the
- * Newton systems: the diffusion matrix of ens_assemble).  stats[e]: iters,
+ * values); else the V-cycle of the set-up hierarchy `mg`, whose fine level
+ * is the matrix mg_values [nnz][s] it was set up with (for the Newton
+ * systems: the diffusion matrix of ens_assemble), FP64 for an FP64
+ * hierarchy and FP32 (values32) for an FP32 one.  An FP32 cycle takes its
+ * input rounded to FP32 and its output is widened back; the Krylov basis,
+ * products and updates stay FP64, and the true residual at each cycle's
+ * end decides convergence.  stats[e]: iters,
  * outer_iters = restart cycles, status, rel_res = the final relative
  * residual.  Synchronises. */
 ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,
-                     const ens_gmres_opts* opts, const ens_mg* mg, const double* mg_values, void* workspace,
+                     const ens_gmres_opts* opts, const ens_mg* mg, const void* mg_values, void* workspace,
                      size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream);
 
 /* Newton's method per sample on F(u) = 0 (Sec. 4, Eq. fenl_lin_sys):
@@ -423,7 +427,7 @@ ens_status ens_newton_workspace_bytes(const ens_graph* graph, int32_t s, int32_t
  * the step and the GMRES workspace.  Synchronises. */
 ens_status ens_newton(int32_t N, const ens_graph* graph, const void* kl, const ens_nl_problem* problem, int32_t s,
                       const double* xi, double* u, const ens_newton_opts* opts, const ens_mg* mg,
-                      const double* mg_values, void* workspace, size_t ws_bytes, ens_newton_stat* stats,
+                      const void* mg_values, void* workspace, size_t ws_bytes, ens_newton_stat* stats,
                       hipStream_t stream);
 
 /* The one-sample baseline with up to `streams` (1..32) solves in flight at

@@ -260,6 +260,49 @@ static __global__ __launch_bounds__(kBlock) void k_gm_spmv(int n, const int32_t*
   ((typename M::vt*)w)[row * M::L + sub] = acc;
 }
 
+// w = A z with an FP32 z (the output of an FP32 cycle) widened to FP64 as
+// it is gathered; products and sums in FP64.
+template <int S>
+static __global__ __launch_bounds__(kBlock) void k_gm_spmv_z32(int n, const int32_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ ci,
+                                                               const double* __restrict__ vals,
+                                                               const float* __restrict__ z, double* __restrict__ w) {
+  using M = EnsMap<double, S>;
+  using vt = typename M::vt;
+  typedef typename vec_t<float, M::V>::type ft;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane % M::L;
+  const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
+  if (row >= n) return;
+  const vt* vv = (const vt*)vals + sub;
+  const ft* zv = (const ft*)z + sub;
+  vt acc = (vt)0.0;
+  const int64_t k1 = rp[row + 1];
+  int64_t k = rp[row];
+  for (; k + 2 < k1; k += 3) {
+    int32_t c3[3];
+    vt a[3];
+    ft b[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c3[j] = ci[k + j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a[j] = load_stream(vv + (k + j) * M::L);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) b[j] = zv[(int64_t)c3[j] * M::L];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int v = 0; v < M::V; ++v) acc[v] += a[j][v] * (double)b[j][v];
+  }
+  for (; k < k1; ++k) {
+    const vt a = load_stream(vv + k * M::L);
+    const ft b = zv[(int64_t)ci[k] * M::L];
+#pragma unroll
+    for (int v = 0; v < M::V; ++v) acc[v] += a[v] * (double)b[v];
+  }
+  ((vt*)w)[row * M::L + sub] = acc;
+}
+
 // part[blk][i*S + e] = sum over the block's chunks of V_i . w, i = 0..j.
 template <int S>
 static __global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t nchunks, const double* __restrict__ V,
@@ -320,14 +363,19 @@ static __global__ __launch_bounds__(kBlock) void k_gm_axpy(int64_t nchunks, cons
   if (NORM) block_partials<S, VM::VS, 1, kBlock / 64>(acc, part + (int64_t)blockIdx.x * pstride);
 }
 
-// vout = w * scale (exact zeros for idle samples); Jacobi: z = D^-1 vout.
-template <int S, bool JAC>
+// Preconditioner forms of the GMRES kernels.
+enum GmPrec { PR_MG64 = 0, PR_JACOBI = 1, PR_MG32 = 2 };
+
+// vout = w * scale (exact zeros for idle samples); then the input of the
+// preconditioner: Jacobi z = D^-1 vout, FP32 cycle z32 = (float) vout.
+template <int S, int PR>
 static __global__ __launch_bounds__(kBlock) void k_gm_scale(int64_t nchunks, const double* __restrict__ w,
                                                             const GmCtl* __restrict__ c, double* __restrict__ vout,
                                                             const double* __restrict__ dinv,
-                                                            double* __restrict__ z) {
+                                                            double* __restrict__ z, float* __restrict__ r32) {
   using VM = VecMap<double, S>;
   using vt = typename VM::vt;
+  typedef typename vec_t<float, VM::V>::type ft;
   const int64_t ch = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (ch >= nchunks) return;
   const int sub = threadIdx.x % VM::L;
@@ -339,16 +387,23 @@ static __global__ __launch_bounds__(kBlock) void k_gm_scale(int64_t nchunks, con
     v[k] = sc == 0.0 ? 0.0 : wv[k] * sc;
   }
   ((vt*)vout)[ch] = v;
-  if (JAC) ((vt*)z)[ch] = ((const vt*)dinv)[ch] * v;
+  if (PR == PR_JACOBI) ((vt*)z)[ch] = ((const vt*)dinv)[ch] * v;
+  if (PR == PR_MG32) {
+    ft f;
+#pragma unroll
+    for (int k = 0; k < VM::V; ++k) f[k] = (float)v[k];
+    ((ft*)r32)[ch] = f;
+  }
 }
 
-// t = sum_{i<k} y_i V_i per sample.
-template <int S>
+// t = sum_{i<k} y_i V_i per sample (F32: stored rounded to FP32 in t32).
+template <int S, bool F32>
 static __global__ __launch_bounds__(kBlock) void k_gm_combine(int64_t nchunks, const double* __restrict__ V,
                                                               int64_t vstride, int k, const GmCtl* __restrict__ c,
-                                                              double* __restrict__ t) {
+                                                              double* __restrict__ t, float* __restrict__ t32) {
   using VM = VecMap<double, S>;
   using vt = typename VM::vt;
+  typedef typename vec_t<float, VM::V>::type ft;
   __shared__ double s_y[kGmMaxRestart][S];
   for (int q = threadIdx.x; q < k * S; q += kBlock) s_y[q / S][q % S] = c->y[q % S][q / S];
   __syncthreads();
@@ -361,22 +416,38 @@ static __global__ __launch_bounds__(kBlock) void k_gm_combine(int64_t nchunks, c
 #pragma unroll
     for (int v = 0; v < VM::V; ++v) acc[v] += s_y[i][VM::sample(sub, v)] * vv[v];
   }
-  ((vt*)t)[ch] = acc;
+  if (F32) {
+    ft f;
+#pragma unroll
+    for (int v = 0; v < VM::V; ++v) f[v] = (float)acc[v];
+    ((ft*)t32)[ch] = f;
+  } else {
+    ((vt*)t)[ch] = acc;
+  }
 }
 
 // x += M t for the samples updated in this cycle (Jacobi: M t = D^-1 t;
-// multigrid: t already holds M t).
-template <int S, bool JAC>
+// multigrid: t, or in FP32 t32, already holds M t).
+template <int S, int PR>
 static __global__ __launch_bounds__(kBlock) void k_gm_addto(int64_t nchunks, const double* __restrict__ t,
+                                                            const float* __restrict__ t32,
                                                             const double* __restrict__ dinv,
                                                             const GmCtl* __restrict__ c, double* __restrict__ x) {
   using VM = VecMap<double, S>;
   using vt = typename VM::vt;
+  typedef typename vec_t<float, VM::V>::type ft;
   const int64_t ch = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (ch >= nchunks) return;
   const int sub = threadIdx.x % VM::L;
-  vt tv = ((const vt*)t)[ch];
-  if (JAC) tv = ((const vt*)dinv)[ch] * tv;
+  vt tv;
+  if (PR == PR_MG32) {
+    const ft f = ((const ft*)t32)[ch];
+#pragma unroll
+    for (int v = 0; v < VM::V; ++v) tv[v] = (double)f[v];
+  } else {
+    tv = ((const vt*)t)[ch];
+  }
+  if (PR == PR_JACOBI) tv = ((const vt*)dinv)[ch] * tv;
   vt xv = ((const vt*)x)[ch];
 #pragma unroll
   for (int v = 0; v < VM::V; ++v)
@@ -428,6 +499,7 @@ struct GmWork {
   GmCtl* ctl;
   double *part, *part1, *rpart;
   double *V, *w, *z, *t, *dinv;
+  float *r32, *z32;  // input and output of an FP32 cycle
   int64_t pstride;
 };
 
@@ -449,7 +521,9 @@ static size_t gm_layout(int64_t n, int S, int restart, GmWork* w, char* base) {
   double* z = (double*)take(vb);
   double* t = (double*)take(vb);
   double* dinv = (double*)take(vb);
-  if (w) *w = GmWork{ctl, part, part1, rpart, V, wv, z, t, dinv, ps};
+  float* r32 = (float*)take(vb / 2);
+  float* z32 = (float*)take(vb / 2);
+  if (w) *w = GmWork{ctl, part, part1, rpart, V, wv, z, t, dinv, r32, z32, ps};
   return off;
 }
 
@@ -505,6 +579,7 @@ static ens_status gmres(const ens_graph* g, const double* vals, const double* b,
   const unsigned rb = (unsigned)row_blocks(n, S);
   const unsigned sb = grid_of(n, (kBlock / 64) * EnsMap<double, S>::RPW);
   const bool jac = plan == nullptr;
+  const bool f32 = plan != nullptr && plan->fp32;
   const double spmv_bytes = (double)g->nnz * (S * 8.0 + 4.0) + 4.0 * (n + 1) + 2.0 * n * S * 8.0;
   const double vbytes = (double)n * S * 8.0;
   hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, st, w.ctl, rtol, restart, max_iter);
@@ -521,17 +596,34 @@ static ens_status gmres(const ens_graph* g, const double* vals, const double* b,
     ens_status rc = read_flag(&w.ctl->n_run, st, &nrun);
     if (rc != ENS_OK) return rc;
     if (nrun == 0) break;
-    if (jac) hipLaunchKernelGGL((k_gm_scale<S, true>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.w, w.ctl, w.V,
-                                w.dinv, w.z);
-    else hipLaunchKernelGGL((k_gm_scale<S, false>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.w, w.ctl, w.V,
-                            (const double*)nullptr, (double*)nullptr);
+    auto scale = [&](double* vout) {
+      if (jac)
+        hipLaunchKernelGGL((k_gm_scale<S, PR_JACOBI>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.w, w.ctl, vout,
+                           w.dinv, w.z, (float*)nullptr);
+      else if (f32)
+        hipLaunchKernelGGL((k_gm_scale<S, PR_MG32>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.w, w.ctl, vout,
+                           (const double*)nullptr, (double*)nullptr, w.r32);
+      else
+        hipLaunchKernelGGL((k_gm_scale<S, PR_MG64>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.w, w.ctl, vout,
+                           (const double*)nullptr, (double*)nullptr, (float*)nullptr);
+    };
+    scale(w.V);
     int steps = 0;
     for (int j = 0; j < restart; ++j) {
       double* vj = w.V + (int64_t)j * vstride;
-      if (!jac) mg_vcycle<double, S>(*plan, vj, w.z, nullptr, st);
-      prof_begin(ENS_K_GM_SPMV, st);
-      hipLaunchKernelGGL((k_gm_spmv<S>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, w.z, w.w);
-      prof_end(ENS_K_GM_SPMV, st, spmv_bytes);
+      if (f32) {
+        mg_vcycle<float, S>(*plan, w.r32, w.z32, nullptr, st);
+        prof_begin(ENS_K_GM_SPMV, st);
+        hipLaunchKernelGGL((k_gm_spmv_z32<S>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals,
+                           w.z32, w.w);
+        prof_end(ENS_K_GM_SPMV, st, spmv_bytes - 4.0 * n * S);
+      } else {
+        if (!jac) mg_vcycle<double, S>(*plan, vj, w.z, nullptr, st);
+        prof_begin(ENS_K_GM_SPMV, st);
+        hipLaunchKernelGGL((k_gm_spmv<S>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, w.z,
+                           w.w);
+        prof_end(ENS_K_GM_SPMV, st, spmv_bytes);
+      }
       for (int pass = 0; pass < 2; ++pass) {
         prof_begin(ENS_K_GM_ORTH, st);
         hipLaunchKernelGGL((k_gm_dots<S>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.w, w.part,
@@ -554,20 +646,26 @@ static ens_status gmres(const ens_graph* g, const double* vals, const double* b,
       rc = read_flag(&w.ctl->n_cyc, st, &ncyc);
       if (rc != ENS_OK) return rc;
       if (ncyc == 0) break;
-      double* vn = w.V + (int64_t)(j + 1) * vstride;
-      if (jac) hipLaunchKernelGGL((k_gm_scale<S, true>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.w, w.ctl, vn,
-                                  w.dinv, w.z);
-      else hipLaunchKernelGGL((k_gm_scale<S, false>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.w, w.ctl, vn,
-                              (const double*)nullptr, (double*)nullptr);
+      scale(w.V + (int64_t)(j + 1) * vstride);
     }
     hipLaunchKernelGGL((k_gm_solve<S>), dim3(1), dim3(64), 0, st, w.ctl);
-    hipLaunchKernelGGL((k_gm_combine<S>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.V, vstride, steps, w.ctl, w.t);
+    if (f32)
+      hipLaunchKernelGGL((k_gm_combine<S, true>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.V, vstride, steps, w.ctl,
+                         (double*)nullptr, w.r32);
+    else
+      hipLaunchKernelGGL((k_gm_combine<S, false>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.V, vstride, steps,
+                         w.ctl, w.t, (float*)nullptr);
     if (jac) {
-      hipLaunchKernelGGL((k_gm_addto<S, true>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.t, w.dinv, w.ctl, x);
+      hipLaunchKernelGGL((k_gm_addto<S, PR_JACOBI>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.t,
+                         (const float*)nullptr, w.dinv, w.ctl, x);
+    } else if (f32) {
+      mg_vcycle<float, S>(*plan, w.r32, w.z32, nullptr, st);
+      hipLaunchKernelGGL((k_gm_addto<S, PR_MG32>), dim3(eg), dim3(kBlock), 0, st, nchunks, (const double*)nullptr,
+                         w.z32, (const double*)nullptr, w.ctl, x);
     } else {
       mg_vcycle<double, S>(*plan, w.t, w.z, nullptr, st);
-      hipLaunchKernelGGL((k_gm_addto<S, false>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.z,
-                         (const double*)nullptr, w.ctl, x);
+      hipLaunchKernelGGL((k_gm_addto<S, PR_MG64>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.z,
+                         (const float*)nullptr, (const double*)nullptr, w.ctl, x);
     }
     hipLaunchKernelGGL((k_gm_residual<S>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b,
                        w.w, w.rpart);
@@ -750,11 +848,11 @@ ens_status check_graph_nl(const ens_graph* g) {
   return ENS_OK;
 }
 
-// The multigrid plan of a set-up FP64 hierarchy, attached to the matrix it
-// was set up with (mg_values).
-ens_status mg_plan_for(const ens_mg* mg, const ens_graph* graph, int32_t s, const double* mg_values, MgPlan* plan) {
+// The multigrid plan of a set-up hierarchy, attached to the fine matrix its
+// cycle runs on (mg_values: FP64 for an FP64 hierarchy, FP32 for an FP32
+// one).
+ens_status mg_plan_for(const ens_mg* mg, const ens_graph* graph, int32_t s, const void* mg_values, MgPlan* plan) {
   ENS_ARG_CHECK(mg->buffer && mg_values && aligned16(mg_values), "multigrid needs its buffer and fine matrix");
-  ENS_ARG_CHECK(!mg->fp32, "the GMRES preconditioner is an FP64 cycle");
   ENS_ARG_CHECK(mg->s == s, "hierarchy built for another ensemble size");
   const int64_t nn = (int64_t)(mg->N + 1) * (mg->N + 1) * (mg->N + 1);
   ENS_ARG_CHECK(graph->n == nn, "graph is not the hierarchy's fine mesh");
@@ -762,7 +860,7 @@ ens_status mg_plan_for(const ens_mg* mg, const ens_graph* graph, int32_t s, cons
     set_error("multigrid hierarchy not set up: call ens_mg_build and ens_mg_setup first");
     return ENS_E_ARG;
   }
-  if (!mg_plan(mg->N, mg->M, s, 0, (char*)mg->buffer, plan)) {
+  if (!mg_plan(mg->N, mg->M, s, mg->fp32 != 0, (char*)mg->buffer, plan)) {
     set_error("multigrid hierarchy of N=%d is not supported", mg->N);
     return ENS_E_UNSUPPORTED;
   }
@@ -770,7 +868,8 @@ ens_status mg_plan_for(const ens_mg* mg, const ens_graph* graph, int32_t s, cons
     set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, plan->bytes);
     return ENS_E_NOMEM;
   }
-  mg_attach_fine(plan, graph->row_ptr, graph->col_idx, mg_values, nullptr);
+  if (mg->fp32) mg_attach_fine(plan, graph->row_ptr, graph->col_idx, nullptr, (const float*)mg_values);
+  else mg_attach_fine(plan, graph->row_ptr, graph->col_idx, (const double*)mg_values, nullptr);
   return ENS_OK;
 }
 
@@ -792,7 +891,7 @@ ens_status ens_gmres_workspace_bytes(const ens_graph* graph, int32_t s, int32_t 
 }
 
 ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,
-                     const ens_gmres_opts* opts, const ens_mg* mg, const double* mg_values, void* workspace,
+                     const ens_gmres_opts* opts, const ens_mg* mg, const void* mg_values, void* workspace,
                      size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream) {
   ens_status st = check_graph_nl(graph);
   if (st != ENS_OK) return st;
@@ -872,7 +971,7 @@ ens_status ens_newton_workspace_bytes(const ens_graph* graph, int32_t s, int32_t
 
 ens_status ens_newton(int32_t N, const ens_graph* graph, const void* kl, const ens_nl_problem* problem, int32_t s,
                       const double* xi, double* u, const ens_newton_opts* opts, const ens_mg* mg,
-                      const double* mg_values, void* workspace, size_t ws_bytes, ens_newton_stat* stats,
+                      const void* mg_values, void* workspace, size_t ws_bytes, ens_newton_stat* stats,
                       hipStream_t stream) {
   ens_status st = check_graph_nl(graph);
   if (st != ENS_OK) return st;

@@ -126,6 +126,34 @@ def test_gmres_converges_like_the_oracle(E, orc, prec, restart):
         assert max(t["iters"] for t in stats) <= 20
 
 
+@pytest.mark.parametrize("restart", [30, 4])
+def test_gmres_with_an_fp32_cycle_reaches_the_fp64_tolerance(E, orc, restart):
+    # the FP32 V-cycle as right preconditioner inside FP64 GMRES: the FP64
+    # true residual decides, so the solve meets rtol like the FP64 cycle
+    N, s, M, rtol = 12, 16, 10, 1e-10
+    g, kl, xt, xi, F, J, K = _nl_system(E, orc, N, s, M, 4450 + restart)
+    K2, K32, _ = E.assemble(g, kl, xt, M, 0.3, want32=True)
+    mg32 = E.Multigrid(N, M, s, fp32=True).setup(g, K2, xt, 0.3, values32=K32)
+    x, stats, st = E.gmres(g, J, F, opts=E.gmres_opts(rtol=rtol, restart=restart, max_iter=2000), mg=mg32,
+                           mg_values=K32)
+    assert st == E.ENS_OK, stats
+    rp, ci = orc.graph(N)
+    Jo, Fo = _np(J), _np(F)
+    xo, ito, _, _ = orc.ens_gmres(N, rp, ci, Jo, Fo, prec=1, M=M, sigma=0.3, xi=xi, rtol=rtol, restart=restart,
+                                  max_iter=2000)
+    xg = _np(x)
+    true = orc.ens_true_residual(rp, ci, Jo, Fo, xg)
+    for e in range(s):
+        assert true[e] <= rtol * (1 + 1e-6), (e, true[e])
+        assert _rel(xg[:, e], xo[:, e]) <= 1e-7
+        # FP32 rounding in M (relative 1e-7) makes the Arnoldi estimate drift
+        # from the true residual near 1e-10, which can cost an extra cycle
+        assert stats[e]["iters"] <= 2 * int(ito[e]) + 4, (e, stats[e]["iters"], ito[e])
+    # a hierarchy without its fine matrix is refused
+    with pytest.raises(E.EnsError):
+        E.gmres(g, J, F, mg=mg32, mg_values=None)
+
+
 def test_gmres_edge_cases(E, orc):
     N, s, M = 8, 8, 5
     g, kl, xt, xi, F, J, K = _nl_system(E, orc, N, s, M, 4500)
@@ -148,7 +176,7 @@ def test_gmres_edge_cases(E, orc):
             E.gmres(g, J, F, opts=E.gmres_opts(restart=bad))
     with pytest.raises(E.EnsError):
         E.gmres(g, J, F, mg=E.Multigrid(N, M, s), mg_values=K)  # built, not set up
-    mg32 = E.Multigrid(N, M, s, fp32=True)
+    mg32 = E.Multigrid(N, M, s, fp32=True)  # built, not set up
     with pytest.raises(E.EnsError):
         E.gmres(g, J, F, mg=mg32, mg_values=K)
 
@@ -185,6 +213,32 @@ def test_newton_matches_oracle(E, orc, prec, N, s):
         fn = np.linalg.norm(Fg[:, e]) / np.linalg.norm(ld[:, e])
         assert fn <= rtol * (1 + 1e-6), (e, fn)
         assert abs(stats[e]["rel_res"] - fn) <= 1e-6 * rtol + 1e-3 * fn
+        assert _rel(ug[:, e], ut[:, e]) <= 1e-6
+
+
+def test_newton_with_an_fp32_cycle(E, orc):
+    N, s, M, sigma, alpha, beta, rtol = 16, 32, 10, 0.3, 10.0, 100.0, 1e-8
+    xi = draw_xi(4650, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    K, K32, _ = E.assemble(g, kl, xt, M, sigma, want32=True)
+    mg32 = E.Multigrid(N, M, s, fp32=True).setup(g, K, xt, sigma, values32=K32)
+    prob = E.nl_problem(M, sigma, alpha, beta, VEL)
+    u, stats, st = E.newton(g, kl, xt, prob, opts=E.newton_opts(rtol=rtol), mg=mg32, mg_values=K32)
+    assert st == E.ENS_OK, stats
+    uo, nio, _, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi,
+                                         prec=orc.PREC_MG, rtol=rtol)
+    ut, _, _, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi,
+                                       prec=orc.PREC_MG, rtol=1e-13, lin_rtol=1e-12)
+    ug = _np(u)
+    rp, ci = orc.graph(N)
+    Fg, _, ld = orc.ens_nl_assemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, ug,
+                                    want_jac=False)
+    for e in range(s):
+        assert stats[e]["status"] == 0
+        assert abs(stats[e]["newton_iters"] - int(nio[e])) <= 1
+        assert np.linalg.norm(Fg[:, e]) <= rtol * np.linalg.norm(ld[:, e]) * (1 + 1e-6)
         assert _rel(ug[:, e], ut[:, e]) <= 1e-6
 
 
