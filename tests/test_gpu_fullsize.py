@@ -98,3 +98,49 @@ def test_headline_workload_refinement(E, orc):
             assert dv <= 1e-13
             assert res <= w.rtol * (1 + 1e-6)
             assert abs(res - stats[e]["rel_res"]) <= 1e-3 * res
+
+
+def test_newton_workload(E, orc):
+    """128^3, s = 32, Newton with FP32-multigrid-preconditioned GMRES as
+    bench.py times it.  Samples 0 and 31: the oracle evaluates the nonlinear
+    residual of the GPU solution (<= 1e-8 |load|), and the GPU residual and
+    Jacobian at that solution element by element (1e-12 of the load, 1e-13
+    of the Jacobian's scale)."""
+    import workloads as W
+    w = W.NEWTON
+    xi = w.xi()
+    dev = "cuda"
+    g = E.graph_build(w.N)
+    kl = E.kl_build(w.N, w.M, w.L)
+    xt = torch.as_tensor(xi, device=dev)
+    K, K32, _ = E.assemble(g, kl, xt, w.M, w.sigma, want32=True)
+    mg = E.Multigrid(w.N, w.M, w.s, fp32=True).setup(g, K, xt, w.sigma, values32=K32)
+    prob = E.nl_problem(w.M, w.sigma, W.NEWTON_ALPHA, W.NEWTON_BETA, W.NEWTON_VEL)
+    u, stats, st = E.newton(g, kl, xt, prob, opts=E.newton_opts(rtol=w.rtol, lin_rtol=W.NEWTON_LIN_RTOL,
+                                                                restart=W.NEWTON_RESTART), mg=mg, mg_values=K32)
+    assert st == E.ENS_OK, stats
+    print(f"GPU done: Newton steps {[t['newton_iters'] for t in stats]}", flush=True)
+    del mg, K, K32
+    Fg, Jg, _ = E.nl_assemble(g, kl, xt, prob, u)
+    check = [0, 31]
+    ug = u.cpu().numpy()
+    fg = {e: Fg[:, e].cpu().numpy() for e in check}
+    jg = {e: Jg[:, e].cpu().numpy() for e in check}
+    del Fg, Jg
+    rp, ci = orc.graph(w.N)
+
+    def one(e):
+        ac = orc.kl_coef_qp(w.N, w.M, w.L, w.kappa0, w.sigma, xi[e])
+        F, J, ld = orc.nl_assemble_scalar(w.N, rp, ci, ac, w.f, W.NEWTON_ALPHA, np.array(W.NEWTON_VEL),
+                                          W.NEWTON_BETA, ug[:, e])
+        # F nearly cancels at the root, so its error is measured against the
+        # size of its terms (the load)
+        return e, np.linalg.norm(F) / np.linalg.norm(ld), np.abs(fg[e] - F).max() / np.abs(ld).max(), \
+            np.abs(jg[e] - J).max() / np.abs(J).max()
+
+    with cf.ThreadPoolExecutor(2) as ex:
+        for e, res, dF, dJ in ex.map(one, check):
+            print(f"sample {e}: |F|/|load| {res:.3e}, F {dF:.2e}, J {dJ:.2e}", flush=True)
+            assert res <= w.rtol * (1 + 1e-6)
+            assert abs(stats[e]["rel_res"] - res) <= 1e-3 * res + 1e-14
+            assert dF <= 1e-12 and dJ <= 1e-13
