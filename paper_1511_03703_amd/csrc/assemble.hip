@@ -26,6 +26,7 @@ constexpr int kAsmMaxM = 16;
 __constant__ double c_G[8][8][8];  // [q][a][b], symmetric in (a,b)
 __constant__ double c_N[8][8];     // [q][a]: N_a at Gauss point q
 __constant__ double c_dN[8][8][3]; // [q][a][d]: reference derivative of N_a along axis d
+__constant__ double c_NN[8][8][8]; // [q][a][b]: N_a N_b at Gauss point q
 
 static bool g_G_ready[64];
 
@@ -80,6 +81,12 @@ static hipError_t upload_G() {
     }
   }
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_N), Nq, sizeof(Nq));
+  if (e != hipSuccess) return e;
+  double NN[8][8][8];
+  for (int q = 0; q < 8; ++q)
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b) NN[q][a][b] = Nq[q][a] * Nq[q][b];
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_NN), NN, sizeof(NN));
   if (e != hipSuccess) return e;
   return hipMemcpyToSymbol(HIP_SYMBOL(c_dN), dN, sizeof(dN));
 }
@@ -218,16 +225,19 @@ __global__ __launch_bounds__(256) void k_assemble(int N, const double* __restric
 // diffusion_sys, Eq. fenl_lin_sys, Alg. "assembly" with alpha, beta != 0),
 // row-owned like k_assemble: lane e of a row's group gathers the element
 // solution u_e of its sample for each element around the node (ascending
-// element id), evaluates u_h and its reference gradient at the 8 Gauss
-// points and adds
-//   F_a  += sum_q (h/8) kappa_q dN_a.g_q + (h^2/8) alpha N_a (v.g_q)
-//                 + (h^3/8) (beta N_a u_q^2 - f N_a)
-//   J_ab += sum_q (h/8) kappa_q G_q[a][b] + (h^2/8) alpha N_a (v.dN_b)
-//                 + (h^3/8) 2 beta u_q N_a N_b
-// with g_q = sum_b dN_b(q) u_b the reference gradient (physical = g/h).
-// Boundary rows: F = u and identity rows; boundary columns of interior
-// rows stored as zeros; load (optional) = the source part of F.
-template <int S, int LDS>
+// element id) and forms the element's Jacobian row a
+//   J_ab = D_ab + alpha (h^2/8) C_ab + 2 beta (h^3/8) sum_q u_q N_a N_b,
+//   D_ab = (h/8) sum_q kappa_q G_q[a][b],   C_ab = sum_q N_a (v.dN_b)
+// (C does not depend on the element: one 8x8 table per launch), with u_q
+// the interpolated solution at Gauss point q.  Since the diffusion and
+// advection terms are linear in u and the reaction term quadratic, the
+// element residual is
+//   F_a = sum_b (D_ab + alpha (h^2/8) C_ab + beta (h^3/8) sum_q u_q N_a N_b) u_b
+//         - (h^3/8) f sum_q N_a,
+// so no gradient of u_h is formed.  Boundary rows: F = u and identity rows;
+// boundary columns of interior rows stored as zeros; load (optional) = the
+// source part of F.
+template <int S, int LDS, bool JAC>
 __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __restrict__ kl_sqrt_lam,
                                                       const int32_t* __restrict__ kl_triple,
                                                       const double* __restrict__ kl_phi, int M, double kappa0,
@@ -238,15 +248,18 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
                                                       double* __restrict__ F, double* __restrict__ load) {
   constexpr int RPB = 256 / S;
   __shared__ double s_cm[S * kAsmMaxM];
-  __shared__ double s_dv[8][8];  // v . dN_b at point q
+  __shared__ double s_adv[8][8];  // C_ab = sum_q N_a (v . dN_b)
   extern __shared__ double s_phi[];
   for (int t = threadIdx.x; t < S * M; t += blockDim.x) {
     const int ee = t / M, m = t % M;
     s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)ee * M + m];
   }
   if (threadIdx.x < 64) {
-    const int q = threadIdx.x >> 3, b = threadIdx.x & 7;
-    s_dv[q][b] = vx * c_dN[q][b][0] + vy * c_dN[q][b][1] + vz * c_dN[q][b][2];
+    const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
+    double c = 0.0;
+    for (int q = 0; q < 8; ++q)
+      c += c_N[q][a] * (vx * c_dN[q][b][0] + vy * c_dN[q][b][1] + vz * c_dN[q][b][2]);
+    s_adv[a][b] = c;
   }
   if (LDS)
     for (int t = threadIdx.x; t < M * 2 * N; t += blockDim.x) s_phi[t] = kl_phi[t];
@@ -263,8 +276,8 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
   const double wd = h * 0.125;             // diffusion: w_q / h^2
   const double wa = h * h * 0.125 * alpha; // advection: alpha w_q / h
   const double wr = h * h * h * 0.125;     // reaction and source: w_q
+  const double wb = wr * beta;
   const int64_t two_n = 2 * (int64_t)N;
-  const bool jac = values != nullptr;
 
   double acc[27];
 #pragma unroll
@@ -289,40 +302,34 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
                                                               (int64_t)n1 * (ez + ((b >> 2) & 1)));
           ue[b] = u[node * S + e];
         }
-        double rq[8];
+        double uq[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          double uq = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+          double t = 0.0;
 #pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            uq += c_N[q][b] * ue[b];
-            g0 += c_dN[q][b][0] * ue[b];
-            g1 += c_dN[q][b][1] * ue[b];
-            g2 += c_dN[q][b][2] * ue[b];
-          }
-          const double na = c_N[q][ai];
-          const double diff = c_dN[q][ai][0] * g0 + c_dN[q][ai][1] * g1 + c_dN[q][ai][2] * g2;
-          fa += wd * kq[q] * diff + wa * na * (vx * g0 + vy * g1 + vz * g2) +
-                wr * (beta * na * uq * uq - fsrc * na);
-          la += wr * fsrc * na;
-          rq[q] = wr * 2.0 * beta * uq * na;
+          for (int b = 0; b < 8; ++b) t += c_N[q][b] * ue[b];
+          uq[q] = t;
+          la += wr * fsrc * c_N[q][ai];
         }
-        if (jac) {
 #pragma unroll
-          for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < 8; ++b) {
+          double dg = 0.0, rn = 0.0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            dg += kq[q] * c_G[q][ai][b];
+            rn += uq[q] * c_NN[q][ai][b];
+          }
+          const double lin = wd * dg + wa * s_adv[ai][b];
+          fa += (lin + wb * rn) * ue[b];
+          if (JAC) {
             const int dx = ex_off + (b & 1), dy = ey_off + ((b >> 1) & 1), dz = ez_off + ((b >> 2) & 1);
-            const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-            double jab = 0.0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-              jab += wd * kq[q] * c_G[q][ai][b] + wa * c_N[q][ai] * s_dv[q][b] + rq[q] * c_N[q][b];
-            acc[slot27] += jab;
+            acc[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] += lin + 2.0 * wb * rn;
           }
         }
       }
 
   const bool bnd_row = (ii == 0 || ii == N || jj == 0 || jj == N || kk == 0 || kk == N);
-  if (jac) {
+  if (JAC) {
     const int64_t start = row_ptr[row];
     int pos = 0;
 #pragma unroll
@@ -342,7 +349,7 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
           ++pos;
         }
   }
-  F[row * S + e] = bnd_row ? u[row * S + e] : fa;
+  F[row * S + e] = bnd_row ? u[row * S + e] : fa - la;
   if (load) load[row * S + e] = bnd_row ? 0.0 : la;
 }
 
@@ -440,22 +447,26 @@ extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const v
   const size_t lds_bytes = table > 0 && table <= 48 * 1024 ? table : 0;
   prof_begin(ENS_K_NL_ASSEMBLE, stream);
   switch (s) {
-#define ENS_NL_CASE(SS)                                                                                        \
-  case SS:                                                                                                     \
-    if (lds_bytes)                                                                                             \
-      hipLaunchKernelGGL((k_nl_assemble<SS, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, stream, N, sq, tr, \
-                         phi, M, prob->kappa0, prob->sigma, prob->f, prob->alpha, prob->beta, prob->vx, prob->vy,  \
-                         prob->vz, xi, graph->row_ptr, u, values, F, load);                                      \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_nl_assemble<SS, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, N, sq, tr, phi, M, \
-                         prob->kappa0, prob->sigma, prob->f, prob->alpha, prob->beta, prob->vx, prob->vy, prob->vz, \
-                         xi, graph->row_ptr, u, values, F, load);                                                \
+#define ENS_NL_LAUNCH(SS, LL, JJ)                                                                                \
+  hipLaunchKernelGGL((k_nl_assemble<SS, LL, JJ>), dim3((unsigned)blocks), dim3(256), LL ? lds_bytes : 0, stream, N, \
+                     sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, prob->alpha, prob->beta, prob->vx,         \
+                     prob->vy, prob->vz, xi, graph->row_ptr, u, values, F, load)
+#define ENS_NL_CASE(SS)                                                     \
+  case SS:                                                                  \
+    if (lds_bytes) {                                                        \
+      if (values) ENS_NL_LAUNCH(SS, 1, true);                               \
+      else ENS_NL_LAUNCH(SS, 1, false);                                     \
+    } else {                                                                \
+      if (values) ENS_NL_LAUNCH(SS, 0, true);                               \
+      else ENS_NL_LAUNCH(SS, 0, false);                                     \
+    }                                                                       \
     break;
     ENS_NL_CASE(4)
     ENS_NL_CASE(8)
     ENS_NL_CASE(16)
     ENS_NL_CASE(32)
 #undef ENS_NL_CASE
+#undef ENS_NL_LAUNCH
   }
   ENS_LAUNCH_CHECK();
   const double bytes = (values ? (double)nnz * s * 8.0 : 0.0) + (double)n * s * 8.0 * (load ? 3.0 : 2.0) +
