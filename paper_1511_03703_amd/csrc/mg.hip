@@ -73,7 +73,7 @@ static double mg_built_L(const ens_mg* mg) {
   return r ? r->L : 0.0;
 }
 
-constexpr int kMgPartRows = 1024;
+constexpr int kMgPartRows = 8192;
 
 static size_t r256m(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -159,13 +159,14 @@ __device__ inline ChebK cheb_consts(double lmax) {
   return ChebK{1.0 / theta, rho1 * rho0, 2.0 * rho1 / delta};
 }
 
-// One pass over the rows for D^-1 (in the cycle precision, from the FP64
-// diagonal) and the per-sample Gershgorin bound max_i sum_j |a_ij| / a_ii
-// (row sums in ascending entry order, FP64): block maxima over a
-// grid-stride range of rows, then one block over the block maxima.
+// One pass over the rows of the matrix the cycle runs on (FP64, or the FP32
+// copy for an FP32 cycle) for D^-1 and the per-sample Gershgorin bound
+// max_i sum_j |a_ij| / a_ii (row sums in ascending entry order, in FP64):
+// block maxima over a grid-stride range of rows, then one block over the
+// block maxima.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_mg_diag_bound(int64_t n, const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ ci, const double* __restrict__ vals,
+                                                       const int32_t* __restrict__ ci, const T* __restrict__ vals,
                                                        T* __restrict__ dinv, double* __restrict__ part) {
   constexpr int G = 256 / S;
   __shared__ double red[G][S];
@@ -173,8 +174,10 @@ __global__ __launch_bounds__(256) void k_mg_diag_bound(int64_t n, const int32_t*
   double m = 0.0;
   for (int64_t row = (int64_t)blockIdx.x * G + g; row < n; row += (int64_t)gridDim.x * G) {
     double s = 0.0, dg = 0.0;
-    for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
-      const double v = vals[k * S + e];
+    const int64_t k1 = rp[row + 1];
+#pragma unroll 3
+    for (int64_t k = rp[row]; k < k1; ++k) {
+      const double v = (double)vals[k * S + e];
       s += fabs(v);
       if (ci[k] == row) dg = v;
     }
@@ -517,8 +520,8 @@ static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* 
       if (rc != ENS_OK) return rc;
     }
     const unsigned gb = blocks_for(l.n, 256 / S) < (unsigned)kMgPartRows ? blocks_for(l.n, 256 / S) : kMgPartRows;
-    if (P.fp32)
-      hipLaunchKernelGGL((k_mg_diag_bound<float, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals,
+    if (P.fp32)  // the FP32 cycle's own matrix: its D^-1 and its bound
+      hipLaunchKernelGGL((k_mg_diag_bound<float, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals32,
                          (float*)l.dinv, P.part);
     else
       hipLaunchKernelGGL((k_mg_diag_bound<double, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals,
