@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import gc
 import json
 import os
 import sys
@@ -191,19 +192,32 @@ def run_solve(args):
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=mg_opts, workspace=ws)
 
     def timed(step, steps, warmup):
+        # profiling is on during the warmup too, so the timed steps repeat
+        # exactly the warmup's host work; the interpreter's cyclic garbage
+        # collector (a full pass over torch's objects takes tens of ms) is
+        # run once here and paused until the timing ends
+        ens.prof_enable(True)
+        gc.collect()
+        gc.disable()
         for i in range(warmup):
+            tw = time.perf_counter()
             _, stats, st = step()
-            log(f"warmup {i}: status {st}, iters {[t['iters'] for t in stats][:8]}...")
+            log(f"warmup {i}: {(time.perf_counter() - tw) * 1e3:.1f} ms, status {st}, "
+                f"iters {[t['iters'] for t in stats][:8]}...")
         torch.cuda.synchronize()
         ens.prof_reset()
-        ens.prof_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        marks = []
         for i in range(steps):
-            _, stats, st = step()
+            _, stats, st = step()  # ends with the solver's own synchronisation
+            marks.append(time.perf_counter())
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        gc.enable()
         ens.prof_enable(False)
+        per = [round((b - a) * 1e3, 2) for a, b in zip([t0] + marks[:-1], marks)]
+        log(f"ms per step: {per}")
         return el, stats
 
     def spmv_roofline():
@@ -465,12 +479,15 @@ def run_batch(args):
     for i in range(args.warmup):
         pool.run(xi, sigma, opts)
     torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     for i in range(args.steps):
         wave_times.clear()
         stats, rc = pool.run(xi, sigma, opts, on_wave=on_wave)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    gc.enable()
     per_step = elapsed / args.steps
     ok = rc == ens.ENS_OK and all(t["status"] == 0 and t["rel_res"] <= rtol * (1 + 1e-6) for st in stats
                                   for t in st)
@@ -658,11 +675,14 @@ def run_learned(args):
         eval_pass(collect=False)
     ens.prof_reset()
     ens.prof_enable(True)
+    gc.collect()
+    gc.disable()
     t_zero = t_learn = 0.0
     for _ in range(args.steps):
         tz, tl = eval_pass(collect=False)
         t_zero += tz
         t_learn += tl
+    gc.enable()
     ens.prof_enable(False)
     pq = ens.prof_query(ens.K_SPMV_F64)
     nt = W.LEARNED_TEST * args.steps
@@ -751,17 +771,20 @@ def run_mg(args):
         x.zero_()
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=opts, workspace=ws)
 
+    ens.prof_enable(True)
+    gc.collect()
+    gc.disable()
     for i in range(args.warmup):
         _, stats, st = step()
         log(f"warmup {i}: status {st}, iters {[t['iters'] for t in stats][:8]}...")
     torch.cuda.synchronize()
     ens.prof_reset()
-    ens.prof_enable(True)
     t0 = time.perf_counter()
     for i in range(args.steps):
         _, stats, st = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    gc.enable()
     ens.prof_enable(False)
     pr = ens.prof_query(ens.K_MG_ROW)
     ps = ens.prof_query(ens.K_SPMV_F32 if mixed else ens.K_SPMV_F64)
@@ -861,18 +884,21 @@ def run_newton(args):
         u.zero_()
         return ens.newton(g, kl, xi, prob, u=u, opts=opts, mg=mg, mg_values=K32 if mg32 else K, workspace=ws)
 
+    ens.prof_enable(True)
+    gc.collect()
+    gc.disable()
     for i in range(args.warmup):
         _, stats, st = step()
         log(f"warmup {i}: status {st}, newton {[t['newton_iters'] for t in stats][:8]}..., "
             f"gmres {[t['lin_iters'] for t in stats][:8]}...")
     torch.cuda.synchronize()
     ens.prof_reset()
-    ens.prof_enable(True)
     t0 = time.perf_counter()
     for i in range(args.steps):
         _, stats, st = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    gc.enable()
     ens.prof_enable(False)
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
     kernels = {f"k_mg_row<{'float' if mg32 else 'double'},32,*> (fine-level V-cycle passes)": ens.K_MG_ROW,

@@ -533,7 +533,8 @@ ens_status ens_stream_triad(double* a, const double* b, const double* c, double 
                             hipStream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
- * launch of the listed kernels while enabled. */
+ * launch of the listed kernels while enabled.  Enabling creates a pool of
+ * events up front (outside any region the caller times). */
 enum {
   ENS_K_SPMV_F64 = 0,   /* ensemble SpMV (standalone and inside CG), FP64 */
   ENS_K_SPMV_F32 = 1,   /* ensemble SpMV, FP32 (refinement inner loop)   */

@@ -197,9 +197,18 @@ ens_status ens_stream_triad(double* a, const double* b, const double* c, double 
   return ENS_OK;
 }
 
+// Events are created here, ahead of the timed work, so that no event
+// creation falls inside a measured region (each costs host time).
+constexpr size_t kProfEventPool = 1024;
+
 ens_status ens_prof_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on != 0;
+  while (g_prof_on && g_free_events.size() + 2 * g_pending.size() < kProfEventPool) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    g_free_events.push_back(e);
+  }
   return ENS_OK;
 }
 

@@ -194,11 +194,11 @@ __global__ __launch_bounds__(256) void k_mg_diag_bound(int64_t n, const int32_t*
   }
 }
 
-// out[e] = max over `rows` partial rows: G = 256/S threads per sample stride
+// out[e] = max over `rows` partial rows: G = 1024/S threads per sample stride
 // the rows, then combine in LDS (max is exact in any order).
 template <int S>
-__global__ __launch_bounds__(256) void k_mg_max(const double* __restrict__ part, int rows, double* __restrict__ out) {
-  constexpr int G = 256 / S;
+__global__ __launch_bounds__(1024) void k_mg_max(const double* __restrict__ part, int rows, double* __restrict__ out) {
+  constexpr int G = 1024 / S;
   __shared__ double red[G][S];
   const int e = threadIdx.x % S, g = threadIdx.x / S;
   double t = 0.0;
@@ -526,7 +526,7 @@ static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* 
     else
       hipLaunchKernelGGL((k_mg_diag_bound<double, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals,
                          (double*)l.dinv, P.part);
-    hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(256), 0, st, P.part, (int)gb, l.lmax);
+    hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(1024), 0, st, P.part, (int)gb, l.lmax);
   }
   const MgLevel& c = P.lv[P.levels - 1];
   if (c.m > 0)

@@ -366,6 +366,53 @@ static __global__ __launch_bounds__(kBlock) void k_gm_axpy(int64_t nchunks, cons
 // Preconditioner forms of the GMRES kernels.
 enum GmPrec { PR_MG64 = 0, PR_JACOBI = 1, PR_MG32 = 2 };
 
+// The first pass's update w -= sum_{i<=j} coef_i V_i fused with the second
+// pass's partials V_i . w on the updated w (j < JM): each V_i chunk is read
+// once and kept in registers for both uses.
+template <int S, int JM>
+static __global__ __launch_bounds__(kBlock) void k_gm_axpy_dots(int64_t nchunks, const double* __restrict__ V,
+                                                                int64_t vstride, int j, const GmCtl* __restrict__ c,
+                                                                double* __restrict__ w, double* __restrict__ part,
+                                                                int64_t pstride) {
+  using VM = VecMap<double, S>;
+  using vt = typename VM::vt;
+  static_assert(JM % kGmChunk == 0, "JM must be a multiple of the partial chunk");
+  __shared__ double s_coef[JM][S];
+  for (int t = threadIdx.x; t < JM * S; t += kBlock) s_coef[t / S][t % S] = t / S <= j ? c->coef[t % S][t / S] : 0.0;
+  __syncthreads();
+  const int sub = threadIdx.x % VM::L;
+  double acc[JM][VM::VS];
+#pragma unroll
+  for (int i = 0; i < JM; ++i)
+#pragma unroll
+    for (int v = 0; v < VM::VS; ++v) acc[i][v] = 0.0;
+  const int64_t step = (int64_t)gridDim.x * kBlock;
+  for (int64_t ch = (int64_t)blockIdx.x * kBlock + threadIdx.x; ch < nchunks; ch += step) {
+    vt wv = ((const vt*)w)[ch];
+    vt vv[JM];
+#pragma unroll
+    for (int i = 0; i < JM; ++i)
+      if (i <= j) {
+        vv[i] = ((const vt*)(V + (int64_t)i * vstride))[ch];
+#pragma unroll
+        for (int v = 0; v < VM::V; ++v) wv[v] -= s_coef[i][VM::sample(sub, v)] * vv[i][v];
+      }
+    ((vt*)w)[ch] = wv;
+#pragma unroll
+    for (int i = 0; i < JM; ++i)
+      if (i <= j)
+#pragma unroll
+        for (int v = 0; v < VM::V; ++v) acc[i][v] += vv[i][v] * wv[v];
+  }
+#pragma unroll
+  for (int g = 0; g < JM / kGmChunk; ++g) {
+    block_partials<S, VM::VS, kGmChunk, kBlock / 64>(
+        *reinterpret_cast<double(*)[kGmChunk][VM::VS]>(&acc[g * kGmChunk][0]),
+        part + (int64_t)blockIdx.x * pstride + (int64_t)g * kGmChunk * S);
+    __syncthreads();
+  }
+}
+
 // vout = w * scale (exact zeros for idle samples); then the input of the
 // preconditioner: Jacobi z = D^-1 vout, FP32 cycle z32 = (float) vout.
 template <int S, int PR>
@@ -624,21 +671,33 @@ static ens_status gmres(const ens_graph* g, const double* vals, const double* b,
                            w.w);
         prof_end(ENS_K_GM_SPMV, st, spmv_bytes);
       }
-      for (int pass = 0; pass < 2; ++pass) {
+      // classical Gram-Schmidt twice: h1 = V^T w, w -= V h1, h2 = V^T w,
+      // w -= V h2 and |w|^2; for j < 16 the middle two passes are one kernel
+      auto dots = [&]() {
         prof_begin(ENS_K_GM_ORTH, st);
         hipLaunchKernelGGL((k_gm_dots<S>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.w, w.part,
                            w.pstride);
         prof_end(ENS_K_GM_ORTH, st, vbytes * (j + 1 + (j + kGmChunk) / kGmChunk));
-        gm_reduce<S>(w, w.part, sg, (j + 1) * S, w.pstride, pass == 0 ? GM_H1 : GM_H2, j, mask, st);
-        prof_begin(ENS_K_GM_ORTH, st);
-        if (pass == 0)
-          hipLaunchKernelGGL((k_gm_axpy<S, false>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.ctl,
-                             w.w, w.part, w.pstride);
-        else
-          hipLaunchKernelGGL((k_gm_axpy<S, true>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.ctl,
-                             w.w, w.part, w.pstride);
-        prof_end(ENS_K_GM_ORTH, st, vbytes * (j + 3));
-      }
+      };
+      dots();
+      gm_reduce<S>(w, w.part, sg, (j + 1) * S, w.pstride, GM_H1, j, mask, st);
+      prof_begin(ENS_K_GM_ORTH, st);
+      if (j < 8)
+        hipLaunchKernelGGL((k_gm_axpy_dots<S, 8>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.ctl,
+                           w.w, w.part, w.pstride);
+      else if (j < 16)
+        hipLaunchKernelGGL((k_gm_axpy_dots<S, 16>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.ctl,
+                           w.w, w.part, w.pstride);
+      else
+        hipLaunchKernelGGL((k_gm_axpy<S, false>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.ctl,
+                           w.w, w.part, w.pstride);
+      prof_end(ENS_K_GM_ORTH, st, vbytes * (j + 3));
+      if (j >= 16) dots();
+      gm_reduce<S>(w, w.part, sg, (j + 1) * S, w.pstride, GM_H2, j, mask, st);
+      prof_begin(ENS_K_GM_ORTH, st);
+      hipLaunchKernelGGL((k_gm_axpy<S, true>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.ctl, w.w,
+                         w.part, w.pstride);
+      prof_end(ENS_K_GM_ORTH, st, vbytes * (j + 3));
       gm_reduce<S>(w, w.part, sg, S, w.pstride, GM_NORM, j, mask, st);
       ENS_LAUNCH_CHECK();
       steps = j + 1;
