@@ -926,8 +926,13 @@ def run_newton(args):
                    "linear_solver": f"GMRES({W.NEWTON_RESTART}) to {lin_rtol:g}, right-preconditioned by "
                                     "the multigrid V-cycle of the diffusion operator"
                                     + (" in FP32" if mg32 else " in FP64")},
+        # the fine-level FP32 cycle passes are the same launches (kernel,
+        # mesh, ensemble size) as in the headline step, whose HBM counters
+        # are on record
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic("k_mg_row<float,32,*>") if dom.startswith("k_mg_row<float,32") else None,
+                     "kernel": dom,
                      "launches": pd["launches"], "avg_launch_ms": round(pd["total_ms"] / max(pd["launches"], 1), 5),
                      "bytes_per_launch": round(pd["bytes"] / max(pd["launches"], 1))},
         "all_converged": bool(ok),
