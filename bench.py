@@ -117,6 +117,7 @@ def main():
                          "optima at 128^3, s=32)")
     ap.add_argument("--check-every", type=int, default=16)
     ap.add_argument("--lin-rtol", type=float, default=None, help="newton: GMRES tolerance per Newton step")
+    ap.add_argument("--jac-fp64", action="store_true", help="newton: keep the Jacobian in FP64 for GMRES")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (hardware-counter calibration)")
     args = ap.parse_args()
@@ -873,8 +874,9 @@ def run_newton(args):
     u = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)
     mg = ens.Multigrid(w.N, w.M, w.s, fp32=mg32, L=w.L, device=dev)
     lin_rtol = args.lin_rtol if args.lin_rtol is not None else W.NEWTON_LIN_RTOL
-    opts = ens.newton_opts(rtol=w.rtol, lin_rtol=lin_rtol, restart=W.NEWTON_RESTART)
-    ws = torch.empty(ens.newton_workspace_bytes(g, w.s, W.NEWTON_RESTART), dtype=torch.uint8, device=dev)
+    jac32 = not args.jac_fp64
+    opts = ens.newton_opts(rtol=w.rtol, lin_rtol=lin_rtol, restart=W.NEWTON_RESTART, jac32=jac32)
+    ws = torch.empty(ens.newton_workspace_bytes(g, w.s, opts), dtype=torch.uint8, device=dev)
     log(f"newton workload: N={w.N} s={w.s} workspace {ws.numel() / 2**30:.1f} GiB, "
         f"hierarchy {mg.buffer.numel() / 2**30:.2f} GiB")
 
@@ -925,7 +927,8 @@ def run_newton(args):
                    "velocity": [round(v, 6) for v in W.NEWTON_VEL], "f": w.f, "rtol": w.rtol, "seed": w.seed,
                    "linear_solver": f"GMRES({W.NEWTON_RESTART}) to {lin_rtol:g}, right-preconditioned by "
                                     "the multigrid V-cycle of the diffusion operator"
-                                    + (" in FP32" if mg32 else " in FP64")},
+                                    + (" in FP32" if mg32 else " in FP64")
+                                    + ("; Jacobian stored in FP32" if jac32 else "; Jacobian in FP64")},
         # the fine-level FP32 cycle passes are the same launches (kernel,
         # mesh, ensemble size) as in the headline step, whose HBM counters
         # are on record

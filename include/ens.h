@@ -165,14 +165,16 @@ typedef struct {
  * their values).  Boundary rows: F_i = u_i and identity rows; boundary
  * columns of interior rows are stored zeros.
  *   u       (device) [n][s] in
- *   values  (device) [nnz][s] FP64 Jacobian out; may be NULL (residual only)
+ *   values  (device) [nnz][s] FP64 Jacobian out; may be NULL
+ *   values32 (device) [nnz][s] the Jacobian rounded to FP32, out; may be
+ *           NULL (both NULL: residual only)
  *   F       (device) [n][s] out
  *   load    (device) [n][s] out, the source part sum w_q f N_a of interior
  *           rows (zero on the boundary, so F(0) = -load); may be NULL
  * Other arguments as for ens_assemble.  Never synchronises. */
 ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const void* kl, const ens_nl_problem* problem,
-                           int32_t s, const double* xi, const double* u, double* values, double* F, double* load,
-                           hipStream_t stream);
+                           int32_t s, const double* xi, const double* u, double* values, float* values32, double* F,
+                           double* load, hipStream_t stream);
 
 /* ----------------------------------------------------------------- SpMV */
 
@@ -410,6 +412,9 @@ typedef struct {
   double lin_rtol;
   int32_t restart;       /* GMRES restart length, 1..32 */
   int32_t lin_max_iter;  /* GMRES iterations per Newton step */
+  int32_t jac32;         /* 1: the Newton systems use the Jacobian rounded to
+                            FP32 (read and widened by the FP64 GMRES); F, the
+                            step and u stay FP64 and the FP64 |F| decides */
 } ens_newton_opts;
 
 typedef struct {
@@ -420,7 +425,8 @@ typedef struct {
   double rel_res;        /* |F(u)| / |load| at exit */
 } ens_newton_stat;
 
-ens_status ens_newton_workspace_bytes(const ens_graph* graph, int32_t s, int32_t restart, size_t* bytes);
+ens_status ens_newton_workspace_bytes(const ens_graph* graph, int32_t s, const ens_newton_opts* opts,
+                                      size_t* bytes);
 /* u [n][s] (device, in: initial guess, out: solution); xi [s][M] (device);
  * kl from ens_kl_build(N, problem->M, problem->L); mg / mg_values as for
  * ens_gmres (NULL: Jacobi).  The workspace holds the Jacobian, F, the load,

@@ -245,7 +245,8 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
                                                       double vy, double vz, const double* __restrict__ xi,
                                                       const int32_t* __restrict__ row_ptr,
                                                       const double* __restrict__ u, double* __restrict__ values,
-                                                      double* __restrict__ F, double* __restrict__ load) {
+                                                      float* __restrict__ values32, double* __restrict__ F,
+                                                      double* __restrict__ load) {
   constexpr int RPB = 256 / S;
   __shared__ double s_cm[S * kAsmMaxM];
   __shared__ double s_adv[8][8];  // C_ab = sum_q N_a (v . dN_b)
@@ -345,7 +346,8 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
           const bool bnd_col = (x == 0 || x == N || y == 0 || y == N || z == 0 || z == N);
           if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
           else if (bnd_col) v = 0.0;
-          values[(start + pos) * S + e] = v;
+          if (values) values[(start + pos) * S + e] = v;
+          if (values32) values32[(start + pos) * S + e] = (float)v;
           ++pos;
         }
   }
@@ -415,7 +417,8 @@ extern "C" ens_status ens_assemble(int32_t N, const ens_graph* graph, const void
 
 extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const void* kl,
                                       const ens_nl_problem* prob, int32_t s, const double* xi, const double* u,
-                                      double* values, double* F, double* load, hipStream_t stream) {
+                                      double* values, float* values32, double* F, double* load,
+                                      hipStream_t stream) {
   int64_t n = 0, nnz = 0;
   ens_status st = ens_mesh_sizes(N, &n, &nnz, nullptr);
   if (st != ENS_OK) return st;
@@ -450,14 +453,14 @@ extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const v
 #define ENS_NL_LAUNCH(SS, LL, JJ)                                                                                \
   hipLaunchKernelGGL((k_nl_assemble<SS, LL, JJ>), dim3((unsigned)blocks), dim3(256), LL ? lds_bytes : 0, stream, N, \
                      sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, prob->alpha, prob->beta, prob->vx,         \
-                     prob->vy, prob->vz, xi, graph->row_ptr, u, values, F, load)
+                     prob->vy, prob->vz, xi, graph->row_ptr, u, values, values32, F, load)
 #define ENS_NL_CASE(SS)                                                     \
   case SS:                                                                  \
     if (lds_bytes) {                                                        \
-      if (values) ENS_NL_LAUNCH(SS, 1, true);                               \
+      if (values || values32) ENS_NL_LAUNCH(SS, 1, true);                   \
       else ENS_NL_LAUNCH(SS, 1, false);                                     \
     } else {                                                                \
-      if (values) ENS_NL_LAUNCH(SS, 0, true);                               \
+      if (values || values32) ENS_NL_LAUNCH(SS, 0, true);                   \
       else ENS_NL_LAUNCH(SS, 0, false);                                     \
     }                                                                       \
     break;
@@ -469,8 +472,8 @@ extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const v
 #undef ENS_NL_LAUNCH
   }
   ENS_LAUNCH_CHECK();
-  const double bytes = (values ? (double)nnz * s * 8.0 : 0.0) + (double)n * s * 8.0 * (load ? 3.0 : 2.0) +
-                       4.0 * (n + 1);
+  const double bytes = (values ? (double)nnz * s * 8.0 : 0.0) + (values32 ? (double)nnz * s * 4.0 : 0.0) +
+                       (double)n * s * 8.0 * (load ? 3.0 : 2.0) + 4.0 * (n + 1);
   prof_end(ENS_K_NL_ASSEMBLE, stream, bytes);
   return ENS_OK;
 }

@@ -246,43 +246,25 @@ static __global__ void k_gm_solve(GmCtl* c) {
 
 // --------------------------------------------------------- vector kernels ---
 
-template <int S>
-static __global__ __launch_bounds__(kBlock) void k_gm_spmv(int n, const int32_t* __restrict__ rp,
-                                                           const int32_t* __restrict__ ci,
-                                                           const double* __restrict__ vals,
-                                                           const double* __restrict__ z, double* __restrict__ w) {
-  using M = EnsMap<double, S>;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sub = lane % M::L;
-  const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
-  if (row >= n) return;
-  typename M::vt acc = ens_row_product<double, S>(ci, vals, z, rp[row], rp[row + 1], sub);
-  ((typename M::vt*)w)[row * M::L + sub] = acc;
-}
-
-// w = A z with an FP32 z (the output of an FP32 cycle) widened to FP64 as
-// it is gathered; products and sums in FP64.
-template <int S>
-static __global__ __launch_bounds__(kBlock) void k_gm_spmv_z32(int n, const int32_t* __restrict__ rp,
-                                                               const int32_t* __restrict__ ci,
-                                                               const double* __restrict__ vals,
-                                                               const float* __restrict__ z, double* __restrict__ w) {
+// sum_k vals[k] z[col k] for the two samples of lane `sub`, the values (TV)
+// and z (TZ) widened to FP64 as they are read; entries in ascending order.
+template <int S, typename TV, typename TZ>
+__device__ inline typename EnsMap<double, S>::vt gm_row_product(const int32_t* __restrict__ ci,
+                                                                const TV* __restrict__ vals,
+                                                                const TZ* __restrict__ z, int64_t k0, int64_t k1,
+                                                                int sub) {
   using M = EnsMap<double, S>;
   using vt = typename M::vt;
-  typedef typename vec_t<float, M::V>::type ft;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sub = lane % M::L;
-  const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
-  if (row >= n) return;
-  const vt* vv = (const vt*)vals + sub;
-  const ft* zv = (const ft*)z + sub;
+  typedef typename vec_t<TV, M::V>::type at;
+  typedef typename vec_t<TZ, M::V>::type zt;
+  const at* vv = (const at*)vals + sub;
+  const zt* zv = (const zt*)z + sub;
   vt acc = (vt)0.0;
-  const int64_t k1 = rp[row + 1];
-  int64_t k = rp[row];
+  int64_t k = k0;
   for (; k + 2 < k1; k += 3) {
     int32_t c3[3];
-    vt a[3];
-    ft b[3];
+    at a[3];
+    zt b[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) c3[j] = ci[k + j];
 #pragma unroll
@@ -292,15 +274,75 @@ static __global__ __launch_bounds__(kBlock) void k_gm_spmv_z32(int n, const int3
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-      for (int v = 0; v < M::V; ++v) acc[v] += a[j][v] * (double)b[j][v];
+      for (int v = 0; v < M::V; ++v) acc[v] += (double)a[j][v] * (double)b[j][v];
   }
   for (; k < k1; ++k) {
-    const vt a = load_stream(vv + k * M::L);
-    const ft b = zv[(int64_t)ci[k] * M::L];
+    const at a = load_stream(vv + k * M::L);
+    const zt b = zv[(int64_t)ci[k] * M::L];
 #pragma unroll
-    for (int v = 0; v < M::V; ++v) acc[v] += a[v] * (double)b[v];
+    for (int v = 0; v < M::V; ++v) acc[v] += (double)a[v] * (double)b[v];
   }
-  ((vt*)w)[row * M::L + sub] = acc;
+  return acc;
+}
+
+// w = A z: the matrix in FP64 or FP32 (TV), z in FP64 or, from an FP32
+// cycle, FP32 (TZ); products and sums in FP64.
+template <int S, typename TV, typename TZ>
+static __global__ __launch_bounds__(kBlock) void k_gm_spmv(int n, const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const TV* __restrict__ vals, const TZ* __restrict__ z,
+                                                           double* __restrict__ w) {
+  using M = EnsMap<double, S>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane % M::L;
+  const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
+  if (row >= n) return;
+  ((typename M::vt*)w)[row * M::L + sub] = gm_row_product<S, TV, TZ>(ci, vals, z, rp[row], rp[row + 1], sub);
+}
+
+// w = A z for an FP32 matrix with the FP32 row mapping: each lane reads 16
+// bytes (4 samples) of the value stream, gathers those samples of z (FP64
+// or FP32) and accumulates in FP64.
+template <int S, typename TZ>
+static __global__ __launch_bounds__(kBlock) void k_gm_spmv_v32(int n, const int32_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ ci,
+                                                               const float* __restrict__ vals,
+                                                               const TZ* __restrict__ z, double* __restrict__ w) {
+  using M = EnsMap<float, S>;  // V = 4 samples per lane
+  typedef typename vec_t<float, 4>::type f4;
+  typedef typename vec_t<TZ, 4>::type z4;
+  typedef typename vec_t<double, 4>::type d4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane % M::L;
+  const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
+  if (row >= n) return;
+  const f4* vv = (const f4*)vals + sub;
+  const TZ* zs = z + sub * 4;
+  d4 acc = (d4)0.0;
+  const int64_t k1 = rp[row + 1];
+  int64_t k = rp[row];
+  for (; k + 2 < k1; k += 3) {
+    int32_t c3[3];
+    f4 a[3];
+    z4 b[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c3[j] = ci[k + j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a[j] = load_stream(vv + (k + j) * M::L);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) b[j] = *(const z4*)(zs + (int64_t)c3[j] * S);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] += (double)a[j][v] * (double)b[j][v];
+  }
+  for (; k < k1; ++k) {
+    const f4 a = load_stream(vv + k * M::L);
+    const z4 b = *(const z4*)(zs + (int64_t)ci[k] * S);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] += (double)a[v] * (double)b[v];
+  }
+  *(d4*)(w + row * S + sub * 4) = acc;
 }
 
 // part[blk][i*S + e] = sum over the block's chunks of V_i . w, i = 0..j.
@@ -510,22 +552,50 @@ static __global__ __launch_bounds__(kBlock) void k_gm_zero_x(int64_t total, cons
   if (i < total && c->zx[i % S]) x[i] = 0.0;
 }
 
-template <int S>
+// r = b - A x (matrix in FP64 or FP32, widened) for the row tile, with the
+// block's partials |r|^2 and |b|^2.
+template <int S, typename TV>
 static __global__ __launch_bounds__(kBlock) void k_gm_residual(int n, const int32_t* __restrict__ rp,
                                                                const int32_t* __restrict__ ci,
-                                                               const double* __restrict__ vals,
+                                                               const TV* __restrict__ vals,
                                                                const double* __restrict__ x,
                                                                const double* __restrict__ b, double* __restrict__ r,
                                                                double* __restrict__ part) {
-  residual_body<S, double, kBlock / 64>(n, rp, ci, vals, x, b, r, blockIdx.x, part + (int64_t)blockIdx.x * 2 * S);
+  using M = EnsMap<double, S>;
+  using vt = typename M::vt;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane % M::L;
+  double acc[2][M::V];
+#pragma unroll
+  for (int v = 0; v < M::V; ++v) acc[0][v] = acc[1][v] = 0.0;
+  const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
+  if (row < n) {
+    const vt ax = gm_row_product<S, TV, double>(ci, vals, x, rp[row], rp[row + 1], sub);
+    const vt bv = ((const vt*)b)[row * M::L + sub];
+    const vt rv = bv - ax;
+    ((vt*)r)[row * M::L + sub] = rv;
+#pragma unroll
+    for (int v = 0; v < M::V; ++v) {
+      acc[0][v] = rv[v] * rv[v];
+      acc[1][v] = bv[v] * bv[v];
+    }
+  }
+  block_partials<S, M::V, 2, kBlock / 64>(acc, part + (int64_t)blockIdx.x * 2 * S);
 }
 
-template <int S>
+// dinv[i][e] = 1 / A_ii[e] in FP64 (the diagonal widened from TV).
+template <int S, typename TV>
 static __global__ __launch_bounds__(kBlock) void k_gm_dinv(int n, const int32_t* __restrict__ rp,
                                                            const int32_t* __restrict__ ci,
-                                                           const double* __restrict__ vals,
-                                                           double* __restrict__ dinv) {
-  diag_inv_body<double, S>(n, rp, ci, vals, dinv, blockIdx.x);
+                                                           const TV* __restrict__ vals, double* __restrict__ dinv) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t row = t / S;
+  const int e = (int)(t % S);
+  if (row >= n) return;
+  double d = 0.0;
+  for (int64_t k = rp[row]; k < rp[row + 1]; ++k)
+    if (ci[k] == row) d = (double)vals[k * S + e];
+  dinv[row * S + e] = 1.0 / d;
 }
 
 // ------------------------------------------------------------ host side ---
@@ -616,8 +686,8 @@ static ens_status read_flag(const int32_t* dev, hipStream_t st, int32_t* out) {
 // GMRES on (graph, vals) for all samples; x in/out.  plan != nullptr:
 // multigrid preconditioner, else Jacobi.  mask (device, nullable): samples
 // that take part.
-template <int S>
-static ens_status gmres(const ens_graph* g, const double* vals, const double* b, double* x, double rtol, int restart,
+template <int S, typename TV>
+static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, double* x, double rtol, int restart,
                         int max_iter, const MgPlan* plan, const GmWork& w, const int32_t* mask, hipStream_t st) {
   const int n = g->n;
   const int64_t nchunks = (int64_t)n * S / VecMap<double, S>::V;
@@ -627,12 +697,12 @@ static ens_status gmres(const ens_graph* g, const double* vals, const double* b,
   const unsigned sb = grid_of(n, (kBlock / 64) * EnsMap<double, S>::RPW);
   const bool jac = plan == nullptr;
   const bool f32 = plan != nullptr && plan->fp32;
-  const double spmv_bytes = (double)g->nnz * (S * 8.0 + 4.0) + 4.0 * (n + 1) + 2.0 * n * S * 8.0;
+  const double spmv_bytes = (double)g->nnz * (S * (double)sizeof(TV) + 4.0) + 4.0 * (n + 1) + 2.0 * n * S * 8.0;
   const double vbytes = (double)n * S * 8.0;
   hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, st, w.ctl, rtol, restart, max_iter);
-  if (jac) hipLaunchKernelGGL((k_gm_dinv<S>), dim3(grid_of((int64_t)n * S, kBlock)), dim3(kBlock), 0, st, n,
+  if (jac) hipLaunchKernelGGL((k_gm_dinv<S, TV>), dim3(grid_of((int64_t)n * S, kBlock)), dim3(kBlock), 0, st, n,
                               g->row_ptr, g->col_idx, vals, w.dinv);
-  hipLaunchKernelGGL((k_gm_residual<S>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b, w.w,
+  hipLaunchKernelGGL((k_gm_residual<S, TV>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b, w.w,
                      w.rpart);
   gm_reduce<S>(w, w.rpart, rb, 2 * S, 2 * S, GM_START, 0, mask, st);
   hipLaunchKernelGGL((k_gm_zero_x<S>), dim3(grid_of((int64_t)n * S, kBlock)), dim3(kBlock), 0, st, (int64_t)n * S,
@@ -658,19 +728,26 @@ static ens_status gmres(const ens_graph* g, const double* vals, const double* b,
     int steps = 0;
     for (int j = 0; j < restart; ++j) {
       double* vj = w.V + (int64_t)j * vstride;
-      if (f32) {
-        mg_vcycle<float, S>(*plan, w.r32, w.z32, nullptr, st);
-        prof_begin(ENS_K_GM_SPMV, st);
-        hipLaunchKernelGGL((k_gm_spmv_z32<S>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals,
-                           w.z32, w.w);
-        prof_end(ENS_K_GM_SPMV, st, spmv_bytes - 4.0 * n * S);
+      if (f32) mg_vcycle<float, S>(*plan, w.r32, w.z32, nullptr, st);
+      else if (!jac) mg_vcycle<double, S>(*plan, vj, w.z, nullptr, st);
+      prof_begin(ENS_K_GM_SPMV, st);
+      if (sizeof(TV) == 4) {
+        const unsigned sb32 = grid_of(n, (kBlock / 64) * EnsMap<float, S>::RPW);
+        if (f32)
+          hipLaunchKernelGGL((k_gm_spmv_v32<S, float>), dim3(sb32), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx,
+                             (const float*)vals, w.z32, w.w);
+        else
+          hipLaunchKernelGGL((k_gm_spmv_v32<S, double>), dim3(sb32), dim3(kBlock), 0, st, n, g->row_ptr,
+                             g->col_idx, (const float*)vals, (const double*)w.z, w.w);
       } else {
-        if (!jac) mg_vcycle<double, S>(*plan, vj, w.z, nullptr, st);
-        prof_begin(ENS_K_GM_SPMV, st);
-        hipLaunchKernelGGL((k_gm_spmv<S>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, w.z,
-                           w.w);
-        prof_end(ENS_K_GM_SPMV, st, spmv_bytes);
+        if (f32)
+          hipLaunchKernelGGL((k_gm_spmv<S, TV, float>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx,
+                             vals, w.z32, w.w);
+        else
+          hipLaunchKernelGGL((k_gm_spmv<S, TV, double>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx,
+                             vals, w.z, w.w);
       }
+      prof_end(ENS_K_GM_SPMV, st, spmv_bytes - (f32 ? 4.0 * n * S : 0.0));
       // classical Gram-Schmidt twice: h1 = V^T w, w -= V h1, h2 = V^T w,
       // w -= V h2 and |w|^2; for j < 16 the middle two passes are one kernel
       auto dots = [&]() {
@@ -726,7 +803,7 @@ static ens_status gmres(const ens_graph* g, const double* vals, const double* b,
       hipLaunchKernelGGL((k_gm_addto<S, PR_MG64>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.z,
                          (const float*)nullptr, (const double*)nullptr, w.ctl, x);
     }
-    hipLaunchKernelGGL((k_gm_residual<S>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b,
+    hipLaunchKernelGGL((k_gm_residual<S, TV>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b,
                        w.w, w.rpart);
     gm_reduce<S>(w, w.rpart, rb, 2 * S, 2 * S, GM_START, 1, mask, st);
     ENS_LAUNCH_CHECK();
@@ -840,11 +917,12 @@ static __global__ void k_fill_zero64(int64_t total, double* __restrict__ x) {
 
 struct NtWork {
   NtCtl* ctl;
-  double *J, *F, *load, *d, *npart;
+  void* J;  // Jacobian values, FP64 or (jac32) FP32
+  double *F, *load, *d, *npart;
   GmWork gm;
 };
 
-static size_t nt_layout(int64_t n, int64_t nnz, int S, int restart, NtWork* w, char* base) {
+static size_t nt_layout(int64_t n, int64_t nnz, int S, int restart, bool jac32, NtWork* w, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -852,7 +930,7 @@ static size_t nt_layout(int64_t n, int64_t nnz, int S, int restart, NtWork* w, c
     return p;
   };
   NtCtl* ctl = (NtCtl*)take(sizeof(NtCtl));
-  double* J = (double*)take((size_t)nnz * S * sizeof(double));
+  void* J = take((size_t)nnz * S * (jac32 ? sizeof(float) : sizeof(double)));
   const size_t vb = (size_t)n * S * sizeof(double);
   double* F = (double*)take(vb);
   double* load = (double*)take(vb);
@@ -875,7 +953,8 @@ static ens_status newton(int N, const ens_graph* g, const void* kl, const ens_nl
   hipLaunchKernelGGL(k_nt_init, dim3(1), dim3(64), 0, st, w.ctl, o.rtol, o.max_newton);
   ENS_LAUNCH_CHECK();
   for (int k = 0;; ++k) {
-    ens_status rc = ens_nl_assemble(N, g, kl, prob, S, xi, u, w.J, w.F, k == 0 ? w.load : nullptr, st);
+    ens_status rc = ens_nl_assemble(N, g, kl, prob, S, xi, u, o.jac32 ? nullptr : (double*)w.J,
+                                    o.jac32 ? (float*)w.J : nullptr, w.F, k == 0 ? w.load : nullptr, st);
     if (rc != ENS_OK) return rc;
     hipLaunchKernelGGL((k_nt_norms<S>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.F,
                        k == 0 ? (const double*)w.load : (const double*)nullptr, w.npart, (int64_t)2 * S);
@@ -887,7 +966,12 @@ static ens_status newton(int N, const ens_graph* g, const void* kl, const ens_nl
     if (rc != ENS_OK) return rc;
     if (na == 0) break;
     hipLaunchKernelGGL(k_fill_zero64, dim3(grid_of(total, kBlock)), dim3(kBlock), 0, st, total, w.d);
-    rc = gmres<S>(g, w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm, w.ctl->active, st);
+    if (o.jac32)
+      rc = gmres<S, float>(g, (const float*)w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm,
+                           w.ctl->active, st);
+    else
+      rc = gmres<S, double>(g, (const double*)w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm,
+                            w.ctl->active, st);
     if (rc != ENS_OK) return rc;
     hipLaunchKernelGGL((k_nt_after<S>), dim3(1), dim3(64), 0, st, w.ctl, (const GmCtl*)w.gm.ctl);
     hipLaunchKernelGGL((k_nt_update<S>), dim3(grid_of(total, kBlock)), dim3(kBlock), 0, st, total, w.ctl, w.d, u);
@@ -979,8 +1063,8 @@ ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, co
   switch (s) {
 #define ENS_GM_CASE(SS)                                                                                       \
   case SS:                                                                                                    \
-    st = gmres<SS>(graph, values, b, x, opts->rtol, opts->restart, opts->max_iter, mg ? &plan : nullptr, w,   \
-                   nullptr, stream);                                                                          \
+    st = gmres<SS, double>(graph, values, b, x, opts->rtol, opts->restart, opts->max_iter, mg ? &plan : nullptr, \
+                           w, nullptr, stream);                                                               \
     break;
     ENS_GM_CASE(4)
     ENS_GM_CASE(8)
@@ -1015,16 +1099,17 @@ ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, co
   return rc;
 }
 
-ens_status ens_newton_workspace_bytes(const ens_graph* graph, int32_t s, int32_t restart, size_t* bytes) {
+ens_status ens_newton_workspace_bytes(const ens_graph* graph, int32_t s, const ens_newton_opts* opts,
+                                      size_t* bytes) {
   ens_status st = check_graph_nl(graph);
   if (st != ENS_OK) return st;
-  ENS_ARG_CHECK(bytes, "null output");
-  ENS_ARG_CHECK(restart >= 1 && restart <= kGmMaxRestart, "restart must be in 1..32");
+  ENS_ARG_CHECK(bytes && opts, "null output or options");
+  ENS_ARG_CHECK(opts->restart >= 1 && opts->restart <= kGmMaxRestart, "restart must be in 1..32");
   if (!supported_s(s)) {
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
   }
-  *bytes = nt_layout(graph->n, graph->nnz, s, restart, nullptr, nullptr);
+  *bytes = nt_layout(graph->n, graph->nnz, s, opts->restart, opts->jac32 != 0, nullptr, nullptr);
   return ENS_OK;
 }
 
@@ -1046,7 +1131,7 @@ ens_status ens_newton(int32_t N, const ens_graph* graph, const void* kl, const e
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
   }
-  const size_t need = nt_layout(graph->n, graph->nnz, s, opts->restart, nullptr, nullptr);
+  const size_t need = nt_layout(graph->n, graph->nnz, s, opts->restart, opts->jac32 != 0, nullptr, nullptr);
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     return ENS_E_NOMEM;
@@ -1058,7 +1143,7 @@ ens_status ens_newton(int32_t N, const ens_graph* graph, const void* kl, const e
     if (st != ENS_OK) return st;
   }
   NtWork w;
-  nt_layout(graph->n, graph->nnz, s, opts->restart, &w, (char*)workspace);
+  nt_layout(graph->n, graph->nnz, s, opts->restart, opts->jac32 != 0, &w, (char*)workspace);
   switch (s) {
 #define ENS_NT_CASE(SS)                                                                           \
   case SS:                                                                                        \

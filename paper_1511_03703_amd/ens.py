@@ -72,7 +72,7 @@ class ens_gmres_opts(ctypes.Structure):
 
 class ens_newton_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_newton", ctypes.c_int32), ("lin_rtol", ctypes.c_double),
-                ("restart", ctypes.c_int32), ("lin_max_iter", ctypes.c_int32)]
+                ("restart", ctypes.c_int32), ("lin_max_iter", ctypes.c_int32), ("jac32", ctypes.c_int32)]
 
 
 class ens_newton_stat(ctypes.Structure):
@@ -103,11 +103,11 @@ _SIGS = [
     ("ens_kl_bytes", _I32, [_I32, _I32, ctypes.POINTER(_SZ)]),
     ("ens_kl_build", _I32, [_I32, _I32, _D, _P, _P]),
     ("ens_assemble", _I32, [_I32, _GP, _P, ctypes.POINTER(ens_problem), _I32, _P, _P, _P, _P, _P]),
-    ("ens_nl_assemble", _I32, [_I32, _GP, _P, ctypes.POINTER(ens_nl_problem), _I32, _P, _P, _P, _P, _P, _P]),
+    ("ens_nl_assemble", _I32, [_I32, _GP, _P, ctypes.POINTER(ens_nl_problem), _I32, _P, _P, _P, _P, _P, _P, _P]),
     ("ens_gmres_workspace_bytes", _I32, [_GP, _I32, _I32, ctypes.POINTER(_SZ)]),
     ("ens_gmres", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_gmres_opts), ctypes.POINTER(ens_mg), _P, _P, _SZ,
                          ctypes.POINTER(ens_cg_stat), _P]),
-    ("ens_newton_workspace_bytes", _I32, [_GP, _I32, _I32, ctypes.POINTER(_SZ)]),
+    ("ens_newton_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(ens_newton_opts), ctypes.POINTER(_SZ)]),
     ("ens_newton", _I32, [_I32, _GP, _P, ctypes.POINTER(ens_nl_problem), _I32, _P, _P, ctypes.POINTER(ens_newton_opts),
                           ctypes.POINTER(ens_mg), _P, _P, _SZ, ctypes.POINTER(ens_newton_stat), _P]),
     ("ens_spmv", _I32, [_GP, _I32, _I32, _P, _P, _P, _P]),
@@ -282,22 +282,27 @@ def nl_problem(M: int, sigma: float, alpha: float, beta: float, vel=DEFAULT_VEL,
 
 
 def nl_assemble(g: Graph, kl: torch.Tensor, xi: torch.Tensor, prob: ens_nl_problem, u: torch.Tensor,
-                want_jac=True, want_load=False, values=None, F=None, load=None, stream=None):
+                want_jac=True, want_load=False, want_jac32=False, values=None, values32=None, F=None, load=None,
+                stream=None):
     """Residual F [n][s], Jacobian values [nnz][s] (or None) and load [n][s]
-    (or None) of the nonlinear problem at u [n][s]."""
+    (or None) of the nonlinear problem at u [n][s]; with want_jac32 the
+    FP32 Jacobian is returned too: (F, values, load, values32)."""
     s = xi.shape[0]
     dev = u.device
     if want_jac and values is None:
         values = torch.empty((g.nnz, s), dtype=torch.float64, device=dev)
+    if want_jac32 and values32 is None:
+        values32 = torch.empty((g.nnz, s), dtype=torch.float32, device=dev)
     if F is None:
         F = torch.empty((g.n, s), dtype=torch.float64, device=dev)
     if want_load and load is None:
         load = torch.empty((g.n, s), dtype=torch.float64, device=dev)
     gc = g.c()
     _check(lib().ens_nl_assemble(g.N, ctypes.byref(gc), _ptr(kl), ctypes.byref(prob), s, _ptr(xi), _ptr(u),
-                                 _ptr(values if want_jac else None), _ptr(F), _ptr(load if want_load else None),
-                                 _stream(stream)), "ens_nl_assemble")
-    return F, (values if want_jac else None), (load if want_load else None)
+                                 _ptr(values if want_jac else None), _ptr(values32 if want_jac32 else None), _ptr(F),
+                                 _ptr(load if want_load else None), _stream(stream)), "ens_nl_assemble")
+    out = (F, (values if want_jac else None), (load if want_load else None))
+    return out + (values32,) if want_jac32 else out
 
 
 def gmres_opts(rtol=1e-10, restart=30, max_iter=1000) -> ens_gmres_opts:
@@ -333,13 +338,14 @@ def gmres(g: Graph, values, b, x=None, opts: ens_gmres_opts | None = None, mg=No
     return x, _stats_list(stats, s), st
 
 
-def newton_opts(rtol=1e-8, max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000) -> ens_newton_opts:
-    return ens_newton_opts(rtol, max_newton, lin_rtol, restart, lin_max_iter)
+def newton_opts(rtol=1e-8, max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000,
+                jac32=False) -> ens_newton_opts:
+    return ens_newton_opts(rtol, max_newton, lin_rtol, restart, lin_max_iter, int(jac32))
 
 
-def newton_workspace_bytes(g: Graph, s: int, restart: int) -> int:
+def newton_workspace_bytes(g: Graph, s: int, opts: ens_newton_opts) -> int:
     nb = _SZ()
-    _check(lib().ens_newton_workspace_bytes(ctypes.byref(g.c()), s, restart, ctypes.byref(nb)),
+    _check(lib().ens_newton_workspace_bytes(ctypes.byref(g.c()), s, ctypes.byref(opts), ctypes.byref(nb)),
            "ens_newton_workspace_bytes")
     return nb.value
 
@@ -354,7 +360,7 @@ def newton(g: Graph, kl: torch.Tensor, xi: torch.Tensor, prob: ens_nl_problem, u
         opts = newton_opts()
     if u is None:
         u = torch.zeros((g.n, s), dtype=torch.float64, device=xi.device)
-    nbytes = newton_workspace_bytes(g, s, opts.restart)
+    nbytes = newton_workspace_bytes(g, s, opts)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=xi.device)
     stats = (ens_newton_stat * s)()

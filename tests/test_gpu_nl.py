@@ -60,10 +60,14 @@ def test_nl_assembly_matches_oracle(E, orc, N, s, M):
     # boundary rows: F = u exactly, identity rows
     bnd = _boundary(N)
     assert np.array_equal(_np(F)[bnd], u[bnd])
-    # residual only (no Jacobian) gives the same F
+    # residual only (no Jacobian) gives the same F; the FP32 Jacobian is the
+    # FP64 one rounded to nearest
     F2, J2, _ = E.nl_assemble(g, kl, torch.as_tensor(xi, device=DEV), prob, torch.as_tensor(u, device=DEV),
                               want_jac=False)
     assert J2 is None and torch.equal(F2, F)
+    F3, _, _, J32 = E.nl_assemble(g, kl, torch.as_tensor(xi, device=DEV), prob, torch.as_tensor(u, device=DEV),
+                                  want_jac=False, want_jac32=True)
+    assert torch.equal(F3, F) and torch.equal(J32, J.to(torch.float32))
 
 
 def _nl_system(E, orc, N, s, M, seed, alpha=5.0, beta=30.0, sigma=0.3):
@@ -231,6 +235,39 @@ def test_newton_with_an_fp32_cycle(E, orc):
                                          prec=orc.PREC_MG, rtol=rtol)
     ut, _, _, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi,
                                        prec=orc.PREC_MG, rtol=1e-13, lin_rtol=1e-12)
+    ug = _np(u)
+    rp, ci = orc.graph(N)
+    Fg, _, ld = orc.ens_nl_assemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, ug,
+                                    want_jac=False)
+    for e in range(s):
+        assert stats[e]["status"] == 0
+        assert abs(stats[e]["newton_iters"] - int(nio[e])) <= 1
+        assert np.linalg.norm(Fg[:, e]) <= rtol * np.linalg.norm(ld[:, e]) * (1 + 1e-6)
+        assert _rel(ug[:, e], ut[:, e]) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["jacobi", "mg32"])
+def test_newton_with_an_fp32_jacobian(E, orc, prec):
+    # the Newton systems on the Jacobian rounded to FP32: F, the step and u
+    # stay FP64, so the root and the stopping rule are those of the oracle
+    N, s, M, sigma, alpha, beta, rtol = 12, 16, 10, 0.3, 10.0, 100.0, 1e-8
+    xi = draw_xi(4660, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    mg, K32 = None, None
+    if prec == "mg32":
+        K, K32, _ = E.assemble(g, kl, xt, M, sigma, want32=True)
+        mg = E.Multigrid(N, M, s, fp32=True).setup(g, K, xt, sigma, values32=K32)
+    prob = E.nl_problem(M, sigma, alpha, beta, VEL)
+    u, stats, st = E.newton(g, kl, xt, prob, opts=E.newton_opts(rtol=rtol, lin_rtol=3e-3, jac32=True), mg=mg,
+                            mg_values=K32)
+    assert st == E.ENS_OK, stats
+    pc = orc.PREC_JACOBI if prec == "jacobi" else orc.PREC_MG
+    _, nio, _, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, prec=pc,
+                                        rtol=rtol, lin_rtol=3e-3)
+    ut, _, _, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, prec=pc,
+                                       rtol=1e-13, lin_rtol=1e-12)
     ug = _np(u)
     rp, ci = orc.graph(N)
     Fg, _, ld = orc.ens_nl_assemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, ug,
