@@ -2,21 +2,21 @@
 //
 // Alg. "assembly" (Sec. 4) loops over cells and scatters each element matrix
 // into the global matrix with atomic adds.  Here the loop is turned inside
-// out: a group of s lanes owns one matrix row (one node), and lane e owns
-// sample e of that row.  The lane visits the (up to 8) elements around the
-// node in ascending element id, evaluates the coefficient of its sample at
-// the element's 8 Gauss points, and adds the element row K_e[a_i][.] into a
-// 27-entry register row.  No atomics are needed, each entry is
-// 0 + K_e1 + K_e2 + ... in ascending element order, and since every K_e is
-// formed from a symmetric table with the same operations for (a,b) and (b,a)
-// the assembled matrix is bitwise symmetric.  The writes of a row are
-// s-contiguous ([nnz][s]) and coalesced across the lane group.
+// out: a lane owns one matrix row (one node) of one sample, visits the (up
+// to 8) elements around the node in ascending element id and adds the
+// element row K_e[a_i][.] into a 27-entry register row.  No atomics are
+// needed, each entry is 0 + K_e1 + K_e2 + ... in ascending element order,
+// and since every K_e is formed from a symmetric table with the same
+// operations for (a,b) and (b,a) the assembled matrix is bitwise symmetric.
+// The coefficient at each element's Gauss points is evaluated once per
+// workgroup tile into LDS (k_assemble_tile).  The writes of a row are
+// sample-contiguous ([nnz][s]).
 //
 // Element matrix on the uniform mesh (h = 1/N, 2x2x2 Gauss, weight h^3/8):
 //   K_e[a][b] = sum_q kappa_q (h/8) G_q[a][b],
 //   G_q[a][b] = grad_ref N_a(g_q) . grad_ref N_b(g_q)       (dimensionless)
 // kappa_q = kappa0 + sigma sum_m sqrt(lambda_m) phi_m(x_q) y_m, with the 1D
-// factors of phi_m read from the KL table (staged in LDS when it fits).
+// factors of phi_m read from the KL table.
 #include "common.hpp"
 
 namespace ens {
@@ -115,46 +115,85 @@ __device__ inline void kl_points(const double* __restrict__ tab, const int32_t* 
   for (int q = 0; q < 8; ++q) kq[q] = kappa0 + kq[q];
 }
 
-// LDS: the 1D eigenfunction table (M x 2N doubles) is staged in LDS when it
-// fits (dynamic shared memory of the launch); otherwise it is read from the
-// cached global table.
-template <int S, int LDS>
-__global__ __launch_bounds__(256) void k_assemble(int N, const double* __restrict__ kl_sqrt_lam,
-                                                   const int32_t* __restrict__ kl_triple,
-                                                   const double* __restrict__ kl_phi, int M, double kappa0,
-                                                   double sigma, double fsrc, const double* __restrict__ xi,
-                                                   const int32_t* __restrict__ row_ptr,
-                                                   double* __restrict__ values, float* __restrict__ values32,
-                                                   double* __restrict__ rhs) {
-  constexpr int RPB = 256 / S;  // rows per block
-  // sigma sqrt(lambda_m) y_m of every sample of the block, [e][m]
-  __shared__ double s_cm[S * kAsmMaxM];
-  extern __shared__ double s_phi[];
-  for (int t = threadIdx.x; t < S * M; t += blockDim.x) {
-    const int ee = t / M, m = t % M;
-    s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)ee * M + m];
-  }
-  if (LDS)
-    for (int t = threadIdx.x; t < M * 2 * N; t += blockDim.x) s_phi[t] = kl_phi[t];
-  __syncthreads();
-  const double* tab = LDS ? s_phi : kl_phi;
-
+// Tiled form of the same assembly: a workgroup owns a TX x TZ patch of
+// nodes in one y-plane for SB of the samples.  It first evaluates the
+// coefficient (times h/8) at the 8 Gauss points of each of the
+// (TX+1) x 2 x (TZ+1) elements touching the patch, once per element and
+// sample, into LDS; then each (row, sample) lane gathers its (up to 8)
+// elements from LDS in ascending element id and adds the element rows
+// exactly as k_assemble does, so the result is bitwise the same while the
+// coefficient is evaluated about a third as often.  LDS rows are padded to
+// SB+1 samples so that neighbouring rows of a wavefront read alternate bank
+// halves.
+template <int S, int SB>
+__global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __restrict__ kl_sqrt_lam,
+                                                        const int32_t* __restrict__ kl_triple,
+                                                        const double* __restrict__ kl_phi, int M, double kappa0,
+                                                        double sigma, double fsrc, const double* __restrict__ xi,
+                                                        const int32_t* __restrict__ row_ptr,
+                                                        double* __restrict__ values, float* __restrict__ values32,
+                                                        double* __restrict__ rhs) {
+  constexpr int R = 256 / SB;  // rows per workgroup
+  constexpr int TZ = 4, TX = R / TZ;
+  constexpr int EX = TX + 1, NE = EX * 2 * (TZ + 1);
+  constexpr int G = S / SB;    // sample groups
+  constexpr int PS = SB + 1;   // padded sample stride in LDS
+  static_assert(R % TZ == 0 && S % SB == 0, "tile shape");
+  __shared__ double s_cm[SB * kAsmMaxM];
+  __shared__ double s_k[NE * 8 * PS];  // [element][q][sample]
   const int n1 = N + 1;
-  const int64_t n = (int64_t)n1 * n1 * n1;
-  const int e = threadIdx.x % S;
-  const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / S;
-  if (row >= n) return;
-  const int ii = (int)(row % n1), jj = (int)((row / n1) % n1), kk = (int)(row / ((int64_t)n1 * n1));
+  const int ntx = (n1 + TX - 1) / TX, ntz = (n1 + TZ - 1) / TZ;
+  // Workgroups are dealt to the 8 XCDs round-robin by index; the G sample
+  // groups of one tile take indices 8 apart (same XCD, dispatched together)
+  // so their partial writes of each row's sample ensemble meet in one L2.
+  const int64_t tiles = (int64_t)ntx * ntz * n1;
+  int64_t bid = blockIdx.x, tile;
+  int sg;
+  if (G > 1 && (bid / (8 * G)) < tiles / 8) {
+    const int64_t blk = bid / (8 * G), rem = bid % (8 * G);
+    sg = (int)(rem / 8);
+    tile = blk * 8 + rem % 8;
+  } else {
+    const int64_t rest = bid - (tiles / 8) * 8 * G;  // the last tiles % 8 tiles, plainly
+    sg = (int)(G > 1 ? rest % G : 0);
+    tile = (G > 1 ? (tiles / 8) * 8 + rest / G : bid);
+  }
+  const int xt = (int)(tile % ntx);
+  tile /= ntx;
+  const int zt = (int)(tile % ntz);
+  const int y = (int)(tile / ntz);
+  const int x0 = xt * TX, z0 = zt * TZ, e0 = sg * SB;
+  for (int t = threadIdx.x; t < SB * M; t += blockDim.x) {
+    const int ee = t / M, m = t % M;
+    s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + ee) * M + m];
+  }
+  __syncthreads();
   const double h = 1.0 / (double)N;
-  const double wscale = h * 0.125;  // w_q / h^2
+  const double wscale = h * 0.125;
   const int64_t two_n = 2 * (int64_t)N;
+  for (int p = threadIdx.x; p < NE * SB; p += blockDim.x) {
+    const int le = p / SB, sb = p % SB;
+    const int lx = le % EX, ly = (le / EX) % 2, lz = le / (2 * EX);
+    const int ex = x0 - 1 + lx, ey = y - 1 + ly, ez = z0 - 1 + lz;
+    if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
+    double kq[8];
+    kl_points(kl_phi, kl_triple, s_cm + sb * M, M, two_n, ex, ey, ez, kappa0, kq);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s_k[(le * 8 + q) * PS + sb] = kq[q] * wscale;
+  }
+  __syncthreads();
+
+  const int r = threadIdx.x / SB, sb = threadIdx.x % SB;
+  const int rx = r % TX, rz = r / TX;
+  const int ii = x0 + rx, jj = y, kk = z0 + rz;
+  if (ii > N || kk > N) return;
+  const int e = e0 + sb;
+  const int64_t row = (int64_t)ii + n1 * ((int64_t)jj + (int64_t)n1 * kk);
 
   double acc[27];
 #pragma unroll
   for (int t = 0; t < 27; ++t) acc[t] = 0.0;
   int nelem = 0;
-
-  // elements around the node in ascending id: (ez, ey, ex) lexicographic
 #pragma unroll
   for (int ez_off = -1; ez_off <= 0; ++ez_off)
 #pragma unroll
@@ -164,27 +203,11 @@ __global__ __launch_bounds__(256) void k_assemble(int N, const double* __restric
         const int ex = ii + ex_off, ey = jj + ey_off, ez = kk + ez_off;
         if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
         ++nelem;
-        const int ai = (-ex_off) + 2 * (-ey_off) + 4 * (-ez_off);  // local index of the node
+        const int ai = (-ex_off) + 2 * (-ey_off) + 4 * (-ez_off);
+        const int le = (rx + 1 + ex_off) + EX * ((1 + ey_off) + 2 * (rz + 1 + ez_off));
         double kq[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) kq[q] = 0.0;
-#pragma unroll 2
-        for (int m = 0; m < M; ++m) {
-          // mode m at the 8 points: c_m X(qx) Y(qy) Z(qz), the (qy, qz)
-          // products formed once for both qx
-          const double c = s_cm[e * M + m];
-          const double* px = tab + kl_triple[3 * m + 0] * two_n + 2 * ex;
-          const double* py = tab + kl_triple[3 * m + 1] * two_n + 2 * ey;
-          const double* pz = tab + kl_triple[3 * m + 2] * two_n + 2 * ez;
-          const double fx[2] = {px[0], px[1]}, fy[2] = {py[0], py[1]}, fz[2] = {pz[0], pz[1]};
-          double yz[4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) yz[t] = c * (fy[t & 1] * fz[t >> 1]);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) kq[q] = (kappa0 + kq[q]) * wscale;
+        for (int q = 0; q < 8; ++q) kq[q] = s_k[(le * 8 + q) * PS + sb];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
           const int dx = ex_off + (b & 1), dy = ey_off + ((b >> 1) & 1), dz = ez_off + ((b >> 2) & 1);
@@ -205,11 +228,11 @@ __global__ __launch_bounds__(256) void k_assemble(int N, const double* __restric
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int x = ii + dx, y = jj + dy, z = kk + dz;
-        if (x < 0 || y < 0 || z < 0 || x > N || y > N || z > N) continue;
+        const int x = ii + dx, yy = jj + dy, z = kk + dz;
+        if (x < 0 || yy < 0 || z < 0 || x > N || yy > N || z > N) continue;
         const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
         double v = acc[slot27];
-        const bool bnd_col = (x == 0 || x == N || y == 0 || y == N || z == 0 || z == N);
+        const bool bnd_col = (x == 0 || x == N || yy == 0 || yy == N || z == 0 || z == N);
         if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
         else if (bnd_col) v = 0.0;
         const int64_t k = (start + pos) * S + e;
@@ -217,7 +240,6 @@ __global__ __launch_bounds__(256) void k_assemble(int N, const double* __restric
         if (values32) values32[k] = (float)v;
         ++pos;
       }
-  // load: each element adds sum_q f N_a(g_q) h^3/8 = f h^3/8 to its vertices
   rhs[row * S + e] = bnd_row ? 0.0 : (double)nelem * (fsrc * h * h * h * 0.125);
 }
 
@@ -388,25 +410,20 @@ extern "C" ens_status ens_assemble(int32_t N, const ens_graph* graph, const void
   const double* sq = (const double*)base;
   const int32_t* tr = (const int32_t*)(base + (size_t)M * 5 * sizeof(double) + (size_t)M * sizeof(int32_t));
   const double* phi = (const double*)(base + phi_off);
-  const int rpb = 256 / s;
-  int64_t blocks = (n + rpb - 1) / rpb;
-  const size_t table = (size_t)M * 2 * N * sizeof(double);
-  const size_t lds_bytes = table > 0 && table <= 48 * 1024 ? table : 0;
   prof_begin(ENS_K_ASSEMBLE, stream);
   switch (s) {
-#define ENS_ASM_CASE(SS)                                                                                  \
-  case SS:                                                                                                \
-    if (lds_bytes)                                                                                        \
-      hipLaunchKernelGGL((k_assemble<SS, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, stream, N, sq, tr,  \
-                         phi, M, prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values, values32, rhs); \
-    else                                                                                                  \
-      hipLaunchKernelGGL((k_assemble<SS, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, N, sq, tr, phi, M, \
-                         prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values, values32, rhs);  \
-    break;
-    ENS_ASM_CASE(4)
-    ENS_ASM_CASE(8)
-    ENS_ASM_CASE(16)
-    ENS_ASM_CASE(32)
+#define ENS_ASM_CASE(SS, SB)                                                                                 \
+  case SS: {                                                                                                 \
+    constexpr int R = 256 / SB, TX = R / 4;                                                                  \
+    const int64_t tiles = (int64_t)((N + TX) / TX) * ((N + 4) / 4) * (N + 1) * (SS / SB);                    \
+    hipLaunchKernelGGL((k_assemble_tile<SS, SB>), dim3((unsigned)tiles), dim3(256), 0, stream, N, sq, tr, phi,  \
+                       M, prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values, values32, rhs);      \
+    break;                                                                                                   \
+  }
+    ENS_ASM_CASE(4, 4)
+    ENS_ASM_CASE(8, 8)
+    ENS_ASM_CASE(16, 8)
+    ENS_ASM_CASE(32, 8)
 #undef ENS_ASM_CASE
   }
   ENS_LAUNCH_CHECK();
