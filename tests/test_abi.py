@@ -91,3 +91,48 @@ def test_workspace_size_grows_with_problem(E):
     assert E.lib().ens_cg_workspace_bytes(ctypes.byref(gc), 32, ctypes.byref(o), ctypes.byref(b)) == 0
     assert b.value < b64
     assert b64 >= 4 * 4913 * 32 * 8
+
+
+def test_nonlinear_and_multigrid_argument_errors_without_gpu(E):
+    L = E.lib()
+    g = E.ens_graph(2146689, 57066625, 256, 512)
+    b = ctypes.c_size_t()
+    # GMRES restart range and ensemble sizes
+    for bad in (0, 33):
+        assert L.ens_gmres_workspace_bytes(ctypes.byref(g), 32, bad, ctypes.byref(b)) == E.ENS_E_ARG
+    assert L.ens_gmres_workspace_bytes(ctypes.byref(g), 12, 30, ctypes.byref(b)) == E.ENS_E_UNSUPPORTED
+    assert L.ens_gmres_workspace_bytes(ctypes.byref(g), 32, 30, ctypes.byref(b)) == E.ENS_OK
+    # the basis alone is (restart + 1) vectors
+    assert b.value > 31 * 2146689 * 32 * 8
+    # the FP32 Jacobian shrinks the Newton workspace by nnz * s * 4 bytes (up to alignment)
+    o64, o32 = E.newton_opts(jac32=False), E.newton_opts(jac32=True)
+    b64, b32 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.ens_newton_workspace_bytes(ctypes.byref(g), 32, ctypes.byref(o64), ctypes.byref(b64)) == E.ENS_OK
+    assert L.ens_newton_workspace_bytes(ctypes.byref(g), 32, ctypes.byref(o32), ctypes.byref(b32)) == E.ENS_OK
+    assert abs((b64.value - b32.value) - 57066625 * 32 * 4) < 512
+    # GMRES refusals before any launch: misaligned buffers, workspace too small
+    opts = E.gmres_opts(restart=30)
+    stats = (E.ens_cg_stat * 32)()
+    st = L.ens_gmres(ctypes.byref(g), 32, ctypes.c_void_p(8), ctypes.c_void_p(256), ctypes.c_void_p(512),
+                     ctypes.byref(opts), None, None, ctypes.c_void_p(1024), 1 << 40, stats, None)
+    assert st == E.ENS_E_ARG
+    st = L.ens_gmres(ctypes.byref(g), 32, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(512),
+                     ctypes.byref(opts), None, None, ctypes.c_void_p(1024), 4096, stats, None)
+    assert st == E.ENS_E_NOMEM
+    # Newton: the graph must be the N^3 mesh's
+    prob = E.nl_problem(10, 0.3, 10.0, 100.0)
+    nst = (E.ens_newton_stat * 32)()
+    st = L.ens_newton(64, ctypes.byref(g), ctypes.c_void_p(256), ctypes.byref(prob), 32, ctypes.c_void_p(256),
+                      ctypes.c_void_p(512), ctypes.byref(o32), None, None, ctypes.c_void_p(1024), 1 << 40, nst, None)
+    assert st == E.ENS_E_ARG
+    # multigrid: odd coarse blocks beyond the dense solve are refused; an
+    # unknown buffer is neither built nor set up
+    assert L.ens_mg_bytes(11, 10, 8, 0, ctypes.byref(b)) == E.ENS_E_UNSUPPORTED
+    assert L.ens_mg_bytes(128, 10, 32, 1, ctypes.byref(b)) == E.ENS_OK and b.value > 57066625 * 32 * 4 // 8
+    desc = E.ens_mg(16, 10, 8, 0, ctypes.c_void_p(1 << 20), 1 << 30)
+    gs = E.ens_graph(17 ** 3, 49 ** 3, 256, 512)
+    pr = E.ens_problem(10, 1.0, 1.0, 0.3, 1.0)
+    st = L.ens_mg_setup(ctypes.byref(desc), ctypes.byref(gs), ctypes.c_void_p(256), None, ctypes.byref(pr),
+                        ctypes.c_void_p(512), None)
+    assert st == E.ENS_E_ARG and b"not built" in L.ens_last_error()
+    assert L.ens_mg_release(ctypes.byref(desc)) == E.ENS_OK
