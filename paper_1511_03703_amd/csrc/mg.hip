@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
   vt dn;
   if (MODE == MG_CHEB1) dn = k2 * dv;
   else dn = k1 * ((const vt*)d)[i] + k2 * dv;
-  ((vt*)d)[i] = dn;
+  store_stream((vt*)d + i, dn);
   store_stream((vt*)out + i, ((const vt*)x)[i] + dn);
 }
 
