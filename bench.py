@@ -192,6 +192,8 @@ def run_solve(args):
         x.zero_()
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=mg_opts, workspace=ws)
 
+    step_ms = []
+
     def timed(step, steps, warmup):
         # profiling is on during the warmup too, so the timed steps repeat
         # exactly the warmup's host work; the interpreter's cyclic garbage
@@ -219,6 +221,8 @@ def run_solve(args):
         ens.prof_enable(False)
         per = [round((b - a) * 1e3, 2) for a, b in zip([t0] + marks[:-1], marks)]
         log(f"ms per step: {per}")
+        step_ms.clear()
+        step_ms.extend(per)
         return el, stats
 
     def spmv_roofline():
@@ -244,6 +248,7 @@ def run_solve(args):
                 "avg_launch_ms": round(pr["total_ms"] / max(pr["launches"], 1), 5), "launches": pr["launches"]}
 
     elapsed, stats = timed(step_mg if use_mg else step_jacobi, args.steps, args.warmup)
+    head_steps = list(step_ms)
     roofline = mg_roofline() if use_mg else spmv_roofline()
     pa = ens.prof_query(ens.K_ASSEMBLE)
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
@@ -276,6 +281,8 @@ def run_solve(args):
         # every level's assembly in one step (launches under 5 % of the
         # longest one are not recorded)
         "assembly_ms_per_step": round(pa["total_ms"] / max(args.steps, 1), 3),
+        "step_ms": {"median": float(np.median(head_steps)), "min": min(head_steps), "max": max(head_steps)},
+        "env": {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__},
     }
     x_head = x.clone() if not args.no_context else None
     if use_mg and not args.no_context:
@@ -365,6 +372,21 @@ def run_solve(args):
         e1.record()
         torch.cuda.synchronize()
         t_sc = e0.elapsed_time(e1) / 10
+        # the STREAM-style triad a = b + q c on 3 x 4 GiB of FP64 (the
+        # bandwidth the paper bounds its products with)
+        na = (4 << 30) // 8
+        ta = torch.empty(na, dtype=torch.float64, device=dev)
+        tb = torch.rand(na, dtype=torch.float64, device=dev)
+        tc = torch.rand(na, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            ens.stream_triad(ta, tb, tc, 0.5)
+        e0.record()
+        for _ in range(5):
+            ens.stream_triad(ta, tb, tc, 0.5)
+        e1.record()
+        torch.cuda.synchronize()
+        triad_gbs = 3.0 * na * 8 / (e0.elapsed_time(e1) / 5) / 1e6
+        del ta, tb, tc
         b_ens = spmv_bytes(w.n, w.nnz, w.s, wb)
         b_sc = spmv_bytes(w.n, w.nnz, 1, wb)
         jac_rate = out["jacobi"]["value"] if use_mg else value
@@ -397,6 +419,7 @@ def run_solve(args):
                      "scalar_ms": round(t_sc, 5), "scalar_GBs": round(b_sc / t_sc / 1e6, 1),
                      "speedup_s_times_scalar_over_ensemble": round(w.s * t_sc / t_ens, 3),
                      "dtype": "f32" if w.mixed else "f64"},
+            "triad_GBs": round(triad_gbs, 1),
         }
         del xv, yv, x1, y1
 
