@@ -1421,15 +1421,32 @@ int orc_ens_gmres(int N, const int32_t *rp, const int32_t *ci, int s, const doub
 /* Newton's method on F(u) = 0 (Sec. 4, Eq. fenl_lin_sys), one sample:       */
 /*   k = 0, 1, ...: F, A at u_k; stop when ||F(u_k)|| <= rtol ||load||        */
 /*   (||F(u_0)|| when the load is zero); otherwise A d = F by GMRES to the   */
-/*   relative tolerance lin_rtol from d = 0, and u_{k+1} = u_k - d.          */
+/*   relative tolerance eta_k from d = 0, and u_{k+1} = u_k - d.             */
+/* forcing 0: eta_k = lin_rtol.  forcing 1: the second choice of Eisenstat   */
+/* and Walker (SIAM J. Sci. Comput. 17, 1996) with gamma = 0.9, exponent 2,  */
+/* eta_0 = eta_max = lin_rtol: eta_k = gamma (|F_k| / |F_{k-1}|)^2, raised   */
+/* to gamma eta_{k-1}^2 when that exceeds 0.1, capped at eta_max, and kept   */
+/* at least 0.5 rtol ref / |F_k| (no solve tighter than the Newton test      */
+/* needs).                                                                   */
 /* Statuses: converged; max steps; breakdown (the linear solve broke down);  */
 /* non-finite.  fnorm (nullable, max_newton + 1 entries) receives ||F(u_k)||. */
 /* ------------------------------------------------------------------------ */
 
+static double ew_forcing(int k, double eta_prev, double fn, double fprev, double lin_rtol, double floor_tol) {
+  if (k == 0) return lin_rtol;
+  const double gamma = 0.9;
+  double eta = gamma * (fn / fprev) * (fn / fprev);
+  const double safe = gamma * eta_prev * eta_prev;
+  if (safe > 0.1 && safe > eta) eta = safe;
+  if (eta > lin_rtol) eta = lin_rtol;
+  if (eta < floor_tol) eta = floor_tol;
+  return eta;
+}
+
 int orc_newton(int N, int M, double L, double kappa0, double sigma, double fconst, double alpha, const double *vel,
                double beta, const double *xi, double *u, int prec, double rtol, int max_newton, double lin_rtol,
-               int restart, int lin_max_iter, int32_t *newton_iters, int32_t *lin_iters, double *rel_res,
-               int32_t *status, double *fnorm) {
+               int restart, int lin_max_iter, int forcing, int32_t *newton_iters, int32_t *lin_iters,
+               double *rel_res, int32_t *status, double *fnorm) {
   const int64_t n = orc_num_nodes(N), nnz = orc_graph_nnz(N), ne = orc_num_elems(N);
   int32_t *rp = malloc(sizeof(int32_t) * (size_t)(n + 1)), *ci = malloc(sizeof(int32_t) * (size_t)nnz);
   double *ac = malloc(sizeof(double) * 8 * (size_t)ne), *vals = malloc(sizeof(double) * (size_t)nnz);
@@ -1450,7 +1467,7 @@ int orc_newton(int N, int M, double L, double kappa0, double sigma, double fcons
     }
   }
   int st = ORC_MAXITER, k = 0, lin_total = 0;
-  double ref = 0.0, fn = 0.0;
+  double ref = 0.0, fn = 0.0, fprev = 0.0, eta = lin_rtol;
   for (; rc == ORC_OK; ++k) {
     orc_nl_assemble_scalar(N, rp, ci, ac, fconst, alpha, vel, beta, u, F, vals, ld);
     fn = sqrt(dot(n, F, F));
@@ -1471,10 +1488,13 @@ int orc_newton(int N, int M, double L, double kappa0, double sigma, double fcons
       }
       P.dinv = dinv;
     }
+    if (forcing == 1) eta = ew_forcing(k, eta, fn, fprev, lin_rtol, 0.5 * rtol * ref / fn);
+    fprev = fn;
     for (int64_t i = 0; i < n; ++i) d[i] = 0.0;
     int32_t it = 0, ls = 0;
     double lr = 0.0;
-    rc = gmres_core(n, rp, ci, vals, F, d, &P, lin_rtol, restart, lin_max_iter, -1, &it, &lr, &ls);
+    rc = gmres_core(n, rp, ci, vals, F, d, &P, forcing == 1 ? eta : lin_rtol, restart, lin_max_iter, -1, &it, &lr,
+                    &ls);
     lin_total += it;
     if (ls == ORC_NONFINITE) { st = ORC_NONFINITE; break; }
     if (ls == ORC_BREAKDOWN) { st = ORC_BREAKDOWN; break; }
@@ -1493,8 +1513,8 @@ int orc_newton(int N, int M, double L, double kappa0, double sigma, double fcons
  * [s][max_newton + 1] nullable. */
 int orc_ens_newton(int N, int M, double L, double kappa0, double sigma, double fconst, double alpha,
                    const double *vel, double beta, int s, const double *xi, double *u, int prec, double rtol,
-                   int max_newton, double lin_rtol, int restart, int lin_max_iter, int32_t *newton_iters,
-                   int32_t *lin_iters, double *rel_res, int32_t *status, double *fnorm) {
+                   int max_newton, double lin_rtol, int restart, int lin_max_iter, int forcing,
+                   int32_t *newton_iters, int32_t *lin_iters, double *rel_res, int32_t *status, double *fnorm) {
   const int64_t n = orc_num_nodes(N);
   int rc = ORC_OK;
   #pragma omp parallel for schedule(dynamic, 1)
@@ -1503,8 +1523,8 @@ int orc_ens_newton(int N, int M, double L, double kappa0, double sigma, double f
     if (!ue) { rc = ORC_E_NOMEM; continue; }
     for (int64_t i = 0; i < n; ++i) ue[i] = u[i * s + e];
     int r = orc_newton(N, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi + (int64_t)e * M, ue, prec, rtol,
-                       max_newton, lin_rtol, restart, lin_max_iter, &newton_iters[e], &lin_iters[e], &rel_res[e],
-                       &status[e], fnorm ? fnorm + (int64_t)e * (max_newton + 1) : NULL);
+                       max_newton, lin_rtol, restart, lin_max_iter, forcing, &newton_iters[e], &lin_iters[e],
+                       &rel_res[e], &status[e], fnorm ? fnorm + (int64_t)e * (max_newton + 1) : NULL);
     if (r) rc = r;
     for (int64_t i = 0; i < n; ++i) u[i * s + e] = ue[i];
     free(ue);

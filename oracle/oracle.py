@@ -94,10 +94,10 @@ def lib():
         L.orc_ens_gmres.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int, dbl,
                                     dbl, dbl, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
         L.orc_newton.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl, vp, vp, ctypes.c_int,
-                                 dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+                                 dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_ens_newton.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl, ctypes.c_int, vp,
-                                     vp, ctypes.c_int, dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp,
-                                     vp, vp]
+                                     vp, ctypes.c_int, dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -426,10 +426,14 @@ def ens_gmres(N, rp, ci, values, b, x0=None, prec=PREC_JACOBI, M=0, L=1.0, kappa
     return x, it, rr, st
 
 
+FORCING_FIXED, FORCING_EW = 0, 1
+
+
 def ens_newton(N, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi, u0=None, prec=PREC_MG, rtol=1e-8,
-               max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000):
-    """Newton per sample.  Returns (u [n][s], newton_iters, lin_iters,
-    rel_res, status, fnorm [s][max_newton + 1])."""
+               max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000, forcing=FORCING_FIXED):
+    """Newton per sample (forcing: fixed lin_rtol, or Eisenstat-Walker with
+    eta_0 = eta_max = lin_rtol).  Returns (u [n][s], newton_iters,
+    lin_iters, rel_res, status, fnorm [s][max_newton + 1])."""
     xi = _f64(xi)
     s = xi.shape[0]
     n = num_nodes(N)
@@ -440,6 +444,6 @@ def ens_newton(N, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi, u0=None, pr
     st = np.zeros(s, np.int32)
     fn = np.zeros((s, max_newton + 1))
     _check(lib().orc_ens_newton(N, M, L, kappa0, sigma, fconst, alpha, _p(_f64(vel)), beta, s, _p(xi), _p(u), prec,
-                                rtol, max_newton, lin_rtol, restart, lin_max_iter, _p(ni), _p(li), _p(rr), _p(st),
-                                _p(fn)))
+                                rtol, max_newton, lin_rtol, restart, lin_max_iter, int(forcing), _p(ni), _p(li),
+                                _p(rr), _p(st), _p(fn)))
     return u, ni, li, rr, st, fn
