@@ -404,8 +404,9 @@ ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, co
  * at u_k assemble F and A = dF/du (ens_nl_assemble); stop the sample when
  * |F(u_k)| <= rtol |load| (|F(u_0)| if the load is zero), at non-finite
  * norms, or after max_newton steps; otherwise solve A d = F by ens_gmres to
- * lin_rtol from d = 0 and set u_{k+1} = u_k - d.  A linear solve that
- * breaks down or turns non-finite stops its sample with that status. */
+ * the forcing term of the step (opts->forcing) from d = 0 and set
+ * u_{k+1} = u_k - d.  A linear solve that breaks down or turns non-finite
+ * stops its sample with that status. */
 typedef struct {
   double rtol;
   int32_t max_newton;
@@ -415,6 +416,12 @@ typedef struct {
   int32_t jac32;         /* 1: the Newton systems use the Jacobian rounded to
                             FP32 (read and widened by the FP64 GMRES); F, the
                             step and u stay FP64 and the FP64 |F| decides */
+  int32_t forcing;       /* GMRES tolerance of step k: 0 -> lin_rtol; 1 ->
+                            the second choice of Eisenstat and Walker (1996):
+                            eta_k = 0.9 (|F_k|/|F_{k-1}|)^2, raised to
+                            0.9 eta_{k-1}^2 when that exceeds 0.1, at most
+                            lin_rtol (also eta_0), at least
+                            0.5 rtol |load| / |F_k| */
 } ens_newton_opts;
 
 typedef struct {

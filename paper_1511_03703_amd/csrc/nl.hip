@@ -45,10 +45,11 @@ struct GmCtl {
 
 struct NtCtl {
   double ref[kMaxS], fnorm[kMaxS], rel_res[kMaxS];
+  double eta[kMaxS], fprev[kMaxS];  // forcing term of the coming solve; |F| of the last step
   int32_t status[kMaxS], active[kMaxS], iters[kMaxS], lin_iters[kMaxS];
   int32_t n_active;
-  int32_t max_newton;
-  double rtol;
+  int32_t max_newton, forcing;
+  double rtol, lin_rtol;
 };
 
 // ------------------------------------------------------------ reductions ---
@@ -92,14 +93,15 @@ static __global__ __launch_bounds__(kBlock) void k_gm_red1(const double* __restr
 // ------------------------------------------------------------- finalize ---
 
 template <int S>
-__device__ void gm_finalize(GmCtl* c, const double* tot, int op, int arg, const int32_t* mask) {
+__device__ void gm_finalize(GmCtl* c, const double* tot, int op, int arg, const int32_t* mask,
+                            const double* rtol_e) {
   const int e = threadIdx.x;
   if (e < S) {
     switch (op) {
       case GM_START: {  // tot: |r|^2 [S], |b|^2 [S]; arg 0 first residual, 1 after a cycle
         if (arg == 0) {
           c->bnorm[e] = sqrt(tot[S + e]);
-          c->tol[e] = c->rtol * c->bnorm[e];
+          c->tol[e] = (rtol_e ? rtol_e[e] : c->rtol) * c->bnorm[e];
           c->iters[e] = 0;
           c->cycles[e] = 0;
           c->zx[e] = 0;
@@ -211,10 +213,11 @@ __device__ void gm_finalize(GmCtl* c, const double* tot, int op, int arg, const 
 template <int S>
 static __global__ __launch_bounds__(kBlock) void k_gm_final(const double* __restrict__ part, int64_t rows, int Q,
                                                             int64_t stride, GmCtl* c, int op, int arg,
-                                                            const int32_t* __restrict__ mask) {
+                                                            const int32_t* __restrict__ mask,
+                                                            const double* __restrict__ rtol_e) {
   __shared__ double tot[(kGmMaxRestart + 1) * kMaxS];
   sum_block_rows(part, 0, rows, Q, stride, tot);
-  gm_finalize<S>(c, tot, op, arg, mask);
+  gm_finalize<S>(c, tot, op, arg, mask, rtol_e);
 }
 
 static __global__ void k_gm_init(GmCtl* c, double rtol, int restart, int max_iter) {
@@ -658,16 +661,17 @@ static unsigned stream_grid(int64_t nchunks) {
 // finalize step.
 template <int S>
 static void gm_reduce(const GmWork& w, const double* part, int64_t rows, int Q, int64_t stride, int op, int arg,
-                      const int32_t* mask, hipStream_t st) {
+                      const int32_t* mask, const double* rtol_e, hipStream_t st) {
   if (rows <= 64) {
-    hipLaunchKernelGGL((k_gm_final<S>), dim3(1), dim3(kBlock), 0, st, part, rows, Q, stride, w.ctl, op, arg, mask);
+    hipLaunchKernelGGL((k_gm_final<S>), dim3(1), dim3(kBlock), 0, st, part, rows, Q, stride, w.ctl, op, arg, mask,
+                       rtol_e);
     return;
   }
   int64_t r = rows / 16;
   if (r > kGmRed) r = kGmRed;
   hipLaunchKernelGGL(k_gm_red1, dim3((unsigned)r), dim3(kBlock), 0, st, part, rows, Q, stride, w.part1);
   hipLaunchKernelGGL((k_gm_final<S>), dim3(1), dim3(kBlock), 0, st, w.part1, r, Q, (int64_t)Q, w.ctl, op, arg,
-                     mask);
+                     mask, rtol_e);
 }
 
 static ens_status read_flag(const int32_t* dev, hipStream_t st, int32_t* out) {
@@ -688,7 +692,8 @@ static ens_status read_flag(const int32_t* dev, hipStream_t st, int32_t* out) {
 // that take part.
 template <int S, typename TV>
 static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, double* x, double rtol, int restart,
-                        int max_iter, const MgPlan* plan, const GmWork& w, const int32_t* mask, hipStream_t st) {
+                        int max_iter, const MgPlan* plan, const GmWork& w, const int32_t* mask,
+                        const double* rtol_e, hipStream_t st) {
   const int n = g->n;
   const int64_t nchunks = (int64_t)n * S / VecMap<double, S>::V;
   const int64_t vstride = (int64_t)n * S;
@@ -704,7 +709,7 @@ static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, dou
                               g->row_ptr, g->col_idx, vals, w.dinv);
   hipLaunchKernelGGL((k_gm_residual<S, TV>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b, w.w,
                      w.rpart);
-  gm_reduce<S>(w, w.rpart, rb, 2 * S, 2 * S, GM_START, 0, mask, st);
+  gm_reduce<S>(w, w.rpart, rb, 2 * S, 2 * S, GM_START, 0, mask, rtol_e, st);
   hipLaunchKernelGGL((k_gm_zero_x<S>), dim3(grid_of((int64_t)n * S, kBlock)), dim3(kBlock), 0, st, (int64_t)n * S,
                      w.ctl, x);
   ENS_LAUNCH_CHECK();
@@ -757,7 +762,7 @@ static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, dou
         prof_end(ENS_K_GM_ORTH, st, vbytes * (j + 1 + (j + kGmChunk) / kGmChunk));
       };
       dots();
-      gm_reduce<S>(w, w.part, sg, (j + 1) * S, w.pstride, GM_H1, j, mask, st);
+      gm_reduce<S>(w, w.part, sg, (j + 1) * S, w.pstride, GM_H1, j, mask, rtol_e, st);
       prof_begin(ENS_K_GM_ORTH, st);
       if (j < 8)
         hipLaunchKernelGGL((k_gm_axpy_dots<S, 8>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.ctl,
@@ -770,12 +775,12 @@ static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, dou
                            w.w, w.part, w.pstride);
       prof_end(ENS_K_GM_ORTH, st, vbytes * (j + 3));
       if (j >= 16) dots();
-      gm_reduce<S>(w, w.part, sg, (j + 1) * S, w.pstride, GM_H2, j, mask, st);
+      gm_reduce<S>(w, w.part, sg, (j + 1) * S, w.pstride, GM_H2, j, mask, rtol_e, st);
       prof_begin(ENS_K_GM_ORTH, st);
       hipLaunchKernelGGL((k_gm_axpy<S, true>), dim3(sg), dim3(kBlock), 0, st, nchunks, w.V, vstride, j, w.ctl, w.w,
                          w.part, w.pstride);
       prof_end(ENS_K_GM_ORTH, st, vbytes * (j + 3));
-      gm_reduce<S>(w, w.part, sg, S, w.pstride, GM_NORM, j, mask, st);
+      gm_reduce<S>(w, w.part, sg, S, w.pstride, GM_NORM, j, mask, rtol_e, st);
       ENS_LAUNCH_CHECK();
       steps = j + 1;
       int32_t ncyc = 0;
@@ -805,7 +810,7 @@ static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, dou
     }
     hipLaunchKernelGGL((k_gm_residual<S, TV>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b,
                        w.w, w.rpart);
-    gm_reduce<S>(w, w.rpart, rb, 2 * S, 2 * S, GM_START, 1, mask, st);
+    gm_reduce<S>(w, w.rpart, rb, 2 * S, 2 * S, GM_START, 1, mask, rtol_e, st);
     ENS_LAUNCH_CHECK();
   }
   return ENS_OK;
@@ -869,6 +874,24 @@ static __global__ __launch_bounds__(kBlock) void k_nt_final(const double* __rest
         c->active[e] = 0;
       }
     }
+    if (c->active[e]) {
+      // forcing term of this step's linear solve: fixed, or the second
+      // choice of Eisenstat and Walker (gamma 0.9, exponent 2, safeguard
+      // gamma eta^2 above 0.1, eta_0 = eta_max = lin_rtol, and no tighter
+      // than 0.5 rtol ref / |F|)
+      double eta = c->lin_rtol;
+      if (c->forcing == 1 && k > 0) {
+        const double gamma = 0.9;
+        eta = gamma * (fn / c->fprev[e]) * (fn / c->fprev[e]);
+        const double safe = gamma * c->eta[e] * c->eta[e];
+        if (safe > 0.1 && safe > eta) eta = safe;
+        if (eta > c->lin_rtol) eta = c->lin_rtol;
+        const double floor_tol = 0.5 * c->rtol * c->ref[e] / fn;
+        if (eta < floor_tol) eta = floor_tol;
+      }
+      c->eta[e] = eta;
+      c->fprev[e] = fn;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -901,13 +924,19 @@ static __global__ __launch_bounds__(kBlock) void k_nt_update(int64_t total, cons
   if (i < total && c->active[i % S]) u[i] -= d[i];
 }
 
-static __global__ void k_nt_init(NtCtl* c, double rtol, int max_newton) {
+static __global__ void k_nt_init(NtCtl* c, double rtol, int max_newton, int forcing, double lin_rtol) {
   if (threadIdx.x == 0) {
     c->rtol = rtol;
     c->max_newton = max_newton;
+    c->forcing = forcing;
+    c->lin_rtol = lin_rtol;
     c->n_active = 0;
   }
-  if (threadIdx.x < kMaxS) c->active[threadIdx.x] = 0;
+  if (threadIdx.x < kMaxS) {
+    c->active[threadIdx.x] = 0;
+    c->eta[threadIdx.x] = lin_rtol;
+    c->fprev[threadIdx.x] = 0.0;
+  }
 }
 
 static __global__ void k_fill_zero64(int64_t total, double* __restrict__ x) {
@@ -950,7 +979,7 @@ static ens_status newton(int N, const ens_graph* g, const void* kl, const ens_nl
   const int64_t total = n * S;
   const int64_t nchunks = total / VecMap<double, S>::V;
   const unsigned sg = stream_grid(nchunks);
-  hipLaunchKernelGGL(k_nt_init, dim3(1), dim3(64), 0, st, w.ctl, o.rtol, o.max_newton);
+  hipLaunchKernelGGL(k_nt_init, dim3(1), dim3(64), 0, st, w.ctl, o.rtol, o.max_newton, o.forcing, o.lin_rtol);
   ENS_LAUNCH_CHECK();
   for (int k = 0;; ++k) {
     ens_status rc = ens_nl_assemble(N, g, kl, prob, S, xi, u, o.jac32 ? nullptr : (double*)w.J,
@@ -968,10 +997,10 @@ static ens_status newton(int N, const ens_graph* g, const void* kl, const ens_nl
     hipLaunchKernelGGL(k_fill_zero64, dim3(grid_of(total, kBlock)), dim3(kBlock), 0, st, total, w.d);
     if (o.jac32)
       rc = gmres<S, float>(g, (const float*)w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm,
-                           w.ctl->active, st);
+                           w.ctl->active, w.ctl->eta, st);
     else
       rc = gmres<S, double>(g, (const double*)w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm,
-                            w.ctl->active, st);
+                            w.ctl->active, w.ctl->eta, st);
     if (rc != ENS_OK) return rc;
     hipLaunchKernelGGL((k_nt_after<S>), dim3(1), dim3(64), 0, st, w.ctl, (const GmCtl*)w.gm.ctl);
     hipLaunchKernelGGL((k_nt_update<S>), dim3(grid_of(total, kBlock)), dim3(kBlock), 0, st, total, w.ctl, w.d, u);
@@ -1064,7 +1093,7 @@ ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, co
 #define ENS_GM_CASE(SS)                                                                                       \
   case SS:                                                                                                    \
     st = gmres<SS, double>(graph, values, b, x, opts->rtol, opts->restart, opts->max_iter, mg ? &plan : nullptr, \
-                           w, nullptr, stream);                                                               \
+                           w, nullptr, nullptr, stream);                                                      \
     break;
     ENS_GM_CASE(4)
     ENS_GM_CASE(8)
@@ -1125,6 +1154,7 @@ ens_status ens_newton(int32_t N, const ens_graph* graph, const void* kl, const e
   ENS_ARG_CHECK(opts->rtol >= 0.0 && opts->lin_rtol >= 0.0, "tolerances must be >= 0");
   ENS_ARG_CHECK(opts->max_newton >= 0 && opts->lin_max_iter >= 0, "iteration caps must be >= 0");
   ENS_ARG_CHECK(opts->restart >= 1 && opts->restart <= kGmMaxRestart, "restart must be in 1..32");
+  ENS_ARG_CHECK(opts->forcing == 0 || opts->forcing == 1, "forcing must be 0 (fixed) or 1 (adaptive)");
   const int64_t nn = (int64_t)(N + 1) * (N + 1) * (N + 1);
   ENS_ARG_CHECK(N >= 1 && graph->n == nn, "graph is not the N^3 mesh's graph");
   if (!supported_s(s)) {

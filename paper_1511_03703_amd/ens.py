@@ -72,7 +72,8 @@ class ens_gmres_opts(ctypes.Structure):
 
 class ens_newton_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_newton", ctypes.c_int32), ("lin_rtol", ctypes.c_double),
-                ("restart", ctypes.c_int32), ("lin_max_iter", ctypes.c_int32), ("jac32", ctypes.c_int32)]
+                ("restart", ctypes.c_int32), ("lin_max_iter", ctypes.c_int32), ("jac32", ctypes.c_int32),
+                ("forcing", ctypes.c_int32)]
 
 
 class ens_newton_stat(ctypes.Structure):
@@ -338,9 +339,12 @@ def gmres(g: Graph, values, b, x=None, opts: ens_gmres_opts | None = None, mg=No
     return x, _stats_list(stats, s), st
 
 
-def newton_opts(rtol=1e-8, max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000,
-                jac32=False) -> ens_newton_opts:
-    return ens_newton_opts(rtol, max_newton, lin_rtol, restart, lin_max_iter, int(jac32))
+FORCING_FIXED, FORCING_EW = 0, 1
+
+
+def newton_opts(rtol=1e-8, max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000, jac32=False,
+                forcing=FORCING_FIXED) -> ens_newton_opts:
+    return ens_newton_opts(rtol, max_newton, lin_rtol, restart, lin_max_iter, int(jac32), int(forcing))
 
 
 def newton_workspace_bytes(g: Graph, s: int, opts: ens_newton_opts) -> int:

@@ -101,8 +101,8 @@ def test_headline_workload_refinement(E, orc):
 
 
 def test_newton_workload(E, orc):
-    """128^3, s = 32, Newton with FP32-multigrid-preconditioned GMRES on the
-    FP32 Jacobian, as bench.py times it.  Samples 0 and 31: the oracle evaluates the nonlinear
+    """128^3, s = 32, Newton with adaptive forcing and FP32-multigrid-
+    preconditioned GMRES on the FP32 Jacobian, as bench.py times it.  Samples 0 and 31: the oracle evaluates the nonlinear
     residual of the GPU solution (<= 1e-8 |load|), and the GPU residual and
     Jacobian at that solution element by element (1e-12 of the load, 1e-13
     of the Jacobian's scale)."""
@@ -116,8 +116,9 @@ def test_newton_workload(E, orc):
     K, K32, _ = E.assemble(g, kl, xt, w.M, w.sigma, want32=True)
     mg = E.Multigrid(w.N, w.M, w.s, fp32=True).setup(g, K, xt, w.sigma, values32=K32)
     prob = E.nl_problem(w.M, w.sigma, W.NEWTON_ALPHA, W.NEWTON_BETA, W.NEWTON_VEL)
-    u, stats, st = E.newton(g, kl, xt, prob, opts=E.newton_opts(rtol=w.rtol, lin_rtol=W.NEWTON_LIN_RTOL,
-                                                                restart=W.NEWTON_RESTART, jac32=True),
+    u, stats, st = E.newton(g, kl, xt, prob, opts=E.newton_opts(rtol=w.rtol, lin_rtol=W.NEWTON_ETA_MAX,
+                                                                restart=W.NEWTON_RESTART, jac32=True,
+                                                                forcing=E.FORCING_EW),
                             mg=mg, mg_values=K32)
     assert st == E.ENS_OK, stats
     print(f"GPU done: Newton steps {[t['newton_iters'] for t in stats]}", flush=True)

@@ -279,6 +279,47 @@ def test_newton_with_an_fp32_jacobian(E, orc, prec):
         assert _rel(ug[:, e], ut[:, e]) <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["jacobi", "mg"])
+def test_newton_with_adaptive_forcing_matches_oracle(E, orc, prec):
+    # the per-sample Eisenstat-Walker forcing terms on both sides: equal
+    # Newton steps, GMRES counts within the usual +-2 per step, the root
+    N, s, M, sigma, alpha, beta, rtol = 12, 16, 10, 0.3, 10.0, 100.0, 1e-8
+    xi = draw_xi(4670, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    mg, K = None, None
+    if prec == "mg":
+        K, _, _ = E.assemble(g, kl, xt, M, sigma)
+        mg = _mg(E, N, M, s, g, K, xt, sigma)
+    prob = E.nl_problem(M, sigma, alpha, beta, VEL)
+    u, stats, st = E.newton(g, kl, xt, prob, opts=E.newton_opts(rtol=rtol, lin_rtol=0.3, forcing=E.FORCING_EW),
+                            mg=mg, mg_values=K)
+    assert st == E.ENS_OK, stats
+    pc = orc.PREC_JACOBI if prec == "jacobi" else orc.PREC_MG
+    _, nio, lio, _, sto, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, prec=pc,
+                                            rtol=rtol, lin_rtol=0.3, forcing=orc.FORCING_EW)
+    _, _, lif, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, prec=pc,
+                                        rtol=rtol, lin_rtol=3e-3)
+    ut, _, _, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, prec=pc,
+                                       rtol=1e-13, lin_rtol=1e-12)
+    ug = _np(u)
+    rp, ci = orc.graph(N)
+    Fg, _, ld = orc.ens_nl_assemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, ug,
+                                    want_jac=False)
+    for e in range(s):
+        assert stats[e]["status"] == 0 and sto[e] == 0
+        assert stats[e]["newton_iters"] == nio[e], (e, stats[e], nio[e])
+        assert abs(stats[e]["lin_iters"] - int(lio[e])) <= 2 * nio[e], (e, stats[e], lio[e])
+        assert np.linalg.norm(Fg[:, e]) <= rtol * np.linalg.norm(ld[:, e]) * (1 + 1e-6)
+        assert _rel(ug[:, e], ut[:, e]) <= 1e-6
+    print("GMRES iterations, adaptive vs fixed 3e-3 (oracle):", int(lio.sum()), int(lif.sum()))
+    with pytest.raises(E.EnsError):
+        o = E.newton_opts(forcing=E.FORCING_EW)
+        o.forcing = 2
+        E.newton(g, kl, xt, prob, opts=o)
+
+
 def test_newton_linear_case_is_one_step_to_the_cg_solution(E, orc):
     N, s, M, sigma = 8, 8, 10, 0.3
     xi = draw_xi(4700, s, M)

@@ -71,7 +71,8 @@ NEWTON = Workload("q1_128cube_s32_newton", N=128, s=32, M=10, sigma=0.3, rtol=1e
 NEWTON_ALPHA = 10.0
 NEWTON_BETA = 100.0
 NEWTON_VEL = (3 ** -0.5, 3 ** -0.5, 3 ** -0.5)
-NEWTON_LIN_RTOL = 3e-3   # measured fastest of 1e-2, 3e-3, 1e-3, 1e-4 at 128^3, s = 32
+NEWTON_LIN_RTOL = 3e-3   # fixed forcing: measured fastest of 1e-2, 3e-3, 1e-3, 1e-4 at 128^3, s = 32
+NEWTON_ETA_MAX = 0.3     # Eisenstat-Walker forcing: eta_0 = eta_max
 NEWTON_RESTART = 30
 
 BATCH_MESHES = (32, 48, 64, 96)
