@@ -189,8 +189,9 @@ def run_solve(args):
         return ens.cg(g, vals, rhs, x=x, values32=v32, opts=opts, workspace=ws)
 
     def step_mg():
-        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, values32=v32, rhs=rhs)
-        mg.setup(g, vals, xi, w.sigma, values32=v32, kappa0=w.kappa0, f=w.f)
+        # fine assembly with the hierarchy's fine-level D^-1 and bound fused in,
+        # then the coarse levels
+        mg.assemble_setup(g, kl, xi, w.sigma, vals, rhs, values32=v32, kappa0=w.kappa0, f=w.f)
         x.zero_()
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=mg_opts, workspace=ws)
 
@@ -792,8 +793,7 @@ def run_mg(args):
     log(f"mg workload: N={w.N} s={w.s} hierarchy {mg.buffer.numel() / 2**30:.2f} GiB")
 
     def step():
-        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, values32=v32, rhs=rhs)
-        mg.setup(g, vals, xi, w.sigma, values32=v32, kappa0=w.kappa0, f=w.f)
+        mg.assemble_setup(g, kl, xi, w.sigma, vals, rhs, values32=v32, kappa0=w.kappa0, f=w.f)
         x.zero_()
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=opts, workspace=ws)
 
@@ -908,8 +908,7 @@ def run_newton(args):
         f"hierarchy {mg.buffer.numel() / 2**30:.2f} GiB")
 
     def step():
-        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=K, values32=K32, rhs=rhs)
-        mg.setup(g, K, xi, w.sigma, values32=K32, kappa0=w.kappa0, f=w.f)
+        mg.assemble_setup(g, kl, xi, w.sigma, K, rhs, values32=K32, kappa0=w.kappa0, f=w.f)
         u.zero_()
         return ens.newton(g, kl, xi, prob, u=u, opts=opts, mg=mg, mg_values=K32 if mg32 else K, workspace=ws)
 

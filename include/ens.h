@@ -354,6 +354,14 @@ ens_status ens_mg_build(const ens_mg* mg, double L, hipStream_t stream);
  * matrices must stay unchanged while the hierarchy is used. */
 ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* values, const float* values32,
                         const ens_problem* problem, const double* xi, hipStream_t stream);
+/* ens_assemble of the fine matrix (values, values32, rhs as there; kl from
+ * ens_kl_build(N, M, L)) followed by ens_mg_setup, with the fine level's D^-1
+ * and Gershgorin bound formed inside the assembly (the same values, bitwise,
+ * without a separate pass over the fine matrix).  Arguments and errors as
+ * for the two calls; stream ordered. */
+ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
+                                 const ens_problem* problem, const double* xi, double* values, float* values32,
+                                 double* rhs, hipStream_t stream);
 /* Forget the buffer's built / set-up record (host only, never fails on an
  * unknown buffer).  Call it before the buffer is freed: a later allocation
  * at the same address would otherwise pass as built. */

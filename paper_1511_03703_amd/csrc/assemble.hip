@@ -18,6 +18,7 @@
 // kappa_q = kappa0 + sigma sum_m sqrt(lambda_m) phi_m(x_q) y_m, with the 1D
 // factors of phi_m read from the KL table.
 #include "common.hpp"
+#include "mg.hpp"
 
 namespace ens {
 
@@ -125,14 +126,20 @@ __device__ inline void kl_points(const double* __restrict__ tab, const int32_t* 
 // coefficient is evaluated about a third as often.  LDS rows are padded to
 // SB+1 samples so that neighbouring rows of a wavefront read alternate bank
 // halves.
-template <int S, int SB>
+// BND (fused multigrid set-up of this level): 0 none; 1 D^-1 in FP32 and
+// the Gershgorin bound of the FP32 values; 2 D^-1 and the bound of the FP64
+// values.  Each lane forms its row's sum_j |a_ij| / a_ii in ascending entry
+// order in FP64 exactly as k_mg_diag_bound does, and the workgroup writes
+// the maximum over its rows per sample to bpart[tile][s].
+template <int S, int SB, int BND>
 __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __restrict__ kl_sqrt_lam,
                                                         const int32_t* __restrict__ kl_triple,
                                                         const double* __restrict__ kl_phi, int M, double kappa0,
                                                         double sigma, double fsrc, const double* __restrict__ xi,
                                                         const int32_t* __restrict__ row_ptr,
                                                         double* __restrict__ values, float* __restrict__ values32,
-                                                        double* __restrict__ rhs) {
+                                                        double* __restrict__ rhs, void* __restrict__ dinv,
+                                                        double* __restrict__ bpart) {
   constexpr int R = 256 / SB;  // rows per workgroup
   constexpr int TZ = 4, TX = R / TZ;
   constexpr int EX = TX + 1, NE = EX * 2 * (TZ + 1);
@@ -158,6 +165,7 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
     sg = (int)(G > 1 ? rest % G : 0);
     tile = (G > 1 ? (tiles / 8) * 8 + rest / G : bid);
   }
+  const int64_t tile_id = tile;
   const int xt = (int)(tile % ntx);
   tile /= ntx;
   const int zt = (int)(tile % ntz);
@@ -186,7 +194,10 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
   const int r = threadIdx.x / SB, sb = threadIdx.x % SB;
   const int rx = r % TX, rz = r / TX;
   const int ii = x0 + rx, jj = y, kk = z0 + rz;
-  if (ii > N || kk > N) return;
+  const bool live = ii <= N && kk <= N;
+  if (!BND && !live) return;
+  double qrow = 0.0;  // this row's Gershgorin ratio (BND)
+  if (live) {
   const int e = e0 + sb;
   const int64_t row = (int64_t)ii + n1 * ((int64_t)jj + (int64_t)n1 * kk);
 
@@ -222,6 +233,7 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
   const bool bnd_row = (ii == 0 || ii == N || jj == 0 || jj == N || kk == 0 || kk == N);
   const int64_t start = row_ptr[row];
   int pos = 0;
+  double sabs = 0.0, dg = 0.0;
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
@@ -238,9 +250,31 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
         const int64_t k = (start + pos) * S + e;
         values[k] = v;
         if (values32) values32[k] = (float)v;
+        if (BND) {
+          const double vc = BND == 1 ? (double)(float)v : v;  // the value the cycle runs on
+          sabs += fabs(vc);
+          if (slot27 == 13) dg = vc;
+        }
         ++pos;
       }
   rhs[row * S + e] = bnd_row ? 0.0 : (double)nelem * (fsrc * h * h * h * 0.125);
+  if (BND == 1) ((float*)dinv)[row * S + e] = 1.0f / (float)dg;
+  if (BND == 2) ((double*)dinv)[row * S + e] = 1.0 / dg;
+  if (BND) qrow = sabs / dg;
+  }
+  if (BND) {
+    __shared__ double s_q[256];
+    s_q[threadIdx.x] = qrow;
+    __syncthreads();
+    if (threadIdx.x < SB) {
+      double m = 0.0;
+      for (int rr = 0; rr < R; ++rr) {
+        const double q = s_q[rr * SB + threadIdx.x];
+        m = q > m ? q : m;
+      }
+      bpart[tile_id * S + e0 + threadIdx.x] = m;
+    }
+  }
 }
 
 // Residual and Jacobian of the nonlinear problem (Sec. 4, Eq.
@@ -377,6 +411,62 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
   if (load) load[row * S + e] = bnd_row ? 0.0 : la;
 }
 
+// Sample groups per tile: 8 samples per workgroup, all of them for s = 4.
+static constexpr int asm_sb(int S) { return S < 8 ? S : 8; }
+
+int64_t asm_tiles(int N, int S) {
+  const int TX = (256 / asm_sb(S)) / 4;
+  return (int64_t)((N + TX) / TX) * ((N + 4) / 4) * (N + 1);
+}
+
+ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, const int32_t* tr, const double* phi,
+                           const ens_problem* prob, int s, const double* xi, double* values, float* values32,
+                           double* rhs, int bnd, void* dinv, double* bpart, hipStream_t stream) {
+  int64_t n = 0, nnz = 0;
+  ens_status st = ens_mesh_sizes(N, &n, &nnz, nullptr);
+  if (st != ENS_OK) return st;
+  int dev = 0;
+  ENS_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 64 && !g_G_ready[dev]) {
+    ENS_HIP_TRY(upload_G());
+    g_G_ready[dev] = true;
+  }
+  const int M = prob->M;
+  prof_begin(ENS_K_ASSEMBLE, stream);
+  switch (s) {
+#define ENS_ASM_LAUNCH(SS, SB, BB)                                                                              \
+  hipLaunchKernelGGL((k_assemble_tile<SS, SB, BB>), dim3((unsigned)(asm_tiles(N, SS) * (SS / SB))), dim3(256), 0, \
+                     stream, N, sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values,   \
+                     values32, rhs, dinv, bpart)
+#define ENS_ASM_CASE(SS)                                             \
+  case SS:                                                           \
+    if (bnd == 1) ENS_ASM_LAUNCH(SS, asm_sb(SS), 1);                 \
+    else if (bnd == 2) ENS_ASM_LAUNCH(SS, asm_sb(SS), 2);            \
+    else ENS_ASM_LAUNCH(SS, asm_sb(SS), 0);                          \
+    break;
+    ENS_ASM_CASE(4)
+    ENS_ASM_CASE(8)
+    ENS_ASM_CASE(16)
+    ENS_ASM_CASE(32)
+#undef ENS_ASM_CASE
+#undef ENS_ASM_LAUNCH
+  }
+  ENS_LAUNCH_CHECK();
+  double bytes = (double)nnz * s * (8.0 + (values32 ? 4.0 : 0.0)) + (double)n * s * 8.0 + 4.0 * (n + 1);
+  if (bnd) bytes += (double)n * s * (bnd == 1 ? 4.0 : 8.0);
+  prof_end(ENS_K_ASSEMBLE, stream, bytes);
+  return ENS_OK;
+}
+
+// The KL table's parts (layout of ens_kl_build).
+void kl_parts(const void* kl, int M, const double** sq, const int32_t** tr, const double** phi) {
+  const char* base = (const char*)kl;
+  const size_t phi_off = ((size_t)M * 5 * sizeof(double) + (size_t)M * 4 * sizeof(int32_t) + 15) & ~(size_t)15;
+  *sq = (const double*)base;
+  *tr = (const int32_t*)(base + (size_t)M * 5 * sizeof(double) + (size_t)M * sizeof(int32_t));
+  *phi = (const double*)(base + phi_off);
+}
+
 }  // namespace ens
 
 using namespace ens;
@@ -397,39 +487,10 @@ extern "C" ens_status ens_assemble(int32_t N, const ens_graph* graph, const void
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
   }
-  int dev = 0;
-  ENS_HIP_TRY(hipGetDevice(&dev));
-  if (dev < 64 && !g_G_ready[dev]) {
-    ENS_HIP_TRY(upload_G());
-    g_G_ready[dev] = true;
-  }
-  const int M = prob->M;
-  const char* base = (const char*)kl;
-  // KL table layout (see ens_kl_build): sqrt_lam3 at 0, triple at 5M doubles + M ints
-  size_t phi_off = ((size_t)M * 5 * sizeof(double) + (size_t)M * 4 * sizeof(int32_t) + 15) & ~(size_t)15;
-  const double* sq = (const double*)base;
-  const int32_t* tr = (const int32_t*)(base + (size_t)M * 5 * sizeof(double) + (size_t)M * sizeof(int32_t));
-  const double* phi = (const double*)(base + phi_off);
-  prof_begin(ENS_K_ASSEMBLE, stream);
-  switch (s) {
-#define ENS_ASM_CASE(SS, SB)                                                                                 \
-  case SS: {                                                                                                 \
-    constexpr int R = 256 / SB, TX = R / 4;                                                                  \
-    const int64_t tiles = (int64_t)((N + TX) / TX) * ((N + 4) / 4) * (N + 1) * (SS / SB);                    \
-    hipLaunchKernelGGL((k_assemble_tile<SS, SB>), dim3((unsigned)tiles), dim3(256), 0, stream, N, sq, tr, phi,  \
-                       M, prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values, values32, rhs);      \
-    break;                                                                                                   \
-  }
-    ENS_ASM_CASE(4, 4)
-    ENS_ASM_CASE(8, 8)
-    ENS_ASM_CASE(16, 8)
-    ENS_ASM_CASE(32, 8)
-#undef ENS_ASM_CASE
-  }
-  ENS_LAUNCH_CHECK();
-  double bytes = (double)nnz * s * (8.0 + (values32 ? 4.0 : 0.0)) + (double)n * s * 8.0 + 4.0 * (n + 1);
-  prof_end(ENS_K_ASSEMBLE, stream, bytes);
-  return ENS_OK;
+  const double *sq = nullptr, *phi = nullptr;
+  const int32_t* tr = nullptr;
+  kl_parts(kl, prob->M, &sq, &tr, &phi);
+  return assemble_launch(N, graph, sq, tr, phi, prob, s, xi, values, values32, rhs, 0, nullptr, nullptr, stream);
 }
 
 extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const void* kl,

@@ -132,6 +132,8 @@ bool mg_plan(int N, int M, int S, int fp32, char* base, MgPlan* plan) {
   if (c.m > kMgMaxCoarse) return false;
   c.ainv = (double*)take(sizeof(double) * S * (c.m > 0 ? c.m * c.m : 1));
   plan->part = (double*)take(sizeof(double) * kMgPartRows * S);
+  // per-tile bound maxima of the fine level when its assembly forms them
+  plan->fine_part = (double*)take(sizeof(double) * (size_t)asm_tiles(N, S) * S);
   plan->bytes = off;
   return true;
 }
@@ -191,6 +193,29 @@ __global__ __launch_bounds__(256) void k_mg_diag_bound(int64_t n, const int32_t*
     double t = red[0][e];
     for (int j = 1; j < G; ++j) t = red[j][e] > t ? red[j][e] : t;
     part[(int64_t)blockIdx.x * S + e] = t;
+  }
+}
+
+// First stage of a long maximum: workgroup b takes the b-th contiguous
+// range of rows and writes its per-sample maximum to out[b][S].
+template <int S>
+__global__ __launch_bounds__(1024) void k_mg_max_stage(const double* __restrict__ part, int64_t rows,
+                                                       double* __restrict__ out) {
+  constexpr int G = 1024 / S;
+  __shared__ double red[G][S];
+  const int e = threadIdx.x % S, g = threadIdx.x / S;
+  const int64_t r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
+  double t = 0.0;
+  for (int64_t r = r0 + g; r < r1; r += G) {
+    const double v = part[r * S + e];
+    t = v > t ? v : t;
+  }
+  red[g][e] = t;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double u = red[0][e];
+    for (int j = 1; j < G; ++j) u = red[j][e] > u ? red[j][e] : u;
+    out[(int64_t)blockIdx.x * S + e] = u;
   }
 }
 
@@ -510,14 +535,27 @@ static ens_status build(const MgPlan& P, int M, double L, hipStream_t st) {
   return ENS_OK;
 }
 
+// fine_done: the fine level's D^-1 and per-tile bound maxima were formed by
+// its assembly (ens_mg_assemble_setup); only their maximum is taken here.
 template <int S>
-static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* xi, hipStream_t st) {
+static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* xi, hipStream_t st,
+                        bool fine_done = false) {
   for (int k = 0; k < P.levels; ++k) {
     const MgLevel& l = P.lv[k];
     if (k > 0) {
       ens_graph g{(int32_t)l.n, l.nnz, l.own_rp, l.own_ci};
       ens_status rc = ens_assemble(l.N, &g, l.kl, &prob, S, xi, l.own_vals, l.own_vals32, (double*)l.b, st);
       if (rc != ENS_OK) return rc;
+    }
+    if (k == 0 && fine_done) {
+      // maximum of the per-tile maxima in two stages (exact in any order)
+      const int64_t rows = asm_tiles(l.N, S);
+      int64_t g1 = rows / 256;
+      if (g1 < 1) g1 = 1;
+      if (g1 > 256) g1 = 256;
+      hipLaunchKernelGGL(k_mg_max_stage<S>, dim3((unsigned)g1), dim3(1024), 0, st, P.fine_part, rows, P.part);
+      hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(1024), 0, st, P.part, (int)g1, l.lmax);
+      continue;
     }
     const unsigned gb = blocks_for(l.n, 256 / S) < (unsigned)kMgPartRows ? blocks_for(l.n, 256 / S) : kMgPartRows;
     if (P.fp32)  // the FP32 cycle's own matrix: its D^-1 and its bound
@@ -605,6 +643,51 @@ ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* 
     case 8: rc = setup<8>(plan, *problem, xi, stream); break;
     case 16: rc = setup<16>(plan, *problem, xi, stream); break;
     default: rc = setup<32>(plan, *problem, xi, stream); break;
+  }
+  if (rc == ENS_OK) mg_mark(mg, Lb, 2);
+  return rc;
+}
+
+ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
+                                 const ens_problem* problem, const double* xi, double* values, float* values32,
+                                 double* rhs, hipStream_t stream) {
+  ENS_ARG_CHECK(mg && graph && kl && problem && xi && values && rhs && mg->buffer, "null argument");
+  ENS_ARG_CHECK(((uintptr_t)mg->buffer & 255u) == 0, "multigrid buffer must be 256-byte aligned");
+  ENS_ARG_CHECK(aligned16(values) && aligned16(rhs), "values and rhs must be 16-byte aligned");
+  ENS_ARG_CHECK(!mg->fp32 || (values32 && aligned16(values32)), "an FP32 cycle needs the FP32 fine matrix");
+  ENS_ARG_CHECK(problem->M == mg->M && problem->M >= 0 && problem->M <= 16, "problem->M differs or is out of range");
+  int64_t n = 0, nnz = 0;
+  ens_status rc = ens_mesh_sizes(mg->N, &n, &nnz, nullptr);
+  if (rc != ENS_OK) return rc;
+  ENS_ARG_CHECK(graph->n == n && graph->nnz == nnz && graph->row_ptr && graph->col_idx,
+                "graph is not the N^3 mesh's graph");
+  size_t need = 0;
+  rc = ens_mg_bytes(mg->N, mg->M, mg->s, mg->fp32, &need);
+  if (rc != ENS_OK) return rc;
+  if (mg->bytes < need) {
+    set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, need);
+    return ENS_E_NOMEM;
+  }
+  const double Lb = mg_built_L(mg);
+  if (Lb <= 0.0) {
+    set_error("multigrid buffer not built: call ens_mg_build first");
+    return ENS_E_ARG;
+  }
+  ENS_ARG_CHECK(problem->L == Lb, "problem->L differs from the correlation length the hierarchy was built for");
+  MgPlan plan;
+  mg_plan(mg->N, mg->M, mg->s, mg->fp32 != 0, (char*)mg->buffer, &plan);
+  mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values, mg->fp32 ? values32 : nullptr);
+  const double *sq = nullptr, *phi = nullptr;
+  const int32_t* tr = nullptr;
+  kl_parts(kl, problem->M, &sq, &tr, &phi);
+  rc = assemble_launch(mg->N, graph, sq, tr, phi, problem, mg->s, xi, values, values32, rhs, mg->fp32 ? 1 : 2,
+                       plan.lv[0].dinv, plan.fine_part, stream);
+  if (rc != ENS_OK) return rc;
+  switch (mg->s) {
+    case 4: rc = setup<4>(plan, *problem, xi, stream, true); break;
+    case 8: rc = setup<8>(plan, *problem, xi, stream, true); break;
+    case 16: rc = setup<16>(plan, *problem, xi, stream, true); break;
+    default: rc = setup<32>(plan, *problem, xi, stream, true); break;
   }
   if (rc == ENS_OK) mg_mark(mg, Lb, 2);
   return rc;

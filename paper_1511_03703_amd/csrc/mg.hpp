@@ -40,8 +40,19 @@ struct MgPlan {
   int fp32 = 0;  // cycle in FP32 (vectors, D^-1 and matrices)
   MgLevel lv[kMgMaxLevels];
   double* part = nullptr;  // [kMgPartRows][S] scratch of the bound reduction
+  double* fine_part = nullptr;  // [tiles][S] fine-level bound maxima formed by the assembly
   size_t bytes = 0;
 };
+
+// The tiled assembly (assemble.hip): tiles of the N^3 mesh for s samples
+// (the rows of a fused bound's partial array), the launcher with an optional
+// fused D^-1 and bound (bnd 1: FP32, 2: FP64; dinv of that type, bpart
+// [tiles][s]), and the parts of a KL table.
+int64_t asm_tiles(int N, int S);
+ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, const int32_t* tr, const double* phi,
+                           const ens_problem* prob, int s, const double* xi, double* values, float* values32,
+                           double* rhs, int bnd, void* dinv, double* bpart, hipStream_t stream);
+void kl_parts(const void* kl, int M, const double** sq, const int32_t** tr, const double** phi);
 
 int mg_levels(int N, int* Ns);
 // 0: buffer unknown; 1: built (ens_mg_build); 2: set up (ens_mg_setup).

@@ -122,6 +122,8 @@ _SIGS = [
     ("ens_mg_build", _I32, [ctypes.POINTER(ens_mg), ctypes.c_double, _P]),
     ("ens_mg_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, _P, ctypes.POINTER(ens_problem), _P, _P]),
     ("ens_mg_release", _I32, [ctypes.POINTER(ens_mg)]),
+    ("ens_mg_assemble_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_problem), _P, _P, _P, _P,
+                                     _P]),
     ("ens_cg_mg", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(ens_mg), _P, _SZ,
                          ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_scalar_cg_concurrent_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(_SZ)]),
@@ -477,6 +479,18 @@ class Multigrid:
             lib().ens_mg_release(ctypes.byref(self.desc))
         except Exception:
             pass
+
+    def assemble_setup(self, g: Graph, kl, xi, sigma, values, rhs, values32=None, kappa0=1.0, f=1.0, stream=None):
+        """Assemble the fine matrix into values (values32), rhs and set the
+        hierarchy up in one call, the fine level's D^-1 and bound formed by
+        the assembly."""
+        prob = ens_problem(self.desc.M, self.L, kappa0, sigma, f)
+        gc = g.c()
+        self._values = (values, values32)
+        _check(lib().ens_mg_assemble_setup(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(kl), ctypes.byref(prob),
+                                           _ptr(xi), _ptr(values), _ptr(values32), _ptr(rhs), _stream(stream)),
+               "ens_mg_assemble_setup")
+        return self
 
     def setup(self, g: Graph, values, xi, sigma, values32=None, L=None, kappa0=1.0, f=1.0, stream=None):
         if L is not None and L != self.L:

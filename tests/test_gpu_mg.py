@@ -166,3 +166,27 @@ def test_mixed_refinement_with_fp32_multigrid(E, orc, N, s):
         E.cg_mg(g, vals, rhs, mg64, values32=v32, opts=E.cg_opts(mixed=True))
     with pytest.raises(E.EnsError):
         E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts())
+
+
+@pytest.mark.parametrize("N,s,fp32", [(16, 32, True), (12, 8, False), (8, 4, True), (20, 16, False)])
+def test_fused_assembly_and_setup_equal_the_two_calls(E, N, s, fp32):
+    # the fine level's D^-1 and bound formed inside the assembly are the
+    # separate pass's bitwise: the same matrices, loads and solve
+    M, sigma = 10, 0.3
+    xi = draw_xi(1490 + N, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    vals, v32, rhs = E.assemble(g, kl, xt, M, sigma, want32=fp32)
+    mg1 = E.Multigrid(N, M, s, fp32=fp32).setup(g, vals, xt, sigma, values32=v32)
+    vals2 = torch.full_like(vals, float("nan"))
+    v322 = torch.full_like(v32, float("nan")) if fp32 else None
+    rhs2 = torch.full_like(rhs, float("nan"))
+    mg2 = E.Multigrid(N, M, s, fp32=fp32).assemble_setup(g, kl, xt, sigma, vals2, rhs2, values32=v322)
+    assert torch.equal(vals, vals2) and torch.equal(rhs, rhs2)
+    if fp32:
+        assert torch.equal(v32, v322)
+    opts = E.cg_opts(rtol=1e-8 if fp32 else 1e-10, mixed=fp32, check_every=4)
+    x1, st1, _ = E.cg_mg(g, vals, rhs, mg1, values32=v32, opts=opts)
+    x2, st2, _ = E.cg_mg(g, vals2, rhs2, mg2, values32=v322, opts=opts)
+    assert torch.equal(x1, x2) and st1 == st2
