@@ -132,8 +132,10 @@ bool mg_plan(int N, int M, int S, int fp32, char* base, MgPlan* plan) {
   if (c.m > kMgMaxCoarse) return false;
   c.ainv = (double*)take(sizeof(double) * S * (c.m > 0 ? c.m * c.m : 1));
   plan->part = (double*)take(sizeof(double) * kMgPartRows * S);
-  // per-tile bound maxima of the fine level when its assembly forms them
-  plan->fine_part = (double*)take(sizeof(double) * (size_t)asm_tiles(N, S) * S);
+  // per-tile bound maxima of each level, formed by its assembly (the fine
+  // level's only with ens_mg_assemble_setup)
+  for (int k = 0; k < plan->levels; ++k)
+    plan->lv[k].tpart = (double*)take(sizeof(double) * (size_t)asm_tiles(plan->lv[k].N, S) * S);
   plan->bytes = off;
   return true;
 }
@@ -543,17 +545,23 @@ static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* 
   for (int k = 0; k < P.levels; ++k) {
     const MgLevel& l = P.lv[k];
     if (k > 0) {
+      // the coarse operator, with its D^-1 and per-tile bounds formed by the
+      // assembly
       ens_graph g{(int32_t)l.n, l.nnz, l.own_rp, l.own_ci};
-      ens_status rc = ens_assemble(l.N, &g, l.kl, &prob, S, xi, l.own_vals, l.own_vals32, (double*)l.b, st);
+      const double *sq = nullptr, *phi = nullptr;
+      const int32_t* tr = nullptr;
+      kl_parts(l.kl, prob.M, &sq, &tr, &phi);
+      ens_status rc = assemble_launch(l.N, &g, sq, tr, phi, &prob, S, xi, l.own_vals, l.own_vals32, (double*)l.b,
+                                      P.fp32 ? 1 : 2, l.dinv, l.tpart, st);
       if (rc != ENS_OK) return rc;
     }
-    if (k == 0 && fine_done) {
+    if (k > 0 || fine_done) {
       // maximum of the per-tile maxima in two stages (exact in any order)
       const int64_t rows = asm_tiles(l.N, S);
       int64_t g1 = rows / 256;
       if (g1 < 1) g1 = 1;
       if (g1 > 256) g1 = 256;
-      hipLaunchKernelGGL(k_mg_max_stage<S>, dim3((unsigned)g1), dim3(1024), 0, st, P.fine_part, rows, P.part);
+      hipLaunchKernelGGL(k_mg_max_stage<S>, dim3((unsigned)g1), dim3(1024), 0, st, l.tpart, rows, P.part);
       hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(1024), 0, st, P.part, (int)g1, l.lmax);
       continue;
     }
@@ -681,7 +689,7 @@ ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const
   const int32_t* tr = nullptr;
   kl_parts(kl, problem->M, &sq, &tr, &phi);
   rc = assemble_launch(mg->N, graph, sq, tr, phi, problem, mg->s, xi, values, values32, rhs, mg->fp32 ? 1 : 2,
-                       plan.lv[0].dinv, plan.fine_part, stream);
+                       plan.lv[0].dinv, plan.lv[0].tpart, stream);
   if (rc != ENS_OK) return rc;
   switch (mg->s) {
     case 4: rc = setup<4>(plan, *problem, xi, stream, true); break;

@@ -33,6 +33,7 @@ struct MgLevel {
   void *b = nullptr, *xa = nullptr, *xb = nullptr, *r = nullptr, *d = nullptr;  // cycle precision
   int64_t m = 0;           // coarsest level: interior unknowns
   double* ainv = nullptr;  // coarsest level: [S][m][m]
+  double* tpart = nullptr; // [tiles][S] bound maxima per assembly tile
 };
 
 struct MgPlan {
@@ -40,7 +41,6 @@ struct MgPlan {
   int fp32 = 0;  // cycle in FP32 (vectors, D^-1 and matrices)
   MgLevel lv[kMgMaxLevels];
   double* part = nullptr;  // [kMgPartRows][S] scratch of the bound reduction
-  double* fine_part = nullptr;  // [tiles][S] fine-level bound maxima formed by the assembly
   size_t bytes = 0;
 };
 
