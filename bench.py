@@ -930,10 +930,10 @@ def run_newton(args):
     ens.prof_enable(False)
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
     kernels = {f"k_mg_row<{'float' if mg32 else 'double'},32,*> (fine-level V-cycle passes)": ens.K_MG_ROW,
-               "k_nl_assemble<32,1> (residual and Jacobian)": ens.K_NL_ASSEMBLE,
+               "k_nl_assemble<32,8,*> (residual and Jacobian)": ens.K_NL_ASSEMBLE,
                "k_gm_spmv<32> (GMRES product w = A z)": ens.K_GM_SPMV,
                "k_gm_dots/k_gm_axpy<32> (Gram-Schmidt passes)": ens.K_GM_ORTH,
-               "k_assemble<32,1> (diffusion matrix for the preconditioner)": ens.K_ASSEMBLE}
+               "k_assemble_tile<32,8,*> (diffusion matrix for the preconditioner)": ens.K_ASSEMBLE}
     prof = {k: ens.prof_query(v) for k, v in kernels.items()}
     per_kernel = {k: {"ms_per_step": round(p["total_ms"] / args.steps, 3), "launches": p["launches"],
                       "GBs": round(p["bytes"] / (p["total_ms"] * 1e-3) / 1e9, 1) if p["launches"] else None}

@@ -116,6 +116,33 @@ __device__ inline void kl_points(const double* __restrict__ tab, const int32_t* 
   for (int q = 0; q < 8; ++q) kq[q] = kappa0 + kq[q];
 }
 
+// Workgroup index -> (tile, sample group) of the TX x TZ node patches of
+// one y-plane.  Workgroups are dealt to the 8 XCDs round-robin by index; the
+// G sample groups of one tile take indices 8 apart (same XCD, dispatched
+// together) so their partial writes of each row's sample ensemble meet in
+// one L2.
+template <int TX, int TZ, int G>
+__device__ inline void tile_decode(int N, int64_t bid, int64_t* tile_id, int* sg, int* x0, int* y, int* z0) {
+  const int n1 = N + 1;
+  const int ntx = (n1 + TX - 1) / TX, ntz = (n1 + TZ - 1) / TZ;
+  const int64_t tiles = (int64_t)ntx * ntz * n1;
+  int64_t tile;
+  if (G > 1 && (bid / (8 * G)) < tiles / 8) {
+    const int64_t blk = bid / (8 * G), rem = bid % (8 * G);
+    *sg = (int)(rem / 8);
+    tile = blk * 8 + rem % 8;
+  } else {
+    const int64_t rest = bid - (tiles / 8) * 8 * G;  // the last tiles % 8 tiles, plainly
+    *sg = (int)(G > 1 ? rest % G : 0);
+    tile = (G > 1 ? (tiles / 8) * 8 + rest / G : bid);
+  }
+  *tile_id = tile;
+  *x0 = (int)(tile % ntx) * TX;
+  tile /= ntx;
+  *z0 = (int)(tile % ntz) * TZ;
+  *y = (int)(tile / ntz);
+}
+
 // Tiled form of the same assembly: a workgroup owns a TX x TZ patch of
 // nodes in one y-plane for SB of the samples.  It first evaluates the
 // coefficient (times h/8) at the 8 Gauss points of each of the
@@ -149,28 +176,10 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
   __shared__ double s_cm[SB * kAsmMaxM];
   __shared__ double s_k[NE * 8 * PS];  // [element][q][sample]
   const int n1 = N + 1;
-  const int ntx = (n1 + TX - 1) / TX, ntz = (n1 + TZ - 1) / TZ;
-  // Workgroups are dealt to the 8 XCDs round-robin by index; the G sample
-  // groups of one tile take indices 8 apart (same XCD, dispatched together)
-  // so their partial writes of each row's sample ensemble meet in one L2.
-  const int64_t tiles = (int64_t)ntx * ntz * n1;
-  int64_t bid = blockIdx.x, tile;
-  int sg;
-  if (G > 1 && (bid / (8 * G)) < tiles / 8) {
-    const int64_t blk = bid / (8 * G), rem = bid % (8 * G);
-    sg = (int)(rem / 8);
-    tile = blk * 8 + rem % 8;
-  } else {
-    const int64_t rest = bid - (tiles / 8) * 8 * G;  // the last tiles % 8 tiles, plainly
-    sg = (int)(G > 1 ? rest % G : 0);
-    tile = (G > 1 ? (tiles / 8) * 8 + rest / G : bid);
-  }
-  const int64_t tile_id = tile;
-  const int xt = (int)(tile % ntx);
-  tile /= ntx;
-  const int zt = (int)(tile % ntz);
-  const int y = (int)(tile / ntz);
-  const int x0 = xt * TX, z0 = zt * TZ, e0 = sg * SB;
+  int64_t tile_id;
+  int sg, x0, y, z0;
+  tile_decode<TX, TZ, G>(N, blockIdx.x, &tile_id, &sg, &x0, &y, &z0);
+  const int e0 = sg * SB;
   for (int t = threadIdx.x; t < SB * M; t += blockDim.x) {
     const int ee = t / M, m = t % M;
     s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + ee) * M + m];
@@ -293,7 +302,7 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
 // so no gradient of u_h is formed.  Boundary rows: F = u and identity rows;
 // boundary columns of interior rows stored as zeros; load (optional) = the
 // source part of F.
-template <int S, int LDS, bool JAC>
+template <int S, int SB, bool JAC>
 __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __restrict__ kl_sqrt_lam,
                                                       const int32_t* __restrict__ kl_triple,
                                                       const double* __restrict__ kl_phi, int M, double kappa0,
@@ -303,13 +312,22 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
                                                       const double* __restrict__ u, double* __restrict__ values,
                                                       float* __restrict__ values32, double* __restrict__ F,
                                                       double* __restrict__ load) {
-  constexpr int RPB = 256 / S;
-  __shared__ double s_cm[S * kAsmMaxM];
+  // the workgroup tiling of k_assemble_tile; the coefficient kept raw
+  // (kappa0 + sum) in LDS, unpadded, for three workgroups per CU
+  constexpr int R = 256 / SB;
+  constexpr int TZ = 4, TX = R / TZ;
+  constexpr int EX = TX + 1, NE = EX * 2 * (TZ + 1);
+  constexpr int G = S / SB;
+  __shared__ double s_cm[SB * kAsmMaxM];
   __shared__ double s_adv[8][8];  // C_ab = sum_q N_a (v . dN_b)
-  extern __shared__ double s_phi[];
-  for (int t = threadIdx.x; t < S * M; t += blockDim.x) {
+  __shared__ double s_k[NE * 8 * SB];
+  int64_t tile_id;
+  int sg, x0, y, z0;
+  tile_decode<TX, TZ, G>(N, blockIdx.x, &tile_id, &sg, &x0, &y, &z0);
+  const int e0 = sg * SB;
+  for (int t = threadIdx.x; t < SB * M; t += blockDim.x) {
     const int ee = t / M, m = t % M;
-    s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)ee * M + m];
+    s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + ee) * M + m];
   }
   if (threadIdx.x < 64) {
     const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
@@ -318,23 +336,32 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
       c += c_N[q][a] * (vx * c_dN[q][b][0] + vy * c_dN[q][b][1] + vz * c_dN[q][b][2]);
     s_adv[a][b] = c;
   }
-  if (LDS)
-    for (int t = threadIdx.x; t < M * 2 * N; t += blockDim.x) s_phi[t] = kl_phi[t];
   __syncthreads();
-  const double* tab = LDS ? s_phi : kl_phi;
+  const int64_t two_n = 2 * (int64_t)N;
+  for (int p = threadIdx.x; p < NE * SB; p += blockDim.x) {
+    const int le = p / SB, sb = p % SB;
+    const int lx = le % EX, ly = (le / EX) % 2, lz = le / (2 * EX);
+    const int ex = x0 - 1 + lx, ey = y - 1 + ly, ez = z0 - 1 + lz;
+    if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
+    double kq[8];
+    kl_points(kl_phi, kl_triple, s_cm + sb * M, M, two_n, ex, ey, ez, kappa0, kq);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s_k[(le * 8 + q) * SB + sb] = kq[q];
+  }
+  __syncthreads();
 
   const int n1 = N + 1;
-  const int64_t n = (int64_t)n1 * n1 * n1;
-  const int e = threadIdx.x % S;
-  const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / S;
-  if (row >= n) return;
-  const int ii = (int)(row % n1), jj = (int)((row / n1) % n1), kk = (int)(row / ((int64_t)n1 * n1));
+  const int rr = threadIdx.x / SB, sbl = threadIdx.x % SB;
+  const int rx = rr % TX, rz = rr / TX;
+  const int ii = x0 + rx, jj = y, kk = z0 + rz;
+  if (ii > N || kk > N) return;
+  const int e = e0 + sbl;
+  const int64_t row = (int64_t)ii + n1 * ((int64_t)jj + (int64_t)n1 * kk);
   const double h = 1.0 / (double)N;
   const double wd = h * 0.125;             // diffusion: w_q / h^2
   const double wa = h * h * 0.125 * alpha; // advection: alpha w_q / h
   const double wr = h * h * h * 0.125;     // reaction and source: w_q
   const double wb = wr * beta;
-  const int64_t two_n = 2 * (int64_t)N;
 
   double acc[27];
 #pragma unroll
@@ -350,8 +377,10 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
         const int ex = ii + ex_off, ey = jj + ey_off, ez = kk + ez_off;
         if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
         const int ai = (-ex_off) + 2 * (-ey_off) + 4 * (-ez_off);
+        const int le = (rx + 1 + ex_off) + EX * ((1 + ey_off) + 2 * (rz + 1 + ez_off));
         double kq[8];
-        kl_points(tab, kl_triple, s_cm + e * M, M, two_n, ex, ey, ez, kappa0, kq);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) kq[q] = s_k[(le * 8 + q) * SB + sbl];
         double ue[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -517,30 +546,19 @@ extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const v
     g_G_ready[dev] = true;
   }
   const int M = prob->M;
-  const char* base = (const char*)kl;
-  size_t phi_off = ((size_t)M * 5 * sizeof(double) + (size_t)M * 4 * sizeof(int32_t) + 15) & ~(size_t)15;
-  const double* sq = (const double*)base;
-  const int32_t* tr = (const int32_t*)(base + (size_t)M * 5 * sizeof(double) + (size_t)M * sizeof(int32_t));
-  const double* phi = (const double*)(base + phi_off);
-  const int rpb = 256 / s;
-  const int64_t blocks = (n + rpb - 1) / rpb;
-  const size_t table = (size_t)M * 2 * N * sizeof(double);
-  const size_t lds_bytes = table > 0 && table <= 48 * 1024 ? table : 0;
+  const double *sq, *phi;
+  const int32_t* tr;
+  kl_parts(kl, M, &sq, &tr, &phi);
   prof_begin(ENS_K_NL_ASSEMBLE, stream);
   switch (s) {
-#define ENS_NL_LAUNCH(SS, LL, JJ)                                                                                \
-  hipLaunchKernelGGL((k_nl_assemble<SS, LL, JJ>), dim3((unsigned)blocks), dim3(256), LL ? lds_bytes : 0, stream, N, \
-                     sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, prob->alpha, prob->beta, prob->vx,         \
-                     prob->vy, prob->vz, xi, graph->row_ptr, u, values, values32, F, load)
-#define ENS_NL_CASE(SS)                                                     \
-  case SS:                                                                  \
-    if (lds_bytes) {                                                        \
-      if (values || values32) ENS_NL_LAUNCH(SS, 1, true);                   \
-      else ENS_NL_LAUNCH(SS, 1, false);                                     \
-    } else {                                                                \
-      if (values || values32) ENS_NL_LAUNCH(SS, 0, true);                   \
-      else ENS_NL_LAUNCH(SS, 0, false);                                     \
-    }                                                                       \
+#define ENS_NL_LAUNCH(SS, JJ)                                                                                     \
+  hipLaunchKernelGGL((k_nl_assemble<SS, asm_sb(SS), JJ>), dim3((unsigned)(asm_tiles(N, SS) * (SS / asm_sb(SS)))),   \
+                     dim3(256), 0, stream, N, sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, prob->alpha,      \
+                     prob->beta, prob->vx, prob->vy, prob->vz, xi, graph->row_ptr, u, values, values32, F, load)
+#define ENS_NL_CASE(SS)                                  \
+  case SS:                                               \
+    if (values || values32) ENS_NL_LAUNCH(SS, true);     \
+    else ENS_NL_LAUNCH(SS, false);                       \
     break;
     ENS_NL_CASE(4)
     ENS_NL_CASE(8)
