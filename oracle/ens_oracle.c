@@ -891,7 +891,8 @@ typedef struct {
   double *b, *x, *r, *d, *ax;
   int64_t m;        /* coarsest level: interior unknowns */
   int64_t *imap;    /* coarsest level: interior node ids */
-  double *chol;     /* coarsest level: Cholesky factor of the interior block */
+  double *chol;     /* coarsest level: Cholesky factor (lu: LU factors) of the interior block */
+  int lu;
 } orc_level;
 
 static void free_levels(orc_level *lv, int L) {
@@ -931,10 +932,51 @@ static void chol_solve(int64_t m, const double *Lf, const double *b, double *x) 
   }
 }
 
+int orc_nl_assemble_scalar(int N, const int32_t *row_ptr, const int32_t *col_idx, const double *acoef,
+                           double fconst, double alpha, const double *vel, double beta, const double *u,
+                           double *F, double *values, double *load);
+
+/* Doolittle LU of a dense m x m matrix in place, without pivoting (unit
+ * lower factor below the diagonal, upper factor on and above it).  Used for
+ * matrices whose symmetric part is positive definite, whose pivots are then
+ * all positive; a pivot that is not is reported. */
+static int lu_factor(int64_t m, double *A) {
+  for (int64_t k = 0; k < m; ++k) {
+    const double p = A[k * m + k];
+    if (!(p > 0.0)) return 1;
+    for (int64_t i = k + 1; i < m; ++i) {
+      const double l = A[i * m + k] / p;
+      A[i * m + k] = l;
+      for (int64_t j = k + 1; j < m; ++j) A[i * m + j] -= l * A[k * m + j];
+    }
+  }
+  return 0;
+}
+
+static void lu_solve(int64_t m, const double *F, const double *b, double *x) {
+  for (int64_t i = 0; i < m; ++i) {
+    double v = b[i];
+    for (int64_t k = 0; k < i; ++k) v -= F[i * m + k] * x[k];
+    x[i] = v;
+  }
+  for (int64_t i = m - 1; i >= 0; --i) {
+    double v = x[i];
+    for (int64_t k = i + 1; k < m; ++k) v -= F[i * m + k] * x[k];
+    x[i] = v / F[i * m + i];
+  }
+}
+
 /* Levels for one sample: matrices assembled on every mesh of the hierarchy
- * with the sample's KL coefficient; level 0's load vector into b0 (nullable). */
+ * with the sample's KL coefficient; level 0's load vector into b0 (nullable).
+ * adv = 0: the diffusion matrix (Alg. assembly).  adv = 1: the linear part
+ * D + alpha C of the nonlinear Jacobian (Eq. fenl_lin_sys with beta = 0,
+ * i.e. the Jacobian at u = 0 of a problem without reaction) rediscretized on
+ * every mesh; its coarsest interior block is factored by LU: on interior
+ * nodes C is skew-symmetric (the basis functions of interior nodes vanish on
+ * the boundary and v is constant), so the block's symmetric part is that of
+ * the diffusion block and no pivoting is needed. */
 static int build_levels(int N, int M, double L, double kappa0, double sigma, double fconst, const double *xi,
-                        orc_level *lv, int *nlev, double *b0) {
+                        int adv, double alpha, const double *vel, orc_level *lv, int *nlev, double *b0) {
   int32_t Ns[ORC_MG_MAX_LEVELS];
   const int nl = orc_mg_levels(N, Ns);
   memset(lv, 0, sizeof(orc_level) * (size_t)nl);
@@ -961,7 +1003,13 @@ static int build_levels(int N, int M, double L, double kappa0, double sigma, dou
     }
     orc_graph(l->N, l->rp, l->ci);
     orc_kl_coef_qp(l->N, M, L, kappa0, sigma, xi, ac);
-    orc_assemble_scalar(l->N, l->rp, l->ci, ac, 0, fconst, 1, l->v, load);
+    if (adv) {
+      /* r and x are zero here: x serves as u = 0, r receives F(0) = -load */
+      orc_nl_assemble_scalar(l->N, l->rp, l->ci, ac, fconst, alpha, vel, 0.0, l->x, l->r, l->v, load);
+      for (int64_t t = 0; t < l->n; ++t) l->r[t] = 0.0;
+    } else {
+      orc_assemble_scalar(l->N, l->rp, l->ci, ac, 0, fconst, 1, l->v, load);
+    }
     if (k == 0 && b0) memcpy(b0, load, sizeof(double) * (size_t)l->n);
     free(ac); free(load);
     l->lmax = orc_gershgorin(l->n, l->rp, l->ci, l->v);
@@ -980,7 +1028,8 @@ static int build_levels(int N, int M, double L, double kappa0, double sigma, dou
       for (int64_t bcol = 0; bcol < c->m; ++bcol)
         if (c->imap[bcol] == c->ci[k]) c->chol[a * c->m + bcol] = c->v[k];
   }
-  if (c->m > 0 && chol_factor(c->m, c->chol)) return ORC_E_ARG;
+  c->lu = adv;
+  if (c->m > 0 && (adv ? lu_factor(c->m, c->chol) : chol_factor(c->m, c->chol))) return ORC_E_ARG;
   return ORC_OK;
 }
 
@@ -992,7 +1041,8 @@ static void vcycle(orc_level *lv, int k, int nl, const double *b, double *x) {
     if (l->m > 0) {
       double *bi = l->r, *xi = l->d;
       for (int64_t a = 0; a < l->m; ++a) bi[a] = b[l->imap[a]];
-      chol_solve(l->m, l->chol, bi, xi);
+      if (l->lu) lu_solve(l->m, l->chol, bi, xi);
+      else chol_solve(l->m, l->chol, bi, xi);
       for (int64_t a = 0; a < l->m; ++a) x[l->imap[a]] = xi[a];
     }
     return;
@@ -1012,7 +1062,20 @@ int orc_mg_apply(int N, int M, double L, double kappa0, double sigma, double fco
                  const double *r, double *z) {
   orc_level lv[ORC_MG_MAX_LEVELS];
   int nl = 0;
-  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, lv, &nl, NULL);
+  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 0, 0.0, NULL, lv, &nl, NULL);
+  if (rc == ORC_OK) vcycle(lv, 0, nl, r, z);
+  free_levels(lv, nl);
+  return rc;
+}
+
+/* z = M r for the V-cycle of one sample's advection-diffusion operator
+ * D + alpha C (every level rediscretized, as build_levels with adv = 1). */
+int orc_mg_apply_adv(int N, int M, double L, double kappa0, double sigma, double fconst, double alpha,
+                     const double *vel, const double *xi, const double *r, double *z) {
+  if (!vel) return ORC_E_ARG;
+  orc_level lv[ORC_MG_MAX_LEVELS];
+  int nl = 0;
+  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 1, alpha, vel, lv, &nl, NULL);
   if (rc == ORC_OK) vcycle(lv, 0, nl, r, z);
   free_levels(lv, nl);
   return rc;
@@ -1030,7 +1093,7 @@ int orc_mg_pcg(int N, int M, double L, double kappa0, double sigma, double fcons
   double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
   double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
   if (!b || !r || !z || !p || !q) return ORC_E_NOMEM;
-  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, lv, &nl, b);
+  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 0, 0.0, NULL, lv, &nl, b);
   if (rc != ORC_OK) { free_levels(lv, nl); free(b); free(r); free(z); free(p); free(q); return rc; }
   if (lmax_out)
     for (int k = 0; k < nl; ++k) lmax_out[k] = lv[k].lmax;
@@ -1239,7 +1302,9 @@ int orc_ens_nl_assemble(int N, const int32_t *row_ptr, const int32_t *col_idx, i
 /* solve has converged when the true residual meets the tolerance; a cycle   */
 /* whose estimate met it but whose true residual does not is followed by     */
 /* another.  M: prec 0 Jacobi (the diagonal of A), 1 the multigrid V-cycle   */
-/* of the sample's diffusion operator (the alpha = beta = 0 matrix).          */
+/* of the sample's diffusion operator (the alpha = beta = 0 matrix), 2 the    */
+/* V-cycle of its advection-diffusion operator D + alpha C (beta = 0) with    */
+/* every level rediscretized (alpha and vel used only by 2).                  */
 /* fixed_iters >= 0: exactly that many Arnoldi steps in one cycle (needs     */
 /* fixed_iters <= restart), no residual test.  Iterations count Arnoldi      */
 /* steps (products with A) over all cycles.                                  */
@@ -1248,7 +1313,7 @@ int orc_ens_nl_assemble(int N, const int32_t *row_ptr, const int32_t *col_idx, i
 #define ORC_GM_MAX_RESTART 64
 
 typedef struct {
-  int kind;             /* 0 Jacobi, 1 multigrid */
+  int kind;             /* 0 Jacobi, 1 or 2 multigrid */
   const double *dinv;   /* Jacobi */
   orc_level *lv;        /* multigrid levels */
   int nl;
@@ -1363,8 +1428,9 @@ static int gmres_core(int64_t n, const int32_t *rp, const int32_t *ci, const dou
  * builds the multigrid levels of the sample's diffusion problem (M, L,
  * kappa0, sigma, xi). */
 int orc_gmres(int N, const int32_t *rp, const int32_t *ci, const double *values, const double *b, double *x,
-              int prec, int M, double L, double kappa0, double sigma, const double *xi, double rtol, int restart,
-              int max_iter, int fixed_iters, int32_t *iters, double *rel_res, int32_t *status) {
+              int prec, int M, double L, double kappa0, double sigma, const double *xi, double alpha,
+              const double *vel, double rtol, int restart, int max_iter, int fixed_iters, int32_t *iters,
+              double *rel_res, int32_t *status) {
   const int64_t n = orc_num_nodes(N);
   orc_prec P;
   memset(&P, 0, sizeof(P));
@@ -1383,7 +1449,7 @@ int orc_gmres(int N, const int32_t *rp, const int32_t *ci, const double *values,
     }
     P.dinv = dinv;
   } else {
-    rc = build_levels(N, M, L, kappa0, sigma, 1.0, xi, lv, &P.nl, NULL);
+    rc = build_levels(N, M, L, kappa0, sigma, 1.0, xi, prec == 2, alpha, vel, lv, &P.nl, NULL);
     P.lv = lv;
   }
   if (rc == ORC_OK)
@@ -1396,9 +1462,9 @@ int orc_gmres(int N, const int32_t *rp, const int32_t *ci, const double *values,
 /* GMRES for every sample of an ensemble (matrix values [nnz][s], b and x
  * [n][s], one sample per thread); fixed_iters [s] nullable. */
 int orc_ens_gmres(int N, const int32_t *rp, const int32_t *ci, int s, const double *values, const double *b,
-                  double *x, int prec, int M, double L, double kappa0, double sigma, const double *xi, double rtol,
-                  int restart, int max_iter, const int32_t *fixed_iters, int32_t *iters, double *rel_res,
-                  int32_t *status) {
+                  double *x, int prec, int M, double L, double kappa0, double sigma, const double *xi, double alpha,
+                  const double *vel, double rtol, int restart, int max_iter, const int32_t *fixed_iters,
+                  int32_t *iters, double *rel_res, int32_t *status) {
   const int64_t n = orc_num_nodes(N), nnz = rp[n];
   int rc = ORC_OK;
   #pragma omp parallel for schedule(dynamic, 1)
@@ -1408,8 +1474,8 @@ int orc_ens_gmres(int N, const int32_t *rp, const int32_t *ci, int s, const doub
     if (!ve || !be || !xe) { rc = ORC_E_NOMEM; free(ve); free(be); free(xe); continue; }
     for (int64_t k = 0; k < nnz; ++k) ve[k] = values[k * s + e];
     for (int64_t i = 0; i < n; ++i) { be[i] = b[i * s + e]; xe[i] = x[i * s + e]; }
-    int r = orc_gmres(N, rp, ci, ve, be, xe, prec, M, L, kappa0, sigma, xi + (int64_t)e * M, rtol, restart,
-                      max_iter, fixed_iters ? fixed_iters[e] : -1, &iters[e], &rel_res[e], &status[e]);
+    int r = orc_gmres(N, rp, ci, ve, be, xe, prec, M, L, kappa0, sigma, xi + (int64_t)e * M, alpha, vel, rtol,
+                      restart, max_iter, fixed_iters ? fixed_iters[e] : -1, &iters[e], &rel_res[e], &status[e]);
     if (r) rc = r;
     for (int64_t i = 0; i < n; ++i) x[i * s + e] = xe[i];
     free(ve); free(be); free(xe);
@@ -1462,7 +1528,7 @@ int orc_newton(int N, int M, double L, double kappa0, double sigma, double fcons
     orc_kl_coef_qp(N, M, L, kappa0, sigma, xi, ac);
     P.kind = prec;
     if (prec != 0) {
-      rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, lv, &P.nl, NULL);
+      rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, prec == 2, alpha, vel, lv, &P.nl, NULL);
       P.lv = lv;
     }
   }

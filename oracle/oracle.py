@@ -71,6 +71,7 @@ def lib():
         L.orc_gershgorin.argtypes = [i64, vp, vp, vp]
         L.orc_mg_cheb2.argtypes = [i64, vp, vp, vp, dbl, vp, vp, ctypes.c_int, vp, vp, vp]
         L.orc_mg_apply.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, vp, vp]
+        L.orc_mg_apply_adv.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, vp, vp, vp]
         L.orc_mg_pcg.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, vp, dbl, ctypes.c_int,
                                  ctypes.c_int, vp, vp, vp, vp]
         L.orc_ens_mg_pcg.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int, vp, vp, dbl,
@@ -90,9 +91,9 @@ def lib():
         L.orc_ens_nl_assemble.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl,
                                           ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_gmres.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, vp,
-                                dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+                                dbl, vp, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.orc_ens_gmres.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int, dbl,
-                                    dbl, dbl, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
+                                    dbl, dbl, vp, dbl, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
         L.orc_newton.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl, vp, vp, ctypes.c_int,
                                  dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_ens_newton.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl, ctypes.c_int, vp,
@@ -312,6 +313,14 @@ def mg_apply(N, M, L, kappa0, sigma, fconst, xi, r):
     return z
 
 
+def mg_apply_adv(N, M, L, kappa0, sigma, fconst, alpha, vel, xi, r):
+    """z = M r for the V-cycle of the advection-diffusion operator D + alpha C."""
+    z = np.zeros(num_nodes(N))
+    _check(lib().orc_mg_apply_adv(N, M, L, kappa0, sigma, fconst, alpha, _p(_f64(vel)), _p(_f64(xi)),
+                                  _p(_f64(r)), _p(z)))
+    return z
+
+
 def max_threads():
     return int(lib().orc_max_threads())
 
@@ -379,7 +388,7 @@ def cholesky_solve(A, b):
 
 # ------------------------------------------------------- nonlinear problem
 
-PREC_JACOBI, PREC_MG = 0, 1
+PREC_JACOBI, PREC_MG, PREC_MG_ADV = 0, 1, 2
 
 
 def nl_assemble_scalar(N, rp, ci, acoef, fconst, alpha, vel, beta, u, want_jac=True):
@@ -408,9 +417,10 @@ def ens_nl_assemble(N, rp, ci, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi
 
 
 def ens_gmres(N, rp, ci, values, b, x0=None, prec=PREC_JACOBI, M=0, L=1.0, kappa0=1.0, sigma=0.0, xi=None,
-              rtol=1e-10, restart=30, max_iter=10000, fixed_iters=None):
-    """Right-preconditioned restarted GMRES per sample.  Returns (x [n][s],
-    iters, rel_res, status)."""
+              rtol=1e-10, restart=30, max_iter=10000, fixed_iters=None, alpha=0.0, vel=(0.0, 0.0, 0.0)):
+    """Right-preconditioned restarted GMRES per sample (prec: Jacobi, the
+    diffusion V-cycle, or the V-cycle of D + alpha C, which alone uses alpha
+    and vel).  Returns (x [n][s], iters, rel_res, status)."""
     values = _f64(values)
     s = values.shape[1]
     n = num_nodes(N)
@@ -421,8 +431,8 @@ def ens_gmres(N, rp, ci, values, b, x0=None, prec=PREC_JACOBI, M=0, L=1.0, kappa
     st = np.zeros(s, np.int32)
     fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, np.int32)
     _check(lib().orc_ens_gmres(N, _p(rp), _p(ci), s, _p(values), _p(_f64(b)), _p(x), prec, M, L, kappa0, sigma,
-                               _p(xi), rtol, restart, max_iter, None if fi is None else _p(fi), _p(it), _p(rr),
-                               _p(st)))
+                               _p(xi), alpha, _p(_f64(vel)), rtol, restart, max_iter, None if fi is None else _p(fi),
+                               _p(it), _p(rr), _p(st)))
     return x, it, rr, st
 
 

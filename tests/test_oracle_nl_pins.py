@@ -137,15 +137,73 @@ def _nl_system(orc, N, M=5, seed=3010, alpha=5.0, beta=30.0, s=1):
     return rp, ci, xi, J, F
 
 
-def _prec_dense(orc, N, M, xi, J, rp, ci, prec):
+def _prec_dense(orc, N, M, xi, J, rp, ci, prec, alpha=5.0):
     n = orc.num_nodes(N)
     if prec == orc.PREC_JACOBI:
         d = J[[np.flatnonzero(ci[rp[i]:rp[i + 1]] == i)[0] + rp[i] for i in range(n)]]
         return np.diag(1.0 / d)
+    if prec == orc.PREC_MG_ADV:
+        return np.stack([orc.mg_apply_adv(N, M, 1.0, 1.0, 0.3, 1.0, alpha, VEL, xi, np.eye(n)[j]) for j in range(n)],
+                        1)
     return np.stack([orc.mg_apply(N, M, 1.0, 1.0, 0.3, 1.0, xi, np.eye(n)[j]) for j in range(n)], 1)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+def _adv_operator(orc, N, M, xi, alpha):
+    # D + alpha C: the Jacobian at u = 0 of the problem without reaction
+    rp, ci = orc.graph(N)
+    ac = orc.kl_coef_qp(N, M, 1.0, 1.0, 0.3, xi)
+    _, J, _ = orc.nl_assemble_scalar(N, rp, ci, ac, 1.0, alpha, VEL, 0.0, np.zeros(orc.num_nodes(N)))
+    return rp, ci, J
+
+
+def test_advection_vcycle_on_one_level_is_the_exact_solve(orc):
+    # N = 4 has no coarser level: the cycle is the LU solve of D + alpha C
+    # (identity boundary rows), against a dense solve
+    N, M, alpha = 4, 5, 12.0
+    xi = draw_xi(3080, 1, M)[0]
+    assert orc.mg_levels(N) == [N]
+    rp, ci, J = _adv_operator(orc, N, M, xi, alpha)
+    A = orc.crs_to_dense(rp, ci, J)
+    assert np.abs(A - A.T).max() > 1e-3 * np.abs(A).max()   # nonsymmetric
+    r = draw_vector(3081, orc.num_nodes(N))
+    z = orc.mg_apply_adv(N, M, 1.0, 1.0, 0.3, 1.0, alpha, VEL, xi, r)
+    zd = np.linalg.solve(A, r)
+    assert np.abs(z - zd).max() <= 1e-12 * np.abs(zd).max()
+
+
+def test_advection_vcycle_is_the_two_level_composition(orc):
+    # N = 8 over N = 4: pre-smoothing, residual, restriction, exact coarse
+    # solve, prolongation, post-smoothing, with D + alpha C rediscretized on
+    # both meshes (a cycle that kept the diffusion matrix on either level
+    # would differ), composed here from the pinned pieces
+    Nf, Nc, M, alpha = 8, 4, 5, 10.0
+    xi = draw_xi(3082, 1, M)[0]
+    assert orc.mg_levels(Nf) == [Nf, Nc]
+    rpf, cif, Jf = _adv_operator(orc, Nf, M, xi, alpha)
+    rpc, cic, Jc = _adv_operator(orc, Nc, M, xi, alpha)
+    Af, Ac = orc.crs_to_dense(rpf, cif, Jf), orc.crs_to_dense(rpc, cic, Jc)
+    lmax = orc.gershgorin(rpf, cif, Jf)
+    b = draw_vector(3083, orc.num_nodes(Nf))
+    x = orc.mg_cheb2(rpf, cif, Jf, lmax, b)
+    rc = orc.mg_restrict(Nf, b - Af @ x)
+    x = orc.mg_prolong_add(Nc, np.linalg.solve(Ac, rc), x)
+    x = orc.mg_cheb2(rpf, cif, Jf, lmax, b, x0=x)
+    z = orc.mg_apply_adv(Nf, M, 1.0, 1.0, 0.3, 1.0, alpha, VEL, xi, b)
+    assert np.abs(z - x).max() <= 1e-11 * np.abs(x).max()
+    zd = orc.mg_apply(Nf, M, 1.0, 1.0, 0.3, 1.0, xi, b)
+    assert np.abs(z - zd).max() > 1e-3 * np.abs(x).max()
+
+
+def test_advection_vcycle_without_advection_is_the_diffusion_cycle(orc):
+    N, M = 16, 5
+    xi = draw_xi(3084, 1, M)[0]
+    b = draw_vector(3085, orc.num_nodes(N))
+    z0 = orc.mg_apply_adv(N, M, 1.0, 1.0, 0.3, 1.0, 0.0, VEL, xi, b)
+    zd = orc.mg_apply(N, M, 1.0, 1.0, 0.3, 1.0, xi, b)
+    assert np.abs(z0 - zd).max() <= 1e-12 * np.abs(zd).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_gmres_iterates_minimise_the_residual_over_the_krylov_space(orc, prec):
     # after k steps from x0, x_k = x0 + M K y with K = [r0, (AM) r0, ...] and
     # y the least-squares minimiser of |r0 - A M K y|: brute force with an
@@ -160,7 +218,7 @@ def test_gmres_iterates_minimise_the_residual_over_the_krylov_space(orc, prec):
     r0 = b - A @ x0
     for k in range(1, 6):
         xg, it, _, st = orc.ens_gmres(N, rp, ci, J, F, x0=x0[:, None], prec=prec, M=M, sigma=0.3, xi=xi,
-                                      restart=8, fixed_iters=[k])
+                                      restart=8, fixed_iters=[k], alpha=5.0, vel=VEL)
         assert it[0] == k and st[0] == orc.CONVERGED
         Kb = [r0 / np.linalg.norm(r0)]
         for _ in range(k - 1):
@@ -244,7 +302,7 @@ def test_newton_root_matches_an_independent_nonlinear_solver(orc):
     ref = root(fun, np.zeros(orc.num_nodes(N)), method="hybr", options={"xtol": 1e-13})
     # converged, or stopped at round-off: either way its residual is at noise level
     assert np.linalg.norm(fun(ref.x)) <= 1e-15
-    for prec in (orc.PREC_JACOBI, orc.PREC_MG):
+    for prec in (orc.PREC_JACOBI, orc.PREC_MG, orc.PREC_MG_ADV):
         u, ni, _, _, st, _ = orc.ens_newton(N, M, 1.0, 1.0, 0.3, 1.0, alpha, VEL, beta, xi, prec=prec, rtol=1e-12,
                                             lin_rtol=1e-12)
         assert st[0] == orc.CONVERGED and ni[0] >= 2
@@ -291,3 +349,18 @@ def test_adaptive_forcing_reaches_the_same_root_with_fewer_krylov_steps(orc):
         f = fn[e, :nie[e] + 1]
         assert (np.diff(f) < 0).all()
     assert lie.sum() < lif.sum()
+
+
+def test_advection_cycle_saves_krylov_steps_where_advection_matters(orc):
+    # the diffusion cycle misses the advection term, the D + alpha C cycle
+    # does not: the same Newton iterates' systems need far fewer GMRES
+    # steps, and the root is the same
+    N, M = 16, 5
+    xi = draw_xi(3090, 2, M)
+    kw = dict(rtol=1e-10, lin_rtol=0.3, forcing=orc.FORCING_EW)
+    u1, ni1, li1, _, st1, _ = orc.ens_newton(N, M, 1.0, 1.0, 0.3, 1.0, 10.0, VEL, 100.0, xi, prec=orc.PREC_MG, **kw)
+    u2, ni2, li2, _, st2, _ = orc.ens_newton(N, M, 1.0, 1.0, 0.3, 1.0, 10.0, VEL, 100.0, xi, prec=orc.PREC_MG_ADV,
+                                             **kw)
+    assert (st1 == orc.CONVERGED).all() and (st2 == orc.CONVERGED).all()
+    assert np.abs(u1 - u2).max() <= 1e-8 * np.abs(u1).max()
+    assert li2.sum() <= 0.6 * li1.sum()
