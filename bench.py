@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--check-every", type=int, default=16)
     ap.add_argument("--lin-rtol", type=float, default=None, help="newton: GMRES tolerance per Newton step")
     ap.add_argument("--jac-fp64", action="store_true", help="newton: keep the Jacobian in FP64 for GMRES")
+    ap.add_argument("--newton-mg", default="adv", choices=["adv", "diffusion"],
+                    help="newton: the multigrid cycle of D + alpha C (adv) or of the diffusion operator D")
     ap.add_argument("--forcing", default="ew", choices=["ew", "fixed"],
                     help="newton: GMRES tolerance per step, Eisenstat-Walker or fixed")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -907,8 +909,13 @@ def run_newton(args):
     log(f"newton workload: N={w.N} s={w.s} workspace {ws.numel() / 2**30:.1f} GiB, "
         f"hierarchy {mg.buffer.numel() / 2**30:.2f} GiB")
 
+    adv = args.newton_mg == "adv"
+
     def step():
-        mg.assemble_setup(g, kl, xi, w.sigma, K, rhs, values32=K32, kappa0=w.kappa0, f=w.f)
+        if adv:
+            mg.assemble_setup_adv(g, kl, xi, prob, K, rhs, values32=K32)
+        else:
+            mg.assemble_setup(g, kl, xi, w.sigma, K, rhs, values32=K32, kappa0=w.kappa0, f=w.f)
         u.zero_()
         return ens.newton(g, kl, xi, prob, u=u, opts=opts, mg=mg, mg_values=K32 if mg32 else K, workspace=ws)
 
@@ -933,7 +940,7 @@ def run_newton(args):
                "k_nl_assemble<32,8,*> (residual and Jacobian)": ens.K_NL_ASSEMBLE,
                "k_gm_spmv<32> (GMRES product w = A z)": ens.K_GM_SPMV,
                "k_gm_dots/k_gm_axpy<32> (Gram-Schmidt passes)": ens.K_GM_ORTH,
-               "k_assemble_tile<32,8,*> (diffusion matrix for the preconditioner)": ens.K_ASSEMBLE}
+               "k_assemble_tile<32,8,*> (the preconditioner's matrices, every level)": ens.K_ASSEMBLE}
     prof = {k: ens.prof_query(v) for k, v in kernels.items()}
     per_kernel = {k: {"ms_per_step": round(p["total_ms"] / args.steps, 3), "launches": p["launches"],
                       "GBs": round(p["bytes"] / (p["total_ms"] * 1e-3) / 1e9, 1) if p["launches"] else None}
@@ -954,7 +961,9 @@ def run_newton(args):
                    "linear_solver": f"GMRES({W.NEWTON_RESTART}) to "
                                     + (f"Eisenstat-Walker forcing terms (eta_max {lin_rtol:g})" if ew
                                        else f"{lin_rtol:g}") + ", right-preconditioned by "
-                                    "the multigrid V-cycle of the diffusion operator"
+                                    + ("the multigrid V-cycle of the advection-diffusion operator D + alpha C "
+                                       "(every level rediscretized)" if adv
+                                       else "the multigrid V-cycle of the diffusion operator")
                                     + (" in FP32" if mg32 else " in FP64")
                                     + ("; Jacobian stored in FP32" if jac32 else "; Jacobian in FP64")},
         # the fine-level FP32 cycle passes are the same launches (kernel,
@@ -982,7 +991,8 @@ def run_newton(args):
         t0 = time.perf_counter()
         _, ni, li, rr, st_o, _ = orc.ens_newton(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, W.NEWTON_ALPHA,
                                                 np.array(W.NEWTON_VEL), W.NEWTON_BETA, w.xi()[:threads],
-                                                prec=orc.PREC_MG, rtol=w.rtol, max_newton=1, lin_rtol=lin_rtol,
+                                                prec=orc.PREC_MG_ADV if adv else orc.PREC_MG, rtol=w.rtol,
+                                                max_newton=1, lin_rtol=lin_rtol,
                                                 restart=W.NEWTON_RESTART,
                                                 forcing=orc.FORCING_EW if ew else orc.FORCING_FIXED)
         tc = time.perf_counter() - t0

@@ -362,6 +362,24 @@ ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* 
 ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
                                  const ens_problem* problem, const double* xi, double* values, float* values32,
                                  double* rhs, hipStream_t stream);
+/* ens_mg_assemble_setup for the advection-diffusion operator D + alpha C,
+ * the linear part of the nonlinear problem's Jacobian (Sec. 4, Eq.
+ * fenl_lin_sys with beta = 0; D the diffusion matrix of Alg. assembly,
+ * C_ab = int N_a v.grad N_b), rediscretized on every level with the
+ * problem's kappa, alpha and v: the fine matrix into values / values32 (rhs:
+ * the load), D^-1 and Gershgorin bounds max_i sum_j |a_ij| / a_ii of every
+ * level, the coarsest inverse (Gauss-Jordan without pivoting: on interior
+ * nodes C is skew-symmetric, so the block's symmetric part is the diffusion
+ * block's, positive definite).  Meant as the right preconditioner of
+ * ens_gmres and ens_newton (mg_values = values, or values32 for an FP32
+ * hierarchy): it sees the advection the diffusion cycle misses.
+ * problem->beta is not used.  ens_cg_mg refuses a hierarchy set up this way
+ * (ENS_E_ARG) until ens_mg_setup or ens_mg_assemble_setup sets it up again.
+ * Arguments and errors otherwise as for ens_mg_assemble_setup; non-finite
+ * alpha or v: ENS_E_ARG. */
+ens_status ens_mg_assemble_setup_adv(const ens_mg* mg, const ens_graph* graph, const void* kl,
+                                     const ens_nl_problem* problem, const double* xi, double* values,
+                                     float* values32, double* rhs, hipStream_t stream);
 /* Forget the buffer's built / set-up record (host only, never fails on an
  * unknown buffer).  Call it before the buffer is freed: a later allocation
  * at the same address would otherwise pass as built. */

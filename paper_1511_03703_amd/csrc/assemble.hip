@@ -158,11 +158,16 @@ __device__ inline void tile_decode(int N, int64_t bid, int64_t* tile_id, int* sg
 // values.  Each lane forms its row's sum_j |a_ij| / a_ii in ascending entry
 // order in FP64 exactly as k_mg_diag_bound does, and the workgroup writes
 // the maximum over its rows per sample to bpart[tile][s].
-template <int S, int SB, int BND>
+// ADV: the advection-diffusion operator D + alpha C instead (the linear part
+// of the nonlinear problem's Jacobian, Eq. fenl_lin_sys with beta = 0):
+// every element row also gets alpha (h^2/8) C_ab, C_ab = sum_q N_a (v.dN_b)
+// one 8x8 table per launch.
+template <int S, int SB, int BND, bool ADV>
 __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __restrict__ kl_sqrt_lam,
                                                         const int32_t* __restrict__ kl_triple,
                                                         const double* __restrict__ kl_phi, int M, double kappa0,
-                                                        double sigma, double fsrc, const double* __restrict__ xi,
+                                                        double sigma, double fsrc, double alpha, double vx,
+                                                        double vy, double vz, const double* __restrict__ xi,
                                                         const int32_t* __restrict__ row_ptr,
                                                         double* __restrict__ values, float* __restrict__ values32,
                                                         double* __restrict__ rhs, void* __restrict__ dinv,
@@ -175,6 +180,7 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
   static_assert(R % TZ == 0 && S % SB == 0, "tile shape");
   __shared__ double s_cm[SB * kAsmMaxM];
   __shared__ double s_k[NE * 8 * PS];  // [element][q][sample]
+  __shared__ double s_adv[ADV ? 64 : 1];
   const int n1 = N + 1;
   int64_t tile_id;
   int sg, x0, y, z0;
@@ -183,6 +189,13 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
   for (int t = threadIdx.x; t < SB * M; t += blockDim.x) {
     const int ee = t / M, m = t % M;
     s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + ee) * M + m];
+  }
+  if (ADV && threadIdx.x < 64) {
+    const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
+    double c = 0.0;
+    for (int q = 0; q < 8; ++q)
+      c += c_N[q][a] * (vx * c_dN[q][b][0] + vy * c_dN[q][b][1] + vz * c_dN[q][b][2]);
+    s_adv[threadIdx.x] = c;
   }
   __syncthreads();
   const double h = 1.0 / (double)N;
@@ -235,6 +248,7 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
           double kab = 0.0;
 #pragma unroll
           for (int q = 0; q < 8; ++q) kab += kq[q] * c_G[q][ai][b];
+          if (ADV) kab += h * h * 0.125 * alpha * s_adv[ai * 8 + b];
           acc[slot27] += kab;
         }
       }
@@ -450,7 +464,7 @@ int64_t asm_tiles(int N, int S) {
 
 ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, const int32_t* tr, const double* phi,
                            const ens_problem* prob, int s, const double* xi, double* values, float* values32,
-                           double* rhs, int bnd, void* dinv, double* bpart, hipStream_t stream) {
+                           double* rhs, int bnd, void* dinv, double* bpart, hipStream_t stream, const double* adv) {
   int64_t n = 0, nnz = 0;
   ens_status st = ens_mesh_sizes(N, &n, &nnz, nullptr);
   if (st != ENS_OK) return st;
@@ -460,18 +474,27 @@ ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, cons
     ENS_HIP_TRY(upload_G());
     g_G_ready[dev] = true;
   }
+  const bool with_adv = adv && adv[0] != 0.0;
+  if (with_adv && bnd == 0) {
+    set_error("the advection-diffusion assembly is built only with a fused multigrid set-up");
+    return ENS_E_UNSUPPORTED;
+  }
+  const double av[4] = {with_adv ? adv[0] : 0.0, with_adv ? adv[1] : 0.0, with_adv ? adv[2] : 0.0,
+                        with_adv ? adv[3] : 0.0};
   const int M = prob->M;
   prof_begin(ENS_K_ASSEMBLE, stream);
   switch (s) {
-#define ENS_ASM_LAUNCH(SS, SB, BB)                                                                              \
-  hipLaunchKernelGGL((k_assemble_tile<SS, SB, BB>), dim3((unsigned)(asm_tiles(N, SS) * (SS / SB))), dim3(256), 0, \
-                     stream, N, sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, xi, graph->row_ptr, values,   \
-                     values32, rhs, dinv, bpart)
-#define ENS_ASM_CASE(SS)                                             \
-  case SS:                                                           \
-    if (bnd == 1) ENS_ASM_LAUNCH(SS, asm_sb(SS), 1);                 \
-    else if (bnd == 2) ENS_ASM_LAUNCH(SS, asm_sb(SS), 2);            \
-    else ENS_ASM_LAUNCH(SS, asm_sb(SS), 0);                          \
+#define ENS_ASM_LAUNCH(SS, SB, BB, AA)                                                                            \
+  hipLaunchKernelGGL((k_assemble_tile<SS, SB, BB, AA>), dim3((unsigned)(asm_tiles(N, SS) * (SS / SB))), dim3(256), \
+                     0, stream, N, sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, av[0], av[1], av[2], av[3], \
+                     xi, graph->row_ptr, values, values32, rhs, dinv, bpart)
+#define ENS_ASM_CASE(SS)                                                   \
+  case SS:                                                                 \
+    if (with_adv && bnd == 1) ENS_ASM_LAUNCH(SS, asm_sb(SS), 1, true);     \
+    else if (with_adv && bnd == 2) ENS_ASM_LAUNCH(SS, asm_sb(SS), 2, true); \
+    else if (bnd == 1) ENS_ASM_LAUNCH(SS, asm_sb(SS), 1, false);           \
+    else if (bnd == 2) ENS_ASM_LAUNCH(SS, asm_sb(SS), 2, false);           \
+    else ENS_ASM_LAUNCH(SS, asm_sb(SS), 0, false);                         \
     break;
     ENS_ASM_CASE(4)
     ENS_ASM_CASE(8)
@@ -519,7 +542,8 @@ extern "C" ens_status ens_assemble(int32_t N, const ens_graph* graph, const void
   const double *sq = nullptr, *phi = nullptr;
   const int32_t* tr = nullptr;
   kl_parts(kl, prob->M, &sq, &tr, &phi);
-  return assemble_launch(N, graph, sq, tr, phi, prob, s, xi, values, values32, rhs, 0, nullptr, nullptr, stream);
+  return assemble_launch(N, graph, sq, tr, phi, prob, s, xi, values, values32, rhs, 0, nullptr, nullptr, stream,
+                         nullptr);
 }
 
 extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const void* kl,

@@ -772,6 +772,10 @@ ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, co
     set_error("multigrid hierarchy not set up: call ens_mg_build and ens_mg_setup first");
     return ENS_E_ARG;
   }
+  if (mg_nonsym(mg)) {
+    set_error("multigrid hierarchy set up for a nonsymmetric operator: CG needs a symmetric preconditioner");
+    return ENS_E_ARG;
+  }
   MgPlan plan;
   if (!mg_plan(mg->N, mg->M, s, mg->fp32 != 0, (char*)mg->buffer, &plan)) {
     set_error("multigrid hierarchy of N=%d is not supported", mg->N);

@@ -22,6 +22,7 @@
 // buffers because every row pass gathers its input at neighbouring rows.
 #include <string.h>
 
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -38,19 +39,24 @@ struct MgRecord {
   int N, M, s, fp32;
   double L;
   int stage;  // 1 built, 2 set up
+  int adv;    // set up for the advection-diffusion operator (nonsymmetric)
 };
 static std::mutex g_mg_mu;
 static std::vector<MgRecord> g_mg;
 
-static void mg_mark(const ens_mg* mg, double L, int stage) {
+static void mg_mark(const ens_mg* mg, double L, int stage, int adv = 0) {
   std::lock_guard<std::mutex> lk(g_mg_mu);
   for (auto& r : g_mg)
     if (r.buffer == mg->buffer) {
-      if (stage == 1) r = MgRecord{mg->buffer, mg->N, mg->M, mg->s, mg->fp32, L, 1};
-      else if (r.N == mg->N && r.M == mg->M && r.s == mg->s && r.fp32 == mg->fp32) r.stage = stage;
+      if (stage == 1) {
+        r = MgRecord{mg->buffer, mg->N, mg->M, mg->s, mg->fp32, L, 1, 0};
+      } else if (r.N == mg->N && r.M == mg->M && r.s == mg->s && r.fp32 == mg->fp32) {
+        r.stage = stage;
+        r.adv = adv;
+      }
       return;
     }
-  g_mg.push_back(MgRecord{mg->buffer, mg->N, mg->M, mg->s, mg->fp32, L, stage});
+  g_mg.push_back(MgRecord{mg->buffer, mg->N, mg->M, mg->s, mg->fp32, L, stage, adv});
 }
 
 static const MgRecord* mg_find(const ens_mg* mg) {
@@ -64,6 +70,14 @@ int mg_stage(const ens_mg* mg) {
   std::lock_guard<std::mutex> lk(g_mg_mu);
   const MgRecord* r = mg_find(mg);
   return r ? r->stage : 0;
+}
+
+// Whether the buffer is set up for a nonsymmetric (advection-diffusion)
+// operator.
+int mg_nonsym(const ens_mg* mg) {
+  std::lock_guard<std::mutex> lk(g_mg_mu);
+  const MgRecord* r = mg_find(mg);
+  return r ? r->adv : 0;
 }
 
 // The correlation length the buffer was built for (0: not built).
@@ -243,8 +257,10 @@ __global__ __launch_bounds__(1024) void k_mg_max(const double* __restrict__ part
 }
 
 // Dense inverse of sample e's interior block of the coarsest matrix, by
-// Gauss-Jordan elimination in place (the block is symmetric positive
-// definite, so the diagonal pivots are positive).  One workgroup per sample.
+// Gauss-Jordan elimination in place without pivoting: the block's symmetric
+// part is positive definite (the diffusion block; with advection the
+// interior block of C is skew-symmetric and adds nothing to it), so the
+// diagonal pivots are positive.  One workgroup per sample.
 template <int S>
 __global__ __launch_bounds__(256) void k_mg_inverse(int N, const int32_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci, const double* __restrict__ vals,
@@ -539,9 +555,11 @@ static ens_status build(const MgPlan& P, int M, double L, hipStream_t st) {
 
 // fine_done: the fine level's D^-1 and per-tile bound maxima were formed by
 // its assembly (ens_mg_assemble_setup); only their maximum is taken here.
+// adv (nullable): {alpha, vx, vy, vz} of the advection-diffusion operator
+// every coarse level is rediscretized with.
 template <int S>
 static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* xi, hipStream_t st,
-                        bool fine_done = false) {
+                        bool fine_done = false, const double* adv = nullptr) {
   for (int k = 0; k < P.levels; ++k) {
     const MgLevel& l = P.lv[k];
     if (k > 0) {
@@ -552,7 +570,7 @@ static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* 
       const int32_t* tr = nullptr;
       kl_parts(l.kl, prob.M, &sq, &tr, &phi);
       ens_status rc = assemble_launch(l.N, &g, sq, tr, phi, &prob, S, xi, l.own_vals, l.own_vals32, (double*)l.b,
-                                      P.fp32 ? 1 : 2, l.dinv, l.tpart, st);
+                                      P.fp32 ? 1 : 2, l.dinv, l.tpart, st, adv);
       if (rc != ENS_OK) return rc;
     }
     if (k > 0 || fine_done) {
@@ -656,9 +674,9 @@ ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* 
   return rc;
 }
 
-ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
-                                 const ens_problem* problem, const double* xi, double* values, float* values32,
-                                 double* rhs, hipStream_t stream) {
+static ens_status assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
+                                 const ens_problem* problem, const double* adv, const double* xi, double* values,
+                                 float* values32, double* rhs, hipStream_t stream) {
   ENS_ARG_CHECK(mg && graph && kl && problem && xi && values && rhs && mg->buffer, "null argument");
   ENS_ARG_CHECK(((uintptr_t)mg->buffer & 255u) == 0, "multigrid buffer must be 256-byte aligned");
   ENS_ARG_CHECK(aligned16(values) && aligned16(rhs), "values and rhs must be 16-byte aligned");
@@ -689,16 +707,34 @@ ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const
   const int32_t* tr = nullptr;
   kl_parts(kl, problem->M, &sq, &tr, &phi);
   rc = assemble_launch(mg->N, graph, sq, tr, phi, problem, mg->s, xi, values, values32, rhs, mg->fp32 ? 1 : 2,
-                       plan.lv[0].dinv, plan.lv[0].tpart, stream);
+                       plan.lv[0].dinv, plan.lv[0].tpart, stream, adv);
   if (rc != ENS_OK) return rc;
   switch (mg->s) {
-    case 4: rc = setup<4>(plan, *problem, xi, stream, true); break;
-    case 8: rc = setup<8>(plan, *problem, xi, stream, true); break;
-    case 16: rc = setup<16>(plan, *problem, xi, stream, true); break;
-    default: rc = setup<32>(plan, *problem, xi, stream, true); break;
+    case 4: rc = setup<4>(plan, *problem, xi, stream, true, adv); break;
+    case 8: rc = setup<8>(plan, *problem, xi, stream, true, adv); break;
+    case 16: rc = setup<16>(plan, *problem, xi, stream, true, adv); break;
+    default: rc = setup<32>(plan, *problem, xi, stream, true, adv); break;
   }
-  if (rc == ENS_OK) mg_mark(mg, Lb, 2);
+  if (rc == ENS_OK) mg_mark(mg, Lb, 2, adv && adv[0] != 0.0 ? 1 : 0);
   return rc;
+}
+
+ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
+                                 const ens_problem* problem, const double* xi, double* values, float* values32,
+                                 double* rhs, hipStream_t stream) {
+  return assemble_setup(mg, graph, kl, problem, nullptr, xi, values, values32, rhs, stream);
+}
+
+ens_status ens_mg_assemble_setup_adv(const ens_mg* mg, const ens_graph* graph, const void* kl,
+                                     const ens_nl_problem* problem, const double* xi, double* values,
+                                     float* values32, double* rhs, hipStream_t stream) {
+  ENS_ARG_CHECK(problem, "null problem");
+  ENS_ARG_CHECK(std::isfinite(problem->alpha) && std::isfinite(problem->vx) && std::isfinite(problem->vy) &&
+                    std::isfinite(problem->vz),
+                "alpha and v must be finite");
+  const ens_problem lin{problem->M, problem->L, problem->kappa0, problem->sigma, problem->f};
+  const double adv[4] = {problem->alpha, problem->vx, problem->vy, problem->vz};
+  return assemble_setup(mg, graph, kl, &lin, adv, xi, values, values32, rhs, stream);
 }
 
 ens_status ens_mg_release(const ens_mg* mg) {

@@ -47,16 +47,22 @@ struct MgPlan {
 // The tiled assembly (assemble.hip): tiles of the N^3 mesh for s samples
 // (the rows of a fused bound's partial array), the launcher with an optional
 // fused D^-1 and bound (bnd 1: FP32, 2: FP64; dinv of that type, bpart
-// [tiles][s]), and the parts of a KL table.
+// [tiles][s]; adv: {alpha, vx, vy, vz} of an advection term alpha v.grad u,
+// with a fused bound only; nullptr or alpha = 0: diffusion alone), and the
+// parts of a KL table.
 int64_t asm_tiles(int N, int S);
 ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, const int32_t* tr, const double* phi,
                            const ens_problem* prob, int s, const double* xi, double* values, float* values32,
-                           double* rhs, int bnd, void* dinv, double* bpart, hipStream_t stream);
+                           double* rhs, int bnd, void* dinv, double* bpart, hipStream_t stream,
+                           const double* adv = nullptr);
 void kl_parts(const void* kl, int M, const double** sq, const int32_t** tr, const double** phi);
 
 int mg_levels(int N, int* Ns);
 // 0: buffer unknown; 1: built (ens_mg_build); 2: set up (ens_mg_setup).
 int mg_stage(const ens_mg* mg);
+// 1 if the buffer is set up for the (nonsymmetric) advection-diffusion
+// operator (ens_mg_assemble_setup_adv).
+int mg_nonsym(const ens_mg* mg);
 // Carve the hierarchy buffer (base nullable: sizes only).  Returns false if
 // the coarsest level is too large for its dense solve.
 bool mg_plan(int N, int M, int S, int fp32, char* base, MgPlan* plan);

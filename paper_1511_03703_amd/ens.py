@@ -124,6 +124,8 @@ _SIGS = [
     ("ens_mg_release", _I32, [ctypes.POINTER(ens_mg)]),
     ("ens_mg_assemble_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_problem), _P, _P, _P, _P,
                                      _P]),
+    ("ens_mg_assemble_setup_adv", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_nl_problem), _P, _P, _P,
+                                         _P, _P]),
     ("ens_cg_mg", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(ens_mg), _P, _SZ,
                          ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_scalar_cg_concurrent_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(_SZ)]),
@@ -490,6 +492,20 @@ class Multigrid:
         _check(lib().ens_mg_assemble_setup(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(kl), ctypes.byref(prob),
                                            _ptr(xi), _ptr(values), _ptr(values32), _ptr(rhs), _stream(stream)),
                "ens_mg_assemble_setup")
+        return self
+
+    def assemble_setup_adv(self, g: Graph, kl, xi, problem: ens_nl_problem, values, rhs, values32=None,
+                           stream=None):
+        """As assemble_setup, for the advection-diffusion operator D + alpha C
+        of `problem` (its beta unused) on every level: a preconditioner for
+        GMRES and Newton, which multigrid CG refuses."""
+        if problem.M != self.desc.M or problem.L != self.L:
+            raise ValueError("problem M / L differ from the hierarchy's")
+        gc = g.c()
+        self._values = (values, values32)
+        _check(lib().ens_mg_assemble_setup_adv(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(kl),
+                                               ctypes.byref(problem), _ptr(xi), _ptr(values), _ptr(values32),
+                                               _ptr(rhs), _stream(stream)), "ens_mg_assemble_setup_adv")
         return self
 
     def setup(self, g: Graph, values, xi, sigma, values32=None, L=None, kappa0=1.0, f=1.0, stream=None):

@@ -135,4 +135,21 @@ def test_nonlinear_and_multigrid_argument_errors_without_gpu(E):
     st = L.ens_mg_setup(ctypes.byref(desc), ctypes.byref(gs), ctypes.c_void_p(256), None, ctypes.byref(pr),
                         ctypes.c_void_p(512), None)
     assert st == E.ENS_E_ARG and b"not built" in L.ens_last_error()
+    # the advection-diffusion set-up: alpha and v must be finite, and it too
+    # refuses an unbuilt buffer, before any launch
+    for bad in (dict(alpha=float("nan")), dict(vel=(float("inf"), 0.0, 0.0))):
+        kw = dict(alpha=10.0, vel=(1.0, 0.0, 0.0))
+        kw.update(bad)
+        npr = E.nl_problem(10, 0.3, kw["alpha"], 100.0, vel=kw["vel"])
+        st = L.ens_mg_assemble_setup_adv(ctypes.byref(desc), ctypes.byref(gs), ctypes.c_void_p(256),
+                                         ctypes.byref(npr), ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                                         None, ctypes.c_void_p(2048), None)
+        assert st == E.ENS_E_ARG and b"finite" in L.ens_last_error()
+    npr = E.nl_problem(10, 0.3, 10.0, 100.0)
+    st = L.ens_mg_assemble_setup_adv(ctypes.byref(desc), ctypes.byref(gs), ctypes.c_void_p(256), ctypes.byref(npr),
+                                     ctypes.c_void_p(512), ctypes.c_void_p(1024), None, ctypes.c_void_p(2048), None)
+    assert st == E.ENS_E_ARG and b"not built" in L.ens_last_error()
+    assert L.ens_mg_assemble_setup_adv(ctypes.byref(desc), ctypes.byref(gs), ctypes.c_void_p(256), None,
+                                       ctypes.c_void_p(512), ctypes.c_void_p(1024), None, ctypes.c_void_p(2048),
+                                       None) == E.ENS_E_ARG
     assert L.ens_mg_release(ctypes.byref(desc)) == E.ENS_OK

@@ -101,11 +101,13 @@ def test_headline_workload_refinement(E, orc):
 
 
 def test_newton_workload(E, orc):
-    """128^3, s = 32, Newton with adaptive forcing and FP32-multigrid-
-    preconditioned GMRES on the FP32 Jacobian, as bench.py times it.  Samples 0 and 31: the oracle evaluates the nonlinear
-    residual of the GPU solution (<= 1e-8 |load|), and the GPU residual and
-    Jacobian at that solution element by element (1e-12 of the load, 1e-13
-    of the Jacobian's scale)."""
+    """128^3, s = 32, Newton with adaptive forcing and GMRES on the FP32
+    Jacobian preconditioned by the FP32 V-cycle of D + alpha C, as bench.py
+    times it.  Samples 0 and 31: the oracle evaluates the nonlinear residual
+    of the GPU solution (<= 1e-8 |load|), the GPU residual and Jacobian at
+    that solution element by element (1e-12 of the load, 1e-13 of the
+    Jacobian's scale), and the fine matrix of the hierarchy against its
+    Jacobian at u = 0 without reaction (1e-13)."""
     import workloads as W
     w = W.NEWTON
     xi = w.xi()
@@ -113,18 +115,22 @@ def test_newton_workload(E, orc):
     g = E.graph_build(w.N)
     kl = E.kl_build(w.N, w.M, w.L)
     xt = torch.as_tensor(xi, device=dev)
-    K, K32, _ = E.assemble(g, kl, xt, w.M, w.sigma, want32=True)
-    mg = E.Multigrid(w.N, w.M, w.s, fp32=True).setup(g, K, xt, w.sigma, values32=K32)
     prob = E.nl_problem(w.M, w.sigma, W.NEWTON_ALPHA, W.NEWTON_BETA, W.NEWTON_VEL)
+    K = torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
+    K32 = torch.empty((w.nnz, w.s), dtype=torch.float32, device=dev)
+    rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
+    mg = E.Multigrid(w.N, w.M, w.s, fp32=True).assemble_setup_adv(g, kl, xt, prob, K, rhs, values32=K32)
     u, stats, st = E.newton(g, kl, xt, prob, opts=E.newton_opts(rtol=w.rtol, lin_rtol=W.NEWTON_ETA_MAX,
                                                                 restart=W.NEWTON_RESTART, jac32=True,
                                                                 forcing=E.FORCING_EW),
                             mg=mg, mg_values=K32)
     assert st == E.ENS_OK, stats
-    print(f"GPU done: Newton steps {[t['newton_iters'] for t in stats]}", flush=True)
+    print(f"GPU done: Newton steps {[t['newton_iters'] for t in stats]}, "
+          f"GMRES {[t['lin_iters'] for t in stats]}", flush=True)
+    check = [0, 31]
+    kg = {e: K[:, e].cpu().numpy() for e in check}
     del mg, K, K32
     Fg, Jg, _ = E.nl_assemble(g, kl, xt, prob, u)
-    check = [0, 31]
     ug = u.cpu().numpy()
     fg = {e: Fg[:, e].cpu().numpy() for e in check}
     jg = {e: Jg[:, e].cpu().numpy() for e in check}
@@ -137,12 +143,14 @@ def test_newton_workload(E, orc):
                                           W.NEWTON_BETA, ug[:, e])
         # F nearly cancels at the root, so its error is measured against the
         # size of its terms (the load)
+        _, J0, _ = orc.nl_assemble_scalar(w.N, rp, ci, ac, w.f, W.NEWTON_ALPHA, np.array(W.NEWTON_VEL), 0.0,
+                                          np.zeros(w.n))
         return e, np.linalg.norm(F) / np.linalg.norm(ld), np.abs(fg[e] - F).max() / np.abs(ld).max(), \
-            np.abs(jg[e] - J).max() / np.abs(J).max()
+            np.abs(jg[e] - J).max() / np.abs(J).max(), np.abs(kg[e] - J0).max() / np.abs(J0).max()
 
     with cf.ThreadPoolExecutor(2) as ex:
-        for e, res, dF, dJ in ex.map(one, check):
-            print(f"sample {e}: |F|/|load| {res:.3e}, F {dF:.2e}, J {dJ:.2e}", flush=True)
+        for e, res, dF, dJ, dK in ex.map(one, check):
+            print(f"sample {e}: |F|/|load| {res:.3e}, F {dF:.2e}, J {dJ:.2e}, D + alpha C {dK:.2e}", flush=True)
             assert res <= w.rtol * (1 + 1e-6)
             assert abs(stats[e]["rel_res"] - res) <= 1e-3 * res + 1e-14
-            assert dF <= 1e-12 and dJ <= 1e-13
+            assert dF <= 1e-12 and dJ <= 1e-13 and dK <= 1e-13

@@ -1,0 +1,162 @@
+"""GPU parity of the advection-diffusion multigrid hierarchy: every level
+rediscretized as D + alpha C, the linear part of the nonlinear problem's
+Jacobian (Sec. 4, Eq. fenl_lin_sys with beta = 0), used as the right
+preconditioner of GMRES and Newton.  Against the oracle's cycle of the same
+operator: the fine matrix and load element by element (1e-13 of the
+array's scale), GMRES iterates at fixed step counts (1e-9 relative, as for
+the diffusion cycle), Newton's steps and root; multigrid CG refuses the
+nonsymmetric hierarchy."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import draw_xi, draw_vector
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+VEL = (3 ** -0.5, 3 ** -0.5, 3 ** -0.5)
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1511_03703_amd import ens
+    ens.lib()
+    assert torch.cuda.is_available()
+    return ens
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _boundary(N):
+    n1 = N + 1
+    i = np.arange(n1 ** 3)
+    c = np.stack([i % n1, (i // n1) % n1, i // (n1 * n1)], 1)
+    return ((c == 0) | (c == N)).any(1)
+
+
+def _adv_mg(E, N, M, s, g, kl, xt, prob, fp32=False):
+    nnz, n = g.nnz, g.n
+    K = torch.full((nnz, s), float("nan"), dtype=torch.float64, device=DEV)
+    K32 = torch.full((nnz, s), float("nan"), dtype=torch.float32, device=DEV) if fp32 else None
+    rhs = torch.full((n, s), float("nan"), dtype=torch.float64, device=DEV)
+    mg = E.Multigrid(N, M, s, fp32=fp32).assemble_setup_adv(g, kl, xt, prob, K, rhs, values32=K32)
+    return mg, K, K32, rhs
+
+
+@pytest.mark.parametrize("N,s,M,fp32", [(6, 4, 5, False), (9, 8, 10, True), (12, 32, 10, True), (5, 16, 3, False)])
+def test_advection_operator_matches_the_oracle_jacobian(E, orc, N, s, M, fp32):
+    sigma, alpha, beta = 0.3, 7.0, 55.0
+    xi = draw_xi(4700 + N, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    prob = E.nl_problem(M, sigma, alpha, beta, VEL)
+    mg, K, K32, rhs = _adv_mg(E, N, M, s, g, kl, xt, prob, fp32)
+    rp, ci = orc.graph(N)
+    u0 = np.zeros((orc.num_nodes(N), s))
+    _, Jo, lo = orc.ens_nl_assemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), 0.0, xi, u0)
+    Kg = _np(K)
+    assert np.abs(Kg - Jo).max() <= 1e-13 * np.abs(Jo).max()
+    assert np.abs(_np(rhs) - lo).max() <= 1e-13 * np.abs(lo).max()
+    if fp32:
+        assert torch.equal(K32, K.to(torch.float32))
+    # alpha = 0 is the diffusion set-up, bitwise
+    p0 = E.nl_problem(M, sigma, 0.0, beta, VEL)
+    _, K0, _, rhs0 = _adv_mg(E, N, M, s, g, kl, xt, p0, fp32)
+    Kd, _, rd = E.assemble(g, kl, xt, M, sigma)
+    assert torch.equal(K0, Kd) and torch.equal(rhs0, rd)
+
+
+@pytest.mark.parametrize("N,s,k", [(8, 8, 1), (8, 4, 5), (12, 16, 9), (6, 32, 12)])
+def test_gmres_fixed_steps_with_the_advection_cycle_match_oracle(E, orc, N, s, k):
+    M, sigma, alpha, beta = 5, 0.3, 5.0, 30.0
+    xi = draw_xi(4720 + N + k, s, M)
+    u = draw_vector(4721 + N + k, (orc.num_nodes(N), s), 0.0, 0.05)
+    u[_boundary(N)] = 0.0
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    prob = E.nl_problem(M, sigma, alpha, beta, VEL)
+    F, J, _ = E.nl_assemble(g, kl, xt, prob, torch.as_tensor(u, device=DEV))
+    mg, K, _, _ = _adv_mg(E, N, M, s, g, kl, xt, prob)
+    x0 = draw_vector(4730 + k, (orc.num_nodes(N), s), -0.01, 0.01)
+    x0[_boundary(N)] = 0.0
+    x = torch.as_tensor(x0, device=DEV).clone()
+    x, stats, _ = E.gmres(g, J, F, x=x, opts=E.gmres_opts(rtol=0.0, restart=max(k, 2), max_iter=k), mg=mg,
+                          mg_values=K)
+    assert all(t["iters"] == k for t in stats), stats
+    rp, ci = orc.graph(N)
+    xo, _, _, _ = orc.ens_gmres(N, rp, ci, _np(J), _np(F), x0=x0, prec=orc.PREC_MG_ADV, M=M, sigma=sigma, xi=xi,
+                                restart=max(k, 2), fixed_iters=[k] * s, alpha=alpha, vel=np.array(VEL))
+    xg = _np(x)
+    for e in range(s):
+        assert _rel(xg[:, e], xo[:, e]) <= 1e-9, (e, _rel(xg[:, e], xo[:, e]))
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_newton_with_the_advection_cycle_matches_oracle(E, orc, fp32):
+    # FP64 cycle: the oracle's Newton steps, GMRES counts within +-2 per step
+    # and its root.  FP32 cycle on the FP32 Jacobian with adaptive forcing
+    # (the configuration the benchmark times): same root and stopping rule.
+    N, s, M, sigma, alpha, beta, rtol = 12, 16, 10, 0.3, 10.0, 100.0, 1e-8
+    xi = draw_xi(4740 + fp32, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    prob = E.nl_problem(M, sigma, alpha, beta, VEL)
+    mg, K, K32, _ = _adv_mg(E, N, M, s, g, kl, xt, prob, fp32)
+    if fp32:
+        opts = E.newton_opts(rtol=rtol, lin_rtol=0.3, jac32=True, forcing=E.FORCING_EW)
+        okw = dict(lin_rtol=0.3, forcing=orc.FORCING_EW)
+    else:
+        opts = E.newton_opts(rtol=rtol, lin_rtol=1e-4)
+        okw = dict(lin_rtol=1e-4)
+    u, stats, st = E.newton(g, kl, xt, prob, opts=opts, mg=mg, mg_values=K32 if fp32 else K)
+    assert st == E.ENS_OK, stats
+    _, nio, lio, _, sto, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi,
+                                            prec=orc.PREC_MG_ADV, rtol=rtol, **okw)
+    _, _, lid, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi,
+                                        prec=orc.PREC_MG, rtol=rtol, **okw)
+    ut, _, _, _, _, _ = orc.ens_newton(N, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi,
+                                       prec=orc.PREC_MG_ADV, rtol=1e-13, lin_rtol=1e-12)
+    ug = _np(u)
+    rp, ci = orc.graph(N)
+    Fg, _, ld = orc.ens_nl_assemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, alpha, np.array(VEL), beta, xi, ug,
+                                    want_jac=False)
+    for e in range(s):
+        assert stats[e]["status"] == 0 and sto[e] == 0
+        if fp32:
+            assert abs(stats[e]["newton_iters"] - int(nio[e])) <= 1
+        else:
+            assert stats[e]["newton_iters"] == nio[e], (e, stats[e], nio[e])
+            assert abs(stats[e]["lin_iters"] - int(lio[e])) <= 2 * nio[e], (e, stats[e], lio[e])
+        assert np.linalg.norm(Fg[:, e]) <= rtol * np.linalg.norm(ld[:, e]) * (1 + 1e-6)
+        assert _rel(ug[:, e], ut[:, e]) <= 1e-6
+    # the point of the cycle: fewer Krylov steps than the diffusion cycle
+    assert sum(t["lin_iters"] for t in stats) < 0.7 * int(lid.sum())
+
+
+def test_cg_refuses_the_advection_hierarchy_until_set_up_again(E, orc):
+    N, s, M, sigma = 8, 8, 10, 0.3
+    xi = draw_xi(4750, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    prob = E.nl_problem(M, sigma, 10.0, 0.0, VEL)
+    mg, _, _, _ = _adv_mg(E, N, M, s, g, kl, xt, prob)
+    K, _, b = E.assemble(g, kl, xt, M, sigma)
+    with pytest.raises(E.EnsError, match="nonsymmetric"):
+        E.cg_mg(g, K, b, mg, opts=E.cg_opts(rtol=1e-10))
+    K2 = torch.empty_like(K)
+    b2 = torch.empty_like(b)
+    mg.assemble_setup(g, kl, xt, sigma, K2, b2)
+    x, stats, st = E.cg_mg(g, K2, b2, mg, opts=E.cg_opts(rtol=1e-10))
+    assert st == E.ENS_OK and all(t["status"] == 0 for t in stats)
