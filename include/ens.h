@@ -415,11 +415,13 @@ ens_status ens_gmres_workspace_bytes(const ens_graph* graph, int32_t s, int32_t 
  * device FP64.  Preconditioner M: mg == NULL -> Jacobi (the diagonal of
  * values); else the V-cycle of the set-up hierarchy `mg`, whose fine level
  * is the matrix mg_values [nnz][s] it was set up with (for the Newton
- * systems: the diffusion matrix of ens_assemble), FP64 for an FP64
- * hierarchy and FP32 (values32) for an FP32 one.  An FP32 cycle takes its
- * input rounded to FP32 and its output is widened back; the Krylov basis,
- * products and updates stay FP64, and the true residual at each cycle's
- * end decides convergence.  stats[e]: iters,
+ * systems: the diffusion matrix of ens_mg_assemble_setup, or D + alpha C
+ * of ens_mg_assemble_setup_adv), FP64 for an FP64 hierarchy and FP32
+ * (values32) for an FP32 one.  An FP32 cycle takes its input rounded to
+ * FP32 and its output is widened back; the Krylov basis, products and
+ * updates stay FP64, and the true residual at each cycle's end decides
+ * convergence.  With multigrid the workspace keeps each step's M v_j and a
+ * cycle ends with x += sum_j y_j M v_j (no further cycle).  stats[e]: iters,
  * outer_iters = restart cycles, status, rel_res = the final relative
  * residual.  Synchronises. */
 ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, const double* b, double* x,

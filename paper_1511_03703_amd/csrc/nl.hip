@@ -488,14 +488,13 @@ static __global__ __launch_bounds__(kBlock) void k_gm_scale(int64_t nchunks, con
   }
 }
 
-// t = sum_{i<k} y_i V_i per sample (F32: stored rounded to FP32 in t32).
-template <int S, bool F32>
+// t = sum_{i<k} y_i V_i per sample.
+template <int S>
 static __global__ __launch_bounds__(kBlock) void k_gm_combine(int64_t nchunks, const double* __restrict__ V,
                                                               int64_t vstride, int k, const GmCtl* __restrict__ c,
-                                                              double* __restrict__ t, float* __restrict__ t32) {
+                                                              double* __restrict__ t) {
   using VM = VecMap<double, S>;
   using vt = typename VM::vt;
-  typedef typename vec_t<float, VM::V>::type ft;
   __shared__ double s_y[kGmMaxRestart][S];
   for (int q = threadIdx.x; q < k * S; q += kBlock) s_y[q / S][q % S] = c->y[q % S][q / S];
   __syncthreads();
@@ -508,42 +507,55 @@ static __global__ __launch_bounds__(kBlock) void k_gm_combine(int64_t nchunks, c
 #pragma unroll
     for (int v = 0; v < VM::V; ++v) acc[v] += s_y[i][VM::sample(sub, v)] * vv[v];
   }
-  if (F32) {
-    ft f;
-#pragma unroll
-    for (int v = 0; v < VM::V; ++v) f[v] = (float)acc[v];
-    ((ft*)t32)[ch] = f;
-  } else {
-    ((vt*)t)[ch] = acc;
-  }
+  ((vt*)t)[ch] = acc;
 }
 
-// x += M t for the samples updated in this cycle (Jacobi: M t = D^-1 t;
-// multigrid: t, or in FP32 t32, already holds M t).
-template <int S, int PR>
+// Jacobi end of a cycle: x += D^-1 t for the samples updated in it.
+template <int S>
 static __global__ __launch_bounds__(kBlock) void k_gm_addto(int64_t nchunks, const double* __restrict__ t,
-                                                            const float* __restrict__ t32,
                                                             const double* __restrict__ dinv,
                                                             const GmCtl* __restrict__ c, double* __restrict__ x) {
   using VM = VecMap<double, S>;
   using vt = typename VM::vt;
-  typedef typename vec_t<float, VM::V>::type ft;
   const int64_t ch = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (ch >= nchunks) return;
   const int sub = threadIdx.x % VM::L;
-  vt tv;
-  if (PR == PR_MG32) {
-    const ft f = ((const ft*)t32)[ch];
-#pragma unroll
-    for (int v = 0; v < VM::V; ++v) tv[v] = (double)f[v];
-  } else {
-    tv = ((const vt*)t)[ch];
-  }
-  if (PR == PR_JACOBI) tv = ((const vt*)dinv)[ch] * tv;
+  const vt tv = ((const vt*)dinv)[ch] * ((const vt*)t)[ch];
   vt xv = ((const vt*)x)[ch];
 #pragma unroll
   for (int v = 0; v < VM::V; ++v)
     if (c->upd[VM::sample(sub, v)]) xv[v] += tv[v];
+  ((vt*)x)[ch] = xv;
+}
+
+// Multigrid end of a cycle: x += sum_{i<k} y_i z_i for the samples updated
+// in it, z_i = M v_i kept from the cycle's steps in the cycle's precision
+// TZ.  With a fixed preconditioner M (V y) is that same sum, so the cycle
+// ends without a further application of M.  A sample's y is zero beyond
+// its own steps, where its basis vectors, and so its z, are zero.
+template <int S, typename TZ>
+static __global__ __launch_bounds__(kBlock) void k_gm_zupdate(int64_t nchunks, const TZ* __restrict__ Z,
+                                                              int64_t zstride, int k, const GmCtl* __restrict__ c,
+                                                              double* __restrict__ x) {
+  using VM = VecMap<double, S>;
+  using vt = typename VM::vt;
+  typedef typename vec_t<TZ, VM::V>::type zt;
+  __shared__ double s_y[kGmMaxRestart][S];
+  for (int q = threadIdx.x; q < k * S; q += kBlock) s_y[q / S][q % S] = c->y[q % S][q / S];
+  __syncthreads();
+  const int64_t ch = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (ch >= nchunks) return;
+  const int sub = threadIdx.x % VM::L;
+  vt acc = (vt)0.0;
+  for (int i = 0; i < k; ++i) {
+    const zt zv = ((const zt*)(Z + (int64_t)i * zstride))[ch];
+#pragma unroll
+    for (int v = 0; v < VM::V; ++v) acc[v] += s_y[i][VM::sample(sub, v)] * (double)zv[v];
+  }
+  vt xv = ((const vt*)x)[ch];
+#pragma unroll
+  for (int v = 0; v < VM::V; ++v)
+    if (c->upd[VM::sample(sub, v)]) xv[v] += acc[v];
   ((vt*)x)[ch] = xv;
 }
 
@@ -619,7 +631,8 @@ struct GmWork {
   GmCtl* ctl;
   double *part, *part1, *rpart;
   double *V, *w, *z, *t, *dinv;
-  float *r32, *z32;  // input and output of an FP32 cycle
+  float* r32;  // input of an FP32 cycle
+  void* Z;     // z_j = M v_j of a cycle's steps: restart vectors, FP64 or (FP32 cycle) FP32
   int64_t pstride;
 };
 
@@ -642,8 +655,8 @@ static size_t gm_layout(int64_t n, int S, int restart, GmWork* w, char* base) {
   double* t = (double*)take(vb);
   double* dinv = (double*)take(vb);
   float* r32 = (float*)take(vb / 2);
-  float* z32 = (float*)take(vb / 2);
-  if (w) *w = GmWork{ctl, part, part1, rpart, V, wv, z, t, dinv, r32, z32, ps};
+  void* Z = take(vb * (size_t)restart);
+  if (w) *w = GmWork{ctl, part, part1, rpart, V, wv, z, t, dinv, r32, Z, ps};
   return off;
 }
 
@@ -733,24 +746,26 @@ static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, dou
     int steps = 0;
     for (int j = 0; j < restart; ++j) {
       double* vj = w.V + (int64_t)j * vstride;
-      if (f32) mg_vcycle<float, S>(*plan, w.r32, w.z32, nullptr, st);
-      else if (!jac) mg_vcycle<double, S>(*plan, vj, w.z, nullptr, st);
+      float* zj32 = (float*)w.Z + (int64_t)j * vstride;
+      double* zj = jac ? w.z : (double*)w.Z + (int64_t)j * vstride;
+      if (f32) mg_vcycle<float, S>(*plan, w.r32, zj32, nullptr, st);
+      else if (!jac) mg_vcycle<double, S>(*plan, vj, zj, nullptr, st);
       prof_begin(ENS_K_GM_SPMV, st);
       if (sizeof(TV) == 4) {
         const unsigned sb32 = grid_of(n, (kBlock / 64) * EnsMap<float, S>::RPW);
         if (f32)
           hipLaunchKernelGGL((k_gm_spmv_v32<S, float>), dim3(sb32), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx,
-                             (const float*)vals, w.z32, w.w);
+                             (const float*)vals, (const float*)zj32, w.w);
         else
           hipLaunchKernelGGL((k_gm_spmv_v32<S, double>), dim3(sb32), dim3(kBlock), 0, st, n, g->row_ptr,
-                             g->col_idx, (const float*)vals, (const double*)w.z, w.w);
+                             g->col_idx, (const float*)vals, (const double*)zj, w.w);
       } else {
         if (f32)
           hipLaunchKernelGGL((k_gm_spmv<S, TV, float>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx,
-                             vals, w.z32, w.w);
+                             vals, (const float*)zj32, w.w);
         else
           hipLaunchKernelGGL((k_gm_spmv<S, TV, double>), dim3(sb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx,
-                             vals, w.z, w.w);
+                             vals, (const double*)zj, w.w);
       }
       prof_end(ENS_K_GM_SPMV, st, spmv_bytes - (f32 ? 4.0 * n * S : 0.0));
       // classical Gram-Schmidt twice: h1 = V^T w, w -= V h1, h2 = V^T w,
@@ -790,23 +805,15 @@ static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, dou
       scale(w.V + (int64_t)(j + 1) * vstride);
     }
     hipLaunchKernelGGL((k_gm_solve<S>), dim3(1), dim3(64), 0, st, w.ctl);
-    if (f32)
-      hipLaunchKernelGGL((k_gm_combine<S, true>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.V, vstride, steps, w.ctl,
-                         (double*)nullptr, w.r32);
-    else
-      hipLaunchKernelGGL((k_gm_combine<S, false>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.V, vstride, steps,
-                         w.ctl, w.t, (float*)nullptr);
     if (jac) {
-      hipLaunchKernelGGL((k_gm_addto<S, PR_JACOBI>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.t,
-                         (const float*)nullptr, w.dinv, w.ctl, x);
+      hipLaunchKernelGGL((k_gm_combine<S>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.V, vstride, steps, w.ctl, w.t);
+      hipLaunchKernelGGL((k_gm_addto<S>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.t, w.dinv, w.ctl, x);
     } else if (f32) {
-      mg_vcycle<float, S>(*plan, w.r32, w.z32, nullptr, st);
-      hipLaunchKernelGGL((k_gm_addto<S, PR_MG32>), dim3(eg), dim3(kBlock), 0, st, nchunks, (const double*)nullptr,
-                         w.z32, (const double*)nullptr, w.ctl, x);
+      hipLaunchKernelGGL((k_gm_zupdate<S, float>), dim3(eg), dim3(kBlock), 0, st, nchunks, (const float*)w.Z,
+                         vstride, steps, w.ctl, x);
     } else {
-      mg_vcycle<double, S>(*plan, w.t, w.z, nullptr, st);
-      hipLaunchKernelGGL((k_gm_addto<S, PR_MG64>), dim3(eg), dim3(kBlock), 0, st, nchunks, w.z,
-                         (const float*)nullptr, (const double*)nullptr, w.ctl, x);
+      hipLaunchKernelGGL((k_gm_zupdate<S, double>), dim3(eg), dim3(kBlock), 0, st, nchunks, (const double*)w.Z,
+                         vstride, steps, w.ctl, x);
     }
     hipLaunchKernelGGL((k_gm_residual<S, TV>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b,
                        w.w, w.rpart);
