@@ -24,73 +24,51 @@ namespace ens {
 
 constexpr int kAsmMaxM = 16;
 
-__constant__ double c_G[8][8][8];  // [q][a][b], symmetric in (a,b)
-__constant__ double c_N[8][8];     // [q][a]: N_a at Gauss point q
-__constant__ double c_dN[8][8][3]; // [q][a][d]: reference derivative of N_a along axis d
-__constant__ double c_NN[8][8][8]; // [q][a][b]: N_a N_b at Gauss point q
+// Q1 element tables at the 2 x 2 x 2 Gauss points (Sec. 4, Alg. assembly),
+// fixed at compile time: with the element loops unrolled every entry the
+// kernels read is a known constant, and since the reference coordinate of
+// a Gauss point along each axis is (1 -+ 1/sqrt 3)/2 the tables hold only
+// a few distinct values, which the compiler keeps in registers instead of
+// loading (and spilling) a table per element.
+struct Q1Tables {
+  double G[8][8][8];   // [q][a][b]: grad N_a . grad N_b (reference), symmetric in (a,b)
+  double N[8][8];      // [q][a]: N_a at Gauss point q
+  double dN[8][8][3];  // [q][a][d]: reference derivative of N_a along axis d
+  double NN[8][8][8];  // [q][a][b]: N_a N_b at Gauss point q
+};
 
-static bool g_G_ready[64];
-
-static hipError_t upload_G() {
-  double G[8][8][8];
+constexpr Q1Tables q1_tables() {
+  Q1Tables t{};
   const double r = 0.57735026918962576451;
   const double g[2] = {0.5 * (1.0 - r), 0.5 * (1.0 + r)};
   for (int q = 0; q < 8; ++q) {
-    double s[3] = {g[q & 1], g[(q >> 1) & 1], g[(q >> 2) & 1]};
-    double l[2][3], d[2] = {-1.0, 1.0};
-    for (int t = 0; t < 3; ++t) {
-      l[0][t] = 1.0 - s[t];
-      l[1][t] = s[t];
-    }
-    for (int a = 0; a < 8; ++a)
-      for (int b = 0; b < 8; ++b) {
-        int ax[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
-        int bx[3] = {b & 1, (b >> 1) & 1, (b >> 2) & 1};
-        double dot = 0.0;
-        for (int dim = 0; dim < 3; ++dim) {
-          double fa = d[ax[dim]], fb = d[bx[dim]];
-          for (int o = 0; o < 3; ++o)
-            if (o != dim) {
-              fa *= l[ax[o]][o];
-              fb *= l[bx[o]][o];
-            }
-          dot += fa * fb;
-        }
-        G[q][a][b] = dot;
-      }
-    // force exact symmetry of the table
-    for (int a = 0; a < 8; ++a)
-      for (int b = a + 1; b < 8; ++b) G[q][b][a] = G[q][a][b];
-  }
-  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_G), G, sizeof(G));
-  if (e != hipSuccess) return e;
-  // shape functions and their reference gradients at the Gauss points
-  double Nq[8][8], dN[8][8][3];
-  for (int q = 0; q < 8; ++q) {
-    double s3[3] = {g[q & 1], g[(q >> 1) & 1], g[(q >> 2) & 1]};
+    const double s3[3] = {g[q & 1], g[(q >> 1) & 1], g[(q >> 2) & 1]};
     for (int a = 0; a < 8; ++a) {
-      int ax[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
-      double l[3], d[3];
-      for (int t = 0; t < 3; ++t) {
-        l[t] = ax[t] ? s3[t] : 1.0 - s3[t];
-        d[t] = ax[t] ? 1.0 : -1.0;
+      const int ax[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
+      double l[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < 3; ++k) {
+        l[k] = ax[k] ? s3[k] : 1.0 - s3[k];
+        d[k] = ax[k] ? 1.0 : -1.0;
       }
-      Nq[q][a] = l[0] * l[1] * l[2];
-      dN[q][a][0] = d[0] * l[1] * l[2];
-      dN[q][a][1] = l[0] * d[1] * l[2];
-      dN[q][a][2] = l[0] * l[1] * d[2];
+      t.N[q][a] = l[0] * l[1] * l[2];
+      t.dN[q][a][0] = d[0] * l[1] * l[2];
+      t.dN[q][a][1] = l[0] * d[1] * l[2];
+      t.dN[q][a][2] = l[0] * l[1] * d[2];
     }
-  }
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c_N), Nq, sizeof(Nq));
-  if (e != hipSuccess) return e;
-  double NN[8][8][8];
-  for (int q = 0; q < 8; ++q)
     for (int a = 0; a < 8; ++a)
-      for (int b = 0; b < 8; ++b) NN[q][a][b] = Nq[q][a] * Nq[q][b];
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c_NN), NN, sizeof(NN));
-  if (e != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_dN), dN, sizeof(dN));
+      for (int b = a; b < 8; ++b) {
+        double dot = 0.0;
+        for (int k = 0; k < 3; ++k) dot += t.dN[q][a][k] * t.dN[q][b][k];
+        t.G[q][a][b] = dot;
+        t.G[q][b][a] = dot;
+      }
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b) t.NN[q][a][b] = t.N[q][a] * t.N[q][b];
+  }
+  return t;
 }
+
+__device__ constexpr Q1Tables kQ1 = q1_tables();
 
 // Sum of the KL modes of sample e at the 8 Gauss points of element
 // (ex, ey, ez): kq[q] = kappa0 + sum_m c_m X(qx) Y(qy) Z(qz).
@@ -194,7 +172,7 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
     const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
     double c = 0.0;
     for (int q = 0; q < 8; ++q)
-      c += c_N[q][a] * (vx * c_dN[q][b][0] + vy * c_dN[q][b][1] + vz * c_dN[q][b][2]);
+      c += kQ1.N[q][a] * (vx * kQ1.dN[q][b][0] + vy * kQ1.dN[q][b][1] + vz * kQ1.dN[q][b][2]);
     s_adv[threadIdx.x] = c;
   }
   __syncthreads();
@@ -247,7 +225,7 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
           const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
           double kab = 0.0;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) kab += kq[q] * c_G[q][ai][b];
+          for (int q = 0; q < 8; ++q) kab += kq[q] * kQ1.G[q][ai][b];
           if (ADV) kab += h * h * 0.125 * alpha * s_adv[ai * 8 + b];
           acc[slot27] += kab;
         }
@@ -347,7 +325,7 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
     const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
     double c = 0.0;
     for (int q = 0; q < 8; ++q)
-      c += c_N[q][a] * (vx * c_dN[q][b][0] + vy * c_dN[q][b][1] + vz * c_dN[q][b][2]);
+      c += kQ1.N[q][a] * (vx * kQ1.dN[q][b][0] + vy * kQ1.dN[q][b][1] + vz * kQ1.dN[q][b][2]);
     s_adv[a][b] = c;
   }
   __syncthreads();
@@ -407,17 +385,17 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
         for (int q = 0; q < 8; ++q) {
           double t = 0.0;
 #pragma unroll
-          for (int b = 0; b < 8; ++b) t += c_N[q][b] * ue[b];
+          for (int b = 0; b < 8; ++b) t += kQ1.N[q][b] * ue[b];
           uq[q] = t;
-          la += wr * fsrc * c_N[q][ai];
+          la += wr * fsrc * kQ1.N[q][ai];
         }
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
           double dg = 0.0, rn = 0.0;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            dg += kq[q] * c_G[q][ai][b];
-            rn += uq[q] * c_NN[q][ai][b];
+            dg += kq[q] * kQ1.G[q][ai][b];
+            rn += uq[q] * kQ1.NN[q][ai][b];
           }
           const double lin = wd * dg + wa * s_adv[ai][b];
           fa += (lin + wb * rn) * ue[b];
@@ -468,12 +446,6 @@ ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, cons
   int64_t n = 0, nnz = 0;
   ens_status st = ens_mesh_sizes(N, &n, &nnz, nullptr);
   if (st != ENS_OK) return st;
-  int dev = 0;
-  ENS_HIP_TRY(hipGetDevice(&dev));
-  if (dev < 64 && !g_G_ready[dev]) {
-    ENS_HIP_TRY(upload_G());
-    g_G_ready[dev] = true;
-  }
   const bool with_adv = adv && adv[0] != 0.0;
   if (with_adv && bnd == 0) {
     set_error("the advection-diffusion assembly is built only with a fused multigrid set-up");
@@ -562,12 +534,6 @@ extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const v
   if (!supported_s(s)) {
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
-  }
-  int dev = 0;
-  ENS_HIP_TRY(hipGetDevice(&dev));
-  if (dev < 64 && !g_G_ready[dev]) {
-    ENS_HIP_TRY(upload_G());
-    g_G_ready[dev] = true;
   }
   const int M = prob->M;
   const double *sq, *phi;

@@ -569,7 +569,7 @@ static __global__ __launch_bounds__(kBlock) void k_gm_zero_x(int64_t total, cons
 
 // r = b - A x (matrix in FP64 or FP32, widened) for the row tile, with the
 // block's partials |r|^2 and |b|^2.
-template <int S, typename TV>
+template <int S, typename TV, bool XZ = false>
 static __global__ __launch_bounds__(kBlock) void k_gm_residual(int n, const int32_t* __restrict__ rp,
                                                                const int32_t* __restrict__ ci,
                                                                const TV* __restrict__ vals,
@@ -585,7 +585,8 @@ static __global__ __launch_bounds__(kBlock) void k_gm_residual(int n, const int3
   for (int v = 0; v < M::V; ++v) acc[0][v] = acc[1][v] = 0.0;
   const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
   if (row < n) {
-    const vt ax = gm_row_product<S, TV, double>(ci, vals, x, rp[row], rp[row + 1], sub);
+    // XZ: x = 0 is known, so r = b without the product
+    const vt ax = XZ ? (vt)0.0 : gm_row_product<S, TV, double>(ci, vals, x, rp[row], rp[row + 1], sub);
     const vt bv = ((const vt*)b)[row * M::L + sub];
     const vt rv = bv - ax;
     ((vt*)r)[row * M::L + sub] = rv;
@@ -706,7 +707,7 @@ static ens_status read_flag(const int32_t* dev, hipStream_t st, int32_t* out) {
 template <int S, typename TV>
 static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, double* x, double rtol, int restart,
                         int max_iter, const MgPlan* plan, const GmWork& w, const int32_t* mask,
-                        const double* rtol_e, hipStream_t st) {
+                        const double* rtol_e, hipStream_t st, bool x_zero = false) {
   const int n = g->n;
   const int64_t nchunks = (int64_t)n * S / VecMap<double, S>::V;
   const int64_t vstride = (int64_t)n * S;
@@ -720,8 +721,12 @@ static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, dou
   hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, st, w.ctl, rtol, restart, max_iter);
   if (jac) hipLaunchKernelGGL((k_gm_dinv<S, TV>), dim3(grid_of((int64_t)n * S, kBlock)), dim3(kBlock), 0, st, n,
                               g->row_ptr, g->col_idx, vals, w.dinv);
-  hipLaunchKernelGGL((k_gm_residual<S, TV>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b, w.w,
-                     w.rpart);
+  if (x_zero)
+    hipLaunchKernelGGL((k_gm_residual<S, TV, true>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals,
+                       x, b, w.w, w.rpart);
+  else
+    hipLaunchKernelGGL((k_gm_residual<S, TV>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b,
+                       w.w, w.rpart);
   gm_reduce<S>(w, w.rpart, rb, 2 * S, 2 * S, GM_START, 0, mask, rtol_e, st);
   hipLaunchKernelGGL((k_gm_zero_x<S>), dim3(grid_of((int64_t)n * S, kBlock)), dim3(kBlock), 0, st, (int64_t)n * S,
                      w.ctl, x);
@@ -1004,10 +1009,10 @@ static ens_status newton(int N, const ens_graph* g, const void* kl, const ens_nl
     hipLaunchKernelGGL(k_fill_zero64, dim3(grid_of(total, kBlock)), dim3(kBlock), 0, st, total, w.d);
     if (o.jac32)
       rc = gmres<S, float>(g, (const float*)w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm,
-                           w.ctl->active, w.ctl->eta, st);
+                           w.ctl->active, w.ctl->eta, st, true);
     else
       rc = gmres<S, double>(g, (const double*)w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm,
-                            w.ctl->active, w.ctl->eta, st);
+                            w.ctl->active, w.ctl->eta, st, true);
     if (rc != ENS_OK) return rc;
     hipLaunchKernelGGL((k_nt_after<S>), dim3(1), dim3(64), 0, st, w.ctl, (const GmCtl*)w.gm.ctl);
     hipLaunchKernelGGL((k_nt_update<S>), dim3(grid_of(total, kBlock)), dim3(kBlock), 0, st, total, w.ctl, w.d, u);
