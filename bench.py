@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--pool-gib", type=float, default=192.0, help="batch: resident pool size")
     ap.add_argument("--batch-s", type=int, default=0, help="batch: fix s (skip the autotuner)")
     ap.add_argument("--batch-tile", type=int, default=4, help="batch: tile when --batch-s is given")
+    ap.add_argument("--group", default="contrast", choices=["contrast", "draw"],
+                    help="batch: form each mesh size's ensembles by coefficient contrast, or in draw order")
     ap.add_argument("--train-steps", type=int, default=8000, help="learned: Adam steps")
     ap.add_argument("--precond", default="mg", choices=["mg", "jacobi"],
                     help="headline/mid/small: preconditioner of the timed solve (default: multigrid)")
@@ -505,15 +507,28 @@ def run_batch(args):
     def on_wave(wv, groups, stats):
         wave_times.append(time.perf_counter())
 
+    grouped = args.group == "contrast"
+
+    def step(**kw):
+        # the grouping (coefficient extremes on the device, host ordering,
+        # regrouped inputs) is part of the timed step
+        xg = pool.group_by_contrast(xi, sigma)[0] if grouped else xi
+        return pool.run(xg, sigma, opts, **kw)
+
     for i in range(args.warmup):
-        pool.run(xi, sigma, opts)
+        step()
     torch.cuda.synchronize()
+    t_g = time.perf_counter()
+    if grouped:
+        pool.group_by_contrast(xi, sigma)
+    torch.cuda.synchronize()
+    t_group = time.perf_counter() - t_g
     gc.collect()
     gc.disable()
     t0 = time.perf_counter()
     for i in range(args.steps):
         wave_times.clear()
-        stats, rc = pool.run(xi, sigma, opts, on_wave=on_wave)
+        stats, rc = step(on_wave=on_wave)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     gc.enable()
@@ -548,6 +563,18 @@ def run_batch(args):
         "all_converged": bool(ok),
         "iters": {str(N): {"median": float(np.median(v)), "max": int(max(v))} for N, v in iters_by_mesh.items()
                   if v},
+        "grouping": {
+            "by": ("coefficient contrast kmax/kmin over the mesh's Gauss points, per mesh size" if grouped
+                   else "draw order"),
+            "seconds": round(t_group, 4) if grouped else 0.0,
+            # an ensemble iterates as long as its slowest sample: the sum of
+            # the groups' maxima is what the batch pays; sorting each mesh
+            # size's samples by their actual counts would give the least
+            "summed_group_max_iters": int(sum(max(t["iters"] for t in st) for st in stats)),
+            "summed_group_max_iters_ideal": int(sum(
+                np.sort(np.asarray(v))[k * s:(k + 1) * s].max() for v in iters_by_mesh.values() if v
+                for k in range(len(v) // s))),
+            "summed_sample_iters": int(sum(t["iters"] for st in stats for t in st))},
         "autotune": tune,
     }
     if not args.no_context:

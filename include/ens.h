@@ -120,6 +120,26 @@ ens_status ens_kl_bytes(int32_t N, int32_t M, size_t* bytes);
  *   abscissa (e + g_q)/N, index 2e+q, g_0 < g_1 the 2-point Gauss nodes). */
 ens_status ens_kl_build(int32_t N, int32_t M, double L, void* kl, hipStream_t stream);
 
+/* ------------------------------------------------------------ grouping */
+
+/* Per-sample extremes of the coefficient over the Gauss points of the N^3
+ * mesh: kmin[e] and kmax[e] (device FP64 [s]) are the minimum and maximum of
+ * kappa(x_q, xi_e) = kappa0 + sigma sum_m sqrt(lambda_m) phi_m(x_q) xi_e[m]
+ * over the 8 N^3 Gauss points (Sec. 4, KL expansion of kappa), for any
+ * s >= 1.  The spread kmax / kmin is the paper's suggested predictor of a
+ * sample's iteration count (Sec. 3.7: the variation of the sample's
+ * parameters over the domain).  kl from ens_kl_build(N, M, L); xi [s][M]
+ * device.  A sample with a non-finite coefficient gets NaN extremes.
+ * Stream ordered; allocates nothing. */
+ens_status ens_kl_extrema(int32_t N, const void* kl, const ens_problem* problem, int32_t s, const double* xi,
+                          double* kmin, double* kmax, hipStream_t stream);
+/* Order `count` samples for grouping into ensembles (Sec. 3.7: samples of
+ * similar iteration counts belong in one ensemble): perm (host, [count])
+ * lists the sample indices by ascending key (host, [count]), equal keys in
+ * index order, non-finite keys last in index order; consecutive runs of
+ * perm are the ensembles.  Host only; count = 0 is a no-op. */
+ens_status ens_group_order(int64_t count, const double* key, int32_t* perm);
+
 /* ------------------------------------------------------------- assembly */
 
 /* Ensemble assembly of A and f (Alg. "assembly" made atomic-free): every

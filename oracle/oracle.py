@@ -186,6 +186,19 @@ def kl_coef_qp(N, M, L, kappa0, sigma, xi):
     return out
 
 
+def sample_extrema(N, M, L, kappa0, sigma, xi):
+    """Per-sample minimum and maximum of the coefficient over the Gauss
+    points of the N^3 mesh (the variation of a sample's parameters over the
+    domain, Sec. 3.7's predictor of its iteration count), by evaluating it
+    at every point: (kmin [s], kmax [s])."""
+    xi = np.atleast_2d(_f64(xi))
+    kmin, kmax = np.zeros(xi.shape[0]), np.zeros(xi.shape[0])
+    for e in range(xi.shape[0]):
+        a = kl_coef_qp(N, M, L, kappa0, sigma, xi[e])
+        kmin[e], kmax[e] = (np.nan, np.nan) if not np.isfinite(a).all() else (a.min(), a.max())
+    return kmin, kmax
+
+
 # ----------------------------------------------------------------- assembly
 
 

@@ -91,6 +91,33 @@ class BatchPool:
         for N in sorted(set(self.meshes)):
             self.graphs[N] = (ens.graph_build(N), ens.kl_build(N, M, L))
 
+    def group_by_contrast(self, xi_groups, sigma: float, kappa0: float = 1.0):
+        """Regroup the samples of the groups on each mesh by the contrast
+        kmax / kmin of their coefficient over that mesh's Gauss points
+        (Sec. 3.7: samples of similar parameter variation need similar
+        iteration counts, and an ensemble runs as long as its slowest
+        sample).  Returns (xi regrouped [groups][s][M] on the device,
+        order [groups * s]: order[g * s + j] is the draw-order index of the
+        sample now at position j of group g)."""
+        import numpy as np
+        import torch
+
+        ens, s = self.ens, self.s
+        G = len(self.meshes)
+        flat = xi_groups.reshape(G * s, -1)
+        order = np.arange(G * s, dtype=np.int64)
+        meshes = np.asarray(self.meshes)
+        for N in sorted(set(self.meshes)):
+            gidx = np.flatnonzero(meshes == N)
+            samples = (gidx[:, None] * s + np.arange(s)[None, :]).reshape(-1)
+            _, kl = self.graphs[N]
+            kmin, kmax = ens.kl_extrema(N, kl, flat[torch.as_tensor(samples, device=flat.device)].contiguous(),
+                                        self.M, sigma, L=self.L, kappa0=kappa0)
+            perm = ens.group_order((kmax / kmin).cpu().numpy())
+            order[samples] = samples[perm]
+        regrouped = flat[torch.as_tensor(order, device=flat.device)].reshape(xi_groups.shape).contiguous()
+        return regrouped, order
+
     def _carve(self, off: int, nbytes: int, shape):
         import torch
 

@@ -432,6 +432,51 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
   if (load) load[row * S + e] = bnd_row ? 0.0 : la;
 }
 
+// Per-sample extremes of the coefficient over the 8 N^3 Gauss points of
+// the mesh, one workgroup per sample: each lane scans a stride of the
+// elements and the workgroup folds its lanes' extremes (exact in any
+// order).  A non-finite value makes both extremes NaN.
+__device__ inline double ext_min(double a, double b) { return (a != a || b != b) ? NAN : (b < a ? b : a); }
+__device__ inline double ext_max(double a, double b) { return (a != a || b != b) ? NAN : (b > a ? b : a); }
+
+__global__ __launch_bounds__(256) void k_kl_extrema(int N, const double* __restrict__ kl_sqrt_lam,
+                                                     const int32_t* __restrict__ kl_triple,
+                                                     const double* __restrict__ kl_phi, int M, double kappa0,
+                                                     double sigma, const double* __restrict__ xi,
+                                                     double* __restrict__ kmin, double* __restrict__ kmax) {
+  __shared__ double s_cm[kAsmMaxM];
+  __shared__ double s_lo[256], s_hi[256];
+  const int64_t e = blockIdx.x;
+  if (threadIdx.x < M) s_cm[threadIdx.x] = sigma * kl_sqrt_lam[threadIdx.x] * xi[e * M + threadIdx.x];
+  __syncthreads();
+  const int64_t ne = (int64_t)N * N * N, two_n = 2 * (int64_t)N;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int64_t el = threadIdx.x; el < ne; el += blockDim.x) {
+    const int ex = (int)(el % N), ey = (int)((el / N) % N), ez = (int)(el / ((int64_t)N * N));
+    double kq[8];
+    kl_points(kl_phi, kl_triple, s_cm, M, two_n, ex, ey, ez, kappa0, kq);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      lo = ext_min(lo, kq[q]);
+      hi = ext_max(hi, kq[q]);
+    }
+  }
+  s_lo[threadIdx.x] = lo;
+  s_hi[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s_lo[threadIdx.x] = ext_min(s_lo[threadIdx.x], s_lo[threadIdx.x + w]);
+      s_hi[threadIdx.x] = ext_max(s_hi[threadIdx.x], s_hi[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    kmin[e] = s_lo[0];
+    kmax[e] = s_hi[0];
+  }
+}
+
 // Sample groups per tile: 8 samples per workgroup, all of them for s = 4.
 static constexpr int asm_sb(int S) { return S < 8 ? S : 8; }
 
@@ -561,5 +606,21 @@ extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const v
   const double bytes = (values ? (double)nnz * s * 8.0 : 0.0) + (values32 ? (double)nnz * s * 4.0 : 0.0) +
                        (double)n * s * 8.0 * (load ? 3.0 : 2.0) + 4.0 * (n + 1);
   prof_end(ENS_K_NL_ASSEMBLE, stream, bytes);
+  return ENS_OK;
+}
+
+extern "C" ens_status ens_kl_extrema(int32_t N, const void* kl, const ens_problem* prob, int32_t s,
+                                     const double* xi, double* kmin, double* kmax, hipStream_t stream) {
+  ENS_ARG_CHECK(N >= 1 && N <= 1024, "N out of range");
+  ENS_ARG_CHECK(prob && s >= 1, "null problem or no samples");
+  ENS_ARG_CHECK(prob->M >= 0 && prob->M <= kAsmMaxM, "M out of range");
+  ENS_ARG_CHECK(prob->M == 0 || (kl && xi), "null KL table or inputs");
+  ENS_ARG_CHECK(kmin && kmax, "null output");
+  const double *sq = nullptr, *phi = nullptr;
+  const int32_t* tr = nullptr;
+  kl_parts(kl, prob->M, &sq, &tr, &phi);
+  hipLaunchKernelGGL(k_kl_extrema, dim3((unsigned)s), dim3(256), 0, stream, N, sq, tr, phi, prob->M, prob->kappa0,
+                     prob->sigma, xi, kmin, kmax);
+  ENS_LAUNCH_CHECK();
   return ENS_OK;
 }

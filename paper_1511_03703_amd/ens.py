@@ -11,6 +11,7 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -124,6 +125,8 @@ _SIGS = [
     ("ens_mg_release", _I32, [ctypes.POINTER(ens_mg)]),
     ("ens_mg_assemble_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_problem), _P, _P, _P, _P,
                                      _P]),
+    ("ens_kl_extrema", _I32, [_I32, _P, ctypes.POINTER(ens_problem), _I32, _P, _P, _P, _P]),
+    ("ens_group_order", _I32, [ctypes.c_int64, _P, _P]),
     ("ens_mg_assemble_setup_adv", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_nl_problem), _P, _P, _P,
                                          _P, _P]),
     ("ens_cg_mg", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(ens_mg), _P, _SZ,
@@ -279,6 +282,29 @@ def assemble(g: Graph, kl: torch.Tensor, xi: torch.Tensor, M: int, sigma: float,
 # ------------------------------------------------------ nonlinear problem
 
 DEFAULT_VEL = (3 ** -0.5, 3 ** -0.5, 3 ** -0.5)
+
+
+def kl_extrema(N: int, kl: torch.Tensor, xi: torch.Tensor, M: int, sigma: float, L: float = 1.0,
+               kappa0: float = 1.0, stream=None):
+    """Per-sample minimum and maximum of the coefficient over the N^3 mesh's
+    Gauss points: (kmin [s], kmax [s]) device FP64."""
+    s = xi.shape[0]
+    kmin = torch.empty(s, dtype=torch.float64, device=xi.device)
+    kmax = torch.empty(s, dtype=torch.float64, device=xi.device)
+    prob = ens_problem(M, L, kappa0, sigma, 1.0)
+    _check(lib().ens_kl_extrema(N, _ptr(kl), ctypes.byref(prob), s, _ptr(xi), _ptr(kmin), _ptr(kmax),
+                                _stream(stream)), "ens_kl_extrema")
+    return kmin, kmax
+
+
+def group_order(key) -> np.ndarray:
+    """Sample order for grouping into ensembles: ascending key, ties and
+    non-finite keys in index order (non-finite last)."""
+    key = np.ascontiguousarray(key, dtype=np.float64)
+    perm = np.empty(key.shape[0], dtype=np.int32)
+    _check(lib().ens_group_order(key.shape[0], key.ctypes.data_as(ctypes.c_void_p),
+                                 perm.ctypes.data_as(ctypes.c_void_p)), "ens_group_order")
+    return perm
 
 
 def nl_problem(M: int, sigma: float, alpha: float, beta: float, vel=DEFAULT_VEL, L: float = 1.0,

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -153,3 +154,33 @@ def test_nonlinear_and_multigrid_argument_errors_without_gpu(E):
                                        ctypes.c_void_p(512), ctypes.c_void_p(1024), None, ctypes.c_void_p(2048),
                                        None) == E.ENS_E_ARG
     assert L.ens_mg_release(ctypes.byref(desc)) == E.ENS_OK
+
+
+def test_group_order_on_the_host(E):
+    # ascending key, ties in index order, non-finite keys last in index order
+    key = np.array([3.0, 1.0, np.nan, 1.0, -2.0, np.inf, 0.5, 1.0])
+    perm = E.group_order(key)
+    assert perm.tolist() == [4, 6, 1, 3, 7, 0, 2, 5]
+    rng = np.random.default_rng(7)
+    key = rng.integers(0, 20, 1000).astype(float)
+    perm = E.group_order(key)
+    assert sorted(perm.tolist()) == list(range(1000))
+    ks = key[perm]
+    assert (np.diff(ks) >= 0).all()
+    for v in np.unique(key):  # ties stay in index order
+        sel = perm[ks == v]
+        assert (np.diff(sel) > 0).all()
+    assert E.group_order(np.zeros(0)).shape == (0,)
+    assert E.lib().ens_group_order(-1, None, None) == E.ENS_E_ARG
+    assert E.lib().ens_group_order(3, None, None) == E.ENS_E_ARG
+
+
+def test_kl_extrema_argument_errors_without_gpu(E):
+    L = E.lib()
+    pr = E.ens_problem(10, 1.0, 1.0, 0.3, 1.0)
+    p = ctypes.c_void_p(256)
+    assert L.ens_kl_extrema(8, p, None, 4, p, p, p, None) == E.ENS_E_ARG
+    assert L.ens_kl_extrema(8, p, ctypes.byref(pr), 0, p, p, p, None) == E.ENS_E_ARG
+    assert L.ens_kl_extrema(0, p, ctypes.byref(pr), 4, p, p, p, None) == E.ENS_E_ARG
+    assert L.ens_kl_extrema(8, None, ctypes.byref(pr), 4, p, p, p, None) == E.ENS_E_ARG
+    assert L.ens_kl_extrema(8, p, ctypes.byref(pr), 4, p, None, p, None) == E.ENS_E_ARG
