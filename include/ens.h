@@ -453,8 +453,11 @@ ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, co
  * |F(u_k)| <= rtol |load| (|F(u_0)| if the load is zero), at non-finite
  * norms, or after max_newton steps; otherwise solve A d = F by ens_gmres to
  * the forcing term of the step (opts->forcing) from d = 0 and set
- * u_{k+1} = u_k - d.  A linear solve that breaks down or turns non-finite
- * stops its sample with that status. */
+ * u_{k+1} = u_k - d.  The inner solve accepts a cycle's Arnoldi residual
+ * estimate when it meets the forcing term (the true residual is formed only
+ * before a further cycle; the next step's exact |F| is the check).  A
+ * linear solve that breaks down or turns non-finite stops its sample with
+ * that status. */
 typedef struct {
   double rtol;
   int32_t max_newton;

@@ -247,6 +247,26 @@ static __global__ void k_gm_solve(GmCtl* c) {
   }
 }
 
+// End of a cycle when the estimate is trusted: a running sample whose
+// Arnoldi residual estimate |g_k| met its tolerance has converged (in exact
+// arithmetic the estimate is the true residual of the right-preconditioned
+// system); the others go on to the true residual and, if it is needed, a
+// further cycle.
+template <int S>
+static __global__ void k_gm_accept(GmCtl* c) {
+  const int e = threadIdx.x;
+  if (e < S && c->run[e] && c->k[e] > 0 && fabs(c->g[e][c->k[e]]) <= c->tol[e]) {
+    c->status[e] = ENS_SAMPLE_CONVERGED;
+    c->run[e] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nr = 0;
+    for (int q = 0; q < S; ++q) nr += c->run[q];
+    c->n_run = nr;
+  }
+}
+
 // --------------------------------------------------------- vector kernels ---
 
 // sum_k vals[k] z[col k] for the two samples of lane `sub`, the values (TV)
@@ -707,7 +727,7 @@ static ens_status read_flag(const int32_t* dev, hipStream_t st, int32_t* out) {
 template <int S, typename TV>
 static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, double* x, double rtol, int restart,
                         int max_iter, const MgPlan* plan, const GmWork& w, const int32_t* mask,
-                        const double* rtol_e, hipStream_t st, bool x_zero = false) {
+                        const double* rtol_e, hipStream_t st, bool x_zero = false, bool trust = false) {
   const int n = g->n;
   const int64_t nchunks = (int64_t)n * S / VecMap<double, S>::V;
   const int64_t vstride = (int64_t)n * S;
@@ -819,6 +839,16 @@ static ens_status gmres(const ens_graph* g, const TV* vals, const double* b, dou
     } else {
       hipLaunchKernelGGL((k_gm_zupdate<S, double>), dim3(eg), dim3(kBlock), 0, st, nchunks, (const double*)w.Z,
                          vstride, steps, w.ctl, x);
+    }
+    if (trust) {
+      // samples whose estimate met the tolerance stop here; the true
+      // residual is formed only if a further cycle is needed
+      hipLaunchKernelGGL((k_gm_accept<S>), dim3(1), dim3(64), 0, st, w.ctl);
+      ENS_LAUNCH_CHECK();
+      int32_t nleft = 0;
+      rc = read_flag(&w.ctl->n_run, st, &nleft);
+      if (rc != ENS_OK) return rc;
+      if (nleft == 0) break;
     }
     hipLaunchKernelGGL((k_gm_residual<S, TV>), dim3(rb), dim3(kBlock), 0, st, n, g->row_ptr, g->col_idx, vals, x, b,
                        w.w, w.rpart);
@@ -1009,10 +1039,10 @@ static ens_status newton(int N, const ens_graph* g, const void* kl, const ens_nl
     hipLaunchKernelGGL(k_fill_zero64, dim3(grid_of(total, kBlock)), dim3(kBlock), 0, st, total, w.d);
     if (o.jac32)
       rc = gmres<S, float>(g, (const float*)w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm,
-                           w.ctl->active, w.ctl->eta, st, true);
+                           w.ctl->active, w.ctl->eta, st, true, true);
     else
       rc = gmres<S, double>(g, (const double*)w.J, w.F, w.d, o.lin_rtol, o.restart, o.lin_max_iter, plan, w.gm,
-                            w.ctl->active, w.ctl->eta, st, true);
+                            w.ctl->active, w.ctl->eta, st, true, true);
     if (rc != ENS_OK) return rc;
     hipLaunchKernelGGL((k_nt_after<S>), dim3(1), dim3(64), 0, st, w.ctl, (const GmCtl*)w.gm.ctl);
     hipLaunchKernelGGL((k_nt_update<S>), dim3(grid_of(total, kBlock)), dim3(kBlock), 0, st, total, w.ctl, w.d, u);
