@@ -922,7 +922,8 @@ def run_newton(args):
     xi = torch.as_tensor(w.xi(), device=dev)
     prob = ens.nl_problem(w.M, w.sigma, W.NEWTON_ALPHA, W.NEWTON_BETA, W.NEWTON_VEL, L=w.L, kappa0=w.kappa0, f=w.f)
     mg32 = not args.mg_fp64
-    K = torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
+    # an FP32 hierarchy needs no FP64 fine matrix: it is not formed
+    K = None if mg32 else torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
     K32 = torch.empty((w.nnz, w.s), dtype=torch.float32, device=dev) if mg32 else None
     rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
     u = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)

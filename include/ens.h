@@ -377,8 +377,10 @@ ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* 
 /* ens_assemble of the fine matrix (values, values32, rhs as there; kl from
  * ens_kl_build(N, M, L)) followed by ens_mg_setup, with the fine level's D^-1
  * and Gershgorin bound formed inside the assembly (the same values, bitwise,
- * without a separate pass over the fine matrix).  Arguments and errors as
- * for the two calls; stream ordered. */
+ * without a separate pass over the fine matrix).  An FP32 hierarchy of more
+ * than one level does not read the FP64 fine matrix: values may then be
+ * NULL, and only values32 is formed.  Arguments and errors as for the two
+ * calls; stream ordered. */
 ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
                                  const ens_problem* problem, const double* xi, double* values, float* values32,
                                  double* rhs, hipStream_t stream);

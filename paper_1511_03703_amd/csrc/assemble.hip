@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
         if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
         else if (bnd_col) v = 0.0;
         const int64_t k = (start + pos) * S + e;
-        values[k] = v;
+        if (values) values[k] = v;
         if (values32) values32[k] = (float)v;
         if (BND) {
           const double vc = BND == 1 ? (double)(float)v : v;  // the value the cycle runs on
@@ -521,7 +521,7 @@ ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, cons
 #undef ENS_ASM_LAUNCH
   }
   ENS_LAUNCH_CHECK();
-  double bytes = (double)nnz * s * (8.0 + (values32 ? 4.0 : 0.0)) + (double)n * s * 8.0 + 4.0 * (n + 1);
+  double bytes = (double)nnz * s * ((values ? 8.0 : 0.0) + (values32 ? 4.0 : 0.0)) + (double)n * s * 8.0 + 4.0 * (n + 1);
   if (bnd) bytes += (double)n * s * (bnd == 1 ? 4.0 : 8.0);
   prof_end(ENS_K_ASSEMBLE, stream, bytes);
   return ENS_OK;

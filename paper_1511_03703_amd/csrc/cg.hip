@@ -325,8 +325,8 @@ static void residual(const ens_graph* g, const double* vals, const double* x, co
   const unsigned sb = grid_for(g->n, 4 * M::RPW);
   if (initial) {
     const int64_t total = (int64_t)g->n * S;
-    hipLaunchKernelGGL(k_x_nonzero, dim3(grid_for(total, 256 * 16) < 1024 ? grid_for(total, 256 * 16) : 1024),
-                       dim3(256), 0, st, total, x, w.ctl);
+    const unsigned xb = grid_for(total / 2, 256 * 4);
+    hipLaunchKernelGGL(k_x_nonzero, dim3(xb < 2048 ? xb : 2048), dim3(256), 0, st, total, x, w.ctl);
   }
   hipLaunchKernelGGL((k_residual<S, TR>), dim3(sb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
                      rout, w.part, initial ? (const Ctl*)w.ctl : (const Ctl*)nullptr);

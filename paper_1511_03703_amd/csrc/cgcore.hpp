@@ -607,10 +607,22 @@ __device__ inline void pupdate_z_body(int64_t nchunks, const T* __restrict__ z, 
 
 // c->xnz = 1 if any of the `total` entries of x is nonzero (every block
 // that finds one stores the same value).
+// total is n * S with S >= 4, so x is read as 16-byte pairs, four loads in
+// flight per lane.
 __device__ inline void x_nonzero_body(int64_t total, const double* __restrict__ x, Ctl* c) {
+  const int64_t nv = total / 2, stride = (int64_t)gridDim.x * blockDim.x;
+  const double2* __restrict__ xv = (const double2*)x;
   int any = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
-    any |= x[i] != 0.0;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    const double2 a = xv[i], b = xv[i + stride], d = xv[i + 2 * stride], e = xv[i + 3 * stride];
+    any |= (a.x != 0.0) | (a.y != 0.0) | (b.x != 0.0) | (b.y != 0.0) | (d.x != 0.0) | (d.y != 0.0) |
+           (e.x != 0.0) | (e.y != 0.0);
+  }
+  for (; i < nv; i += stride) {
+    const double2 a = xv[i];
+    any |= (a.x != 0.0) | (a.y != 0.0);
+  }
   if (__syncthreads_or(any) && threadIdx.x == 0) c->xnz = 1;
 }
 

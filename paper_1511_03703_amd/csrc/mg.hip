@@ -677,9 +677,10 @@ ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* 
 static ens_status assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
                                  const ens_problem* problem, const double* adv, const double* xi, double* values,
                                  float* values32, double* rhs, hipStream_t stream) {
-  ENS_ARG_CHECK(mg && graph && kl && problem && xi && values && rhs && mg->buffer, "null argument");
+  ENS_ARG_CHECK(mg && graph && kl && problem && xi && rhs && mg->buffer, "null argument");
+  ENS_ARG_CHECK(values || mg->fp32, "an FP64 hierarchy needs the FP64 fine matrix");
   ENS_ARG_CHECK(((uintptr_t)mg->buffer & 255u) == 0, "multigrid buffer must be 256-byte aligned");
-  ENS_ARG_CHECK(aligned16(values) && aligned16(rhs), "values and rhs must be 16-byte aligned");
+  ENS_ARG_CHECK((!values || aligned16(values)) && aligned16(rhs), "values and rhs must be 16-byte aligned");
   ENS_ARG_CHECK(!mg->fp32 || (values32 && aligned16(values32)), "an FP32 cycle needs the FP32 fine matrix");
   ENS_ARG_CHECK(problem->M == mg->M && problem->M >= 0 && problem->M <= 16, "problem->M differs or is out of range");
   int64_t n = 0, nnz = 0;
@@ -702,6 +703,8 @@ static ens_status assemble_setup(const ens_mg* mg, const ens_graph* graph, const
   ENS_ARG_CHECK(problem->L == Lb, "problem->L differs from the correlation length the hierarchy was built for");
   MgPlan plan;
   mg_plan(mg->N, mg->M, mg->s, mg->fp32 != 0, (char*)mg->buffer, &plan);
+  // a one-level hierarchy inverts the fine matrix itself, in FP64
+  ENS_ARG_CHECK(values || plan.levels > 1, "a one-level hierarchy needs the FP64 fine matrix");
   mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values, mg->fp32 ? values32 : nullptr);
   const double *sq = nullptr, *phi = nullptr;
   const int32_t* tr = nullptr;

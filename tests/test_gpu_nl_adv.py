@@ -160,3 +160,31 @@ def test_cg_refuses_the_advection_hierarchy_until_set_up_again(E, orc):
     mg.assemble_setup(g, kl, xt, sigma, K2, b2)
     x, stats, st = E.cg_mg(g, K2, b2, mg, opts=E.cg_opts(rtol=1e-10))
     assert st == E.ENS_OK and all(t["status"] == 0 for t in stats)
+
+
+def test_fp32_hierarchy_without_the_fp64_fine_matrix(E, orc):
+    # an FP32 hierarchy of several levels never reads the FP64 fine matrix:
+    # set up without it, it forms the same FP32 matrix and load and gives the
+    # same Newton solve, bitwise; a one-level hierarchy refuses
+    N, s, M, sigma = 12, 8, 10, 0.3
+    xi = draw_xi(4760, s, M)
+    g = E.graph_build(N)
+    kl = E.kl_build(N, M)
+    xt = torch.as_tensor(xi, device=DEV)
+    prob = E.nl_problem(M, sigma, 10.0, 100.0, VEL)
+    mg1, _, K32a, rhsa = _adv_mg(E, N, M, s, g, kl, xt, prob, fp32=True)
+    K32b = torch.full((g.nnz, s), float("nan"), dtype=torch.float32, device=DEV)
+    rhsb = torch.full((g.n, s), float("nan"), dtype=torch.float64, device=DEV)
+    mg2 = E.Multigrid(N, M, s, fp32=True).assemble_setup_adv(g, kl, xt, prob, None, rhsb, values32=K32b)
+    assert torch.equal(K32a, K32b) and torch.equal(rhsa, rhsb)
+    opts = E.newton_opts(rtol=1e-8, lin_rtol=0.3, jac32=True, forcing=E.FORCING_EW)
+    u1, st1, _ = E.newton(g, kl, xt, prob, opts=opts, mg=mg1, mg_values=K32a)
+    u2, st2, _ = E.newton(g, kl, xt, prob, opts=opts, mg=mg2, mg_values=K32b)
+    assert torch.equal(u1, u2) and st1 == st2
+    g4, kl4 = E.graph_build(4), E.kl_build(4, M)
+    with pytest.raises(E.EnsError, match="one-level"):
+        E.Multigrid(4, M, s, fp32=True).assemble_setup_adv(
+            g4, kl4, xt, prob, None, torch.empty((g4.n, s), dtype=torch.float64, device=DEV),
+            values32=torch.empty((g4.nnz, s), dtype=torch.float32, device=DEV))
+    with pytest.raises(E.EnsError, match="FP64 hierarchy"):
+        E.Multigrid(N, M, s).assemble_setup_adv(g, kl, xt, prob, None, rhsb)
