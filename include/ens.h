@@ -517,7 +517,7 @@ ens_status ens_relayout(const double* src, double* dst, int64_t rows, int32_t s,
 /* ------------------------------------------------- learned initial guess */
 
 /* A reduced basis and a small network predict an initial guess for CG from
- * the KL inputs y of a sample; CG remains the solver and the judge of the
+ * the KL inputs y of a sample; CG remains the solver and decides the
  * error (an extension of the method; the paper solves from zero).
  *
  * Network: 10 -> 256 -> 256 -> 32, GELU (exact erf form) after the two
