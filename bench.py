@@ -129,8 +129,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
-              f"path is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the path is measured on one GPU's "
+              f"share at its real shape; sharding over several GPUs is designed, not built.", file=sys.stderr)
         sys.exit(2)
     heavy = args.workload in ("batch", "learned")
     if args.steps is None:
