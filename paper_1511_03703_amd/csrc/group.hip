@@ -5,7 +5,7 @@
 // of that predictor is ens_kl_extrema (assemble.hip), and this host step
 // turns any per-sample key into an order whose consecutive runs are the
 // ensembles.
-#include <math.h>
+#include <cmath>
 
 #include <algorithm>
 #include <numeric>
