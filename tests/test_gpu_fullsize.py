@@ -7,6 +7,10 @@ configuration bench.py times, on samples the oracle can afford one by one.
   128^3, s = 32, FP32 CG in FP64 refinement to 1e-8: samples 0 and 31 --
       the oracle assembles each sample from scratch and checks the true FP64
       residual of the GPU solution (<= 1e-8) and the assembled values (1e-13).
+  The batch: one group of the drawn batch per mesh size (32^3 .. 96^3,
+      s = 32, tile 4), FP64 Jacobi-CG to 1e-8: samples 0 and 31 of each
+      against the oracle at the GPU's iteration counts (relative 1e-9), the
+      oracle's own counts within +-1, the true residual <= 1e-8.
 """
 import concurrent.futures as cf
 
@@ -154,3 +158,38 @@ def test_newton_workload(E, orc):
             assert res <= w.rtol * (1 + 1e-6)
             assert abs(stats[e]["rel_res"] - res) <= 1e-3 * res + 1e-14
             assert dF <= 1e-12 and dJ <= 1e-13 and dK <= 1e-13
+
+
+def test_batch_workload_sampled(E, orc):
+    import workloads as W
+    meshes = W.batch_meshes()
+    s, M, sigma, rtol = 32, W.BATCH_M, W.BATCH_SIGMA, W.BATCH_RTOL
+    xi_all = W.draw_xi(W.BATCH_XI_SEED, len(meshes) * s, M).reshape(len(meshes), s, M)
+    picks = [int(np.flatnonzero(meshes == N)[0]) for N in W.BATCH_MESHES]
+    groups = []
+    for gi in picks:
+        N = int(meshes[gi])
+        g, kl = E.graph_build(N), E.kl_build(N, M)
+        v, _, b = E.assemble(g, kl, torch.as_tensor(xi_all[gi], device="cuda"), M, sigma)
+        groups.append([g, v, b, torch.zeros_like(b)])
+    stats, rc, _ = E.solve_batch(groups, s, E.batch_opts(rtol=rtol, check_every=16, tile=4))
+    assert rc == E.ENS_OK
+    xs = [gr[3][:, [0, s - 1]].cpu().numpy() for gr in groups]
+    del groups
+    torch.cuda.empty_cache()
+    print(f"GPU done: iterations {[[st[0]['iters'], st[-1]['iters']] for st in stats]}", flush=True)
+    for gi, st, x in zip(picks, stats, xs):
+        N = int(meshes[gi])
+        rp, ci = orc.graph(N)
+        xi = xi_all[gi][[0, s - 1]]
+        ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+        iters = np.array([st[0]["iters"], st[-1]["iters"]], np.int32)
+        xo, _, _, _ = orc.ens_pcg(rp, ci, ov, ob, fixed_iters=iters)
+        _, itt, _, _ = orc.ens_pcg(rp, ci, ov, ob, rtol=rtol)
+        true = orc.ens_true_residual(rp, ci, ov, ob, x)
+        for k in range(2):
+            print(f"N={N} sample {k}: iters {iters[k]} (oracle {itt[k]}), rel diff "
+                  f"{_rel(x[:, k], xo[:, k]):.2e}, true residual {true[k]:.2e}", flush=True)
+            assert _rel(x[:, k], xo[:, k]) <= 1e-9
+            assert abs(int(itt[k]) - int(iters[k])) <= 1
+            assert true[k] <= rtol * (1 + 1e-6)
