@@ -7,6 +7,11 @@ configuration bench.py times, on samples the oracle can afford one by one.
   128^3, s = 32, FP32 CG in FP64 refinement to 1e-8: samples 0 and 31 --
       the oracle assembles each sample from scratch and checks the true FP64
       residual of the GPU solution (<= 1e-8) and the assembled values (1e-13).
+  The learned guess at 64^3, s = 32 (a reduced training set of 256
+      snapshots): held-out samples 0 and 31 solved by FP64 Jacobi-CG from the
+      network's guess, against the oracle started from the same guess at the
+      GPU's iteration counts (relative 1e-9), its own counts within +-1, the
+      true residual <= 1e-8.
   The batch: one group of the drawn batch per mesh size (32^3 .. 96^3,
       s = 32, tile 4), FP64 Jacobi-CG to 1e-8: samples 0 and 31 of each
       against the oracle at the GPU's iteration counts (relative 1e-9), the
@@ -193,3 +198,41 @@ def test_batch_workload_sampled(E, orc):
             assert _rel(x[:, k], xo[:, k]) <= 1e-9
             assert abs(int(itt[k]) - int(iters[k])) <= 1
             assert true[k] <= rtol * (1 + 1e-6)
+
+
+def test_learned_workload_sampled(E, orc):
+    import workloads as W
+    from paper_1511_03703_amd.learned import LearnedGuess
+    w = W.LEARNED
+    g, kl = E.graph_build(w.N), E.kl_build(w.N, w.M, w.L)
+    train_xi = W.draw_xi(W.LEARNED_TRAIN_SEED, 256, w.M)
+    Sm = torch.zeros((g.n, 256), dtype=torch.float64, device="cuda")
+    for j in range(256 // w.s):
+        v, _, b = E.assemble(g, kl, torch.as_tensor(train_xi[w.s * j:w.s * (j + 1)], device="cuda"), w.M, w.sigma)
+        x, _, rc = E.cg(g, v, b, opts=E.cg_opts(rtol=1e-10))
+        assert rc == E.ENS_OK
+        E.pod_collect(x, Sm, w.s * j)
+    lg = LearnedGuess(r=32, device="cuda")
+    T = lg.fit_basis(Sm, eig_seed=W.LEARNED_INIT_SEED)
+    lg.fit_network(torch.as_tensor(train_xi, dtype=torch.float32, device="cuda"), T, steps=600,
+                   init_seed=W.LEARNED_INIT_SEED + 1, order_seed=W.LEARNED_INIT_SEED + 2, batch=64, halvings=2)
+    test_xi = W.draw_xi(W.LEARNED_TEST_SEED, w.s, w.M)
+    v, _, b = E.assemble(g, kl, torch.as_tensor(test_xi, device="cuda"), w.M, w.sigma)
+    x0 = lg.guess(torch.as_tensor(test_xi, dtype=torch.float32, device="cuda"))
+    x, st, rc = E.cg(g, v, b, x=x0.clone(), opts=E.cg_opts(rtol=w.rtol))
+    assert rc == E.ENS_OK
+    pick = [0, w.s - 1]
+    xg, x0g = x[:, pick].cpu().numpy(), x0[:, pick].cpu().numpy()
+    iters = np.array([st[e]["iters"] for e in pick], np.int32)
+    print(f"GPU done: iterations {[t['iters'] for t in st]}", flush=True)
+    rp, ci = orc.graph(w.N)
+    ov, ob = orc.assemble_ensemble(w.N, rp, ci, w.M, w.L, w.kappa0, w.sigma, w.f, test_xi[pick])
+    xo, _, _, _ = orc.ens_pcg(rp, ci, ov, ob, x0=x0g, fixed_iters=iters)
+    _, itt, _, _ = orc.ens_pcg(rp, ci, ov, ob, x0=x0g, rtol=w.rtol)
+    true = orc.ens_true_residual(rp, ci, ov, ob, xg)
+    for k in range(2):
+        print(f"sample {pick[k]}: iters {iters[k]} (oracle {itt[k]}), rel diff {_rel(xg[:, k], xo[:, k]):.2e}, "
+              f"true residual {true[k]:.2e}", flush=True)
+        assert _rel(xg[:, k], xo[:, k]) <= 1e-9
+        assert abs(int(itt[k]) - int(iters[k])) <= 1
+        assert true[k] <= w.rtol * (1 + 1e-6)
