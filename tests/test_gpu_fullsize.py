@@ -7,6 +7,10 @@ configuration bench.py times, on samples the oracle can afford one by one.
   128^3, s = 32, FP32 CG in FP64 refinement to 1e-8: samples 0 and 31 --
       the oracle assembles each sample from scratch and checks the true FP64
       residual of the GPU solution (<= 1e-8) and the assembled values (1e-13).
+  The one-sample baseline at 64^3 (the mid workload's 16 samples in the
+      sample-major layout, 16 lanes per row as timed): samples 0 and 15
+      against the oracle at the GPU's iteration counts (relative 1e-9), its
+      own counts within +-1.
   The learned guess at 64^3, s = 32 (a reduced training set of 256
       snapshots): held-out samples 0 and 31 solved by FP64 Jacobi-CG from the
       network's guess, against the oracle started from the same guess at the
@@ -236,3 +240,31 @@ def test_learned_workload_sampled(E, orc):
         assert _rel(xg[:, k], xo[:, k]) <= 1e-9
         assert abs(int(itt[k]) - int(iters[k])) <= 1
         assert true[k] <= w.rtol * (1 + 1e-6)
+
+
+def test_one_sample_baseline_at_64_cubed(E, orc):
+    w = MID
+    xi = w.xi()
+    g = E.graph_build(w.N)
+    kl = E.kl_build(w.N, w.M, w.L)
+    vals, _, rhs = E.assemble(g, kl, torch.as_tensor(xi, device="cuda"), w.M, w.sigma)
+    vsm, bsm = E.relayout(vals, True), E.relayout(rhs, True)
+    del vals
+    xs, stats, st = E.scalar_cg(g, vsm, bsm, opts=E.cg_opts(rtol=w.rtol), lanes_per_row=16)
+    assert st == E.ENS_OK
+    check = [0, w.s - 1]
+    xg = {e: xs[e].cpu().numpy() for e in check}
+    print(f"GPU done: iterations {[t['iters'] for t in stats]}", flush=True)
+    rp, ci = orc.graph(w.N)
+
+    def one(e):
+        v, b = _oracle_sample(orc, rp, ci, w, xi[e])
+        xo = orc.pcg(rp, ci, v, b, fixed_iters=stats[e]["iters"])[0]
+        _, it_tol, _, _ = orc.pcg(rp, ci, v, b, rtol=w.rtol)
+        return e, _rel(xg[e], xo), it_tol
+
+    with cf.ThreadPoolExecutor(2) as ex:
+        for e, dx, it_tol in ex.map(one, check):
+            print(f"sample {e}: x {dx:.2e} iters gpu {stats[e]['iters']} oracle {it_tol}", flush=True)
+            assert dx <= 1e-9
+            assert abs(int(it_tol) - stats[e]["iters"]) <= 1
