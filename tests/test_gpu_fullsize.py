@@ -4,9 +4,11 @@ configuration bench.py times, on samples the oracle can afford one by one.
   64^3, s = 16, FP64 Jacobi-CG to 1e-10: samples 0-3 compared at the GPU's
       iteration counts (relative 1e-9), iteration counts within +-1, values
       of those samples against the oracle's scalar assembly (1e-13).
-  128^3, s = 32, FP32 CG in FP64 refinement to 1e-8: samples 0 and 31 --
-      the oracle assembles each sample from scratch and checks the true FP64
-      residual of the GPU solution (<= 1e-8) and the assembled values (1e-13).
+  128^3, s = 32, FP32 CG in FP64 refinement to 1e-8, with Jacobi and with
+      the FP32 multigrid cycle of the timed step: samples 0 and 31 -- the
+      oracle assembles each sample from scratch and checks the true FP64
+      residual of both GPU solutions (<= 1e-8) and the assembled values
+      (1e-13).
   The one-sample baseline at 64^3 (the mid workload's 16 samples in the
       sample-major layout, 16 lanes per row as timed): samples 0 and 15
       against the oracle at the GPU's iteration counts (relative 1e-9), its
@@ -94,23 +96,36 @@ def test_headline_workload_refinement(E, orc):
     xg = {e: x[:, e].cpu().numpy() for e in check}
     g32 = v32[:, check[0]].cpu().numpy()
     assert np.array_equal(g32, gv[check[0]].astype(np.float32))
-    del vals, v32
-    torch.cuda.empty_cache()
     print(f"GPU done: inner iterations {[s['iters'] for s in stats]}", flush=True)
+    # the timed step: the same refinement with the FP32 multigrid cycle, its
+    # fine matrix formed by the fused assembly and set-up
+    mg = E.Multigrid(w.N, w.M, w.s, fp32=True, L=w.L)
+    mg.assemble_setup(g, kl, torch.as_tensor(xi, device="cuda"), w.sigma, vals, rhs, values32=v32)
+    opts_mg = E.cg_opts(rtol=w.rtol, mixed=True, inner_rtol=1e-4, check_every=4)
+    xm, stats_mg, st = E.cg_mg(g, vals, rhs, mg, values32=v32, opts=opts_mg)
+    assert st == E.ENS_OK
+    xmg = {e: xm[:, e].cpu().numpy() for e in check}
+    print(f"GPU done: multigrid inner iterations {[s['iters'] for s in stats_mg]}", flush=True)
+    del vals, v32, mg, xm
+    torch.cuda.empty_cache()
     rp, ci = orc.graph(w.N)
 
     def one(e):
         v, b = _oracle_sample(orc, rp, ci, w, xi[e])
-        res = np.linalg.norm(b - orc.spmv(rp, ci, v, xg[e])) / np.linalg.norm(b)
-        return e, _rel(gv[e], v), res
+        nb = np.linalg.norm(b)
+        res = np.linalg.norm(b - orc.spmv(rp, ci, v, xg[e])) / nb
+        res_mg = np.linalg.norm(b - orc.spmv(rp, ci, v, xmg[e])) / nb
+        return e, _rel(gv[e], v), res, res_mg
 
     with cf.ThreadPoolExecutor(2) as ex:
-        for e, dv, res in ex.map(one, check):
-            print(f"sample {e}: values {dv:.2e} true residual {res:.3e} (GPU reported {stats[e]['rel_res']:.3e})",
-                  flush=True)
+        for e, dv, res, res_mg in ex.map(one, check):
+            print(f"sample {e}: values {dv:.2e} true residual {res:.3e} (GPU reported {stats[e]['rel_res']:.3e}), "
+                  f"multigrid {res_mg:.3e} (GPU reported {stats_mg[e]['rel_res']:.3e})", flush=True)
             assert dv <= 1e-13
             assert res <= w.rtol * (1 + 1e-6)
             assert abs(res - stats[e]["rel_res"]) <= 1e-3 * res
+            assert res_mg <= w.rtol * (1 + 1e-6)
+            assert abs(res_mg - stats_mg[e]["rel_res"]) <= 1e-3 * res_mg
 
 
 def test_newton_workload(E, orc):
