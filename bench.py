@@ -118,6 +118,8 @@ def main():
                     help="refinement inner tolerance (default: 1e-4 with multigrid, 1e-5 with Jacobi, the measured "
                          "optima at 128^3, s=32)")
     ap.add_argument("--check-every", type=int, default=16)
+    ap.add_argument("--compact", action="store_true",
+                    help="FP64 solve workloads: finish the last s/2 iterating samples in a compacted ensemble")
     ap.add_argument("--lin-rtol", type=float, default=None, help="newton: GMRES tolerance per Newton step")
     ap.add_argument("--jac-fp64", action="store_true", help="newton: keep the Jacobian in FP64 for GMRES")
     ap.add_argument("--newton-mg", default="adv", choices=["adv", "diffusion"],
@@ -169,7 +171,8 @@ def run_solve(args):
     rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
     x = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)
     jac_inner = args.inner_rtol if args.inner_rtol is not None else 1e-5
-    opts = ens.cg_opts(rtol=w.rtol, mixed=w.mixed, inner_rtol=jac_inner, check_every=args.check_every)
+    opts = ens.cg_opts(rtol=w.rtol, mixed=w.mixed, inner_rtol=jac_inner, check_every=args.check_every,
+                       compact=args.compact and not w.mixed)
     ws = torch.empty(ens.cg_workspace_bytes(g, w.s, opts), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     if args.calib_copy_mb > 0:

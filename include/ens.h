@@ -232,13 +232,25 @@ typedef struct {
                              the test is |r| <= rtol |b| over all samples
                              together.  FP64 only (mixed must be 0); stats
                              still report each sample's true residual. */
+  int32_t compact;        /* 1: compaction of finished samples (Sec. 3.7: a
+                             finished sample still costs its share of every
+                             pass over the ensemble).  FP64 per-sample CG
+                             only (mixed and coupled 0; ENS_E_ARG otherwise),
+                             s >= 8 (no effect for s = 4): at the first poll
+                             where at most s/2 samples still iterate, those
+                             samples move to an ensemble of s/2 (matrix
+                             values, x, r, p, D^-1 and their CG state
+                             gathered), finish there, and x and the stats are
+                             scattered back.  Each sample's iterates are
+                             those of the uncompacted solve up to rounding;
+                             the workspace grows by the s/2 ensemble. */
 } ens_cg_opts;
 
 typedef struct {
   int32_t iters;       /* CG iterations (mixed: total inner iterations)      */
   int32_t outer_iters; /* mixed: refinement steps taken; 0 for FP64 CG       */
   int32_t status;      /* ENS_SAMPLE_*                                       */
-  int32_t reserved;
+  int32_t compacted;   /* 1 if the sample finished in the compacted ensemble */
   double rel_res;      /* true FP64 residual |b - A x| / |b| of the result   */
 } ens_cg_stat;
 

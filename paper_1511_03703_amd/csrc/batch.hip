@@ -424,7 +424,7 @@ static ens_status solve_batch(const ens_group* groups, int ng, const ens_batch_o
       s.iters = h[i].iters[e];
       s.outer_iters = 0;
       s.status = h[i].status[e];
-      s.reserved = 0;
+      s.compacted = 0;
       s.rel_res = h[i].rel_res[e];
       if (s.status != ENS_SAMPLE_CONVERGED) agg = ENS_W_NOT_CONVERGED;
     }

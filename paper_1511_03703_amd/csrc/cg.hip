@@ -283,10 +283,13 @@ static void cg_iteration(const ens_graph* g, const T* vals, T* x, T* r, T* p, T*
 }
 
 // CG loop on already-initialised state; x is the solution (FP64 CG) or
-// the correction d (refinement inner solve).
+// the correction d (refinement inner solve).  pause_at > 0: return after
+// the first poll that finds 1..pause_at samples still iterating, with
+// *paused_after = the iterations launched so far (left at -1 otherwise).
 template <typename T, int S>
 static ens_status cg_loop(const ens_graph* g, const T* vals, T* x, T* r, T* p, T* q, T* dinv, Work& w,
-                          int max_iter, int check_every, hipStream_t st) {
+                          int max_iter, int check_every, hipStream_t st, int pause_at = 0,
+                          int* paused_after = nullptr) {
   for (int k0 = 0; k0 < max_iter; k0 += check_every) {
     const int k1 = k0 + check_every < max_iter ? k0 + check_every : max_iter;
     for (int k = k0 + 1; k <= k1; ++k) cg_iteration<T, S>(g, vals, x, r, p, q, dinv, w, k, st);
@@ -295,6 +298,10 @@ static ens_status cg_loop(const ens_graph* g, const T* vals, T* x, T* r, T* p, T
     ens_status s2 = poll_active(w.ctl, false, st, &act);
     if (s2 != ENS_OK) return s2;
     if (act == 0) break;
+    if (pause_at > 0 && act <= pause_at && k1 < max_iter) {
+      *paused_after = k1;
+      return ENS_OK;
+    }
   }
   return ENS_OK;
 }
@@ -309,7 +316,7 @@ static ens_status read_stats(Ctl* ctl, int s, ens_cg_stat* stats, hipStream_t st
     stats[e].iters = h.iters[e];
     stats[e].outer_iters = h.oiters[e];
     stats[e].status = h.status[e];
-    stats[e].reserved = 0;
+    stats[e].compacted = h.compacted[e];
     stats[e].rel_res = h.rel_res[e];
     if (h.status[e] != ENS_SAMPLE_CONVERGED) rc = ENS_W_NOT_CONVERGED;
   }
@@ -341,9 +348,163 @@ static void cg_start(int64_t n, const T* r, const T* dinv, T* p, T* xzero, const
   reduce<S, 2>(w, vb, OP_RHO, 0, 0, st);
 }
 
+// ------------------------------------------------------------ compaction --
+
+// Columns of an ensemble picked for the compacted one: j -> sample col[j].
+struct ColPick {
+  int32_t col[kMaxS / 2];
+};
+
+// dst[r][j] = src[r][col[j]] for rows r < rows, j < H.
+template <int S, int H>
+__global__ __launch_bounds__(256) void k_gather_cols(int64_t rows, const double* __restrict__ src,
+                                                     double* __restrict__ dst, ColPick pick) {
+  __shared__ int32_t s_col[H];
+  if (threadIdx.x < H) s_col[threadIdx.x] = pick.col[threadIdx.x];
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * H) return;
+  const int64_t r = t / H;
+  const int j = (int)(t % H);
+  dst[t] = src[r * S + s_col[j]];
+}
+
+// dst[r][col[j]] = src[r][j] for j < m (the samples that moved).
+template <int S, int H>
+__global__ __launch_bounds__(256) void k_scatter_cols(int64_t rows, const double* __restrict__ src,
+                                                      double* __restrict__ dst, ColPick pick, int m) {
+  __shared__ int32_t s_col[H];
+  if (threadIdx.x < H) s_col[threadIdx.x] = pick.col[threadIdx.x];
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * H) return;
+  const int64_t r = t / H;
+  const int j = (int)(t % H);
+  if (j < m) dst[r * S + s_col[j]] = src[t];
+}
+
+// The CG state of the picked samples into the compacted control block; the
+// columns after the m moving samples are padding and never iterate.
+template <int H>
+__global__ void k_ctl_compact(const Ctl* __restrict__ src, Ctl* __restrict__ dst, ColPick pick, int m) {
+  const int j = threadIdx.x;
+  if (j == 0) {
+    dst->rtol = src->rtol;
+    dst->inner_rtol = src->inner_rtol;
+    dst->max_iter = src->max_iter;
+    dst->inner_max_iter = src->inner_max_iter;
+    dst->max_outer = src->max_outer;
+    dst->mixed = src->mixed;
+    dst->coupled = src->coupled;
+    dst->xnz = src->xnz;
+    dst->n_active = m;
+    dst->n_oactive = 0;
+  }
+  if (j < kMaxS) {
+    const bool live = j < H && j < m;
+    const int e = j < H ? pick.col[j] : 0;
+    dst->rho[j] = src->rho[e];
+    dst->alpha[j] = src->alpha[e];
+    dst->beta[j] = src->beta[e];
+    dst->tol2[j] = src->tol2[e];
+    dst->bnorm2[j] = src->bnorm2[e];
+    dst->rel_res[j] = src->rel_res[e];
+    dst->orr_prev[j] = src->orr_prev[e];
+    dst->active[j] = live ? src->active[e] : 0;
+    dst->oactive[j] = 0;
+    dst->iters[j] = src->iters[e];
+    dst->oiters[j] = src->oiters[e];
+    dst->kiter[j] = src->kiter[e];
+    dst->status[j] = src->status[e];
+    dst->zero_b[j] = src->zero_b[e];
+    dst->compacted[j] = live;
+  }
+}
+
+// The moved samples' CG state back into the full control block.
+template <int H>
+__global__ void k_ctl_expand(const Ctl* __restrict__ src, Ctl* __restrict__ dst, ColPick pick, int m) {
+  const int j = threadIdx.x;
+  if (j < H && j < m) {
+    const int e = pick.col[j];
+    dst->rho[e] = src->rho[j];
+    dst->rel_res[e] = src->rel_res[j];
+    dst->active[e] = src->active[j];
+    dst->iters[e] = src->iters[j];
+    dst->kiter[e] = src->kiter[j];
+    dst->status[e] = src->status[j];
+    dst->compacted[e] = 1;
+  }
+  __syncthreads();
+  if (j == 0) {
+    int na = 0;
+    for (int q = 0; q < kMaxS; ++q) na += dst->active[q];
+    dst->n_active = na;
+  }
+}
+
+// Bytes of the compacted ensemble: its control block, matrix values and
+// five vectors (x, r, p, q, D^-1), for an s-sample solve (0 if s < 8).
+static size_t compact_bytes(int64_t n, int64_t nnz, int s) {
+  if (s < 8) return 0;
+  const size_t h = (size_t)s / 2;
+  return round256(sizeof(Ctl)) + round256((size_t)nnz * h * sizeof(double)) +
+         5 * round256((size_t)n * h * sizeof(double));
+}
+
+// Finish the samples still iterating in an ensemble of H = S/2: gather the
+// values, vectors and CG state of the active samples (padded with finished
+// ones, which stay inactive), run the loop there, scatter x and the state
+// back.
+template <int S, int H>
+static ens_status cg_compacted(const ens_graph* g, const double* vals, double* x, const double* r, const double* p,
+                               const double* dinv, Work& w, int max_iter, int check_every, char* base,
+                               hipStream_t st) {
+  int32_t act[kMaxS];
+  ENS_HIP_TRY(hipMemcpyAsync(act, w.ctl->active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+  ENS_HIP_TRY(hipStreamSynchronize(st));
+  ColPick pick{};
+  int m = 0;
+  for (int e = 0; e < S && m < H; ++e)
+    if (act[e]) pick.col[m++] = e;
+  int k = m;
+  for (int e = 0; e < S && k < H; ++e)
+    if (!act[e]) pick.col[k++] = e;
+  const int64_t n = g->n, nnz = g->nnz;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* q = base + off;
+    off += round256(bytes);
+    return q;
+  };
+  Ctl* cc = (Ctl*)take(sizeof(Ctl));
+  double* vc = (double*)take((size_t)nnz * H * sizeof(double));
+  double* xc = (double*)take((size_t)n * H * sizeof(double));
+  double* rc = (double*)take((size_t)n * H * sizeof(double));
+  double* pc = (double*)take((size_t)n * H * sizeof(double));
+  double* qc = (double*)take((size_t)n * H * sizeof(double));
+  double* dc = (double*)take((size_t)n * H * sizeof(double));
+  const unsigned gv = grid_for(nnz * H, 256), gn = grid_for(n * H, 256);
+  hipLaunchKernelGGL((k_gather_cols<S, H>), dim3(gv), dim3(256), 0, st, nnz, vals, vc, pick);
+  hipLaunchKernelGGL((k_gather_cols<S, H>), dim3(gn), dim3(256), 0, st, n, x, xc, pick);
+  hipLaunchKernelGGL((k_gather_cols<S, H>), dim3(gn), dim3(256), 0, st, n, r, rc, pick);
+  hipLaunchKernelGGL((k_gather_cols<S, H>), dim3(gn), dim3(256), 0, st, n, p, pc, pick);
+  hipLaunchKernelGGL((k_gather_cols<S, H>), dim3(gn), dim3(256), 0, st, n, dinv, dc, pick);
+  hipLaunchKernelGGL((k_ctl_compact<H>), dim3(1), dim3(64), 0, st, w.ctl, cc, pick, m);
+  ENS_LAUNCH_CHECK();
+  Work cw = w;
+  cw.ctl = cc;
+  ens_status rc2 = cg_loop<double, H>(g, vc, xc, rc, pc, qc, dc, cw, max_iter, check_every, st);
+  if (rc2 != ENS_OK) return rc2;
+  hipLaunchKernelGGL((k_scatter_cols<S, H>), dim3(gn), dim3(256), 0, st, n, xc, x, pick, m);
+  hipLaunchKernelGGL((k_ctl_expand<H>), dim3(1), dim3(64), 0, st, cc, w.ctl, pick, m);
+  ENS_LAUNCH_CHECK();
+  return ENS_OK;
+}
+
 template <int S>
 static ens_status cg_fp64(const ens_graph* g, const double* vals, const double* b, double* x,
-                          const ens_cg_opts& o, Work& w, hipStream_t st) {
+                          const ens_cg_opts& o, Work& w, hipStream_t st, char* compact_base = nullptr) {
   double* r = (double*)w.vec[0];
   double* p = (double*)w.vec[1];
   double* q = (double*)w.vec[2];
@@ -356,8 +517,16 @@ static ens_status cg_fp64(const ens_graph* g, const double* vals, const double* 
   hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
   cg_start<double, S>(n, r, dinv, p, (double*)nullptr, w, st);
   ENS_LAUNCH_CHECK();
-  ens_status rc = cg_loop<double, S>(g, vals, x, r, p, q, dinv, w, o.max_iter, o.check_every, st);
+  int paused = -1;
+  const int pause_at = (compact_base && S >= 8) ? S / 2 : 0;
+  ens_status rc = cg_loop<double, S>(g, vals, x, r, p, q, dinv, w, o.max_iter, o.check_every, st, pause_at, &paused);
   if (rc != ENS_OK) return rc;
+  if constexpr (S >= 8) {
+    if (paused >= 0) {
+      rc = cg_compacted<S, S / 2>(g, vals, x, r, p, dinv, w, o.max_iter - paused, o.check_every, compact_base, st);
+      if (rc != ENS_OK) return rc;
+    }
+  }
   residual<S, double>(g, vals, x, b, (double*)nullptr, w, OP_TRUE, 0, st);
   ENS_LAUNCH_CHECK();
   return ENS_OK;
@@ -687,7 +856,8 @@ ens_status ens_cg_workspace_bytes(const ens_graph* graph, int32_t s, const ens_c
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
   }
-  *bytes = ws_layout(graph->n, s, opts->mixed != 0, nullptr, nullptr);
+  *bytes = ws_layout(graph->n, s, opts->mixed != 0, nullptr, nullptr) +
+           (opts->compact && !opts->mixed && !opts->coupled ? compact_bytes(graph->n, graph->nnz, s) : 0);
   return ENS_OK;
 }
 
@@ -706,12 +876,16 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
     set_error("coupled CG is implemented for FP64 (mixed = 0) only");
     return ENS_E_UNSUPPORTED;
   }
+  ENS_ARG_CHECK(!opts->compact || (!opts->mixed && !opts->coupled),
+                "compaction is for the FP64 per-sample CG (mixed and coupled 0)");
   if (!supported_s(s)) {
     set_error("ensemble size %d not compiled in", s);
     return ENS_E_UNSUPPORTED;
   }
   const bool mixed = opts->mixed != 0;
-  const size_t need = ws_layout(graph->n, s, mixed, nullptr, nullptr);
+  const size_t base_need = ws_layout(graph->n, s, mixed, nullptr, nullptr);
+  const size_t cbytes = opts->compact ? compact_bytes(graph->n, graph->nnz, s) : 0;
+  const size_t need = base_need + cbytes;
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     return ENS_E_NOMEM;
@@ -730,7 +904,7 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
 #define ENS_CG_CASE(SS)                                                                                      \
   case SS:                                                                                                   \
     st = mixed ? cg_mixed<SS>(graph, values, values32, b, x, o, w, stream)                                  \
-               : cg_fp64<SS>(graph, values, b, x, o, w, stream);                                            \
+               : cg_fp64<SS>(graph, values, b, x, o, w, stream, cbytes ? (char*)workspace + base_need : nullptr); \
     break;
     ENS_CG_CASE(4)
     ENS_CG_CASE(8)

@@ -19,6 +19,7 @@ struct Ctl {
   double rel_res[kMaxS], orr_prev[kMaxS];
   int32_t active[kMaxS], oactive[kMaxS], iters[kMaxS], oiters[kMaxS], kiter[kMaxS], status[kMaxS];
   int32_t zero_b[kMaxS];
+  int32_t compacted[kMaxS];  // the sample finished in the compacted ensemble
   int32_t n_active, n_oactive;
   double rtol, inner_rtol;
   int32_t max_iter, inner_max_iter, max_outer, mixed;
@@ -249,6 +250,7 @@ static __global__ void k_ctl_init(Ctl* c, double rtol, double inner_rtol, int ma
     c->kiter[e] = 0;
     c->status[e] = ENS_SAMPLE_MAXITER;
     c->zero_b[e] = 0;
+    c->compacted[e] = 0;
     c->rel_res[e] = 0.0;
   }
 }

@@ -1162,7 +1162,7 @@ ens_status ens_gmres(const ens_graph* graph, int32_t s, const double* values, co
     stats[e].iters = h->iters[e];
     stats[e].outer_iters = h->cycles[e];
     stats[e].status = h->status[e];
-    stats[e].reserved = 0;
+    stats[e].compacted = 0;
     stats[e].rel_res = h->rel_res[e];
     if (h->status[e] != ENS_SAMPLE_CONVERGED) rc = ENS_W_NOT_CONVERGED;
   }

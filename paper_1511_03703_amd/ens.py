@@ -48,12 +48,13 @@ class ens_problem(ctypes.Structure):
 class ens_cg_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mixed", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32),
-                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32), ("coupled", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32), ("coupled", ctypes.c_int32),
+                ("compact", ctypes.c_int32)]
 
 
 class ens_cg_stat(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("rel_res", ctypes.c_double)]
+                ("compacted", ctypes.c_int32), ("rel_res", ctypes.c_double)]
 
 
 class ens_group(ctypes.Structure):
@@ -435,8 +436,9 @@ def scalar_spmv(g: Graph, values: torch.Tensor, x: torch.Tensor, y=None, lanes_p
 
 
 def cg_opts(rtol=1e-10, max_iter=10000, mixed=False, inner_rtol=1e-5, inner_max_iter=10000, max_outer=10,
-            check_every=16, coupled=False) -> ens_cg_opts:
-    return ens_cg_opts(rtol, max_iter, int(mixed), inner_rtol, inner_max_iter, max_outer, check_every, int(coupled))
+            check_every=16, coupled=False, compact=False) -> ens_cg_opts:
+    return ens_cg_opts(rtol, max_iter, int(mixed), inner_rtol, inner_max_iter, max_outer, check_every, int(coupled),
+                       int(compact))
 
 
 def cg_workspace_bytes(g: Graph, s: int, opts: ens_cg_opts) -> int:
@@ -449,7 +451,7 @@ def cg_workspace_bytes(g: Graph, s: int, opts: ens_cg_opts) -> int:
 
 def _stats_list(st, count):
     return [{"iters": st[e].iters, "outer_iters": st[e].outer_iters, "status": st[e].status,
-             "rel_res": st[e].rel_res} for e in range(count)]
+             "compacted": st[e].compacted, "rel_res": st[e].rel_res} for e in range(count)]
 
 
 def cg(g: Graph, values, b, x=None, values32=None, opts: ens_cg_opts | None = None, workspace=None, stream=None):
