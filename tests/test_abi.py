@@ -184,3 +184,25 @@ def test_kl_extrema_argument_errors_without_gpu(E):
     assert L.ens_kl_extrema(0, p, ctypes.byref(pr), 4, p, p, p, None) == E.ENS_E_ARG
     assert L.ens_kl_extrema(8, None, ctypes.byref(pr), 4, p, p, p, None) == E.ENS_E_ARG
     assert L.ens_kl_extrema(8, p, ctypes.byref(pr), 4, p, None, p, None) == E.ENS_E_ARG
+
+
+def test_compaction_workspace_and_refusals_without_gpu(E):
+    L = E.lib()
+    n, nnz = 17 ** 3, 49 ** 3
+    g = E.ens_graph(n, nnz, 256, 512)
+    b = ctypes.c_size_t()
+    sizes = {}
+    for s in (4, 16):
+        for comp in (False, True):
+            o = E.cg_opts(compact=comp)
+            assert L.ens_cg_workspace_bytes(ctypes.byref(g), s, ctypes.byref(o), ctypes.byref(b)) == E.ENS_OK
+            sizes[s, comp] = b.value
+    # the s/2 ensemble: its matrix values and five vectors, and a control block
+    assert sizes[16, True] - sizes[16, False] >= nnz * 8 * 8 + 5 * n * 8 * 8
+    assert sizes[4, True] == sizes[4, False]
+    # compaction is for the FP64 per-sample CG: refused before any launch
+    stats = (E.ens_cg_stat * 16)()
+    p = ctypes.c_void_p(1 << 20)
+    for o in (E.cg_opts(mixed=True, compact=True), E.cg_opts(coupled=True, compact=True)):
+        st = L.ens_cg(ctypes.byref(g), 16, p, p, p, p, ctypes.byref(o), p, 1 << 40, stats, None)
+        assert st in (E.ENS_E_ARG, E.ENS_E_UNSUPPORTED)
