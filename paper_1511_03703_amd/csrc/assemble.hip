@@ -70,6 +70,13 @@ constexpr Q1Tables q1_tables() {
 
 __device__ constexpr Q1Tables kQ1 = q1_tables();
 
+// 1D factors of the Q1 shape functions at the two Gauss points of an axis:
+// kL1[q][b] = l_b(g_q), l_0 = 1 - t, l_1 = t, g_q = (1 -+ 1/sqrt 3)/2 (the
+// same values the tables above are products of).
+__device__ constexpr double kL1[2][2] = {
+    {1.0 - 0.5 * (1.0 - 0.57735026918962576451), 0.5 * (1.0 - 0.57735026918962576451)},
+    {1.0 - 0.5 * (1.0 + 0.57735026918962576451), 0.5 * (1.0 + 0.57735026918962576451)}};
+
 // Sum of the KL modes of sample e at the 8 Gauss points of element
 // (ex, ey, ez): kq[q] = kappa0 + sum_m c_m X(qx) Y(qy) Z(qz).
 __device__ inline void kl_points(const double* __restrict__ tab, const int32_t* __restrict__ kl_triple,
@@ -380,23 +387,56 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
                                                               (int64_t)n1 * (ez + ((b >> 2) & 1)));
           ue[b] = u[node * S + e];
         }
-        double uq[8];
+        // u_h at the Gauss points and the reaction row
+        // rn_b = sum_q u_q N_a(q) N_b(q) by sum factorisation: N_b(q) is the
+        // product over the axes of the 1D factors l(q_d, b_d), so each is
+        // three contractions of 2 along one axis
+        double uq[8], rnv[8];
+        {
+          double t1[8], t2[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          double t = 0.0;
+          for (int i = 0; i < 8; ++i) {  // i = qx + 2 by + 4 bz
+            const int qx = i & 1, r = i & 6;
+            t1[i] = kL1[qx][0] * ue[r] + kL1[qx][1] * ue[r + 1];
+          }
 #pragma unroll
-          for (int b = 0; b < 8; ++b) t += kQ1.N[q][b] * ue[b];
-          uq[q] = t;
-          la += wr * fsrc * kQ1.N[q][ai];
+          for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 bz
+            const int qy = (i >> 1) & 1, r = i & 5;
+            t2[i] = kL1[qy][0] * t1[r] + kL1[qy][1] * t1[r + 2];
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 qz
+            const int qz = i >> 2, r = i & 3;
+            uq[i] = kL1[qz][0] * t2[r] + kL1[qz][1] * t2[r + 4];
+          }
+          double w[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            w[q] = uq[q] * kQ1.N[q][ai];
+            la += wr * fsrc * kQ1.N[q][ai];
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 bz
+            const int bz = i >> 2, r = i & 3;
+            t1[i] = kL1[0][bz] * w[r] + kL1[1][bz] * w[r + 4];
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {  // i = qx + 2 by + 4 bz
+            const int by = (i >> 1) & 1, r = i & 5;
+            t2[i] = kL1[0][by] * t1[r] + kL1[1][by] * t1[r + 2];
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {  // i = bx + 2 by + 4 bz
+            const int bx = i & 1, r = i & 6;
+            rnv[i] = kL1[0][bx] * t2[r] + kL1[1][bx] * t2[r + 1];
+          }
         }
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-          double dg = 0.0, rn = 0.0;
+          double dg = 0.0;
+          const double rn = rnv[b];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            dg += kq[q] * kQ1.G[q][ai][b];
-            rn += uq[q] * kQ1.NN[q][ai][b];
-          }
+          for (int q = 0; q < 8; ++q) dg += kq[q] * kQ1.G[q][ai][b];
           const double lin = wd * dg + wa * s_adv[ai][b];
           fa += (lin + wb * rn) * ue[b];
           if (JAC) {
