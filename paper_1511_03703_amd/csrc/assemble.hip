@@ -128,16 +128,16 @@ __device__ inline void tile_decode(int N, int64_t bid, int64_t* tile_id, int* sg
   *y = (int)(tile / ntz);
 }
 
-// Tiled form of the same assembly: a workgroup owns a TX x TZ patch of
-// nodes in one y-plane for SB of the samples.  It first evaluates the
-// coefficient (times h/8) at the 8 Gauss points of each of the
-// (TX+1) x 2 x (TZ+1) elements touching the patch, once per element and
-// sample, into LDS; then each (row, sample) lane gathers its (up to 8)
-// elements from LDS in ascending element id and adds the element rows
-// exactly as k_assemble does, so the result is bitwise the same while the
-// coefficient is evaluated about a third as often.  LDS rows are padded to
-// SB+1 samples so that neighbouring rows of a wavefront read alternate bank
-// halves.
+// Ensemble assembly (Alg. "assembly" made atomic-free by row ownership): a
+// workgroup owns a TX x TZ patch of nodes in one y-plane for SB of the
+// samples.  It first evaluates the coefficient (times h/8) at the 8 Gauss
+// points of each of the (TX+1) x 2 x (TZ+1) elements touching the patch,
+// once per element and sample, into LDS; then each (row, sample) lane
+// gathers its (up to 8) elements from LDS in ascending element id and adds
+// the element rows in that fixed order, so the sums are deterministic and
+// the coefficient is evaluated about a third as often as by a lane per row
+// alone.  LDS rows are padded to SB+1 samples so that neighbouring rows of
+// a wavefront read alternate bank halves.
 // BND (fused multigrid set-up of this level): 0 none; 1 D^-1 in FP32 and
 // the Gershgorin bound of the FP32 values; 2 D^-1 and the bound of the FP64
 // values.  Each lane forms its row's sum_j |a_ij| / a_ii in ascending entry
@@ -287,7 +287,8 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
 
 // Residual and Jacobian of the nonlinear problem (Sec. 4, Eq.
 // diffusion_sys, Eq. fenl_lin_sys, Alg. "assembly" with alpha, beta != 0),
-// row-owned like k_assemble: lane e of a row's group gathers the element
+// row-owned like k_assemble_tile (same tiling, the coefficient kept in LDS
+// per patch element): lane e of a row's group gathers the element
 // solution u_e of its sample for each element around the node (ascending
 // element id) and forms the element's Jacobian row a
 //   J_ab = D_ab + alpha (h^2/8) C_ab + 2 beta (h^3/8) sum_q u_q N_a N_b,

@@ -479,7 +479,7 @@ static __global__ __launch_bounds__(kBlock) void k_gm_axpy_dots(int64_t nchunks,
 }
 
 // vout = w * scale (exact zeros for idle samples); then the input of the
-// preconditioner: Jacobi z = D^-1 vout, FP32 cycle z32 = (float) vout.
+// preconditioner: Jacobi z = D^-1 vout, FP32 cycle r32 = (float) vout.
 template <int S, int PR>
 static __global__ __launch_bounds__(kBlock) void k_gm_scale(int64_t nchunks, const double* __restrict__ w,
                                                             const GmCtl* __restrict__ c, double* __restrict__ vout,
