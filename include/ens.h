@@ -243,7 +243,10 @@ typedef struct {
                              gathered), finish there, and x and the stats are
                              scattered back.  Each sample's iterates are
                              those of the uncompacted solve up to rounding;
-                             the workspace grows by the s/2 ensemble. */
+                             the workspace grows by the s/2 ensemble.
+                             Only ens_cg compacts: ens_cg_mg, ens_scalar_cg
+                             and ens_scalar_cg_concurrent return ENS_E_ARG
+                             for compact = 1. */
 } ens_cg_opts;
 
 typedef struct {
@@ -419,7 +422,7 @@ ens_status ens_mg_assemble_setup_adv(const ens_mg* mg, const ens_graph* graph, c
  * at the same address would otherwise pass as built. */
 ens_status ens_mg_release(const ens_mg* mg);
 /* CG with z = M r from the hierarchy, per-sample scalars and masks and the
- * stopping rule of ens_cg (opts->coupled must be 0).  opts->mixed = 0: FP64
+ * stopping rule of ens_cg (opts->coupled and opts->compact must be 0).  opts->mixed = 0: FP64
  * CG with an FP64 cycle.  opts->mixed = 1: the FP32-in-FP64 refinement of
  * ens_cg whose FP32 inner CG (on values32) is preconditioned by an FP32
  * cycle.  Workspace from ens_cg_workspace_bytes(graph, s, opts).
@@ -562,6 +565,18 @@ ens_status ens_mlp_grad(const float* params, int32_t batch, const float* xi, con
 ens_status ens_mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const float* xi,
                          const float* target, int32_t count, int32_t batch, int32_t steps, const int32_t* batch_idx,
                          float lr, float* loss, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1; the optimiser of
+ * ens_mlp_train, which runs this same kernel after each gradient) on `count`
+ * FP32 elements (device): with b1 = 0.9, b2 = 0.999, eps = 1e-8 and t = step
+ * (1-based, the bias correction),
+ *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ *   params -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * params, adam_m, adam_v updated in place, grad read; none may alias another.
+ * ENS_E_ARG for null pointers, count outside [0, INT32_MAX], step < 1 or
+ * lr <= 0.  Stream-ordered, no synchronisation. */
+ens_status ens_mlp_adam(float* params, const float* grad, float* adam_m, float* adam_v, int64_t count, int32_t step,
+                        float lr, hipStream_t stream);
 
 /* POD by the method of snapshots, FP64.  S [n][m] (device) holds one
  * solution per column.

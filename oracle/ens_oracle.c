@@ -1495,10 +1495,16 @@ int orc_ens_gmres(int N, const int32_t *rp, const int32_t *ci, int s, const doub
 /* at least 0.5 rtol ref / |F_k| (no solve tighter than the Newton test      */
 /* needs).                                                                   */
 /* Statuses: converged; max steps; breakdown (the linear solve broke down);  */
-/* non-finite.  fnorm (nullable, max_newton + 1 entries) receives ||F(u_k)||. */
+/* non-finite.  fnorm (nullable, max_newton + 1 entries) receives ||F(u_k)||; */
+/* eta (nullable, max_newton + 1 entries) the tolerance of each Newton       */
+/* system solved (0 where no system was solved).                             */
 /* ------------------------------------------------------------------------ */
 
-static double ew_forcing(int k, double eta_prev, double fn, double fprev, double lin_rtol, double floor_tol) {
+/* The forcing term of Newton step k >= 0 (exported for its pins):
+ * k = 0 gives lin_rtol (= eta_max); later steps the Eisenstat-Walker
+ * choice 2 value from |F_k| = fn, |F_{k-1}| = fprev and eta_{k-1} =
+ * eta_prev, with the safeguard, the cap and the floor floor_tol. */
+double orc_ew_forcing(int k, double eta_prev, double fn, double fprev, double lin_rtol, double floor_tol) {
   if (k == 0) return lin_rtol;
   const double gamma = 0.9;
   double eta = gamma * (fn / fprev) * (fn / fprev);
@@ -1512,7 +1518,7 @@ static double ew_forcing(int k, double eta_prev, double fn, double fprev, double
 int orc_newton(int N, int M, double L, double kappa0, double sigma, double fconst, double alpha, const double *vel,
                double beta, const double *xi, double *u, int prec, double rtol, int max_newton, double lin_rtol,
                int restart, int lin_max_iter, int forcing, int32_t *newton_iters, int32_t *lin_iters,
-               double *rel_res, int32_t *status, double *fnorm) {
+               double *rel_res, int32_t *status, double *fnorm, double *etas) {
   const int64_t n = orc_num_nodes(N), nnz = orc_graph_nnz(N), ne = orc_num_elems(N);
   int32_t *rp = malloc(sizeof(int32_t) * (size_t)(n + 1)), *ci = malloc(sizeof(int32_t) * (size_t)nnz);
   double *ac = malloc(sizeof(double) * 8 * (size_t)ne), *vals = malloc(sizeof(double) * (size_t)nnz);
@@ -1542,6 +1548,7 @@ int orc_newton(int N, int M, double L, double kappa0, double sigma, double fcons
       if (ref == 0.0) ref = fn;
     }
     if (fnorm) fnorm[k] = fn;
+    if (etas) etas[k] = 0.0;
     if (!isfinite(fn)) { st = ORC_NONFINITE; break; }
     if (fn <= rtol * ref) { st = ORC_CONVERGED; break; }
     if (k == max_newton) { st = ORC_MAXITER; break; }
@@ -1554,7 +1561,8 @@ int orc_newton(int N, int M, double L, double kappa0, double sigma, double fcons
       }
       P.dinv = dinv;
     }
-    if (forcing == 1) eta = ew_forcing(k, eta, fn, fprev, lin_rtol, 0.5 * rtol * ref / fn);
+    if (forcing == 1) eta = orc_ew_forcing(k, eta, fn, fprev, lin_rtol, 0.5 * rtol * ref / fn);
+    if (etas) etas[k] = forcing == 1 ? eta : lin_rtol;
     fprev = fn;
     for (int64_t i = 0; i < n; ++i) d[i] = 0.0;
     int32_t it = 0, ls = 0;
@@ -1576,11 +1584,12 @@ int orc_newton(int N, int M, double L, double kappa0, double sigma, double fcons
 }
 
 /* Newton for every sample (u [n][s] in/out, one sample per thread); fnorm
- * [s][max_newton + 1] nullable. */
+ * and etas [s][max_newton + 1] nullable. */
 int orc_ens_newton(int N, int M, double L, double kappa0, double sigma, double fconst, double alpha,
                    const double *vel, double beta, int s, const double *xi, double *u, int prec, double rtol,
                    int max_newton, double lin_rtol, int restart, int lin_max_iter, int forcing,
-                   int32_t *newton_iters, int32_t *lin_iters, double *rel_res, int32_t *status, double *fnorm) {
+                   int32_t *newton_iters, int32_t *lin_iters, double *rel_res, int32_t *status, double *fnorm,
+                   double *etas) {
   const int64_t n = orc_num_nodes(N);
   int rc = ORC_OK;
   #pragma omp parallel for schedule(dynamic, 1)
@@ -1590,7 +1599,8 @@ int orc_ens_newton(int N, int M, double L, double kappa0, double sigma, double f
     for (int64_t i = 0; i < n; ++i) ue[i] = u[i * s + e];
     int r = orc_newton(N, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi + (int64_t)e * M, ue, prec, rtol,
                        max_newton, lin_rtol, restart, lin_max_iter, forcing, &newton_iters[e], &lin_iters[e],
-                       &rel_res[e], &status[e], fnorm ? fnorm + (int64_t)e * (max_newton + 1) : NULL);
+                       &rel_res[e], &status[e], fnorm ? fnorm + (int64_t)e * (max_newton + 1) : NULL,
+                       etas ? etas + (int64_t)e * (max_newton + 1) : NULL);
     if (r) rc = r;
     for (int64_t i = 0; i < n; ++i) u[i * s + e] = ue[i];
     free(ue);

@@ -15,6 +15,9 @@ its matrix products: inputs, weights, the two hidden activations, and the
 back-propagated dY, dZ2, dZ1.  With bf16=False it is the plain FP64
 network (used for finite-difference pins).
 
+`adam_step` is one step of Adam (Kingma and Ba, "Adam: a method for
+stochastic optimization", ICLR 2015, Algorithm 1) in FP64.
+
 POD by the method of snapshots: G = S^T S, eigenpairs of G (numpy eigh, a
 library routine), Phi = S V diag(lambda)^(-1/2), largest-magnitude entry of
 each column positive.
@@ -107,6 +110,22 @@ def init_params(seed):
         b = 1.0 / math.sqrt(fan_in)
         d[name] = rng.uniform(-b, b, size=shape)
     return pack(d)
+
+
+# ------------------------------------------------------------------ Adam
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """Step t (1-based) of Adam on parameters p with gradient g and moments
+    m, v (all FP64); returns the new (p, m, v).  The moments are exponential
+    moving averages of g and g^2, divided by 1 - b^t to remove their bias
+    towards the zero start; the step is lr * mhat / (sqrt(vhat) + eps)."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
 # ------------------------------------------------------------------ POD

@@ -95,10 +95,13 @@ def lib():
         L.orc_ens_gmres.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int, dbl,
                                     dbl, dbl, vp, dbl, vp, dbl, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
         L.orc_newton.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl, vp, vp, ctypes.c_int,
-                                 dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+                                 dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp,
+                                 vp]
         L.orc_ens_newton.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, dbl, ctypes.c_int, vp,
                                      vp, ctypes.c_int, dbl, ctypes.c_int, dbl, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_int, vp, vp, vp, vp, vp]
+                                     ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.orc_ew_forcing.restype = dbl
+        L.orc_ew_forcing.argtypes = [ctypes.c_int, dbl, dbl, dbl, dbl, dbl]
         _lib = L
     return _lib
 
@@ -452,11 +455,19 @@ def ens_gmres(N, rp, ci, values, b, x0=None, prec=PREC_JACOBI, M=0, L=1.0, kappa
 FORCING_FIXED, FORCING_EW = 0, 1
 
 
+def ew_forcing(k, eta_prev, fn, fprev, lin_rtol, floor_tol):
+    """The oracle's forcing term of Newton step k (Eisenstat-Walker choice 2
+    with its safeguard, capped at lin_rtol, at least floor_tol)."""
+    return lib().orc_ew_forcing(int(k), float(eta_prev), float(fn), float(fprev), float(lin_rtol), float(floor_tol))
+
+
 def ens_newton(N, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi, u0=None, prec=PREC_MG, rtol=1e-8,
-               max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000, forcing=FORCING_FIXED):
+               max_newton=20, lin_rtol=1e-4, restart=30, lin_max_iter=1000, forcing=FORCING_FIXED, want_eta=False):
     """Newton per sample (forcing: fixed lin_rtol, or Eisenstat-Walker with
     eta_0 = eta_max = lin_rtol).  Returns (u [n][s], newton_iters,
-    lin_iters, rel_res, status, fnorm [s][max_newton + 1])."""
+    lin_iters, rel_res, status, fnorm [s][max_newton + 1]), and with
+    want_eta the tolerance of every Newton system solved, eta [s][max_newton
+    + 1] (0 past the last system), as a seventh item."""
     xi = _f64(xi)
     s = xi.shape[0]
     n = num_nodes(N)
@@ -466,7 +477,10 @@ def ens_newton(N, M, L, kappa0, sigma, fconst, alpha, vel, beta, xi, u0=None, pr
     rr = np.zeros(s)
     st = np.zeros(s, np.int32)
     fn = np.zeros((s, max_newton + 1))
+    eta = np.zeros((s, max_newton + 1))
     _check(lib().orc_ens_newton(N, M, L, kappa0, sigma, fconst, alpha, _p(_f64(vel)), beta, s, _p(xi), _p(u), prec,
                                 rtol, max_newton, lin_rtol, restart, lin_max_iter, int(forcing), _p(ni), _p(li),
-                                _p(rr), _p(st), _p(fn)))
+                                _p(rr), _p(st), _p(fn), _p(eta)))
+    if want_eta:
+        return u, ni, li, rr, st, fn, eta
     return u, ni, li, rr, st, fn

@@ -927,6 +927,7 @@ ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, co
   ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
   ENS_ARG_CHECK(opts->rtol >= 0.0, "rtol must be >= 0");
   ENS_ARG_CHECK(!opts->coupled, "the multigrid solve uses per-sample scalars");
+  ENS_ARG_CHECK(!opts->compact, "the multigrid solve does not compact (compact must be 0)");
   ENS_ARG_CHECK((opts->mixed != 0) == (mg->fp32 != 0), "mixed mode needs an FP32 cycle, FP64 CG an FP64 one");
   ENS_ARG_CHECK(!opts->mixed || (values32 && aligned16(values32)), "mixed mode needs values32");
   ENS_ARG_CHECK(mg->s == s, "hierarchy built for another ensemble size");
@@ -998,6 +999,7 @@ ens_status ens_scalar_cg_concurrent(const ens_graph* graph, int32_t s, const dou
   ENS_ARG_CHECK(opts && stats && s >= 1, "bad arguments");
   ENS_ARG_CHECK(streams >= 1 && streams <= kMaxSideStreams, "streams must be in 1..32");
   ENS_ARG_CHECK(!opts->mixed && !opts->coupled, "the scalar baseline is per-sample FP64");
+  ENS_ARG_CHECK(!opts->compact, "the scalar baseline does not compact (compact must be 0)");
   ENS_ARG_CHECK(values && b && x && workspace, "null device pointer");
   ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
   if (graph->n == 0) {
@@ -1028,6 +1030,7 @@ ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values
   ENS_ARG_CHECK(opts && stats && s >= 1, "bad arguments");
   ENS_ARG_CHECK(!opts->mixed, "the scalar baseline is FP64 only");
   ENS_ARG_CHECK(!opts->coupled, "the scalar baseline solves samples independently (coupled must be 0)");
+  ENS_ARG_CHECK(!opts->compact, "the scalar baseline does not compact (compact must be 0)");
   ENS_ARG_CHECK(values && b && x && workspace, "null device pointer");
   ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
   const size_t need = ws_layout(graph->n, 1, false, nullptr, nullptr);

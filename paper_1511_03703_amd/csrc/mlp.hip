@@ -203,6 +203,9 @@ __global__ __launch_bounds__(256) void k_colsum(int M, int N, const float* __res
   if (g == 0 && col < N) out[col] = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
 }
 
+// One Adam step (Kingma and Ba 2015, Algorithm 1) per element, FP32:
+// moving averages of g and g^2, divided by the bias corrections c1 = 1 - b1^t
+// and c2 = 1 - b2^t, eps added to the square root of the second moment.
 __global__ void k_adam(int64_t P, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,6 +216,20 @@ __global__ void k_adam(int64_t P, float* __restrict__ p, const float* __restrict
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Adam with beta = (0.9, 0.999), eps = 1e-8 at step t (1-based) over P
+// elements; the bias corrections are formed in FP64 from the FP32 betas.
+static void adam_launch(int64_t P, float* p, const float* g, float* m, float* v, int t, float lr,
+                        hipStream_t stream) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  double p1 = 1.0, p2 = 1.0;
+  for (int k = 0; k < t; ++k) {
+    p1 *= b1;
+    p2 *= b2;
+  }
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, P, p, g, m, v, lr, b1, b2,
+                     eps, (float)(1.0 - p1), (float)(1.0 - p2));
 }
 
 // ------------------------------------------------------------ host side ---
@@ -397,25 +414,28 @@ ens_status ens_mlp_train(float* params, float* adam_m, float* adam_v, int32_t st
   }
   MlpWork w;
   mlp_layout(batch, &w, (char*)workspace);
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  double p1 = 1.0, p2 = 1.0;
-  for (int t = 0; t < step0; ++t) {
-    p1 *= b1;
-    p2 *= b2;
-  }
   weights_bf16(params, w, stream);
   for (int s = 0; s < steps; ++s) {
     load_batch(batch, xi, target, batch_idx + (int64_t)s * batch, w, stream);
     forward(params, batch, w, stream);
     backward(batch, w, stream);
     if (loss) ENS_HIP_TRY(hipMemcpyAsync(loss + s, w.loss, sizeof(float), hipMemcpyDeviceToDevice, stream));
-    p1 *= b1;
-    p2 *= b2;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((kParams + 255) / 256)), dim3(256), 0, stream, (int64_t)kParams,
-                       params, w.grad, adam_m, adam_v, lr, b1, b2, eps, (float)(1.0 - p1), (float)(1.0 - p2));
+    adam_launch(kParams, params, w.grad, adam_m, adam_v, step0 + s + 1, lr, stream);
     weights_bf16(params, w, stream);
     ENS_LAUNCH_CHECK();
   }
+  return ENS_OK;
+}
+
+ens_status ens_mlp_adam(float* params, const float* grad, float* adam_m, float* adam_v, int64_t count, int32_t step,
+                        float lr, hipStream_t stream) {
+  ENS_ARG_CHECK(params && grad && adam_m && adam_v, "null pointer");
+  ENS_ARG_CHECK(count >= 0 && step >= 1, "count must be >= 0 and step >= 1");
+  ENS_ARG_CHECK(lr > 0.0f, "learning rate must be positive");
+  ENS_ARG_CHECK(count <= INT32_MAX, "count must fit in int32");
+  if (count == 0) return ENS_OK;
+  adam_launch(count, params, grad, adam_m, adam_v, step, lr, stream);
+  ENS_LAUNCH_CHECK();
   return ENS_OK;
 }
 

@@ -149,6 +149,7 @@ _SIGS = [
     ("ens_mlp_forward", _I32, [_P, _I32, _P, _P, _P, _SZ, _P]),
     ("ens_mlp_grad", _I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     ("ens_mlp_train", _I32, [_P, _P, _P, _I32, _P, _P, _I32, _I32, _I32, _P, ctypes.c_float, _P, _P, _SZ, _P]),
+    ("ens_mlp_adam", _I32, [_P, _P, _P, _P, ctypes.c_int64, _I32, ctypes.c_float, _P]),
     ("ens_pod_collect", _I32, [_P, _I64, _I32, _P, _I32, _I32, _P]),
     ("ens_pod_gram_workspace_bytes", _I32, [_I64, _I32, ctypes.POINTER(_SZ)]),
     ("ens_pod_gram", _I32, [_P, _I64, _I32, _P, _P, _SZ, _P]),
@@ -690,6 +691,12 @@ def mlp_train(params, adam_m, adam_v, step0, xi, target, batch, batch_idx, lr, l
                                xi.shape[0], batch, steps, _ptr(batch_idx), lr, _ptr(loss), _ptr(ws), ws.numel(),
                                _stream(stream)), "ens_mlp_train")
     return steps
+
+
+def mlp_adam(params, grad, adam_m, adam_v, step, lr, stream=None):
+    """One Adam step (step = t, 1-based) on FP32 device arrays, in place."""
+    _check(lib().ens_mlp_adam(_ptr(params), _ptr(grad), _ptr(adam_m), _ptr(adam_v), params.numel(), step, lr,
+                              _stream(stream)), "ens_mlp_adam")
 
 
 def pod_collect(x, S, col0, stream=None):

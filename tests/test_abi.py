@@ -206,3 +206,26 @@ def test_compaction_workspace_and_refusals_without_gpu(E):
     for o in (E.cg_opts(mixed=True, compact=True), E.cg_opts(coupled=True, compact=True)):
         st = L.ens_cg(ctypes.byref(g), 16, p, p, p, p, ctypes.byref(o), p, 1 << 40, stats, None)
         assert st in (E.ENS_E_ARG, E.ENS_E_UNSUPPORTED)
+    # only ens_cg compacts: the multigrid and one-sample solves refuse the
+    # option instead of ignoring it, before any launch
+    o = E.cg_opts(compact=True)
+    desc = E.ens_mg(16, 10, 16, 0, ctypes.c_void_p(1 << 20), 1 << 30)
+    st = L.ens_cg_mg(ctypes.byref(g), 16, p, None, p, p, ctypes.byref(o), ctypes.byref(desc), p, 1 << 40, stats,
+                     None)
+    assert st == E.ENS_E_ARG and b"compact" in L.ens_last_error()
+    st = L.ens_scalar_cg(ctypes.byref(g), 16, p, p, p, ctypes.byref(o), 16, p, 1 << 40, stats, None)
+    assert st == E.ENS_E_ARG and b"compact" in L.ens_last_error()
+    st = L.ens_scalar_cg_concurrent(ctypes.byref(g), 16, p, p, p, ctypes.byref(o), 16, 8, p, 1 << 40, stats, None)
+    assert st == E.ENS_E_ARG and b"compact" in L.ens_last_error()
+
+
+def test_adam_argument_errors_without_gpu(E):
+    L = E.lib()
+    p = ctypes.c_void_p(256)
+    assert L.ens_mlp_adam(None, p, p, p, 10, 1, ctypes.c_float(1e-3), None) == E.ENS_E_ARG
+    assert L.ens_mlp_adam(p, p, p, p, 10, 0, ctypes.c_float(1e-3), None) == E.ENS_E_ARG
+    assert L.ens_mlp_adam(p, p, p, p, -1, 1, ctypes.c_float(1e-3), None) == E.ENS_E_ARG
+    assert L.ens_mlp_adam(p, p, p, p, 1 << 40, 1, ctypes.c_float(1e-3), None) == E.ENS_E_ARG
+    assert L.ens_mlp_adam(p, p, p, p, 10, 1, ctypes.c_float(0.0), None) == E.ENS_E_ARG
+    # nothing to do: no launch
+    assert L.ens_mlp_adam(p, p, p, p, 0, 1, ctypes.c_float(1e-3), None) == E.ENS_OK

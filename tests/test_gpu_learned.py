@@ -83,6 +83,72 @@ def test_mlp_training_reduces_loss_deterministically(E):
     assert abs(np.mean((y - T[:B]) ** 2) - lo) <= 1e-2 * lo
 
 
+def _adam_ok(p, m, v, po, mo, vo, lr, t):
+    # FP32 state against the FP64 reference started from the same FP32 values:
+    # moments to a few FP32 roundings per step; the parameter step
+    # lr mhat / (sqrt(vhat) + eps) is at most ~lr per coordinate and its FP32
+    # error a few ulp of that, plus the rounding of p itself each step
+    np.testing.assert_allclose(m, mo, rtol=2e-6 * t, atol=1e-30)
+    np.testing.assert_allclose(v, vo, rtol=2e-6 * t, atol=1e-30)
+    err = np.abs(p - po)
+    bound = 1e-7 * t * np.abs(po) + 1e-6 * lr * t
+    assert (err <= bound).all(), float((err / bound).max())
+
+
+@pytest.mark.parametrize("count", [L.P, 1000, 1])
+def test_adam_step_matches_fp64_reference_on_fixed_gradients(E, count):
+    # ens_mlp_adam (the kernel ens_mlp_train runs) against Algorithm 1 of
+    # Kingma and Ba in FP64, on a seeded gradient sequence that mixes
+    # magnitudes from 1e-8 (where eps matters) to 1e2, zeros and sign flips
+    rng = np.random.default_rng(41 + count)
+    lr = 1e-3
+    p = rng.uniform(-1, 1, count).astype(np.float32)
+    pt = _f32(p)
+    mt = torch.zeros_like(pt)
+    vt = torch.zeros_like(pt)
+    po, mo, vo = p.astype(np.float64), np.zeros(count), np.zeros(count)
+    for t in range(1, 11):
+        scale = 10.0 ** rng.integers(-8, 3, count)
+        g = (rng.standard_normal(count) * scale).astype(np.float32)
+        g[rng.random(count) < 0.05] = 0.0
+        E.mlp_adam(pt, _f32(g), mt, vt, t, lr)
+        po, mo, vo = L.adam_step(po, g.astype(np.float64), mo, vo, t, lr)
+        if t in (1, 10):
+            torch.cuda.synchronize()
+            _adam_ok(pt.cpu().numpy(), mt.cpu().numpy(), vt.cpu().numpy(), po, mo, vo, lr, t)
+
+
+@pytest.mark.parametrize("step0,steps", [(0, 1), (5, 1), (0, 10)])
+def test_mlp_train_is_gradient_then_adam(E, step0, steps):
+    # each step of ens_mlp_train = the network gradient of its mini-batch
+    # (ens_mlp_grad, checked against the reference above) followed by the
+    # FP64 Adam step of the reference at t = step0 + k + 1, from the same FP32
+    # state; moments start from a state as after step0 steps.  A run of
+    # `steps` in one call equals the same steps taken one call at a time.
+    rng = np.random.default_rng(7 + step0 + steps)
+    N, B, lr = 256, 64, 2e-3
+    X = rng.uniform(-1, 1, (N, L.IN)).astype(np.float32)
+    T = rng.standard_normal((N, L.OUT)).astype(np.float32)
+    p0 = L.init_params(17).astype(np.float32)
+    m0 = (1e-3 * rng.standard_normal(L.P) * (step0 > 0)).astype(np.float32)
+    v0 = (1e-6 * rng.random(L.P) * (step0 > 0)).astype(np.float32)
+    idx = rng.integers(0, N, steps * B).astype(np.int32)
+    Xt, Tt = _f32(X), _f32(T)
+    pa, ma, va = _f32(p0), _f32(m0), _f32(v0)
+    E.mlp_train(pa, ma, va, step0, Xt, Tt, B, torch.as_tensor(idx, device=DEV), lr)
+    p, m, v = _f32(p0), _f32(m0), _f32(v0)
+    for k in range(steps):
+        rows = idx[k * B:(k + 1) * B]
+        _, g, _ = E.mlp_grad(p, _f32(X[rows]), _f32(T[rows]))
+        po, mo, vo = L.adam_step(p.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64),
+                                 m.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64),
+                                 step0 + k + 1, lr)
+        E.mlp_train(p, m, v, step0 + k, Xt, Tt, B, torch.as_tensor(rows, device=DEV), lr)
+        torch.cuda.synchronize()
+        _adam_ok(p.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy(), po, mo, vo, lr, 1)
+    assert torch.equal(p, pa) and torch.equal(m, ma) and torch.equal(v, va)
+
+
 def test_pod_kernels_match_reference(E):
     rng = np.random.default_rng(6)
     n, m, r, k = 20000, 96, 16, 48

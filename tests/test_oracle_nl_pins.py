@@ -364,3 +364,54 @@ def test_advection_cycle_saves_krylov_steps_where_advection_matters(orc):
     assert (st1 == orc.CONVERGED).all() and (st2 == orc.CONVERGED).all()
     assert np.abs(u1 - u2).max() <= 1e-8 * np.abs(u1).max()
     assert li2.sum() <= 0.6 * li1.sum()
+
+
+def _golden_rows(name):
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(t) for t in line.split()])
+    return rows
+
+
+def test_forcing_term_matches_the_hand_worked_values(orc):
+    # tests/golden/ew_forcing.txt: each branch of Eisenstat-Walker choice 2
+    # (plain ratio, safeguard used and unused, cap, floor, k = 0) worked by
+    # hand from the published definition
+    rows = _golden_rows("ew_forcing.txt")
+    assert len(rows) >= 10
+    for k, eta_prev, fn, fprev, eta_max, floor, want in rows:
+        got = orc.ew_forcing(int(k), eta_prev, fn, fprev, eta_max, floor)
+        assert got == pytest.approx(want, rel=1e-14, abs=0.0), (k, eta_prev, fn, fprev, eta_max, floor)
+
+
+def test_newton_solves_each_system_to_its_forcing_term(orc):
+    # the Newton loop feeds the pinned forcing function the right inputs:
+    # eta_0 = eta_max, then |F_k|, |F_{k-1}|, eta_{k-1} and the floor
+    # 0.5 rtol |load| / |F_k| (|load| = |F(u_0)| from u_0 = 0: boundary rows
+    # are u_i = 0 there and interior rows are minus the load)
+    N, M, s, rtol, eta_max = 6, 5, 3, 1e-11, 0.5
+    xi = draw_xi(3075, s, M)
+    _, ni, _, _, st, fn, eta = orc.ens_newton(N, M, 1.0, 1.0, 0.3, 1.0, 10.0, VEL, 100.0, xi, rtol=rtol,
+                                              lin_rtol=eta_max, forcing=orc.FORCING_EW, want_eta=True)
+    assert (st == orc.CONVERGED).all()
+    seen_below_cap = False
+    for e in range(s):
+        k_last = int(ni[e])
+        assert k_last >= 3
+        assert eta[e, 0] == eta_max
+        for k in range(1, k_last):
+            want = orc.ew_forcing(k, eta[e, k - 1], fn[e, k], fn[e, k - 1], eta_max, 0.5 * rtol * fn[e, 0] / fn[e, k])
+            assert eta[e, k] == want, (e, k)
+            seen_below_cap |= eta[e, k] < eta_max
+        # no system is solved at the converged iterate
+        assert (eta[e, k_last:] == 0.0).all()
+    assert seen_below_cap
+    # fixed forcing solves every system to lin_rtol
+    _, ni2, _, _, _, _, eta2 = orc.ens_newton(N, M, 1.0, 1.0, 0.3, 1.0, 10.0, VEL, 100.0, xi, rtol=rtol,
+                                              lin_rtol=1e-3, want_eta=True)
+    for e in range(s):
+        assert (eta2[e, :ni2[e]] == 1e-3).all()
