@@ -966,8 +966,80 @@ static void lu_solve(int64_t m, const double *F, const double *b, double *x) {
   }
 }
 
+/* Galerkin coarse operator of Alg. vcycle: A^{k+1} = R^k A^k P^k with
+ * R = P^T, P the trilinear interpolation of orc_mg_prolong_add (interior
+ * coarse nodes onto interior fine nodes).  Written out by its definition,
+ *   (P^T A P)_{IJ} = sum over fine i, j of P_{iI} A_{ij} P_{jJ},
+ * one coarse row I at a time: for every interior fine child i of I (the
+ * fine nodes whose interpolation uses I), every stored entry A_ij of fine
+ * row i with j interior, and every interior coarse parent J of j, the term
+ * P_{iI} A_{ij} P_{jJ} is added to entry (I, J).  Boundary coarse rows are
+ * identity rows and boundary columns of interior rows stored zeros (the
+ * Dirichlet treatment of the assembled levels; P has no boundary columns, so
+ * P^T A P has no boundary entries).  Af: the fine level (Nf = 2 Nc elements
+ * per axis) in the layout of orc_graph; vc: the coarse level's values on
+ * orc_graph(Nc).  Returns ORC_E_ARG if a term falls outside the coarse
+ * 27-point pattern (it cannot for nested Q1 meshes). */
+int orc_mg_galerkin(int Nc, const int32_t *rpf, const int32_t *cif, const double *vf, const int32_t *rpc,
+                    const int32_t *cic, double *vc) {
+  const int Nf = 2 * Nc;
+  const int64_t nc = orc_num_nodes(Nc);
+  for (int64_t q = 0; q < rpc[nc]; ++q) vc[q] = 0.0;
+  for (int K = 0; K <= Nc; ++K)
+    for (int J = 0; J <= Nc; ++J)
+      for (int I = 0; I <= Nc; ++I) {
+        const int64_t row = node_id(Nc, I, J, K);
+        if (is_boundary_node(Nc, row)) {
+          for (int64_t q = rpc[row]; q < rpc[row + 1]; ++q)
+            if (cic[q] == row) vc[q] = 1.0;
+          continue;
+        }
+        /* children of (I,J,K): fine nodes 2I-1..2I+1 per axis */
+        for (int ck = 2 * K - 1; ck <= 2 * K + 1; ++ck)
+          for (int cj = 2 * J - 1; cj <= 2 * J + 1; ++cj)
+            for (int cii = 2 * I - 1; cii <= 2 * I + 1; ++cii) {
+              const int64_t i = node_id(Nf, cii, cj, ck);
+              if (is_boundary_node(Nf, i)) continue;
+              int Ai[2], Aj[2], Ak[2];
+              double wi[2], wj[2], wk[2];
+              const int na = axis_parents(cii, Ai, wi), nb = axis_parents(cj, Aj, wj);
+              const int nc3 = axis_parents(ck, Ak, wk);
+              double pI = 0.0; /* P_{iI} */
+              for (int c = 0; c < nc3; ++c)
+                for (int b = 0; b < nb; ++b)
+                  for (int a = 0; a < na; ++a)
+                    if (Ai[a] == I && Aj[b] == J && Ak[c] == K) pI = wi[a] * wj[b] * wk[c];
+              for (int64_t q = rpf[i]; q < rpf[i + 1]; ++q) {
+                const int64_t j = cif[q];
+                if (is_boundary_node(Nf, j)) continue;
+                const int fx = (int)(j % (Nf + 1)), fy = (int)((j / (Nf + 1)) % (Nf + 1)),
+                          fz = (int)(j / ((int64_t)(Nf + 1) * (Nf + 1)));
+                int Bi[2], Bj[2], Bk[2];
+                double ui[2], uj[2], uk[2];
+                const int ma = axis_parents(fx, Bi, ui), mb = axis_parents(fy, Bj, uj), mc = axis_parents(fz, Bk, uk);
+                for (int c = 0; c < mc; ++c)
+                  for (int b = 0; b < mb; ++b)
+                    for (int a = 0; a < ma; ++a) {
+                      const int64_t col = node_id(Nc, Bi[a], Bj[b], Bk[c]);
+                      if (is_boundary_node(Nc, col)) continue;
+                      /* an interior row holds the full 3x3x3 block of
+                       * neighbours in ascending node order */
+                      const int dx = Bi[a] - I, dy = Bj[b] - J, dz = Bk[c] - K;
+                      if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return ORC_E_ARG;
+                      const int64_t slot = rpc[row] + (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                      if (rpc[row + 1] - rpc[row] != 27 || cic[slot] != col) return ORC_E_ARG;
+                      vc[slot] += pI * vf[q] * (ui[a] * uj[b] * uk[c]);
+                    }
+              }
+            }
+      }
+  return ORC_OK;
+}
+
 /* Levels for one sample: matrices assembled on every mesh of the hierarchy
- * with the sample's KL coefficient; level 0's load vector into b0 (nullable).
+ * with the sample's KL coefficient (galerkin = 0), or, with galerkin = 1,
+ * the fine matrix assembled and every coarser one the Galerkin product
+ * P^T A P of the level above; level 0's load vector into b0 (nullable).
  * adv = 0: the diffusion matrix (Alg. assembly).  adv = 1: the linear part
  * D + alpha C of the nonlinear Jacobian (Eq. fenl_lin_sys with beta = 0,
  * i.e. the Jacobian at u = 0 of a problem without reaction) rediscretized on
@@ -976,7 +1048,8 @@ static void lu_solve(int64_t m, const double *F, const double *b, double *x) {
  * the boundary and v is constant), so the block's symmetric part is that of
  * the diffusion block and no pivoting is needed. */
 static int build_levels(int N, int M, double L, double kappa0, double sigma, double fconst, const double *xi,
-                        int adv, double alpha, const double *vel, orc_level *lv, int *nlev, double *b0) {
+                        int adv, double alpha, const double *vel, int galerkin, orc_level *lv, int *nlev,
+                        double *b0) {
   int32_t Ns[ORC_MG_MAX_LEVELS];
   const int nl = orc_mg_levels(N, Ns);
   memset(lv, 0, sizeof(orc_level) * (size_t)nl);
@@ -1003,7 +1076,13 @@ static int build_levels(int N, int M, double L, double kappa0, double sigma, dou
     }
     orc_graph(l->N, l->rp, l->ci);
     orc_kl_coef_qp(l->N, M, L, kappa0, sigma, xi, ac);
-    if (adv) {
+    if (galerkin && k > 0) {
+      const orc_level *f = &lv[k - 1];
+      if (orc_mg_galerkin(l->N, f->rp, f->ci, f->v, l->rp, l->ci, l->v) != ORC_OK) {
+        free(ac); free(load);
+        return ORC_E_ARG;
+      }
+    } else if (adv) {
       /* r and x are zero here: x serves as u = 0, r receives F(0) = -load */
       orc_nl_assemble_scalar(l->N, l->rp, l->ci, ac, fconst, alpha, vel, 0.0, l->x, l->r, l->v, load);
       for (int64_t t = 0; t < l->n; ++t) l->r[t] = 0.0;
@@ -1059,10 +1138,10 @@ static void vcycle(orc_level *lv, int k, int nl, const double *b, double *x) {
 
 /* z = M r for one sample's hierarchy (for building M in tests). */
 int orc_mg_apply(int N, int M, double L, double kappa0, double sigma, double fconst, const double *xi,
-                 const double *r, double *z) {
+                 const double *r, double *z, int galerkin) {
   orc_level lv[ORC_MG_MAX_LEVELS];
   int nl = 0;
-  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 0, 0.0, NULL, lv, &nl, NULL);
+  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 0, 0.0, NULL, galerkin, lv, &nl, NULL);
   if (rc == ORC_OK) vcycle(lv, 0, nl, r, z);
   free_levels(lv, nl);
   return rc;
@@ -1075,7 +1154,7 @@ int orc_mg_apply_adv(int N, int M, double L, double kappa0, double sigma, double
   if (!vel) return ORC_E_ARG;
   orc_level lv[ORC_MG_MAX_LEVELS];
   int nl = 0;
-  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 1, alpha, vel, lv, &nl, NULL);
+  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 1, alpha, vel, 0, lv, &nl, NULL);
   if (rc == ORC_OK) vcycle(lv, 0, nl, r, z);
   free_levels(lv, nl);
   return rc;
@@ -1085,7 +1164,7 @@ int orc_mg_apply_adv(int N, int M, double L, double kappa0, double sigma, double
  * the same stopping rule and failure handling as orc_pcg.  x in: x0. */
 int orc_mg_pcg(int N, int M, double L, double kappa0, double sigma, double fconst, const double *xi, double *x,
                double rtol, int max_iter, int fixed_iters, int32_t *iters_out, double *rel_res_out,
-               int32_t *status_out, double *lmax_out) {
+               int32_t *status_out, double *lmax_out, int galerkin) {
   orc_level lv[ORC_MG_MAX_LEVELS];
   int nl = 0;
   const int64_t n = orc_num_nodes(N);
@@ -1093,7 +1172,7 @@ int orc_mg_pcg(int N, int M, double L, double kappa0, double sigma, double fcons
   double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
   double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
   if (!b || !r || !z || !p || !q) return ORC_E_NOMEM;
-  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 0, 0.0, NULL, lv, &nl, b);
+  int rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, 0, 0.0, NULL, galerkin, lv, &nl, b);
   if (rc != ORC_OK) { free_levels(lv, nl); free(b); free(r); free(z); free(p); free(q); return rc; }
   if (lmax_out)
     for (int k = 0; k < nl; ++k) lmax_out[k] = lv[k].lmax;
@@ -1150,7 +1229,7 @@ int orc_mg_pcg(int N, int M, double L, double kappa0, double sigma, double fcons
  * nullable (each level's Chebyshev bound). */
 int orc_ens_mg_pcg(int N, int M, double L, double kappa0, double sigma, double fconst, int s, const double *xi,
                    double *x, double rtol, int max_iter, const int32_t *fixed_iters, int32_t *iters,
-                   double *rel_res, int32_t *status, double *lmax) {
+                   double *rel_res, int32_t *status, double *lmax, int galerkin) {
   const int64_t n = orc_num_nodes(N);
   int rc = ORC_OK;
   #pragma omp parallel for schedule(dynamic, 1)
@@ -1160,7 +1239,7 @@ int orc_ens_mg_pcg(int N, int M, double L, double kappa0, double sigma, double f
     for (int64_t i = 0; i < n; ++i) xe[i] = x[i * s + e];
     int r = orc_mg_pcg(N, M, L, kappa0, sigma, fconst, xi + (int64_t)e * M, xe, rtol, max_iter,
                        fixed_iters ? fixed_iters[e] : -1, &iters[e], &rel_res[e], &status[e],
-                       lmax ? lmax + (int64_t)e * ORC_MG_MAX_LEVELS : NULL);
+                       lmax ? lmax + (int64_t)e * ORC_MG_MAX_LEVELS : NULL, galerkin);
     if (r) rc = r;
     for (int64_t i = 0; i < n; ++i) x[i * s + e] = xe[i];
     free(xe);
@@ -1449,7 +1528,7 @@ int orc_gmres(int N, const int32_t *rp, const int32_t *ci, const double *values,
     }
     P.dinv = dinv;
   } else {
-    rc = build_levels(N, M, L, kappa0, sigma, 1.0, xi, prec == 2, alpha, vel, lv, &P.nl, NULL);
+    rc = build_levels(N, M, L, kappa0, sigma, 1.0, xi, prec == 2, alpha, vel, 0, lv, &P.nl, NULL);
     P.lv = lv;
   }
   if (rc == ORC_OK)
@@ -1534,7 +1613,7 @@ int orc_newton(int N, int M, double L, double kappa0, double sigma, double fcons
     orc_kl_coef_qp(N, M, L, kappa0, sigma, xi, ac);
     P.kind = prec;
     if (prec != 0) {
-      rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, prec == 2, alpha, vel, lv, &P.nl, NULL);
+      rc = build_levels(N, M, L, kappa0, sigma, fconst, xi, prec == 2, alpha, vel, 0, lv, &P.nl, NULL);
       P.lv = lv;
     }
   }

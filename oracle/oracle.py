@@ -70,12 +70,13 @@ def lib():
         L.orc_gershgorin.restype = dbl
         L.orc_gershgorin.argtypes = [i64, vp, vp, vp]
         L.orc_mg_cheb2.argtypes = [i64, vp, vp, vp, dbl, vp, vp, ctypes.c_int, vp, vp, vp]
-        L.orc_mg_apply.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, vp, vp]
+        L.orc_mg_apply.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, vp, vp, ctypes.c_int]
+        L.orc_mg_galerkin.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, vp]
         L.orc_mg_apply_adv.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, dbl, vp, vp, vp, vp]
         L.orc_mg_pcg.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, vp, dbl, ctypes.c_int,
-                                 ctypes.c_int, vp, vp, vp, vp]
+                                 ctypes.c_int, vp, vp, vp, vp, ctypes.c_int]
         L.orc_ens_mg_pcg.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int, vp, vp, dbl,
-                                     ctypes.c_int, vp, vp, vp, vp, vp]
+                                     ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int]
         L.orc_ens_pcg_coupled.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int,
                                           vp, vp, vp]
         L.orc_solve_sample.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, dbl, vp, dbl,
@@ -323,10 +324,21 @@ def mg_cheb2(rp, ci, vals, lmax, b, x0=None):
     return x
 
 
-def mg_apply(N, M, L, kappa0, sigma, fconst, xi, r):
+def mg_apply(N, M, L, kappa0, sigma, fconst, xi, r, galerkin=False):
+    """z = M r, one V-cycle; coarse levels rediscretized, or with galerkin
+    the products P^T A P of the level above."""
     z = np.zeros(num_nodes(N))
-    _check(lib().orc_mg_apply(N, M, L, kappa0, sigma, fconst, _p(_f64(xi)), _p(_f64(r)), _p(z)))
+    _check(lib().orc_mg_apply(N, M, L, kappa0, sigma, fconst, _p(_f64(xi)), _p(_f64(r)), _p(z), int(galerkin)))
     return z
+
+
+def mg_galerkin(Nc, rpf, cif, vf):
+    """Values of the Galerkin coarse operator P^T A P (identity boundary
+    rows) on orc_graph(Nc), from the fine matrix (rpf, cif, vf) on 2 Nc."""
+    rpc, cic = graph(Nc)
+    vc = np.zeros(cic.shape[0])
+    _check(lib().orc_mg_galerkin(Nc, _p(rpf), _p(cif), _p(_f64(vf)), _p(rpc), _p(cic), _p(vc)))
+    return vc
 
 
 def mg_apply_adv(N, M, L, kappa0, sigma, fconst, alpha, vel, xi, r):
@@ -341,8 +353,10 @@ def max_threads():
     return int(lib().orc_max_threads())
 
 
-def ens_mg_pcg(N, M, L, kappa0, sigma, fconst, xi, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=None):
-    """Multigrid-preconditioned CG per sample (each sample its own hierarchy).
+def ens_mg_pcg(N, M, L, kappa0, sigma, fconst, xi, x0=None, rtol=1e-10, max_iter=10000, fixed_iters=None,
+               galerkin=False):
+    """Multigrid-preconditioned CG per sample (each sample its own hierarchy;
+    coarse levels rediscretized, or Galerkin products with galerkin).
     Returns (x [n][s], iters, rel_res, status, lmax [s][levels])."""
     xi = _f64(xi)
     s = xi.shape[0]
@@ -354,7 +368,7 @@ def ens_mg_pcg(N, M, L, kappa0, sigma, fconst, xi, x0=None, rtol=1e-10, max_iter
     lm = np.zeros((s, MG_MAX_LEVELS))
     fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, np.int32)
     _check(lib().orc_ens_mg_pcg(N, M, L, kappa0, sigma, fconst, s, _p(xi), _p(x), rtol, max_iter,
-                                None if fi is None else _p(fi), _p(it), _p(rr), _p(st), _p(lm)))
+                                None if fi is None else _p(fi), _p(it), _p(rr), _p(st), _p(lm), int(galerkin)))
     return x, it, rr, st, lm[:, :len(mg_levels(N))]
 
 

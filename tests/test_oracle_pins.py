@@ -648,6 +648,117 @@ def test_mg_galerkin_product_equals_coarse_assembly(orc):
                                atol=1e-13 * np.abs(Ac).max())
 
 
+def _hat_P(Nc):
+    """Trilinear interpolation from interior coarse nodes to interior fine
+    nodes built from the coarse hat functions: P[i, J] = prod over axes of
+    max(0, 1 - Nc |x_i - X_J|) at the fine node coordinates x_i."""
+    Nf = 2 * Nc
+
+    def coords(N):
+        idx = np.arange((N + 1) ** 3)
+        c = np.stack([idx % (N + 1), (idx // (N + 1)) % (N + 1), idx // (N + 1) ** 2], 1)
+        return c / N, ((c > 0) & (c < N)).all(1)
+
+    xf, inf_ = coords(Nf)
+    xc, inc = coords(Nc)
+    P = np.prod(np.maximum(0.0, 1.0 - Nc * np.abs(xf[:, None, :] - xc[None, :, :])), axis=2)
+    # at fine nodes the hat values are products of 1 and 1/2: remove the
+    # rounding of the coordinates
+    P = np.round(P * 8.0) / 8.0
+    P[~inf_, :] = 0.0
+    P[:, ~inc] = 0.0
+    return P, inc
+
+
+def _fine_matrix(orc, N, sigma, seed, M=10):
+    rp, ci = orc.graph(N)
+    xi = draw_xi(seed, 1, M)[0]
+    ac = orc.kl_coef_qp(N, M, 1.0, 1.0, sigma, xi)
+    vals, _ = orc.assemble_scalar(N, rp, ci, ac)
+    return rp, ci, vals, xi
+
+
+@pytest.mark.parametrize("Nc", [2, 3, 4])
+def test_mg_galerkin_operator_is_the_dense_triple_product(orc, Nc):
+    # Alg. vcycle forms A^{k+1} = R A^k P with R = P^T: at a variable
+    # coefficient the oracle's product equals dense P^T A P, P built from the
+    # coarse hat functions (not from the oracle's transfer code); boundary
+    # rows are identities and interior rows have no boundary entries
+    rp, ci, vals, _ = _fine_matrix(orc, 2 * Nc, 0.3, 5100 + Nc)
+    P, inner = _hat_P(Nc)
+    np.testing.assert_array_equal(P, _dense_P(orc, Nc))
+    G = P.T @ orc.crs_to_dense(rp, ci, vals) @ P
+    rpc, cic = orc.graph(Nc)
+    Ac = orc.crs_to_dense(rpc, cic, orc.mg_galerkin(Nc, rp, ci, vals))
+    scale = np.abs(G).max()
+    np.testing.assert_allclose(Ac[np.ix_(inner, inner)], G[np.ix_(inner, inner)], rtol=0, atol=1e-14 * scale)
+    bnd = ~inner
+    np.testing.assert_array_equal(Ac[bnd], np.eye(inner.size)[bnd])
+    assert (Ac[np.ix_(inner, bnd)] == 0.0).all()
+    Ai = Ac[np.ix_(inner, inner)]
+    np.testing.assert_allclose(Ai, Ai.T, rtol=0, atol=1e-15 * scale)
+    assert np.linalg.eigvalsh(0.5 * (Ai + Ai.T)).min() > 0.0
+
+
+def test_mg_galerkin_differs_from_rediscretization_only_at_variable_coefficient(orc):
+    Nc = 4
+    rpc, cic = orc.graph(Nc)
+    for sigma, same in ((0.0, True), (0.3, False)):
+        rp, ci, vals, xi = _fine_matrix(orc, 2 * Nc, sigma, 5200)
+        g = orc.mg_galerkin(Nc, rp, ci, vals)
+        ac = orc.kl_coef_qp(Nc, 10, 1.0, 1.0, sigma, xi)
+        r, _ = orc.assemble_scalar(Nc, rpc, cic, ac)
+        d = np.abs(g - r).max() / np.abs(r).max()
+        assert (d <= 1e-14) if same else (d >= 1e-4), (sigma, d)
+
+
+def test_mg_galerkin_coarse_correction_is_an_a_orthogonal_projection(orc):
+    # with A_c = P^T A P the two-grid coarse correction E = I - P A_c^-1 P^T A
+    # satisfies E^2 = E and A E = E^T A (an A-orthogonal projection): the
+    # variational property Galerkin coarse operators are chosen for; the
+    # rediscretized A_c of a variable coefficient has neither
+    Nc = 4
+    rp, ci, vals, xi = _fine_matrix(orc, 2 * Nc, 0.3, 5300)
+    P, inner_c = _hat_P(Nc)
+    Af = orc.crs_to_dense(rp, ci, vals)
+    nf = Af.shape[0]
+    idx = np.arange(nf)
+    c = np.stack([idx % (2 * Nc + 1), (idx // (2 * Nc + 1)) % (2 * Nc + 1), idx // (2 * Nc + 1) ** 2], 1)
+    inner_f = ((c > 0) & (c < 2 * Nc)).all(1)
+    A = Af[np.ix_(inner_f, inner_f)]
+    Pi = P[np.ix_(inner_f, inner_c)]
+    rpc, cic = orc.graph(Nc)
+    ac = orc.kl_coef_qp(Nc, 10, 1.0, 1.0, 0.3, xi)
+    redisc, _ = orc.assemble_scalar(Nc, rpc, cic, ac)
+    for vc, proj in ((orc.mg_galerkin(Nc, rp, ci, vals), True), (redisc, False)):
+        Ac = orc.crs_to_dense(rpc, cic, vc)[np.ix_(inner_c, inner_c)]
+        E = np.eye(A.shape[0]) - Pi @ np.linalg.solve(Ac, Pi.T @ A)
+        d2 = np.abs(E @ E - E).max()
+        dsym = np.abs(A @ E - E.T @ A).max() / np.abs(A).max()
+        if proj:
+            assert d2 <= 1e-12 and dsym <= 1e-12, (d2, dsym)
+        else:
+            assert d2 >= 1e-4, d2
+
+
+def test_mg_galerkin_pcg_converges_to_the_dense_solution(orc):
+    N, M, sigma = 8, 10, 0.3
+    xi = draw_xi(42, 3, M)
+    x, it, rr, st, lm = orc.ens_mg_pcg(N, M, 1.0, 1.0, sigma, 1.0, xi, rtol=1e-12, galerkin=True)
+    rp, ci = orc.graph(N)
+    ov, ob = orc.assemble_ensemble(N, rp, ci, M, 1.0, 1.0, sigma, 1.0, xi)
+    for e in range(3):
+        A = orc.crs_to_dense(rp, ci, np.ascontiguousarray(ov[:, e]))
+        xd = np.linalg.solve(A, ob[:, e])
+        assert st[e] == orc.CONVERGED and rr[e] <= 1e-12 * (1 + 1e-6)
+        assert np.linalg.norm(x[:, e] - xd) <= 1e-10 * np.linalg.norm(xd)
+        assert it[e] <= 10
+        # the coarse level's bound is that of the Galerkin matrix
+        g = orc.mg_galerkin(4, rp, ci, np.ascontiguousarray(ov[:, e]))
+        rpc, cic = orc.graph(4)
+        assert lm[e, 1] == orc.gershgorin(rpc, cic, g)
+
+
 def test_chebyshev_smoother_matches_its_polynomial(orc):
     # order-2 Chebyshev on [lmax/4, lmax] from x = 0: the error in each
     # eigenvector of D^-1 A is multiplied by T2((theta-l)/delta) / T2(theta/delta)
