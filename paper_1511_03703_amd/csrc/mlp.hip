@@ -206,30 +206,35 @@ __global__ __launch_bounds__(256) void k_colsum(int M, int N, const float* __res
 // One Adam step (Kingma and Ba 2015, Algorithm 1) per element, FP32:
 // moving averages of g and g^2, divided by the bias corrections c1 = 1 - b1^t
 // and c2 = 1 - b2^t, eps added to the square root of the second moment.
+// omb1 = 1 - b1 and omb2 = 1 - b2 come in as arguments, each the FP32
+// rounding of the exact value (1.0f - 0.999f would carry the 1.3e-5 relative
+// error of 0.999f into every second moment).
 __global__ void k_adam(int64_t P, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+                       float* __restrict__ v, float lr, float b1, float b2, float omb1, float omb2, float eps,
+                       float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
   const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 // Adam with beta = (0.9, 0.999), eps = 1e-8 at step t (1-based) over P
-// elements; the bias corrections are formed in FP64 from the FP32 betas.
+// elements; 1 - beta and the bias corrections 1 - beta^t are formed in FP64
+// from the decimal betas and rounded once to FP32.
 static void adam_launch(int64_t P, float* p, const float* g, float* m, float* v, int t, float lr,
                         hipStream_t stream) {
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const double b1 = 0.9, b2 = 0.999;
   double p1 = 1.0, p2 = 1.0;
   for (int k = 0; k < t; ++k) {
     p1 *= b1;
     p2 *= b2;
   }
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, P, p, g, m, v, lr, b1, b2,
-                     eps, (float)(1.0 - p1), (float)(1.0 - p2));
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, P, p, g, m, v, lr, (float)b1,
+                     (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, (float)(1.0 - p1), (float)(1.0 - p2));
 }
 
 // ------------------------------------------------------------ host side ---
