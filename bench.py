@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=8000, help="learned: Adam steps")
     ap.add_argument("--precond", default="mg", choices=["mg", "jacobi"],
                     help="headline/mid/small: preconditioner of the timed solve (default: multigrid)")
+    ap.add_argument("--coarse", default="redisc", choices=["redisc", "galerkin"],
+                    help="multigrid coarse operators: assembled on each mesh, or Galerkin products P^T A P")
     ap.add_argument("--mg-fp64", action="store_true",
                     help="mg: FP64 CG with an FP64 cycle instead of the FP32-in-FP64 refinement")
     ap.add_argument("--lr-halvings", type=int, default=3,
@@ -198,7 +200,8 @@ def run_solve(args):
     def step_mg():
         # fine assembly with the hierarchy's fine-level D^-1 and bound fused in,
         # then the coarse levels
-        mg.assemble_setup(g, kl, xi, w.sigma, vals, rhs, values32=v32, kappa0=w.kappa0, f=w.f)
+        mg.assemble_setup(g, kl, xi, w.sigma, vals, rhs, values32=v32, kappa0=w.kappa0, f=w.f,
+                          galerkin=args.coarse == "galerkin")
         x.zero_()
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=mg_opts, workspace=ws)
 
@@ -284,7 +287,9 @@ def run_solve(args):
                    "inner_rtol": (mg_inner if use_mg else jac_inner) if w.mixed else None,
                    "preconditioner": ("multigrid V-cycle (levels N, N/2, .. 4; order-2 Chebyshev; exact coarsest)"
                                       + (" in FP32 inside the FP64 refinement" if w.mixed else "")) if use_mg
-                   else "Jacobi"},
+                   else "Jacobi",
+                   "coarse_operators": ({"redisc": "assembled on each mesh", "galerkin": "Galerkin P^T A P"}
+                                        [args.coarse] if use_mg else None)},
         "roofline": roofline,
         "all_converged": ok,
         "iters": {"inner_total": [t["iters"] for t in stats], "outer": [t["outer_iters"] for t in stats]},
@@ -825,7 +830,8 @@ def run_mg(args):
     log(f"mg workload: N={w.N} s={w.s} hierarchy {mg.buffer.numel() / 2**30:.2f} GiB")
 
     def step():
-        mg.assemble_setup(g, kl, xi, w.sigma, vals, rhs, values32=v32, kappa0=w.kappa0, f=w.f)
+        mg.assemble_setup(g, kl, xi, w.sigma, vals, rhs, values32=v32, kappa0=w.kappa0, f=w.f,
+                          galerkin=args.coarse == "galerkin")
         x.zero_()
         return ens.cg_mg(g, vals, rhs, mg, x=x, values32=v32, opts=opts, workspace=ws)
 
@@ -858,6 +864,8 @@ def run_mg(args):
                    "s": w.s, "M": w.M, "sigma": w.sigma, "rtol": w.rtol, "seed": w.seed,
                    "levels": "128,64,32,16,8,4", "smoother": "Chebyshev order 2 on [lmax/4, lmax]",
                    "coarse": "dense inverse of the 4^3 interior block", "check_every": check,
+                   "coarse_operators": {"redisc": "assembled on each mesh", "galerkin": "Galerkin P^T A P"}[
+                       args.coarse],
                    "inner_rtol": inner if mixed else None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

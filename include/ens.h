@@ -417,6 +417,41 @@ ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const
 ens_status ens_mg_assemble_setup_adv(const ens_mg* mg, const ens_graph* graph, const void* kl,
                                      const ens_nl_problem* problem, const double* xi, double* values,
                                      float* values32, double* rhs, hipStream_t stream);
+/* ens_mg_setup with the coarse operators of Alg. vcycle as printed (Sec.
+ * 3.5): A^{k+1} = R^k A^k P^k, R = P^T, each coarse level the Galerkin
+ * product of the level above instead of an assembly on its own mesh.  Per
+ * sample, in FP64 from the FP64 matrix of the level above (the fine one:
+ * `values`, required); an FP32 cycle's coarse copies are rounded from them.
+ * Every term P_iI A_ij P_jJ is exact (the weights are powers of two) and
+ * the terms of an entry are summed in a fixed order (children of I, then
+ * row entries, then parents of j, each ascending in z, y, x), so the result
+ * is deterministic.  Coarse boundary rows are identity rows and boundary
+ * columns of interior rows stored zeros, as on assembled levels.  D^-1 and
+ * the Gershgorin bound of every level are formed by a pass over the matrix
+ * the cycle runs on, then the coarsest inverse.  No KL input is needed:
+ * the coarse levels see the coefficient only through the fine matrix.
+ * Buffer built by ens_mg_build; graph the N^3 mesh's; arguments and errors
+ * otherwise as for ens_mg_setup.  Stream ordered. */
+ens_status ens_mg_setup_galerkin(const ens_mg* mg, const ens_graph* graph, const double* values,
+                                 const float* values32, hipStream_t stream);
+/* ens_mg_assemble_setup with Galerkin coarse levels (ens_mg_setup_galerkin):
+ * the fine matrix assembled into values (required), values32 and rhs, the
+ * fine level's D^-1 and bound formed by the assembly, then the Galerkin
+ * products.  Arguments and errors as for ens_mg_assemble_setup, except
+ * that values may not be NULL. */
+ens_status ens_mg_assemble_setup_galerkin(const ens_mg* mg, const ens_graph* graph, const void* kl,
+                                          const ens_problem* problem, const double* xi, double* values,
+                                          float* values32, double* rhs, hipStream_t stream);
+/* Where coarse level `level` (1 .. levels-1; level 0 is the caller's fine
+ * matrix) keeps its operator inside the hierarchy buffer: *N its mesh size,
+ * *values its FP64 matrix [nnz(N)][s] on the graph of ens_graph_build(N),
+ * *values32 its FP32 copy (NULL for an FP64 cycle).  Host only; device
+ * pointers into mg->buffer, owned by the caller's buffer, valid as long as
+ * it is; the contents are those of the last set-up.  For inspecting the
+ * coarse operators (rediscretized or Galerkin).  ENS_E_ARG for a level out
+ * of range. */
+ens_status ens_mg_level_values(const ens_mg* mg, int32_t level, int32_t* N, const double** values,
+                               const float** values32);
 /* Forget the buffer's built / set-up record (host only, never fails on an
  * unknown buffer).  Call it before the buffer is freed: a later allocation
  * at the same address would otherwise pass as built. */

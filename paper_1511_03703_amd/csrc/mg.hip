@@ -474,6 +474,117 @@ __global__ __launch_bounds__(256) void k_mg_coarse(int Nc, int64_t m, const doub
   x[t] = (T)acc;
 }
 
+// Galerkin coarse operator of Alg. vcycle, A_c = P^T A_f P with R = P^T, P
+// the trilinear interpolation of k_mg_prolong.  Lane e of a group of S
+// lanes forms the 27 entries of one coarse row for sample e:
+//   (P^T A P)_{IJ} = sum_i P_{iI} sum_j A_ij P_{jJ}.
+// For an interior coarse node I the fine children are i = 2I + o,
+// o in {-1,0,1}^3 (all interior, weight prod (o ? 1/2 : 1)); row i holds the
+// 27 neighbours j = i + d, and a fine node j = 2I + t, t = o + d, has the
+// coarse parents I + t/2 (t even, weight 1) or I + (t-1)/2 and I + (t+1)/2
+// (t odd, 1/2 each).  With o, d and t known at compile time every term goes
+// to a fixed one of 27 register accumulators, indexed by the parent's offset
+// from I, and every weight product is a power of two, so each term
+// A_ij * w is exact and only the additions round; they run in the order
+// children (z, y, x ascending), row entries ascending, parents (z, y, x,
+// ascending).  Terms through a coarse boundary parent land in that
+// parent's accumulator and are dropped at the store: boundary columns of
+// interior rows are stored zeros and boundary rows identity rows, as on
+// the assembled levels (P has no boundary columns).  Interior rows of
+// every level hold the full 3x3x3 neighbour block in ascending order.
+// Workgroups of consecutive rows are dealt to the 8 XCDs in contiguous
+// ranges, so the fine rows that neighbouring coarse rows share are read
+// through one L2.
+__device__ inline int64_t xcd_contiguous_block(int64_t b, int64_t nb) {
+  const int64_t per = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+// An empty asm that reads and writes every accumulator: a point every term
+// so far must have reached.
+template <int T>
+__device__ __forceinline__ void acc_fence(double (&acc)[27]) {
+  if constexpr (T < 27) {
+    asm volatile("" : "+v"(acc[T]));
+    acc_fence<T + 1>(acc);
+  }
+}
+
+// The terms of fine child i = 2I + (OX, OY, OZ) (row `a`, this lane's
+// sample) in entry order, then the fence: the compiler otherwise orders the
+// work by accumulator and keeps all 729 loaded values of a row live.
+template <int C, int S>
+__device__ __forceinline__ void galerkin_children(double (&acc)[27], int I, int J, int K, int64_t pf,
+                                                  const int32_t* __restrict__ rpf, const double* __restrict__ vf,
+                                                  int e) {
+  if constexpr (C < 27) {
+    constexpr int OX = C % 3 - 1, OY = (C / 3) % 3 - 1, OZ = C / 9 - 1;
+    constexpr double wi = (OX ? 0.5 : 1.0) * (OY ? 0.5 : 1.0) * (OZ ? 0.5 : 1.0);
+    const int64_t i = (2 * I + OX) + pf * ((2 * J + OY) + pf * (2 * K + OZ));
+    const double* a = vf + (int64_t)rpf[i] * S + e;
+    double av[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) av[q] = a[q * S];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+      const int tz = OZ + dz, ty = OY + dy, tx = OX + dx;
+      // parents per axis: count, first offset from I; weight
+      const int nz = (tz & 1) ? 2 : 1, ny = (ty & 1) ? 2 : 1, nx = (tx & 1) ? 2 : 1;
+      const int fz = (tz & 1) ? (tz - 1) / 2 : tz / 2, fy = (ty & 1) ? (ty - 1) / 2 : ty / 2,
+                fx = (tx & 1) ? (tx - 1) / 2 : tx / 2;
+      const double wt = wi * ((nz == 2 ? 0.5 : 1.0) * (ny == 2 ? 0.5 : 1.0) * (nx == 2 ? 0.5 : 1.0));
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            if (c >= nz || b >= ny || p >= nx) continue;
+            acc[(fz + c + 1) * 9 + (fy + b + 1) * 3 + (fx + p + 1)] += av[q] * wt;
+          }
+    }
+    acc_fence<0>(acc);
+    galerkin_children<C + 1, S>(acc, I, J, K, pf, rpf, vf, e);
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_mg_galerkin(int Nc, const int32_t* __restrict__ rpf,
+                                                     const double* __restrict__ vf, const int32_t* __restrict__ rpc,
+                                                     const int32_t* __restrict__ cic, double* __restrict__ vc,
+                                                     float* __restrict__ vc32) {
+  constexpr int G = 256 / S;
+  const int e = threadIdx.x % S;
+  const int64_t nc = (int64_t)(Nc + 1) * (Nc + 1) * (Nc + 1);
+  const int64_t row = xcd_contiguous_block(blockIdx.x, gridDim.x) * G + threadIdx.x / S;
+  if (row >= nc) return;
+  const int I = (int)(row % (Nc + 1)), J = (int)((row / (Nc + 1)) % (Nc + 1)),
+            K = (int)(row / ((int64_t)(Nc + 1) * (Nc + 1)));
+  const int64_t q0 = rpc[row];
+  if (I == 0 || J == 0 || K == 0 || I == Nc || J == Nc || K == Nc) {
+    const int64_t q1 = rpc[row + 1];
+    for (int64_t q = q0; q < q1; ++q) {
+      const double v = cic[q] == row ? 1.0 : 0.0;
+      vc[q * S + e] = v;
+      if (vc32) vc32[q * S + e] = (float)v;
+    }
+    return;
+  }
+  double acc[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = 0.0;
+  galerkin_children<0, S>(acc, I, J, K, (int64_t)2 * Nc + 1, rpf, vf, e);
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+    const bool bnd = I + dx == 0 || I + dx == Nc || J + dy == 0 || J + dy == Nc || K + dz == 0 || K + dz == Nc;
+    const double v = bnd ? 0.0 : acc[q];
+    vc[(q0 + q) * S + e] = v;
+    if (vc32) vc32[(q0 + q) * S + e] = (float)v;
+  }
+}
+
 // ------------------------------------------------------------ host side ---
 
 static unsigned blocks_for(int64_t items, int64_t per) {
@@ -553,6 +664,39 @@ static ens_status build(const MgPlan& P, int M, double L, hipStream_t st) {
   return ENS_OK;
 }
 
+// Level bound from the per-tile maxima its assembly wrote: the maximum in
+// two stages (exact in any order).
+template <int S>
+static void tile_bound(const MgPlan& P, const MgLevel& l, hipStream_t st) {
+  const int64_t rows = asm_tiles(l.N, S);
+  int64_t g1 = rows / 256;
+  if (g1 < 1) g1 = 1;
+  if (g1 > 256) g1 = 256;
+  hipLaunchKernelGGL(k_mg_max_stage<S>, dim3((unsigned)g1), dim3(1024), 0, st, l.tpart, rows, P.part);
+  hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(1024), 0, st, P.part, (int)g1, l.lmax);
+}
+
+// D^-1 and the bound of a level by a pass over the matrix the cycle runs
+// on there (the FP32 copy for an FP32 cycle).
+template <int S>
+static void row_bound(const MgPlan& P, const MgLevel& l, hipStream_t st) {
+  const unsigned gb = blocks_for(l.n, 256 / S) < (unsigned)kMgPartRows ? blocks_for(l.n, 256 / S) : kMgPartRows;
+  if (P.fp32)
+    hipLaunchKernelGGL((k_mg_diag_bound<float, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals32,
+                       (float*)l.dinv, P.part);
+  else
+    hipLaunchKernelGGL((k_mg_diag_bound<double, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals,
+                       (double*)l.dinv, P.part);
+  hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(1024), 0, st, P.part, (int)gb, l.lmax);
+}
+
+template <int S>
+static void coarsest_inverse(const MgPlan& P, hipStream_t st) {
+  const MgLevel& c = P.lv[P.levels - 1];
+  if (c.m > 0)
+    hipLaunchKernelGGL(k_mg_inverse<S>, dim3(S), dim3(256), 0, st, c.N, c.rp, c.ci, c.vals, c.m, c.ainv);
+}
+
 // fine_done: the fine level's D^-1 and per-tile bound maxima were formed by
 // its assembly (ens_mg_assemble_setup); only their maximum is taken here.
 // adv (nullable): {alpha, vx, vy, vz} of the advection-diffusion operator
@@ -573,28 +717,32 @@ static ens_status setup(const MgPlan& P, const ens_problem& prob, const double* 
                                       P.fp32 ? 1 : 2, l.dinv, l.tpart, st, adv);
       if (rc != ENS_OK) return rc;
     }
-    if (k > 0 || fine_done) {
-      // maximum of the per-tile maxima in two stages (exact in any order)
-      const int64_t rows = asm_tiles(l.N, S);
-      int64_t g1 = rows / 256;
-      if (g1 < 1) g1 = 1;
-      if (g1 > 256) g1 = 256;
-      hipLaunchKernelGGL(k_mg_max_stage<S>, dim3((unsigned)g1), dim3(1024), 0, st, l.tpart, rows, P.part);
-      hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(1024), 0, st, P.part, (int)g1, l.lmax);
-      continue;
-    }
-    const unsigned gb = blocks_for(l.n, 256 / S) < (unsigned)kMgPartRows ? blocks_for(l.n, 256 / S) : kMgPartRows;
-    if (P.fp32)  // the FP32 cycle's own matrix: its D^-1 and its bound
-      hipLaunchKernelGGL((k_mg_diag_bound<float, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals32,
-                         (float*)l.dinv, P.part);
-    else
-      hipLaunchKernelGGL((k_mg_diag_bound<double, S>), dim3(gb), dim3(256), 0, st, l.n, l.rp, l.ci, l.vals,
-                         (double*)l.dinv, P.part);
-    hipLaunchKernelGGL(k_mg_max<S>, dim3(1), dim3(1024), 0, st, P.part, (int)gb, l.lmax);
+    if (k > 0 || fine_done) tile_bound<S>(P, l, st);
+    else row_bound<S>(P, l, st);
   }
-  const MgLevel& c = P.lv[P.levels - 1];
-  if (c.m > 0)
-    hipLaunchKernelGGL(k_mg_inverse<S>, dim3(S), dim3(256), 0, st, c.N, c.rp, c.ci, c.vals, c.m, c.ainv);
+  coarsest_inverse<S>(P, st);
+  ENS_LAUNCH_CHECK();
+  return ENS_OK;
+}
+
+// Coarse levels as Galerkin products P^T A P of the level above, formed in
+// FP64 from its FP64 matrix (an FP32 cycle's copy rounded from them), D^-1
+// and bounds by a pass over each coarse level's cycle matrix, the coarsest
+// inverse.  fine_done: the fine level's D^-1 and per-tile maxima came from
+// its assembly.  The fine FP64 matrix must be attached.
+template <int S>
+static ens_status setup_galerkin(const MgPlan& P, hipStream_t st, bool fine_done) {
+  for (int k = 0; k < P.levels; ++k) {
+    const MgLevel& l = P.lv[k];
+    if (k > 0) {
+      const MgLevel& f = P.lv[k - 1];
+      hipLaunchKernelGGL(k_mg_galerkin<S>, dim3(blocks_for(l.n, 256 / S)), dim3(256), 0, st, l.N, f.rp, f.vals,
+                         l.rp, l.ci, l.own_vals, P.fp32 ? l.own_vals32 : nullptr);
+    }
+    if (k == 0 && fine_done) tile_bound<S>(P, l, st);
+    else row_bound<S>(P, l, st);
+  }
+  coarsest_inverse<S>(P, st);
   ENS_LAUNCH_CHECK();
   return ENS_OK;
 }
@@ -676,9 +824,10 @@ ens_status ens_mg_setup(const ens_mg* mg, const ens_graph* graph, const double* 
 
 static ens_status assemble_setup(const ens_mg* mg, const ens_graph* graph, const void* kl,
                                  const ens_problem* problem, const double* adv, const double* xi, double* values,
-                                 float* values32, double* rhs, hipStream_t stream) {
+                                 float* values32, double* rhs, hipStream_t stream, bool galerkin = false) {
   ENS_ARG_CHECK(mg && graph && kl && problem && xi && rhs && mg->buffer, "null argument");
   ENS_ARG_CHECK(values || mg->fp32, "an FP64 hierarchy needs the FP64 fine matrix");
+  ENS_ARG_CHECK(values || !galerkin, "Galerkin coarse levels need the FP64 fine matrix");
   ENS_ARG_CHECK(((uintptr_t)mg->buffer & 255u) == 0, "multigrid buffer must be 256-byte aligned");
   ENS_ARG_CHECK((!values || aligned16(values)) && aligned16(rhs), "values and rhs must be 16-byte aligned");
   ENS_ARG_CHECK(!mg->fp32 || (values32 && aligned16(values32)), "an FP32 cycle needs the FP32 fine matrix");
@@ -712,12 +861,18 @@ static ens_status assemble_setup(const ens_mg* mg, const ens_graph* graph, const
   rc = assemble_launch(mg->N, graph, sq, tr, phi, problem, mg->s, xi, values, values32, rhs, mg->fp32 ? 1 : 2,
                        plan.lv[0].dinv, plan.lv[0].tpart, stream, adv);
   if (rc != ENS_OK) return rc;
-  switch (mg->s) {
-    case 4: rc = setup<4>(plan, *problem, xi, stream, true, adv); break;
-    case 8: rc = setup<8>(plan, *problem, xi, stream, true, adv); break;
-    case 16: rc = setup<16>(plan, *problem, xi, stream, true, adv); break;
-    default: rc = setup<32>(plan, *problem, xi, stream, true, adv); break;
-  }
+  if (galerkin) switch (mg->s) {
+      case 4: rc = setup_galerkin<4>(plan, stream, true); break;
+      case 8: rc = setup_galerkin<8>(plan, stream, true); break;
+      case 16: rc = setup_galerkin<16>(plan, stream, true); break;
+      default: rc = setup_galerkin<32>(plan, stream, true); break;
+    }
+  else switch (mg->s) {
+      case 4: rc = setup<4>(plan, *problem, xi, stream, true, adv); break;
+      case 8: rc = setup<8>(plan, *problem, xi, stream, true, adv); break;
+      case 16: rc = setup<16>(plan, *problem, xi, stream, true, adv); break;
+      default: rc = setup<32>(plan, *problem, xi, stream, true, adv); break;
+    }
   if (rc == ENS_OK) mg_mark(mg, Lb, 2, adv && adv[0] != 0.0 ? 1 : 0);
   return rc;
 }
@@ -726,6 +881,48 @@ ens_status ens_mg_assemble_setup(const ens_mg* mg, const ens_graph* graph, const
                                  const ens_problem* problem, const double* xi, double* values, float* values32,
                                  double* rhs, hipStream_t stream) {
   return assemble_setup(mg, graph, kl, problem, nullptr, xi, values, values32, rhs, stream);
+}
+
+ens_status ens_mg_assemble_setup_galerkin(const ens_mg* mg, const ens_graph* graph, const void* kl,
+                                          const ens_problem* problem, const double* xi, double* values,
+                                          float* values32, double* rhs, hipStream_t stream) {
+  return assemble_setup(mg, graph, kl, problem, nullptr, xi, values, values32, rhs, stream, true);
+}
+
+ens_status ens_mg_setup_galerkin(const ens_mg* mg, const ens_graph* graph, const double* values,
+                                 const float* values32, hipStream_t stream) {
+  ENS_ARG_CHECK(mg && graph && values && mg->buffer, "null multigrid argument");
+  ENS_ARG_CHECK(((uintptr_t)mg->buffer & 255u) == 0, "multigrid buffer must be 256-byte aligned");
+  ENS_ARG_CHECK(aligned16(values), "values must be 16-byte aligned");
+  ENS_ARG_CHECK(!mg->fp32 || (values32 && aligned16(values32)), "an FP32 cycle needs the FP32 fine matrix");
+  int64_t n = 0, nnz = 0;
+  ens_status rc = ens_mesh_sizes(mg->N, &n, &nnz, nullptr);
+  if (rc != ENS_OK) return rc;
+  ENS_ARG_CHECK(graph->n == n && graph->nnz == nnz && graph->row_ptr && graph->col_idx,
+                "graph is not the N^3 mesh's graph");
+  size_t need = 0;
+  rc = ens_mg_bytes(mg->N, mg->M, mg->s, mg->fp32, &need);
+  if (rc != ENS_OK) return rc;
+  if (mg->bytes < need) {
+    set_error("multigrid buffer of %zu bytes is smaller than the %zu required", mg->bytes, need);
+    return ENS_E_NOMEM;
+  }
+  const double Lb = mg_built_L(mg);
+  if (Lb <= 0.0) {
+    set_error("multigrid buffer not built: call ens_mg_build first");
+    return ENS_E_ARG;
+  }
+  MgPlan plan;
+  mg_plan(mg->N, mg->M, mg->s, mg->fp32 != 0, (char*)mg->buffer, &plan);
+  mg_attach_fine(&plan, graph->row_ptr, graph->col_idx, values, mg->fp32 ? values32 : nullptr);
+  switch (mg->s) {
+    case 4: rc = setup_galerkin<4>(plan, stream, false); break;
+    case 8: rc = setup_galerkin<8>(plan, stream, false); break;
+    case 16: rc = setup_galerkin<16>(plan, stream, false); break;
+    default: rc = setup_galerkin<32>(plan, stream, false); break;
+  }
+  if (rc == ENS_OK) mg_mark(mg, Lb, 2);
+  return rc;
 }
 
 ens_status ens_mg_assemble_setup_adv(const ens_mg* mg, const ens_graph* graph, const void* kl,
@@ -738,6 +935,21 @@ ens_status ens_mg_assemble_setup_adv(const ens_mg* mg, const ens_graph* graph, c
   const ens_problem lin{problem->M, problem->L, problem->kappa0, problem->sigma, problem->f};
   const double adv[4] = {problem->alpha, problem->vx, problem->vy, problem->vz};
   return assemble_setup(mg, graph, kl, &lin, adv, xi, values, values32, rhs, stream);
+}
+
+ens_status ens_mg_level_values(const ens_mg* mg, int32_t level, int32_t* N, const double** values,
+                               const float** values32) {
+  ENS_ARG_CHECK(mg && mg->buffer && N && values && values32, "null argument");
+  MgPlan plan;
+  if (!mg_plan(mg->N, mg->M, mg->s, mg->fp32 != 0, (char*)mg->buffer, &plan)) {
+    set_error("coarsest multigrid level of N=%d has more than %lld interior unknowns", mg->N, (long long)kMgMaxCoarse);
+    return ENS_E_UNSUPPORTED;
+  }
+  ENS_ARG_CHECK(level >= 1 && level < plan.levels, "level is not a coarse level of this hierarchy");
+  *N = plan.lv[level].N;
+  *values = plan.lv[level].own_vals;
+  *values32 = plan.lv[level].own_vals32;
+  return ENS_OK;
 }
 
 ens_status ens_mg_release(const ens_mg* mg) {

@@ -126,6 +126,11 @@ _SIGS = [
     ("ens_mg_release", _I32, [ctypes.POINTER(ens_mg)]),
     ("ens_mg_assemble_setup", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_problem), _P, _P, _P, _P,
                                      _P]),
+    ("ens_mg_setup_galerkin", _I32, [ctypes.POINTER(ens_mg), _GP, _P, _P, _P]),
+    ("ens_mg_assemble_setup_galerkin", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_problem), _P, _P,
+                                              _P, _P, _P]),
+    ("ens_mg_level_values", _I32, [ctypes.POINTER(ens_mg), _I32, ctypes.POINTER(_I32), ctypes.POINTER(_P),
+                                   ctypes.POINTER(_P)]),
     ("ens_kl_extrema", _I32, [_I32, _P, ctypes.POINTER(ens_problem), _I32, _P, _P, _P, _P]),
     ("ens_group_order", _I32, [ctypes.c_int64, _P, _P]),
     ("ens_mg_assemble_setup_adv", _I32, [ctypes.POINTER(ens_mg), _GP, _P, ctypes.POINTER(ens_nl_problem), _P, _P, _P,
@@ -511,16 +516,47 @@ class Multigrid:
         except Exception:
             pass
 
-    def assemble_setup(self, g: Graph, kl, xi, sigma, values, rhs, values32=None, kappa0=1.0, f=1.0, stream=None):
+    def assemble_setup(self, g: Graph, kl, xi, sigma, values, rhs, values32=None, kappa0=1.0, f=1.0, stream=None,
+                       galerkin=False):
         """Assemble the fine matrix into values (values32), rhs and set the
         hierarchy up in one call, the fine level's D^-1 and bound formed by
-        the assembly."""
+        the assembly; galerkin: coarse levels P^T A P of the level above
+        (ens_mg_assemble_setup_galerkin) instead of their own assemblies."""
         prob = ens_problem(self.desc.M, self.L, kappa0, sigma, f)
         gc = g.c()
         self._values = (values, values32)
-        _check(lib().ens_mg_assemble_setup(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(kl), ctypes.byref(prob),
-                                           _ptr(xi), _ptr(values), _ptr(values32), _ptr(rhs), _stream(stream)),
-               "ens_mg_assemble_setup")
+        fn = lib().ens_mg_assemble_setup_galerkin if galerkin else lib().ens_mg_assemble_setup
+        _check(fn(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(kl), ctypes.byref(prob), _ptr(xi), _ptr(values),
+                  _ptr(values32), _ptr(rhs), _stream(stream)),
+               "ens_mg_assemble_setup_galerkin" if galerkin else "ens_mg_assemble_setup")
+        return self
+
+    def level_values(self, level: int):
+        """(N, FP64 values [nnz][s], FP32 values or None) of coarse level
+        `level`, copied out of the hierarchy buffer."""
+        Nl, v64, v32 = _I32(), _P(), _P()
+        _check(lib().ens_mg_level_values(ctypes.byref(self.desc), level, ctypes.byref(Nl), ctypes.byref(v64),
+                                         ctypes.byref(v32)), "ens_mg_level_values")
+        nnz = (3 * Nl.value + 1) ** 3
+        s = self.desc.s
+        base = self.buffer.data_ptr()
+
+        def view(ptr, dtype, width):
+            off = ptr - base
+            assert off % width == 0 and off + nnz * s * width <= self.buffer.numel()
+            return self.buffer[off:off + nnz * s * width].view(dtype).view(nnz, s).clone()
+
+        a = view(v64.value, torch.float64, 8)
+        b = view(v32.value, torch.float32, 4) if v32.value else None
+        return Nl.value, a, b
+
+    def setup_galerkin(self, g: Graph, values, values32=None, stream=None):
+        """Coarse levels as Galerkin products P^T A P from the FP64 fine
+        matrix `values` (ens_mg_setup_galerkin)."""
+        gc = g.c()
+        self._values = (values, values32)
+        _check(lib().ens_mg_setup_galerkin(ctypes.byref(self.desc), ctypes.byref(gc), _ptr(values), _ptr(values32),
+                                           _stream(stream)), "ens_mg_setup_galerkin")
         return self
 
     def assemble_setup_adv(self, g: Graph, kl, xi, problem: ens_nl_problem, values, rhs, values32=None,
