@@ -284,6 +284,27 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
                   const double* b, double* x, const ens_cg_opts* opts, void* workspace,
                   size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ens_cg with
+ * the workspace taken from a scratch array inside the library instead of a
+ * caller buffer.  Arguments, results and errors as for ens_cg, bitwise the
+ * same results.  The scratch is a file-scope device array of 256 MiB
+ * (ENS_CG_NOALLOC_SCRATCH_BYTES), one per GPU the library runs on, held
+ * until the process ends; a solve whose ens_cg_workspace_bytes exceeds it
+ * returns ENS_E_NOMEM before any device work (for FP64 CG about
+ * 40 n s bytes: 64^3 elements at s = 16 fits, at s = 32 it does not).  The
+ * first call on a device resolves the array's address there
+ * (hipGetSymbolAddress); no call allocates memory: polls copy into host
+ * stack words and the library's profiling events are not used.  Every call
+ * on a GPU uses that GPU's one array, which keeps the last call's contents
+ * (each call initialises what it reads): calls that overlap on one GPU
+ * (other threads or streams) race and must be serialised by the caller.
+ * Synchronises the stream. */
+#define ENS_CG_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+ens_status ens_cg_noalloc(const ens_graph* graph, int32_t s, const double* values, const float* values32,
+                          const double* b, double* x, const ens_cg_opts* opts, ens_cg_stat* stats,
+                          hipStream_t stream);
+
 /* The same Jacobi-CG for s independent systems solved one after another
  * with one-sample kernels on the sample-major layout of Eq. kron_sys:
  * values [s][nnz], b and x [s][n] (device).  FP64 only (opts->mixed must

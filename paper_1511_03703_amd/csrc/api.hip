@@ -89,8 +89,13 @@ static hipEvent_t take_event() {
   return e;
 }
 
+// Profiling paused on this thread (ProfPause): no event is taken or created.
+static thread_local int g_prof_paused = 0;
+ProfPause::ProfPause() { ++g_prof_paused; }
+ProfPause::~ProfPause() { --g_prof_paused; }
+
 void prof_begin(int k, hipStream_t st) {
-  if (!g_prof_on || k < 0 || k >= ENS_K_COUNT) return;
+  if (!g_prof_on || g_prof_paused || k < 0 || k >= ENS_K_COUNT) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = take_event();
   if (!e) return;
@@ -100,7 +105,7 @@ void prof_begin(int k, hipStream_t st) {
 }
 
 void prof_end(int k, hipStream_t st, double bytes) {
-  if (!g_prof_on || k < 0 || k >= ENS_K_COUNT) return;
+  if (!g_prof_on || g_prof_paused || k < 0 || k >= ENS_K_COUNT) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_open_valid[k]) return;
   hipEvent_t e = take_event();

@@ -26,6 +26,9 @@
 // launch it saves).  Every kernel of the iteration returns immediately when
 // the active count is zero, and the host reads the count once per chunk of
 // iterations, so the loop ends on the device.
+#include <mutex>
+#include <vector>
+
 #include "cgcore.hpp"
 #include "mg.hpp"
 
@@ -189,6 +192,9 @@ struct Work {
   double* part;   // block partials, [blocks][2 s]
   double* part1;  // first-stage sums, [kRedBlocks][2 s]
   void* vec[5];
+  // polls copy into a stack word instead of the device context's pinned one
+  // (for the entry point that must not allocate, even the context)
+  bool pageable_poll = false;
 };
 
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -246,7 +252,17 @@ static void reduce(const Work& w, int64_t nrows, int op, int arg, int gate, hipS
   hipLaunchKernelGGL((k_reduce_final<S, NQ>), dim3(1), dim3(kBlock), 0, st, w.part1, r, w.ctl, op, arg, gate);
 }
 
-static ens_status poll_active(Ctl* ctl, bool outer, hipStream_t st, int32_t* out) {
+static ens_status poll_active(const Work& w, bool outer, hipStream_t st, int32_t* out) {
+  Ctl* ctl = w.ctl;
+  if (w.pageable_poll) {
+    int32_t h = 0;
+    ENS_HIP_TRY(hipMemcpyAsync(&h, outer ? &ctl->n_oactive : &ctl->n_active, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st));
+    ENS_HIP_TRY(hipStreamSynchronize(st));
+    prof_collect();
+    *out = h;
+    return ENS_OK;
+  }
   DeviceCtx* cx = device_ctx();
   if (!cx) {
     set_error("device context unavailable");
@@ -295,7 +311,7 @@ static ens_status cg_loop(const ens_graph* g, const T* vals, T* x, T* r, T* p, T
     for (int k = k0 + 1; k <= k1; ++k) cg_iteration<T, S>(g, vals, x, r, p, q, dinv, w, k, st);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
-    ens_status s2 = poll_active(w.ctl, false, st, &act);
+    ens_status s2 = poll_active(w, false, st, &act);
     if (s2 != ENS_OK) return s2;
     if (act == 0) break;
     if (pause_at > 0 && act <= pause_at && k1 < max_iter) {
@@ -551,7 +567,7 @@ static ens_status cg_mixed(const ens_graph* g, const double* vals, const float* 
       hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
-    ens_status rc = poll_active(w.ctl, true, st, &act);
+    ens_status rc = poll_active(w, true, st, &act);
     if (rc != ENS_OK) return rc;
     if (act == 0) break;
     cg_start<float, S>(n, r, dinv, p, d, w, st);
@@ -627,7 +643,7 @@ static ens_status cg_scalar_one(const ens_graph* g, const double* vals, const do
     scalar_iters<G>(g, vals, x, w, k0, k1, st);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
-    ens_status rc = poll_active(w.ctl, false, st, &act);
+    ens_status rc = poll_active(w, false, st, &act);
     if (rc != ENS_OK) return rc;
     if (act == 0) break;
   }
@@ -782,7 +798,7 @@ static ens_status cg_mg(const ens_graph* g, const double* vals, const double* b,
     mg_iterations<double, S>(g, vals, plan, x, r, p, q, z, w, k0, k1, st);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
-    ens_status rc = poll_active(w.ctl, false, st, &act);
+    ens_status rc = poll_active(w, false, st, &act);
     if (rc != ENS_OK) return rc;
     if (act == 0) break;
   }
@@ -810,7 +826,7 @@ static ens_status cg_mixed_mg(const ens_graph* g, const double* vals, const floa
       hipLaunchKernelGGL(k_zero_where<S>, dim3(grid_for(total, 256 * 8)), dim3(kBlock), 0, st, total, x, w.ctl);
     ENS_LAUNCH_CHECK();
     int32_t act = 0;
-    ens_status rc = poll_active(w.ctl, true, st, &act);
+    ens_status rc = poll_active(w, true, st, &act);
     if (rc != ENS_OK) return rc;
     if (act == 0) break;
     hipLaunchKernelGGL(k_fill_zero<float>, dim3(grid_for(total, 256)), dim3(256), 0, st, total, d);
@@ -820,7 +836,7 @@ static ens_status cg_mixed_mg(const ens_graph* g, const double* vals, const floa
       const int k1 = k0 + o.check_every < o.inner_max_iter ? k0 + o.check_every : o.inner_max_iter;
       mg_iterations<float, S>(g, vals32, plan, d, r, p, q, z, w, k0, k1, st);
       ENS_LAUNCH_CHECK();
-      rc = poll_active(w.ctl, false, st, &act);
+      rc = poll_active(w, false, st, &act);
       if (rc != ENS_OK) return rc;
       if (act == 0) break;
     }
@@ -842,28 +858,11 @@ static ens_cg_opts normalized(const ens_cg_opts* in) {
   return o;
 }
 
-}  // namespace ens
-
-using namespace ens;
-
-extern "C" {
-
-ens_status ens_cg_workspace_bytes(const ens_graph* graph, int32_t s, const ens_cg_opts* opts, size_t* bytes) {
-  ens_status st = check_graph(graph);
-  if (st != ENS_OK) return st;
-  ENS_ARG_CHECK(opts && bytes, "null argument");
-  if (!supported_s(s)) {
-    set_error("ensemble size %d not compiled in", s);
-    return ENS_E_UNSUPPORTED;
-  }
-  *bytes = ws_layout(graph->n, s, opts->mixed != 0, nullptr, nullptr) +
-           (opts->compact && !opts->mixed && !opts->coupled ? compact_bytes(graph->n, graph->nnz, s) : 0);
-  return ENS_OK;
-}
-
-ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const float* values32, const double* b,
-                  double* x, const ens_cg_opts* opts, void* workspace, size_t ws_bytes, ens_cg_stat* stats,
-                  hipStream_t stream) {
+// ens_cg on a given workspace; pageable_poll: polls without the device
+// context (ens_cg_noalloc).
+static ens_status cg_run(const ens_graph* graph, int32_t s, const double* values, const float* values32,
+                         const double* b, double* x, const ens_cg_opts* opts, void* workspace, size_t ws_bytes,
+                         ens_cg_stat* stats, hipStream_t stream, bool pageable_poll) {
   ens_status st = check_graph(graph);
   if (st != ENS_OK) return st;
   ENS_ARG_CHECK(opts && stats, "null options or stats");
@@ -896,6 +895,7 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
   }
   Work w;
   ws_layout(graph->n, s, mixed, &w, (char*)workspace);
+  w.pageable_poll = pageable_poll;
   ens_cg_opts o = normalized(opts);
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, w.ctl, o.rtol, o.inner_rtol, o.max_iter,
                      o.inner_max_iter, o.max_outer, (int)mixed, o.coupled ? 1 : 0);
@@ -914,6 +914,90 @@ ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const
   }
   if (st != ENS_OK) return st;
   return read_stats(w.ctl, s, stats, stream);
+}
+
+// Workspace bytes of ens_cg for these options (graph and s checked).
+static size_t cg_ws_need(const ens_graph* graph, int s, const ens_cg_opts& o) {
+  return ws_layout(graph->n, s, o.mixed != 0, nullptr, nullptr) +
+         (o.compact && !o.mixed && !o.coupled ? compact_bytes(graph->n, graph->nnz, s) : 0);
+}
+
+// Workspace of ens_cg_noalloc: a file-scope device array, one copy per GPU,
+// held until the process ends and shared by every call on that GPU.  In host
+// code the name is a host-side stand-in, never a device address: kernels
+// and copies get the address hipGetSymbolAddress returns, resolved once per
+// device with that device current.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;  // by device id
+
+static ens_status scratch_ptr(void** out) {
+  int dev = 0;
+  ENS_HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+      return ENS_E_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ENS_OK;
+}
+
+}  // namespace ens
+
+using namespace ens;
+
+extern "C" {
+
+ens_status ens_cg_workspace_bytes(const ens_graph* graph, int32_t s, const ens_cg_opts* opts, size_t* bytes) {
+  ens_status st = check_graph(graph);
+  if (st != ENS_OK) return st;
+  ENS_ARG_CHECK(opts && bytes, "null argument");
+  if (!supported_s(s)) {
+    set_error("ensemble size %d not compiled in", s);
+    return ENS_E_UNSUPPORTED;
+  }
+  *bytes = ws_layout(graph->n, s, opts->mixed != 0, nullptr, nullptr) +
+           (opts->compact && !opts->mixed && !opts->coupled ? compact_bytes(graph->n, graph->nnz, s) : 0);
+  return ENS_OK;
+}
+
+ens_status ens_cg(const ens_graph* graph, int32_t s, const double* values, const float* values32, const double* b,
+                  double* x, const ens_cg_opts* opts, void* workspace, size_t ws_bytes, ens_cg_stat* stats,
+                  hipStream_t stream) {
+  return cg_run(graph, s, values, values32, b, x, opts, workspace, ws_bytes, stats, stream, false);
+}
+
+ens_status ens_cg_noalloc(const ens_graph* graph, int32_t s, const double* values, const float* values32,
+                          const double* b, double* x, const ens_cg_opts* opts, ens_cg_stat* stats,
+                          hipStream_t stream) {
+  // size check first: it needs no device and allocates nothing
+  ens_status st = check_graph(graph);
+  if (st != ENS_OK) return st;
+  ENS_ARG_CHECK(opts, "null options");
+  if (!supported_s(s)) {
+    set_error("ensemble size %d not compiled in", s);
+    return ENS_E_UNSUPPORTED;
+  }
+  const size_t need = cg_ws_need(graph, s, *opts);
+  if (need > kScratchBytes) {
+    set_error("ens_cg_noalloc needs %zu bytes of workspace; its scratch array holds %zu (use ens_cg with a "
+              "caller workspace)", need, kScratchBytes);
+    return ENS_E_NOMEM;
+  }
+  void* ws = nullptr;
+  st = scratch_ptr(&ws);
+  if (st != ENS_OK) return st;
+  ProfPause no_events;
+  return cg_run(graph, s, values, values32, b, x, opts, ws, kScratchBytes, stats, stream, true);
 }
 
 ens_status ens_cg_mg(const ens_graph* graph, int32_t s, const double* values, const float* values32, const double* b,

@@ -102,5 +102,11 @@ bool ensure_side_streams(DeviceCtx* c, int count);
 void prof_begin(int kernel_id, hipStream_t st);
 void prof_end(int kernel_id, hipStream_t st, double bytes);
 void prof_collect();  // resolve pending event pairs (call after a stream sync)
+// While one lives, prof_begin / prof_end do nothing on this thread (for
+// entry points that must not create events).
+struct ProfPause {
+  ProfPause();
+  ~ProfPause();
+};
 
 }  // namespace ens

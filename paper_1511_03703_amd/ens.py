@@ -118,6 +118,8 @@ _SIGS = [
     ("ens_cg_workspace_bytes", _I32, [_GP, _I32, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(_SZ)]),
     ("ens_cg", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _P, _SZ,
                       ctypes.POINTER(ens_cg_stat), _P]),
+    ("ens_cg_noalloc", _I32, [_GP, _I32, _P, _P, _P, _P, ctypes.POINTER(ens_cg_opts), ctypes.POINTER(ens_cg_stat),
+                              _P]),
     ("ens_scalar_cg", _I32, [_GP, _I32, _P, _P, _P, ctypes.POINTER(ens_cg_opts), _I32, _P, _SZ,
                              ctypes.POINTER(ens_cg_stat), _P]),
     ("ens_mg_bytes", _I32, [_I32, _I32, _I32, _I32, ctypes.POINTER(_SZ)]),
@@ -476,6 +478,24 @@ def cg(g: Graph, values, b, x=None, values32=None, opts: ens_cg_opts | None = No
     st = _check(lib().ens_cg(ctypes.byref(gc), s, _ptr(values), _ptr(values32), _ptr(b), _ptr(x),
                              ctypes.byref(opts), _ptr(workspace), workspace.numel(), stats, _stream(stream)),
                 "ens_cg", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
+    return x, _stats_list(stats, s), st
+
+
+CG_NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def cg_noalloc(g: Graph, values, b, x, values32=None, opts: ens_cg_opts | None = None, stream=None):
+    """ens_cg on the library's own scratch array (ens_cg_noalloc): nothing is
+    allocated, x (in: x0, out: the solution) must be given.  Returns (x,
+    stats, status)."""
+    s = values.shape[1]
+    if opts is None:
+        opts = cg_opts()
+    stats = (ens_cg_stat * s)()
+    gc = g.c()
+    st = _check(lib().ens_cg_noalloc(ctypes.byref(gc), s, _ptr(values), _ptr(values32), _ptr(b), _ptr(x),
+                                     ctypes.byref(opts), stats, _stream(stream)),
+                "ens_cg_noalloc", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
     return x, _stats_list(stats, s), st
 
 

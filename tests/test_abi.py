@@ -229,3 +229,26 @@ def test_adam_argument_errors_without_gpu(E):
     assert L.ens_mlp_adam(p, p, p, p, 10, 1, ctypes.c_float(0.0), None) == E.ENS_E_ARG
     # nothing to do: no launch
     assert L.ens_mlp_adam(p, p, p, p, 0, 1, ctypes.c_float(1e-3), None) == E.ENS_OK
+
+
+def test_noalloc_cg_refuses_sizes_beyond_its_scratch_without_gpu(E):
+    # the size check comes before any device call
+    L = E.lib()
+    stats = (E.ens_cg_stat * 32)()
+    opts = E.cg_opts()
+    big = E.ens_graph(2146689, 57066625, 256, 512)       # 128^3 elements
+    st = L.ens_cg_noalloc(ctypes.byref(big), 32, ctypes.c_void_p(256), None, ctypes.c_void_p(512),
+                          ctypes.c_void_p(768), ctypes.byref(opts), stats, None)
+    assert st == E.ENS_E_NOMEM
+    assert b"scratch" in L.ens_last_error()
+    # 64^3 elements: s = 16 fits the 256 MiB, s = 32 does not
+    gc = E.ens_graph(274625, 7189057, 256, 512)
+    b = ctypes.c_size_t()
+    for s, fits in ((16, True), (32, False)):
+        assert L.ens_cg_workspace_bytes(ctypes.byref(gc), s, ctypes.byref(opts), ctypes.byref(b)) == 0
+        assert (b.value <= E.CG_NOALLOC_SCRATCH_BYTES) == fits, (s, b.value)
+    st = L.ens_cg_noalloc(ctypes.byref(gc), 32, ctypes.c_void_p(256), None, ctypes.c_void_p(512),
+                          ctypes.c_void_p(768), ctypes.byref(opts), stats, None)
+    assert st == E.ENS_E_NOMEM
+    assert L.ens_cg_noalloc(ctypes.byref(gc), 5, ctypes.c_void_p(256), None, ctypes.c_void_p(512),
+                            ctypes.c_void_p(768), ctypes.byref(opts), stats, None) == E.ENS_E_UNSUPPORTED
