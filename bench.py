@@ -72,6 +72,50 @@ def load_traffic(kernel_name):
     return ent.get("bytes_per_launch")
 
 
+def host_env():
+    """Where the numbers come from: the host's CPUs (model, count, the share
+    this process may use, the OpenMP threads the oracle gets), the ROCm
+    toolchain the library was compiled with, and the HIP runtime actually
+    mapped into this process (torch loads its own libamdhip64, whose soname
+    the library's dependency then resolves to)."""
+    import ctypes
+
+    import torch
+
+    env = {"device": torch.cuda.get_device_name(0), "torch": torch.__version__, "torch_hip": torch.version.hip,
+           "nproc": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0)),
+           "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            env["cpu_model"] = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        env["cpu_model"] = None
+    try:
+        with open("/opt/rocm/.info/version") as fh:
+            env["rocm_toolchain"] = fh.read().strip()
+    except OSError:
+        env["rocm_toolchain"] = None
+    with open("/proc/self/maps") as fh:
+        libs = sorted({l.split()[-1] for l in fh if "libamdhip64" in l})
+    env["hip_runtime_lib"] = libs
+    try:
+        v = ctypes.c_int()
+        ctypes.CDLL("libamdhip64.so.7").hipRuntimeGetVersion(ctypes.byref(v))
+        env["hip_runtime_version"] = v.value
+    except OSError:
+        env["hip_runtime_version"] = None
+    return env
+
+
+def oracle_threads(requested):
+    """OpenMP threads of the CPU baseline: the requested count, or (0) the
+    threads the oracle's OpenMP runtime offers this process, at most 32."""
+    if requested > 0:
+        return requested
+    from oracle import oracle as orc
+    return max(1, min(orc.max_threads(), 32))
+
+
 def cpu_baseline(N, M, sigma, rtol, xi, iters_fp64, cap_iters, L=1.0, kappa0=1.0, f=1.0):
     """The FP64 oracle (graph, KL, assembly, Jacobi-CG) on the rows of `xi` in
     parallel, one sample per OpenMP thread, on the host cores.  Bounded: each
@@ -114,7 +158,8 @@ def main():
                     help="learned: the step count is split into this many + 1 equal stages, lr halved per stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true", help="skip the FP64 / scalar comparison runs")
-    ap.add_argument("--cpu-threads", type=int, default=4)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="CPU oracle threads and samples (0: what OpenMP offers the process, at most 32)")
     ap.add_argument("--cpu-cap-iters", type=int, default=25)
     ap.add_argument("--inner-rtol", type=float, default=None,
                     help="refinement inner tolerance (default: 1e-4 with multigrid, 1e-5 with Jacobi, the measured "
@@ -297,7 +342,7 @@ def run_solve(args):
         # longest one are not recorded)
         "assembly_ms_per_step": round(pa["total_ms"] / max(args.steps, 1), 3),
         "step_ms": {"median": float(np.median(head_steps)), "min": min(head_steps), "max": max(head_steps)},
-        "env": {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__},
+        "env": host_env(),
     }
     x_head = x.clone() if not args.no_context else None
     if use_mg and not args.no_context:
@@ -440,7 +485,7 @@ def run_solve(args):
 
     if not args.no_cpu_baseline and use_mg:
         from oracle import oracle as orc
-        threads = min(args.cpu_threads, w.s)
+        threads = min(oracle_threads(args.cpu_threads), w.s)
         log("CPU oracle baseline (multigrid PCG) ...")
         t0 = time.perf_counter()
         _, it, _, _, _ = orc.ens_mg_pcg(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, w.xi()[:threads], rtol=w.rtol)
@@ -453,7 +498,7 @@ def run_solve(args):
             "seconds_measured": round(tc, 2)}
     elif not args.no_cpu_baseline:
         its = iters_fp64 if iters_fp64 is not None else [300] * w.s
-        threads = min(args.cpu_threads, w.s)
+        threads = min(oracle_threads(args.cpu_threads), w.s)
         log("CPU oracle baseline ...")
         t0 = time.perf_counter()
         v, used, _, t_set, t_cg = cpu_baseline(w.N, w.M, w.sigma, w.rtol, w.xi()[:threads], its,
@@ -466,6 +511,7 @@ def run_solve(args):
                        f"{[int(i) for i in its[:threads]]}"),
             "seconds_measured": round(time.perf_counter() - t0, 2)}
 
+    out.setdefault("env", host_env())
     print(json.dumps(out), flush=True)
 
 
@@ -613,10 +659,11 @@ def run_batch(args):
         t0 = time.perf_counter()
         per_mesh = {}
         used_max = 0
+        nth = oracle_threads(args.cpu_threads)
         for N in W.BATCH_MESHES:
             its = iters_by_mesh[int(N)] or [200]
-            xi_c = W.draw_xi(W.BATCH_XI_SEED, args.cpu_threads, M)
-            med = [int(np.median(its))] * args.cpu_threads
+            xi_c = W.draw_xi(W.BATCH_XI_SEED, nth, M)
+            med = [int(np.median(its))] * nth
             _, used, full, _, _ = cpu_baseline(int(N), M, sigma, rtol, xi_c, med, args.cpu_cap_iters)
             per_mesh[int(N)] = float(np.mean(full))
             used_max = max(used_max, used)
@@ -624,11 +671,12 @@ def run_batch(args):
         t_cpu = sum(s * per_mesh[int(N)] for N in meshes) / used_max
         out["cpu_baseline"] = {
             "value": G * s / t_cpu, "unit": "samples/s", "cores": used_max, "kind": "oracle",
-            "sample": (f"{args.cpu_threads} samples per mesh size, one per OpenMP thread, Jacobi-CG capped at "
+            "sample": (f"{nth} samples per mesh size, one per OpenMP thread, Jacobi-CG capped at "
                        f"{args.cpu_cap_iters} iterations and scaled to each mesh's median GPU FP64 iteration "
                        f"count; per-sample seconds {{N: s}} = "
                        f"{ {k: round(v, 2) for k, v in per_mesh.items()} }, summed over the 256 x s samples"),
             "seconds_measured": round(time.perf_counter() - t0, 2)}
+    out.setdefault("env", host_env())
     print(json.dumps(out), flush=True)
 
 
@@ -788,7 +836,7 @@ def run_learned(args):
     if not args.no_cpu_baseline:
         log("CPU oracle baseline ...")
         t0 = time.perf_counter()
-        threads = min(args.cpu_threads, s)
+        threads = min(oracle_threads(args.cpu_threads), s)
         v, used, _, t_set, t_cg = cpu_baseline(w.N, M, w.sigma, rtol, test_xi[:threads], it_zero[:threads],
                                                args.cpu_cap_iters, w.L, w.kappa0, w.f)
         out["cpu_baseline"] = {
@@ -797,6 +845,7 @@ def run_learned(args):
                        f"one per OpenMP thread; set-up {t_set:.1f} s, CG capped at {args.cpu_cap_iters} "
                        f"iterations ({t_cg:.1f} s), scaled to the GPU zero-guess iteration counts"),
             "seconds_measured": round(time.perf_counter() - t0, 2)}
+    out.setdefault("env", host_env())
     print(json.dumps(out), flush=True)
 
 
@@ -899,7 +948,7 @@ def run_mg(args):
                                                        "reference": "GPU FP64 multigrid CG to 1e-12"}}
     if not args.no_cpu_baseline:
         from oracle import oracle as orc
-        threads = min(args.cpu_threads, w.s)
+        threads = min(oracle_threads(args.cpu_threads), w.s)
         log("CPU oracle baseline (multigrid PCG) ...")
         t0 = time.perf_counter()
         _, it, rr, st_o, _ = orc.ens_mg_pcg(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, w.xi()[:threads], rtol=w.rtol)
@@ -911,6 +960,7 @@ def run_mg(args):
                        f"available): hierarchy set-up and multigrid PCG to {w.rtol:g} in full, "
                        f"iterations {[int(v) for v in it]}"),
             "seconds_measured": round(tc, 2)}
+    out.setdefault("env", host_env())
     print(json.dumps(out), flush=True)
 
 
@@ -1025,7 +1075,7 @@ def run_newton(args):
         # Jacobian, GMRES, update, and the next residual) of `threads`
         # samples, scaled by the Newton steps the samples take.
         from oracle import oracle as orc
-        threads = min(args.cpu_threads, w.s)
+        threads = min(oracle_threads(args.cpu_threads), w.s)
         log("CPU oracle baseline (first Newton step) ...")
         t0 = time.perf_counter()
         _, ni, li, rr, st_o, _ = orc.ens_newton(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, W.NEWTON_ALPHA,
@@ -1046,6 +1096,7 @@ def run_newton(args):
                        + (" (an overestimate of the oracle's speed: later steps solve to tighter tolerances)"
                           if ew else "")),
             "seconds_measured": round(tc, 2)}
+    out.setdefault("env", host_env())
     print(json.dumps(out), flush=True)
 
 

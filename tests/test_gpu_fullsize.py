@@ -9,6 +9,10 @@ configuration bench.py times, on samples the oracle can afford one by one.
       oracle assembles each sample from scratch and checks the true FP64
       residual of both GPU solutions (<= 1e-8) and the assembled values
       (1e-13).
+  128^3, s = 32, FP64 CG with the FP64 multigrid cycle to 1e-8 (coarse
+      levels rediscretized; and Galerkin): samples 0 and 31 (0) against the
+      oracle's MG-PCG at the GPU's iteration counts (relative 1e-9), its own
+      counts within +-1, the true residual <= 1e-8.
   The one-sample baseline at 64^3 (the mid workload's 16 samples in the
       sample-major layout, 16 lanes per row as timed): samples 0 and 15
       against the oracle at the GPU's iteration counts (relative 1e-9), its
@@ -126,6 +130,47 @@ def test_headline_workload_refinement(E, orc):
             assert abs(res - stats[e]["rel_res"]) <= 1e-3 * res
             assert res_mg <= w.rtol * (1 + 1e-6)
             assert abs(res_mg - stats_mg[e]["rel_res"]) <= 1e-3 * res_mg
+
+
+@pytest.mark.parametrize("galerkin", [False, True])
+def test_headline_fp64_multigrid_equal_iterations(E, orc, galerkin):
+    # bench.py --workload mg --mg-fp64: FP64 CG with the FP64 V-cycle (levels
+    # 128 .. 4) on the headline samples to 1e-8.  Samples 0 and 31 (sample 0
+    # alone for Galerkin levels) against the oracle's MG-PCG with the same
+    # kind of coarse levels at the GPU's iteration counts (relative 1e-9),
+    # the oracle's own counts within +-1, the true residual <= 1e-8.
+    w = HEADLINE
+    xi = w.xi()
+    g = E.graph_build(w.N)
+    kl = E.kl_build(w.N, w.M, w.L)
+    xt = torch.as_tensor(xi, device="cuda")
+    vals = torch.empty((w.nnz, w.s), dtype=torch.float64, device="cuda")
+    rhs = torch.empty((w.n, w.s), dtype=torch.float64, device="cuda")
+    mg = E.Multigrid(w.N, w.M, w.s, L=w.L)
+    mg.assemble_setup(g, kl, xt, w.sigma, vals, rhs, kappa0=w.kappa0, f=w.f, galerkin=galerkin)
+    x, stats, st = E.cg_mg(g, vals, rhs, mg, opts=E.cg_opts(rtol=w.rtol, check_every=4))
+    assert st == E.ENS_OK
+    check = [0] if galerkin else [0, w.s - 1]
+    iters = np.array([stats[e]["iters"] for e in check], np.int32)
+    xg = x.cpu().numpy()[:, check]
+    print(f"GPU done (galerkin={galerkin}): iterations {[t['iters'] for t in stats]}", flush=True)
+    del vals, rhs, mg, x
+    torch.cuda.empty_cache()
+    sub = np.ascontiguousarray(xi[check])
+    xo, _, _, _, _ = orc.ens_mg_pcg(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, sub, fixed_iters=iters,
+                                    galerkin=galerkin)
+    _, ito, rro, sto, _ = orc.ens_mg_pcg(w.N, w.M, w.L, w.kappa0, w.sigma, w.f, sub, rtol=w.rtol,
+                                         galerkin=galerkin)
+    rp, ci = orc.graph(w.N)
+    for j, e in enumerate(check):
+        v, b = _oracle_sample(orc, rp, ci, w, xi[e])
+        res = np.linalg.norm(b - orc.spmv(rp, ci, v, xg[:, j])) / np.linalg.norm(b)
+        err = _rel(xg[:, j], xo[:, j])
+        print(f"sample {e}: GPU {iters[j]} iterations, oracle {ito[j]}; rel. error at equal count {err:.2e}; "
+              f"true residual {res:.3e}", flush=True)
+        assert err <= 1e-9
+        assert abs(int(ito[j]) - int(iters[j])) <= 1 and sto[j] == 0
+        assert res <= w.rtol * (1 + 1e-6)
 
 
 def test_newton_workload(E, orc):
