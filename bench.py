@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="default 5 (solve workloads), 1 (batch, learned)")
     ap.add_argument("--warmup", type=int, default=None, help="default 1 (solve workloads), 0 (batch, learned)")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "mid", "small", "batch", "learned", "mg", "newton"])
+                    choices=["headline", "mid", "small", "batch", "learned", "mg", "newton", "assembly"])
     ap.add_argument("--pool-gib", type=float, default=192.0, help="batch: resident pool size")
     ap.add_argument("--batch-s", type=int, default=0, help="batch: fix s (skip the autotuner)")
     ap.add_argument("--batch-tile", type=int, default=4, help="batch: tile when --batch-s is given")
@@ -194,7 +194,27 @@ def main():
         return run_mg(args)
     if args.workload == "newton":
         return run_newton(args)
+    if args.workload == "assembly":
+        return run_assembly(args)
     return run_solve(args)
+
+
+def calibration_copy(args):
+    """One plain device copy of --calib-copy-mb MiB (k_copy16: that many bytes
+    read and written), whose FETCH_SIZE / WRITE_SIZE counters scale the
+    counters of the kernels profiled in the same run."""
+    if args.calib_copy_mb <= 0:
+        return
+    import torch
+
+    from paper_1511_03703_amd import ens
+    nb = args.calib_copy_mb << 20
+    src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    ens.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    log(f"calibration copy of {nb} bytes done")
+    del src, dst
 
 
 def run_solve(args):
@@ -222,14 +242,7 @@ def run_solve(args):
                        compact=args.compact and not w.mixed)
     ws = torch.empty(ens.cg_workspace_bytes(g, w.s, opts), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
-    if args.calib_copy_mb > 0:
-        nb = args.calib_copy_mb << 20
-        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        ens.stream_copy(src, dst)
-        torch.cuda.synchronize()
-        log(f"calibration copy of {nb} bytes done")
-        del src, dst
+    calibration_copy(args)
 
     use_mg = args.precond == "mg"
     mg = ens.Multigrid(w.N, w.M, w.s, fp32=w.mixed, L=w.L, device=dev) if use_mg else None
@@ -960,6 +973,87 @@ def run_mg(args):
                        f"available): hierarchy set-up and multigrid PCG to {w.rtol:g} in full, "
                        f"iterations {[int(v) for v in it]}"),
             "seconds_measured": round(tc, 2)}
+    out.setdefault("env", host_env())
+    print(json.dumps(out), flush=True)
+
+
+def assembly_bytes(n, nnz, s, fp64=True, fp32=True, rhs=True, dinv32=False):
+    """Algorithmic bytes written by one ensemble assembly: the [nnz][s]
+    values (FP64 and / or FP32), the [n][s] load vector, an FP32 D^-1 of a
+    fused multigrid set-up; the inputs (KL table, y, row offsets) are
+    negligible."""
+    return nnz * s * (8.0 * fp64 + 4.0 * fp32) + n * s * (8.0 * rhs + 4.0 * dinv32)
+
+
+def run_assembly(args):
+    """The two assembly kernels at the headline size (128^3, s = 32, the
+    headline samples), each timed alone: the linear ensemble assembly of A
+    (FP64 and FP32 copy) and f (ens_assemble, Alg. assembly), and the
+    nonlinear residual with the FP32 Jacobian (ens_nl_assemble, as each
+    Newton step of the newton workload forms them) at a seeded state u."""
+    import numpy as np
+    import torch
+
+    from paper_1511_03703_amd import ens
+    import workloads as W
+
+    w = W.HEADLINE
+    dev = "cuda"
+    torch.cuda.set_device(0)
+    g = ens.graph_build(w.N)
+    kl = ens.kl_build(w.N, w.M, w.L)
+    xi = torch.as_tensor(w.xi(), device=dev)
+    vals = torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
+    v32 = torch.empty((w.nnz, w.s), dtype=torch.float32, device=dev)
+    rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
+    prob = ens.nl_problem(w.M, w.sigma, W.NEWTON_ALPHA, W.NEWTON_BETA, W.NEWTON_VEL, L=w.L, kappa0=w.kappa0, f=w.f)
+    u = torch.as_tensor(W.draw_vector(1090, (w.n, w.s), 0.0, 0.05), device=dev)
+    F = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    calibration_copy(args)
+
+    def lin():
+        ens.assemble(g, kl, xi, w.M, w.sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, values32=v32, rhs=rhs)
+
+    def nonlin():
+        ens.nl_assemble(g, kl, xi, prob, u, want_jac=False, want_jac32=True, values32=v32, F=F)
+
+    out_k = {}
+    for name, fn, kid in (("assemble", lin, ens.K_ASSEMBLE), ("nl_assemble", nonlin, ens.K_NL_ASSEMBLE)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ens.prof_enable(True)
+        ens.prof_reset()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ens.prof_enable(False)
+        pq = ens.prof_query(kid)
+        avg_ms = pq["total_ms"] / max(pq["launches"], 1)
+        by = pq["bytes"] / max(pq["launches"], 1)
+        out_k[name] = {"ms_per_launch": round(avg_ms, 4), "launches": pq["launches"],
+                       "bytes_per_launch": round(by), "GBs": round(by / (avg_ms * 1e-3) / 1e9, 1),
+                       "wall_ms_per_step": round(el / args.steps * 1e3, 3)}
+        log(f"{name}: {avg_ms:.3f} ms per launch, {by / (avg_ms * 1e-3) / 1e9:.1f} GB/s")
+    a = out_k["assemble"]
+    out = {
+        "metric": "ensemble Q1 assembly of A (FP64 + FP32 copy) and f at 128^3, s=32: assembled samples/s",
+        "value": round(w.s / (a["ms_per_launch"] * 1e-3), 3), "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": a["ms_per_launch"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "q1_128cube_s32_assembly", "mesh": f"{w.N}^3 Q1 hexahedra", "n": w.n, "nnz": w.nnz,
+                   "s": w.s, "M": w.M, "sigma": w.sigma, "seed": w.seed,
+                   "nl": {"alpha": W.NEWTON_ALPHA, "beta": W.NEWTON_BETA, "u": "U[0, 0.05] seed 1090",
+                          "jacobian": "FP32"}},
+        "roofline": {"bound": "hbm", "achieved": a["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(a["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_assemble_tile<32,0,false>", "bytes_per_launch": a["bytes_per_launch"],
+                     "avg_launch_ms": a["ms_per_launch"], "launches": a["launches"]},
+        "kernels": out_k,
+    }
     out.setdefault("env", host_env())
     print(json.dumps(out), flush=True)
 

@@ -101,16 +101,110 @@ __device__ inline void kl_points(const double* __restrict__ tab, const int32_t* 
   for (int q = 0; q < 8; ++q) kq[q] = kappa0 + kq[q];
 }
 
-// Workgroup index -> (tile, sample group) of the TX x TZ node patches of
-// one y-plane.  Workgroups are dealt to the 8 XCDs round-robin by index; the
-// G sample groups of one tile take indices 8 apart (same XCD, dispatched
-// together) so their partial writes of each row's sample ensemble meet in
-// one L2.
-template <int TX, int TZ, int G>
-__device__ inline void tile_decode(int N, int64_t bid, int64_t* tile_id, int* sg, int* x0, int* y, int* z0) {
+// Node tiles of the assemblies: a workgroup owns R = TX x TY x TZ nodes
+// (one lane per row and sample); the elements touching the tile form an
+// EX x EY x EZ block.
+template <int Rv, int TYv>
+struct AsmTile {
+  static constexpr int R = Rv;
+  static constexpr int TY = TYv, TZ = 4, TX = R / (TY * TZ);
+  static constexpr int EX = TX + 1, EY = TY + 1, EZ = TZ + 1, NE = EX * EY * EZ;
+  static_assert(TX * TY * TZ == R, "tile shape");
+};
+
+// LDS slot of Gauss point q of tile element le for sample sb: the 8 points
+// of an element are stored in the order q ^ (le & 7), so that the lanes of a
+// wavefront, which read the same q of consecutive elements, hit different
+// banks without padding the rows.
+template <int SB>
+__device__ inline int kslot(int le, int q, int sb) {
+  return ((le * 8 + (q ^ (le & 7))) * SB) + sb;
+}
+
+// LDS doubles of a tile's 1D KL factors: for each of the M modes its 1D
+// eigenfunction at the 2 Gauss abscissae of each element column along x, y
+// and z of the tile's element block.
+template <int EX, int EY, int EZ>
+__host__ __device__ constexpr int tab_doubles(int M) { return M * 2 * (EX + EY + EZ); }
+
+// Phase 1 of the tiled assemblies: the coefficient at the 8 Gauss points of
+// every element of the tile's EX x EY x EZ element block (origin ex0, ey0,
+// ez0) for the SB samples e0.., times `scale`, into s_k[kslot(le, q, sb)].
+// The 1D factors of the tile are staged in s_tab first (sample-independent,
+// read from the KL table once per workgroup), and each lane keeps the
+// coefficients c_m = sigma sqrt(lambda_m) y_m of its one sample in
+// registers (the NT lanes are a multiple of SB, so a lane's items all have
+// the same sample).  The sum follows kl_points operation by operation, so the values
+// are bitwise those of kl_points.  Ends with a barrier.
+template <int NT, int SB, int EX, int EY, int EZ, bool SCALED>
+__device__ inline void tile_coefficients(int N, const double* __restrict__ kl_sqrt_lam,
+                                         const int32_t* __restrict__ kl_triple, const double* __restrict__ kl_phi,
+                                         int M, double kappa0, double sigma, const double* __restrict__ xi, int e0,
+                                         int ex0, int ey0, int ez0, double scale, double* s_tab, double* s_k) {
+  static_assert(NT % SB == 0, "a lane's items must share one sample");
+  constexpr int NE = EX * EY * EZ;
+  const int64_t two_n = 2 * (int64_t)N;
+  double* s_x = s_tab;               // [M][EX][2]
+  double* s_y = s_tab + M * 2 * EX;  // [M][EY][2]
+  double* s_z = s_y + M * 2 * EY;    // [M][EZ][2]
+  for (int t = threadIdx.x; t < M * 2 * (EX + EY + EZ); t += NT) {
+    int m, l, q, axis, e0a, ext;
+    if (t < M * 2 * EX) {
+      m = t / (2 * EX), l = (t / 2) % EX, q = t & 1, axis = 0, e0a = ex0, ext = EX;
+    } else if (t < M * 2 * (EX + EY)) {
+      const int u = t - M * 2 * EX;
+      m = u / (2 * EY), l = (u / 2) % EY, q = u & 1, axis = 1, e0a = ey0, ext = EY;
+    } else {
+      const int u = t - M * 2 * (EX + EY);
+      m = u / (2 * EZ), l = (u / 2) % EZ, q = u & 1, axis = 2, e0a = ez0, ext = EZ;
+    }
+    (void)ext;
+    const int el = e0a + l;
+    s_tab[t] = (el >= 0 && el < N) ? kl_phi[kl_triple[3 * m + axis] * two_n + 2 * el + q] : 0.0;
+  }
+  const int sb = threadIdx.x % SB;
+  double c[kAsmMaxM];
+#pragma unroll
+  for (int m = 0; m < kAsmMaxM; ++m) c[m] = m < M ? sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + sb) * M + m] : 0.0;
+  __syncthreads();
+  for (int p = threadIdx.x; p < NE * SB; p += NT) {
+    const int le = p / SB;
+    const int lx = le % EX, ly = (le / EX) % EY, lz = le / (EX * EY);
+    const int ex = ex0 + lx, ey = ey0 + ly, ez = ez0 + lz;
+    if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
+    double kq[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) kq[q] = 0.0;
+#pragma unroll
+    for (int m = 0; m < kAsmMaxM; ++m) {
+      if (m >= M) break;
+      const double fx[2] = {s_x[(m * EX + lx) * 2], s_x[(m * EX + lx) * 2 + 1]};
+      const double fy[2] = {s_y[(m * EY + ly) * 2], s_y[(m * EY + ly) * 2 + 1]};
+      const double fz[2] = {s_z[(m * EZ + lz) * 2], s_z[(m * EZ + lz) * 2 + 1]};
+      double yz[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) yz[t] = c[m] * (fy[t & 1] * fz[t >> 1]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double k = kappa0 + kq[q];
+      s_k[kslot<SB>(le, q, sb)] = SCALED ? k * scale : k;
+    }
+  }
+  __syncthreads();
+}
+
+// Workgroup index -> (tile, sample group, tile origin).  Workgroups are
+// dealt to the 8 XCDs round-robin by index; the G sample groups of one tile
+// take indices 8 apart (same XCD, dispatched together) so their partial
+// writes of each row's sample ensemble meet in one L2.
+template <int TX, int TY, int TZ, int G>
+__device__ inline void tile_decode(int N, int64_t bid, int64_t* tile_id, int* sg, int* x0, int* y0, int* z0) {
   const int n1 = N + 1;
-  const int ntx = (n1 + TX - 1) / TX, ntz = (n1 + TZ - 1) / TZ;
-  const int64_t tiles = (int64_t)ntx * ntz * n1;
+  const int ntx = (n1 + TX - 1) / TX, nty = (n1 + TY - 1) / TY, ntz = (n1 + TZ - 1) / TZ;
+  const int64_t tiles = (int64_t)ntx * ntz * nty;
   int64_t tile;
   if (G > 1 && (bid / (8 * G)) < tiles / 8) {
     const int64_t blk = bid / (8 * G), rem = bid % (8 * G);
@@ -125,19 +219,23 @@ __device__ inline void tile_decode(int N, int64_t bid, int64_t* tile_id, int* sg
   *x0 = (int)(tile % ntx) * TX;
   tile /= ntx;
   *z0 = (int)(tile % ntz) * TZ;
-  *y = (int)(tile / ntz);
+  *y0 = (int)(tile / ntz) * TY;
 }
 
 // Ensemble assembly (Alg. "assembly" made atomic-free by row ownership): a
-// workgroup owns a TX x TZ patch of nodes in one y-plane for SB of the
-// samples.  It first evaluates the coefficient (times h/8) at the 8 Gauss
-// points of each of the (TX+1) x 2 x (TZ+1) elements touching the patch,
-// once per element and sample, into LDS; then each (row, sample) lane
-// gathers its (up to 8) elements from LDS in ascending element id and adds
-// the element rows in that fixed order, so the sums are deterministic and
-// the coefficient is evaluated about a third as often as by a lane per row
-// alone.  LDS rows are padded to SB+1 samples so that neighbouring rows of
-// a wavefront read alternate bank halves.
+// workgroup owns a 4 x 2 x 4 block of nodes for all S samples (32 S lanes,
+// one per row and sample, sample fastest).  It first evaluates the
+// coefficient (times h/8) at the 8 Gauss points of each of the 5 x 3 x 5
+// elements touching the block, once per element and sample, into LDS
+// (153.6 KB for s = 32; the Gauss points of an element in a swizzled order
+// instead of padded rows); then each (row, sample) lane gathers its (up to
+// 8) elements from LDS in ascending element id and adds the element rows in
+// that fixed order, so the sums are deterministic and the coefficient is
+// evaluated 2.3 times per row instead of 8.  A wavefront holds whole sample
+// ensembles of its rows, so every store of a matrix entry writes full
+// 128-byte lines (s = 32: two FP64 lines, one FP32 line); split over
+// workgroups of fewer samples, the partial lines of the FP32 copy alone took
+// longer than the whole assembly does now.
 // BND (fused multigrid set-up of this level): 0 none; 1 D^-1 in FP32 and
 // the Gershgorin bound of the FP32 values; 2 D^-1 and the bound of the FP64
 // values.  Each lane forms its row's sum_j |a_ij| / a_ii in ascending entry
@@ -147,65 +245,55 @@ __device__ inline void tile_decode(int N, int64_t bid, int64_t* tile_id, int* sg
 // of the nonlinear problem's Jacobian, Eq. fenl_lin_sys with beta = 0):
 // every element row also gets alpha (h^2/8) C_ab, C_ab = sum_q N_a (v.dN_b)
 // one 8x8 table per launch.
-template <int S, int SB, int BND, bool ADV>
-__global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __restrict__ kl_sqrt_lam,
-                                                        const int32_t* __restrict__ kl_triple,
-                                                        const double* __restrict__ kl_phi, int M, double kappa0,
-                                                        double sigma, double fsrc, double alpha, double vx,
-                                                        double vy, double vz, const double* __restrict__ xi,
-                                                        const int32_t* __restrict__ row_ptr,
-                                                        double* __restrict__ values, float* __restrict__ values32,
-                                                        double* __restrict__ rhs, void* __restrict__ dinv,
-                                                        double* __restrict__ bpart) {
-  constexpr int R = 256 / SB;  // rows per workgroup
-  constexpr int TZ = 4, TX = R / TZ;
-  constexpr int EX = TX + 1, NE = EX * 2 * (TZ + 1);
-  constexpr int G = S / SB;    // sample groups
-  constexpr int PS = SB + 1;   // padded sample stride in LDS
-  static_assert(R % TZ == 0 && S % SB == 0, "tile shape");
-  __shared__ double s_cm[SB * kAsmMaxM];
-  __shared__ double s_k[NE * 8 * PS];  // [element][q][sample]
-  __shared__ double s_adv[ADV ? 64 : 1];
+template <int S, int BND, bool ADV>
+__global__ __launch_bounds__(32 * S) void k_assemble_tile(int N, const double* __restrict__ kl_sqrt_lam,
+                                                           const int32_t* __restrict__ kl_triple,
+                                                           const double* __restrict__ kl_phi, int M, double kappa0,
+                                                           double sigma, double fsrc, double alpha, double vx,
+                                                           double vy, double vz, const double* __restrict__ xi,
+                                                           const int32_t* __restrict__ row_ptr,
+                                                           double* __restrict__ values, float* __restrict__ values32,
+                                                           double* __restrict__ rhs, void* __restrict__ dinv,
+                                                           double* __restrict__ bpart) {
+  using T = AsmTile<32, 2>;
+  constexpr int SB = S, NT = T::R * S;
+  constexpr int TX = T::TX, TY = T::TY, EX = T::EX, EY = T::EY, NE = T::NE;
+  constexpr int NTAB = tab_doubles<T::EX, T::EY, T::EZ>(kAsmMaxM);
+  static_assert(NT <= NE * 8 * SB && NTAB >= 64, "tile shape");
+  // [kappa at the Gauss points, [element][q][sample] | the tile's 1D KL
+  // factors]; after the coefficients the factor area takes the advection
+  // table, after the row pass the kappa area the per-row bounds
+  __shared__ double s_buf[NE * 8 * SB + NTAB];
+  double* s_k = s_buf;
+  double* s_tab = s_buf + NE * 8 * SB;
+  double* s_adv = s_tab;
   const int n1 = N + 1;
   int64_t tile_id;
-  int sg, x0, y, z0;
-  tile_decode<TX, TZ, G>(N, blockIdx.x, &tile_id, &sg, &x0, &y, &z0);
-  const int e0 = sg * SB;
-  for (int t = threadIdx.x; t < SB * M; t += blockDim.x) {
-    const int ee = t / M, m = t % M;
-    s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + ee) * M + m];
-  }
-  if (ADV && threadIdx.x < 64) {
-    const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
-    double c = 0.0;
-    for (int q = 0; q < 8; ++q)
-      c += kQ1.N[q][a] * (vx * kQ1.dN[q][b][0] + vy * kQ1.dN[q][b][1] + vz * kQ1.dN[q][b][2]);
-    s_adv[threadIdx.x] = c;
-  }
-  __syncthreads();
+  int sg, x0, y0, z0;
+  tile_decode<TX, TY, T::TZ, 1>(N, blockIdx.x, &tile_id, &sg, &x0, &y0, &z0);
+  const int e0 = 0;
   const double h = 1.0 / (double)N;
-  const double wscale = h * 0.125;
-  const int64_t two_n = 2 * (int64_t)N;
-  for (int p = threadIdx.x; p < NE * SB; p += blockDim.x) {
-    const int le = p / SB, sb = p % SB;
-    const int lx = le % EX, ly = (le / EX) % 2, lz = le / (2 * EX);
-    const int ex = x0 - 1 + lx, ey = y - 1 + ly, ez = z0 - 1 + lz;
-    if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
-    double kq[8];
-    kl_points(kl_phi, kl_triple, s_cm + sb * M, M, two_n, ex, ey, ez, kappa0, kq);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) s_k[(le * 8 + q) * PS + sb] = kq[q] * wscale;
+  tile_coefficients<NT, SB, EX, EY, T::EZ, true>(N, kl_sqrt_lam, kl_triple, kl_phi, M, kappa0, sigma, xi, e0,
+                                                  x0 - 1, y0 - 1, z0 - 1, h * 0.125, s_tab, s_k);
+  if (ADV) {
+    if (threadIdx.x < 64) {
+      const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
+      double c = 0.0;
+      for (int q = 0; q < 8; ++q)
+        c += kQ1.N[q][a] * (vx * kQ1.dN[q][b][0] + vy * kQ1.dN[q][b][1] + vz * kQ1.dN[q][b][2]);
+      s_adv[threadIdx.x] = c;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   const int r = threadIdx.x / SB, sb = threadIdx.x % SB;
-  const int rx = r % TX, rz = r / TX;
-  const int ii = x0 + rx, jj = y, kk = z0 + rz;
-  const bool live = ii <= N && kk <= N;
+  const int rx = r % TX, ry = (r / TX) % TY, rz = r / (TX * TY);
+  const int ii = x0 + rx, jj = y0 + ry, kk = z0 + rz;
+  const bool live = ii <= N && jj <= N && kk <= N;
   if (!BND && !live) return;
   double qrow = 0.0;  // this row's Gershgorin ratio (BND)
-  if (live) {
   const int e = e0 + sb;
+  if (live) {
   const int64_t row = (int64_t)ii + n1 * ((int64_t)jj + (int64_t)n1 * kk);
 
   double acc[27];
@@ -222,10 +310,10 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
         if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
         ++nelem;
         const int ai = (-ex_off) + 2 * (-ey_off) + 4 * (-ez_off);
-        const int le = (rx + 1 + ex_off) + EX * ((1 + ey_off) + 2 * (rz + 1 + ez_off));
+        const int le = (rx + 1 + ex_off) + EX * ((ry + 1 + ey_off) + EY * (rz + 1 + ez_off));
         double kq[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) kq[q] = s_k[(le * 8 + q) * PS + sb];
+        for (int q = 0; q < 8; ++q) kq[q] = s_k[kslot<SB>(le, q, sb)];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
           const int dx = ex_off + (b & 1), dy = ey_off + ((b >> 1) & 1), dz = ez_off + ((b >> 2) & 1);
@@ -271,16 +359,17 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
   if (BND) qrow = sabs / dg;
   }
   if (BND) {
-    __shared__ double s_q[256];
+    __syncthreads();  // every lane is done with s_k
+    double* s_q = s_k;
     s_q[threadIdx.x] = qrow;
     __syncthreads();
     if (threadIdx.x < SB) {
       double m = 0.0;
-      for (int rr = 0; rr < R; ++rr) {
+      for (int rr = 0; rr < T::R; ++rr) {
         const double q = s_q[rr * SB + threadIdx.x];
         m = q > m ? q : m;
       }
-      bpart[tile_id * S + e0 + threadIdx.x] = m;
+      bpart[tile_id * S + threadIdx.x] = m;
     }
   }
 }
@@ -303,58 +392,48 @@ __global__ __launch_bounds__(256) void k_assemble_tile(int N, const double* __re
 // boundary columns of interior rows stored as zeros; load (optional) = the
 // source part of F.
 template <int S, int SB, bool JAC>
-__global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __restrict__ kl_sqrt_lam,
-                                                      const int32_t* __restrict__ kl_triple,
-                                                      const double* __restrict__ kl_phi, int M, double kappa0,
-                                                      double sigma, double fsrc, double alpha, double beta, double vx,
-                                                      double vy, double vz, const double* __restrict__ xi,
-                                                      const int32_t* __restrict__ row_ptr,
-                                                      const double* __restrict__ u, double* __restrict__ values,
-                                                      float* __restrict__ values32, double* __restrict__ F,
-                                                      double* __restrict__ load) {
-  // the workgroup tiling of k_assemble_tile; the coefficient kept raw
-  // (kappa0 + sum) in LDS, unpadded, for three workgroups per CU
-  constexpr int R = 256 / SB;
-  constexpr int TZ = 4, TX = R / TZ;
-  constexpr int EX = TX + 1, NE = EX * 2 * (TZ + 1);
-  constexpr int G = S / SB;
-  __shared__ double s_cm[SB * kAsmMaxM];
-  __shared__ double s_adv[8][8];  // C_ab = sum_q N_a (v . dN_b)
-  __shared__ double s_k[NE * 8 * SB];
+__global__ __launch_bounds__(32 * SB) void k_nl_assemble(int N, const double* __restrict__ kl_sqrt_lam,
+                                                         const int32_t* __restrict__ kl_triple,
+                                                         const double* __restrict__ kl_phi, int M, double kappa0,
+                                                         double sigma, double fsrc, double alpha, double beta,
+                                                         double vx, double vy, double vz, const double* __restrict__ xi,
+                                                         const int32_t* __restrict__ row_ptr,
+                                                         const double* __restrict__ u, double* __restrict__ values,
+                                                         float* __restrict__ values32, double* __restrict__ F,
+                                                         double* __restrict__ load) {
+  // the workgroup tiling of k_assemble_tile (SB of the S samples of a
+  // 4 x 2 x 4 node block), the coefficient kept raw (kappa0 + sum) in LDS;
+  // after the coefficients the factor area holds the advection table
+  // C_ab = sum_q N_a (v . dN_b)
+  using T = AsmTile<32, 2>;
+  constexpr int NT = T::R * SB, G = S / SB;
+  constexpr int TX = T::TX, TY = T::TY, EX = T::EX, EY = T::EY, NE = T::NE;
+  constexpr int NTAB = tab_doubles<T::EX, T::EY, T::EZ>(kAsmMaxM);
+  static_assert(NTAB >= 64, "tile shape");
+  __shared__ double s_buf[NE * 8 * SB + NTAB];
+  double* s_k = s_buf;
+  double* s_tab = s_buf + NE * 8 * SB;
+  double* s_adv = s_tab;
   int64_t tile_id;
-  int sg, x0, y, z0;
-  tile_decode<TX, TZ, G>(N, blockIdx.x, &tile_id, &sg, &x0, &y, &z0);
+  int sg, x0, y0, z0;
+  tile_decode<TX, TY, T::TZ, G>(N, blockIdx.x, &tile_id, &sg, &x0, &y0, &z0);
   const int e0 = sg * SB;
-  for (int t = threadIdx.x; t < SB * M; t += blockDim.x) {
-    const int ee = t / M, m = t % M;
-    s_cm[t] = sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + ee) * M + m];
-  }
+  tile_coefficients<NT, SB, EX, EY, T::EZ, false>(N, kl_sqrt_lam, kl_triple, kl_phi, M, kappa0, sigma, xi, e0,
+                                                   x0 - 1, y0 - 1, z0 - 1, 1.0, s_tab, s_k);
   if (threadIdx.x < 64) {
     const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
     double c = 0.0;
     for (int q = 0; q < 8; ++q)
       c += kQ1.N[q][a] * (vx * kQ1.dN[q][b][0] + vy * kQ1.dN[q][b][1] + vz * kQ1.dN[q][b][2]);
-    s_adv[a][b] = c;
-  }
-  __syncthreads();
-  const int64_t two_n = 2 * (int64_t)N;
-  for (int p = threadIdx.x; p < NE * SB; p += blockDim.x) {
-    const int le = p / SB, sb = p % SB;
-    const int lx = le % EX, ly = (le / EX) % 2, lz = le / (2 * EX);
-    const int ex = x0 - 1 + lx, ey = y - 1 + ly, ez = z0 - 1 + lz;
-    if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
-    double kq[8];
-    kl_points(kl_phi, kl_triple, s_cm + sb * M, M, two_n, ex, ey, ez, kappa0, kq);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) s_k[(le * 8 + q) * SB + sb] = kq[q];
+    s_adv[threadIdx.x] = c;
   }
   __syncthreads();
 
   const int n1 = N + 1;
   const int rr = threadIdx.x / SB, sbl = threadIdx.x % SB;
-  const int rx = rr % TX, rz = rr / TX;
-  const int ii = x0 + rx, jj = y, kk = z0 + rz;
-  if (ii > N || kk > N) return;
+  const int rx = rr % TX, ry = (rr / TX) % TY, rz = rr / (TX * TY);
+  const int ii = x0 + rx, jj = y0 + ry, kk = z0 + rz;
+  if (ii > N || jj > N || kk > N) return;
   const int e = e0 + sbl;
   const int64_t row = (int64_t)ii + n1 * ((int64_t)jj + (int64_t)n1 * kk);
   const double h = 1.0 / (double)N;
@@ -367,108 +446,117 @@ __global__ __launch_bounds__(256) void k_nl_assemble(int N, const double* __rest
 #pragma unroll
   for (int t = 0; t < 27; ++t) acc[t] = 0.0;
   double fa = 0.0, la = 0.0;
+  const bool bnd_row = (ii == 0 || ii == N || jj == 0 || jj == N || kk == 0 || kk == N);
+  const int64_t start = JAC ? (int64_t)row_ptr[row] : 0;
+  int pos = 0;
+  // the entries of neighbour plane dz are final once the elements below
+  // it are added (plane -1 after the lower elements, planes 0 and +1 after
+  // all): stored then, in entry order, so fewer accumulators stay live
+  auto store_plane = [&](int dz) {
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = ii + dx, y = jj + dy, z = kk + dz;
+        if (x < 0 || y < 0 || z < 0 || x > N || y > N || z > N) continue;
+        const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        double v = acc[slot27];
+        const bool bnd_col = (x == 0 || x == N || y == 0 || y == N || z == 0 || z == N);
+        if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
+        else if (bnd_col) v = 0.0;
+        if (values) values[(start + pos) * S + e] = v;
+        if (values32) values32[(start + pos) * S + e] = (float)v;
+        ++pos;
+      }
+  };
 
 #pragma unroll
-  for (int ez_off = -1; ez_off <= 0; ++ez_off)
+  for (int ez_off = -1; ez_off <= 0; ++ez_off) {
 #pragma unroll
     for (int ey_off = -1; ey_off <= 0; ++ey_off)
 #pragma unroll
       for (int ex_off = -1; ex_off <= 0; ++ex_off) {
-        const int ex = ii + ex_off, ey = jj + ey_off, ez = kk + ez_off;
-        if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
-        const int ai = (-ex_off) + 2 * (-ey_off) + 4 * (-ez_off);
-        const int le = (rx + 1 + ex_off) + EX * ((1 + ey_off) + 2 * (rz + 1 + ez_off));
-        double kq[8];
+          const int ex = ii + ex_off, ey = jj + ey_off, ez = kk + ez_off;
+          if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
+          const int ai = (-ex_off) + 2 * (-ey_off) + 4 * (-ez_off);
+          const int le = (rx + 1 + ex_off) + EX * ((ry + 1 + ey_off) + EY * (rz + 1 + ez_off));
+          double kq[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) kq[q] = s_k[(le * 8 + q) * SB + sbl];
-        double ue[8];
+          for (int q = 0; q < 8; ++q) kq[q] = s_k[kslot<SB>(le, q, sbl)];
+          double ue[8];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int64_t node = (int64_t)(ex + (b & 1)) + n1 * ((int64_t)(ey + ((b >> 1) & 1)) +
-                                                              (int64_t)n1 * (ez + ((b >> 2) & 1)));
-          ue[b] = u[node * S + e];
+          for (int b = 0; b < 8; ++b) {
+            const int64_t node = (int64_t)(ex + (b & 1)) + n1 * ((int64_t)(ey + ((b >> 1) & 1)) +
+                                                                (int64_t)n1 * (ez + ((b >> 2) & 1)));
+            ue[b] = u[node * S + e];
+          }
+          // u_h at the Gauss points and the reaction row
+          // rn_b = sum_q u_q N_a(q) N_b(q) by sum factorisation: N_b(q) is the
+          // product over the axes of the 1D factors l(q_d, b_d), so each is
+          // three contractions of 2 along one axis
+          double uq[8], rnv[8];
+          {
+            double t1[8], t2[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {  // i = qx + 2 by + 4 bz
+              const int qx = i & 1, r = i & 6;
+              t1[i] = kL1[qx][0] * ue[r] + kL1[qx][1] * ue[r + 1];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 bz
+              const int qy = (i >> 1) & 1, r = i & 5;
+              t2[i] = kL1[qy][0] * t1[r] + kL1[qy][1] * t1[r + 2];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 qz
+              const int qz = i >> 2, r = i & 3;
+              uq[i] = kL1[qz][0] * t2[r] + kL1[qz][1] * t2[r + 4];
+            }
+            double w[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              w[q] = uq[q] * kQ1.N[q][ai];
+              la += wr * fsrc * kQ1.N[q][ai];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 bz
+              const int bz = i >> 2, r = i & 3;
+              t1[i] = kL1[0][bz] * w[r] + kL1[1][bz] * w[r + 4];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {  // i = qx + 2 by + 4 bz
+              const int by = (i >> 1) & 1, r = i & 5;
+              t2[i] = kL1[0][by] * t1[r] + kL1[1][by] * t1[r + 2];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {  // i = bx + 2 by + 4 bz
+              const int bx = i & 1, r = i & 6;
+              rnv[i] = kL1[0][bx] * t2[r] + kL1[1][bx] * t2[r + 1];
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            double dg = 0.0;
+            const double rn = rnv[b];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dg += kq[q] * kQ1.G[q][ai][b];
+            const double lin = wd * dg + wa * s_adv[ai * 8 + b];
+            fa += (lin + wb * rn) * ue[b];
+            if (JAC) {
+              const int dx = ex_off + (b & 1), dy = ey_off + ((b >> 1) & 1), dz = ez_off + ((b >> 2) & 1);
+              acc[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] += lin + 2.0 * wb * rn;
+            }
+          }
         }
-        // u_h at the Gauss points and the reaction row
-        // rn_b = sum_q u_q N_a(q) N_b(q) by sum factorisation: N_b(q) is the
-        // product over the axes of the 1D factors l(q_d, b_d), so each is
-        // three contractions of 2 along one axis
-        double uq[8], rnv[8];
-        {
-          double t1[8], t2[8];
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {  // i = qx + 2 by + 4 bz
-            const int qx = i & 1, r = i & 6;
-            t1[i] = kL1[qx][0] * ue[r] + kL1[qx][1] * ue[r + 1];
-          }
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 bz
-            const int qy = (i >> 1) & 1, r = i & 5;
-            t2[i] = kL1[qy][0] * t1[r] + kL1[qy][1] * t1[r + 2];
-          }
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 qz
-            const int qz = i >> 2, r = i & 3;
-            uq[i] = kL1[qz][0] * t2[r] + kL1[qz][1] * t2[r + 4];
-          }
-          double w[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            w[q] = uq[q] * kQ1.N[q][ai];
-            la += wr * fsrc * kQ1.N[q][ai];
-          }
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 bz
-            const int bz = i >> 2, r = i & 3;
-            t1[i] = kL1[0][bz] * w[r] + kL1[1][bz] * w[r + 4];
-          }
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {  // i = qx + 2 by + 4 bz
-            const int by = (i >> 1) & 1, r = i & 5;
-            t2[i] = kL1[0][by] * t1[r] + kL1[1][by] * t1[r + 2];
-          }
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {  // i = bx + 2 by + 4 bz
-            const int bx = i & 1, r = i & 6;
-            rnv[i] = kL1[0][bx] * t2[r] + kL1[1][bx] * t2[r + 1];
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          double dg = 0.0;
-          const double rn = rnv[b];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) dg += kq[q] * kQ1.G[q][ai][b];
-          const double lin = wd * dg + wa * s_adv[ai][b];
-          fa += (lin + wb * rn) * ue[b];
-          if (JAC) {
-            const int dx = ex_off + (b & 1), dy = ey_off + ((b >> 1) & 1), dz = ez_off + ((b >> 2) & 1);
-            acc[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] += lin + 2.0 * wb * rn;
-          }
-        }
+    if (JAC) {
+      if (ez_off < 0) store_plane(-1);
+      else {
+        store_plane(0);
+        store_plane(1);
       }
-
-  const bool bnd_row = (ii == 0 || ii == N || jj == 0 || jj == N || kk == 0 || kk == N);
-  if (JAC) {
-    const int64_t start = row_ptr[row];
-    int pos = 0;
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int x = ii + dx, y = jj + dy, z = kk + dz;
-          if (x < 0 || y < 0 || z < 0 || x > N || y > N || z > N) continue;
-          const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-          double v = acc[slot27];
-          const bool bnd_col = (x == 0 || x == N || y == 0 || y == N || z == 0 || z == N);
-          if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
-          else if (bnd_col) v = 0.0;
-          if (values) values[(start + pos) * S + e] = v;
-          if (values32) values32[(start + pos) * S + e] = (float)v;
-          ++pos;
-        }
+    }
   }
+
   F[row * S + e] = bnd_row ? u[row * S + e] : fa - la;
   if (load) load[row * S + e] = bnd_row ? 0.0 : la;
 }
@@ -518,12 +606,22 @@ __global__ __launch_bounds__(256) void k_kl_extrema(int N, const double* __restr
   }
 }
 
-// Sample groups per tile: 8 samples per workgroup, all of them for s = 4.
-static constexpr int asm_sb(int S) { return S < 8 ? S : 8; }
+template <int R, int TY>
+static int64_t tiles_of(int N) {
+  using T = AsmTile<R, TY>;
+  return (int64_t)((N + T::TX) / T::TX) * ((N + T::TY) / T::TY) * ((N + T::TZ) / T::TZ);
+}
 
+// Samples per workgroup of the nonlinear assembly: 8 (256 lanes, 3 per CU;
+// at 128^3, s = 32 this ran 7.9 ms per launch against 8.1 ms for all 32
+// samples in one workgroup, whose full-line stores do not pay for its
+// single workgroup per CU in this arithmetic-bound kernel).
+static constexpr int nl_sb(int S) { return S < 8 ? S : 8; }
+
+// Tiles of both assemblies (rows of the linear one's fused bound partials).
 int64_t asm_tiles(int N, int S) {
-  const int TX = (256 / asm_sb(S)) / 4;
-  return (int64_t)((N + TX) / TX) * ((N + 4) / 4) * (N + 1);
+  (void)S;
+  return tiles_of<32, 2>(N);
 }
 
 ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, const int32_t* tr, const double* phi,
@@ -542,17 +640,17 @@ ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, cons
   const int M = prob->M;
   prof_begin(ENS_K_ASSEMBLE, stream);
   switch (s) {
-#define ENS_ASM_LAUNCH(SS, SB, BB, AA)                                                                            \
-  hipLaunchKernelGGL((k_assemble_tile<SS, SB, BB, AA>), dim3((unsigned)(asm_tiles(N, SS) * (SS / SB))), dim3(256), \
-                     0, stream, N, sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, av[0], av[1], av[2], av[3], \
-                     xi, graph->row_ptr, values, values32, rhs, dinv, bpart)
-#define ENS_ASM_CASE(SS)                                                   \
-  case SS:                                                                 \
-    if (with_adv && bnd == 1) ENS_ASM_LAUNCH(SS, asm_sb(SS), 1, true);     \
-    else if (with_adv && bnd == 2) ENS_ASM_LAUNCH(SS, asm_sb(SS), 2, true); \
-    else if (bnd == 1) ENS_ASM_LAUNCH(SS, asm_sb(SS), 1, false);           \
-    else if (bnd == 2) ENS_ASM_LAUNCH(SS, asm_sb(SS), 2, false);           \
-    else ENS_ASM_LAUNCH(SS, asm_sb(SS), 0, false);                         \
+#define ENS_ASM_LAUNCH(SS, BB, AA)                                                                                \
+  hipLaunchKernelGGL((k_assemble_tile<SS, BB, AA>), dim3((unsigned)asm_tiles(N, SS)), dim3(32 * SS), 0, stream, N, sq, \
+                     tr, phi, M, prob->kappa0, prob->sigma, prob->f, av[0], av[1], av[2], av[3], xi, graph->row_ptr,  \
+                     values, values32, rhs, dinv, bpart)
+#define ENS_ASM_CASE(SS)                                         \
+  case SS:                                                       \
+    if (with_adv && bnd == 1) ENS_ASM_LAUNCH(SS, 1, true);       \
+    else if (with_adv && bnd == 2) ENS_ASM_LAUNCH(SS, 2, true);  \
+    else if (bnd == 1) ENS_ASM_LAUNCH(SS, 1, false);             \
+    else if (bnd == 2) ENS_ASM_LAUNCH(SS, 2, false);             \
+    else ENS_ASM_LAUNCH(SS, 0, false);                           \
     break;
     ENS_ASM_CASE(4)
     ENS_ASM_CASE(8)
@@ -627,10 +725,11 @@ extern "C" ens_status ens_nl_assemble(int32_t N, const ens_graph* graph, const v
   kl_parts(kl, M, &sq, &tr, &phi);
   prof_begin(ENS_K_NL_ASSEMBLE, stream);
   switch (s) {
-#define ENS_NL_LAUNCH(SS, JJ)                                                                                     \
-  hipLaunchKernelGGL((k_nl_assemble<SS, asm_sb(SS), JJ>), dim3((unsigned)(asm_tiles(N, SS) * (SS / asm_sb(SS)))),   \
-                     dim3(256), 0, stream, N, sq, tr, phi, M, prob->kappa0, prob->sigma, prob->f, prob->alpha,      \
-                     prob->beta, prob->vx, prob->vy, prob->vz, xi, graph->row_ptr, u, values, values32, F, load)
+#define ENS_NL_LAUNCH(SS, JJ)                                                                                    \
+  hipLaunchKernelGGL((k_nl_assemble<SS, nl_sb(SS), JJ>), dim3((unsigned)(asm_tiles(N, SS) * (SS / nl_sb(SS)))),      \
+                     dim3(32 * nl_sb(SS)), 0, stream, N, sq, tr,                                                      \
+                     phi, M, prob->kappa0, prob->sigma, prob->f, prob->alpha, prob->beta, prob->vx, prob->vy,       \
+                     prob->vz, xi, graph->row_ptr, u, values, values32, F, load)
 #define ENS_NL_CASE(SS)                                  \
   case SS:                                               \
     if (values || values32) ENS_NL_LAUNCH(SS, true);     \
