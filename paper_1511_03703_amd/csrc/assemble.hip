@@ -121,76 +121,75 @@ __device__ inline int kslot(int le, int q, int sb) {
   return ((le * 8 + (q ^ (le & 7))) * SB) + sb;
 }
 
-// LDS doubles of a tile's 1D KL factors: for each of the M modes its 1D
-// eigenfunction at the 2 Gauss abscissae of each element column along x, y
-// and z of the tile's element block.
+// LDS doubles of a tile's KL factors: for each of the M modes its 1D
+// eigenfunction at the 2 Gauss abscissae of each element column along x,
+// and the products Y(qy) Z(qz) for each (y, z) element pair of the tile's
+// element block.
 template <int EX, int EY, int EZ>
-__host__ __device__ constexpr int tab_doubles(int M) { return M * 2 * (EX + EY + EZ); }
+__host__ __device__ constexpr int tab_doubles(int M) { return M * (2 * EX + 4 * EY * EZ); }
 
 // Phase 1 of the tiled assemblies: the coefficient at the 8 Gauss points of
 // every element of the tile's EX x EY x EZ element block (origin ex0, ey0,
 // ez0) for the SB samples e0.., times `scale`, into s_k[kslot(le, q, sb)].
-// The 1D factors of the tile are staged in s_tab first (sample-independent,
-// read from the KL table once per workgroup), and each lane keeps the
-// coefficients c_m = sigma sqrt(lambda_m) y_m of its one sample in
-// registers (the NT lanes are a multiple of SB, so a lane's items all have
-// the same sample).  The sum follows kl_points operation by operation, so the values
-// are bitwise those of kl_points.  Ends with a barrier.
+// The sample-independent factors are staged in s_tab first (the x factors
+// and the y-z products, read from the KL table once per workgroup), and
+// each lane keeps the coefficients c_m = sigma sqrt(lambda_m) y_m of its one
+// sample in registers (the NT lanes are a multiple of 2 SB, so a lane's
+// items all have the same sample and z half).  An item is one element,
+// sample and z half (4 Gauss points).  The sum follows kl_points operation
+// by operation (the y-z product is formed once per tile instead of per
+// sample: the same rounding), so the values are bitwise those of
+// kl_points.  Ends with a barrier.
 template <int NT, int SB, int EX, int EY, int EZ, bool SCALED>
 __device__ inline void tile_coefficients(int N, const double* __restrict__ kl_sqrt_lam,
                                          const int32_t* __restrict__ kl_triple, const double* __restrict__ kl_phi,
                                          int M, double kappa0, double sigma, const double* __restrict__ xi, int e0,
                                          int ex0, int ey0, int ez0, double scale, double* s_tab, double* s_k) {
-  static_assert(NT % SB == 0, "a lane's items must share one sample");
+  static_assert(NT % (2 * SB) == 0, "a lane's items must share one sample and z half");
   constexpr int NE = EX * EY * EZ;
   const int64_t two_n = 2 * (int64_t)N;
   double* s_x = s_tab;               // [M][EX][2]
-  double* s_y = s_tab + M * 2 * EX;  // [M][EY][2]
-  double* s_z = s_y + M * 2 * EY;    // [M][EZ][2]
-  for (int t = threadIdx.x; t < M * 2 * (EX + EY + EZ); t += NT) {
-    int m, l, q, axis, e0a, ext;
-    if (t < M * 2 * EX) {
-      m = t / (2 * EX), l = (t / 2) % EX, q = t & 1, axis = 0, e0a = ex0, ext = EX;
-    } else if (t < M * 2 * (EX + EY)) {
-      const int u = t - M * 2 * EX;
-      m = u / (2 * EY), l = (u / 2) % EY, q = u & 1, axis = 1, e0a = ey0, ext = EY;
-    } else {
-      const int u = t - M * 2 * (EX + EY);
-      m = u / (2 * EZ), l = (u / 2) % EZ, q = u & 1, axis = 2, e0a = ez0, ext = EZ;
-    }
-    (void)ext;
-    const int el = e0a + l;
-    s_tab[t] = (el >= 0 && el < N) ? kl_phi[kl_triple[3 * m + axis] * two_n + 2 * el + q] : 0.0;
+  double* s_yz = s_tab + M * 2 * EX;  // [M][EY][EZ][4], index qy + 2 qz
+  for (int t = threadIdx.x; t < M * 2 * EX; t += NT) {
+    const int m = t / (2 * EX), l = (t / 2) % EX, q = t & 1;
+    const int el = ex0 + l;
+    s_x[t] = (el >= 0 && el < N) ? kl_phi[kl_triple[3 * m] * two_n + 2 * el + q] : 0.0;
   }
-  const int sb = threadIdx.x % SB;
+  for (int t = threadIdx.x; t < M * 4 * EY * EZ; t += NT) {
+    const int m = t / (4 * EY * EZ), r = t % (4 * EY * EZ);
+    const int ly = r / (4 * EZ), lz = (r / 4) % EZ, qy = r & 1, qz = (r >> 1) & 1;
+    const int ey = ey0 + ly, ez = ez0 + lz;
+    double v = 0.0;
+    if (ey >= 0 && ey < N && ez >= 0 && ez < N)
+      v = kl_phi[kl_triple[3 * m + 1] * two_n + 2 * ey + qy] * kl_phi[kl_triple[3 * m + 2] * two_n + 2 * ez + qz];
+    s_yz[t] = v;
+  }
+  const int sb = threadIdx.x % SB, hz = (threadIdx.x / SB) & 1;
   double c[kAsmMaxM];
 #pragma unroll
   for (int m = 0; m < kAsmMaxM; ++m) c[m] = m < M ? sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + sb) * M + m] : 0.0;
   __syncthreads();
-  for (int p = threadIdx.x; p < NE * SB; p += NT) {
-    const int le = p / SB;
+  for (int p = threadIdx.x; p < NE * 2 * SB; p += NT) {
+    const int le = p / (2 * SB);
     const int lx = le % EX, ly = (le / EX) % EY, lz = le / (EX * EY);
     const int ex = ex0 + lx, ey = ey0 + ly, ez = ez0 + lz;
     if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
-    double kq[8];
+    double kq[4];  // Gauss points qx + 2 qy + 4 hz
 #pragma unroll
-    for (int q = 0; q < 8; ++q) kq[q] = 0.0;
+    for (int q = 0; q < 4; ++q) kq[q] = 0.0;
 #pragma unroll
     for (int m = 0; m < kAsmMaxM; ++m) {
       if (m >= M) break;
       const double fx[2] = {s_x[(m * EX + lx) * 2], s_x[(m * EX + lx) * 2 + 1]};
-      const double fy[2] = {s_y[(m * EY + ly) * 2], s_y[(m * EY + ly) * 2 + 1]};
-      const double fz[2] = {s_z[(m * EZ + lz) * 2], s_z[(m * EZ + lz) * 2 + 1]};
-      double yz[4];
+      const double* pyz = s_yz + ((m * EY + ly) * EZ + lz) * 4 + 2 * hz;
+      const double yz[2] = {c[m] * pyz[0], c[m] * pyz[1]};
 #pragma unroll
-      for (int t = 0; t < 4; ++t) yz[t] = c[m] * (fy[t & 1] * fz[t >> 1]);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
+      for (int q = 0; q < 4; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const double k = kappa0 + kq[q];
-      s_k[kslot<SB>(le, q, sb)] = SCALED ? k * scale : k;
+      s_k[kslot<SB>(le, q + 4 * hz, sb)] = SCALED ? k * scale : k;
     }
   }
   __syncthreads();
@@ -328,31 +327,39 @@ __global__ __launch_bounds__(32 * S) void k_assemble_tile(int N, const double* _
 
   const bool bnd_row = (ii == 0 || ii == N || jj == 0 || jj == N || kk == 0 || kk == N);
   const int64_t start = row_ptr[row];
-  int pos = 0;
   double sabs = 0.0, dg = 0.0;
+  auto put = [&](int64_t k, int slot27, double v) {
+    if (values) values[k] = v;
+    if (values32) values32[k] = (float)v;
+    if (BND) {
+      const double vc = BND == 1 ? (double)(float)v : v;  // the value the cycle runs on
+      sabs += fabs(vc);
+      if (slot27 == 13) dg = vc;
+    }
+  };
+  if (ii >= 2 && jj >= 2 && kk >= 2 && ii <= N - 2 && jj <= N - 2 && kk <= N - 2) {
+    // all 27 neighbours interior: entry t of the row is neighbour t
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz)
+    for (int t = 0; t < 27; ++t) put((start + t) * S + e, t, acc[t]);
+  } else {
+    int pos = 0;
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
+    for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int x = ii + dx, yy = jj + dy, z = kk + dz;
-        if (x < 0 || yy < 0 || z < 0 || x > N || yy > N || z > N) continue;
-        const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-        double v = acc[slot27];
-        const bool bnd_col = (x == 0 || x == N || yy == 0 || yy == N || z == 0 || z == N);
-        if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
-        else if (bnd_col) v = 0.0;
-        const int64_t k = (start + pos) * S + e;
-        if (values) values[k] = v;
-        if (values32) values32[k] = (float)v;
-        if (BND) {
-          const double vc = BND == 1 ? (double)(float)v : v;  // the value the cycle runs on
-          sabs += fabs(vc);
-          if (slot27 == 13) dg = vc;
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = ii + dx, yy = jj + dy, z = kk + dz;
+          if (x < 0 || yy < 0 || z < 0 || x > N || yy > N || z > N) continue;
+          const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+          double v = acc[slot27];
+          const bool bnd_col = (x == 0 || x == N || yy == 0 || yy == N || z == 0 || z == N);
+          if (bnd_row) v = (slot27 == 13) ? 1.0 : 0.0;
+          else if (bnd_col) v = 0.0;
+          put((start + pos) * S + e, slot27, v);
+          ++pos;
         }
-        ++pos;
-      }
+  }
   rhs[row * S + e] = bnd_row ? 0.0 : (double)nelem * (fsrc * h * h * h * 0.125);
   if (BND == 1) ((float*)dinv)[row * S + e] = 1.0f / (float)dg;
   if (BND == 2) ((double*)dinv)[row * S + e] = 1.0 / dg;
@@ -452,7 +459,16 @@ __global__ __launch_bounds__(32 * SB) void k_nl_assemble(int N, const double* __
   // the entries of neighbour plane dz are final once the elements below
   // it are added (plane -1 after the lower elements, planes 0 and +1 after
   // all): stored then, in entry order, so fewer accumulators stay live
+  const bool deep = ii >= 2 && jj >= 2 && kk >= 2 && ii <= N - 2 && jj <= N - 2 && kk <= N - 2;
   auto store_plane = [&](int dz) {
+    if (deep) {  // all 27 neighbours interior: entry t of the row is neighbour t
+#pragma unroll
+      for (int t = (dz + 1) * 9; t < (dz + 2) * 9; ++t) {
+        if (values) values[(start + t) * S + e] = acc[t];
+        if (values32) values32[(start + t) * S + e] = (float)acc[t];
+      }
+      return;
+    }
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
