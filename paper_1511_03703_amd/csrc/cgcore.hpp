@@ -285,8 +285,12 @@ __device__ inline void residual_body(int n, const int32_t* __restrict__ rp, cons
 #pragma unroll
   for (int j = 0; j < M::V; ++j) acc[0][j] = acc[1][j] = 0.0;
   const int64_t row = (blk * NW + wave) * M::RPW + lane / M::L;
+  constexpr int R = NW * M::RPW;
+  __shared__ RowTileLds<R> tile;
+  const bool staged = !x_zero && stage_row_tile(tile, n, rp, ci, blk * R);
   if (row < n) {
-    typename M::vt ax = x_zero ? (typename M::vt)0.0 : ens_row_product<double, S>(ci, vals, x, rp[row], rp[row + 1], sub);
+    typename M::vt ax = x_zero ? (typename M::vt)0.0
+                               : tile_row_product<double, S>(tile, staged, (int)(row - blk * R), ci, vals, x, sub);
     typename M::vt bv = ((const typename M::vt*)b)[row * M::L + sub];
     typename M::vt r = bv - ax;
 #pragma unroll
@@ -352,8 +356,11 @@ __device__ inline void spmv_dot_body(int n, const int32_t* __restrict__ rp, cons
 #pragma unroll
   for (int j = 0; j < M::V; ++j) acc[0][j] = 0.0;
   const int64_t row = (blk * NW + wave) * M::RPW + lane / M::L;
+  constexpr int R = NW * M::RPW;
+  __shared__ RowTileLds<R> tile;
+  const bool staged = stage_row_tile(tile, n, rp, ci, blk * R);
   if (row < n) {
-    typename M::vt qv = ens_row_product<T, S>(ci, vals, p, rp[row], rp[row + 1], sub);
+    typename M::vt qv = tile_row_product<T, S>(tile, staged, (int)(row - blk * R), ci, vals, p, sub);
     store_stream((typename M::vt*)q + row * M::L + sub, qv);
     typename M::vt pv = ((const typename M::vt*)p)[row * M::L + sub];
 #pragma unroll

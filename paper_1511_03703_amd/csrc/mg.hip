@@ -349,8 +349,11 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane % M::L;
   const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
+  constexpr int R = 4 * M::RPW;
+  __shared__ RowTileLds<R> tile;
+  const bool staged = stage_row_tile(tile, n, rp, ci, (int64_t)blockIdx.x * R);
   if (row >= n) return;
-  const vt ax = ens_row_product<T, S>(ci, vals, x, rp[row], rp[row + 1], sub);
+  const vt ax = tile_row_product<T, S>(tile, staged, (int)(row - (int64_t)blockIdx.x * R), ci, vals, x, sub);
   const int64_t i = row * M::L + sub;
   const vt res = ((const vt*)b)[i] - ax;
   if (MODE == MG_RES) {

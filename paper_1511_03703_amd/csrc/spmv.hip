@@ -4,7 +4,8 @@
 
 namespace ens {
 
-// One workgroup of 256 lanes = 4 wavefronts, each on RPW consecutive rows.
+// One workgroup of 256 lanes = 4 wavefronts, each on RPW consecutive rows;
+// the tile's row offsets and column indices staged in LDS.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_ens_spmv(int n, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const T* __restrict__ vals,
@@ -13,8 +14,11 @@ __global__ __launch_bounds__(256) void k_ens_spmv(int n, const int32_t* __restri
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane % M::L;
   const int64_t row = ((int64_t)blockIdx.x * 4 + wave) * M::RPW + lane / M::L;
+  constexpr int R = 4 * M::RPW;
+  __shared__ RowTileLds<R> tile;
+  const bool staged = stage_row_tile(tile, n, rp, ci, (int64_t)blockIdx.x * R);
   if (row >= n) return;
-  typename M::vt acc = ens_row_product<T, S>(ci, vals, x, rp[row], rp[row + 1], sub);
+  typename M::vt acc = tile_row_product<T, S>(tile, staged, (int)(row - (int64_t)blockIdx.x * R), ci, vals, x, sub);
   store_stream((typename M::vt*)y + row * M::L + sub, acc);
 }
 

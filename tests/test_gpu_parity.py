@@ -150,6 +150,28 @@ def test_spmv_random_graphs(E, orc, s, n):
     assert np.max(np.abs(y32 - ref)) <= 2e-6 * scale
 
 
+@pytest.mark.parametrize("s", [4, 32])
+@pytest.mark.parametrize("lo,hi", [(40, 64), (0, 8)])
+def test_spmv_row_tiles_staged_and_not(E, orc, s, lo, hi):
+    # a workgroup stages its rows' indices in LDS when they average at most
+    # 32 per row and reads them from global memory otherwise: rows of 40-64
+    # entries take the second path in every tile, rows of 0-8 the first
+    rng = np.random.default_rng(lo * 1000 + s)
+    n = 2000
+    lens = rng.integers(lo, hi + 1, n)
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum(lens)
+    ci = np.concatenate([np.sort(rng.choice(n, L, replace=False)) for L in lens]).astype(np.int32)
+    vals = rng.standard_normal((int(rp[-1]), s))
+    x = rng.standard_normal((n, s))
+    ref = orc.ens_spmv(rp, ci, vals, x)
+    g = E.graph_from_arrays(_t(rp, torch.int32), _t(ci, torch.int32))
+    scale = max(np.abs(vals).max(initial=0.0) * np.abs(x).max(), 1.0) * 64
+    for dt, tol in ((torch.float64, 1e-15), (torch.float32, 2e-6)):
+        y = _np(E.spmv(g, _t(vals, dt), _t(x, dt)))
+        assert np.max(np.abs(y - ref)) <= tol * scale
+
+
 @pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
 def test_scalar_spmv(E, orc, lanes):
     rng = np.random.default_rng(lanes)
@@ -365,3 +387,16 @@ def test_coupled_mixed_is_refused(E):
     with pytest.raises(E.EnsError) as ex:
         E.cg(g, vals, rhs, values32=v32, opts=E.cg_opts(mixed=True, coupled=True))
     assert ex.value.status == E.ENS_E_UNSUPPORTED
+
+
+def test_stream_read_folds_every_word(E):
+    # the read-only bandwidth kernel reads every 16-byte chunk exactly once:
+    # the XOR of its per-workgroup words is the XOR of the buffer's words
+    rng = np.random.default_rng(77)
+    for nbytes in (16, 4096 * 3 + 16 * 7, 64 << 20):
+        words = rng.integers(0, 2 ** 32, nbytes // 4, dtype=np.uint64).astype(np.uint32)
+        src = torch.as_tensor(words.view(np.int32), device=DEV)
+        out = E.stream_read(src)
+        blocks = min(E.STREAM_READ_BLOCKS, (nbytes // 16 + 255) // 256)
+        got = np.bitwise_xor.reduce(_np(out)[:blocks].view(np.uint32))
+        assert got == np.bitwise_xor.reduce(words), nbytes
