@@ -141,7 +141,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="default 5 (solve workloads), 1 (batch, learned)")
     ap.add_argument("--warmup", type=int, default=None, help="default 1 (solve workloads), 0 (batch, learned)")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "mid", "small", "batch", "learned", "mg", "newton", "assembly"])
+                    choices=["headline", "mid", "small", "batch", "learned", "mg", "newton", "assembly",
+                             "coupled"])
     ap.add_argument("--pool-gib", type=float, default=192.0, help="batch: resident pool size")
     ap.add_argument("--batch-s", type=int, default=0, help="batch: fix s (skip the autotuner)")
     ap.add_argument("--batch-tile", type=int, default=4, help="batch: tile when --batch-s is given")
@@ -196,6 +197,8 @@ def main():
         return run_newton(args)
     if args.workload == "assembly":
         return run_assembly(args)
+    if args.workload == "coupled":
+        return run_coupled(args)
     return run_solve(args)
 
 
@@ -459,6 +462,23 @@ def run_solve(args):
         e1.record()
         torch.cuda.synchronize()
         triad_gbs = 3.0 * na * 8 / (e0.elapsed_time(e1) / 5) / 1e6
+        # the read-only and copy ceilings on the same 4 GiB buffers
+        for _ in range(2):
+            ens.stream_read(tb)
+        e0.record()
+        for _ in range(5):
+            ens.stream_read(tb)
+        e1.record()
+        torch.cuda.synchronize()
+        read_gbs = na * 8 / (e0.elapsed_time(e1) / 5) / 1e6
+        for _ in range(2):
+            ens.stream_copy(tb, ta)
+        e0.record()
+        for _ in range(5):
+            ens.stream_copy(tb, ta)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * na * 8 / (e0.elapsed_time(e1) / 5) / 1e6
         del ta, tb, tc
         b_ens = spmv_bytes(w.n, w.nnz, w.s, wb)
         b_sc = spmv_bytes(w.n, w.nnz, 1, wb)
@@ -493,6 +513,8 @@ def run_solve(args):
                      "speedup_s_times_scalar_over_ensemble": round(w.s * t_sc / t_ens, 3),
                      "dtype": "f32" if w.mixed else "f64"},
             "triad_GBs": round(triad_gbs, 1),
+            "read_GBs": round(read_gbs, 1),
+            "copy_GBs": round(copy_gbs, 1),
         }
         del xv, yv, x1, y1
 
@@ -1053,6 +1075,72 @@ def run_assembly(args):
                      "kernel": "k_assemble_tile<32,0,false>", "bytes_per_launch": a["bytes_per_launch"],
                      "avg_launch_ms": a["ms_per_launch"], "launches": a["launches"]},
         "kernels": out_k,
+    }
+    out.setdefault("env", host_env())
+    print(json.dumps(out), flush=True)
+
+
+def run_coupled(args):
+    """The coupled ensemble CG (one alpha, beta and stopping test for the
+    whole commuted system, as the paper's solver runs it) against the
+    per-sample ensemble CG on the headline samples (128^3, s = 32, FP64
+    Jacobi-CG to 1e-8) as sigma rises: the coupled iteration count follows
+    the union of the samples' spectra (Sec. 3.7), the per-sample one the
+    slowest sample.  One step = both solves at every sigma."""
+    import numpy as np
+    import torch
+
+    from paper_1511_03703_amd import ens
+    import workloads as W
+
+    w = W.HEADLINE
+    dev = "cuda"
+    torch.cuda.set_device(0)
+    g = ens.graph_build(w.N)
+    kl = ens.kl_build(w.N, w.M, w.L)
+    xi = torch.as_tensor(w.xi(), device=dev)
+    vals = torch.empty((w.nnz, w.s), dtype=torch.float64, device=dev)
+    rhs = torch.empty((w.n, w.s), dtype=torch.float64, device=dev)
+    x = torch.zeros((w.n, w.s), dtype=torch.float64, device=dev)
+    ws = torch.empty(ens.cg_workspace_bytes(g, w.s, ens.cg_opts()), dtype=torch.uint8, device=dev)
+    sigmas = (0.1, 0.2, 0.3)
+    rows = []
+    total_s, total_t = 0, 0.0
+    for sigma in sigmas:
+        ens.assemble(g, kl, xi, w.M, sigma, L=w.L, kappa0=w.kappa0, f=w.f, values=vals, rhs=rhs)
+        res = {"sigma": sigma}
+        for name, coupled in (("per_sample", False), ("coupled", True)):
+            opts = ens.cg_opts(rtol=w.rtol, check_every=args.check_every, coupled=coupled)
+            best = None
+            for rep in range(args.warmup + args.steps):
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st, rc = ens.cg(g, vals, rhs, x=x, opts=opts, workspace=ws)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                if rep >= args.warmup:
+                    best = t if best is None else min(best, t)
+            its = [t_["iters"] for t_ in st]
+            res[name] = {"iters_max": max(its), "iters_min": min(its), "seconds": round(best, 4),
+                         "samples_per_s": round(w.s / best, 3),
+                         "all_converged": all(t_["status"] == 0 and t_["rel_res"] <= w.rtol * (1 + 1e-6) for t_ in st)}
+            if coupled:
+                total_s += w.s
+                total_t += best
+        res["coupled_over_slowest_sample"] = round(res["coupled"]["iters_max"] / res["per_sample"]["iters_max"], 3)
+        rows.append(res)
+        log(f"sigma {sigma}: per-sample {res['per_sample']['iters_min']}-{res['per_sample']['iters_max']} iterations "
+            f"({res['per_sample']['seconds']} s), coupled {res['coupled']['iters_max']} ({res['coupled']['seconds']} s)")
+    out = {
+        "metric": "solved samples/s at 128^3, s=32, 1e-8: coupled ensemble CG (the paper's solve), sigma 0.1-0.3",
+        "value": round(total_s / total_t, 3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total_t / len(sigmas) * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "q1_128cube_s32_coupled_sweep", "mesh": f"{w.N}^3 Q1 hexahedra", "n": w.n,
+                   "nnz": w.nnz, "s": w.s, "M": w.M, "sigmas": list(sigmas), "rtol": w.rtol, "seed": w.seed,
+                   "preconditioner": "Jacobi", "check_every": args.check_every},
+        "sweep": rows,
     }
     out.setdefault("env", host_env())
     print(json.dumps(out), flush=True)

@@ -680,6 +680,13 @@ ens_status ens_pod_reconstruct(const double* Phi, int64_t n, int32_t r, const fl
 ens_status ens_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 ens_status ens_stream_triad(double* a, const double* b, const double* c, double q, int64_t n,
                             hipStream_t stream);
+/* Pure read stream of `bytes` bytes (multiple of 16, 16-byte aligned src),
+ * the read-only bandwidth ceiling next to the copy and the triad: every
+ * 16-byte chunk is read once and folded by XOR into one word per workgroup,
+ * out (device) [ENS_STREAM_READ_BLOCKS] uint32 (only the first
+ * min(ENS_STREAM_READ_BLOCKS, bytes / 4096) written).  Never synchronises. */
+#define ENS_STREAM_READ_BLOCKS 8192
+ens_status ens_stream_read(const void* src, size_t bytes, uint32_t* out, hipStream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
  * launch of the listed kernels while enabled.  Enabling creates a pool of

@@ -146,6 +146,32 @@ __global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u
   }
 }
 
+// Pure read stream: every 16-byte chunk read once (non-temporal, as the
+// products read their values), folded by XOR into one word per workgroup.
+__global__ __launch_bounds__(256) void k_read16(const u32x4* __restrict__ src, int64_t n16,
+                                                uint32_t* __restrict__ out) {
+  constexpr int U = 16;  // independent loads in flight per lane
+  __shared__ uint32_t red[256];
+  u32x4 a = {0u, 0u, 0u, 0u};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < U; ++u) a ^= v[u];
+  }
+  for (; i < n16; i += stride) a ^= __builtin_nontemporal_load(src + i);
+  red[threadIdx.x] = a[0] ^ a[1] ^ a[2] ^ a[3];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] ^= red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 __global__ __launch_bounds__(256) void k_triad(double* __restrict__ a, const double* __restrict__ b,
                                                 const double* __restrict__ c, double q, int64_t n) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -187,6 +213,19 @@ ens_status ens_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, stream, (const u32x4*)src, (u32x4*)dst,
                      n16);
+  ENS_LAUNCH_CHECK();
+  return ENS_OK;
+}
+
+ens_status ens_stream_read(const void* src, size_t bytes, uint32_t* out, hipStream_t stream) {
+  ENS_ARG_CHECK(src && out, "null pointer");
+  ENS_ARG_CHECK(bytes % 16 == 0, "bytes must be a multiple of 16");
+  ENS_ARG_CHECK(aligned16(src), "src must be 16-byte aligned");
+  if (bytes == 0) return ENS_OK;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  int64_t blocks = (n16 + 255) / 256;
+  if (blocks > ENS_STREAM_READ_BLOCKS) blocks = ENS_STREAM_READ_BLOCKS;
+  hipLaunchKernelGGL(k_read16, dim3((unsigned)blocks), dim3(256), 0, stream, (const u32x4*)src, n16, out);
   ENS_LAUNCH_CHECK();
   return ENS_OK;
 }

@@ -151,6 +151,7 @@ _SIGS = [
                                   ctypes.POINTER(_I32), _P, _P]),
     ("ens_stream_copy", _I32, [_P, _P, _SZ, _P]),
     ("ens_stream_triad", _I32, [_P, _P, _P, _D, _I64, _P]),
+    ("ens_stream_read", _I32, [_P, _SZ, _P, _P]),
     ("ens_mlp_param_count", _I64, []),
     ("ens_mlp_workspace_bytes", _I32, [_I32, ctypes.POINTER(_SZ)]),
     ("ens_mlp_forward", _I32, [_P, _I32, _P, _P, _P, _SZ, _P]),
@@ -668,6 +669,19 @@ def relayout(src: torch.Tensor, to_sample_major: bool, out=None, stream=None):
 def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
     nb = src.numel() * src.element_size()
     _check(lib().ens_stream_copy(_ptr(src), _ptr(dst), nb, _stream(stream)), "ens_stream_copy")
+
+
+STREAM_READ_BLOCKS = 8192
+
+
+def stream_read(src: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Read every byte of src once (the read-only bandwidth ceiling); returns
+    the per-workgroup XOR words."""
+    if out is None:
+        out = torch.empty(STREAM_READ_BLOCKS, dtype=torch.int32, device=src.device)
+    nb = src.numel() * src.element_size()
+    _check(lib().ens_stream_read(_ptr(src), nb, _ptr(out), _stream(stream)), "ens_stream_read")
+    return out
 
 
 def stream_triad(a, b, c, q: float, stream=None):
