@@ -646,9 +646,15 @@ ens_status ens_mlp_adam(float* params, const float* grad, float* adam_m, float* 
  * ens_pod_basis:   Phi [n][r] = S V diag(lambda)^(-1/2), each column's
  *                  largest-magnitude entry made positive.
  * ens_pod_project: C [s][r] = X^T Phi for an ensemble X [n][s].
- * ens_pod_standardize: per-coefficient mean mu [r] and standard deviation
- *                  sd [r] of C [m][r], and the network targets
- *                  T [m][r] = (C - mu) / sd in FP32.
+ * ens_pod_standardize: per-coefficient mean mu [r] over the m rows of
+ *                  C [m][r] (r <= 1024), a scale sd [r] and the network
+ *                  targets T [m][r] = (C - mu) / sd in FP32; common = 0:
+ *                  sd[j] the standard deviation of coefficient j;
+ *                  common = 1: every sd[j] the largest of those
+ *                  deviations, so the targets keep the coefficients'
+ *                  relative sizes and a network's squared error on them is
+ *                  the squared error of the reconstructed guess (Phi is
+ *                  orthonormal).
  * ens_pod_reconstruct: x0 [n][s] = Phi (mu + sd c)^T for network outputs
  *                  c [s][r] (FP32; mu, sd nullable for raw coefficients),
  *                  written in the ensemble layout ready for ens_cg;
@@ -666,8 +672,8 @@ ens_status ens_pod_basis(const double* S, int64_t n, int32_t m, const double* V,
 ens_status ens_pod_project_workspace_bytes(int64_t n, int32_t r, int32_t s, size_t* bytes);
 ens_status ens_pod_project(const double* Phi, const double* X, int64_t n, int32_t r, int32_t s, double* C,
                            void* workspace, size_t ws_bytes, hipStream_t stream);
-ens_status ens_pod_standardize(const double* C, int32_t m, int32_t r, double* mu, double* sd, float* T,
-                               hipStream_t stream);
+ens_status ens_pod_standardize(const double* C, int32_t m, int32_t r, int32_t common, double* mu, double* sd,
+                               float* T, hipStream_t stream);
 ens_status ens_pod_reconstruct(const double* Phi, int64_t n, int32_t r, const float* c, const double* mu,
                                const double* sd, int32_t s, double* x0, hipStream_t stream);
 

@@ -290,20 +290,37 @@ __global__ __launch_bounds__(256) void k_reconstruct(int64_t n, int r, int s, co
 
 // Per-column mean and standard deviation of C [m][r] (one thread per
 // column, rows in order) and the standardised targets T = (C - mu) / sd.
-__global__ void k_standardize(int m, int r, const double* __restrict__ C, double* __restrict__ mu,
+// Mean and standard deviation of each coefficient over the m snapshots
+// (one lane per coefficient, one workgroup), the scale of each coefficient
+// its own deviation or (common) the largest of them, and the network
+// targets T = (C - mu) / scale.  With one common scale the targets keep the
+// coefficients' relative sizes, so the network's squared error is the
+// squared error of the lifted guess in the orthonormal basis.
+__global__ void k_standardize(int m, int r, int common, const double* __restrict__ C, double* __restrict__ mu,
                               double* __restrict__ sd, float* __restrict__ T) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= r) return;
-  double s1 = 0.0;
-  for (int i = 0; i < m; ++i) s1 += C[(int64_t)i * r + j];
-  const double mean = s1 / m;
-  double s2 = 0.0;
-  for (int i = 0; i < m; ++i) {
-    const double d = C[(int64_t)i * r + j] - mean;
-    s2 += d * d;
+  __shared__ double s_dev[1024];
+  const int j = threadIdx.x;
+  double mean = 0.0, dev = 0.0;
+  if (j < r) {
+    double s1 = 0.0;
+    for (int i = 0; i < m; ++i) s1 += C[(int64_t)i * r + j];
+    mean = s1 / m;
+    double s2 = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double d = C[(int64_t)i * r + j] - mean;
+      s2 += d * d;
+    }
+    dev = sqrt(s2 / m);
   }
-  double dev = sqrt(s2 / m);
+  s_dev[j] = dev;
+  __syncthreads();
+  if (common) {
+    double mx = 0.0;
+    for (int k = 0; k < r; ++k) mx = s_dev[k] > mx ? s_dev[k] : mx;
+    dev = mx;
+  }
   if (!(dev > 0.0)) dev = 1.0;
+  if (j >= r) return;
   mu[j] = mean;
   sd[j] = dev;
   for (int i = 0; i < m; ++i) T[(int64_t)i * r + j] = (float)((C[(int64_t)i * r + j] - mean) / dev);
@@ -455,10 +472,11 @@ ens_status ens_pod_reconstruct(const double* Phi, int64_t n, int32_t r, const fl
   return ENS_OK;
 }
 
-ens_status ens_pod_standardize(const double* C, int32_t m, int32_t r, double* mu, double* sd, float* T,
-                               hipStream_t stream) {
-  ENS_ARG_CHECK(C && mu && sd && T && m >= 1 && r >= 1, "bad standardize arguments");
-  hipLaunchKernelGGL(k_standardize, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, stream, m, r, C, mu, sd, T);
+ens_status ens_pod_standardize(const double* C, int32_t m, int32_t r, int32_t common, double* mu, double* sd,
+                               float* T, hipStream_t stream) {
+  ENS_ARG_CHECK(C && mu && sd && T && m >= 1 && r >= 1 && r <= 1024, "bad standardize arguments");
+  hipLaunchKernelGGL(k_standardize, dim3(1), dim3((unsigned)((r + 63) / 64 * 64)), 0, stream, m, r, common, C, mu,
+                     sd, T);
   ENS_LAUNCH_CHECK();
   return ENS_OK;
 }

@@ -166,7 +166,7 @@ _SIGS = [
     ("ens_pod_basis", _I32, [_P, _I64, _I32, _P, _P, _I32, _P, _P]),
     ("ens_pod_project_workspace_bytes", _I32, [_I64, _I32, _I32, ctypes.POINTER(_SZ)]),
     ("ens_pod_project", _I32, [_P, _P, _I64, _I32, _I32, _P, _P, _SZ, _P]),
-    ("ens_pod_standardize", _I32, [_P, _I32, _I32, _P, _P, _P, _P]),
+    ("ens_pod_standardize", _I32, [_P, _I32, _I32, _I32, _P, _P, _P, _P]),
     ("ens_pod_reconstruct", _I32, [_P, _I64, _I32, _P, _P, _P, _I32, _P, _P]),
     ("ens_prof_enable", _I32, [_I32]),
     ("ens_prof_reset", _I32, []),
@@ -816,12 +816,14 @@ def pod_project(Phi, X, stream=None):
     return C
 
 
-def pod_standardize(C, stream=None):
+def pod_standardize(C, common=False, stream=None):
+    """(mu, sd, T) of the coefficients C [m][r]: T = (C - mu) / sd with sd each
+    coefficient's deviation, or with common the largest for all."""
     m, r = C.shape
     mu = torch.empty(r, dtype=torch.float64, device=C.device)
     sd = torch.empty(r, dtype=torch.float64, device=C.device)
     T = torch.empty((m, r), dtype=torch.float32, device=C.device)
-    _check(lib().ens_pod_standardize(_ptr(C), m, r, _ptr(mu), _ptr(sd), _ptr(T), _stream(stream)),
+    _check(lib().ens_pod_standardize(_ptr(C), m, r, int(common), _ptr(mu), _ptr(sd), _ptr(T), _stream(stream)),
            "ens_pod_standardize")
     return mu, sd, T
 

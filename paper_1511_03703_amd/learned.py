@@ -26,9 +26,13 @@ class LearnedGuess:
         self.lam = None
         self.loss = None
 
-    def fit_basis(self, S: torch.Tensor, eig_seed: int, oversample: int = 32, eig_iters: int = 12):
-        """S [n][m] FP64 snapshots (device).  Returns the standardised targets
-        [m][r] (FP32) of the snapshots' POD coefficients."""
+    def fit_basis(self, S: torch.Tensor, eig_seed: int, oversample: int = 32, eig_iters: int = 12,
+                  common_scale: bool = True):
+        """S [n][m] FP64 snapshots (device).  Returns the network targets
+        [m][r] (FP32): the snapshots' POD coefficients centred and divided by
+        one common scale (the largest coefficient deviation), so the training
+        loss weighs each coefficient by its share of the guess's error, or
+        with common_scale=False each by its own deviation."""
         m = S.shape[1]
         G = ens.pod_gram(S)
         k = min(m, self.r + oversample)
@@ -36,7 +40,7 @@ class LearnedGuess:
         V, self.lam = ens.pod_eig(G, self.r, start, eig_iters)
         self.Phi = ens.pod_basis(S, V, self.lam)
         C = ens.pod_project(self.Phi, S)
-        self.mu, self.sd, T = ens.pod_standardize(C)
+        self.mu, self.sd, T = ens.pod_standardize(C, common=common_scale)
         return T
 
     def fit_network(self, xi: torch.Tensor, T: torch.Tensor, steps: int, init_seed: int, order_seed: int,

@@ -188,6 +188,14 @@ def test_pod_kernels_match_reference(E):
     x0 = E.pod_reconstruct(Phi, Tt, mu, sd).cpu().numpy()
     cre = mu.cpu().numpy() + sd.cpu().numpy() * c32.astype(np.float64)
     assert _rel(x0, Pn @ cre.T) <= 1e-13
+    # one common scale: the largest coefficient deviation for every column,
+    # the targets keep the coefficients' relative sizes
+    mu2, sd2, T2 = E.pod_standardize(torch.as_tensor(C, device=DEV), common=True)
+    np.testing.assert_array_equal(mu2.cpu().numpy(), mu.cpu().numpy())
+    big = C.std(0).max()
+    np.testing.assert_allclose(sd2.cpu().numpy(), np.full(r, big), rtol=1e-12)
+    np.testing.assert_allclose(T2.cpu().numpy(), ((C - C.mean(0)) / big).astype(np.float32), rtol=1e-6,
+                               atol=1e-7)
 
 
 def test_learned_guess_saves_iterations(E):
