@@ -352,6 +352,31 @@ ens_status ens_batch_workspace_bytes(const ens_group* groups, int32_t n_groups, 
 ens_status ens_solve_batch(const ens_group* groups, int32_t n_groups, int32_t s, const ens_batch_opts* opts,
                            void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* The KL inputs of one group for ens_assemble_solve_batch. */
+typedef struct {
+  int32_t N;          /* the group's mesh: N^3 elements (graph of ens_graph_build(N)) */
+  const void* kl;     /* (device) ens_kl_build(N, problem->M, problem->L)             */
+  const double* xi;   /* (device) [s][M] KL inputs of the group's samples             */
+} ens_group_input;
+
+/* Assembly and batched solve of a wave of groups in one call: every group's
+ * matrix and load vector are assembled (ens_assemble's operator, FP64
+ * values, Alg. assembly) into its values and b (outputs here; the const of
+ * ens_group does not apply), its x set to zero, and the groups solved as by
+ * ens_solve_batch.  The assemblies of all groups run as one launch over
+ * all their tiles, and with opts->use_graph that launch, the solver's
+ * set-up and the first chunk of iterations are one captured graph, the
+ * further chunks another, replayed.  Results equal ens_assemble per group
+ * followed by ens_solve_batch, bitwise.  Workspace from
+ * ens_assemble_solve_batch_workspace_bytes (the solver's plus the assembly
+ * tables); s in {8, 16, 32}; synchronises. */
+ens_status ens_assemble_solve_batch_workspace_bytes(const ens_group* groups, const ens_group_input* inputs,
+                                                    int32_t n_groups, int32_t s, const ens_problem* problem,
+                                                    const ens_batch_opts* opts, size_t* bytes);
+ens_status ens_assemble_solve_batch(const ens_group* groups, const ens_group_input* inputs, int32_t n_groups,
+                                    int32_t s, const ens_problem* problem, const ens_batch_opts* opts,
+                                    void* workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Autotuner for ens_solve_batch (the ensemble size must suit the
  * architecture, Sec. 3 and Sec. 5): for every candidate ensemble size
  * s_cand[ns] (8, 16, 32) and row-tile shape tile_cand[nt] (2, 4, 8

@@ -4,8 +4,9 @@ A batch of sample groups (an ensemble of s samples on one mesh each) is
 streamed through one preallocated device buffer in waves: a wave is the
 longest run of consecutive groups whose buffers (matrix values, load vector,
 solution) and solver workspace fit the pool; its groups are assembled into the
-pool and solved by one ens_solve_batch call, then the next wave reuses the
-same memory.  Graphs and KL tables are shared by all groups on one mesh and
+pool and solved by one ens_assemble_solve_batch call (the assemblies, the
+solver's set-up and its first chunk of iterations one captured graph), then
+the next wave reuses the same memory.  Graphs and KL tables are shared by all groups on one mesh and
 stay resident outside the pool.
 
 The wave planner is host logic only (no device calls).
@@ -33,10 +34,11 @@ def group_buffer_bytes(N: int, s: int) -> int:
 
 
 def group_workspace_bound(N: int, s: int) -> int:
-    """Upper bound of one group's share of the ens_solve_batch workspace: four
-    solver vectors [n][s], per-block partials and per-group tables."""
+    """Upper bound of one group's share of the ens_assemble_solve_batch
+    workspace: four solver vectors [n][s], per-block partials, per-group
+    tables and the assembly's workgroup table (one entry per 32 nodes)."""
     n, _ = mesh_sizes(N)
-    return 4 * _r(8 * n * s) + 16 * 8 * n + 64 * 1024
+    return 4 * _r(8 * n * s) + 16 * 8 * n + 64 * 1024 + _r(4 * (n // 32 + 3 * (N + 1) ** 2))
 
 
 @dataclass
@@ -137,7 +139,7 @@ class BatchPool:
         worst = ens.ENS_OK
         for wv in self.waves:
             off = 0
-            groups = []
+            groups, inputs = [], []
             for gi in range(wv.first, wv.first + wv.count):
                 N = self.meshes[gi]
                 g, kl = self.graphs[N]
@@ -145,12 +147,13 @@ class BatchPool:
                 vals, off = self._carve(off, 8 * nnz * s, (nnz, s))
                 b, off = self._carve(off, 8 * n * s, (n, s))
                 x, off = self._carve(off, 8 * n * s, (n, s))
-                ens.assemble(g, kl, xi_groups[gi], self.M, sigma, L=self.L, kappa0=kappa0, f=f, values=vals,
-                             rhs=b)
-                x.zero_()
                 groups.append((g, vals, b, x))
+                inputs.append((N, kl, xi_groups[gi]))
+            # the wave's assemblies, the solver's set-up and its first chunk
+            # of iterations run as one captured graph
             ws = self.pool[off:]
-            stats, rc, used = ens.solve_batch(groups, s, opts, workspace=ws, strict_workspace=True)
+            stats, rc, used = ens.assemble_solve_batch(groups, inputs, s, self.M, sigma, opts, workspace=ws, L=self.L,
+                                                       kappa0=kappa0, f=f, strict_workspace=True)
             if on_wave is not None:
                 on_wave(wv, groups, stats)
             all_stats.extend(stats)

@@ -244,16 +244,18 @@ __device__ inline void tile_decode(int N, int64_t bid, int64_t* tile_id, int* sg
 // of the nonlinear problem's Jacobian, Eq. fenl_lin_sys with beta = 0):
 // every element row also gets alpha (h^2/8) C_ab, C_ab = sum_q N_a (v.dN_b)
 // one 8x8 table per launch.
+// The body of k_assemble_tile for tile `bid`; xzero (nullable): a solution
+// [n][s] whose rows of the tile are set to zero too.
 template <int S, int BND, bool ADV>
-__global__ __launch_bounds__(32 * S) void k_assemble_tile(int N, const double* __restrict__ kl_sqrt_lam,
-                                                           const int32_t* __restrict__ kl_triple,
-                                                           const double* __restrict__ kl_phi, int M, double kappa0,
-                                                           double sigma, double fsrc, double alpha, double vx,
-                                                           double vy, double vz, const double* __restrict__ xi,
-                                                           const int32_t* __restrict__ row_ptr,
-                                                           double* __restrict__ values, float* __restrict__ values32,
-                                                           double* __restrict__ rhs, void* __restrict__ dinv,
-                                                           double* __restrict__ bpart) {
+__device__ __forceinline__ void assemble_tile_body(int N, const double* __restrict__ kl_sqrt_lam,
+                                                   const int32_t* __restrict__ kl_triple,
+                                                   const double* __restrict__ kl_phi, int M, double kappa0,
+                                                   double sigma, double fsrc, double alpha, double vx, double vy,
+                                                   double vz, const double* __restrict__ xi,
+                                                   const int32_t* __restrict__ row_ptr, double* __restrict__ values,
+                                                   float* __restrict__ values32, double* __restrict__ rhs,
+                                                   void* __restrict__ dinv, double* __restrict__ bpart, int64_t bid,
+                                                   double* __restrict__ xzero) {
   using T = AsmTile<32, 2>;
   constexpr int SB = S, NT = T::R * S;
   constexpr int TX = T::TX, TY = T::TY, EX = T::EX, EY = T::EY, NE = T::NE;
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(32 * S) void k_assemble_tile(int N, const double* _
   const int n1 = N + 1;
   int64_t tile_id;
   int sg, x0, y0, z0;
-  tile_decode<TX, TY, T::TZ, 1>(N, blockIdx.x, &tile_id, &sg, &x0, &y0, &z0);
+  tile_decode<TX, TY, T::TZ, 1>(N, bid, &tile_id, &sg, &x0, &y0, &z0);
   const int e0 = 0;
   const double h = 1.0 / (double)N;
   tile_coefficients<NT, SB, EX, EY, T::EZ, true>(N, kl_sqrt_lam, kl_triple, kl_phi, M, kappa0, sigma, xi, e0,
@@ -361,6 +363,7 @@ __global__ __launch_bounds__(32 * S) void k_assemble_tile(int N, const double* _
         }
   }
   rhs[row * S + e] = bnd_row ? 0.0 : (double)nelem * (fsrc * h * h * h * 0.125);
+  if (xzero) xzero[row * S + e] = 0.0;
   if (BND == 1) ((float*)dinv)[row * S + e] = 1.0f / (float)dg;
   if (BND == 2) ((double*)dinv)[row * S + e] = 1.0 / dg;
   if (BND) qrow = sabs / dg;
@@ -379,6 +382,32 @@ __global__ __launch_bounds__(32 * S) void k_assemble_tile(int N, const double* _
       bpart[tile_id * S + threadIdx.x] = m;
     }
   }
+}
+
+template <int S, int BND, bool ADV>
+__global__ __launch_bounds__(32 * S) void k_assemble_tile(int N, const double* __restrict__ kl_sqrt_lam,
+                                                           const int32_t* __restrict__ kl_triple,
+                                                           const double* __restrict__ kl_phi, int M, double kappa0,
+                                                           double sigma, double fsrc, double alpha, double vx,
+                                                           double vy, double vz, const double* __restrict__ xi,
+                                                           const int32_t* __restrict__ row_ptr,
+                                                           double* __restrict__ values, float* __restrict__ values32,
+                                                           double* __restrict__ rhs, void* __restrict__ dinv,
+                                                           double* __restrict__ bpart) {
+  assemble_tile_body<S, BND, ADV>(N, kl_sqrt_lam, kl_triple, kl_phi, M, kappa0, sigma, fsrc, alpha, vx, vy, vz, xi,
+                                  row_ptr, values, values32, rhs, dinv, bpart, blockIdx.x, nullptr);
+}
+
+// The assemblies of every group of a batch in one launch: workgroup b takes
+// tile b - tile0 of group blk_grp[b] (FP64 values and load vector, the
+// solution set to zero).
+template <int S>
+__global__ __launch_bounds__(32 * S) void kb_assemble(const AsmGroupDev* __restrict__ groups,
+                                                       const int32_t* __restrict__ blk_grp, int M, double kappa0,
+                                                       double sigma, double fsrc) {
+  const AsmGroupDev& g = groups[blk_grp[blockIdx.x]];
+  assemble_tile_body<S, 0, false>(g.N, g.sq, g.tr, g.phi, M, kappa0, sigma, fsrc, 0.0, 0.0, 0.0, 0.0, g.xi, g.rp,
+                                  g.values, nullptr, g.rhs, nullptr, nullptr, (int64_t)blockIdx.x - g.tile0, g.x);
 }
 
 // Residual and Jacobian of the nonlinear problem (Sec. 4, Eq.
@@ -638,6 +667,27 @@ static constexpr int nl_sb(int S) { return S < 8 ? S : 8; }
 int64_t asm_tiles(int N, int S) {
   (void)S;
   return tiles_of<32, 2>(N);
+}
+
+ens_status batch_assemble_launch(int S, const AsmGroupDev* groups, const int32_t* blk_grp, int64_t blocks,
+                                 const ens_problem& prob, hipStream_t st) {
+  if (blocks <= 0) return ENS_OK;
+  switch (S) {
+#define ENS_BASM(SS)                                                                                         \
+  case SS:                                                                                                   \
+    hipLaunchKernelGGL(kb_assemble<SS>, dim3((unsigned)blocks), dim3(32 * SS), 0, st, groups, blk_grp, prob.M, \
+                       prob.kappa0, prob.sigma, prob.f);                                                     \
+    break;
+    ENS_BASM(8)
+    ENS_BASM(16)
+    ENS_BASM(32)
+#undef ENS_BASM
+    default:
+      set_error("batch ensemble size %d not compiled in (8, 16, 32)", S);
+      return ENS_E_UNSUPPORTED;
+  }
+  ENS_LAUNCH_CHECK();
+  return ENS_OK;
 }
 
 ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, const int32_t* tr, const double* phi,

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "cgcore.hpp"
+#include "mg.hpp"
 
 namespace ens {
 
@@ -317,9 +318,56 @@ static ens_status poll(int32_t* dev_count, hipStream_t st, int32_t* out) {
   return ENS_OK;
 }
 
+// Optional first work of a batch solve, enqueued on the solve's stream
+// before the CG set-up (the assembly of ens_assemble_solve_batch).
+struct Prologue {
+  const AsmGroupDev* groups = nullptr;  // device
+  const int32_t* blk_grp = nullptr;     // device
+  int64_t blocks = 0;
+  const ens_problem* prob = nullptr;
+};
+
+// The CG set-up of all groups: control blocks, D^-1, r = b - A x and its
+// norms, x zeroed where b is, the first direction and rho.
+template <int S, int NW>
+static void batch_setup(const BatchDev& bd, const Layout& L, int ng, double rtol, int max_iter, hipStream_t st) {
+  hipLaunchKernelGGL(kb_ctl_init, dim3((unsigned)(ng < 1024 ? ng : 1024)), dim3(64), 0, st, bd, ng, rtol, max_iter);
+  hipLaunchKernelGGL(kb_diag_inv<S>, dim3(2048), dim3(256), 0, st, bd, ng);
+  hipLaunchKernelGGL((kb_residual<S, NW>), dim3((unsigned)L.row_blocks), dim3(NW * 64), 0, st, bd, 1);
+  hipLaunchKernelGGL((kb_stage1<2 * S, 0>), dim3((unsigned)L.red_rows), dim3(256), 0, st, bd, 0);
+  hipLaunchKernelGGL((kb_final<S, 2, 0>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_START, 0, 0);
+  hipLaunchKernelGGL(kb_zero_where<S>, dim3(1024), dim3(256), 0, st, bd, ng);
+  hipLaunchKernelGGL(kb_cg_start<S>, dim3((unsigned)L.vec_blocks), dim3(256), 0, st, bd);
+  hipLaunchKernelGGL((kb_stage1<2 * S, 1>), dim3((unsigned)L.redv_rows), dim3(256), 0, st, bd, 0);
+  hipLaunchKernelGGL((kb_final<S, 2, 1>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_RHO, 0, 0);
+}
+
+// Capture `enqueue` on st into an executable graph.
+template <typename F>
+static ens_status capture(hipStream_t st, F&& enqueue, hipGraph_t* graph, hipGraphExec_t* exec) {
+  ENS_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  ens_status rc = enqueue();
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipStreamEndCapture(st, graph);
+  if (rc != ENS_OK || e1 != hipSuccess || e2 != hipSuccess) {
+    if (*graph) (void)hipGraphDestroy(*graph);
+    *graph = nullptr;
+    if (rc == ENS_OK) set_error("graph capture failed: %s / %s", hipGetErrorString(e1), hipGetErrorString(e2));
+    return rc != ENS_OK ? rc : ENS_E_HIP;
+  }
+  hipError_t e3 = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+  if (e3 != hipSuccess) {
+    (void)hipGraphDestroy(*graph);
+    *graph = nullptr;
+    set_error("graph instantiation failed: %s", hipGetErrorString(e3));
+    return ENS_E_HIP;
+  }
+  return ENS_OK;
+}
+
 template <int S, int NW>
 static ens_status solve_batch(const ens_group* groups, int ng, const ens_batch_opts& o, void* ws, size_t ws_bytes,
-                              hipStream_t user) {
+                              hipStream_t user, const Prologue* pro = nullptr) {
   Layout L;
   ens_status rc = plan<S, NW>(groups, ng, L);
   if (rc != ENS_OK) return rc;
@@ -350,62 +398,62 @@ static ens_status solve_batch(const ens_group* groups, int ng, const ens_batch_o
                              hipMemcpyHostToDevice, st));
   const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
   const int chunk = o.check_every > 0 ? o.check_every : 16;
-  hipLaunchKernelGGL(kb_ctl_init, dim3((unsigned)(ng < 1024 ? ng : 1024)), dim3(64), 0, st, bd, ng, o.rtol, max_iter);
-  hipLaunchKernelGGL(kb_diag_inv<S>, dim3(2048), dim3(256), 0, st, bd, ng);
-  hipLaunchKernelGGL((kb_residual<S, NW>), dim3((unsigned)L.row_blocks), dim3(NW * 64), 0, st, bd, 1);
-  hipLaunchKernelGGL((kb_stage1<2 * S, 0>), dim3((unsigned)L.red_rows), dim3(256), 0, st, bd, 0);
-  hipLaunchKernelGGL((kb_final<S, 2, 0>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_START, 0, 0);
-  hipLaunchKernelGGL(kb_zero_where<S>, dim3(1024), dim3(256), 0, st, bd, ng);
-  hipLaunchKernelGGL(kb_cg_start<S>, dim3((unsigned)L.vec_blocks), dim3(256), 0, st, bd);
-  hipLaunchKernelGGL((kb_stage1<2 * S, 1>), dim3((unsigned)L.redv_rows), dim3(256), 0, st, bd, 0);
-  hipLaunchKernelGGL((kb_final<S, 2, 1>), dim3((unsigned)ng), dim3(256), 0, st, bd, (int)OP_RHO, 0, 0);
-  ENS_LAUNCH_CHECK();
-
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  if (o.use_graph) {
-    ENS_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  // first: [assembly,] set-up, one chunk of iterations, the active count;
+  // then: one chunk and the count, repeated until no sample is active
+  auto first = [&]() -> ens_status {
+    if (pro) {
+      ens_status r2 = batch_assemble_launch(S, pro->groups, pro->blk_grp, pro->blocks, *pro->prob, st);
+      if (r2 != ENS_OK) return r2;
+    }
+    batch_setup<S, NW>(bd, L, ng, o.rtol, max_iter, st);
     for (int k = 0; k < chunk; ++k) batch_iteration<S, NW>(bd, L, ng, st);
     hipLaunchKernelGGL(kb_count, dim3(1), dim3(256), 0, st, bd, ng, dcount);
-    hipError_t e1 = hipGetLastError();
-    hipError_t e2 = hipStreamEndCapture(st, &graph);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      set_error("graph capture failed: %s / %s", hipGetErrorString(e1), hipGetErrorString(e2));
-      return ENS_E_HIP;
-    }
-    hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e3 != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      set_error("graph instantiation failed: %s", hipGetErrorString(e3));
-      return ENS_E_HIP;
+    return ENS_OK;
+  };
+  auto next = [&]() -> ens_status {
+    for (int k = 0; k < chunk; ++k) batch_iteration<S, NW>(bd, L, ng, st);
+    hipLaunchKernelGGL(kb_count, dim3(1), dim3(256), 0, st, bd, ng, dcount);
+    return ENS_OK;
+  };
+  hipGraph_t g_first = nullptr, g_next = nullptr;
+  hipGraphExec_t x_first = nullptr, x_next = nullptr;
+  auto release = [&]() {
+    if (x_first) (void)hipGraphExecDestroy(x_first);
+    if (g_first) (void)hipGraphDestroy(g_first);
+    if (x_next) (void)hipGraphExecDestroy(x_next);
+    if (g_next) (void)hipGraphDestroy(g_next);
+  };
+  if (o.use_graph) {
+    rc = capture(st, first, &g_first, &x_first);
+    if (rc == ENS_OK) rc = capture(st, next, &g_next, &x_next);
+    if (rc != ENS_OK) {
+      release();
+      return rc;
     }
   }
   ens_status out = ENS_OK;
   for (int k0 = 0; k0 < max_iter; k0 += chunk) {
     if (o.use_graph) {
-      hipError_t e = hipGraphLaunch(exec, st);
+      hipError_t e = hipGraphLaunch(k0 == 0 ? x_first : x_next, st);
       if (e != hipSuccess) {
         set_error("graph launch failed: %s", hipGetErrorString(e));
         out = ENS_E_HIP;
         break;
       }
     } else {
-      for (int k = 0; k < chunk; ++k) batch_iteration<S, NW>(bd, L, ng, st);
-      hipLaunchKernelGGL(kb_count, dim3(1), dim3(256), 0, st, bd, ng, dcount);
+      out = k0 == 0 ? first() : next();
       hipError_t e = hipGetLastError();
-      if (e != hipSuccess) {
+      if (out == ENS_OK && e != hipSuccess) {
         set_error("launch failed: %s", hipGetErrorString(e));
         out = ENS_E_HIP;
-        break;
       }
+      if (out != ENS_OK) break;
     }
     int32_t act = 0;
     out = poll(dcount, st, &act);
     if (out != ENS_OK || act == 0) break;
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
+  release();
   if (out != ENS_OK) return out;
   // true residuals
   hipLaunchKernelGGL((kb_residual<S, NW>), dim3((unsigned)L.row_blocks), dim3(NW * 64), 0, st, bd, 0);
@@ -429,6 +477,59 @@ static ens_status solve_batch(const ens_group* groups, int ng, const ens_batch_o
       if (s.status != ENS_SAMPLE_CONVERGED) agg = ENS_W_NOT_CONVERGED;
     }
   return agg;
+}
+
+// ens_assemble_solve_batch: the groups' assembly descriptors and the
+// workgroup -> group table of the flat assembly launch follow the solver's
+// workspace; need != nullptr: sizes only.
+template <int S, int NW>
+static ens_status assemble_solve(const ens_group* groups, const ens_group_input* in, int ng, const ens_problem& prob,
+                                 const ens_batch_opts& o, void* ws, size_t ws_bytes, hipStream_t user, size_t* need) {
+  Layout L;
+  ens_status rc = plan<S, NW>(groups, ng, L);
+  if (rc != ENS_OK) return rc;
+  std::vector<AsmGroupDev> ag(ng);
+  std::vector<int32_t> bg;
+  int64_t blocks = 0;
+  for (int i = 0; i < ng; ++i) {
+    ENS_ARG_CHECK(in[i].kl && in[i].xi, "null assembly input");
+    int64_t n = 0, nnz = 0;
+    rc = ens_mesh_sizes(in[i].N, &n, &nnz, nullptr);
+    if (rc != ENS_OK) return rc;
+    ENS_ARG_CHECK(groups[i].graph->n == n && groups[i].graph->nnz == nnz, "group graph is not its mesh's graph");
+    AsmGroupDev& d = ag[i];
+    d.N = in[i].N;
+    d.tile0 = blocks;
+    kl_parts(in[i].kl, prob.M, &d.sq, &d.tr, &d.phi);
+    d.xi = in[i].xi;
+    d.rp = groups[i].graph->row_ptr;
+    d.values = const_cast<double*>(groups[i].values);
+    d.rhs = const_cast<double*>(groups[i].b);
+    d.x = groups[i].x;
+    const int64_t t = asm_tiles(in[i].N, S);
+    bg.insert(bg.end(), (size_t)t, i);
+    blocks += t;
+  }
+  const size_t off_ag = r256(L.bytes), off_bg = off_ag + r256(sizeof(AsmGroupDev) * ng);
+  const size_t total = off_bg + r256(sizeof(int32_t) * (size_t)blocks);
+  if (need) {
+    *need = total;
+    return ENS_OK;
+  }
+  if (ws_bytes < total) {
+    set_error("batch workspace of %zu bytes is smaller than the %zu required", ws_bytes, total);
+    return ENS_E_NOMEM;
+  }
+  char* w = (char*)ws;
+  ENS_HIP_TRY(hipMemcpyAsync(w + off_ag, ag.data(), sizeof(AsmGroupDev) * ng, hipMemcpyHostToDevice, user));
+  ENS_HIP_TRY(hipMemcpyAsync(w + off_bg, bg.data(), sizeof(int32_t) * bg.size(), hipMemcpyHostToDevice, user));
+  Prologue pro;
+  pro.groups = (const AsmGroupDev*)(w + off_ag);
+  pro.blk_grp = (const int32_t*)(w + off_bg);
+  pro.blocks = blocks;
+  pro.prob = &prob;
+  // the host tables stay alive until solve_batch has synchronised
+  return solve_batch<S, NW>(groups, ng, o, ws, ws_bytes, user, &pro);
 }
 
 static bool tile_ok(int t) { return t == 2 || t == 4 || t == 8; }
@@ -457,11 +558,52 @@ static ens_status dispatch(const ens_group* g, int ng, int32_t s, const ens_batc
   }
 }
 
+template <int S>
+static ens_status dispatch_asm_tile(const ens_group* g, const ens_group_input* in, int ng, const ens_problem& pr,
+                                    const ens_batch_opts& o, void* ws, size_t b, hipStream_t st, size_t* need) {
+  switch (o.tile) {
+    case 2: return assemble_solve<S, 2>(g, in, ng, pr, o, ws, b, st, need);
+    case 4: return assemble_solve<S, 4>(g, in, ng, pr, o, ws, b, st, need);
+    default: return assemble_solve<S, 8>(g, in, ng, pr, o, ws, b, st, need);
+  }
+}
+
+static ens_status dispatch_asm(const ens_group* g, const ens_group_input* in, int ng, int32_t s,
+                               const ens_problem& pr, const ens_batch_opts& o, void* ws, size_t b, hipStream_t st,
+                               size_t* need) {
+  switch (s) {
+    case 8: return dispatch_asm_tile<8>(g, in, ng, pr, o, ws, b, st, need);
+    case 16: return dispatch_asm_tile<16>(g, in, ng, pr, o, ws, b, st, need);
+    case 32: return dispatch_asm_tile<32>(g, in, ng, pr, o, ws, b, st, need);
+    default: set_error("batch ensemble size %d not compiled in (8, 16, 32)", s); return ENS_E_UNSUPPORTED;
+  }
+}
+
 }  // namespace ens
 
 using namespace ens;
 
 extern "C" {
+
+ens_status ens_assemble_solve_batch_workspace_bytes(const ens_group* groups, const ens_group_input* inputs,
+                                                    int32_t n_groups, int32_t s, const ens_problem* problem,
+                                                    const ens_batch_opts* opts, size_t* bytes) {
+  ENS_ARG_CHECK(groups && inputs && n_groups >= 1 && problem && opts && bytes, "bad batch arguments");
+  ENS_ARG_CHECK(tile_ok(opts->tile), "tile must be 2, 4 or 8 wavefronts");
+  ENS_ARG_CHECK(problem->M >= 0 && problem->M <= 16, "problem->M out of range");
+  return dispatch_asm(groups, inputs, n_groups, s, *problem, *opts, nullptr, 0, nullptr, bytes);
+}
+
+ens_status ens_assemble_solve_batch(const ens_group* groups, const ens_group_input* inputs, int32_t n_groups,
+                                    int32_t s, const ens_problem* problem, const ens_batch_opts* opts,
+                                    void* workspace, size_t ws_bytes, hipStream_t stream) {
+  ENS_ARG_CHECK(groups && inputs && n_groups >= 1 && problem && opts && workspace, "bad batch arguments");
+  ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
+  ENS_ARG_CHECK(tile_ok(opts->tile), "tile must be 2, 4 or 8 wavefronts");
+  ENS_ARG_CHECK(opts->rtol >= 0.0, "rtol must be >= 0");
+  ENS_ARG_CHECK(problem->M >= 0 && problem->M <= 16, "problem->M out of range");
+  return dispatch_asm(groups, inputs, n_groups, s, *problem, *opts, workspace, ws_bytes, stream, nullptr);
+}
 
 ens_status ens_batch_workspace_bytes(const ens_group* groups, int32_t n_groups, int32_t s, const ens_batch_opts* opts,
                                      size_t* bytes) {

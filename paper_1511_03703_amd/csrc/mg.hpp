@@ -57,6 +57,23 @@ ens_status assemble_launch(int N, const ens_graph* graph, const double* sq, cons
                            const double* adv = nullptr);
 void kl_parts(const void* kl, int M, const double** sq, const int32_t** tr, const double** phi);
 
+// One group of a batched assembly: its mesh, KL table parts, KL inputs
+// [s][M], graph, and the buffers it fills (FP64 values, load vector, the
+// solution set to zero); tile0 is its first workgroup in the flat launch.
+struct AsmGroupDev {
+  int32_t N;
+  int64_t tile0;
+  const double *sq, *phi;
+  const int32_t* tr;
+  const double* xi;
+  const int32_t* rp;
+  double *values, *rhs, *x;
+};
+// The assemblies of a batch's groups in one launch of `blocks` workgroups
+// (the groups' asm_tiles summed); blk_grp [blocks] maps workgroup -> group.
+ens_status batch_assemble_launch(int S, const AsmGroupDev* groups, const int32_t* blk_grp, int64_t blocks,
+                                 const ens_problem& prob, hipStream_t st);
+
 int mg_levels(int N, int* Ns);
 // 0: buffer unknown; 1: built (ens_mg_build); 2: set up (ens_mg_setup).
 int mg_stage(const ens_mg* mg);

@@ -62,6 +62,10 @@ class ens_group(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("stats", ctypes.POINTER(ens_cg_stat))]
 
 
+class ens_group_input(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("kl", ctypes.c_void_p), ("xi", ctypes.c_void_p)]
+
+
 class ens_nl_problem(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32), ("L", ctypes.c_double), ("kappa0", ctypes.c_double),
                 ("sigma", ctypes.c_double), ("f", ctypes.c_double), ("alpha", ctypes.c_double),
@@ -145,6 +149,11 @@ _SIGS = [
     ("ens_relayout", _I32, [_P, _P, _I64, _I32, _I32, _P]),
     ("ens_batch_workspace_bytes", _I32, [ctypes.POINTER(ens_group), _I32, _I32, ctypes.POINTER(ens_batch_opts),
                                          ctypes.POINTER(_SZ)]),
+    ("ens_assemble_solve_batch_workspace_bytes", _I32, [ctypes.POINTER(ens_group), ctypes.POINTER(ens_group_input),
+                                                         _I32, _I32, ctypes.POINTER(ens_problem),
+                                                         ctypes.POINTER(ens_batch_opts), ctypes.POINTER(_SZ)]),
+    ("ens_assemble_solve_batch", _I32, [ctypes.POINTER(ens_group), ctypes.POINTER(ens_group_input), _I32, _I32,
+                                        ctypes.POINTER(ens_problem), ctypes.POINTER(ens_batch_opts), _P, _SZ, _P]),
     ("ens_solve_batch", _I32, [ctypes.POINTER(ens_group), _I32, _I32, ctypes.POINTER(ens_batch_opts), _P, _SZ, _P]),
     ("ens_batch_autotune", _I32, [_P, _I32, ctypes.POINTER(ens_problem), _P, _P, _I32, _P, _I32,
                                   ctypes.POINTER(ens_batch_opts), ctypes.c_char_p, ctypes.POINTER(_I32),
@@ -870,6 +879,41 @@ def solve_batch(groups, s, opts: ens_batch_opts | None = None, workspace=None, s
         workspace = torch.empty(nb.value, dtype=torch.uint8, device=groups[0][1].device)
     rc = _check(lib().ens_solve_batch(arr, len(groups), s, ctypes.byref(opts), _ptr(workspace), workspace.numel(),
                                       _stream(stream)), "ens_solve_batch", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
+    return [_stats_list(st, s) for st in stats], rc, workspace
+
+
+def assemble_solve_batch(groups, inputs, s, M, sigma, opts: ens_batch_opts | None = None, workspace=None,
+                         L=1.0, kappa0=1.0, f=1.0, stream=None, strict_workspace=False):
+    """Assemble and solve a wave of groups in one call (ens_assemble_solve_batch).
+    groups: list of (Graph, values [nnz][s], b [n][s], x [n][s]) -- values,
+    b and x are written; inputs: list of (N, kl table, xi [s][M] device).
+    Returns (per-group stats lists, status, workspace)."""
+    if opts is None:
+        opts = batch_opts()
+    keep = []
+    arr = (ens_group * len(groups))()
+    inp = (ens_group_input * len(groups))()
+    stats = []
+    for i, ((g, v, b, x), (N, kl, xi)) in enumerate(zip(groups, inputs)):
+        gc = g.c()
+        st = (ens_cg_stat * s)()
+        keep.append(gc)
+        stats.append(st)
+        arr[i] = ens_group(ctypes.pointer(gc), v.data_ptr(), b.data_ptr(), x.data_ptr(), st)
+        inp[i] = ens_group_input(int(N), kl.data_ptr(), xi.data_ptr())
+    prob = ens_problem(M, L, kappa0, sigma, f)
+    nb = _SZ()
+    _check(lib().ens_assemble_solve_batch_workspace_bytes(arr, inp, len(groups), s, ctypes.byref(prob),
+                                                          ctypes.byref(opts), ctypes.byref(nb)),
+           "ens_assemble_solve_batch_workspace_bytes")
+    if workspace is not None and workspace.numel() < nb.value and strict_workspace:
+        raise EnsError(ENS_E_NOMEM, "assemble_solve_batch",
+                       f"workspace of {workspace.numel()} bytes, {nb.value} required")
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=groups[0][1].device)
+    rc = _check(lib().ens_assemble_solve_batch(arr, inp, len(groups), s, ctypes.byref(prob), ctypes.byref(opts),
+                                               _ptr(workspace), workspace.numel(), _stream(stream)),
+                "ens_assemble_solve_batch", allow=(ENS_OK, ENS_W_NOT_CONVERGED))
     return [_stats_list(st, s) for st in stats], rc, workspace
 
 

@@ -239,3 +239,45 @@ def test_pool_waves_equal_one_batch(E):
     assert stats_pool == stats_one
     for i in range(G):
         assert torch.equal(xs[i], groups[i][3])
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("s", [8, 32])
+def test_assemble_solve_batch_equals_assembly_then_batch(E, orc, s, use_graph):
+    """ens_assemble_solve_batch (one flat assembly launch in the first
+    captured graph) against ens_assemble per group + ens_solve_batch: the
+    same kernels' arithmetic, so values, loads, solutions and statistics are
+    bitwise equal; every group against the oracle as well."""
+    meshes, M, sigma, rtol = [6, 10, 4, 8, 10, 3], 10, 0.3, 1e-10
+    xis = [draw_xi(900 + 5 * i + s, s, M) for i in range(len(meshes))]
+    ref = [_group(E, N, s, M, sigma, xi) for N, xi in zip(meshes, xis)]
+    opts = E.batch_opts(rtol=rtol, check_every=5, tile=4, use_graph=use_graph)
+    stats_ref, rc_ref, _ = E.solve_batch(ref, s, opts)
+    groups, inputs = [], []
+    for N, xi, r in zip(meshes, xis, ref):
+        g, kl = _GRAPHS[(N, M)]
+        # poison the outputs: the call must write every entry
+        groups.append([g, torch.full_like(r[1], np.nan), torch.full_like(r[2], np.nan),
+                       torch.full_like(r[3], np.nan)])
+        inputs.append((N, kl, torch.as_tensor(xi, device=DEV)))
+    stats, rc, _ = E.assemble_solve_batch(groups, inputs, s, M, sigma, opts)
+    assert rc == rc_ref == E.ENS_OK
+    for gr, r, st, st_ref in zip(groups, ref, stats, stats_ref):
+        assert torch.equal(gr[1], r[1]) and torch.equal(gr[2], r[2]) and torch.equal(gr[3], r[3])
+        assert st == st_ref
+    for (N, xi, gr, st) in zip(meshes, xis, groups, stats):
+        _oracle_check(orc, N, M, sigma, xi, _np(gr[3]), st, rtol)
+
+
+def test_assemble_solve_batch_errors(E):
+    N, s, M = 4, 8, 10
+    g, kl = E.graph_build(N), E.kl_build(N, M)
+    v = torch.empty(((3 * N + 1) ** 3, s), dtype=torch.float64, device=DEV)
+    b = torch.empty(((N + 1) ** 3, s), dtype=torch.float64, device=DEV)
+    x = torch.empty_like(b)
+    xi = torch.as_tensor(draw_xi(950, s, M), device=DEV)
+    with pytest.raises(E.EnsError):   # the input's mesh is not the graph's
+        E.assemble_solve_batch([(g, v, b, x)], [(N + 1, kl, xi)], s, M, 0.3)
+    with pytest.raises(E.EnsError):   # s = 4 is not a batch size
+        E.assemble_solve_batch([(g, v[:, :4].contiguous(), b[:, :4].contiguous(), x[:, :4].contiguous())],
+                               [(N, kl, xi[:4].contiguous())], 4, M, 0.3)
