@@ -388,13 +388,22 @@ ens_status ens_assemble_solve_batch(const ens_group* groups, const ens_group_inp
  * (samples/s, index a*nt + c).  With scores NULL and an entry for the same
  * meshes, problem and options in cache_path (nullable; a text file of lines
  * "key s tile", the last one wins), the cached pair is returned without
- * trials; every completed search appends its result.  Allocates the trial
- * buffers with hipMalloc (about 32 * 8 * (nnz + 3 n) bytes per mesh) and
- * frees them before returning; synchronises. */
+ * trials (workspace may then be NULL); every completed search appends its
+ * result.  The trial buffers (each mesh's graph, KL table and 32 samples'
+ * values, b and x, then the largest solver workspace of the candidates)
+ * live in the caller-owned device `workspace` (256-byte aligned) of
+ * ws_bytes >= ens_batch_autotune_workspace_bytes(...) bytes, about
+ * 32 * 8 * (nnz + 3 n) bytes per mesh; the library allocates no device
+ * memory.  Synchronises (the timing of each trial needs it); on an error
+ * the stream is drained before returning. */
+ens_status ens_batch_autotune_workspace_bytes(const int32_t* meshes, int32_t nm, const ens_problem* problem,
+                                              const int32_t* s_cand, int32_t ns, const int32_t* tile_cand,
+                                              int32_t nt, const ens_batch_opts* base, size_t* bytes);
 ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, const ens_problem* problem, const double* xi_host,
                               const int32_t* s_cand, int32_t ns, const int32_t* tile_cand, int32_t nt,
                               const ens_batch_opts* base, const char* cache_path, int32_t* best_s,
-                              int32_t* best_tile, double* scores, hipStream_t stream);
+                              int32_t* best_tile, double* scores, void* workspace, size_t ws_bytes,
+                              hipStream_t stream);
 
 /* ------------------------------------------------------------ multigrid */
 

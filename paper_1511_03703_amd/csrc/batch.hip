@@ -671,16 +671,72 @@ struct TrialMesh {
   ens_graph g{};
 };
 
-}  // namespace ens
+constexpr int kTrial = 32;  // samples per mesh in every trial
 
-extern "C" ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, const ens_problem* prob,
-                                         const double* xi_host, const int32_t* s_cand, int32_t ns,
-                                         const int32_t* tile_cand, int32_t nt, const ens_batch_opts* base,
-                                         const char* cache_path, int32_t* best_s, int32_t* best_tile,
-                                         double* scores, hipStream_t stream) {
-  ENS_ARG_CHECK(meshes && nm >= 1 && prob && xi_host && s_cand && ns >= 1 && tile_cand && nt >= 1 && base,
-                "bad arguments");
-  ENS_ARG_CHECK(best_s && best_tile && base->rtol >= 0.0, "bad arguments");
+// The autotuner's caller-owned workspace: each mesh's trial buffers at
+// 256-byte aligned offsets from `base`, then the largest batch-solver
+// workspace any candidate needs.  With base == nullptr only the sizes are
+// formed (the solver's need depends on the shapes alone, so its plan runs
+// on the offsets themselves).
+static ens_status tune_layout(char* base, const int32_t* meshes, int nm, const ens_problem& pr,
+                              const int32_t* s_cand, int ns, const int32_t* tile_cand, int nt,
+                              const ens_batch_opts& o0, std::vector<TrialMesh>& t, char** ws, size_t* ws_need,
+                              size_t* total) {
+  // a non-null stand-in address keeps the plan's pointer checks meaningful
+  // when only sizes are wanted; nothing is dereferenced then
+  char* b0 = base ? base : (char*)(uintptr_t)256;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = b0 + off;
+    off += r256(bytes);
+    return p;
+  };
+  const int M = pr.M;
+  t.assign(nm, TrialMesh{});
+  for (int i = 0; i < nm; ++i) {
+    TrialMesh& m = t[i];
+    m.N = meshes[i];
+    ens_status rc = ens_mesh_sizes(m.N, &m.n, &m.nnz, nullptr);
+    if (rc != ENS_OK) return rc;
+    size_t klb = 0;
+    rc = ens_kl_bytes(m.N, M, &klb);
+    if (rc != ENS_OK) return rc;
+    m.rp = (int32_t*)take(sizeof(int32_t) * (m.n + 1));
+    m.ci = (int32_t*)take(sizeof(int32_t) * m.nnz);
+    m.kl = take(klb);
+    m.xi = (double*)take(sizeof(double) * kTrial * (M > 0 ? M : 1));
+    m.vals = (double*)take(sizeof(double) * kTrial * m.nnz);
+    m.b = (double*)take(sizeof(double) * kTrial * m.n);
+    m.x = (double*)take(sizeof(double) * kTrial * m.n);
+    m.g = ens_graph{(int32_t)m.n, m.nnz, m.rp, m.ci};
+  }
+  size_t need = 0;
+  std::vector<ens_cg_stat> stats((size_t)kTrial);
+  for (int a = 0; a < ns; ++a) {
+    const int s = s_cand[a];
+    std::vector<ens_group> gr;
+    for (int i = 0; i < nm; ++i)
+      for (int j = 0; j < kTrial / s; ++j)
+        gr.push_back(ens_group{&t[i].g, t[i].vals, t[i].b, t[i].x, stats.data()});
+    for (int c = 0; c < nt; ++c) {
+      ens_batch_opts o = o0;
+      o.tile = tile_cand[c];
+      size_t nb = 0;
+      ens_status rc = ens_batch_workspace_bytes(gr.data(), (int)gr.size(), s, &o, &nb);
+      if (rc != ENS_OK) return rc;
+      need = nb > need ? nb : need;
+    }
+  }
+  *ws = take(need);
+  *ws_need = need;
+  *total = off;
+  return ENS_OK;
+}
+
+static ens_status tune_check(const int32_t* meshes, int32_t nm, const ens_problem* prob, const int32_t* s_cand,
+                             int32_t ns, const int32_t* tile_cand, int32_t nt, const ens_batch_opts* base) {
+  ENS_ARG_CHECK(meshes && nm >= 1 && prob && s_cand && ns >= 1 && tile_cand && nt >= 1 && base, "bad arguments");
+  ENS_ARG_CHECK(base->rtol >= 0.0, "rtol must be >= 0");
   for (int i = 0; i < nm; ++i) ENS_ARG_CHECK(meshes[i] >= 1, "mesh sizes must be >= 1");
   for (int i = 0; i < ns; ++i)
     if (s_cand[i] != 8 && s_cand[i] != 16 && s_cand[i] != 32) {
@@ -688,6 +744,32 @@ extern "C" ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, cons
       return ENS_E_UNSUPPORTED;
     }
   for (int i = 0; i < nt; ++i) ENS_ARG_CHECK(tile_ok(tile_cand[i]), "tile must be 2, 4 or 8");
+  return ENS_OK;
+}
+
+}  // namespace ens
+
+extern "C" ens_status ens_batch_autotune_workspace_bytes(const int32_t* meshes, int32_t nm,
+                                                         const ens_problem* prob, const int32_t* s_cand,
+                                                         int32_t ns, const int32_t* tile_cand, int32_t nt,
+                                                         const ens_batch_opts* base, size_t* bytes) {
+  ENS_ARG_CHECK(bytes, "bad arguments");
+  ens_status rc = tune_check(meshes, nm, prob, s_cand, ns, tile_cand, nt, base);
+  if (rc != ENS_OK) return rc;
+  std::vector<TrialMesh> t;
+  char* ws = nullptr;
+  size_t need = 0;
+  return tune_layout(nullptr, meshes, nm, *prob, s_cand, ns, tile_cand, nt, *base, t, &ws, &need, bytes);
+}
+
+extern "C" ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, const ens_problem* prob,
+                                         const double* xi_host, const int32_t* s_cand, int32_t ns,
+                                         const int32_t* tile_cand, int32_t nt, const ens_batch_opts* base,
+                                         const char* cache_path, int32_t* best_s, int32_t* best_tile,
+                                         double* scores, void* workspace, size_t ws_bytes, hipStream_t stream) {
+  ens_status rc = tune_check(meshes, nm, prob, s_cand, ns, tile_cand, nt, base);
+  if (rc != ENS_OK) return rc;
+  ENS_ARG_CHECK(xi_host && best_s && best_tile, "bad arguments");
   const std::string key = tune_key(meshes, nm, *prob, *base);
   int cs = 0, ct = 0;
   if (!scores && cache_lookup(cache_path, key, &cs, &ct)) {
@@ -695,14 +777,20 @@ extern "C" ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, cons
     *best_tile = ct;
     return ENS_OK;
   }
-  constexpr int kTrial = 32;  // samples per mesh in every trial
+  ENS_ARG_CHECK(workspace, "the trials need a workspace (ens_batch_autotune_workspace_bytes)");
+  ENS_ARG_CHECK(((uintptr_t)workspace & 255u) == 0, "workspace must be 256-byte aligned");
   const int M = prob->M;
-  std::vector<TrialMesh> t(nm);
+  std::vector<TrialMesh> t;
+  char* ws = nullptr;
+  size_t ws_need = 0, total = 0;
+  rc = tune_layout((char*)workspace, meshes, nm, *prob, s_cand, ns, tile_cand, nt, *base, t, &ws, &ws_need, &total);
+  if (rc != ENS_OK) return rc;
+  if (ws_bytes < total) {
+    set_error("autotune workspace too small: %zu < %zu bytes", ws_bytes, total);
+    return ENS_E_ARG;
+  }
   std::vector<ens_cg_stat> stats((size_t)nm * kTrial);
-  void* ws = nullptr;
-  size_t ws_have = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  ens_status rc = ENS_OK;
   double best = -1.0;
 #define TUNE_TRY(expr)                                             \
   do {                                                             \
@@ -717,26 +805,12 @@ extern "C" ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, cons
   TUNE_TRY(hipEventCreate(&e1));
   for (int i = 0; i < nm; ++i) {
     TrialMesh& m = t[i];
-    m.N = meshes[i];
-    rc = ens_mesh_sizes(m.N, &m.n, &m.nnz, nullptr);
-    if (rc != ENS_OK) goto done;
-    size_t klb = 0;
-    rc = ens_kl_bytes(m.N, M, &klb);
-    if (rc != ENS_OK) goto done;
-    TUNE_TRY(hipMalloc(&m.rp, sizeof(int32_t) * (m.n + 1)));
-    TUNE_TRY(hipMalloc(&m.ci, sizeof(int32_t) * m.nnz));
-    TUNE_TRY(hipMalloc(&m.kl, klb));
-    TUNE_TRY(hipMalloc(&m.xi, sizeof(double) * kTrial * (M > 0 ? M : 1)));
-    TUNE_TRY(hipMalloc(&m.vals, sizeof(double) * kTrial * m.nnz));
-    TUNE_TRY(hipMalloc(&m.b, sizeof(double) * kTrial * m.n));
-    TUNE_TRY(hipMalloc(&m.x, sizeof(double) * kTrial * m.n));
     if (M > 0)
       TUNE_TRY(hipMemcpyAsync(m.xi, xi_host + (size_t)i * kTrial * M, sizeof(double) * kTrial * M,
                               hipMemcpyHostToDevice, stream));
     rc = ens_graph_build(m.N, m.rp, m.ci, stream);
     if (rc == ENS_OK) rc = ens_kl_build(m.N, M, prob->L, m.kl, stream);
     if (rc != ENS_OK) goto done;
-    m.g = ens_graph{(int32_t)m.n, m.nnz, m.rp, m.ci};
   }
   for (int a = 0; a < ns; ++a) {
     const int s = s_cand[a];
@@ -755,22 +829,12 @@ extern "C" ens_status ens_batch_autotune(const int32_t* meshes, int32_t nm, cons
     for (int c = 0; c < nt; ++c) {
       ens_batch_opts o = *base;
       o.tile = tile_cand[c];
-      size_t need = 0;
-      rc = ens_batch_workspace_bytes(gr.data(), (int)gr.size(), s, &o, &need);
-      if (rc != ENS_OK) goto done;
-      if (need > ws_have) {
-        if (ws) (void)hipFree(ws);
-        ws = nullptr;
-        ws_have = 0;
-        TUNE_TRY(hipMalloc(&ws, need));
-        ws_have = need;
-      }
       float ms = 0.f;
       const int reps = (a == 0 && c == 0) ? 2 : 1;  // the very first solve also warms up
       for (int rep = 0; rep < reps; ++rep) {
         for (int i = 0; i < nm; ++i) TUNE_TRY(hipMemsetAsync(t[i].x, 0, sizeof(double) * kTrial * t[i].n, stream));
         TUNE_TRY(hipEventRecord(e0, stream));
-        rc = ens_solve_batch(gr.data(), (int)gr.size(), s, &o, ws, ws_have, stream);
+        rc = ens_solve_batch(gr.data(), (int)gr.size(), s, &o, ws, ws_need, stream);
         if (rc != ENS_OK && rc != ENS_W_NOT_CONVERGED) goto done;
         TUNE_TRY(hipEventRecord(e1, stream));
         TUNE_TRY(hipEventSynchronize(e1));
@@ -791,15 +855,6 @@ done:
 #undef TUNE_TRY
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  for (auto& m : t) {
-    (void)hipFree(m.rp);
-    (void)hipFree(m.ci);
-    (void)hipFree(m.kl);
-    (void)hipFree(m.xi);
-    (void)hipFree(m.vals);
-    (void)hipFree(m.b);
-    (void)hipFree(m.x);
-  }
-  if (ws) (void)hipFree(ws);
+  if (rc != ENS_OK) (void)hipStreamSynchronize(stream);  // no trial work left in flight on the caller's buffer
   return rc;
 }

@@ -155,9 +155,11 @@ _SIGS = [
     ("ens_assemble_solve_batch", _I32, [ctypes.POINTER(ens_group), ctypes.POINTER(ens_group_input), _I32, _I32,
                                         ctypes.POINTER(ens_problem), ctypes.POINTER(ens_batch_opts), _P, _SZ, _P]),
     ("ens_solve_batch", _I32, [ctypes.POINTER(ens_group), _I32, _I32, ctypes.POINTER(ens_batch_opts), _P, _SZ, _P]),
+    ("ens_batch_autotune_workspace_bytes", _I32, [_P, _I32, ctypes.POINTER(ens_problem), _P, _I32, _P, _I32,
+                                                  ctypes.POINTER(ens_batch_opts), ctypes.POINTER(_SZ)]),
     ("ens_batch_autotune", _I32, [_P, _I32, ctypes.POINTER(ens_problem), _P, _P, _I32, _P, _I32,
                                   ctypes.POINTER(ens_batch_opts), ctypes.c_char_p, ctypes.POINTER(_I32),
-                                  ctypes.POINTER(_I32), _P, _P]),
+                                  ctypes.POINTER(_I32), _P, _P, _SZ, _P]),
     ("ens_stream_copy", _I32, [_P, _P, _SZ, _P]),
     ("ens_stream_triad", _I32, [_P, _P, _P, _D, _I64, _P]),
     ("ens_stream_read", _I32, [_P, _SZ, _P, _P]),
@@ -934,11 +936,17 @@ def batch_autotune(meshes, M, sigma, xi_host, opts: ens_batch_opts | None = None
     scores = np.zeros(len(sc) * len(tc)) if want_scores else None
     bs, bt = _I32(), _I32()
     prob = ens_problem(M, L, kappa0, sigma, f)
+    need = _SZ(0)
+    _check(lib().ens_batch_autotune_workspace_bytes(m.ctypes.data, len(m), ctypes.byref(prob), sc.ctypes.data,
+                                                    len(sc), tc.ctypes.data, len(tc), ctypes.byref(opts),
+                                                    ctypes.byref(need)), "ens_batch_autotune_workspace_bytes")
+    ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device="cuda")
     _check(lib().ens_batch_autotune(m.ctypes.data, len(m), ctypes.byref(prob), xi.ctypes.data, sc.ctypes.data,
                                     len(sc), tc.ctypes.data, len(tc), ctypes.byref(opts),
                                     None if cache_path is None else str(cache_path).encode(), ctypes.byref(bs),
                                     ctypes.byref(bt), None if scores is None else scores.ctypes.data,
-                                    _stream(stream)), "ens_batch_autotune")
+                                    _ptr(ws), ws.numel(), _stream(stream)), "ens_batch_autotune")
+    del ws
     table = None
     if scores is not None:
         table = {(int(a), int(b)): float(scores[i * len(tc) + j]) for i, a in enumerate(sc) for j, b in enumerate(tc)}

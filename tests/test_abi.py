@@ -252,3 +252,42 @@ def test_noalloc_cg_refuses_sizes_beyond_its_scratch_without_gpu(E):
     assert st == E.ENS_E_NOMEM
     assert L.ens_cg_noalloc(ctypes.byref(gc), 5, ctypes.c_void_p(256), None, ctypes.c_void_p(512),
                             ctypes.c_void_p(768), ctypes.byref(opts), stats, None) == E.ENS_E_UNSUPPORTED
+
+
+def test_autotune_workspace_is_caller_owned_without_gpu(E):
+    L = E.lib()
+    pr = E.ens_problem(10, 1.0, 1.0, 0.2, 1.0)
+    o = E.batch_opts()
+    meshes = (ctypes.c_int32 * 2)(8, 12)
+    sc = (ctypes.c_int32 * 3)(8, 16, 32)
+    tc = (ctypes.c_int32 * 3)(2, 4, 8)
+    b = ctypes.c_size_t()
+    assert L.ens_batch_autotune_workspace_bytes(meshes, 2, ctypes.byref(pr), sc, 3, tc, 3, ctypes.byref(o),
+                                                ctypes.byref(b)) == E.ENS_OK
+    # at least the 32 trial samples' values, b and x of every mesh
+    trial = 0
+    for N in (8, 12):
+        n, nnz = (N + 1) ** 3, (3 * N + 1) ** 3
+        trial += 32 * 8 * (nnz + 2 * n)
+    assert b.value >= trial
+    one = ctypes.c_size_t()
+    assert L.ens_batch_autotune_workspace_bytes(meshes, 1, ctypes.byref(pr), sc, 3, tc, 3, ctypes.byref(o),
+                                                ctypes.byref(one)) == E.ENS_OK
+    assert 0 < one.value < b.value
+    # refused before any device work: no workspace, one too small, bad candidates
+    xi = (ctypes.c_double * (2 * 32 * 10))()
+    bs, bt = ctypes.c_int32(), ctypes.c_int32()
+    scores = (ctypes.c_double * 9)()
+    st = L.ens_batch_autotune(meshes, 2, ctypes.byref(pr), xi, sc, 3, tc, 3, ctypes.byref(o), None,
+                              ctypes.byref(bs), ctypes.byref(bt), scores, None, 0, None)
+    assert st == E.ENS_E_ARG and b"workspace" in L.ens_last_error()
+    st = L.ens_batch_autotune(meshes, 2, ctypes.byref(pr), xi, sc, 3, tc, 3, ctypes.byref(o), None,
+                              ctypes.byref(bs), ctypes.byref(bt), scores, ctypes.c_void_p(1 << 20), b.value - 1, None)
+    assert st == E.ENS_E_ARG and b"too small" in L.ens_last_error()
+    st = L.ens_batch_autotune(meshes, 2, ctypes.byref(pr), xi, sc, 3, tc, 3, ctypes.byref(o), None,
+                              ctypes.byref(bs), ctypes.byref(bt), scores, ctypes.c_void_p((1 << 20) + 16), b.value,
+                              None)
+    assert st == E.ENS_E_ARG and b"aligned" in L.ens_last_error()
+    bad = (ctypes.c_int32 * 1)(12)
+    assert L.ens_batch_autotune_workspace_bytes(meshes, 2, ctypes.byref(pr), bad, 1, tc, 3, ctypes.byref(o),
+                                                ctypes.byref(b)) == E.ENS_E_UNSUPPORTED
