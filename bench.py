@@ -480,6 +480,7 @@ def run_solve(args):
         e1.record()
         torch.cuda.synchronize()
         copy_gbs = 2.0 * na * 8 / (e0.elapsed_time(e1) / 5) / 1e6
+        write_gbs = write_ceiling(ta)
         del ta, tb, tc
         b_ens = spmv_bytes(w.n, w.nnz, w.s, wb)
         b_sc = spmv_bytes(w.n, w.nnz, 1, wb)
@@ -516,6 +517,7 @@ def run_solve(args):
             "triad_GBs": round(triad_gbs, 1),
             "read_GBs": round(read_gbs, 1),
             "copy_GBs": round(copy_gbs, 1),
+            "write_GBs": round(write_gbs, 1),
         }
         del xv, yv, x1, y1
 
@@ -1025,6 +1027,23 @@ def assembly_bytes(n, nnz, s, fp64=True, fp32=True, rhs=True, dinv32=False):
     return nnz * s * (8.0 * fp64 + 4.0 * fp32) + n * s * (8.0 * rhs + 4.0 * dinv32)
 
 
+def write_ceiling(buf):
+    """Write-only stream rate (GB/s) over the buffer: 2 untimed passes, 5
+    timed ones."""
+    import torch
+
+    from paper_1511_03703_amd import ens
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        ens.stream_write(buf, 1)
+    e0.record()
+    for _ in range(5):
+        ens.stream_write(buf, 2)
+    e1.record()
+    torch.cuda.synchronize()
+    return buf.numel() * buf.element_size() / (e0.elapsed_time(e1) / 5) / 1e6
+
+
 def run_assembly(args):
     """The two assembly kernels at the headline size (128^3, s = 32, the
     headline samples), each timed alone: the linear ensemble assembly of A
@@ -1094,6 +1113,14 @@ def run_assembly(args):
                      "avg_launch_ms": a["ms_per_launch"], "launches": a["launches"]},
         "kernels": out_k,
     }
+    del vals, v32, rhs, u, F
+    wb = torch.empty((4 << 30) // 8, dtype=torch.float64, device=dev)
+    wgbs = write_ceiling(wb)
+    del wb
+    out["context"] = {"write_GBs": round(wgbs, 1),
+                      "assemble_floor_ms_at_write_ceiling": round(a["bytes_per_launch"] / (wgbs * 1e6), 4),
+                      "assemble_frac_of_write_ceiling": round(a["GBs"] / wgbs, 4)}
+    log(f"write ceiling {wgbs:.1f} GB/s: assembly at {a['GBs'] / wgbs:.3f} of it")
     out.setdefault("env", host_env())
     print(json.dumps(out), flush=True)
 
@@ -1232,7 +1259,7 @@ def run_newton(args):
                "k_nl_assemble<32,8,*> (residual and Jacobian)": ens.K_NL_ASSEMBLE,
                "k_gm_spmv<32> (GMRES product w = A z)": ens.K_GM_SPMV,
                "k_gm_dots/k_gm_axpy<32> (Gram-Schmidt passes)": ens.K_GM_ORTH,
-               "k_assemble_tile<32,8,*> (the preconditioner's matrices, every level)": ens.K_ASSEMBLE}
+               "k_assemble_tile<32,*,true> (the preconditioner's matrices, every level)": ens.K_ASSEMBLE}
     prof = {k: ens.prof_query(v) for k, v in kernels.items()}
     per_kernel = {k: {"ms_per_step": round(p["total_ms"] / args.steps, 3), "launches": p["launches"],
                       "GBs": round(p["bytes"] / (p["total_ms"] * 1e-3) / 1e9, 1) if p["launches"] else None}

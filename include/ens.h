@@ -722,11 +722,17 @@ ens_status ens_stream_triad(double* a, const double* b, const double* c, double 
                             hipStream_t stream);
 /* Pure read stream of `bytes` bytes (multiple of 16, 16-byte aligned src),
  * the read-only bandwidth ceiling next to the copy and the triad: every
- * 16-byte chunk is read once and folded by XOR into one word per workgroup,
- * out (device) [ENS_STREAM_READ_BLOCKS] uint32 (only the first
- * min(ENS_STREAM_READ_BLOCKS, bytes / 4096) written).  Never synchronises. */
-#define ENS_STREAM_READ_BLOCKS 8192
+ * 16-byte chunk is read once, and the chunks of each ENS_STREAM_READ_CHUNK_BYTES
+ * piece are folded by XOR into one word, out (device)
+ * [ceil(bytes / ENS_STREAM_READ_CHUNK_BYTES)] uint32.  ENS_E_RANGE above
+ * 128 GiB.  Never synchronises. */
+#define ENS_STREAM_READ_CHUNK_BYTES 16384
 ens_status ens_stream_read(const void* src, size_t bytes, uint32_t* out, hipStream_t stream);
+/* Pure write stream: dst (device, 16-byte aligned) [bytes / 16] 16-byte
+ * chunks set to (value, value ^ 1, value ^ 2, value ^ 3) with ordinary
+ * stores, as the assemblies write their values; the write-only bandwidth
+ * ceiling.  bytes a multiple of 16.  Never synchronises. */
+ens_status ens_stream_write(void* dst, size_t bytes, uint32_t value, hipStream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
  * launch of the listed kernels while enabled.  Enabling creates a pool of

@@ -163,6 +163,7 @@ _SIGS = [
     ("ens_stream_copy", _I32, [_P, _P, _SZ, _P]),
     ("ens_stream_triad", _I32, [_P, _P, _P, _D, _I64, _P]),
     ("ens_stream_read", _I32, [_P, _SZ, _P, _P]),
+    ("ens_stream_write", _I32, [_P, _SZ, ctypes.c_uint32, _P]),
     ("ens_mlp_param_count", _I64, []),
     ("ens_mlp_workspace_bytes", _I32, [_I32, ctypes.POINTER(_SZ)]),
     ("ens_mlp_forward", _I32, [_P, _I32, _P, _P, _P, _SZ, _P]),
@@ -682,17 +683,28 @@ def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
     _check(lib().ens_stream_copy(_ptr(src), _ptr(dst), nb, _stream(stream)), "ens_stream_copy")
 
 
-STREAM_READ_BLOCKS = 8192
+STREAM_READ_CHUNK_BYTES = 16384
 
 
 def stream_read(src: torch.Tensor, out: torch.Tensor | None = None, stream=None):
     """Read every byte of src once (the read-only bandwidth ceiling); returns
-    the per-workgroup XOR words."""
-    if out is None:
-        out = torch.empty(STREAM_READ_BLOCKS, dtype=torch.int32, device=src.device)
+    the XOR word of every STREAM_READ_CHUNK_BYTES piece."""
     nb = src.numel() * src.element_size()
+    words = max(1, -(-nb // STREAM_READ_CHUNK_BYTES))
+    if out is None:
+        out = torch.empty(words, dtype=torch.int32, device=src.device)
+    if out.numel() < words:
+        raise ValueError(f"out must hold {words} words")
     _check(lib().ens_stream_read(_ptr(src), nb, _ptr(out), _stream(stream)), "ens_stream_read")
     return out
+
+
+def stream_write(dst: torch.Tensor, value: int = 0, stream=None):
+    """Write every byte of dst once (the write-only bandwidth ceiling):
+    16-byte chunks (value, value ^ 1, value ^ 2, value ^ 3) as uint32."""
+    nb = dst.numel() * dst.element_size()
+    _check(lib().ens_stream_write(_ptr(dst), nb, value & 0xFFFFFFFF, _stream(stream)), "ens_stream_write")
+    return dst
 
 
 def stream_triad(a, b, c, q: float, stream=None):

@@ -397,6 +397,44 @@ def test_stream_read_folds_every_word(E):
         words = rng.integers(0, 2 ** 32, nbytes // 4, dtype=np.uint64).astype(np.uint32)
         src = torch.as_tensor(words.view(np.int32), device=DEV)
         out = E.stream_read(src)
-        blocks = min(E.STREAM_READ_BLOCKS, (nbytes // 16 + 255) // 256)
-        got = np.bitwise_xor.reduce(_np(out)[:blocks].view(np.uint32))
-        assert got == np.bitwise_xor.reduce(words), nbytes
+        pieces = -(-nbytes // E.STREAM_READ_CHUNK_BYTES)
+        assert out.numel() == pieces
+        got = _np(out).view(np.uint32)
+        assert np.bitwise_xor.reduce(got) == np.bitwise_xor.reduce(words), nbytes
+        # each word folds exactly its own 16 KB piece
+        per = E.STREAM_READ_CHUNK_BYTES // 4
+        want = [np.bitwise_xor.reduce(words[k * per:(k + 1) * per]) for k in range(min(pieces, 64))]
+        assert np.array_equal(got[:len(want)], np.array(want, np.uint32)), nbytes
+
+
+def test_stream_copy_and_triad(E):
+    # the copy moves every 16-byte chunk, the triad forms a = b + q c per
+    # element (one rounding of the fused multiply-add or two: within an
+    # FP64 rounding of |b| + |q c| of each other), ragged sizes included
+    rng = np.random.default_rng(78)
+    for n in (1, 255, 257 * 256 + 3, 1 << 22):
+        b = rng.standard_normal(n)
+        c = rng.standard_normal(n)
+        tb, tc = _t(b), _t(c)
+        ta = torch.full((n + 32,), 5.0, dtype=torch.float64, device=DEV)
+        E.stream_triad(ta[:n], tb, tc, 0.75)
+        got = _np(ta)
+        assert (np.abs(got[:n] - (b + 0.75 * c)) <= 2.0 ** -52 * (np.abs(b) + np.abs(0.75 * c))).all(), n
+        assert (got[n:] == 5.0).all()
+        if n % 2 == 0:
+            dst = torch.full((n + 32,), -1.0, dtype=torch.float64, device=DEV)
+            E.stream_copy(tb, dst[:n])
+            got = _np(dst)
+            assert np.array_equal(got[:n], b) and (got[n:] == -1.0).all(), n
+
+
+def test_stream_write_sets_every_chunk(E):
+    # the write-only bandwidth kernel writes every 16-byte chunk, and only
+    # those of the buffer it is given (a guard region after it is untouched)
+    for nbytes in (16, 4096 * 3 + 16 * 7, 64 << 20):
+        buf = torch.full((nbytes // 4 + 64,), -7, dtype=torch.int32, device=DEV)
+        E.stream_write(buf[: nbytes // 4], 0x5A5A0000)
+        got = _np(buf).view(np.uint32)
+        want = np.tile(np.array([0x5A5A0000, 0x5A5A0001, 0x5A5A0002, 0x5A5A0003], np.uint32), nbytes // 16)
+        assert np.array_equal(got[: nbytes // 4], want), nbytes
+        assert (got[nbytes // 4:] == np.uint32(0xFFFFFFF9)).all(), nbytes
