@@ -169,27 +169,48 @@ __device__ inline void tile_coefficients(int N, const double* __restrict__ kl_sq
 #pragma unroll
   for (int m = 0; m < kAsmMaxM; ++m) c[m] = m < M ? sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + sb) * M + m] : 0.0;
   __syncthreads();
-  for (int p = threadIdx.x; p < NE * 2 * SB; p += NT) {
-    const int le = p / (2 * SB);
-    const int lx = le % EX, ly = (le / EX) % EY, lz = le / (EX * EY);
+  // a lane's items are elements le0, le0 + D, le0 + 2 D, ... (D = NT / 2 SB):
+  // their block coordinates advance by D's digits with carries instead of
+  // being divided out per item
+  constexpr int D = NT / (2 * SB);
+  constexpr int DX = D % EX, DY = (D / EX) % EY, DZ = D / (EX * EY);
+  int le = threadIdx.x / (2 * SB);
+  int lx = le % EX, ly = (le / EX) % EY, lz = le / (EX * EY);
+  for (; le < NE; le += D) {
     const int ex = ex0 + lx, ey = ey0 + ly, ez = ez0 + lz;
-    if (ex < 0 || ey < 0 || ez < 0 || ex >= N || ey >= N || ez >= N) continue;
-    double kq[4];  // Gauss points qx + 2 qy + 4 hz
+    if (ex >= 0 && ey >= 0 && ez >= 0 && ex < N && ey < N && ez < N) {
+      double kq[4];  // Gauss points qx + 2 qy + 4 hz
 #pragma unroll
-    for (int q = 0; q < 4; ++q) kq[q] = 0.0;
+      for (int q = 0; q < 4; ++q) kq[q] = 0.0;
+      const double* px = s_x + lx * 2;
+      const double* pyz = s_yz + (ly * EZ + lz) * 4 + 2 * hz;
+      // every mode up to the largest M, each skipped by a uniform branch
+      // when absent: the coefficients stay in fixed registers
 #pragma unroll
-    for (int m = 0; m < kAsmMaxM; ++m) {
-      if (m >= M) break;
-      const double fx[2] = {s_x[(m * EX + lx) * 2], s_x[(m * EX + lx) * 2 + 1]};
-      const double* pyz = s_yz + ((m * EY + ly) * EZ + lz) * 4 + 2 * hz;
-      const double yz[2] = {c[m] * pyz[0], c[m] * pyz[1]};
+      for (int m = 0; m < kAsmMaxM; ++m) {
+        if (m < M) {
+          const double fx[2] = {px[m * 2 * EX], px[m * 2 * EX + 1]};
+          const double yz[2] = {c[m] * pyz[m * 4 * EY * EZ], c[m] * pyz[m * 4 * EY * EZ + 1]};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
+          for (int q = 0; q < 4; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double k = kappa0 + kq[q];
+        s_k[kslot<SB>(le, q + 4 * hz, sb)] = SCALED ? k * scale : k;
+      }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double k = kappa0 + kq[q];
-      s_k[kslot<SB>(le, q + 4 * hz, sb)] = SCALED ? k * scale : k;
+    lx += DX;
+    ly += DY;
+    lz += DZ;
+    if (lx >= EX) {
+      lx -= EX;
+      ++ly;
+    }
+    if (ly >= EY) {
+      ly -= EY;
+      ++lz;
     }
   }
   __syncthreads();
