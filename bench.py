@@ -99,9 +99,16 @@ def host_env():
         libs = sorted({l.split()[-1] for l in fh if "libamdhip64" in l})
     env["hip_runtime_lib"] = libs
     try:
+        hip = ctypes.CDLL("libamdhip64.so.7")
         v = ctypes.c_int()
-        ctypes.CDLL("libamdhip64.so.7").hipRuntimeGetVersion(ctypes.byref(v))
+        hip.hipRuntimeGetVersion(ctypes.byref(v))
         env["hip_runtime_version"] = v.value
+        # peak engine and memory clocks and the compute units the runtime
+        # reports (hipDeviceAttribute ClockRate = 5, MemoryClockRate = 60,
+        # MultiprocessorCount = 63 in hip_runtime_api.h of ROCm 7)
+        for key, attr, scale in (("gpu_clock_mhz", 5, 1e-3), ("mem_clock_mhz", 60, 1e-3), ("compute_units", 63, 1)):
+            if hip.hipDeviceGetAttribute(ctypes.byref(v), attr, torch.cuda.current_device()) == 0:
+                env[key] = v.value * scale if scale != 1 else v.value
     except OSError:
         env["hip_runtime_version"] = None
     return env

@@ -90,6 +90,15 @@ typedef struct {
 const char* ens_last_error(void);
 const char* ens_status_string(ens_status st);
 int32_t ens_abi_version(void);
+/* Release the library's own per-device state: each device context (its
+ * pinned poll word, work stream, join events and the concurrent baseline's
+ * side streams, whose queued work is waited for first) and the pool of
+ * profiling events (pending timings are completed and kept; profiling is
+ * switched off).  Caller-owned buffers are untouched, and the state is
+ * created again on the next call that needs it.  No library call may be
+ * in flight on any thread when it runs.  Returns ENS_E_HIP with the first
+ * runtime error met, after releasing what it could. */
+ens_status ens_shutdown(void);
 
 /* ------------------------------------------------------------ mesh/graph */
 

@@ -61,6 +61,35 @@ bool ensure_side_streams(DeviceCtx* c, int count) {
   return true;
 }
 
+// Release every device's context (see ens_shutdown).  Returns the first
+// HIP error met, after releasing what it can.
+static hipError_t release_contexts() {
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  hipError_t first = hipSuccess;
+  auto keep = [&](hipError_t e) {
+    if (first == hipSuccess && e != hipSuccess) first = e;
+  };
+  int cur = 0;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  for (DeviceCtx*& c : g_ctx) {
+    if (!c) continue;
+    keep(hipSetDevice(c->device));
+    keep(hipStreamSynchronize(c->work_stream));
+    for (hipStream_t st : c->side) keep(hipStreamSynchronize(st));
+    for (hipEvent_t e : c->side_ev) keep(hipEventDestroy(e));
+    for (hipStream_t st : c->side) keep(hipStreamDestroy(st));
+    keep(hipEventDestroy(c->ev_in));
+    keep(hipEventDestroy(c->ev_out));
+    keep(hipStreamDestroy(c->work_stream));
+    keep(hipHostFree(c->host_flag));
+    delete c;
+    c = nullptr;
+  }
+  g_ctx.clear();
+  if (have_cur) keep(hipSetDevice(cur));
+  return first;
+}
+
 // ------------------------------------------------------------- profiling ---
 
 struct PendingPair {
@@ -226,6 +255,33 @@ const char* ens_status_string(ens_status st) {
 }
 
 int32_t ens_abi_version(void) { return 1; }
+
+ens_status ens_shutdown(void) {
+  // the profiling events: wait for the pending pairs, keep their
+  // durations, then destroy every event (the durations stay queryable)
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& p : g_pending) (void)hipEventSynchronize(p.b);
+  }
+  prof_collect();
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = false;
+    for (hipEvent_t e : g_free_events) (void)hipEventDestroy(e);
+    g_free_events.clear();
+    for (int k = 0; k < ENS_K_COUNT; ++k)
+      if (g_open_valid[k]) {
+        (void)hipEventDestroy(g_open[k]);
+        g_open_valid[k] = false;
+      }
+  }
+  const hipError_t e = release_contexts();
+  if (e != hipSuccess) {
+    set_error("ens_shutdown: %s", hipGetErrorString(e));
+    return ENS_E_HIP;
+  }
+  return ENS_OK;
+}
 
 ens_status ens_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
   ENS_ARG_CHECK(src && dst, "null pointer");

@@ -105,6 +105,7 @@ _SIGS = [
     ("ens_last_error", ctypes.c_char_p, []),
     ("ens_status_string", ctypes.c_char_p, [_I32]),
     ("ens_abi_version", _I32, []),
+    ("ens_shutdown", _I32, []),
     ("ens_mesh_sizes", _I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     ("ens_graph_build", _I32, [_I32, _P, _P, _P]),
     ("ens_kl_bytes", _I32, [_I32, _I32, ctypes.POINTER(_SZ)]),
@@ -709,6 +710,12 @@ def stream_write(dst: torch.Tensor, value: int = 0, stream=None):
 
 def stream_triad(a, b, c, q: float, stream=None):
     _check(lib().ens_stream_triad(_ptr(a), _ptr(b), _ptr(c), q, a.numel(), _stream(stream)), "ens_stream_triad")
+
+
+def shutdown():
+    """Release the library's per-device state (ens_shutdown); it is created
+    again by the next call that needs it."""
+    _check(lib().ens_shutdown(), "ens_shutdown")
 
 
 def prof_enable(on: bool = True):

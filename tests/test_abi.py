@@ -291,3 +291,10 @@ def test_autotune_workspace_is_caller_owned_without_gpu(E):
     bad = (ctypes.c_int32 * 1)(12)
     assert L.ens_batch_autotune_workspace_bytes(meshes, 2, ctypes.byref(pr), bad, 1, tc, 3, ctypes.byref(o),
                                                 ctypes.byref(b)) == E.ENS_E_UNSUPPORTED
+
+
+def test_shutdown_without_state_is_a_no_op(E):
+    # no device context exists in a process that made no device call
+    L = E.lib()
+    assert L.ens_shutdown() == E.ENS_OK
+    assert L.ens_shutdown() == E.ENS_OK

@@ -277,6 +277,26 @@ def test_ensemble_equals_scalar_solves(E, orc):
         assert torch.equal(xc, xs1) and stc == st1
 
 
+def test_shutdown_releases_and_state_comes_back(E):
+    # the library's own state (device context, side streams, profiling
+    # events) is released and rebuilt on demand; results are unchanged
+    N, s, M, rtol = 6, 4, 3, 1e-10
+    g, vals, _, rhs = _gpu_system(E, N, s, M, 0.2, draw_xi(41, s, M))
+    vsm, bsm = E.relayout(vals, True), E.relayout(rhs, True)
+    E.prof_enable(True)
+    E.prof_reset()
+    x0, st0, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=rtol))
+    xc0, stc0, _ = E.scalar_cg_concurrent(g, vsm, bsm, opts=E.cg_opts(rtol=rtol), lanes_per_row=8, streams=3)
+    E.shutdown()
+    assert E.prof_query(E.K_SPMV_F64)["launches"] > 0  # timings taken before survive
+    E.shutdown()  # a second call finds nothing to release
+    x1, st1, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=rtol))
+    xc1, stc1, _ = E.scalar_cg_concurrent(g, vsm, bsm, opts=E.cg_opts(rtol=rtol), lanes_per_row=8, streams=3)
+    assert torch.equal(x0, x1) and st0 == st1
+    assert torch.equal(xc0, xc1) and stc0 == stc1
+    E.prof_enable(False)
+
+
 def test_cg_edge_cases(E, orc):
     N, s, M = 6, 4, 3
     xi = draw_xi(2, s, M)
