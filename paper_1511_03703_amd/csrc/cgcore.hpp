@@ -291,7 +291,7 @@ __device__ inline void residual_body(int n, const int32_t* __restrict__ rp, cons
   if (row < n) {
     typename M::vt ax = x_zero ? (typename M::vt)0.0
                                : tile_row_product<double, S>(tile, staged, (int)(row - blk * R), ci, vals, x, sub);
-    typename M::vt bv = ((const typename M::vt*)b)[row * M::L + sub];
+    typename M::vt bv = load_stream((const typename M::vt*)b + row * M::L + sub);
     typename M::vt r = bv - ax;
 #pragma unroll
     for (int j = 0; j < M::V; ++j) {
@@ -323,8 +323,8 @@ __device__ inline void cg_start_body(int64_t nchunks, const T* __restrict__ r, c
   for (int u = 0; u < kU; ++u) {
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
-      rv[u] = ((const vt*)r)[i];
-      dv[u] = ((const vt*)dinv)[i];
+      rv[u] = load_stream((const vt*)r + i);
+      dv[u] = load_stream((const vt*)dinv + i);
     }
   }
 #pragma unroll
@@ -395,11 +395,11 @@ __device__ inline void update_body(int64_t nchunks, T* __restrict__ x, const T* 
   for (int u = 0; u < kU; ++u) {
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
-      pv[u] = ((const vt*)p)[i];
-      qv[u] = ((const vt*)q)[i];
-      rv[u] = ((const vt*)r)[i];
-      xv[u] = ((const vt*)x)[i];
-      dv[u] = ((const vt*)dinv)[i];
+      pv[u] = load_stream((const vt*)p + i);
+      qv[u] = load_stream((const vt*)q + i);
+      rv[u] = load_stream((const vt*)r + i);
+      xv[u] = load_stream((const vt*)x + i);
+      dv[u] = load_stream((const vt*)dinv + i);
     }
   }
 #pragma unroll
@@ -460,9 +460,9 @@ __device__ inline void pupdate_body(int64_t nchunks, const T* __restrict__ r, co
   for (int u = 0; u < kU; ++u) {
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
-      pv[u] = ((const vt*)p)[i];
-      rv[u] = ((const vt*)r)[i];
-      dv[u] = ((const vt*)dinv)[i];
+      pv[u] = load_stream((const vt*)p + i);
+      rv[u] = load_stream((const vt*)r + i);
+      dv[u] = load_stream((const vt*)dinv + i);
     }
   }
 #pragma unroll
@@ -504,10 +504,10 @@ __device__ inline void update_r_body(int64_t nchunks, T* __restrict__ x, const T
   for (int u = 0; u < kU; ++u) {
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
-      pv[u] = ((const vt*)p)[i];
-      qv[u] = ((const vt*)q)[i];
-      rv[u] = ((const vt*)r)[i];
-      xv[u] = ((const vt*)x)[i];
+      pv[u] = load_stream((const vt*)p + i);
+      qv[u] = load_stream((const vt*)q + i);
+      rv[u] = load_stream((const vt*)r + i);
+      xv[u] = load_stream((const vt*)x + i);
     }
   }
 #pragma unroll
@@ -557,8 +557,8 @@ __device__ inline void rz_body(int64_t nchunks, const T* __restrict__ r, const T
   for (int u = 0; u < kU; ++u) {
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
-      rv[u] = ((const vt*)r)[i];
-      zv[u] = ((const vt*)z)[i];
+      rv[u] = load_stream((const vt*)r + i);
+      zv[u] = load_stream((const vt*)z + i);
     }
   }
 #pragma unroll
@@ -597,8 +597,8 @@ __device__ inline void pupdate_z_body(int64_t nchunks, const T* __restrict__ z, 
   for (int u = 0; u < kU; ++u) {
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
-      pv[u] = ((const vt*)p)[i];
-      zv[u] = ((const vt*)z)[i];
+      pv[u] = load_stream((const vt*)p + i);
+      zv[u] = load_stream((const vt*)z + i);
     }
   }
 #pragma unroll

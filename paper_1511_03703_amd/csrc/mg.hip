@@ -316,8 +316,8 @@ __global__ __launch_bounds__(256) void k_mg_cheb0(int64_t nchunks, const T* __re
   for (int u = 0; u < kU; ++u) {
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
-      bv[u] = ((const vt*)b)[i];
-      dv[u] = ((const vt*)dinv)[i];
+      bv[u] = load_stream((const vt*)b + i);
+      dv[u] = load_stream((const vt*)dinv + i);
     }
   }
 #pragma unroll
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
   if (row >= n) return;
   const vt ax = tile_row_product<T, S>(tile, staged, (int)(row - (int64_t)blockIdx.x * R), ci, vals, x, sub);
   const int64_t i = row * M::L + sub;
-  const vt res = ((const vt*)b)[i] - ax;
+  const vt res = load_stream((const vt*)b + i) - ax;
   if (MODE == MG_RES) {
     store_stream((vt*)out + i, res);
     return;
@@ -367,10 +367,10 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
     k1[v] = (T)(MODE == MG_CHEB1 ? 0.0 : c.c1);
     k2[v] = (T)(MODE == MG_CHEB1 ? c.inv_theta : c.c2);
   }
-  const vt dv = ((const vt*)dinv)[i] * res;
+  const vt dv = load_stream((const vt*)dinv + i) * res;
   vt dn;
   if (MODE == MG_CHEB1) dn = k2 * dv;
-  else dn = k1 * ((const vt*)d)[i] + k2 * dv;
+  else dn = k1 * load_stream((const vt*)d + i) + k2 * dv;
   store_stream((vt*)d + i, dn);
   store_stream((vt*)out + i, ((const vt*)x)[i] + dn);
 }
