@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_ir_update(int64_t total, double* __rest
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
     const int e = (int)(i % S);
-    if (c->oactive[e]) x[i] += (double)d[i];
+    if (c->oactive[e]) __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + (double)__builtin_nontemporal_load(d + i), x + i);
   }
 }
 

@@ -325,8 +325,8 @@ __global__ __launch_bounds__(256) void k_mg_cheb0(int64_t nchunks, const T* __re
     const int64_t i = base + u * kBlock;
     if (i < nchunks) {
       const vt dd = dv[u] * bv[u] * it;
-      ((vt*)d)[i] = dd;
-      ((vt*)xa)[i] = dd;
+      store_stream((vt*)d + i, dd);
+      store_stream((vt*)xa + i, dd);
     }
   }
 }
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) void k_mg_prolong(int Nc, const T* __restrict_
         const int64_t cn = I + (int64_t)(Nc + 1) * (J + (int64_t)(Nc + 1) * K);
         acc += (T)(wi[a] * wj[bq] * wk[c]) * ((const vt*)xc)[cn * VM::L + sub];
       }
-  ((vt*)xf)[t] = ((const vt*)xf)[t] + acc;
+  store_stream((vt*)xf + t, load_stream((const vt*)xf + t) + acc);
 }
 
 // Coarsest level: boundary rows are identities (x = B), interior rows take

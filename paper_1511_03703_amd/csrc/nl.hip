@@ -387,7 +387,7 @@ static __global__ __launch_bounds__(kBlock) void k_gm_dots(int64_t nchunks, cons
 #pragma unroll
       for (int q = 0; q < kGmChunk; ++q)
         if (i0 + q <= j) {
-          const vt vv = ((const vt*)(V + (int64_t)(i0 + q) * vstride))[c];
+          const vt vv = load_stream((const vt*)(V + (int64_t)(i0 + q) * vstride) + c);
 #pragma unroll
           for (int v = 0; v < VM::V; ++v) acc[q][v] += vv[v] * wv[v];
         }
@@ -416,7 +416,7 @@ static __global__ __launch_bounds__(kBlock) void k_gm_axpy(int64_t nchunks, cons
   for (int64_t ch = (int64_t)blockIdx.x * kBlock + threadIdx.x; ch < nchunks; ch += step) {
     vt wv = ((const vt*)w)[ch];
     for (int i = 0; i <= j; ++i) {
-      const vt vv = ((const vt*)(V + (int64_t)i * vstride))[ch];
+      const vt vv = load_stream((const vt*)(V + (int64_t)i * vstride) + ch);
 #pragma unroll
       for (int v = 0; v < VM::V; ++v) wv[v] -= s_coef[i][VM::sample(sub, v)] * vv[v];
     }
@@ -458,7 +458,7 @@ static __global__ __launch_bounds__(kBlock) void k_gm_axpy_dots(int64_t nchunks,
 #pragma unroll
     for (int i = 0; i < JM; ++i)
       if (i <= j) {
-        vv[i] = ((const vt*)(V + (int64_t)i * vstride))[ch];
+        vv[i] = load_stream((const vt*)(V + (int64_t)i * vstride) + ch);
 #pragma unroll
         for (int v = 0; v < VM::V; ++v) wv[v] -= s_coef[i][VM::sample(sub, v)] * vv[i][v];
       }
@@ -523,7 +523,7 @@ static __global__ __launch_bounds__(kBlock) void k_gm_combine(int64_t nchunks, c
   const int sub = threadIdx.x % VM::L;
   vt acc = (vt)0.0;
   for (int i = 0; i < k; ++i) {
-    const vt vv = ((const vt*)(V + (int64_t)i * vstride))[ch];
+    const vt vv = load_stream((const vt*)(V + (int64_t)i * vstride) + ch);
 #pragma unroll
     for (int v = 0; v < VM::V; ++v) acc[v] += s_y[i][VM::sample(sub, v)] * vv[v];
   }
