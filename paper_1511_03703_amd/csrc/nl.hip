@@ -319,31 +319,31 @@ static __global__ __launch_bounds__(kBlock) void k_gm_spmv(int n, const int32_t*
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane % M::L;
   const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
+  constexpr int R = (kBlock / 64) * M::RPW;
+  __shared__ RowTileLds<R> tile;  // the row tile's offsets and indices, as in the CG product
+  const bool staged = stage_row_tile(tile, n, rp, ci, (int64_t)blockIdx.x * R);
   if (row >= n) return;
-  ((typename M::vt*)w)[row * M::L + sub] = gm_row_product<S, TV, TZ>(ci, vals, z, rp[row], rp[row + 1], sub);
+  const int lr = (int)(row - (int64_t)blockIdx.x * R);
+  const typename M::vt y = staged
+                               ? gm_row_product<S, TV, TZ>(tile.ci - tile.rp[0], vals, z, tile.rp[lr], tile.rp[lr + 1], sub)
+                               : gm_row_product<S, TV, TZ>(ci, vals, z, tile.rp[lr], tile.rp[lr + 1], sub);
+  store_stream((typename M::vt*)w + row * M::L + sub, y);
 }
 
-// w = A z for an FP32 matrix with the FP32 row mapping: each lane reads 16
-// bytes (4 samples) of the value stream, gathers those samples of z (FP64
-// or FP32) and accumulates in FP64.
+// One row of the FP32-mapped product: entries k0..k1 of the row, column
+// indices from ci (global memory or a staged LDS tile).
 template <int S, typename TZ>
-static __global__ __launch_bounds__(kBlock) void k_gm_spmv_v32(int n, const int32_t* __restrict__ rp,
-                                                               const int32_t* __restrict__ ci,
-                                                               const float* __restrict__ vals,
-                                                               const TZ* __restrict__ z, double* __restrict__ w) {
-  using M = EnsMap<float, S>;  // V = 4 samples per lane
+__device__ inline typename vec_t<double, 4>::type gm_v32_row(const int32_t* ci, const float* __restrict__ vals,
+                                                             const TZ* __restrict__ z, int64_t k0, int64_t k1,
+                                                             int sub) {
+  using M = EnsMap<float, S>;
   typedef typename vec_t<float, 4>::type f4;
   typedef typename vec_t<TZ, 4>::type z4;
   typedef typename vec_t<double, 4>::type d4;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sub = lane % M::L;
-  const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
-  if (row >= n) return;
   const f4* vv = (const f4*)vals + sub;
   const TZ* zs = z + sub * 4;
   d4 acc = (d4)0.0;
-  const int64_t k1 = rp[row + 1];
-  int64_t k = rp[row];
+  int64_t k = k0;
   for (; k + 2 < k1; k += 3) {
     int32_t c3[3];
     f4 a[3];
@@ -365,7 +365,31 @@ static __global__ __launch_bounds__(kBlock) void k_gm_spmv_v32(int n, const int3
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] += (double)a[v] * (double)b[v];
   }
-  *(d4*)(w + row * S + sub * 4) = acc;
+  return acc;
+}
+
+// w = A z for an FP32 matrix with the FP32 row mapping: each lane reads 16
+// bytes (4 samples) of the value stream, gathers those samples of z (FP64
+// or FP32) and accumulates in FP64.
+template <int S, typename TZ>
+static __global__ __launch_bounds__(kBlock) void k_gm_spmv_v32(int n, const int32_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ ci,
+                                                               const float* __restrict__ vals,
+                                                               const TZ* __restrict__ z, double* __restrict__ w) {
+  using M = EnsMap<float, S>;  // V = 4 samples per lane
+  typedef typename vec_t<double, 4>::type d4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane % M::L;
+  const int64_t row = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * M::RPW + lane / M::L;
+  constexpr int R = (kBlock / 64) * M::RPW;
+  __shared__ RowTileLds<R> tile;  // the row tile's offsets and indices, as in the CG product
+  const bool staged = stage_row_tile(tile, n, rp, ci, (int64_t)blockIdx.x * R);
+  if (row >= n) return;
+  const int lr = (int)(row - (int64_t)blockIdx.x * R);
+  const int64_t k0 = tile.rp[lr], k1 = tile.rp[lr + 1];
+  const d4 acc = staged ? gm_v32_row<S, TZ>(tile.ci - tile.rp[0], vals, z, k0, k1, sub)
+                        : gm_v32_row<S, TZ>(ci, vals, z, k0, k1, sub);
+  store_stream((d4*)(w + row * S + sub * 4), acc);
 }
 
 // part[blk][i*S + e] = sum over the block's chunks of V_i . w, i = 0..j.
