@@ -299,8 +299,10 @@ __device__ inline void residual_body(int n, const int32_t* __restrict__ rp, cons
       acc[1][j] = bv[j] * bv[j];
     }
     if (rout) {
+      typename vec_t<TR, M::V>::type rv;
 #pragma unroll
-      for (int j = 0; j < M::V; ++j) rout[row * S + sub * M::V + j] = (TR)r[j];
+      for (int j = 0; j < M::V; ++j) rv[j] = (TR)r[j];
+      store_stream((typename vec_t<TR, M::V>::type*)(rout + row * S + sub * M::V), rv);
     }
   }
   block_partials<S, M::V, 2, NW>(acc, dst);
