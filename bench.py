@@ -51,10 +51,17 @@ def spmv_bytes(n, nnz, s, w):
 
 
 def kernel_source_hash():
+    """Hash of the sources of the CG and cycle kernels, comments and blank
+    lines left out (a comment edit does not change what the counters were
+    taken on)."""
+    import re
+
     h = hashlib.sha256()
     for f in ("rowops.hpp", "cgcore.hpp", "cg.hip", "common.hpp", "mg.hip", "mg.hpp"):
-        with open(os.path.join(ROOT, "paper_1511_03703_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1511_03703_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = (re.sub(r"//.*", "", l).rstrip() for l in text.splitlines())
+        h.update("\n".join(l for l in lines if l).encode())
     return h.hexdigest()[:16]
 
 

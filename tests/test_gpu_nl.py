@@ -107,6 +107,40 @@ def test_gmres_fixed_steps_match_oracle(E, orc, prec, N, s, k):
         assert _rel(xg[:, e], xo[:, e]) <= 1e-9, (e, _rel(xg[:, e], xo[:, e]))
 
 
+@pytest.mark.parametrize("lo,hi", [(40, 64), (0, 8)])
+@pytest.mark.parametrize("s", [8, 32])
+def test_gmres_on_random_graphs_with_and_without_staged_indices(E, orc, lo, hi, s):
+    # the GMRES product stages a row tile's column indices in LDS when its
+    # rows average at most 32 entries and reads them from global memory
+    # otherwise: rows of 40-64 entries take the second path in every tile,
+    # rows of 0-8 (plus the diagonal) the first; diagonally dominant random
+    # values, Jacobi-preconditioned GMRES at a fixed step count
+    N, k = 12, 6
+    n = orc.num_nodes(N)
+    rng = np.random.default_rng(4600 + lo + s)
+    rows = []
+    for i in range(n):
+        cols = set(rng.choice(n, int(rng.integers(lo, hi + 1)), replace=False).tolist())
+        cols.add(i)
+        rows.append(np.array(sorted(cols), np.int32))
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    vals = rng.standard_normal((int(rp[-1]), s))
+    for i in range(n):
+        d = rp[i] + int(np.searchsorted(rows[i], i))
+        vals[d] = np.abs(vals[rp[i]:rp[i + 1]]).sum(0) + 1.0
+    b = rng.standard_normal((n, s))
+    g = E.graph_from_arrays(torch.as_tensor(rp, device=DEV), torch.as_tensor(ci, device=DEV))
+    x, stats, _ = E.gmres(g, torch.as_tensor(vals, device=DEV), torch.as_tensor(b, device=DEV),
+                          opts=E.gmres_opts(rtol=0.0, restart=10, max_iter=k))
+    assert all(t["iters"] == k for t in stats), stats
+    xo, _, _, _ = orc.ens_gmres(N, rp, ci, vals, b, prec=0, restart=10, fixed_iters=[k] * s)
+    xg = _np(x)
+    for e in range(s):
+        assert _rel(xg[:, e], xo[:, e]) <= 1e-9, (e, _rel(xg[:, e], xo[:, e]))
+
+
 @pytest.mark.parametrize("prec,restart", [("jacobi", 30), ("jacobi", 6), ("mg", 30), ("mg", 3)])
 def test_gmres_converges_like_the_oracle(E, orc, prec, restart):
     N, s, M, rtol = 12, 8, 10, 1e-10
