@@ -454,7 +454,10 @@ __global__ __launch_bounds__(32 * S) void kb_assemble(const AsmGroupDev* __restr
 // element residual is
 //   F_a = sum_b (D_ab + alpha (h^2/8) C_ab + beta (h^3/8) sum_q u_q N_a N_b) u_b
 //         - (h^3/8) f sum_q N_a,
-// so no gradient of u_h is formed.  Boundary rows: F = u and identity rows;
+// so no gradient of u_h is formed; the reaction sums sum_q u_q N_a N_b are
+// contracted from the nodal values directly (the triple products of the
+// shape functions factor over the axes), so u_h at the Gauss points is not
+// formed either.  Boundary rows: F = u and identity rows;
 // boundary columns of interior rows stored as zeros; load (optional) = the
 // source part of F.
 template <int S, int SB, bool JAC>
@@ -507,6 +510,7 @@ __global__ __launch_bounds__(32 * SB) void k_nl_assemble(int N, const double* __
   const double wa = h * h * 0.125 * alpha; // advection: alpha w_q / h
   const double wr = h * h * h * 0.125;     // reaction and source: w_q
   const double wb = wr * beta;
+  const double wrf = wr * fsrc;     // an element's load on a node
 
   double acc[27];
 #pragma unroll
@@ -565,50 +569,39 @@ __global__ __launch_bounds__(32 * SB) void k_nl_assemble(int N, const double* __
                                                                 (int64_t)n1 * (ez + ((b >> 2) & 1)));
             ue[b] = u[node * S + e];
           }
-          // u_h at the Gauss points and the reaction row
-          // rn_b = sum_q u_q N_a(q) N_b(q) by sum factorisation: N_b(q) is the
-          // product over the axes of the 1D factors l(q_d, b_d), so each is
-          // three contractions of 2 along one axis
-          double uq[8], rnv[8];
+          // the reaction row rn_b = sum_q u_h(q) N_a(q) N_b(q) = sum_c T_abc u_c,
+          // T_abc = sum_q N_a N_b N_c, a product over the axes of the 1D
+          // sums t(a, b, c) = sum_q l_a l_b l_c over the two Gauss points,
+          // which are 1/2 when a = b = c and 1/6 otherwise: three 2-point
+          // contractions of the element's nodal values, each pair (x0, x1)
+          // giving (x0 + x1)/6 and that plus x_a/3 at the row's own index
+          // (u_h at the Gauss points is never formed)
+          double rnv[8];
           {
+            constexpr double k6 = 1.0 / 6.0, k3 = 1.0 / 3.0;
+            const int ax = ai & 1, ay = (ai >> 1) & 1, az = ai >> 2;
             double t1[8], t2[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {  // i = qx + 2 by + 4 bz
-              const int qx = i & 1, r = i & 6;
-              t1[i] = kL1[qx][0] * ue[r] + kL1[qx][1] * ue[r + 1];
+            for (int r = 0; r < 8; r += 2) {  // along x: (cx) -> (bx), r = 2 cy + 4 cz
+              const double m = (ue[r] + ue[r + 1]) * k6;
+              t1[r + ax] = fma(ue[r + ax], k3, m);
+              t1[r + 1 - ax] = m;
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 bz
-              const int qy = (i >> 1) & 1, r = i & 5;
-              t2[i] = kL1[qy][0] * t1[r] + kL1[qy][1] * t1[r + 2];
+            for (int k = 0; k < 4; ++k) {  // along y: i0 = bx + 4 cz
+              const int i0 = (k & 1) + 4 * (k >> 1);
+              const double m = (t1[i0] + t1[i0 + 2]) * k6;
+              t2[i0 + 2 * ay] = fma(t1[i0 + 2 * ay], k3, m);
+              t2[i0 + 2 * (1 - ay)] = m;
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 qz
-              const int qz = i >> 2, r = i & 3;
-              uq[i] = kL1[qz][0] * t2[r] + kL1[qz][1] * t2[r + 4];
-            }
-            double w[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              w[q] = uq[q] * kQ1.N[q][ai];
-              la += wr * fsrc * kQ1.N[q][ai];
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {  // i = qx + 2 qy + 4 bz
-              const int bz = i >> 2, r = i & 3;
-              t1[i] = kL1[0][bz] * w[r] + kL1[1][bz] * w[r + 4];
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {  // i = qx + 2 by + 4 bz
-              const int by = (i >> 1) & 1, r = i & 5;
-              t2[i] = kL1[0][by] * t1[r] + kL1[1][by] * t1[r + 2];
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {  // i = bx + 2 by + 4 bz
-              const int bx = i & 1, r = i & 6;
-              rnv[i] = kL1[0][bx] * t2[r] + kL1[1][bx] * t2[r + 1];
+            for (int i0 = 0; i0 < 4; ++i0) {  // along z: i0 = bx + 2 by
+              const double m = (t2[i0] + t2[i0 + 4]) * k6;
+              rnv[i0 + 4 * az] = fma(t2[i0 + 4 * az], k3, m);
+              rnv[i0 + 4 * (1 - az)] = m;
             }
           }
+          la += wrf;  // sum_q N_a(q) = 1 for the 2-point rule
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             double dg = 0.0;
