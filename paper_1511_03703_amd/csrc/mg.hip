@@ -336,7 +336,9 @@ enum MgRowMode { MG_RES = 0, MG_CHEB1 = 1, MG_CHEB2 = 2 };
 // Row passes of the cycle (one row tile of 4 wavefronts per block):
 //   MG_RES:   r = B - A x
 //   MG_CHEB1: d = D^-1 (B - A x) / theta;           xout = x + d
-//   MG_CHEB2: d = c1 d + c2 D^-1 (B - A x);          xout = x + d
+//   MG_CHEB2: d' = c1 d + c2 D^-1 (B - A x);         xout = x + d'
+// MG_CHEB2 is the last step of the order-2 smoother, so d' is not stored
+// (nothing reads it: the next smoothing sweep starts a new direction).
 template <typename T, int S, int MODE>
 __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                 const T* __restrict__ vals, const T* __restrict__ x,
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
   vt dn;
   if (MODE == MG_CHEB1) dn = k2 * dv;
   else dn = k1 * load_stream((const vt*)d + i) + k2 * dv;
-  store_stream((vt*)d + i, dn);
+  if (MODE == MG_CHEB1) store_stream((vt*)d + i, dn);
   store_stream((vt*)out + i, ((const vt*)x)[i] + dn);
 }
 
@@ -623,7 +625,7 @@ static void cycle(const MgPlan& P, int k, const T* B, T* OUT, const Ctl* gate, h
   if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xa, B, dinv,
                      l.lmax, d, xb, gate);
-  if (fine) prof_end(ENS_K_MG_ROW, st, mat + 6.0 * vec);
+  if (fine) prof_end(ENS_K_MG_ROW, st, mat + 5.0 * vec);
   if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<T, S, MG_RES>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xb, B, dinv,
                      l.lmax, d, r, gate);
@@ -638,7 +640,7 @@ static void cycle(const MgPlan& P, int k, const T* B, T* OUT, const Ctl* gate, h
   if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xa, B, dinv,
                      l.lmax, d, OUT, gate);
-  if (fine) prof_end(ENS_K_MG_ROW, st, mat + 6.0 * vec);
+  if (fine) prof_end(ENS_K_MG_ROW, st, mat + 5.0 * vec);
 }
 
 template <typename T, int S>
