@@ -762,9 +762,10 @@ static void mg_iterations(const ens_graph* g, const T* vals, const MgPlan& plan,
     reduce<S, 1>(w, sb, OP_ALPHA, 0, 1, st);
     hipLaunchKernelGGL((k_mg_update_r<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, x, p, q, r, w.ctl, w.part);
     reduce<S, 2>(w, vb, OP_UPDATE_R, k, 1, st);
-    mg_vcycle<T, S>(plan, r, z, w.ctl, st);
-    hipLaunchKernelGGL((k_mg_rz<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, r, z, (T*)nullptr, w.ctl, 1, w.part);
-    reduce<S, 2>(w, vb, OP_BETA, 0, 1, st);
+    // the cycle's last fine-level pass also writes the r . z partials, one
+    // row per row tile (sb rows, the tiles of the product above)
+    mg_vcycle<T, S>(plan, r, z, w.ctl, st, w.part);
+    reduce<S, 1>(w, sb, OP_BETA, 0, 1, st);
     hipLaunchKernelGGL((k_mg_pz<T, S>), dim3(vb), dim3(kBlock), 0, st, nchunks, z, p, w.ctl);
   }
 }

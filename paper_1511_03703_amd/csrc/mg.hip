@@ -338,12 +338,16 @@ enum MgRowMode { MG_RES = 0, MG_CHEB1 = 1, MG_CHEB2 = 2 };
 //   MG_CHEB2: d' = c1 d + c2 D^-1 (B - A x);         xout = x + d'
 // MG_CHEB2 is the last step of the order-2 smoother, so d' is not stored
 // (nothing reads it: the next smoothing sweep starts a new direction).
-template <typename T, int S, int MODE>
+// DOT (the cycle's very last pass, on the finest level, inside CG): the
+// block's per-sample partials of B . xout, i.e. r . z with z = M r, go to
+// dot[blockIdx.x][S], so CG needs no separate pass over r and z.
+template <typename T, int S, int MODE, bool DOT = false>
 __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                 const T* __restrict__ vals, const T* __restrict__ x,
                                                 const T* __restrict__ b, const T* __restrict__ dinv,
                                                 const double* __restrict__ lmax, T* __restrict__ d,
-                                                T* __restrict__ out, const Ctl* gate) {
+                                                T* __restrict__ out, const Ctl* gate, double* __restrict__ dot) {
+  static_assert(!DOT || MODE == MG_CHEB2, "the dot is formed in the smoother's last step");
   if (mg_idle(gate)) return;
   using M = EnsMap<T, S>;
   using vt = typename M::vt;
@@ -353,10 +357,14 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
   constexpr int R = 4 * M::RPW;
   __shared__ RowTileLds<R> tile;
   const bool staged = stage_row_tile(tile, n, rp, ci, (int64_t)blockIdx.x * R);
-  if (row >= n) return;
+  double acc[1][M::V];
+#pragma unroll
+  for (int v = 0; v < M::V; ++v) acc[0][v] = 0.0;
+  if (row < n) {
   const vt ax = tile_row_product<T, S>(tile, staged, (int)(row - (int64_t)blockIdx.x * R), ci, vals, x, sub);
   const int64_t i = row * M::L + sub;
-  const vt res = load_stream((const vt*)b + i) - ax;
+  const vt bv = load_stream((const vt*)b + i);
+  const vt res = bv - ax;
   if (MODE == MG_RES) {
     store_stream((vt*)out + i, res);
     return;
@@ -373,7 +381,14 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
   if (MODE == MG_CHEB1) dn = k2 * dv;
   else dn = k1 * load_stream((const vt*)d + i) + k2 * dv;
   if (MODE == MG_CHEB1) store_stream((vt*)d + i, dn);
-  store_stream((vt*)out + i, ((const vt*)x)[i] + dn);
+  const vt xn = ((const vt*)x)[i] + dn;
+  store_stream((vt*)out + i, xn);
+  if (DOT) {
+#pragma unroll
+    for (int v = 0; v < M::V; ++v) acc[0][v] = (double)bv[v] * (double)xn[v];
+  }
+  }
+  if (DOT) block_partials<S, M::V, 1, 4>(acc, dot + (int64_t)blockIdx.x * S);
 }
 
 // Coarse interior node c collects the residual of the fine interior nodes
@@ -597,7 +612,8 @@ static unsigned blocks_for(int64_t items, int64_t per) {
 }
 
 template <typename T, int S>
-static void cycle(const MgPlan& P, int k, const T* B, T* OUT, const Ctl* gate, hipStream_t st) {
+static void cycle(const MgPlan& P, int k, const T* B, T* OUT, const Ctl* gate, hipStream_t st,
+                  double* dot = nullptr) {
   using EM = EnsMap<T, S>;
   using VM = VecMap<T, S>;
   const MgLevel& l = P.lv[k];
@@ -623,31 +639,36 @@ static void cycle(const MgPlan& P, int k, const T* B, T* OUT, const Ctl* gate, h
                      nchunks, B, dinv, l.lmax, d, gate);
   if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, d, B, dinv,
-                     l.lmax, d, xb, gate);
+                     l.lmax, d, xb, gate, (double*)nullptr);
   if (fine) prof_end(ENS_K_MG_ROW, st, mat + 4.0 * vec);  // x is d: one vector read less
   if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<T, S, MG_RES>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xb, B, dinv,
-                     l.lmax, d, r, gate);
+                     l.lmax, d, r, gate, (double*)nullptr);
   if (fine) prof_end(ENS_K_MG_ROW, st, mat + 3.0 * vec);
   hipLaunchKernelGGL((k_mg_restrict<T, S>), dim3(blocks_for(c.n * VM::L, 256)), dim3(256), 0, st, c.N, r, cb, gate);
   cycle<T, S>(P, k + 1, cb, cx, gate, st);
   hipLaunchKernelGGL((k_mg_prolong<T, S>), dim3(blocks_for(l.n * VM::L, 256)), dim3(256), 0, st, c.N, cx, xb, gate);
   if (fine) prof_begin(ENS_K_MG_ROW, st);
   hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB1>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xb, B, dinv,
-                     l.lmax, d, xa, gate);
+                     l.lmax, d, xa, gate, (double*)nullptr);
   if (fine) prof_end(ENS_K_MG_ROW, st, mat + 5.0 * vec);
   if (fine) prof_begin(ENS_K_MG_ROW, st);
-  hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xa, B, dinv,
-                     l.lmax, d, OUT, gate);
+  if (dot && fine)
+    hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB2, true>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xa,
+                       B, dinv, l.lmax, d, OUT, gate, dot);
+  else
+    hipLaunchKernelGGL((k_mg_row<T, S, MG_CHEB2>), dim3(rb), dim3(256), 0, st, (int)l.n, l.rp, l.ci, vals, xa, B,
+                       dinv, l.lmax, d, OUT, gate, (double*)nullptr);
   if (fine) prof_end(ENS_K_MG_ROW, st, mat + 5.0 * vec);
 }
 
 template <typename T, int S>
-void mg_vcycle(const MgPlan& plan, const T* r, T* z, const Ctl* gate, hipStream_t st) {
-  cycle<T, S>(plan, 0, r, z, gate, st);
+void mg_vcycle(const MgPlan& plan, const T* r, T* z, const Ctl* gate, hipStream_t st, double* dot) {
+  cycle<T, S>(plan, 0, r, z, gate, st, dot);
 }
 
-#define ENS_MG_INST(T, S) template void mg_vcycle<T, S>(const MgPlan&, const T*, T*, const Ctl*, hipStream_t);
+#define ENS_MG_INST(T, S) \
+  template void mg_vcycle<T, S>(const MgPlan&, const T*, T*, const Ctl*, hipStream_t, double*);
 ENS_MG_INST(double, 4)
 ENS_MG_INST(double, 8)
 ENS_MG_INST(double, 16)

@@ -86,8 +86,11 @@ bool mg_plan(int N, int M, int S, int fp32, char* base, MgPlan* plan);
 // Attach the fine level's graph and matrices (vals32 only for FP32 cycles).
 void mg_attach_fine(MgPlan* plan, const int32_t* rp, const int32_t* ci, const double* vals, const float* vals32);
 // z = M r for all samples in the cycle precision T; every kernel returns at
-// once when the control block (nullable) reports no active sample.
+// once when the control block (nullable) reports no active sample.  With
+// dot (nullable), the last fine-level pass also writes the per-sample
+// partials of r . z, one row of S doubles per row tile of 4 wavefronts
+// (ceil(n / (4 * rows per wavefront)) rows).
 template <typename T, int S>
-void mg_vcycle(const MgPlan& plan, const T* r, T* z, const Ctl* gate, hipStream_t st);
+void mg_vcycle(const MgPlan& plan, const T* r, T* z, const Ctl* gate, hipStream_t st, double* dot = nullptr);
 
 }  // namespace ens
