@@ -51,17 +51,17 @@ def spmv_bytes(n, nnz, s, w):
 
 
 def kernel_source_hash():
-    """Hash of the sources of the CG and cycle kernels, comments and blank
-    lines left out (a comment edit does not change what the counters were
-    taken on)."""
+    """Hash of the sources of the CG and cycle kernels with comments and all
+    white space left out (an edit of comments or layout does not change what
+    the counters were taken on)."""
     import re
 
     h = hashlib.sha256()
     for f in ("rowops.hpp", "cgcore.hpp", "cg.hip", "common.hpp", "mg.hip", "mg.hpp"):
         with open(os.path.join(ROOT, "paper_1511_03703_amd", "csrc", f)) as fh:
             text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
-        lines = (re.sub(r"//.*", "", l).rstrip() for l in text.splitlines())
-        h.update("\n".join(l for l in lines if l).encode())
+        text = "\n".join(re.sub(r"//.*", "", l) for l in text.splitlines())
+        h.update(re.sub(r"\s+", "", text).encode())
     return h.hexdigest()[:16]
 
 

@@ -361,32 +361,33 @@ __global__ __launch_bounds__(256) void k_mg_row(int n, const int32_t* __restrict
 #pragma unroll
   for (int v = 0; v < M::V; ++v) acc[0][v] = 0.0;
   if (row < n) {
-  const vt ax = tile_row_product<T, S>(tile, staged, (int)(row - (int64_t)blockIdx.x * R), ci, vals, x, sub);
-  const int64_t i = row * M::L + sub;
-  const vt bv = load_stream((const vt*)b + i);
-  const vt res = bv - ax;
-  if (MODE == MG_RES) {
-    store_stream((vt*)out + i, res);
-    return;
-  }
-  vt k1, k2;
+    const vt ax =
+        tile_row_product<T, S>(tile, staged, (int)(row - (int64_t)blockIdx.x * R), ci, vals, x, sub);
+    const int64_t i = row * M::L + sub;
+    const vt bv = load_stream((const vt*)b + i);
+    const vt res = bv - ax;
+    if (MODE == MG_RES) {
+      store_stream((vt*)out + i, res);
+      return;
+    }
+    vt k1, k2;
 #pragma unroll
-  for (int v = 0; v < M::V; ++v) {
-    const ChebK c = cheb_consts(lmax[sub * M::V + v]);
-    k1[v] = (T)(MODE == MG_CHEB1 ? 0.0 : c.c1);
-    k2[v] = (T)(MODE == MG_CHEB1 ? c.inv_theta : c.c2);
-  }
-  const vt dv = load_stream((const vt*)dinv + i) * res;
-  vt dn;
-  if (MODE == MG_CHEB1) dn = k2 * dv;
-  else dn = k1 * load_stream((const vt*)d + i) + k2 * dv;
-  if (MODE == MG_CHEB1) store_stream((vt*)d + i, dn);
-  const vt xn = ((const vt*)x)[i] + dn;
-  store_stream((vt*)out + i, xn);
-  if (DOT) {
+    for (int v = 0; v < M::V; ++v) {
+      const ChebK c = cheb_consts(lmax[sub * M::V + v]);
+      k1[v] = (T)(MODE == MG_CHEB1 ? 0.0 : c.c1);
+      k2[v] = (T)(MODE == MG_CHEB1 ? c.inv_theta : c.c2);
+    }
+    const vt dv = load_stream((const vt*)dinv + i) * res;
+    vt dn;
+    if (MODE == MG_CHEB1) dn = k2 * dv;
+    else dn = k1 * load_stream((const vt*)d + i) + k2 * dv;
+    if (MODE == MG_CHEB1) store_stream((vt*)d + i, dn);
+    const vt xn = ((const vt*)x)[i] + dn;
+    store_stream((vt*)out + i, xn);
+    if (DOT) {
 #pragma unroll
-    for (int v = 0; v < M::V; ++v) acc[0][v] = (double)bv[v] * (double)xn[v];
-  }
+      for (int v = 0; v < M::V; ++v) acc[0][v] = (double)bv[v] * (double)xn[v];
+    }
   }
   if (DOT) block_partials<S, M::V, 1, 4>(acc, dot + (int64_t)blockIdx.x * S);
 }
