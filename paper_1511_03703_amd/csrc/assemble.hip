@@ -338,6 +338,7 @@ __device__ __forceinline__ void assemble_tile_body(int N, const double* __restri
         for (int q = 0; q < 8; ++q) kq[q] = s_k[kslot<SB>(le, q, sb)];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
+          if (b == ai) continue;  // the diagonal follows from the row sum below
           const int dx = ex_off + (b & 1), dy = ey_off + ((b >> 1) & 1), dz = ez_off + ((b >> 2) & 1);
           const int slot27 = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
           double kab = 0.0;
@@ -348,6 +349,18 @@ __device__ __forceinline__ void assemble_tile_body(int N, const double* __restri
         }
       }
 
+  // every element row sums to zero (the shape functions sum to one, so
+  // sum_b grad N_b = 0, and C_ab = sum_q N_a v . grad N_b too), hence so
+  // does the assembled row before the boundary conditions: its diagonal is
+  // minus the sum of its other entries (added in ascending neighbour order),
+  // which saves the 8 diagonal element entries' Gauss sums
+  {
+    double off = 0.0;
+#pragma unroll
+    for (int t = 0; t < 27; ++t)
+      if (t != 13) off += acc[t];
+    acc[13] = -off;
+  }
   const bool bnd_row = (ii == 0 || ii == N || jj == 0 || jj == N || kk == 0 || kk == N);
   const int64_t start = row_ptr[row];
   double sabs = 0.0, dg = 0.0;
