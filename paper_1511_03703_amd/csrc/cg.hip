@@ -72,8 +72,8 @@ __global__ __launch_bounds__(256) void k_diag_inv(int n, const int32_t* __restri
 
 // Wavefronts per workgroup of the CG product and the FP64 residual: 8
 // (a row tile twice as deep as the cycle's row passes) measured 1.2 % (FP32)
-// and 1.9 % (FP64) faster than 4 at 128^3, s = 32; the cycle's passes show
-// no gain and keep 4.
+// and 1.9 % (FP64) faster than 4 at 128^3, s = 32; the cycle's passes gain
+// under 1 % in FP32 and lose 2.7 % in FP64 from it, and keep 4.
 constexpr int kProdWaves = 8;
 
 // One row tile per block (kProdWaves wavefronts).
