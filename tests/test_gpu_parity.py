@@ -92,7 +92,7 @@ def _gpu_system(E, N, s, M, sigma, xi, want32=False, f=1.0):
 
 
 @pytest.mark.parametrize("N,s,M,sigma", [(16, 4, 3, 0.1), (5, 8, 10, 0.3), (6, 16, 10, 0.2), (3, 32, 16, 0.3),
-                                         (1, 4, 10, 0.2), (9, 32, 10, 0.3)])
+                                         (1, 4, 10, 0.2), (9, 32, 10, 0.3), (2, 32, 10, 0.3)])
 def test_assembly_matches_oracle(E, orc, N, s, M, sigma):
     xi = draw_xi(100 + N, s, M)
     g, vals, v32, rhs = _gpu_system(E, N, s, M, sigma, xi, want32=True)
