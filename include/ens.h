@@ -216,8 +216,12 @@ ens_status ens_spmv(const ens_graph* graph, int32_t s, ens_dtype dtype, const vo
 
 /* Scalar CRS product (Fig. "crs") of ONE sample: values [nnz], x and y [n]
  * (device).  This is the one-sample-at-a-time baseline of the paper's
- * speed-up definition (Sec. 4).  lanes_per_row in {4, 8, 16, 32, 64}
- * (0 = default 8) selects how many lanes cooperate on one row. */
+ * speed-up definition (Sec. 4).  lanes_per_row 0 (the default): each
+ * 256-lane workgroup reads the entries of 64 (FP64) or 32 (FP32)
+ * consecutive rows in coalesced sweeps, forms the products in LDS and sums
+ * each row in ascending entry order, every product rounded once;
+ * lanes_per_row in {4, 8, 16, 32, 64}: that many lanes share a row.
+ * Negative or other values: ENS_E_ARG. */
 ens_status ens_scalar_spmv(const ens_graph* graph, ens_dtype dtype, const void* values, const void* x,
                            void* y, int32_t lanes_per_row, hipStream_t stream);
 
@@ -318,8 +322,9 @@ ens_status ens_cg_noalloc(const ens_graph* graph, int32_t s, const double* value
  * with one-sample kernels on the sample-major layout of Eq. kron_sys:
  * values [s][nnz], b and x [s][n] (device).  FP64 only (opts->mixed must
  * be 0).  This is the "s times a single sample" side of the speed-up
- * definition of Sec. 4.  Workspace from ens_cg_workspace_bytes(graph, 4,
- * opts) suffices.  Synchronises. */
+ * definition of Sec. 4.  lanes_per_row selects the one-sample product as
+ * in ens_scalar_spmv (0, the default, or 4, 8, 16, 32).  Workspace from
+ * ens_cg_workspace_bytes(graph, 4, opts) suffices.  Synchronises. */
 ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values, const double* b,
                          double* x, const ens_cg_opts* opts, int32_t lanes_per_row, void* workspace,
                          size_t ws_bytes, ens_cg_stat* stats, hipStream_t stream);

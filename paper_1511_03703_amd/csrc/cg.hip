@@ -31,6 +31,7 @@
 
 #include "cgcore.hpp"
 #include "mg.hpp"
+#include "sctile.hpp"
 
 namespace ens {
 
@@ -190,6 +191,66 @@ __global__ __launch_bounds__(256) void k_cg_spmv_dot_scalar(int n, const int32_t
     acc[0][0] = p[row] * s;
   }
   block_partials<1, 1, 1, kBlock / 64>(acc, part + (int64_t)blockIdx.x);
+}
+
+// G = 0: the same two kernels over row tiles read by the whole workgroup.
+__global__ __launch_bounds__(kScThreads) void k_residual_scalar_tile(int n, const int32_t* __restrict__ rp,
+                                                                    const int32_t* __restrict__ ci,
+                                                                    const double* __restrict__ vals,
+                                                                    const double* __restrict__ x,
+                                                                    const double* __restrict__ b,
+                                                                    double* __restrict__ rout,
+                                                                    double* __restrict__ part) {
+  __shared__ ScTileLds<double> t;
+  const int64_t r0 = (int64_t)blockIdx.x * ScShape<double>::rows;
+  bool has = false;
+  const double s = sc_tile_row<double>(t, n, rp, ci, vals, x, r0, &has);
+  double acc[2][1] = {{0.0}, {0.0}};
+  if (has) {
+    const int64_t row = r0 + threadIdx.x;
+    const double r = b[row] - s;
+    if (rout) rout[row] = r;
+    acc[0][0] = r * r;
+    acc[1][0] = b[row] * b[row];
+  }
+  block_partials<1, 1, 2, kScThreads / 64>(acc, part + (int64_t)blockIdx.x * 2);
+}
+
+__global__ __launch_bounds__(kScThreads) void k_cg_spmv_dot_scalar_tile(int n, const int32_t* __restrict__ rp,
+                                                                       const int32_t* __restrict__ ci,
+                                                                       const double* __restrict__ vals,
+                                                                       const double* __restrict__ p,
+                                                                       double* __restrict__ q, const Ctl* c,
+                                                                       double* __restrict__ part) {
+  if (c->n_active == 0) return;
+  __shared__ ScTileLds<double> t;
+  const int64_t r0 = (int64_t)blockIdx.x * ScShape<double>::rows;
+  bool has = false;
+  const double s = sc_tile_row<double>(t, n, rp, ci, vals, p, r0, &has);
+  double acc[1][1] = {{0.0}};
+  if (has) {
+    const int64_t row = r0 + threadIdx.x;
+    q[row] = s;
+    acc[0][0] = p[row] * s;
+  }
+  block_partials<1, 1, 1, kScThreads / 64>(acc, part + (int64_t)blockIdx.x);
+}
+
+// rows per workgroup of the one-sample product kernels
+template <int G>
+constexpr int sc_rows_per_block() {
+  return G == 0 ? ScShape<double>::rows : kBlock / G;
+}
+
+template <int G>
+static void launch_residual_scalar(const ens_graph* g, const double* vals, const double* x, const double* b,
+                                   double* rout, double* part, unsigned rb, hipStream_t st) {
+  if constexpr (G == 0)
+    hipLaunchKernelGGL(k_residual_scalar_tile, dim3(rb), dim3(kScThreads), 0, st, g->n, g->row_ptr, g->col_idx,
+                       vals, x, b, rout, part);
+  else
+    hipLaunchKernelGGL(k_residual_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x,
+                       b, rout, part);
 }
 
 // ------------------------------------------------------------ host side ---
@@ -597,13 +658,12 @@ static void scalar_setup(const ens_graph* g, const double* vals, const double* b
   double* p = (double*)w.vec[1];
   double* dinv = (double*)w.vec[3];
   const int64_t n = g->n;
-  const unsigned rb = grid_for(n, kBlock / G);
+  const unsigned rb = grid_for(n, sc_rows_per_block<G>());
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, w.ctl, o.rtol, o.inner_rtol, o.max_iter,
                      o.inner_max_iter, o.max_outer, 0, 0);
   hipLaunchKernelGGL((k_diag_inv<double, 1>), dim3(grid_for(n, 256)), dim3(256), 0, st, g->n, g->row_ptr,
                      g->col_idx, vals, dinv);
-  hipLaunchKernelGGL(k_residual_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
-                     r, w.part);
+  launch_residual_scalar<G>(g, vals, x, b, r, w.part, rb, st);
   reduce<1, 2>(w, rb, OP_START, 0, 0, st);
   hipLaunchKernelGGL(k_zero_where<1>, dim3(grid_for(n, 256 * 8)), dim3(kBlock), 0, st, n, x, w.ctl);
   cg_start<double, 1>(n, r, dinv, p, (double*)nullptr, w, st);
@@ -617,12 +677,16 @@ static void scalar_iters(const ens_graph* g, const double* vals, double* x, cons
   double* q = (double*)w.vec[2];
   double* dinv = (double*)w.vec[3];
   const int64_t n = g->n;
-  const unsigned rb = grid_for(n, kBlock / G);
+  const unsigned rb = grid_for(n, sc_rows_per_block<G>());
   const unsigned vb = grid_for(n, (int64_t)kBlock * kU);
   for (int k = k0 + 1; k <= k1; ++k) {
     prof_begin(ENS_K_SCALAR_SPMV, st);
-    hipLaunchKernelGGL(k_cg_spmv_dot_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals,
-                       p, q, w.ctl, w.part);
+    if constexpr (G == 0)
+      hipLaunchKernelGGL(k_cg_spmv_dot_scalar_tile, dim3(rb), dim3(kScThreads), 0, st, g->n, g->row_ptr, g->col_idx,
+                         vals, p, q, w.ctl, w.part);
+    else
+      hipLaunchKernelGGL(k_cg_spmv_dot_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals,
+                         p, q, w.ctl, w.part);
     prof_end(ENS_K_SCALAR_SPMV, st, (double)g->nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n);
     reduce<1, 1>(w, rb, OP_ALPHA, 0, 1, st);
     hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(vb), dim3(kBlock), 0, st, n, x, p, q, r, dinv, w.ctl, w.part);
@@ -634,9 +698,8 @@ static void scalar_iters(const ens_graph* g, const double* vals, double* x, cons
 template <int G>
 static void scalar_finish(const ens_graph* g, const double* vals, const double* b, const double* x, const Work& w,
                           hipStream_t st) {
-  const unsigned rb = grid_for(g->n, kBlock / G);
-  hipLaunchKernelGGL(k_residual_scalar<G>, dim3(rb), dim3(kBlock), 0, st, g->n, g->row_ptr, g->col_idx, vals, x, b,
-                     (double*)nullptr, w.part);
+  const unsigned rb = grid_for(g->n, sc_rows_per_block<G>());
+  launch_residual_scalar<G>(g, vals, x, b, (double*)nullptr, w.part, rb, st);
   reduce<1, 2>(w, rb, OP_TRUE, 0, 0, st);
 }
 
@@ -1106,7 +1169,9 @@ ens_status ens_scalar_cg_concurrent(const ens_graph* graph, int32_t s, const dou
     return ENS_E_NOMEM;
   }
   ens_cg_opts o = normalized(opts);
-  switch (lanes_per_row > 0 ? lanes_per_row : 8) {
+  ENS_ARG_CHECK(lanes_per_row >= 0, "lanes_per_row must be 0 (row tiles) or 4, 8, 16, 32");
+  switch (lanes_per_row) {
+    case 0: return cg_scalar_concurrent<0>(graph, s, values, b, x, o, ns, (char*)workspace, slice, stats, stream);
     case 4: return cg_scalar_concurrent<4>(graph, s, values, b, x, o, ns, (char*)workspace, slice, stats, stream);
     case 8: return cg_scalar_concurrent<8>(graph, s, values, b, x, o, ns, (char*)workspace, slice, stats, stream);
     case 16: return cg_scalar_concurrent<16>(graph, s, values, b, x, o, ns, (char*)workspace, slice, stats, stream);
@@ -1131,7 +1196,8 @@ ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values
     set_error("workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     return ENS_E_NOMEM;
   }
-  int G = lanes_per_row > 0 ? lanes_per_row : 8;
+  ENS_ARG_CHECK(lanes_per_row >= 0, "lanes_per_row must be 0 (row tiles) or 4, 8, 16, 32");
+  const int G = lanes_per_row;
   Work w;
   ws_layout(graph->n, 1, false, &w, (char*)workspace);
   ens_cg_opts o = normalized(opts);
@@ -1141,6 +1207,7 @@ ens_status ens_scalar_cg(const ens_graph* graph, int32_t s, const double* values
     const double* be = b + (int64_t)e * graph->n;
     double* xe = x + (int64_t)e * graph->n;
     switch (G) {
+      case 0: st = cg_scalar_one<0>(graph, ve, be, xe, o, w, stream); break;
       case 4: st = cg_scalar_one<4>(graph, ve, be, xe, o, w, stream); break;
       case 8: st = cg_scalar_one<8>(graph, ve, be, xe, o, w, stream); break;
       case 16: st = cg_scalar_one<16>(graph, ve, be, xe, o, w, stream); break;

@@ -1,6 +1,7 @@
 // Ensemble and scalar CRS products as standalone entry points, and the
 // layout change between the commuted and the sample-major ensemble layouts.
 #include "rowops.hpp"
+#include "sctile.hpp"
 
 namespace ens {
 
@@ -41,6 +42,19 @@ __global__ __launch_bounds__(256) void k_scalar_spmv(int n, const int32_t* __res
   if (ok && g == 0) y[row] = acc;
 }
 
+// Scalar CRS over row tiles read by the whole workgroup (lanes_per_row 0).
+template <typename T>
+__global__ __launch_bounds__(kScThreads) void k_scalar_spmv_tile(int n, const int32_t* __restrict__ rp,
+                                                                const int32_t* __restrict__ ci,
+                                                                const T* __restrict__ vals,
+                                                                const T* __restrict__ x, T* __restrict__ y) {
+  __shared__ ScTileLds<T> t;
+  const int64_t r0 = (int64_t)blockIdx.x * ScShape<T>::rows;
+  bool has = false;
+  const T v = sc_tile_row<T>(t, n, rp, ci, vals, x, r0, &has);
+  if (has) y[r0 + threadIdx.x] = v;
+}
+
 __global__ __launch_bounds__(256) void k_relayout(const double* __restrict__ src, double* __restrict__ dst,
                                                   int64_t rows, int s, int to_sm) {
   const int64_t total = rows * s;
@@ -73,8 +87,15 @@ static ens_status launch_ens_spmv(const ens_graph* g, const void* vals, const vo
 template <typename T>
 static ens_status launch_scalar_spmv(const ens_graph* g, const void* vals, const void* x, void* y, int G,
                                      hipStream_t st) {
+  if (g->n == 0) return ENS_OK;
+  if (G == 0) {
+    const int64_t tiles = (g->n + ScShape<T>::rows - 1) / ScShape<T>::rows;
+    hipLaunchKernelGGL((k_scalar_spmv_tile<T>), dim3((unsigned)tiles), dim3(kScThreads), 0, st, g->n, g->row_ptr,
+                       g->col_idx, (const T*)vals, (const T*)x, (T*)y);
+    ENS_LAUNCH_CHECK();
+    return ENS_OK;
+  }
   const int64_t blocks = (g->n * G + 255) / 256;
-  if (blocks == 0) return ENS_OK;
   switch (G) {
 #define ENS_SC_CASE(GG)                                                                                   \
   case GG:                                                                                                \
@@ -151,7 +172,8 @@ ens_status ens_scalar_spmv(const ens_graph* graph, ens_dtype dtype, const void* 
   ens_status st = check_graph(graph);
   if (st != ENS_OK) return st;
   ENS_ARG_CHECK((values || graph->nnz == 0) && ((x && y && x != y) || graph->n == 0), "null or aliased pointer");
-  int G = lanes_per_row > 0 ? lanes_per_row : 8;
+  ENS_ARG_CHECK(lanes_per_row >= 0, "lanes_per_row must be 0 (row tiles) or 4, 8, 16, 32, 64");
+  const int G = lanes_per_row;
   const double w = dtype == ENS_F64 ? 8.0 : 4.0;
   const double bytes = (double)graph->nnz * (w + 4.0) + 4.0 * (graph->n + 1) + 2.0 * graph->n * w;
   prof_begin(ENS_K_SCALAR_SPMV, stream);

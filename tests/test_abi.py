@@ -74,6 +74,16 @@ def test_argument_errors_without_gpu(E):
     st = L.ens_cg(ctypes.byref(g), 4, ctypes.c_void_p(256), None, ctypes.c_void_p(512), ctypes.c_void_p(768),
                   ctypes.byref(opts), ctypes.c_void_p(1024), 1 << 30, stats, None)
     assert st == E.ENS_E_ARG
+    # one-sample product: lanes_per_row is 0 (row tiles) or a supported count
+    st = L.ens_scalar_spmv(ctypes.byref(g), E.F64, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48),
+                           -1, None)
+    assert st == E.ENS_E_ARG and b"lanes_per_row" in L.ens_last_error()
+    st = L.ens_scalar_spmv(ctypes.byref(g), E.F64, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48),
+                           12, None)
+    assert st == E.ENS_E_ARG and b"lanes_per_row" in L.ens_last_error()
+    st = L.ens_scalar_cg(ctypes.byref(g), 2, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768),
+                         ctypes.byref(E.cg_opts()), -4, ctypes.c_void_p(1024), 1 << 30, stats, None)
+    assert st == E.ENS_E_ARG and b"lanes_per_row" in L.ens_last_error()
     # KL size range
     b = ctypes.c_size_t()
     assert L.ens_kl_bytes(16, 17, ctypes.byref(b)) == E.ENS_E_UNSUPPORTED

@@ -172,7 +172,7 @@ def test_spmv_row_tiles_staged_and_not(E, orc, s, lo, hi):
         assert np.max(np.abs(y - ref)) <= tol * scale
 
 
-@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lanes", [0, 4, 8, 16, 32, 64])
 def test_scalar_spmv(E, orc, lanes):
     rng = np.random.default_rng(lanes)
     n = 3001
@@ -183,6 +183,38 @@ def test_scalar_spmv(E, orc, lanes):
     g = E.graph_from_arrays(_t(rp, torch.int32), _t(ci, torch.int32))
     y = _np(E.scalar_spmv(g, _t(vals), _t(x), lanes_per_row=lanes))
     assert np.max(np.abs(y - ref)) <= 1e-13 * (1 + np.abs(ref).max())
+
+
+def _ascending_sum(rp, ci, vals, x, dt):
+    # each product rounded once, then added in ascending entry order, in dt
+    vals, x = vals.astype(dt), x.astype(dt)
+    y = np.zeros(len(rp) - 1, dt)
+    for r in range(len(rp) - 1):
+        s = dt(0)
+        for k in range(rp[r], rp[r + 1]):
+            s = dt(s + dt(vals[k] * x[ci[k]]))
+        y[r] = s
+    return y
+
+
+@pytest.mark.parametrize("n,maxlen", [(1, 5), (64, 27), (65, 27), (1000, 20), (777, 70), (3001, 40)])
+def test_scalar_spmv_row_tiles(E, orc, n, maxlen):
+    # the row-tile product (lanes_per_row 0): tiles whose entries fit in LDS
+    # (short rows), tiles that read global memory (long rows), both in one
+    # matrix (maxlen 70 puts tiles on either side), ragged last tiles, empty
+    # rows; against the oracle within rounding, and bitwise against the
+    # ascending sum of singly rounded products the header states
+    print(f"scalar row tiles n={n} maxlen={maxlen}", flush=True)
+    rng = np.random.default_rng(7000 + n + maxlen)
+    rp, ci = _random_crs(rng, n, maxlen, n)
+    vals = rng.standard_normal(int(rp[-1]))
+    x = rng.standard_normal(n)
+    ref = orc.spmv(rp, ci, vals, x)
+    g = E.graph_from_arrays(_t(rp, torch.int32), _t(ci, torch.int32))
+    for dt, tdt, tol in ((np.float64, torch.float64, 1e-13), (np.float32, torch.float32, 2e-5)):
+        y = _np(E.scalar_spmv(g, _t(vals, tdt), _t(x, tdt), lanes_per_row=0))
+        assert np.max(np.abs(y - ref)) <= tol * (1 + np.abs(ref).max())
+        assert np.array_equal(y, _ascending_sum(rp, ci, vals, x, dt))
 
 
 def test_spmv_on_assembled_matrix(E, orc):
@@ -256,7 +288,7 @@ def test_ensemble_equals_scalar_solves(E, orc):
     x, stats, _ = E.cg(g, vals, rhs, opts=E.cg_opts(rtol=rtol))
     vsm = E.relayout(vals, True)
     bsm = E.relayout(rhs, True)
-    for lanes in (4, 16):
+    for lanes in (0, 4, 16):
         xs, sstats, st = E.scalar_cg(g, vsm, bsm, opts=E.cg_opts(rtol=rtol), lanes_per_row=lanes)
         assert st == E.ENS_OK
         xe = _np(x)
@@ -269,12 +301,13 @@ def test_ensemble_equals_scalar_solves(E, orc):
     assert np.array_equal(back, _np(vals))
     # the concurrent one-sample baseline runs the same kernels per sample, so
     # its results equal the sequential baseline's bitwise
-    xs1, st1, _ = E.scalar_cg(g, vsm, bsm, opts=E.cg_opts(rtol=rtol, check_every=5), lanes_per_row=8)
-    for streams in (1, 3, 8):
-        xc, stc, rc = E.scalar_cg_concurrent(g, vsm, bsm, opts=E.cg_opts(rtol=rtol, check_every=5), lanes_per_row=8,
-                                             streams=streams)
-        assert rc == E.ENS_OK
-        assert torch.equal(xc, xs1) and stc == st1
+    for lanes in (8, 0):
+        xs1, st1, _ = E.scalar_cg(g, vsm, bsm, opts=E.cg_opts(rtol=rtol, check_every=5), lanes_per_row=lanes)
+        for streams in (1, 3, 8):
+            xc, stc, rc = E.scalar_cg_concurrent(g, vsm, bsm, opts=E.cg_opts(rtol=rtol, check_every=5),
+                                                 lanes_per_row=lanes, streams=streams)
+            assert rc == E.ENS_OK
+            assert torch.equal(xc, xs1) and stc == st1
 
 
 def test_shutdown_releases_and_state_comes_back(E):
