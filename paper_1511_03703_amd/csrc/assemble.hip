@@ -134,18 +134,23 @@ __host__ __device__ constexpr int tab_doubles(int M) { return M * (2 * EX + 4 * 
 // The sample-independent factors are staged in s_tab first (the x factors
 // and the y-z products, read from the KL table once per workgroup), and
 // each lane keeps the coefficients c_m = sigma sqrt(lambda_m) y_m of its one
-// sample in registers (the NT lanes are a multiple of 2 SB, so a lane's
-// items all have the same sample and z half).  An item is one element,
-// sample and z half (4 Gauss points).  The sum follows kl_points operation
-// by operation (the y-z product is formed once per tile instead of per
-// sample: the same rounding), so the values are bitwise those of
-// kl_points.  Ends with a barrier.
-template <int NT, int SB, int EX, int EY, int EZ, bool SCALED>
+// sample in registers (the NT lanes are a multiple of SB, so a lane's items
+// all have the same sample).  An item is one element and sample, its PTS =
+// 8 Gauss points (PTS = 4: half an element, the lanes then a multiple of
+// 2 SB with a fixed z half each); whole elements read 3 instead of 4 LDS
+// factor pairs per 8 points and mode, which made the linear assembly 3.6 %
+// faster (5.10 -> 4.92 ms in alternating runs).  The sum follows kl_points
+// operation by operation (the y-z product is formed once per tile instead
+// of per sample: the same rounding), so the values are bitwise those of
+// kl_points whatever PTS.  Ends with a barrier.
+template <int NT, int SB, int EX, int EY, int EZ, bool SCALED, int PTS = 4>
 __device__ inline void tile_coefficients(int N, const double* __restrict__ kl_sqrt_lam,
                                          const int32_t* __restrict__ kl_triple, const double* __restrict__ kl_phi,
                                          int M, double kappa0, double sigma, const double* __restrict__ xi, int e0,
                                          int ex0, int ey0, int ez0, double scale, double* s_tab, double* s_k) {
-  static_assert(NT % (2 * SB) == 0, "a lane's items must share one sample and z half");
+  static_assert(PTS == 4 || PTS == 8, "an item is half an element or a whole one");
+  constexpr int HALVES = 8 / PTS;  // z halves of an element held by different lanes
+  static_assert(NT % (HALVES * SB) == 0, "a lane's items must share one sample and z half");
   constexpr int NE = EX * EY * EZ;
   const int64_t two_n = 2 * (int64_t)N;
   double* s_x = s_tab;               // [M][EX][2]
@@ -164,7 +169,7 @@ __device__ inline void tile_coefficients(int N, const double* __restrict__ kl_sq
       v = kl_phi[kl_triple[3 * m + 1] * two_n + 2 * ey + qy] * kl_phi[kl_triple[3 * m + 2] * two_n + 2 * ez + qz];
     s_yz[t] = v;
   }
-  const int sb = threadIdx.x % SB, hz = (threadIdx.x / SB) & 1;
+  const int sb = threadIdx.x % SB, hz = HALVES == 2 ? (threadIdx.x / SB) & 1 : 0;
   double c[kAsmMaxM];
 #pragma unroll
   for (int m = 0; m < kAsmMaxM; ++m) c[m] = m < M ? sigma * kl_sqrt_lam[m] * xi[(int64_t)(e0 + sb) * M + m] : 0.0;
@@ -172,16 +177,16 @@ __device__ inline void tile_coefficients(int N, const double* __restrict__ kl_sq
   // a lane's items are elements le0, le0 + D, le0 + 2 D, ... (D = NT / 2 SB):
   // their block coordinates advance by D's digits with carries instead of
   // being divided out per item
-  constexpr int D = NT / (2 * SB);
+  constexpr int D = NT / (HALVES * SB);
   constexpr int DX = D % EX, DY = (D / EX) % EY, DZ = D / (EX * EY);
-  int le = threadIdx.x / (2 * SB);
+  int le = threadIdx.x / (HALVES * SB);
   int lx = le % EX, ly = (le / EX) % EY, lz = le / (EX * EY);
   for (; le < NE; le += D) {
     const int ex = ex0 + lx, ey = ey0 + ly, ez = ez0 + lz;
     if (ex >= 0 && ey >= 0 && ez >= 0 && ex < N && ey < N && ez < N) {
-      double kq[4];  // Gauss points qx + 2 qy + 4 hz
+      double kq[PTS];  // Gauss points qx + 2 qy + 4 (hz or qz)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) kq[q] = 0.0;
+      for (int q = 0; q < PTS; ++q) kq[q] = 0.0;
       const double* px = s_x + lx * 2;
       const double* pyz = s_yz + (ly * EZ + lz) * 4 + 2 * hz;
       // every mode up to the largest M, each skipped by a uniform branch
@@ -190,13 +195,15 @@ __device__ inline void tile_coefficients(int N, const double* __restrict__ kl_sq
       for (int m = 0; m < kAsmMaxM; ++m) {
         if (m < M) {
           const double fx[2] = {px[m * 2 * EX], px[m * 2 * EX + 1]};
-          const double yz[2] = {c[m] * pyz[m * 4 * EY * EZ], c[m] * pyz[m * 4 * EY * EZ + 1]};
+          double yz[PTS / 2];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
+          for (int j = 0; j < PTS / 2; ++j) yz[j] = c[m] * pyz[m * 4 * EY * EZ + j];
+#pragma unroll
+          for (int q = 0; q < PTS; ++q) kq[q] += fx[q & 1] * yz[q >> 1];
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < PTS; ++q) {
         const double k = kappa0 + kq[q];
         s_k[kslot<SB>(le, q + 4 * hz, sb)] = SCALED ? k * scale : k;
       }
@@ -295,7 +302,7 @@ __device__ __forceinline__ void assemble_tile_body(int N, const double* __restri
   tile_decode<TX, TY, T::TZ, 1>(N, bid, &tile_id, &sg, &x0, &y0, &z0);
   const int e0 = 0;
   const double h = 1.0 / (double)N;
-  tile_coefficients<NT, SB, EX, EY, T::EZ, true>(N, kl_sqrt_lam, kl_triple, kl_phi, M, kappa0, sigma, xi, e0,
+  tile_coefficients<NT, SB, EX, EY, T::EZ, true, 8>(N, kl_sqrt_lam, kl_triple, kl_phi, M, kappa0, sigma, xi, e0,
                                                   x0 - 1, y0 - 1, z0 - 1, h * 0.125, s_tab, s_k);
   if (ADV) {
     if (threadIdx.x < 64) {
@@ -500,7 +507,7 @@ __global__ __launch_bounds__(32 * SB) void k_nl_assemble(int N, const double* __
   int sg, x0, y0, z0;
   tile_decode<TX, TY, T::TZ, G>(N, blockIdx.x, &tile_id, &sg, &x0, &y0, &z0);
   const int e0 = sg * SB;
-  tile_coefficients<NT, SB, EX, EY, T::EZ, false>(N, kl_sqrt_lam, kl_triple, kl_phi, M, kappa0, sigma, xi, e0,
+  tile_coefficients<NT, SB, EX, EY, T::EZ, false, 8>(N, kl_sqrt_lam, kl_triple, kl_phi, M, kappa0, sigma, xi, e0,
                                                    x0 - 1, y0 - 1, z0 - 1, 1.0, s_tab, s_k);
   if (threadIdx.x < 64) {
     const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
